@@ -1,0 +1,115 @@
+"""Concrete seeded workloads (frames + poses + forest + parameters).
+
+Seeds: room r uses scene seed r, forest seed 1000 + r; frame noise seeds are
+derived from (room, role, index).  Adaptation poses are independent random
+poses in the room; each query pose lies within 20 cm / 20 degrees of a
+randomly chosen adaptation pose (c1: 4 adaptation frames within 10 cm /
+10 degrees of the query).
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+from . import forest as _forest
+from . import presets as _presets
+from . import scene as _scene
+
+
+@dataclasses.dataclass
+class Frame:
+    depth: np.ndarray      # float32 (h, w)
+    rgb: np.ndarray        # uint8 (h, w, 3)
+    pose: np.ndarray       # float64 (4, 4) camera -> world (ground truth)
+    K: tuple               # (fx, fy, cx, cy) float32
+
+    @property
+    def w(self):
+        return self.depth.shape[1]
+
+    @property
+    def h(self):
+        return self.depth.shape[0]
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    params: dict
+    room: _scene.Room
+    nodes: np.ndarray
+    adapt: list
+    queries: list
+
+
+def _frame(room, pose, w, h, seed, **kw):
+    d, rgb = _scene.render(room, pose, w, h, seed, **kw)
+    return Frame(depth=d, rgb=rgb, pose=pose, K=_scene.intrinsics(w, h))
+
+
+def frame_seed(room_id: int, role: int, index: int) -> int:
+    return 1_000_000 * (room_id + 1) + 100_000 * role + index
+
+
+def decimate(fr: Frame) -> Frame:
+    """2x decimation: pixel (x, y) of the result is pixel (2x, 2y) of the
+    input; fx, fy, cx, cy are halved."""
+    fx, fy, cx, cy = fr.K
+    return Frame(depth=np.ascontiguousarray(fr.depth[::2, ::2]),
+                 rgb=np.ascontiguousarray(fr.rgb[::2, ::2]), pose=fr.pose,
+                 K=(np.float32(fx / 2), np.float32(fy / 2), np.float32(cx / 2), np.float32(cy / 2)))
+
+
+def c1(room_id: int = 0, n_queries: int = 1) -> Workload:
+    params = _presets.preset("c1")
+    room = _scene.make_room(room_id)
+    nodes = _forest.make_forest(1000 + room_id, **_presets.FOREST["c1"])
+    rng = np.random.default_rng(frame_seed(room_id, 9, 0))
+    w, h = 160, 120
+    queries, adapt = [], []
+    for q in range(n_queries):
+        qpose = _scene.random_pose(room, rng)
+        queries.append(_frame(room, qpose, w, h, frame_seed(room_id, 1, q)))
+        if q == 0:
+            for i in range(4):
+                ap = _scene.near_pose(room, qpose, rng, 0.10, 10.0)
+                adapt.append(_frame(room, ap, w, h, frame_seed(room_id, 0, i)))
+    return Workload("c1", params, room, nodes, adapt, queries)
+
+
+def room_setup(room_id: int, n_adapt: int, w: int = 640, h: int = 480, forest_cfg: str = "c2"):
+    room = _scene.make_room(room_id)
+    nodes = _forest.make_forest(1000 + room_id, **_presets.FOREST[forest_cfg])
+    rng = np.random.default_rng(frame_seed(room_id, 8, 0))
+    poses = [_scene.random_pose(room, rng) for _ in range(n_adapt)]
+    adapt = [_frame(room, p, w, h, frame_seed(room_id, 0, i)) for i, p in enumerate(poses)]
+    return room, nodes, adapt
+
+
+def queries_for(room, adapt_poses, n, w=640, h=480, room_id=0, novel_fraction=0.0, start=0):
+    """Query frames near random adaptation poses; a ``novel_fraction`` of them
+    are instead drawn >= 50 cm or >= 50 degrees away from every adaptation
+    pose (the paper's hardest novelty bin)."""
+    rng = np.random.default_rng(frame_seed(room_id, 7, start))
+    out = []
+    for q in range(n):
+        if rng.uniform() < novel_fraction:
+            while True:
+                p = _scene.random_pose(room, rng)
+                far = all((_scene.pose_error(p, a)[0] >= 0.5 or _scene.pose_error(p, a)[1] >= 50.0)
+                          for a in adapt_poses)
+                if far:
+                    break
+        else:
+            base = adapt_poses[int(rng.integers(len(adapt_poses)))]
+            p = _scene.near_pose(room, base, rng, 0.20, 20.0)
+        out.append(_frame(room, p, w, h, frame_seed(room_id, 1, start + q)))
+    return out
+
+
+def c2(room_id: int = 0, n_adapt: int = 50, n_queries: int = 8) -> Workload:
+    params = _presets.preset("c2")
+    room, nodes, adapt = room_setup(room_id, n_adapt)
+    queries = queries_for(room, [f.pose for f in adapt], n_queries, room_id=room_id)
+    return Workload("c2", params, room, nodes, adapt, queries)
