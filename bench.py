@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Relocalisation throughput on one MI355X.
+
+Workload (640x480): a seeded synthetic room, five random depth-15 trees,
+reservoirs of 1024 entries adapted from 50 posed frames, at most 10 modes per
+leaf; relocalisation with 1024 hypotheses, eta = 500 pixels per round, ten
+halving rounds and the final inlier refit.  One benchmark step relocalises a
+batch of 64 such frames (16 distinct query frames x 4 request seeds) through
+the batched path, replayed from a HIP graph.  The plain path (one frame per
+synchronous call) is timed beside it for latency and reloc/s.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "relocalisations/s at 640x480, batched/served vs plain; p50/p99 latency"
+MI355X_VALU_OPS = 256 * 4 * 16 * 2.4e9        # VALU lane-ops/s (one op per lane per clock per SIMD)
+MI355X_HBM = 8.0e12
+
+# Algorithmic VALU operations of one hypothesis-generation iteration (hand
+# count of the definition, not of emitted instructions): two Philox4x32-10
+# blocks (10 rounds x (2 mul-lo + 2 mul-hi + 4 xor) + 9 x 2 key additions =
+# 98 each), three uniform draws into the eligible list and three into M(u)
+# (1 multiply-high each), three back-projections (2 sub + 2 div + 2 mul),
+# the colour check (3 sub + 3 abs + 3 compare), six squared distances
+# (3 sub + 3 mul + 2 add each), six square roots, three rigidity differences
+# (sub + abs + compare) and three distance compares.
+HYP_ITER_OPS = 2 * 98 + 6 + 3 * 6 + 9 + 6 * 8 + 6 + 3 * 3 + 3
+# Algorithmic bytes of one node test: the 16-byte node record and the 4-byte probe.
+NODE_TEST_BYTES = 20
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def percentile(v, q):
+    return float(np.percentile(np.asarray(v, dtype=np.float64), q))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--queries", type=int, default=16)
+    ap.add_argument("--adapt-frames", type=int, default=50)
+    ap.add_argument("--plain", type=int, default=32, help="plain relocalisations timed for latency")
+    ap.add_argument("--cpu-frames", type=int, default=4, help="oracle relocalisations (0 = skip)")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--timer", default="hyp_search", choices=["traverse", "hyp_search", "ransac"])
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}, WORLD_SIZE {world}): "
+              "the relocaliser shards by room across GPUs with no collectives; only the one-GPU "
+              "share is measured here.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1810_12163_amd as rl
+    from rlsynth import scene, workloads
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t_setup = time.time()
+    log(f"[bench] rendering {args.adapt_frames} adaptation frames and {args.queries} queries (640x480)")
+    w = workloads.c2(n_adapt=args.adapt_frames, n_queries=args.queries)
+    p = w.params
+    room = rl.Room(p, w.nodes, 640, 480, device=dev)
+    for i, f in enumerate(w.adapt):
+        room.adapt(torch.from_numpy(f.depth).to(dev), torch.from_numpy(f.rgb).to(dev), f.K, f.pose)
+    room.update_modes()
+    torch.cuda.synchronize()
+    log(f"[bench] room adapted and clustered ({time.time() - t_setup:.1f} s)")
+    qd = [torch.from_numpy(q.depth).to(dev) for q in w.queries]
+    qc = [torch.from_numpy(q.rgb).to(dev) for q in w.queries]
+    B = args.batch
+    frames = [(i % len(w.queries), i // len(w.queries)) for i in range(B)]   # (query, seed)
+
+    # ---- plain path: one frame per synchronous call -----------------------
+    lat = []
+    for k in range(3 + args.plain):
+        qi = k % len(w.queries)
+        t0 = time.perf_counter()
+        room.relocalise(qd[qi], qc[qi], w.queries[qi].K, request_seed=k)
+        dt = time.perf_counter() - t0
+        if k >= 3:
+            lat.append(dt)
+    plain = dict(relocs_per_s=len(lat) / sum(lat), p50_ms=percentile(lat, 50) * 1e3,
+                 p99_ms=percentile(lat, 99) * 1e3, mean_ms=float(np.mean(lat)) * 1e3, frames=len(lat))
+    log(f"[bench] plain: {plain['relocs_per_s']:.1f} reloc/s, p50 {plain['p50_ms']:.2f} ms, "
+        f"p99 {plain['p99_ms']:.2f} ms")
+
+    # algorithmic work of one batch, from the plain path on the same (frame, seed) pairs
+    iters = 0
+    node_tests = 0
+    Imax = p["max_candidate_generation_iterations"]
+    plain_res = []
+    for (qi, s) in frames:
+        r = room.relocalise(qd[qi], qc[qi], w.queries[qi].K, request_seed=s)
+        plain_res.append(r)
+        hy = room.buffer_np(rl.BUF_HYPS, rl.HYP_DTYPE)[:p["max_pose_candidates"]]
+        it = np.where(hy["valid"] != 0, hy["iter"] + 1, Imax)
+        iters += int(it.sum())
+        node_tests += int(np.count_nonzero(w.queries[qi].depth > 0)) * p["n_trees"] * p["depth"]
+
+    # ---- batched path ----------------------------------------------------
+    rounds = rl.rounds_for(p["max_pose_candidates"], p["max_pose_candidates_after_cull"],
+                           p["max_relocalisations_to_output"])
+    batch = rl.Batch(B, 640, 480, p["max_pose_candidates"], p["ransac_inliers_per_iteration"], rounds,
+                     p["n_trees"], p["n_trees"] * p["max_cluster_count"], device=dev)
+    reqs = [(room, qd[qi], qc[qi], w.queries[qi].K, s) for (qi, s) in frames]
+    timer = {"traverse": rl.TIMER_TRAVERSE, "hyp_search": rl.TIMER_HYP_SEARCH, "ransac": rl.TIMER_RANSAC}[args.timer]
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    ev1.record()               # torch creates the underlying hipEvent on first record
+    torch.cuda.synchronize()
+    batch.set_timer(timer, ev0, ev1)
+    use_graph = not args.no_graph
+    for _ in range(args.warmup):
+        res = batch.relocalise(reqs, use_graph=use_graph)
+    torch.cuda.synchronize()
+    step_ms, kern_ms = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        res = batch.relocalise(reqs, use_graph=use_graph)       # synchronous
+        step_ms.append((time.perf_counter() - s0) * 1e3)
+        kern_ms.append(ev0.elapsed_time(ev1))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = B * args.steps / elapsed
+    log(f"[bench] batched: {value:.1f} reloc/s ({elapsed / args.steps * 1e3:.2f} ms per {B}-frame step)")
+
+    same = all(np.array_equal(a["pose"], b["pose"]) and a["energy"] == b["energy"]
+               for a, b in zip(res, plain_res))
+    errs = [scene.pose_error(r["pose"].astype(np.float64), w.queries[qi].pose) for r, (qi, _) in zip(res, frames)]
+    ok = [e[0] <= 0.05 and e[1] <= 5.0 for e in errs]
+
+    # ---- roofline of the timed kernel --------------------------------------
+    kavg = float(np.mean(kern_ms)) * 1e-3
+    if timer == rl.TIMER_HYP_SEARCH:
+        ops = iters * HYP_ITER_OPS
+        roof = dict(kernel="k_hyp_search", bound="alu", achieved=ops / kavg / 1e12,
+                    peak=MI355X_VALU_OPS / 1e12, unit="TOP/s (VALU lane-ops)",
+                    frac=ops / kavg / MI355X_VALU_OPS, traffic=None, launch_ms=kavg * 1e3,
+                    work=f"{iters} generation iterations x {HYP_ITER_OPS} ops")
+    elif timer == rl.TIMER_TRAVERSE:
+        by = node_tests * NODE_TEST_BYTES
+        roof = dict(kernel="k_traverse", bound="hbm", achieved=by / kavg / 1e9, peak=MI355X_HBM / 1e9,
+                    unit="GB/s", frac=by / kavg / MI355X_HBM, traffic=None, launch_ms=kavg * 1e3,
+                    work=f"{node_tests} node tests x {NODE_TEST_BYTES} B")
+    else:
+        roof = dict(kernel="k_score+k_select", bound="alu", achieved=None, peak=MI355X_VALU_OPS / 1e12,
+                    unit="TOP/s", frac=None, traffic=None, launch_ms=kavg * 1e3)
+
+    # ---- CPU baseline: the oracle on a bounded sample ----------------------
+    cpu = None
+    if args.cpu_frames > 0:
+        import oracle
+        nm = room.buffer_np(rl.BUF_NMODES, np.uint8).copy()
+        modes = room.buffer_np(rl.BUF_MODES, np.float32).copy()
+        T, D, M = p["n_trees"], p["depth"], p["max_cluster_count"]
+        t0 = time.perf_counter()
+        for k in range(args.cpu_frames):
+            q = w.queries[k % len(w.queries)]
+            leaves = oracle.traverse(q.depth, q.rgb, None, w.nodes, T, D, p["ref_width"])
+            oracle.estimate_pose(q.depth, q.rgb, q.K, leaves, nm, modes, T, D, M, p, k, trace=False)
+        ct = time.perf_counter() - t0
+        cpu = dict(value=args.cpu_frames / ct, unit="relocalisations/s", cores=1, kind="oracle",
+                   sample=f"{args.cpu_frames} relocalisations of 640x480 query frames (traversal, "
+                          f"hypotheses, RANSAC, refit; modes taken from the room), 1 thread, {ct:.1f} s")
+        log(f"[bench] oracle: {cpu['value']:.3f} reloc/s over {ct:.1f} s")
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "relocalisations/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "640x480 synthetic room; 5 random trees of depth 15; reservoirs 1024; "
+                               "<=10 modes/leaf; 50 adaptation frames; 1024 hypotheses; eta 500; "
+                               "10 halving rounds; inlier refit",
+                   "form": "batched" + (" (hipGraph replay)" if use_graph else ""), "batch": B,
+                   "distinct_frames": len(w.queries)},
+        "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
+        "roofline_kernel": {k: v for k, v in roof.items() if k not in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
+        "cpu_baseline": cpu,
+        "plain": plain,
+        "batched": dict(relocs_per_s=value, step_p50_ms=percentile(step_ms, 50),
+                        step_p99_ms=percentile(step_ms, 99), identical_to_plain=bool(same)),
+        "accuracy": dict(frac_within_5cm_5deg=float(np.mean(ok)),
+                         median_cm=float(np.median([e[0] for e in errs]) * 100),
+                         median_deg=float(np.median([e[1] for e in errs]))),
+        "paper_context": "Fast relocaliser 25.1 ms/frame on a GTX 1080 Ti (Table 3)",
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

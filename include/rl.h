@@ -1,0 +1,295 @@
+/*
+ * rl.h -- C ABI of the MI355X relocaliser library (librl.so).
+ *
+ * The library implements the per-frame hot path of the adaptive
+ * regression-forest camera relocaliser of Cavallari et al., "Real-Time RGB-D
+ * Camera Pose Estimation in Novel Scenes using a Relocalisation Cascade"
+ * (TPAMI 2019, arXiv 1810.12163):
+ *   - Depth and DA-RGB features and routing through every tree (Eq. 1-3,
+ *     Sec. 3.2.1), leaf indexing of an implicit complete binary tree;
+ *   - online adaptation into bounded per-leaf reservoirs and Really Quick
+ *     Shift modes (Sec. 3.2.2);
+ *   - pose estimation: Kabsch hypotheses from pixel triplets with the three
+ *     checks, Eq. 5 energies on growing pixel sets, preemptive halving
+ *     (Sec. 3.2.3), plus an optional closed-form refit over the inliers.
+ *
+ * Conventions (all entry points):
+ *   - Device pointers are HIP device addresses on the current device; host
+ *     pointers are ordinary CPU memory.  The library never frees caller
+ *     memory and never allocates device memory after relocaliser_create /
+ *     rl_batch_create (those allocate nothing on the device either: all
+ *     device state lives in caller-provided buffers).
+ *   - Poses are camera->world, 4x4 row-major float32, metres, last row
+ *     0 0 0 1 (the paper's hypotheses map camera space to world space).
+ *   - Camera frame: x right, y down, z forward; x^C = D(u) K^-1 (u, v, 1)^T on
+ *     integer pixel coordinates.  Depth: float32 metres, 0 = invalid.
+ *   - Errors are returned as rl_status; negative values are errors, and
+ *     rl_last_error() gives a thread-local message.  RL_NO_POSE is not an
+ *     error: no hypothesis survived (energy = +inf, pose = identity).
+ *   - A room handle is bound to one HIP stream and is not thread-safe;
+ *     different rooms may be used concurrently from different threads.
+ */
+#ifndef RL_H_
+#define RL_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RL_OK = 0,
+    RL_NO_POSE = 1,
+    RL_EINVAL = -1,
+    RL_ENOMEM = -2,
+    RL_EDEVICE = -3,
+    RL_EBUSY = -4
+} rl_status;
+
+typedef struct { float fx, fy, cx, cy; } rl_intrinsics;
+
+/* One RGB-D frame in device memory. width and height must be multiples of 4. */
+typedef struct {
+    int32_t width, height;
+    const float* depth;      /* device, height*width float32, row-major, metres, 0 = invalid */
+    const uint8_t* rgb;      /* device, height*width*3 uint8, row-major R,G,B              */
+    rl_intrinsics K;
+} rl_frame;
+
+/*
+ * Parameters.  Names follow the paper's parameter table (Table 8) in
+ * snake_case; the remaining fields are settings the paper leaves open.
+ */
+typedef struct {
+    /* forest structure (nodes are supplied by the caller) */
+    int32_t n_trees;                 /* 1..8                                            */
+    int32_t depth;                   /* split levels, 1..15; 2^depth leaves per tree     */
+    int32_t ref_width;               /* image width the offsets are expressed for        */
+    /* Table 8, Forest */
+    float clusterer_sigma;           /* RQS Gaussian kernel width (m)                    */
+    float clusterer_tau;             /* RQS maximum link distance (m)                    */
+    int32_t max_cluster_count;       /* M_max, 1..64, n_trees * M_max <= 255             */
+    int32_t min_cluster_size;
+    int32_t reservoir_capacity;      /* kappa, 1..4096                                   */
+    /* Table 8, RANSAC */
+    int32_t max_candidate_generation_iterations;
+    int32_t max_pose_candidates;     /* N_max, 1..4096                                   */
+    int32_t max_pose_candidates_after_cull;  /* N_cull; >= N_max disables the initial cull */
+    int32_t ransac_inliers_per_iteration;    /* eta, 1..4096                             */
+    int32_t max_relocalisations_to_output;   /* >= 1                                     */
+    int32_t use_prediction_covariance;       /* Mahalanobis (1) or Euclidean (0) Eq. 5   */
+    int32_t pose_update;                     /* LM refinement: must be 0 (not provided)  */
+    int32_t final_refine;                    /* 1: Kabsch refit over the inliers         */
+    float min_squared_distance_between_sampled_modes;   /* check 2 (m^2)                */
+    float max_translation_error_for_correct_pose;       /* check 3 tolerance (m)        */
+    float max_colour_linf;           /* check 1 threshold, 0..255 scale                  */
+    float inlier_threshold;          /* refit inlier distance (m)                        */
+    float cov_regulariser;           /* lambda added to every mode covariance (m^2)      */
+    uint64_t seed;                   /* generator seed of the room                       */
+} rl_params;
+
+typedef struct rl_room rl_room;
+
+/* Forest node record as supplied by the caller: 16 bytes per branch node,
+ * (2^depth - 1) nodes per tree in implicit complete-tree order, tree-major.
+ * kind 0 = Depth feature, 1 + c = DA-RGB feature on colour channel c. */
+typedef struct { float dx, dy, tau; uint32_t kind; } rl_node;
+
+/*
+ * Fills *out with a named preset: "default", "fast", "intermediate", "slow"
+ * (Table 8 of the paper) or "c1" (160x120, one depth-8 tree, kappa 64,
+ * 64 hypotheses, eta 100) / "c2" (640x480, five depth-15 trees, kappa 1024,
+ * 1024 hypotheses, eta 500, refit).  RL_EINVAL for an unknown name.
+ */
+rl_status rl_params_preset(const char* name, rl_params* out);
+
+/*
+ * Checks a parameter block (RL_EINVAL with a message when invalid).
+ */
+rl_status rl_params_validate(const rl_params* p);
+
+/*
+ * Device bytes a room needs.  persistent: forest, reservoirs, counters and
+ * modes (must outlive the room).  scratch: per-frame work space for frames up
+ * to max_width x max_height.  Both must be 256-byte aligned.
+ */
+rl_status relocaliser_state_bytes(const rl_params* p, int32_t max_width, int32_t max_height,
+                                  size_t* persistent, size_t* scratch);
+
+/*
+ * Creates a room.  host_nodes: n_trees * (2^depth - 1) rl_node records (host);
+ * they are copied into dev_persistent, whose reservoirs and modes are cleared.
+ * dev_persistent / dev_scratch: caller-owned device buffers of at least the
+ * sizes relocaliser_state_bytes reported.  hip_stream: the hipStream_t all
+ * work of this room is queued on (NULL = default stream).
+ */
+rl_status relocaliser_create(const rl_params* p, const rl_node* host_nodes, int32_t max_width,
+                             int32_t max_height, void* dev_persistent, void* dev_scratch,
+                             void* hip_stream, rl_room** out);
+
+/* Destroys the handle (the caller's buffers are left untouched). */
+rl_status relocaliser_destroy(rl_room* room);
+
+/*
+ * Online adaptation (Sec. 3.2.2): when reliable != 0, the pixels on the
+ * 4-pixel grid {(4i, 4j), i, j >= 1} with valid depth are routed through every
+ * tree and their world points x^W = H x^C (with colour) enter the reached
+ * leaves' reservoirs by Algorithm R; reliable == 0 is a no-op (the paper skips
+ * frames whose tracking is unreliable).  cam_to_world: host, 16 floats, must
+ * be rigid (|R^T R - I| <= 1e-3).  Asynchronous on the room's stream; the
+ * frame buffers must stay valid until that work has completed.
+ */
+rl_status relocaliser_adapt(rl_room* room, const rl_frame* frame, const float cam_to_world[16],
+                            int32_t reliable);
+
+/* Re-clusters every leaf whose reservoir changed since the last call (RQS).
+ * relocaliser_relocalise does this implicitly.  Asynchronous. */
+rl_status relocaliser_update_modes(rl_room* room);
+
+/*
+ * Relocalises one frame (Sec. 3.2.3): synchronous on the room's stream.
+ * request_seed selects the generator stream of this request (results do not
+ * depend on anything else).  Outputs (host): cam_to_world_out[16], energy_out
+ * = Eq. 5 energy of the winning hypothesis over the final pixel set (before
+ * any refit), mean_energy_out = energy / |I|.  Returns RL_OK, RL_NO_POSE or
+ * an error.
+ */
+rl_status relocaliser_relocalise(rl_room* room, const rl_frame* frame, uint64_t request_seed,
+                                 float cam_to_world_out[16], float* energy_out,
+                                 float* mean_energy_out);
+
+/* Result record (also the device-side layout written by the batch path). */
+typedef struct {
+    float cam_to_world[16];
+    float energy, mean_energy;
+    int32_t status;          /* RL_OK or RL_NO_POSE */
+    int32_t n_valid;         /* hypotheses that passed generation */
+    int32_t n_inliers;       /* refit inliers (0 without refit) */
+    int32_t winner;          /* winning hypothesis slot, -1 if none */
+    int32_t refitted;
+    int32_t n_eligible;      /* pixels with depth and at least one mode */
+    int32_t rounds;          /* RANSAC rounds run */
+    int32_t n_out;           /* hypotheses returned in the survivor list */
+    int32_t pad[2];
+} rl_result;
+
+/* Like relocaliser_relocalise but returns the full result record (host). */
+rl_status relocaliser_relocalise_ex(rl_room* room, const rl_frame* frame, uint64_t request_seed,
+                                    rl_result* out);
+
+/*
+ * Introspection for tests and tools: byte offset and size of an internal
+ * array inside the caller's persistent (*region = 0) or scratch (*region = 1)
+ * buffer.  which: see RL_BUF_* below.  Contents are valid after the stream
+ * work that produced them has completed.
+ */
+enum {
+    RL_BUF_NODES = 0,      /* rl_node[T][2^D-1]                                   persistent */
+    RL_BUF_RESERVOIR = 1,  /* float4[T][L][kappa]: x, y, z, colour bits             persistent */
+    RL_BUF_SEEN = 2,       /* uint32[T][L] arrivals per leaf                        persistent */
+    RL_BUF_MODES = 3,      /* float[T][L][M][16] mode rows                          persistent */
+    RL_BUF_NMODES = 4,     /* uint8[T][L]                                           persistent */
+    RL_BUF_LEAVES = 5,     /* uint16[w*h][8] leaf per tree, 0xFFFF = none           scratch    */
+    RL_BUF_NM = 6,         /* uint8[w*h] |M(u)|                                     scratch    */
+    RL_BUF_ELIGIBLE = 7,   /* int32[w*h] eligible pixels, raster order              scratch    */
+    RL_BUF_HYPS = 8,       /* hypothesis records (see rl_hypothesis)                scratch    */
+    RL_BUF_ILIST = 9,      /* int32[rounds*eta] scoring pixels I                    scratch    */
+    RL_BUF_TRACE_SLOTS = 10, /* int32[rounds][N] survivors after each round          scratch    */
+    RL_BUF_TRACE_ENERGY = 11,/* double[rounds][N] their energies                      scratch    */
+    RL_BUF_SURVIVORS = 12, /* int32[N] current survivor slots, best first           scratch    */
+    RL_BUF_ENERGY = 13,    /* double[N] energy per slot                             scratch    */
+    RL_BUF_DIRTY = 14      /* uint8[T][L] leaves awaiting re-clustering             persistent */
+};
+rl_status relocaliser_buffer(const rl_room* room, int32_t which, size_t* offset, size_t* bytes,
+                             int32_t* region);
+
+/* Hypothesis record layout of RL_BUF_HYPS (80 bytes). */
+typedef struct {
+    float R[9];       /* row-major rotation (camera -> world), rounded to float32 */
+    float t[3];
+    int32_t pix[3];   /* pixel indices y*w + x of the triplet */
+    int32_t mode[3];  /* index of the sampled mode within M(u) */
+    int32_t iter;     /* generation iteration that passed; -1 if none */
+    int32_t valid;
+} rl_hypothesis;
+
+/* Records survivors and energies of every RANSAC round (off by default). */
+rl_status relocaliser_set_trace(rl_room* room, int32_t on);
+
+/* ---------------------------------------------------------------------- */
+/* Batched relocalisation: many frames (any mix of rooms and resolutions)
+ * through one sequence of launches, optionally replayed from a HIP graph.  */
+
+typedef struct rl_batch rl_batch;
+
+typedef struct {
+    int32_t max_frames;      /* frames per submission                          */
+    int32_t max_width, max_height;
+    int32_t max_hypotheses;  /* largest N of any request                       */
+    int32_t max_eta;         /* largest eta                                    */
+    int32_t max_rounds;      /* largest number of RANSAC rounds                */
+    int32_t n_trees;         /* every room of a batch has this many trees      */
+    int32_t max_modes_per_pixel; /* largest n_trees * M_max                    */
+} rl_batch_params;
+
+typedef struct {
+    rl_room* room;
+    rl_frame frame;
+    uint64_t request_seed;
+    int32_t n_hypotheses;    /* 0 = the room's max_pose_candidates              */
+    int32_t pad;
+} rl_request;
+
+/* Device workspace bytes of a batch context (256-byte aligned buffer). */
+rl_status rl_batch_workspace_bytes(const rl_batch_params* bp, size_t* bytes);
+
+rl_status rl_batch_create(const rl_batch_params* bp, void* dev_workspace, void* hip_stream,
+                          rl_batch** out);
+rl_status rl_batch_destroy(rl_batch* b);
+
+/*
+ * Relocalises n <= max_frames requests with one launch sequence on the
+ * batch's stream.  Every room's modes are brought up to date first.  The
+ * result for request i is identical to relocaliser_relocalise_ex on the same
+ * room, frame and request_seed.  results: host array of n records; the call
+ * is synchronous.  use_graph != 0 captures the launch sequence for this batch
+ * shape once and replays it on later calls with the same shape.
+ */
+rl_status rl_batch_relocalise(rl_batch* b, const rl_request* reqs, int32_t n, rl_result* results,
+                              int32_t use_graph);
+
+/* Asynchronous form: results are written to dev_results (device, n records);
+ * completion is ordered on the batch's stream. */
+rl_status rl_batch_relocalise_async(rl_batch* b, const rl_request* reqs, int32_t n,
+                                    rl_result* dev_results, int32_t use_graph);
+
+/*
+ * Kernel timing: when kernel != RL_TIMER_NONE, the library records
+ * start_event just before and stop_event just after that kernel (or kernel
+ * group) on the stream it launches it on, in every later relocalisation of
+ * this room / batch (also inside captured graphs).  The events are the
+ * caller's hipEvent_t handles, created with timing enabled; read them with
+ * hipEventElapsedTime after the call has completed.
+ */
+enum {
+    RL_TIMER_NONE = 0,
+    RL_TIMER_TRAVERSE = 1,     /* features + routing of every pixel             */
+    RL_TIMER_HYP_SEARCH = 2,   /* hypothesis generation search                  */
+    RL_TIMER_RANSAC = 3        /* all scoring and selection rounds              */
+};
+rl_status relocaliser_set_timer(rl_room* room, int32_t kernel, void* start_event, void* stop_event);
+rl_status rl_batch_set_timer(rl_batch* b, int32_t kernel, void* start_event, void* stop_event);
+
+/* Thread-local message of the last error. */
+const char* rl_last_error(void);
+
+/* Library version string. */
+const char* rl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RL_H_ */

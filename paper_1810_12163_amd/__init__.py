@@ -1,0 +1,350 @@
+"""MI355X relocaliser: Python binding of librl.so (include/rl.h).
+
+Argument marshalling only: every step of the relocaliser runs in the HIP
+kernels of librl.so.  PyTorch provides the device memory (the room's
+persistent and scratch buffers are torch uint8 tensors) and the stream.  If
+the library has not been built, every entry point raises; there is no other
+implementation to fall back to.
+
+    room = Room(params, nodes, max_width=640, max_height=480)
+    room.adapt(depth, rgb, K, pose)           # torch cuda tensors, 4x4 pose
+    res = room.relocalise(depth, rgb, K, request_seed=0)
+    res["pose"], res["energy"], res["status"]
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librl.so")
+
+RL_OK, RL_NO_POSE, RL_EINVAL, RL_ENOMEM, RL_EDEVICE, RL_EBUSY = 0, 1, -1, -2, -3, -4
+
+(BUF_NODES, BUF_RESERVOIR, BUF_SEEN, BUF_MODES, BUF_NMODES, BUF_LEAVES, BUF_NM, BUF_ELIGIBLE,
+ BUF_HYPS, BUF_ILIST, BUF_TRACE_SLOTS, BUF_TRACE_ENERGY, BUF_SURVIVORS, BUF_ENERGY,
+ BUF_DIRTY) = range(15)
+
+HYP_DTYPE = np.dtype([("R", "<f4", (9,)), ("t", "<f4", (3,)), ("pix", "<i4", (3,)),
+                      ("mode", "<i4", (3,)), ("iter", "<i4"), ("valid", "<i4")])
+NODE_DTYPE = np.dtype([("dx", "<f4"), ("dy", "<f4"), ("tau", "<f4"), ("kind", "<u4")])
+
+
+class RlError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"librl status {status}: {message}")
+        self.status = status
+
+
+class Intrinsics(ctypes.Structure):
+    _fields_ = [("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float),
+                ("cy", ctypes.c_float)]
+
+
+class Frame(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("depth", ctypes.c_void_p), ("rgb", ctypes.c_void_p), ("K", Intrinsics)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("n_trees", ctypes.c_int32), ("depth", ctypes.c_int32), ("ref_width", ctypes.c_int32),
+        ("clusterer_sigma", ctypes.c_float), ("clusterer_tau", ctypes.c_float),
+        ("max_cluster_count", ctypes.c_int32), ("min_cluster_size", ctypes.c_int32),
+        ("reservoir_capacity", ctypes.c_int32),
+        ("max_candidate_generation_iterations", ctypes.c_int32),
+        ("max_pose_candidates", ctypes.c_int32), ("max_pose_candidates_after_cull", ctypes.c_int32),
+        ("ransac_inliers_per_iteration", ctypes.c_int32),
+        ("max_relocalisations_to_output", ctypes.c_int32),
+        ("use_prediction_covariance", ctypes.c_int32), ("pose_update", ctypes.c_int32),
+        ("final_refine", ctypes.c_int32),
+        ("min_squared_distance_between_sampled_modes", ctypes.c_float),
+        ("max_translation_error_for_correct_pose", ctypes.c_float),
+        ("max_colour_linf", ctypes.c_float), ("inlier_threshold", ctypes.c_float),
+        ("cov_regulariser", ctypes.c_float), ("seed", ctypes.c_uint64),
+    ]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("cam_to_world", ctypes.c_float * 16), ("energy", ctypes.c_float),
+                ("mean_energy", ctypes.c_float), ("status", ctypes.c_int32),
+                ("n_valid", ctypes.c_int32), ("n_inliers", ctypes.c_int32),
+                ("winner", ctypes.c_int32), ("refitted", ctypes.c_int32),
+                ("n_eligible", ctypes.c_int32), ("rounds", ctypes.c_int32),
+                ("n_out", ctypes.c_int32), ("pad", ctypes.c_int32 * 2)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("room", ctypes.c_void_p), ("frame", Frame), ("request_seed", ctypes.c_uint64),
+                ("n_hypotheses", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class BatchParams(ctypes.Structure):
+    _fields_ = [("max_frames", ctypes.c_int32), ("max_width", ctypes.c_int32),
+                ("max_height", ctypes.c_int32), ("max_hypotheses", ctypes.c_int32),
+                ("max_eta", ctypes.c_int32), ("max_rounds", ctypes.c_int32),
+                ("n_trees", ctypes.c_int32), ("max_modes_per_pixel", ctypes.c_int32)]
+
+
+# every symbol include/rl.h declares
+EXPORTS = [
+    "rl_params_preset", "rl_params_validate", "relocaliser_state_bytes", "relocaliser_create",
+    "relocaliser_destroy", "relocaliser_adapt", "relocaliser_update_modes",
+    "relocaliser_relocalise", "relocaliser_relocalise_ex", "relocaliser_buffer",
+    "relocaliser_set_trace", "rl_batch_workspace_bytes", "rl_batch_create", "rl_batch_destroy",
+    "rl_batch_relocalise", "rl_batch_relocalise_async", "rl_last_error", "rl_version",
+    "relocaliser_set_timer", "rl_batch_set_timer",
+]
+
+TIMER_NONE, TIMER_TRAVERSE, TIMER_HYP_SEARCH, TIMER_RANSAC = 0, 1, 2, 3
+
+_lib = None
+
+
+def lib():
+    """Loads librl.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1810_12163_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, U64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64
+        L.rl_params_preset.argtypes = [ctypes.c_char_p, ctypes.POINTER(Params)]
+        L.rl_params_validate.argtypes = [ctypes.POINTER(Params)]
+        L.relocaliser_state_bytes.argtypes = [ctypes.POINTER(Params), I32, I32,
+                                              ctypes.POINTER(ctypes.c_size_t),
+                                              ctypes.POINTER(ctypes.c_size_t)]
+        L.relocaliser_create.argtypes = [ctypes.POINTER(Params), P, I32, I32, P, P, P,
+                                         ctypes.POINTER(ctypes.c_void_p)]
+        L.relocaliser_destroy.argtypes = [P]
+        L.relocaliser_adapt.argtypes = [P, ctypes.POINTER(Frame), P, I32]
+        L.relocaliser_update_modes.argtypes = [P]
+        L.relocaliser_relocalise.argtypes = [P, ctypes.POINTER(Frame), U64, P, P, P]
+        L.relocaliser_relocalise_ex.argtypes = [P, ctypes.POINTER(Frame), U64, ctypes.POINTER(Result)]
+        L.relocaliser_buffer.argtypes = [P, I32, ctypes.POINTER(ctypes.c_size_t),
+                                         ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(I32)]
+        L.relocaliser_set_trace.argtypes = [P, I32]
+        L.rl_batch_workspace_bytes.argtypes = [ctypes.POINTER(BatchParams), ctypes.POINTER(ctypes.c_size_t)]
+        L.rl_batch_create.argtypes = [ctypes.POINTER(BatchParams), P, P, ctypes.POINTER(ctypes.c_void_p)]
+        L.rl_batch_destroy.argtypes = [P]
+        L.rl_batch_relocalise.argtypes = [P, P, I32, P, I32]
+        L.rl_batch_relocalise_async.argtypes = [P, P, I32, P, I32]
+        L.relocaliser_set_timer.argtypes = [P, I32, P, P]
+        L.rl_batch_set_timer.argtypes = [P, I32, P, P]
+        L.rl_last_error.restype = ctypes.c_char_p
+        L.rl_version.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            getattr(L, name)            # every declared entry point must resolve
+        _lib = L
+    return _lib
+
+
+def _check(status, allow=(RL_OK,)):
+    if status not in allow:
+        raise RlError(status, lib().rl_last_error().decode())
+    return status
+
+
+def params_struct(d: dict) -> Params:
+    p = Params()
+    for name, ctype in Params._fields_:
+        if name not in d:
+            raise KeyError(f"parameter {name} missing")
+        setattr(p, name, d[name])
+    return p
+
+
+def preset(name: str) -> dict:
+    p = Params()
+    _check(lib().rl_params_preset(name.encode(), ctypes.byref(p)))
+    return {n: getattr(p, n) for n, _ in Params._fields_}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _frame(depth, rgb, K) -> Frame:
+    torch = _torch()
+    if not (isinstance(depth, torch.Tensor) and isinstance(rgb, torch.Tensor)):
+        raise TypeError("depth and rgb must be torch tensors on the GPU")
+    if depth.dtype != torch.float32 or depth.dim() != 2 or not depth.is_cuda or not depth.is_contiguous():
+        raise TypeError("depth must be a contiguous (h, w) float32 CUDA tensor")
+    h, w = depth.shape
+    if rgb.dtype != torch.uint8 or tuple(rgb.shape) != (h, w, 3) or not rgb.is_cuda or not rgb.is_contiguous():
+        raise TypeError("rgb must be a contiguous (h, w, 3) uint8 CUDA tensor")
+    f = Frame()
+    f.width, f.height = int(w), int(h)
+    f.depth, f.rgb = depth.data_ptr(), rgb.data_ptr()
+    f.K = Intrinsics(*[float(v) for v in K])
+    return f
+
+
+def _result(r: Result) -> dict:
+    H = np.array(r.cam_to_world[:], dtype=np.float32).reshape(4, 4)
+    return dict(pose=H, energy=float(r.energy), mean_energy=float(r.mean_energy),
+                status="ok" if r.status == RL_OK else "no_pose", n_valid=int(r.n_valid),
+                n_inliers=int(r.n_inliers), winner=int(r.winner), refitted=bool(r.refitted),
+                n_eligible=int(r.n_eligible), rounds=int(r.rounds), n_out=int(r.n_out))
+
+
+class Room:
+    """One scene: forest, reservoirs and modes resident in device memory."""
+
+    def __init__(self, params: dict, nodes: np.ndarray, max_width: int = 640, max_height: int = 480,
+                 stream=None, device=None):
+        torch = _torch()
+        self.params = dict(params)
+        self._p = params_struct(params)
+        L = lib()
+        pb, sb = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(L.relocaliser_state_bytes(ctypes.byref(self._p), max_width, max_height,
+                                         ctypes.byref(pb), ctypes.byref(sb)))
+        self.device = torch.device(device if device is not None else "cuda")
+        self.persistent = torch.empty(pb.value, dtype=torch.uint8, device=self.device)
+        self.scratch = torch.empty(sb.value, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nodes = np.ascontiguousarray(nodes)
+        if nodes.dtype.itemsize != 16 or nodes.size != params["n_trees"] * ((1 << params["depth"]) - 1):
+            raise ValueError("nodes must hold n_trees * (2^depth - 1) 16-byte records")
+        self._nodes = nodes
+        h = ctypes.c_void_p()
+        _check(L.relocaliser_create(ctypes.byref(self._p), nodes.ctypes.data, max_width, max_height,
+                                    self.persistent.data_ptr(), self.scratch.data_ptr(),
+                                    self.stream.cuda_stream, ctypes.byref(h)))
+        self.handle = h.value
+        self.max_width, self.max_height = max_width, max_height
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().relocaliser_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def adapt(self, depth, rgb, K, pose, reliable: bool = True):
+        f = _frame(depth, rgb, K)
+        H = np.ascontiguousarray(np.asarray(pose, dtype=np.float32).reshape(16))
+        _check(lib().relocaliser_adapt(self.handle, ctypes.byref(f), H.ctypes.data, 1 if reliable else 0))
+
+    def update_modes(self):
+        _check(lib().relocaliser_update_modes(self.handle))
+
+    def relocalise(self, depth, rgb, K, request_seed: int = 0) -> dict:
+        f = _frame(depth, rgb, K)
+        r = Result()
+        _check(lib().relocaliser_relocalise_ex(self.handle, ctypes.byref(f), int(request_seed),
+                                               ctypes.byref(r)), allow=(RL_OK, RL_NO_POSE))
+        return _result(r)
+
+    def set_trace(self, on: bool):
+        _check(lib().relocaliser_set_trace(self.handle, 1 if on else 0))
+
+    def set_timer(self, kernel: int, start=None, stop=None):
+        """Record torch.cuda.Event pair (enable_timing=True) around a kernel."""
+        _check(lib().relocaliser_set_timer(self.handle, kernel, start.cuda_event if start else None,
+                                           stop.cuda_event if stop else None))
+
+    def buffer(self, which: int):
+        """torch uint8 view of an internal array (see RL_BUF_* in rl.h)."""
+        off, nb, reg = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_int32()
+        _check(lib().relocaliser_buffer(self.handle, which, ctypes.byref(off), ctypes.byref(nb),
+                                        ctypes.byref(reg)))
+        base = self.persistent if reg.value == 0 else self.scratch
+        return base[off.value:off.value + nb.value]
+
+    def buffer_np(self, which: int, dtype) -> np.ndarray:
+        self.stream.synchronize()
+        return self.buffer(which).cpu().numpy().view(dtype)
+
+
+class Batch:
+    """Many frames from several rooms in one launch sequence (optionally a HIP graph)."""
+
+    def __init__(self, max_frames: int, max_width: int, max_height: int, max_hypotheses: int,
+                 max_eta: int, max_rounds: int, n_trees: int, max_modes_per_pixel: int,
+                 stream=None, device=None):
+        torch = _torch()
+        self._bp = BatchParams(max_frames, max_width, max_height, max_hypotheses, max_eta,
+                               max_rounds, n_trees, max_modes_per_pixel)
+        nb = ctypes.c_size_t()
+        L = lib()
+        _check(L.rl_batch_workspace_bytes(ctypes.byref(self._bp), ctypes.byref(nb)))
+        self.device = torch.device(device if device is not None else "cuda")
+        self.workspace = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        # a stream of its own (default priority): graph capture cannot use the legacy stream
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        h = ctypes.c_void_p()
+        _check(L.rl_batch_create(ctypes.byref(self._bp), self.workspace.data_ptr(),
+                                 self.stream.cuda_stream, ctypes.byref(h)))
+        self.handle = h.value
+        self.max_frames = max_frames
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().rl_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_timer(self, kernel: int, start=None, stop=None):
+        """Record torch.cuda.Event pair (enable_timing=True) around a kernel."""
+        _check(lib().rl_batch_set_timer(self.handle, kernel, start.cuda_event if start else None,
+                                        stop.cuda_event if stop else None))
+
+    @staticmethod
+    def _requests(reqs):
+        arr = (Request * len(reqs))()
+        for i, q in enumerate(reqs):
+            room, depth, rgb, K = q[0], q[1], q[2], q[3]
+            seed = q[4] if len(q) > 4 else 0
+            nh = q[5] if len(q) > 5 else 0
+            arr[i].room = room.handle
+            arr[i].frame = _frame(depth, rgb, K)
+            arr[i].request_seed = int(seed)
+            arr[i].n_hypotheses = int(nh)
+        return arr
+
+    def relocalise(self, reqs, use_graph: bool = True) -> list:
+        """reqs: sequence of (room, depth, rgb, K[, request_seed[, n_hypotheses]])."""
+        arr = self._requests(reqs)
+        res = (Result * len(reqs))()
+        self.stream.wait_stream(_torch().cuda.current_stream(self.device))   # frames were made there
+        _check(lib().rl_batch_relocalise(self.handle, arr, len(reqs), res, 1 if use_graph else 0))
+        return [_result(r) for r in res]
+
+    def relocalise_async(self, reqs, dev_results, use_graph: bool = True):
+        """Queues the batch; dev_results: torch uint8 CUDA tensor of >= len(reqs) * sizeof(Result) bytes."""
+        arr = self._requests(reqs)
+        self.stream.wait_stream(_torch().cuda.current_stream(self.device))
+        _check(lib().rl_batch_relocalise_async(self.handle, arr, len(reqs), dev_results.data_ptr(),
+                                               1 if use_graph else 0))
+
+    @staticmethod
+    def decode(host_bytes: np.ndarray, n: int) -> list:
+        out = []
+        raw = np.ascontiguousarray(host_bytes).view(np.uint8)
+        for i in range(n):
+            r = Result.from_buffer_copy(raw[i * ctypes.sizeof(Result):(i + 1) * ctypes.sizeof(Result)].tobytes())
+            out.append(_result(r))
+        return out
+
+
+def rounds_for(N: int, n_cull: int, n_out: int) -> int:
+    """RANSAC rounds for N hypotheses (initial cull, then halving to n_out)."""
+    n, rounds, first = N, 0, True
+    while first or n > n_out:
+        keep = n_cull if (first and n_cull < n) else ((n + 1) // 2 if n > n_out else n)
+        n, rounds, first = keep, rounds + 1, False
+    return rounds

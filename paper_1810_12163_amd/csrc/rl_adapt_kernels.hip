@@ -1,0 +1,347 @@
+// rl_adapt_kernels.hip -- online forest adaptation and mode finding (gfx950).
+//
+// Adaptation (Sec. 3.2.2): grid pixels (4i, 4j), i, j >= 1, are routed
+// through every tree and their world points enter the reached leaves'
+// reservoirs by Algorithm R.  Arrivals at one leaf must be processed in the
+// canonical order (raster order within a frame), but each arrival's decision
+// depends only on its arrival number n (slot n-1 while n <= kappa, else a
+// Philox draw keyed by (tree, leaf, n)).  So the kernels compute every
+// arrival's n in parallel (rank of the pixel within its leaf's segment) and
+// resolve "later arrival wins" for slots hit twice in one frame, with no
+// per-slot atomics and a result independent of scheduling:
+//   k_ad_items   route, world point, per-leaf arrival counts
+//   k_ad_alloc   one segment per touched leaf
+//   k_ad_scatter items into their leaf segment (any order)
+//   k_ad_rank    rank by pixel index -> n -> slot or none
+//   k_ad_write   write unless a later arrival of the frame takes the same slot
+//   k_ad_cleanup clear the per-frame counters
+// Mode finding (Really Quick Shift, one workgroup per dirty leaf): k_rqs.
+#include <hip/hip_runtime.h>
+
+#include "rl_internal.hpp"
+
+namespace rl {
+
+template <int T>
+__global__ __launch_bounds__(256) void k_ad_items(AdaptArgs a)
+{
+#pragma clang fp contract(off)
+    const int g = blockIdx.x * 256 + threadIdx.x;
+    if (g >= a.G) return;
+    const int x = 4 * (g % a.gw + 1), y = 4 * (g / a.gw + 1);
+    const float d = a.depth[y * a.w + x];
+    if (!depth_ok(d)) {
+#pragma unroll
+        for (int t = 0; t < T; ++t) a.item_leaf[(size_t)t * a.G + g] = (uint16_t)kLeafNone;
+        return;
+    }
+    int leaf[T];
+    route<T>(a.nodes, a.L - 1, a.D, a.depth, a.rgb, a.w, a.h, x, y, d, a.s, leaf);
+    double xc[3];
+    backproject(d, x, y, a.fx, a.fy, a.cx, a.cy, xc);
+    float xw[3];
+    for (int r = 0; r < 3; ++r) {
+        double v = a.H[4 * r + 0] * xc[0] + a.H[4 * r + 1] * xc[1];
+        v = v + a.H[4 * r + 2] * xc[2];
+        v = v + a.H[4 * r + 3];
+        xw[r] = (float)v;
+    }
+    const uint8_t* c = a.rgb + 3 * (y * a.w + x);
+    const uint32_t col = (uint32_t)c[0] | ((uint32_t)c[1] << 8) | ((uint32_t)c[2] << 16);
+    a.item_pt[g] = make_float4(xw[0], xw[1], xw[2], __uint_as_float(col));
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const size_t tl = ((size_t)t << a.D) + leaf[t];
+        a.item_leaf[(size_t)t * a.G + g] = (uint16_t)leaf[t];
+        const uint32_t old = atomicAdd(&a.cnt[tl], 1u);
+        a.item_flag[(size_t)t * a.G + g] = old == 0 ? 1 : 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ad_alloc(AdaptArgs a)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;       // i = t * G + g
+    if (i >= a.T * a.G) return;
+    const int t = i / a.G;
+    const uint16_t lf = a.item_leaf[i];
+    if (lf == kLeafNone || !(a.item_flag[i] & 1)) return;
+    const size_t tl = ((size_t)t << a.D) + lf;
+    a.off[tl] = atomicAdd(&a.counters[1], a.cnt[tl]);
+}
+
+__global__ __launch_bounds__(256) void k_ad_scatter(AdaptArgs a)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= a.T * a.G) return;
+    const int t = i / a.G, g = i % a.G;
+    const uint16_t lf = a.item_leaf[i];
+    if (lf == kLeafNone) return;
+    const size_t tl = ((size_t)t << a.D) + lf;
+    const uint32_t pos = a.off[tl] + atomicAdd(&a.cursor[tl], 1u);
+    a.seg[pos] = g;
+}
+
+__global__ __launch_bounds__(256) void k_ad_rank(AdaptArgs a)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= a.T * a.G) return;
+    const int t = i / a.G, g = i % a.G;
+    const uint16_t lf = a.item_leaf[i];
+    if (lf == kLeafNone) return;
+    const size_t tl = ((size_t)t << a.D) + lf;
+    const uint32_t c = a.cnt[tl], base = a.off[tl];
+    uint32_t rank = 0;
+    for (uint32_t k = 0; k < c; ++k) rank += a.seg[base + k] < g ? 1u : 0u;
+    const uint32_t n = a.seen[tl] + rank + 1u;
+    int slot;
+    if (n <= (uint32_t)a.kappa) {
+        slot = (int)n - 1;
+    } else {
+        const uint4 r = philox(make_uint4(kTagRes << 28, (uint32_t)t, (uint32_t)lf, n), a.key0, a.key1);
+        const uint32_t j = below(r.x, n);
+        slot = j < (uint32_t)a.kappa ? (int)j : -1;
+    }
+    a.item_n[i] = n;
+    a.item_slot[i] = slot;
+    if (rank == c - 1) a.item_flag[i] |= 2;
+}
+
+__global__ __launch_bounds__(256) void k_ad_write(AdaptArgs a)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= a.T * a.G) return;
+    const int t = i / a.G, g = i % a.G;
+    const uint16_t lf = a.item_leaf[i];
+    if (lf == kLeafNone) return;
+    const size_t tl = ((size_t)t << a.D) + lf;
+    const int slot = a.item_slot[i];
+    const uint32_t n = a.item_n[i];
+    if (a.item_flag[i] & 2) a.seen[tl] = n;           // last arrival of the frame
+    if (slot < 0) return;
+    const uint32_t c = a.cnt[tl], base = a.off[tl];
+    for (uint32_t k = 0; k < c; ++k) {
+        const int g2 = a.seg[base + k];
+        const size_t i2 = (size_t)t * a.G + g2;
+        if (a.item_slot[i2] == slot && a.item_n[i2] > n) return;   // overwritten later
+    }
+    a.reservoir[tl * (size_t)a.kappa + (size_t)slot] = a.item_pt[g];
+    if (atomicExch(&a.dirty[tl], 1u) == 0u) {
+        const uint32_t k = atomicAdd(&a.counters[0], 1u);
+        a.dirty_list[k] = (uint32_t)tl;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ad_cleanup(AdaptArgs a)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i == 0) a.counters[1] = 0u;
+    if (i >= a.T * a.G) return;
+    const int t = i / a.G;
+    const uint16_t lf = a.item_leaf[i];
+    if (lf == kLeafNone) return;
+    const size_t tl = ((size_t)t << a.D) + lf;
+    a.cnt[tl] = 0u;
+    a.cursor[tl] = 0u;
+}
+
+// ------------------------------------------------------------------------
+// Really Quick Shift (Fulkerson & Soatto 2010) on one leaf reservoir per
+// workgroup iteration, with the paper's post-processing (Sec. 3.2.2 step 3):
+//   rho_k = sum_j exp(-|P_k - P_j|^2 / (2 sigma^2))   (FP64, j in order)
+//   parent(k) = nearest j with (rho_j, j) > (rho_k, k) and |P_k - P_j| < tau
+//   roots by pointer jumping; clusters of >= min_size points, at most M,
+//   ordered by (size desc, root asc); mean, population covariance, mean
+//   colour, inverse of (covariance + lambda I).
+// Distances are evaluated exactly as written (no contraction).
+__device__ __forceinline__ double dist2(float4 a, float4 b)
+{
+#pragma clang fp contract(off)
+    const double dx = (double)a.x - (double)b.x, dy = (double)a.y - (double)b.y, dz = (double)a.z - (double)b.z;
+    return dx * dx + dy * dy + dz * dz;
+}
+
+__device__ __forceinline__ double rqs_block_sum(double v, double* s_red)
+{
+    s_red[threadIdx.x] = v;
+    __syncthreads();
+    for (int stride = 128; stride > 0; stride >>= 1) {
+        if ((int)threadIdx.x < stride) s_red[threadIdx.x] += s_red[threadIdx.x + stride];
+        __syncthreads();
+    }
+    const double r = s_red[0];
+    __syncthreads();
+    return r;
+}
+
+// dynamic LDS: float4 pts[kappa], double rho[kappa], int parent[kappa], int root[kappa], int size[kappa]
+__global__ __launch_bounds__(256) void k_rqs(RqsArgs a)
+{
+    extern __shared__ unsigned char s_raw[];
+    float4* pts = reinterpret_cast<float4*>(s_raw);
+    double* rho = reinterpret_cast<double*>(s_raw + 16 * (size_t)a.kappa);
+    int* parent = reinterpret_cast<int*>(s_raw + 24 * (size_t)a.kappa);
+    int* root = parent + a.kappa;
+    int* size = root + a.kappa;
+    __shared__ double s_red[256];
+    __shared__ int s_chosen[64];
+    __shared__ int s_ncand;
+    const int tid = threadIdx.x;
+    const uint32_t ndirty = a.counters[0];
+    const double two_s2 = 2.0 * a.sigma * a.sigma;
+    const double tau2 = a.tau * a.tau;
+    for (uint32_t li = blockIdx.x; li < ndirty; li += gridDim.x) {
+        const uint32_t tl = a.dirty_list[li];
+        const int n = (int)min(a.seen[tl], (uint32_t)a.kappa);
+        const float4* src = a.reservoir + (size_t)tl * a.kappa;
+        for (int k = tid; k < n; k += 256) {
+            pts[k] = src[k];
+            size[k] = 0;
+        }
+        if (tid == 0) s_ncand = 0;
+        __syncthreads();
+        for (int k = tid; k < n; k += 256) {
+            const float4 pk = pts[k];
+            double acc = 0.0;
+            for (int j = 0; j < n; ++j) acc += exp(-dist2(pk, pts[j]) / two_s2);
+            rho[k] = acc;
+        }
+        __syncthreads();
+        for (int k = tid; k < n; k += 256) {
+            const float4 pk = pts[k];
+            const double rk = rho[k];
+            int best = -1;
+            double bestd = INFINITY;
+            for (int j = 0; j < n; ++j) {
+                const double rj = rho[j];
+                const bool higher = rj > rk || (rj == rk && j > k);
+                if (!higher) continue;
+                const double d2 = dist2(pk, pts[j]);
+                if (d2 < tau2 && d2 < bestd) {
+                    bestd = d2;
+                    best = j;
+                }
+            }
+            parent[k] = best;
+            root[k] = best < 0 ? k : best;
+        }
+        __syncthreads();
+        // pointer jumping: after ceil(log2 n) + 1 passes every point holds its root
+        for (int pass = 0; (1 << pass) <= 2 * n; ++pass) {
+            for (int k = tid; k < n; k += 256) {
+                const int r = root[k];
+                root[k] = root[r];
+            }
+            __syncthreads();
+        }
+        for (int k = tid; k < n; k += 256) atomicAdd(&size[root[k]], 1);
+        __syncthreads();
+        // candidates ranked by (size desc, root asc); keep ranks < M
+        for (int k = tid; k < n; k += 256) {
+            if (parent[k] >= 0 || size[k] < a.min_size) continue;
+            const int sk = size[k];
+            int rank = 0;
+            for (int j = 0; j < n; ++j) {
+                if (parent[j] >= 0 || size[j] < a.min_size) continue;
+                rank += (size[j] > sk || (size[j] == sk && j < k)) ? 1 : 0;
+            }
+            if (rank < a.M) s_chosen[rank] = k;
+            atomicAdd(&s_ncand, 1);
+        }
+        __syncthreads();
+        const int nm = min(s_ncand, a.M);
+        float4* out = a.modes + (size_t)tl * a.M * 4;
+        for (int m = 0; m < nm; ++m) {
+            const int r = s_chosen[m];
+            double sx = 0, sy = 0, sz = 0, cnt = 0, cr = 0, cg = 0, cb = 0;
+            for (int k = tid; k < n; k += 256) {
+                if (root[k] != r) continue;
+                const float4 pk = pts[k];
+                sx += pk.x; sy += pk.y; sz += pk.z; cnt += 1.0;
+                const uint32_t c = __float_as_uint(pk.w);
+                cr += (double)(c & 0xFFu);
+                cg += (double)((c >> 8) & 0xFFu);
+                cb += (double)((c >> 16) & 0xFFu);
+            }
+            cnt = rqs_block_sum(cnt, s_red);
+            const double mx = rqs_block_sum(sx, s_red) / cnt, my = rqs_block_sum(sy, s_red) / cnt,
+                         mz = rqs_block_sum(sz, s_red) / cnt;
+            const double mr = rqs_block_sum(cr, s_red) / cnt, mg = rqs_block_sum(cg, s_red) / cnt,
+                         mb = rqs_block_sum(cb, s_red) / cnt;
+            double S[6] = {0, 0, 0, 0, 0, 0};
+            for (int k = tid; k < n; k += 256) {
+                if (root[k] != r) continue;
+                const float4 pk = pts[k];
+                const double dx = (double)pk.x - mx, dy = (double)pk.y - my, dz = (double)pk.z - mz;
+                S[0] += dx * dx; S[1] += dx * dy; S[2] += dx * dz;
+                S[3] += dy * dy; S[4] += dy * dz; S[5] += dz * dz;
+            }
+            for (int q = 0; q < 6; ++q) S[q] = rqs_block_sum(S[q], s_red) / cnt;
+            if (tid == 0) {
+                const double A_ = S[0] + a.lambda, B_ = S[1], C_ = S[2], D_ = S[3] + a.lambda, E_ = S[4],
+                             F_ = S[5] + a.lambda;
+                const double ca = D_ * F_ - E_ * E_, cb2 = C_ * E_ - B_ * F_, cc = B_ * E_ - C_ * D_;
+                const double cd = A_ * F_ - C_ * C_, ce = B_ * C_ - A_ * E_, cf = A_ * D_ - B_ * B_;
+                const double det = A_ * ca + B_ * cb2 + C_ * cc;
+                float4* row = out + 4 * m;
+                row[0] = make_float4((float)mx, (float)my, (float)mz, (float)cnt);
+                row[1] = make_float4((float)(ca / det), (float)(cb2 / det), (float)(cc / det), (float)(cd / det));
+                row[2] = make_float4((float)(ce / det), (float)(cf / det), (float)mr, (float)mg);
+                row[3] = make_float4((float)mb, 0.0f, 0.0f, 0.0f);
+            }
+        }
+        if (tid == 0) {
+            a.nmodes[tl] = (uint8_t)nm;
+            a.dirty[tl] = 0u;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_rqs_done(RqsArgs a)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) a.counters[0] = 0u;
+}
+
+// ------------------------------------------------------------------------
+#define RL_CHECK_LAUNCH() do { hipError_t e_ = hipGetLastError(); if (e_ != hipSuccess) return e_; } while (0)
+
+hipError_t launch_adapt(const AdaptArgs& a, hipStream_t st)
+{
+    if (a.G <= 0) return hipSuccess;
+    const dim3 blk(256), g1((a.G + 255) / 256), gT((a.T * a.G + 255) / 256);
+    switch (a.T) {
+        case 1: k_ad_items<1><<<g1, blk, 0, st>>>(a); break;
+        case 2: k_ad_items<2><<<g1, blk, 0, st>>>(a); break;
+        case 3: k_ad_items<3><<<g1, blk, 0, st>>>(a); break;
+        case 4: k_ad_items<4><<<g1, blk, 0, st>>>(a); break;
+        case 5: k_ad_items<5><<<g1, blk, 0, st>>>(a); break;
+        case 6: k_ad_items<6><<<g1, blk, 0, st>>>(a); break;
+        case 7: k_ad_items<7><<<g1, blk, 0, st>>>(a); break;
+        case 8: k_ad_items<8><<<g1, blk, 0, st>>>(a); break;
+        default: return hipErrorInvalidValue;
+    }
+    RL_CHECK_LAUNCH();
+    k_ad_alloc<<<gT, blk, 0, st>>>(a);
+    RL_CHECK_LAUNCH();
+    k_ad_scatter<<<gT, blk, 0, st>>>(a);
+    RL_CHECK_LAUNCH();
+    k_ad_rank<<<gT, blk, 0, st>>>(a);
+    RL_CHECK_LAUNCH();
+    k_ad_write<<<gT, blk, 0, st>>>(a);
+    RL_CHECK_LAUNCH();
+    k_ad_cleanup<<<gT, blk, 0, st>>>(a);
+    RL_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_rqs(const RqsArgs& a, int blocks, hipStream_t st)
+{
+    const size_t lds = 36 * (size_t)a.kappa;
+    k_rqs<<<dim3(blocks), dim3(256), lds, st>>>(a);
+    RL_CHECK_LAUNCH();
+    k_rqs_done<<<dim3(1), dim3(64), 0, st>>>(a);
+    RL_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+}  // namespace rl

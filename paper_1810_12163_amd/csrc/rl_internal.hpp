@@ -1,0 +1,343 @@
+// rl_internal.hpp -- device-side data layout and helpers of librl (gfx950).
+//
+// Every relocalisation kernel reads a device-resident job table: one Job per
+// frame, holding the frame, the room's forest/mode arrays, the parameters
+// and that frame's scratch arrays.  A single frame is a batch of one; a
+// batch of frames from several rooms and resolutions is the same launch
+// sequence with gridDim.y = number of jobs.  Because the launch parameters
+// depend only on the batch shape, the sequence can be captured once in a HIP
+// graph and replayed with new job tables.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rl.h"
+
+namespace rl {
+
+constexpr int kMaxTrees = 8;
+constexpr int kLeafNone = 0xFFFF;
+constexpr uint32_t kTagRes = 1, kTagHyp = 2, kTagScore = 3;
+constexpr int kScoreLdsBytes = 64 * 1024;     // mode rows staged per scoring block
+constexpr int kMaxScoreTile = 16;             // pixels per scoring block
+
+struct JobState {
+    int n_elig;
+    int n_valid;
+    int n_surv;
+    int rounds_run;
+    int done;
+    int pad[3];
+};
+
+struct Hyp {                 // == rl_hypothesis
+    float R[9];
+    float t[3];
+    int pix[3];
+    int mode[3];
+    int iter;
+    int valid;
+};
+static_assert(sizeof(Hyp) == sizeof(rl_hypothesis), "hypothesis layout");
+
+struct Job {
+    // room (persistent)
+    const float4* nodes;      // [T][NT] (dx, dy, tau, kind bits)
+    const float4* modes;      // [T][L][M] rows of 4 float4
+    const uint8_t* nmodes;    // [T][L]
+    int T, D, M, pad0;
+    // frame
+    const float* depth;
+    const uint8_t* rgb;
+    int w, h;
+    float fx, fy, cx, cy;
+    float s;                  // w / ref_width (float32 division)
+    // parameters
+    int N, I_max, eta, n_cull, n_out, use_cov, final_refine, trace;
+    float theta_col;
+    int TP;                   // pixels per scoring block
+    double min_sq_dist, theta_rig, theta_in;
+    uint32_t key0, key1;
+    // scratch
+    uint16_t* leaves;         // [P][8]
+    uint8_t* nmt;             // [P][8] modes per tree's leaf
+    uint8_t* nm;              // [P] |M(u)|
+    int* tile_count;          // [ceil(P/256)]
+    int* eligible;            // [P]
+    int* hyp_best;            // [N]
+    Hyp* hyps;                // [N]
+    int* surv;                // [N]
+    double* E;                // [N] energy per slot
+    double* partial;          // [ptiles][N]
+    int* I;                   // [rounds_max * eta]
+    int* inl;                 // [rounds_max * eta] refit scratch
+    int* trace_slots;         // [rounds_max][N]
+    double* trace_E;          // [rounds_max][N]
+    JobState* st;
+    rl_result* result;
+};
+
+// Arguments of the adaptation kernels (one room, one frame; by value).
+struct AdaptArgs {
+    const float4* nodes;
+    int T, D, L, kappa;
+    const float* depth;
+    const uint8_t* rgb;
+    int w, h, gw, G;
+    float fx, fy, cx, cy, s;
+    double H[12];             // camera->world rows (from float32)
+    uint32_t key0, key1;
+    float4* reservoir;        // [T][L][kappa]
+    uint32_t* seen;           // [T][L]
+    uint32_t* dirty;          // [T][L]
+    uint32_t* dirty_list;     // [T*L]
+    uint32_t* counters;       // [0] dirty count, [1] segment allocator
+    // scratch
+    uint16_t* item_leaf;      // [T][G]
+    float4* item_pt;          // [G]
+    uint8_t* item_flag;       // [T][G] bit0 first arrival at its leaf, bit1 last
+    uint32_t* item_n;         // [T][G] arrival number n
+    int* item_slot;           // [T][G] reservoir slot written or -1
+    uint32_t* cnt;            // [T][L] arrivals this frame
+    uint32_t* cursor;         // [T][L]
+    uint32_t* off;            // [T][L] segment start
+    int* seg;                 // [T][G] items grouped by leaf
+};
+
+struct RqsArgs {
+    const float4* reservoir;
+    const uint32_t* seen;
+    uint32_t* dirty;
+    const uint32_t* dirty_list;
+    uint32_t* counters;
+    float4* modes;
+    uint8_t* nmodes;
+    int kappa, M, min_size;
+    double sigma, tau, lambda;
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): two 32x32->64 multiplies per round
+// on counter words 0 and 2, round keys bumped by the Weyl constants.
+__device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    }
+    return c;
+}
+
+// integer in [0, n): floor(r * n / 2^32)
+__device__ __forceinline__ uint32_t below(uint32_t r, uint32_t n) { return __umulhi(r, n); }
+
+__device__ __forceinline__ bool depth_ok(float d) { return d > 0.0f && d <= 3.0e38f; }
+
+// x^C = D(u) K^-1 (u, v, 1)^T in FP64, evaluated exactly as written.
+__device__ __forceinline__ void backproject(float d, int x, int y, float fx, float fy, float cx,
+                                            float cy, double out[3])
+{
+#pragma clang fp contract(off)
+    out[0] = (double)d * (((double)x - (double)cx) / (double)fx);
+    out[1] = (double)d * (((double)y - (double)cy) / (double)fy);
+    out[2] = (double)d;
+}
+
+// Routes pixel (x, y) with valid depth d through T trees in lockstep: at
+// every level all T node fetches and probe fetches are in flight together.
+// Float32 definition: offset = rint(delta * s * (1/d)), probe clamped to the
+// image, f = D(p) - D(q) or C(p,c) - C(q,c), right child iff f >= tau.
+template <int T>
+__device__ __forceinline__ void route(const float4* __restrict__ nodes, int NT, int D,
+                                      const float* __restrict__ depth,
+                                      const uint8_t* __restrict__ rgb, int w, int h, int x, int y,
+                                      float d, float s, int leaf[T])
+{
+    const float inv = 1.0f / d;
+    const int pc = y * w + x;
+    const float cc[3] = {(float)rgb[3 * pc], (float)rgb[3 * pc + 1], (float)rgb[3 * pc + 2]};
+    int idx[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) idx[t] = 0;
+    for (int lvl = 0; lvl < D; ++lvl) {
+        float4 nd[T];
+#pragma unroll
+        for (int t = 0; t < T; ++t) nd[t] = nodes[t * NT + idx[t]];
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            float fox = rintf((nd[t].x * s) * inv);
+            float foy = rintf((nd[t].y * s) * inv);
+            fox = fminf(fmaxf(fox, -1048576.0f), 1048576.0f);
+            foy = fminf(fmaxf(foy, -1048576.0f), 1048576.0f);
+            const int qx = min(max(x + (int)fox, 0), w - 1);
+            const int qy = min(max(y + (int)foy, 0), h - 1);
+            const int q = qy * w + qx;
+            const uint32_t kind = __float_as_uint(nd[t].w);
+            float f;
+            if (kind == 0u) {
+                f = d - depth[q];
+            } else {
+                const int c = (int)kind - 1;
+                f = cc[c] - (float)rgb[3 * q + c];
+            }
+            idx[t] = 2 * idx[t] + 1 + (f >= nd[t].z ? 1 : 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t) leaf[t] = idx[t] - NT;
+}
+
+// ---------------------------------------------------------------------------
+// Rigid fit from the cross-covariance A = sum (x^C - c^C)(x^W - c^W)^T.
+// Method: eigen-decomposition of A^T A by cyclic Jacobi rotations gives the
+// right singular vectors v1, v2 (largest two); u_k follow from A v_k
+// (Gram-Schmidt), and v3 = v1 x v2, u3 = u1 x u2 complete both bases as
+// rotations, so R = V U^T is the optimal proper rotation (the signed-SVD
+// form of the Kabsch solution).  Degenerate iff sigma_2 < 1e-4 sigma_1,
+// i.e. lambda_2 < 1e-8 lambda_1.  R maps camera to world: x^W ~ R x^C + t.
+template <int P, int Q>
+__device__ __forceinline__ void jacobi_rotate(double (&B)[3][3], double (&V)[3][3])
+{
+    constexpr int R = 3 - P - Q;
+    const double apq = B[P][Q];
+    if (apq == 0.0) return;
+    const double theta = (B[Q][Q] - B[P][P]) / (2.0 * apq);
+    const double tt = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+    const double c = 1.0 / sqrt(tt * tt + 1.0), sn = tt * c;
+    const double arp = B[R][P], arq = B[R][Q];
+    B[P][P] -= tt * apq;
+    B[Q][Q] += tt * apq;
+    B[P][Q] = B[Q][P] = 0.0;
+    B[R][P] = B[P][R] = c * arp - sn * arq;
+    B[R][Q] = B[Q][R] = sn * arp + c * arq;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double vp = V[i][P], vq = V[i][Q];
+        V[i][P] = c * vp - sn * vq;
+        V[i][Q] = sn * vp + c * vq;
+    }
+}
+
+// eigenpair (value, column) compare-swap so that the first is the larger
+__device__ __forceinline__ void eig_order(double& la, double (&va)[3], double& lb, double (&vb)[3])
+{
+    if (lb > la) {
+        const double tl = la;
+        la = lb;
+        lb = tl;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const double tv = va[i];
+            va[i] = vb[i];
+            vb[i] = tv;
+        }
+    }
+}
+
+__device__ __forceinline__ bool rigid_from_cov(const double A[9], const double cc[3], const double cw[3],
+                                               double R[9], double t[3])
+{
+    double B[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            B[i][j] = A[0 * 3 + i] * A[0 * 3 + j] + A[1 * 3 + i] * A[1 * 3 + j] + A[2 * 3 + i] * A[2 * 3 + j];
+    double V[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    for (int sweep = 0; sweep < 32; ++sweep) {
+        const double off = B[0][1] * B[0][1] + B[0][2] * B[0][2] + B[1][2] * B[1][2];
+        const double dia = B[0][0] * B[0][0] + B[1][1] * B[1][1] + B[2][2] * B[2][2];
+        if (off <= 1e-32 * dia || off == 0.0) break;
+        jacobi_rotate<0, 1>(B, V);
+        jacobi_rotate<0, 2>(B, V);
+        jacobi_rotate<1, 2>(B, V);
+    }
+    double l[3] = {B[0][0], B[1][1], B[2][2]};
+    double v1[3], v2[3], v3[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        v1[i] = V[i][0];
+        v2[i] = V[i][1];
+        v3[i] = V[i][2];
+    }
+    eig_order(l[0], v1, l[1], v2);
+    eig_order(l[1], v2, l[2], v3);
+    eig_order(l[0], v1, l[1], v2);
+    if (!(l[0] > 0.0) || l[1] < 1e-8 * l[0]) return false;
+    v3[0] = v1[1] * v2[2] - v1[2] * v2[1];
+    v3[1] = v1[2] * v2[0] - v1[0] * v2[2];
+    v3[2] = v1[0] * v2[1] - v1[1] * v2[0];
+    double u1[3], u2[3], u3[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        u1[i] = A[i * 3 + 0] * v1[0] + A[i * 3 + 1] * v1[1] + A[i * 3 + 2] * v1[2];
+        u2[i] = A[i * 3 + 0] * v2[0] + A[i * 3 + 1] * v2[1] + A[i * 3 + 2] * v2[2];
+    }
+    const double n1 = sqrt(u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]);
+    if (!(n1 > 0.0)) return false;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) u1[i] /= n1;
+    const double pr = u1[0] * u2[0] + u1[1] * u2[1] + u1[2] * u2[2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) u2[i] -= pr * u1[i];
+    const double n2 = sqrt(u2[0] * u2[0] + u2[1] * u2[1] + u2[2] * u2[2]);
+    if (!(n2 > 0.0)) return false;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) u2[i] /= n2;
+    u3[0] = u1[1] * u2[2] - u1[2] * u2[1];
+    u3[1] = u1[2] * u2[0] - u1[0] * u2[2];
+    u3[2] = u1[0] * u2[1] - u1[1] * u2[0];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) R[i * 3 + j] = v1[i] * u1[j] + v2[i] * u2[j] + v3[i] * u3[j];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        t[i] = cw[i] - (R[i * 3 + 0] * cc[0] + R[i * 3 + 1] * cc[1] + R[i * 3 + 2] * cc[2]);
+    return true;
+}
+
+// Per-pixel leaf record: 8 x uint16 leaves packed in a uint4, 8 x uint8 mode
+// counts packed in a uint2.  Extraction by shifts keeps runtime tree indices
+// in registers (no private-memory arrays).
+__device__ __forceinline__ uint32_t leaf_of(uint4 lw, int t)
+{
+    const uint64_t v = t < 4 ? (((uint64_t)lw.y << 32) | lw.x) : (((uint64_t)lw.w << 32) | lw.z);
+    return (uint32_t)(v >> (16 * (t & 3))) & 0xFFFFu;
+}
+
+__device__ __forceinline__ uint32_t count_of(uint2 nw, int t)
+{
+    const uint64_t v = ((uint64_t)nw.y << 32) | nw.x;
+    return (uint32_t)(v >> (8 * t)) & 0xFFu;
+}
+
+__device__ __forceinline__ int modes_total(uint2 nw, int T)
+{
+    int n = 0;
+    for (int t = 0; t < T; ++t) n += (int)count_of(nw, t);
+    return n;
+}
+
+// Mode row m of M(u), the tree-major concatenation of the leaves' modes.
+__device__ __forceinline__ const float4* mode_row(const float4* __restrict__ modes, int T, int D,
+                                                  int M, uint4 lw, uint2 nw, int m)
+{
+    int t = 0;
+    for (; t < T - 1; ++t) {
+        const int c = (int)count_of(nw, t);
+        if (m < c) break;
+        m -= c;
+    }
+    const size_t row = (((size_t)t << D) + leaf_of(lw, t)) * (size_t)M + (size_t)m;
+    return modes + row * 4;
+}
+
+}  // namespace rl

@@ -1,0 +1,658 @@
+// rl_reloc_kernels.hip -- per-frame relocalisation kernels (gfx950, wave64).
+//
+// Pipeline per frame (Sec. 3.2.3 of Cavallari et al., TPAMI 2019):
+//   k_prep          clear per-frame state
+//   k_traverse      features + routing of every pixel through every tree (Eq. 1-3)
+//   k_eligible      raster-order list of pixels with depth and >= 1 mode
+//   k_hyp_search    hypothesis generation: all (slot, 256-iteration chunk)
+//                   pairs in parallel, first passing iteration by atomicMin
+//   k_hyp_finalize  rebuild each slot's winning triplet, Kabsch pose
+//   k_ransac_init   survivors = valid slots in slot order
+//   k_score/k_select  one preemptive-RANSAC round each (Eq. 5, halving)
+//   k_finalize      winner, optional refit over inliers, result record
+#include <hip/hip_runtime.h>
+#include <limits.h>
+
+#include "rl_internal.hpp"
+
+namespace rl {
+
+__device__ __forceinline__ int wave_lane() { return threadIdx.x & 63; }
+
+// exclusive prefix of a predicate within a block of 256 threads (4 waves);
+// returns the prefix, writes the block total to *total.
+__device__ __forceinline__ int block_prefix256(bool pred, int* s_wave, int* total)
+{
+    const unsigned long long b = __ballot(pred);
+    const int lane = wave_lane(), wv = threadIdx.x >> 6;
+    const int below_lane = __popcll(b & ((1ull << lane) - 1ull));
+    if (lane == 0) s_wave[wv] = __popcll(b);
+    __syncthreads();
+    int base = 0, tot = 0;
+    for (int i = 0; i < 4; ++i) {
+        if (i < wv) base += s_wave[i];
+        tot += s_wave[i];
+    }
+    __syncthreads();
+    *total = tot;
+    return base + below_lane;
+}
+
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_prep(const Job* __restrict__ jobs)
+{
+    const Job& J = jobs[blockIdx.y];
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s < J.N) J.hyp_best[s] = INT_MAX;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        J.st->n_elig = 0;
+        J.st->n_valid = 0;
+        J.st->n_surv = 0;
+        J.st->rounds_run = 0;
+        J.st->done = 1;
+    }
+}
+
+// ------------------------------------------------------------------------
+// One thread per pixel, all trees in lockstep.  Writes leaves (16 B/pixel),
+// per-tree mode counts (8 B/pixel), |M(u)| and the tile's eligible count.
+template <int T>
+__global__ __launch_bounds__(256) void k_traverse(const Job* __restrict__ jobs)
+{
+    const Job& J = jobs[blockIdx.y];
+    const int w = J.w, h = J.h, P = w * h;
+    if ((int)blockIdx.x * 256 >= P) return;
+    __shared__ int s_wave[4];
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    bool elig = false;
+    if (p < P) {
+        const int x = p % w, y = p / w;
+        const float d = J.depth[p];
+        uint16_t lf[8];
+        uint8_t nmt[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            lf[t] = (uint16_t)kLeafNone;
+            nmt[t] = 0;
+        }
+        int total = 0;
+        if (depth_ok(d)) {
+            const int NT = (1 << J.D) - 1;
+            int leaf[T];
+            route<T>(J.nodes, NT, J.D, J.depth, J.rgb, w, h, x, y, d, J.s, leaf);
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                lf[t] = (uint16_t)leaf[t];
+                const int c = J.nmodes[((size_t)t << J.D) + leaf[t]];
+                nmt[t] = (uint8_t)c;
+                total += c;
+            }
+        }
+        uint4 lw;
+        lw.x = (uint32_t)lf[0] | ((uint32_t)lf[1] << 16);
+        lw.y = (uint32_t)lf[2] | ((uint32_t)lf[3] << 16);
+        lw.z = (uint32_t)lf[4] | ((uint32_t)lf[5] << 16);
+        lw.w = (uint32_t)lf[6] | ((uint32_t)lf[7] << 16);
+        reinterpret_cast<uint4*>(J.leaves)[p] = lw;
+        uint2 nw;
+        nw.x = (uint32_t)nmt[0] | ((uint32_t)nmt[1] << 8) | ((uint32_t)nmt[2] << 16) | ((uint32_t)nmt[3] << 24);
+        nw.y = (uint32_t)nmt[4] | ((uint32_t)nmt[5] << 8) | ((uint32_t)nmt[6] << 16) | ((uint32_t)nmt[7] << 24);
+        reinterpret_cast<uint2*>(J.nmt)[p] = nw;
+        J.nm[p] = (uint8_t)min(total, 255);
+        elig = total > 0;
+    }
+    int tot;
+    (void)block_prefix256(elig, s_wave, &tot);
+    if (threadIdx.x == 0) J.tile_count[blockIdx.x] = tot;
+}
+
+// Raster-order compaction of eligible pixels over the traversal's tiles.
+__global__ __launch_bounds__(256) void k_eligible(const Job* __restrict__ jobs)
+{
+    const Job& J = jobs[blockIdx.y];
+    const int P = J.w * J.h;
+    const int ntiles = (P + 255) / 256;
+    if ((int)blockIdx.x >= ntiles) return;
+    __shared__ int s_wave[4];
+    __shared__ int s_red[256];
+    int acc = 0;
+    for (int j = threadIdx.x; j < (int)blockIdx.x; j += 256) acc += J.tile_count[j];
+    s_red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int stride = 128; stride > 0; stride >>= 1) {
+        if ((int)threadIdx.x < stride) s_red[threadIdx.x] += s_red[threadIdx.x + stride];
+        __syncthreads();
+    }
+    const int base = s_red[0];
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    const bool e = p < P && J.nm[p] > 0;
+    int tot;
+    const int pre = block_prefix256(e, s_wave, &tot);
+    if (e) J.eligible[base + pre] = p;
+    if ((int)blockIdx.x == ntiles - 1 && threadIdx.x == 0) J.st->n_elig = base + tot;
+}
+
+// ------------------------------------------------------------------------
+// One generation iteration (Sec. 3.2.3): three pixels and one mode each from
+// Philox counters (HYP|blk, slot, it, 0), blk = 0, 1; the colour check on the
+// drawn pair, the minimum-distance check, the rigidity check, then Kabsch.
+// The check quantities are evaluated exactly as written (no contraction).
+template <bool WRITE>
+__device__ __forceinline__ bool hyp_try(const Job& J, int n_elig, int slot, int it, Hyp* out)
+{
+#pragma clang fp contract(off)
+    const uint4 a = philox(make_uint4((kTagHyp << 28) | 0u, (uint32_t)slot, (uint32_t)it, 0u), J.key0, J.key1);
+    const uint4 b = philox(make_uint4((kTagHyp << 28) | 1u, (uint32_t)slot, (uint32_t)it, 0u), J.key0, J.key1);
+    const uint32_t rp[3] = {a.x, a.y, a.z}, rm[3] = {a.w, b.x, b.y};
+    const int kc = (int)below(b.z, 3u);
+    int pix[3], mi[3];
+    double xc[3][3], xw[3][3];
+    const float4* crow = nullptr;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int p = J.eligible[below(rp[k], (uint32_t)n_elig)];
+        pix[k] = p;
+        const uint4 lw = reinterpret_cast<const uint4*>(J.leaves)[p];
+        const uint2 nw = reinterpret_cast<const uint2*>(J.nmt)[p];
+        mi[k] = (int)below(rm[k], (uint32_t)modes_total(nw, J.T));
+        const float4* row = mode_row(J.modes, J.T, J.D, J.M, lw, nw, mi[k]);
+        if (k == kc) crow = row;
+        const float4 mu = row[0];
+        xw[k][0] = mu.x;
+        xw[k][1] = mu.y;
+        xw[k][2] = mu.z;
+        backproject(J.depth[p], p % J.w, p / J.w, J.fx, J.fy, J.cx, J.cy, xc[k]);
+    }
+    // check 1: colour of the drawn pair
+    {
+        const float4 c2 = crow[2], c3 = crow[3];
+        const int pc = kc == 0 ? pix[0] : kc == 1 ? pix[1] : pix[2];
+        const uint8_t* px = J.rgb + 3 * pc;
+        if (fabsf((float)px[0] - c2.z) > J.theta_col || fabsf((float)px[1] - c2.w) > J.theta_col ||
+            fabsf((float)px[2] - c3.x) > J.theta_col)
+            return false;
+    }
+    // checks 2 and 3
+    const int PA[3] = {0, 0, 1}, PB[3] = {1, 2, 2};
+    double dw2[3], dc2[3];
+    bool ok = true;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        double dx = xw[PA[q]][0] - xw[PB[q]][0], dy = xw[PA[q]][1] - xw[PB[q]][1], dz = xw[PA[q]][2] - xw[PB[q]][2];
+        dw2[q] = dx * dx + dy * dy + dz * dz;
+        dx = xc[PA[q]][0] - xc[PB[q]][0];
+        dy = xc[PA[q]][1] - xc[PB[q]][1];
+        dz = xc[PA[q]][2] - xc[PB[q]][2];
+        dc2[q] = dx * dx + dy * dy + dz * dz;
+        if (dw2[q] < J.min_sq_dist) ok = false;
+    }
+    if (!ok) return false;
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+        if (fabs(sqrt(dc2[q]) - sqrt(dw2[q])) > J.theta_rig) ok = false;
+    if (!ok) return false;
+    double cc[3], cw[3], A[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        cc[i] = (xc[0][i] + xc[1][i] + xc[2][i]) / 3.0;
+        cw[i] = (xw[0][i] + xw[1][i] + xw[2][i]) / 3.0;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            A[i * 3 + j] = (xc[0][i] - cc[i]) * (xw[0][j] - cw[j]) + (xc[1][i] - cc[i]) * (xw[1][j] - cw[j])
+                         + (xc[2][i] - cc[i]) * (xw[2][j] - cw[j]);
+    double R[9], t[3];
+    if (!rigid_from_cov(A, cc, cw, R, t)) return false;
+    if (WRITE) {
+        for (int i = 0; i < 9; ++i) out->R[i] = (float)R[i];
+        for (int i = 0; i < 3; ++i) out->t[i] = (float)t[i];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            out->pix[k] = pix[k];
+            out->mode[k] = mi[k];
+        }
+    }
+    return true;
+}
+
+// grid.x = Nmax * chunks (chunk-major), 256 iterations per block.  A block
+// whose chunk starts after an already-found passing iteration exits early;
+// the minimum is exact because every lower iteration is always evaluated.
+__global__ __launch_bounds__(256) void k_hyp_search(const Job* __restrict__ jobs, int Nmax)
+{
+    const Job& J = jobs[blockIdx.y];
+    const int slot = blockIdx.x % Nmax, chunk = blockIdx.x / Nmax;
+    if (slot >= J.N) return;
+    const int it0 = chunk * 256;
+    if (it0 >= J.I_max) return;
+    const int n_elig = J.st->n_elig;
+    if (n_elig <= 0) return;
+    if (__hip_atomic_load(&J.hyp_best[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < it0) return;
+    const int it = it0 + threadIdx.x;
+    const bool pass = it < J.I_max && hyp_try<false>(J, n_elig, slot, it, nullptr);
+    __shared__ int s_min[4];
+    const unsigned long long bal = __ballot(pass);
+    if (wave_lane() == 0) s_min[threadIdx.x >> 6] = bal ? it0 + (threadIdx.x & ~63) + __ffsll((long long)bal) - 1 : INT_MAX;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int m = min(min(s_min[0], s_min[1]), min(s_min[2], s_min[3]));
+        if (m != INT_MAX) atomicMin(&J.hyp_best[slot], m);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_hyp_finalize(const Job* __restrict__ jobs)
+{
+    const Job& J = jobs[blockIdx.y];
+    const int slot = blockIdx.x * 256 + threadIdx.x;
+    if (slot >= J.N) return;
+    Hyp hy;
+    for (int i = 0; i < 9; ++i) hy.R[i] = 0.0f;
+    for (int i = 0; i < 3; ++i) {
+        hy.t[i] = 0.0f;
+        hy.pix[i] = -1;
+        hy.mode[i] = -1;
+    }
+    hy.iter = -1;
+    hy.valid = 0;
+    const int best = J.hyp_best[slot];
+    const int n_elig = J.st->n_elig;
+    if (best < J.I_max && n_elig > 0 && hyp_try<true>(J, n_elig, slot, best, &hy)) {
+        hy.iter = best;
+        hy.valid = 1;
+        atomicAdd(&J.st->n_valid, 1);
+    }
+    J.hyps[slot] = hy;
+}
+
+// Survivors = valid slots in ascending slot order; energies cleared.
+__global__ __launch_bounds__(256) void k_ransac_init(const Job* __restrict__ jobs)
+{
+    const Job& J = jobs[blockIdx.y];
+    __shared__ int s_wave[4];
+    int base = 0;
+    for (int s0 = 0; s0 < J.N; s0 += 256) {
+        const int s = s0 + threadIdx.x;
+        const bool v = s < J.N && J.hyps[s].valid;
+        if (s < J.N) J.E[s] = 0.0;
+        int tot;
+        const int pre = block_prefix256(v, s_wave, &tot);
+        if (v) J.surv[base + pre] = s;
+        base += tot;
+    }
+    if (threadIdx.x == 0) {
+        J.st->n_surv = base;
+        J.st->rounds_run = 0;
+        J.st->done = (base == 0 || J.st->n_elig <= 0) ? 1 : 0;
+    }
+}
+
+// ------------------------------------------------------------------------
+// One scoring round: grid.x = ptiles * htiles.  A block stages TP of this
+// round's pixels (back-projection and every mode of M(u) in FP64) in LDS and
+// each thread accumulates one survivor's Eq. 5 terms over them; all lanes
+// read the same mode row, so LDS reads are broadcasts.
+__global__ __launch_bounds__(256) void k_score(const Job* __restrict__ jobs, int round, int nptiles)
+{
+    const Job& J = jobs[blockIdx.y];
+    if (J.st->done) return;
+    const int n = J.st->n_surv;
+    const int ptile = blockIdx.x % nptiles, htile = blockIdx.x / nptiles;
+    const int TP = J.TP;
+    const int k0 = ptile * TP;
+    if (k0 >= J.eta || htile * 256 >= n) return;
+    const int tp = min(TP, J.eta - k0);
+    extern __shared__ double s_rows[];               // 9 doubles per mode row
+    __shared__ double s_x[kMaxScoreTile][3];
+    __shared__ uint4 s_lw[kMaxScoreTile];
+    __shared__ uint2 s_nw[kMaxScoreTile];
+    __shared__ int s_off[kMaxScoreTile + 1];
+    const int tid = threadIdx.x;
+    if (tid < tp) {
+        const int k = k0 + tid;
+        const uint4 rb = philox(make_uint4(kTagScore << 28, (uint32_t)round, (uint32_t)(k >> 2), 0u), J.key0, J.key1);
+        const uint32_t rv = (k & 3) == 0 ? rb.x : (k & 3) == 1 ? rb.y : (k & 3) == 2 ? rb.z : rb.w;
+        const int p = J.eligible[below(rv, (uint32_t)J.st->n_elig)];
+        if (htile == 0) J.I[round * J.eta + k] = p;
+        backproject(J.depth[p], p % J.w, p / J.w, J.fx, J.fy, J.cx, J.cy, s_x[tid]);
+        s_lw[tid] = reinterpret_cast<const uint4*>(J.leaves)[p];
+        s_nw[tid] = reinterpret_cast<const uint2*>(J.nmt)[p];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int o = 0;
+        for (int i = 0; i < tp; ++i) {
+            s_off[i] = o;
+            o += modes_total(s_nw[i], J.T);
+        }
+        s_off[tp] = o;
+    }
+    __syncthreads();
+    const int nrows = s_off[tp];
+    for (int j = tid; j < nrows; j += 256) {
+        int i = 0;
+        while (s_off[i + 1] <= j) ++i;
+        const float4* row = mode_row(J.modes, J.T, J.D, J.M, s_lw[i], s_nw[i], j - s_off[i]);
+        const float4 a = row[0], b = row[1], c = row[2];
+        double* o = s_rows + 9 * j;
+        o[0] = a.x; o[1] = a.y; o[2] = a.z;
+        o[3] = b.x; o[4] = b.y; o[5] = b.z; o[6] = b.w; o[7] = c.x; o[8] = c.y;
+    }
+    __syncthreads();
+    const int pos = htile * 256 + tid;
+    if (pos >= n) return;
+    const int slot = J.surv[pos];
+    const Hyp& hy = J.hyps[slot];
+    double R[9], t[3];
+    for (int i = 0; i < 9; ++i) R[i] = hy.R[i];
+    for (int i = 0; i < 3; ++i) t[i] = hy.t[i];
+    const bool cov = J.use_cov != 0;
+    double acc = 0.0;
+    for (int i = 0; i < tp; ++i) {
+        const double x0 = s_x[i][0], x1 = s_x[i][1], x2 = s_x[i][2];
+        const double y0 = R[0] * x0 + R[1] * x1 + R[2] * x2 + t[0];
+        const double y1 = R[3] * x0 + R[4] * x1 + R[5] * x2 + t[1];
+        const double y2 = R[6] * x0 + R[7] * x1 + R[8] * x2 + t[2];
+        double best = INFINITY;
+        for (int j = s_off[i]; j < s_off[i + 1]; ++j) {
+            const double* m = s_rows + 9 * j;
+            const double d0 = y0 - m[0], d1 = y1 - m[1], d2 = y2 - m[2];
+            double q;
+            if (cov)
+                q = d0 * (m[3] * d0 + m[4] * d1 + m[5] * d2) + d1 * (m[4] * d0 + m[6] * d1 + m[7] * d2)
+                  + d2 * (m[5] * d0 + m[7] * d1 + m[8] * d2);
+            else
+                q = d0 * d0 + d1 * d1 + d2 * d2;
+            best = fmin(best, q);
+        }
+        acc += sqrt(fmax(best, 0.0));
+    }
+    J.partial[(size_t)ptile * J.N + pos] = acc;
+}
+
+// Adds the round's partial sums (tile order), ranks survivors by
+// (energy, slot) and keeps the initial cull or the better half.
+__global__ __launch_bounds__(1024) void k_select(const Job* __restrict__ jobs, int round, int nptiles)
+{
+    const Job& J = jobs[blockIdx.y];
+    if (J.st->done) return;
+    extern __shared__ unsigned char s_raw[];
+    const int n = J.st->n_surv;
+    double* sE = reinterpret_cast<double*>(s_raw);
+    int* sS = reinterpret_cast<int*>(s_raw + sizeof(double) * (size_t)J.N);
+    const int ptiles = min(nptiles, (J.eta + J.TP - 1) / J.TP);
+    for (int p = threadIdx.x; p < n; p += blockDim.x) {
+        const int s = J.surv[p];
+        double acc = 0.0;
+        for (int tI = 0; tI < ptiles; ++tI) acc += J.partial[(size_t)tI * J.N + p];
+        const double e = J.E[s] + acc;
+        J.E[s] = e;
+        sE[p] = isnan(e) ? INFINITY : e;
+        sS[p] = s;
+    }
+    __syncthreads();
+    int keep;
+    if (round == 0 && J.n_cull < n) keep = J.n_cull;
+    else if (n > J.n_out) keep = (n + 1) / 2;
+    else keep = n;
+    for (int p = threadIdx.x; p < n; p += blockDim.x) {
+        const double e = sE[p];
+        const int s = sS[p];
+        int rank = 0;
+        for (int q = 0; q < n; ++q) {
+            const double eq = sE[q];
+            rank += (eq < e || (eq == e && sS[q] < s)) ? 1 : 0;
+        }
+        if (rank < keep) {
+            J.surv[rank] = s;
+            if (J.trace) {
+                J.trace_slots[(size_t)round * J.N + rank] = s;
+                J.trace_E[(size_t)round * J.N + rank] = e;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        J.st->n_surv = keep;
+        J.st->rounds_run = round + 1;
+        J.st->done = keep <= J.n_out ? 1 : 0;
+    }
+}
+
+// ------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum256(double v, double* s_red)
+{
+    s_red[threadIdx.x] = v;
+    __syncthreads();
+    for (int stride = 128; stride > 0; stride >>= 1) {
+        if ((int)threadIdx.x < stride) s_red[threadIdx.x] += s_red[threadIdx.x + stride];
+        __syncthreads();
+    }
+    const double r = s_red[0];
+    __syncthreads();
+    return r;
+}
+
+// Winner, optional refit over inliers, result record.
+__global__ __launch_bounds__(256) void k_finalize(const Job* __restrict__ jobs)
+{
+    const Job& J = jobs[blockIdx.y];
+    __shared__ double s_red[256];
+    __shared__ double s_pose[12];
+    __shared__ int s_refit;
+    rl_result* res = J.result;
+    const int n = J.st->n_surv;
+    const int rounds = J.st->rounds_run;
+    if (n <= 0 || rounds <= 0) {
+        if (threadIdx.x < 16) res->cam_to_world[threadIdx.x] = (threadIdx.x % 5 == 0) ? 1.0f : 0.0f;
+        if (threadIdx.x == 0) {
+            res->energy = INFINITY;
+            res->mean_energy = INFINITY;
+            res->status = RL_NO_POSE;
+            res->n_valid = J.st->n_valid;
+            res->n_inliers = 0;
+            res->winner = -1;
+            res->refitted = 0;
+            res->n_eligible = J.st->n_elig;
+            res->rounds = rounds;
+            res->n_out = 0;
+        }
+        return;
+    }
+    const int win = J.surv[0];
+    const Hyp& hy = J.hyps[win];
+    if (threadIdx.x < 9) s_pose[threadIdx.x] = hy.R[threadIdx.x];
+    if (threadIdx.x < 3) s_pose[9 + threadIdx.x] = hy.t[threadIdx.x];
+    if (threadIdx.x == 0) s_refit = 0;
+    __syncthreads();
+    const int nI = rounds * J.eta;
+    int n_inl = 0;
+    if (J.final_refine) {
+        double R[9], t[3];
+        for (int i = 0; i < 9; ++i) R[i] = s_pose[i];
+        for (int i = 0; i < 3; ++i) t[i] = s_pose[9 + i];
+        double sc[3] = {0, 0, 0}, sw[3] = {0, 0, 0}, cnt = 0;
+        for (int k = threadIdx.x; k < nI; k += 256) {
+            const int p = J.I[k];
+            double x[3];
+            backproject(J.depth[p], p % J.w, p / J.w, J.fx, J.fy, J.cx, J.cy, x);
+            const double y0 = R[0] * x[0] + R[1] * x[1] + R[2] * x[2] + t[0];
+            const double y1 = R[3] * x[0] + R[4] * x[1] + R[5] * x[2] + t[1];
+            const double y2 = R[6] * x[0] + R[7] * x[1] + R[8] * x[2] + t[2];
+            const uint4 lw = reinterpret_cast<const uint4*>(J.leaves)[p];
+            const uint2 nw = reinterpret_cast<const uint2*>(J.nmt)[p];
+            const int nm = modes_total(nw, J.T);
+            double best = INFINITY;
+            int bm = -1;
+            for (int m = 0; m < nm; ++m) {
+                const float4* row = mode_row(J.modes, J.T, J.D, J.M, lw, nw, m);
+                const float4 a = row[0];
+                const double d0 = y0 - a.x, d1 = y1 - a.y, d2 = y2 - a.z;
+                double q;
+                if (J.use_cov) {
+                    const float4 b = row[1], c = row[2];
+                    q = d0 * (b.x * d0 + b.y * d1 + b.z * d2) + d1 * (b.y * d0 + b.w * d1 + c.x * d2)
+                      + d2 * (b.z * d0 + c.x * d1 + c.y * d2);
+                } else {
+                    q = d0 * d0 + d1 * d1 + d2 * d2;
+                }
+                q = fmax(q, 0.0);
+                if (q < best) {
+                    best = q;
+                    bm = m;
+                }
+            }
+            int flag = -1;
+            if (bm >= 0) {
+                const float4 a = mode_row(J.modes, J.T, J.D, J.M, lw, nw, bm)[0];
+                const double d0 = y0 - a.x, d1 = y1 - a.y, d2 = y2 - a.z;
+                if (sqrt(d0 * d0 + d1 * d1 + d2 * d2) <= J.theta_in) {
+                    flag = bm;
+                    cnt += 1.0;
+                    sc[0] += x[0]; sc[1] += x[1]; sc[2] += x[2];
+                    sw[0] += a.x; sw[1] += a.y; sw[2] += a.z;
+                }
+            }
+            J.inl[k] = flag;
+        }
+        const double tc = block_sum256(cnt, s_red);
+        double cc[3], cw[3];
+        for (int i = 0; i < 3; ++i) {
+            cc[i] = block_sum256(sc[i], s_red);
+            cw[i] = block_sum256(sw[i], s_red);
+        }
+        n_inl = (int)tc;
+        if (n_inl >= 3) {
+            for (int i = 0; i < 3; ++i) {
+                cc[i] /= tc;
+                cw[i] /= tc;
+            }
+            double A[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+            for (int k = threadIdx.x; k < nI; k += 256) {
+                const int m = J.inl[k];
+                if (m < 0) continue;
+                const int p = J.I[k];
+                double x[3];
+                backproject(J.depth[p], p % J.w, p / J.w, J.fx, J.fy, J.cx, J.cy, x);
+                const uint4 lw = reinterpret_cast<const uint4*>(J.leaves)[p];
+                const uint2 nw = reinterpret_cast<const uint2*>(J.nmt)[p];
+                const float4 a = mode_row(J.modes, J.T, J.D, J.M, lw, nw, m)[0];
+                const double wv[3] = {(double)a.x - cw[0], (double)a.y - cw[1], (double)a.z - cw[2]};
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j) A[i * 3 + j] += (x[i] - cc[i]) * wv[j];
+            }
+            for (int i = 0; i < 9; ++i) A[i] = block_sum256(A[i], s_red);
+            if (threadIdx.x == 0) {
+                double R2[9], t2[3];
+                if (rigid_from_cov(A, cc, cw, R2, t2)) {
+                    for (int i = 0; i < 9; ++i) s_pose[i] = R2[i];
+                    for (int i = 0; i < 3; ++i) s_pose[9 + i] = t2[i];
+                    s_refit = 1;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (threadIdx.x == 0) {
+        float* H = res->cam_to_world;
+        for (int i = 0; i < 3; ++i) {
+            for (int j = 0; j < 3; ++j) H[4 * i + j] = (float)s_pose[3 * i + j];
+            H[4 * i + 3] = (float)s_pose[9 + i];
+        }
+        H[12] = H[13] = H[14] = 0.0f;
+        H[15] = 1.0f;
+        const double e = J.E[win];
+        res->energy = (float)e;
+        res->mean_energy = (float)(e / (double)nI);
+        res->status = RL_OK;
+        res->n_valid = J.st->n_valid;
+        res->n_inliers = n_inl;
+        res->winner = win;
+        res->refitted = s_refit;
+        res->n_eligible = J.st->n_elig;
+        res->rounds = rounds;
+        res->n_out = min(n, J.n_out);
+    }
+}
+
+// ------------------------------------------------------------------------
+// host-side launchers (called by the runtime)
+#define RL_CHECK_LAUNCH() do { hipError_t e_ = hipGetLastError(); if (e_ != hipSuccess) return e_; } while (0)
+
+hipError_t launch_prep(const Job* jobs, int njobs, int maxN, hipStream_t st)
+{
+    k_prep<<<dim3((maxN + 255) / 256, njobs), dim3(256), 0, st>>>(jobs);
+    RL_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_traverse(const Job* jobs, int njobs, int maxP, int T, hipStream_t st)
+{
+    const dim3 blk(256), gp((maxP + 255) / 256, njobs);
+    switch (T) {
+        case 1: k_traverse<1><<<gp, blk, 0, st>>>(jobs); break;
+        case 2: k_traverse<2><<<gp, blk, 0, st>>>(jobs); break;
+        case 3: k_traverse<3><<<gp, blk, 0, st>>>(jobs); break;
+        case 4: k_traverse<4><<<gp, blk, 0, st>>>(jobs); break;
+        case 5: k_traverse<5><<<gp, blk, 0, st>>>(jobs); break;
+        case 6: k_traverse<6><<<gp, blk, 0, st>>>(jobs); break;
+        case 7: k_traverse<7><<<gp, blk, 0, st>>>(jobs); break;
+        case 8: k_traverse<8><<<gp, blk, 0, st>>>(jobs); break;
+        default: return hipErrorInvalidValue;
+    }
+    RL_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_eligible(const Job* jobs, int njobs, int maxP, hipStream_t st)
+{
+    k_eligible<<<dim3((maxP + 255) / 256, njobs), dim3(256), 0, st>>>(jobs);
+    RL_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_hyp_search(const Job* jobs, int njobs, int maxN, int maxIters, hipStream_t st)
+{
+    const long long chunks = (maxIters + 255) / 256;
+    const long long gx = chunks * (long long)maxN;
+    if (gx > 0x7fffffffLL) return hipErrorInvalidValue;
+    k_hyp_search<<<dim3((unsigned)gx, njobs), dim3(256), 0, st>>>(jobs, maxN);
+    RL_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_hyp_finalize(const Job* jobs, int njobs, int maxN, hipStream_t st)
+{
+    k_hyp_finalize<<<dim3((maxN + 255) / 256, njobs), dim3(256), 0, st>>>(jobs);
+    RL_CHECK_LAUNCH();
+    k_ransac_init<<<dim3(1, njobs), dim3(256), 0, st>>>(jobs);
+    RL_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_score(const Job* jobs, int njobs, int round, int nptiles, int maxSurv,
+                        size_t score_lds, hipStream_t st)
+{
+    const int htiles = (maxSurv + 255) / 256;
+    k_score<<<dim3(nptiles * htiles, njobs), dim3(256), score_lds, st>>>(jobs, round, nptiles);
+    RL_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_select(const Job* jobs, int njobs, int round, int nptiles, int maxN, hipStream_t st)
+{
+    const size_t sel_lds = (sizeof(double) + sizeof(int)) * (size_t)maxN;
+    k_select<<<dim3(1, njobs), dim3(1024), sel_lds, st>>>(jobs, round, nptiles);
+    RL_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_finalize(const Job* jobs, int njobs, hipStream_t st)
+{
+    k_finalize<<<dim3(1, njobs), dim3(256), 0, st>>>(jobs);
+    RL_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+}  // namespace rl

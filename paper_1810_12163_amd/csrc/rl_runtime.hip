@@ -1,0 +1,933 @@
+// rl_runtime.hip -- host runtime and C ABI of librl (see include/rl.h).
+//
+// All device state lives in caller-provided buffers; this file computes
+// their layouts, validates every argument before any launch, fills the job
+// tables and queues the kernel sequences on the caller's stream.  Batches
+// can be captured into a HIP graph per batch shape and replayed.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "rl_internal.hpp"
+
+#define RL_API extern "C" __attribute__((visibility("default")))
+
+namespace rl {
+hipError_t launch_prep(const Job* jobs, int njobs, int maxN, hipStream_t st);
+hipError_t launch_traverse(const Job* jobs, int njobs, int maxP, int T, hipStream_t st);
+hipError_t launch_eligible(const Job* jobs, int njobs, int maxP, hipStream_t st);
+hipError_t launch_hyp_search(const Job* jobs, int njobs, int maxN, int maxIters, hipStream_t st);
+hipError_t launch_hyp_finalize(const Job* jobs, int njobs, int maxN, hipStream_t st);
+hipError_t launch_score(const Job* jobs, int njobs, int round, int nptiles, int maxSurv,
+                        size_t score_lds, hipStream_t st);
+hipError_t launch_select(const Job* jobs, int njobs, int round, int nptiles, int maxN, hipStream_t st);
+hipError_t launch_finalize(const Job* jobs, int njobs, hipStream_t st);
+hipError_t launch_adapt(const AdaptArgs& a, hipStream_t st);
+hipError_t launch_rqs(const RqsArgs& a, int blocks, hipStream_t st);
+
+__global__ void k_fill_u32(uint32_t* p, size_t n, uint32_t v)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_u8(uint8_t* p, size_t n, uint8_t v)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+}  // namespace rl
+
+using namespace rl;
+
+namespace {
+
+thread_local std::string g_err;
+
+rl_status fail(rl_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+rl_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(RL_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Carver {
+    size_t cur = 0;
+    size_t take(size_t bytes)
+    {
+        const size_t o = cur;
+        cur += align256(bytes);
+        return o;
+    }
+};
+
+int rounds_for(int N, int n_cull, int n_out, std::vector<int>* entering = nullptr)
+{
+    int n = N, rounds = 0;
+    bool first = true;
+    while (first || n > n_out) {
+        if (entering) entering->push_back(n);
+        int keep = n;
+        if (first && n_cull < n) keep = n_cull;
+        else if (n > n_out) keep = (n + 1) / 2;
+        n = keep;
+        ++rounds;
+        first = false;
+        if (rounds > 64) break;
+    }
+    return rounds;
+}
+
+int score_tile(int rows_per_pixel)
+{
+    int tp = kScoreLdsBytes / (rows_per_pixel * 72);
+    if (tp < 1) tp = 1;
+    if (tp > kMaxScoreTile) tp = kMaxScoreTile;
+    return tp;
+}
+
+// Per-frame (relocalisation) scratch of one job slot.
+struct FrameLayout {
+    size_t state, result, leaves, nmt, nm, tile_count, eligible, hyp_best, hyps, surv, E, partial,
+        I, inl, trace_slots, trace_E, total;
+};
+
+FrameLayout frame_layout(int maxP, int N, int eta, int rounds, int TP, size_t base)
+{
+    Carver c;
+    c.cur = base;
+    FrameLayout L;
+    L.state = c.take(sizeof(JobState));
+    L.result = c.take(sizeof(rl_result));
+    L.leaves = c.take((size_t)maxP * 16);
+    L.nmt = c.take((size_t)maxP * 8);
+    L.nm = c.take((size_t)maxP);
+    L.tile_count = c.take((size_t)((maxP + 255) / 256) * 4);
+    L.eligible = c.take((size_t)maxP * 4);
+    L.hyp_best = c.take((size_t)N * 4);
+    L.hyps = c.take((size_t)N * sizeof(Hyp));
+    L.surv = c.take((size_t)N * 4);
+    L.E = c.take((size_t)N * 8);
+    const int ptiles = (eta + TP - 1) / TP;
+    L.partial = c.take((size_t)ptiles * N * 8);
+    L.I = c.take((size_t)rounds * eta * 4);
+    L.inl = c.take((size_t)rounds * eta * 4);
+    L.trace_slots = c.take((size_t)rounds * N * 4);
+    L.trace_E = c.take((size_t)rounds * N * 8);
+    L.total = c.cur - base;
+    return L;
+}
+
+struct PersistLayout {
+    size_t nodes, reservoir, seen, dirty, dirty_list, counters, modes, nmodes, total;
+};
+
+PersistLayout persist_layout(const rl_params& p)
+{
+    const size_t T = p.n_trees, L = (size_t)1 << p.depth, NT = L - 1;
+    Carver c;
+    PersistLayout P;
+    P.nodes = c.take(T * NT * 16);
+    P.reservoir = c.take(T * L * (size_t)p.reservoir_capacity * 16);
+    P.seen = c.take(T * L * 4);
+    P.dirty = c.take(T * L * 4);
+    P.dirty_list = c.take(T * L * 4);
+    P.counters = c.take(256);
+    P.modes = c.take(T * L * (size_t)p.max_cluster_count * 64);
+    P.nmodes = c.take(T * L);
+    P.total = c.cur;
+    return P;
+}
+
+struct AdaptLayout {
+    size_t item_leaf, item_pt, item_flag, item_n, item_slot, cnt, cursor, off, seg, total;
+};
+
+AdaptLayout adapt_layout(const rl_params& p, int G, size_t base)
+{
+    const size_t T = p.n_trees, L = (size_t)1 << p.depth;
+    Carver c;
+    c.cur = base;
+    AdaptLayout A;
+    A.item_leaf = c.take(T * G * 2);
+    A.item_pt = c.take((size_t)G * 16);
+    A.item_flag = c.take(T * G);
+    A.item_n = c.take(T * G * 4);
+    A.item_slot = c.take(T * G * 4);
+    A.cnt = c.take(T * L * 4);
+    A.cursor = c.take(T * L * 4);
+    A.off = c.take(T * L * 4);
+    A.seg = c.take(T * G * 4);
+    A.total = c.cur - base;
+    return A;
+}
+
+int grid_items(int w, int h) { return (w / 4 - 1) * (h / 4 - 1); }
+
+bool finite_f(float v) { return std::isfinite(v); }
+
+rl_status validate_frame(const rl_frame* f, int max_w, int max_h)
+{
+    if (!f) return fail(RL_EINVAL, "frame is NULL");
+    if (f->width <= 0 || f->height <= 0 || f->width % 4 || f->height % 4)
+        return fail(RL_EINVAL, "frame size %dx%d: width and height must be positive multiples of 4",
+                    f->width, f->height);
+    if (f->width < 8 || f->height < 8) return fail(RL_EINVAL, "frame must be at least 8x8");
+    if (f->width > max_w || f->height > max_h)
+        return fail(RL_EINVAL, "frame %dx%d exceeds the %dx%d the scratch was sized for", f->width,
+                    f->height, max_w, max_h);
+    if (!f->depth || !f->rgb) return fail(RL_EINVAL, "frame depth/rgb pointer is NULL");
+    const rl_intrinsics& K = f->K;
+    if (!(finite_f(K.fx) && finite_f(K.fy) && finite_f(K.cx) && finite_f(K.cy)) || !(K.fx > 0) || !(K.fy > 0))
+        return fail(RL_EINVAL, "invalid intrinsics");
+    return RL_OK;
+}
+
+uint64_t stream_key64(uint64_t seed, uint64_t request_seed)
+{
+    return seed + request_seed * 0x9E3779B97F4A7C15ULL;
+}
+
+int device_lds_limit()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 65536;
+    return v;
+}
+
+// Optional HIP-event pair recorded around one kernel of the sequence.
+struct Timer {
+    int kernel = RL_TIMER_NONE;
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
+}  // namespace
+
+struct rl_room {
+    rl_params p;
+    int T, D, M, kappa, N, eta, rounds, TP;
+    size_t L;
+    int max_w, max_h, maxP, G;
+    char* pers;
+    char* scr;
+    PersistLayout PL;
+    FrameLayout FL;
+    AdaptLayout AL;
+    size_t job_off;
+    hipStream_t stream;
+    hipEvent_t ev;
+    Job* job_host;
+    rl_result* res_host;
+    int trace;
+    bool modes_stale;
+    std::vector<int> entering;
+    Timer timer;
+};
+
+struct rl_batch {
+    rl_batch_params bp;
+    char* ws;
+    hipStream_t stream;
+    hipEvent_t ev;
+    int TP, rows;
+    size_t score_lds;
+    size_t jobs_off, results_off;
+    std::vector<FrameLayout> slots;
+    Timer timer;
+    Job* job_host;
+    rl_result* res_host;
+    std::map<std::vector<long long>, hipGraphExec_t> graphs;
+};
+
+// ------------------------------------------------------------------------
+RL_API const char* rl_last_error(void) { return g_err.c_str(); }
+RL_API const char* rl_version(void) { return "librl 0.1 (gfx950)"; }
+
+RL_API rl_status rl_params_preset(const char* name, rl_params* out)
+{
+    if (!name || !out) return fail(RL_EINVAL, "NULL argument");
+    rl_params p;
+    std::memset(&p, 0, sizeof(p));
+    p.n_trees = 5;
+    p.depth = 15;
+    p.ref_width = 640;
+    p.max_colour_linf = 30.0f;
+    p.inlier_threshold = 0.05f;
+    p.cov_regulariser = 1e-6f;
+    p.clusterer_sigma = 0.1f;
+    p.max_cluster_count = 50;
+    p.max_pose_candidates_after_cull = 64;
+    const std::string n(name);
+    if (n == "default") {
+        p.clusterer_tau = 0.05f; p.min_cluster_size = 20; p.reservoir_capacity = 1024;
+        p.max_candidate_generation_iterations = 6000; p.max_pose_candidates = 1024;
+        p.max_translation_error_for_correct_pose = 0.05f;
+        p.min_squared_distance_between_sampled_modes = 0.09f; p.pose_update = 1;
+        p.ransac_inliers_per_iteration = 512; p.use_prediction_covariance = 1;
+        p.max_relocalisations_to_output = 16;
+    } else if (n == "fast") {
+        p.clusterer_tau = 0.2f; p.min_cluster_size = 5; p.reservoir_capacity = 2048;
+        p.max_candidate_generation_iterations = 500; p.max_pose_candidates = 2048;
+        p.max_translation_error_for_correct_pose = 0.05f;
+        p.min_squared_distance_between_sampled_modes = 0.0f; p.pose_update = 0;
+        p.ransac_inliers_per_iteration = 256; p.use_prediction_covariance = 0;
+        p.max_relocalisations_to_output = 1;
+    } else if (n == "intermediate") {
+        p.clusterer_tau = 0.2f; p.min_cluster_size = 5; p.reservoir_capacity = 2048;
+        p.max_candidate_generation_iterations = 1000; p.max_pose_candidates = 2048;
+        p.max_translation_error_for_correct_pose = 0.1f;
+        p.min_squared_distance_between_sampled_modes = 0.09f; p.pose_update = 1;
+        p.ransac_inliers_per_iteration = 256; p.use_prediction_covariance = 0;
+        p.max_relocalisations_to_output = 1;
+    } else if (n == "slow") {
+        p.clusterer_tau = 0.2f; p.min_cluster_size = 5; p.reservoir_capacity = 2048;
+        p.max_candidate_generation_iterations = 250; p.max_pose_candidates = 2048;
+        p.max_translation_error_for_correct_pose = 0.1f;
+        p.min_squared_distance_between_sampled_modes = 0.0225f; p.pose_update = 1;
+        p.ransac_inliers_per_iteration = 256; p.use_prediction_covariance = 0;
+        p.max_relocalisations_to_output = 16;
+    } else if (n == "c1" || n == "c2") {
+        p.clusterer_tau = 0.05f; p.min_cluster_size = 20; p.max_cluster_count = 10;
+        p.reservoir_capacity = 1024; p.max_candidate_generation_iterations = 6000;
+        p.max_pose_candidates = 1024; p.max_pose_candidates_after_cull = 1024;
+        p.max_translation_error_for_correct_pose = 0.05f;
+        p.min_squared_distance_between_sampled_modes = 0.09f; p.pose_update = 0;
+        p.ransac_inliers_per_iteration = 500; p.use_prediction_covariance = 1;
+        p.max_relocalisations_to_output = 1; p.final_refine = 1;
+        if (n == "c1") {
+            p.n_trees = 1; p.depth = 8; p.ref_width = 160; p.clusterer_tau = 0.2f;
+            p.min_cluster_size = 5; p.max_cluster_count = 5; p.reservoir_capacity = 64;
+            p.max_pose_candidates = 64; p.max_pose_candidates_after_cull = 64;
+            p.ransac_inliers_per_iteration = 100; p.final_refine = 0;
+        }
+    } else {
+        return fail(RL_EINVAL, "unknown preset '%s'", name);
+    }
+    *out = p;
+    return RL_OK;
+}
+
+RL_API rl_status rl_params_validate(const rl_params* p)
+{
+    if (!p) return fail(RL_EINVAL, "params is NULL");
+    if (p->n_trees < 1 || p->n_trees > kMaxTrees) return fail(RL_EINVAL, "n_trees must be in 1..8");
+    if (p->depth < 1 || p->depth > 15) return fail(RL_EINVAL, "depth must be in 1..15");
+    if (p->ref_width < 1) return fail(RL_EINVAL, "ref_width must be positive");
+    if (p->max_cluster_count < 1 || p->max_cluster_count > 64) return fail(RL_EINVAL, "max_cluster_count must be in 1..64");
+    if (p->n_trees * p->max_cluster_count > 255) return fail(RL_EINVAL, "n_trees * max_cluster_count must be <= 255");
+    if (p->min_cluster_size < 1) return fail(RL_EINVAL, "min_cluster_size must be >= 1");
+    if (p->reservoir_capacity < 1 || p->reservoir_capacity > 4096) return fail(RL_EINVAL, "reservoir_capacity must be in 1..4096");
+    if (p->max_candidate_generation_iterations < 1) return fail(RL_EINVAL, "max_candidate_generation_iterations must be >= 1");
+    if (p->max_pose_candidates < 1 || p->max_pose_candidates > 4096) return fail(RL_EINVAL, "max_pose_candidates must be in 1..4096");
+    if (p->max_pose_candidates_after_cull < 1) return fail(RL_EINVAL, "max_pose_candidates_after_cull must be >= 1");
+    if (p->ransac_inliers_per_iteration < 1 || p->ransac_inliers_per_iteration > 4096) return fail(RL_EINVAL, "ransac_inliers_per_iteration must be in 1..4096");
+    if (p->max_relocalisations_to_output < 1) return fail(RL_EINVAL, "max_relocalisations_to_output must be >= 1");
+    if (p->pose_update != 0) return fail(RL_EINVAL, "pose_update (Levenberg-Marquardt refinement) is not provided; set it to 0");
+    const float fs[] = {p->clusterer_sigma, p->clusterer_tau, p->min_squared_distance_between_sampled_modes,
+                        p->max_translation_error_for_correct_pose, p->max_colour_linf, p->inlier_threshold,
+                        p->cov_regulariser};
+    for (float v : fs)
+        if (!finite_f(v) || v < 0) return fail(RL_EINVAL, "float parameters must be finite and >= 0");
+    if (!(p->clusterer_sigma > 0)) return fail(RL_EINVAL, "clusterer_sigma must be > 0");
+    if ((long long)p->max_candidate_generation_iterations * p->max_pose_candidates > 0x7fffffffLL * 200LL)
+        return fail(RL_EINVAL, "too many generation iterations");
+    return RL_OK;
+}
+
+RL_API rl_status relocaliser_state_bytes(const rl_params* p, int32_t max_width, int32_t max_height,
+                                         size_t* persistent, size_t* scratch)
+{
+    rl_status s = rl_params_validate(p);
+    if (s != RL_OK) return s;
+    if (max_width < 8 || max_height < 8 || max_width % 4 || max_height % 4)
+        return fail(RL_EINVAL, "max frame size must be multiples of 4, at least 8x8");
+    if (!persistent || !scratch) return fail(RL_EINVAL, "NULL output");
+    const int N = p->max_pose_candidates, eta = p->ransac_inliers_per_iteration;
+    const int R = rounds_for(N, p->max_pose_candidates_after_cull, p->max_relocalisations_to_output);
+    const int TP = score_tile(p->n_trees * p->max_cluster_count);
+    *persistent = persist_layout(*p).total;
+    const size_t job = align256(sizeof(Job));
+    const FrameLayout FL = frame_layout(max_width * max_height, N, eta, R, TP, job);
+    const AdaptLayout AL = adapt_layout(*p, grid_items(max_width, max_height), job + FL.total);
+    *scratch = job + FL.total + AL.total;
+    return RL_OK;
+}
+
+static Job make_job(const rl_room* r, char* scr, const FrameLayout& FL, const rl_frame* f,
+                    uint64_t request_seed, int N)
+{
+    Job J;
+    std::memset(&J, 0, sizeof(J));
+    J.nodes = reinterpret_cast<const float4*>(r->pers + r->PL.nodes);
+    J.modes = reinterpret_cast<const float4*>(r->pers + r->PL.modes);
+    J.nmodes = reinterpret_cast<const uint8_t*>(r->pers + r->PL.nmodes);
+    J.T = r->T;
+    J.D = r->D;
+    J.M = r->M;
+    J.depth = f->depth;
+    J.rgb = f->rgb;
+    J.w = f->width;
+    J.h = f->height;
+    J.fx = f->K.fx;
+    J.fy = f->K.fy;
+    J.cx = f->K.cx;
+    J.cy = f->K.cy;
+    J.s = (float)f->width / (float)r->p.ref_width;
+    J.N = N;
+    J.I_max = r->p.max_candidate_generation_iterations;
+    J.eta = r->eta;
+    J.n_cull = r->p.max_pose_candidates_after_cull;
+    J.n_out = r->p.max_relocalisations_to_output;
+    J.use_cov = r->p.use_prediction_covariance;
+    J.final_refine = r->p.final_refine;
+    J.trace = r->trace;
+    J.theta_col = r->p.max_colour_linf;
+    J.TP = r->TP;
+    J.min_sq_dist = r->p.min_squared_distance_between_sampled_modes;
+    J.theta_rig = r->p.max_translation_error_for_correct_pose;
+    J.theta_in = r->p.inlier_threshold;
+    const uint64_t k = stream_key64(r->p.seed, request_seed);
+    J.key0 = (uint32_t)k;
+    J.key1 = (uint32_t)(k >> 32);
+    J.leaves = reinterpret_cast<uint16_t*>(scr + FL.leaves);
+    J.nmt = reinterpret_cast<uint8_t*>(scr + FL.nmt);
+    J.nm = reinterpret_cast<uint8_t*>(scr + FL.nm);
+    J.tile_count = reinterpret_cast<int*>(scr + FL.tile_count);
+    J.eligible = reinterpret_cast<int*>(scr + FL.eligible);
+    J.hyp_best = reinterpret_cast<int*>(scr + FL.hyp_best);
+    J.hyps = reinterpret_cast<Hyp*>(scr + FL.hyps);
+    J.surv = reinterpret_cast<int*>(scr + FL.surv);
+    J.E = reinterpret_cast<double*>(scr + FL.E);
+    J.partial = reinterpret_cast<double*>(scr + FL.partial);
+    J.I = reinterpret_cast<int*>(scr + FL.I);
+    J.inl = reinterpret_cast<int*>(scr + FL.inl);
+    J.trace_slots = reinterpret_cast<int*>(scr + FL.trace_slots);
+    J.trace_E = reinterpret_cast<double*>(scr + FL.trace_E);
+    J.st = reinterpret_cast<JobState*>(scr + FL.state);
+    J.result = reinterpret_cast<rl_result*>(scr + FL.result);
+    return J;
+}
+
+static RqsArgs rqs_args(rl_room* r)
+{
+    RqsArgs a;
+    a.reservoir = reinterpret_cast<const float4*>(r->pers + r->PL.reservoir);
+    a.seen = reinterpret_cast<const uint32_t*>(r->pers + r->PL.seen);
+    a.dirty = reinterpret_cast<uint32_t*>(r->pers + r->PL.dirty);
+    a.dirty_list = reinterpret_cast<const uint32_t*>(r->pers + r->PL.dirty_list);
+    a.counters = reinterpret_cast<uint32_t*>(r->pers + r->PL.counters);
+    a.modes = reinterpret_cast<float4*>(r->pers + r->PL.modes);
+    a.nmodes = reinterpret_cast<uint8_t*>(r->pers + r->PL.nmodes);
+    a.kappa = r->kappa;
+    a.M = r->M;
+    a.min_size = r->p.min_cluster_size;
+    a.sigma = r->p.clusterer_sigma;
+    a.tau = r->p.clusterer_tau;
+    a.lambda = r->p.cov_regulariser;
+    return a;
+}
+
+static rl_status fill_u32(void* p, size_t n, uint32_t v, hipStream_t st)
+{
+    if (n == 0) return RL_OK;
+    k_fill_u32<<<dim3(1024), dim3(256), 0, st>>>(reinterpret_cast<uint32_t*>(p), n, v);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RL_OK : hip_fail(e, "fill");
+}
+
+static rl_status fill_u8(void* p, size_t n, uint8_t v, hipStream_t st)
+{
+    if (n == 0) return RL_OK;
+    k_fill_u8<<<dim3(1024), dim3(256), 0, st>>>(reinterpret_cast<uint8_t*>(p), n, v);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RL_OK : hip_fail(e, "fill");
+}
+
+RL_API rl_status relocaliser_create(const rl_params* p, const rl_node* host_nodes, int32_t max_width,
+                                    int32_t max_height, void* dev_persistent, void* dev_scratch,
+                                    void* hip_stream, rl_room** out)
+{
+    if (!out) return fail(RL_EINVAL, "out is NULL");
+    *out = nullptr;
+    size_t pb = 0, sb = 0;
+    rl_status s = relocaliser_state_bytes(p, max_width, max_height, &pb, &sb);
+    if (s != RL_OK) return s;
+    if (!host_nodes || !dev_persistent || !dev_scratch) return fail(RL_EINVAL, "NULL buffer");
+    if (((uintptr_t)dev_persistent & 255) || ((uintptr_t)dev_scratch & 255))
+        return fail(RL_EINVAL, "device buffers must be 256-byte aligned");
+    const size_t NT = ((size_t)1 << p->depth) - 1;
+    for (size_t i = 0; i < (size_t)p->n_trees * NT; ++i) {
+        const rl_node& nd = host_nodes[i];
+        if (nd.kind > 3 || !finite_f(nd.dx) || !finite_f(nd.dy) || !finite_f(nd.tau))
+            return fail(RL_EINVAL, "node %zu: kind must be 0..3 and parameters finite", i);
+    }
+    const int lds = device_lds_limit();
+    if ((size_t)36 * p->reservoir_capacity + 4096 > (size_t)lds)
+        return fail(RL_EINVAL, "reservoir_capacity %d needs %zu bytes of LDS per workgroup; device allows %d",
+                    p->reservoir_capacity, (size_t)36 * p->reservoir_capacity + 4096, lds);
+    rl_room* r = new rl_room();
+    r->p = *p;
+    r->T = p->n_trees;
+    r->D = p->depth;
+    r->M = p->max_cluster_count;
+    r->kappa = p->reservoir_capacity;
+    r->N = p->max_pose_candidates;
+    r->eta = p->ransac_inliers_per_iteration;
+    r->rounds = rounds_for(r->N, p->max_pose_candidates_after_cull, p->max_relocalisations_to_output, &r->entering);
+    r->TP = score_tile(r->T * r->M);
+    r->L = (size_t)1 << r->D;
+    r->max_w = max_width;
+    r->max_h = max_height;
+    r->maxP = max_width * max_height;
+    r->G = grid_items(max_width, max_height);
+    r->pers = reinterpret_cast<char*>(dev_persistent);
+    r->scr = reinterpret_cast<char*>(dev_scratch);
+    r->PL = persist_layout(*p);
+    r->job_off = 0;
+    r->FL = frame_layout(r->maxP, r->N, r->eta, r->rounds, r->TP, align256(sizeof(Job)));
+    r->AL = adapt_layout(*p, r->G, align256(sizeof(Job)) + r->FL.total);
+    r->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    r->trace = 0;
+    r->modes_stale = false;
+    hipError_t e = hipEventCreateWithFlags(&r->ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        delete r;
+        return hip_fail(e, "hipEventCreate");
+    }
+    e = hipHostMalloc(reinterpret_cast<void**>(&r->job_host), sizeof(Job), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&r->res_host), sizeof(rl_result), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(r->ev);
+        delete r;
+        return fail(RL_ENOMEM, "pinned host allocation failed: %s", hipGetErrorString(e));
+    }
+    e = hipMemcpyAsync(r->pers + r->PL.nodes, host_nodes, (size_t)r->T * NT * sizeof(rl_node),
+                       hipMemcpyHostToDevice, r->stream);
+    if (e != hipSuccess) {
+        relocaliser_destroy(r);
+        return hip_fail(e, "copy nodes");
+    }
+    const size_t TL = (size_t)r->T * r->L;
+    rl_status fs = RL_OK;
+    if (fs == RL_OK) fs = fill_u32(r->pers + r->PL.seen, TL, 0, r->stream);
+    if (fs == RL_OK) fs = fill_u32(r->pers + r->PL.dirty, TL, 0, r->stream);
+    if (fs == RL_OK) fs = fill_u32(r->pers + r->PL.counters, 64, 0, r->stream);
+    if (fs == RL_OK) fs = fill_u8(r->pers + r->PL.nmodes, TL, 0, r->stream);
+    if (fs == RL_OK) fs = fill_u32(r->scr + r->AL.cnt, TL, 0, r->stream);
+    if (fs == RL_OK) fs = fill_u32(r->scr + r->AL.cursor, TL, 0, r->stream);
+    if (fs == RL_OK) fs = fill_u32(r->scr + r->FL.state, sizeof(JobState) / 4, 0, r->stream);
+    if (fs != RL_OK) {
+        relocaliser_destroy(r);
+        return fs;
+    }
+    e = hipStreamSynchronize(r->stream);
+    if (e != hipSuccess) {
+        relocaliser_destroy(r);
+        return hip_fail(e, "create");
+    }
+    *out = r;
+    return RL_OK;
+}
+
+RL_API rl_status relocaliser_destroy(rl_room* r)
+{
+    if (!r) return RL_OK;
+    if (r->job_host) (void)hipHostFree(r->job_host);
+    if (r->res_host) (void)hipHostFree(r->res_host);
+    if (r->ev) (void)hipEventDestroy(r->ev);
+    delete r;
+    return RL_OK;
+}
+
+RL_API rl_status relocaliser_set_trace(rl_room* r, int32_t on)
+{
+    if (!r) return fail(RL_EINVAL, "room is NULL");
+    r->trace = on ? 1 : 0;
+    return RL_OK;
+}
+
+RL_API rl_status relocaliser_adapt(rl_room* r, const rl_frame* f, const float H[16], int32_t reliable)
+{
+    if (!r) return fail(RL_EINVAL, "room is NULL");
+    rl_status s = validate_frame(f, r->max_w, r->max_h);
+    if (s != RL_OK) return s;
+    if (!H) return fail(RL_EINVAL, "pose is NULL");
+    for (int i = 0; i < 16; ++i)
+        if (!finite_f(H[i])) return fail(RL_EINVAL, "pose has a non-finite entry");
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double dot = 0;
+            for (int k = 0; k < 3; ++k) dot += (double)H[4 * k + i] * H[4 * k + j];
+            if (std::fabs(dot - (i == j ? 1.0 : 0.0)) > 1e-3) return fail(RL_EINVAL, "pose is not rigid");
+        }
+    if (std::fabs(H[12]) > 1e-6f || std::fabs(H[13]) > 1e-6f || std::fabs(H[14]) > 1e-6f || std::fabs(H[15] - 1.0f) > 1e-6f)
+        return fail(RL_EINVAL, "pose last row must be 0 0 0 1");
+    if (!reliable) return RL_OK;
+    AdaptArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.nodes = reinterpret_cast<const float4*>(r->pers + r->PL.nodes);
+    a.T = r->T;
+    a.D = r->D;
+    a.L = (int)r->L;
+    a.kappa = r->kappa;
+    a.depth = f->depth;
+    a.rgb = f->rgb;
+    a.w = f->width;
+    a.h = f->height;
+    a.gw = f->width / 4 - 1;
+    a.G = grid_items(f->width, f->height);
+    a.fx = f->K.fx;
+    a.fy = f->K.fy;
+    a.cx = f->K.cx;
+    a.cy = f->K.cy;
+    a.s = (float)f->width / (float)r->p.ref_width;
+    for (int i = 0; i < 12; ++i) a.H[i] = (double)H[i];
+    const uint64_t k = stream_key64(r->p.seed, 0);
+    a.key0 = (uint32_t)k;
+    a.key1 = (uint32_t)(k >> 32);
+    a.reservoir = reinterpret_cast<float4*>(r->pers + r->PL.reservoir);
+    a.seen = reinterpret_cast<uint32_t*>(r->pers + r->PL.seen);
+    a.dirty = reinterpret_cast<uint32_t*>(r->pers + r->PL.dirty);
+    a.dirty_list = reinterpret_cast<uint32_t*>(r->pers + r->PL.dirty_list);
+    a.counters = reinterpret_cast<uint32_t*>(r->pers + r->PL.counters);
+    a.item_leaf = reinterpret_cast<uint16_t*>(r->scr + r->AL.item_leaf);
+    a.item_pt = reinterpret_cast<float4*>(r->scr + r->AL.item_pt);
+    a.item_flag = reinterpret_cast<uint8_t*>(r->scr + r->AL.item_flag);
+    a.item_n = reinterpret_cast<uint32_t*>(r->scr + r->AL.item_n);
+    a.item_slot = reinterpret_cast<int*>(r->scr + r->AL.item_slot);
+    a.cnt = reinterpret_cast<uint32_t*>(r->scr + r->AL.cnt);
+    a.cursor = reinterpret_cast<uint32_t*>(r->scr + r->AL.cursor);
+    a.off = reinterpret_cast<uint32_t*>(r->scr + r->AL.off);
+    a.seg = reinterpret_cast<int*>(r->scr + r->AL.seg);
+    const hipError_t e = launch_adapt(a, r->stream);
+    if (e != hipSuccess) return hip_fail(e, "adapt launch");
+    r->modes_stale = true;
+    return RL_OK;
+}
+
+static rl_status ensure_modes(rl_room* r, hipStream_t st)
+{
+    if (!r->modes_stale) return RL_OK;
+    const hipError_t e = launch_rqs(rqs_args(r), 1024, st);
+    if (e != hipSuccess) return hip_fail(e, "mode update launch");
+    r->modes_stale = false;
+    return RL_OK;
+}
+
+RL_API rl_status relocaliser_update_modes(rl_room* r)
+{
+    if (!r) return fail(RL_EINVAL, "room is NULL");
+    return ensure_modes(r, r->stream);
+}
+
+static hipError_t launch_sequence(const Job* jobs, int njobs, int maxP, int maxN, int maxIters, int T,
+                                  const std::vector<int>& entering, int nptiles, size_t score_lds,
+                                  const Timer& tm, hipStream_t st)
+{
+    hipError_t e;
+#define RL_TRY(x) do { e = (x); if (e != hipSuccess) return e; } while (0)
+#define RL_MARK(k, ev) do { if (tm.kernel == (k)) RL_TRY(hipEventRecord(tm.ev, st)); } while (0)
+    RL_TRY(launch_prep(jobs, njobs, maxN, st));
+    RL_MARK(RL_TIMER_TRAVERSE, start);
+    RL_TRY(launch_traverse(jobs, njobs, maxP, T, st));
+    RL_MARK(RL_TIMER_TRAVERSE, stop);
+    RL_TRY(launch_eligible(jobs, njobs, maxP, st));
+    RL_MARK(RL_TIMER_HYP_SEARCH, start);
+    RL_TRY(launch_hyp_search(jobs, njobs, maxN, maxIters, st));
+    RL_MARK(RL_TIMER_HYP_SEARCH, stop);
+    RL_TRY(launch_hyp_finalize(jobs, njobs, maxN, st));
+    RL_MARK(RL_TIMER_RANSAC, start);
+    for (int r = 0; r < (int)entering.size(); ++r) {
+        RL_TRY(launch_score(jobs, njobs, r, nptiles, entering[r], score_lds, st));
+        RL_TRY(launch_select(jobs, njobs, r, nptiles, maxN, st));
+    }
+    RL_MARK(RL_TIMER_RANSAC, stop);
+    RL_TRY(launch_finalize(jobs, njobs, st));
+#undef RL_MARK
+#undef RL_TRY
+    return hipSuccess;
+}
+
+RL_API rl_status relocaliser_relocalise_ex(rl_room* r, const rl_frame* f, uint64_t request_seed, rl_result* out)
+{
+    if (!r || !out) return fail(RL_EINVAL, "NULL argument");
+    rl_status s = validate_frame(f, r->max_w, r->max_h);
+    if (s != RL_OK) return s;
+    s = ensure_modes(r, r->stream);
+    if (s != RL_OK) return s;
+    *r->job_host = make_job(r, r->scr, r->FL, f, request_seed, r->N);
+    Job* jd = reinterpret_cast<Job*>(r->scr + r->job_off);
+    hipError_t e = hipMemcpyAsync(jd, r->job_host, sizeof(Job), hipMemcpyHostToDevice, r->stream);
+    if (e != hipSuccess) return hip_fail(e, "job upload");
+    const int nptiles = (r->eta + r->TP - 1) / r->TP;
+    const size_t score_lds = (size_t)r->TP * r->T * r->M * 72;
+    e = launch_sequence(jd, 1, f->width * f->height, r->N, r->p.max_candidate_generation_iterations, r->T,
+                        r->entering, nptiles, score_lds, r->timer, r->stream);
+    if (e != hipSuccess) return hip_fail(e, "relocalise launch");
+    e = hipMemcpyAsync(r->res_host, r->scr + r->FL.result, sizeof(rl_result), hipMemcpyDeviceToHost, r->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
+    if (e != hipSuccess) return hip_fail(e, "relocalise");
+    *out = *r->res_host;
+    return out->status == RL_OK ? RL_OK : RL_NO_POSE;
+}
+
+RL_API rl_status relocaliser_relocalise(rl_room* r, const rl_frame* f, uint64_t request_seed, float H[16],
+                                        float* energy, float* mean_energy)
+{
+    rl_result res;
+    const rl_status s = relocaliser_relocalise_ex(r, f, request_seed, &res);
+    if (s < 0) return s;
+    if (H) std::memcpy(H, res.cam_to_world, sizeof(float) * 16);
+    if (energy) *energy = res.energy;
+    if (mean_energy) *mean_energy = res.mean_energy;
+    return s;
+}
+
+RL_API rl_status relocaliser_buffer(const rl_room* r, int32_t which, size_t* offset, size_t* bytes, int32_t* region)
+{
+    if (!r || !offset || !bytes || !region) return fail(RL_EINVAL, "NULL argument");
+    const size_t TL = (size_t)r->T * r->L;
+    switch (which) {
+        case RL_BUF_NODES: *offset = r->PL.nodes; *bytes = TL / r->L * (r->L - 1) * 16; *region = 0; break;
+        case RL_BUF_RESERVOIR: *offset = r->PL.reservoir; *bytes = TL * r->kappa * 16; *region = 0; break;
+        case RL_BUF_SEEN: *offset = r->PL.seen; *bytes = TL * 4; *region = 0; break;
+        case RL_BUF_MODES: *offset = r->PL.modes; *bytes = TL * r->M * 64; *region = 0; break;
+        case RL_BUF_NMODES: *offset = r->PL.nmodes; *bytes = TL; *region = 0; break;
+        case RL_BUF_DIRTY: *offset = r->PL.dirty; *bytes = TL * 4; *region = 0; break;
+        case RL_BUF_LEAVES: *offset = r->FL.leaves; *bytes = (size_t)r->maxP * 16; *region = 1; break;
+        case RL_BUF_NM: *offset = r->FL.nm; *bytes = (size_t)r->maxP; *region = 1; break;
+        case RL_BUF_ELIGIBLE: *offset = r->FL.eligible; *bytes = (size_t)r->maxP * 4; *region = 1; break;
+        case RL_BUF_HYPS: *offset = r->FL.hyps; *bytes = (size_t)r->N * sizeof(Hyp); *region = 1; break;
+        case RL_BUF_ILIST: *offset = r->FL.I; *bytes = (size_t)r->rounds * r->eta * 4; *region = 1; break;
+        case RL_BUF_TRACE_SLOTS: *offset = r->FL.trace_slots; *bytes = (size_t)r->rounds * r->N * 4; *region = 1; break;
+        case RL_BUF_TRACE_ENERGY: *offset = r->FL.trace_E; *bytes = (size_t)r->rounds * r->N * 8; *region = 1; break;
+        case RL_BUF_SURVIVORS: *offset = r->FL.surv; *bytes = (size_t)r->N * 4; *region = 1; break;
+        case RL_BUF_ENERGY: *offset = r->FL.E; *bytes = (size_t)r->N * 8; *region = 1; break;
+        default: return fail(RL_EINVAL, "unknown buffer %d", which);
+    }
+    return RL_OK;
+}
+
+// ------------------------------------------------------------------------
+// batches
+
+static int batch_rounds(const rl_batch_params& bp) { return bp.max_rounds; }
+
+RL_API rl_status rl_batch_workspace_bytes(const rl_batch_params* bp, size_t* bytes)
+{
+    if (!bp || !bytes) return fail(RL_EINVAL, "NULL argument");
+    if (bp->max_frames < 1 || bp->max_frames > 4096) return fail(RL_EINVAL, "max_frames must be in 1..4096");
+    if (bp->max_width < 8 || bp->max_height < 8 || bp->max_width % 4 || bp->max_height % 4)
+        return fail(RL_EINVAL, "max frame size must be multiples of 4, at least 8x8");
+    if (bp->max_hypotheses < 1 || bp->max_hypotheses > 4096) return fail(RL_EINVAL, "max_hypotheses must be in 1..4096");
+    if (bp->max_eta < 1 || bp->max_eta > 4096) return fail(RL_EINVAL, "max_eta must be in 1..4096");
+    if (bp->max_rounds < 1 || bp->max_rounds > 64) return fail(RL_EINVAL, "max_rounds must be in 1..64");
+    if (bp->n_trees < 1 || bp->n_trees > kMaxTrees) return fail(RL_EINVAL, "n_trees must be in 1..8");
+    if (bp->max_modes_per_pixel < 1 || bp->max_modes_per_pixel > 255) return fail(RL_EINVAL, "max_modes_per_pixel must be in 1..255");
+    const int TP = score_tile(bp->max_modes_per_pixel);
+    Carver c;
+    c.take((size_t)bp->max_frames * sizeof(Job));
+    c.take((size_t)bp->max_frames * sizeof(rl_result));
+    const FrameLayout FL = frame_layout(bp->max_width * bp->max_height, bp->max_hypotheses, bp->max_eta,
+                                        batch_rounds(*bp), TP, 0);
+    *bytes = c.cur + (size_t)bp->max_frames * align256(FL.total);
+    return RL_OK;
+}
+
+RL_API rl_status rl_batch_create(const rl_batch_params* bp, void* ws, void* hip_stream, rl_batch** out)
+{
+    if (!out) return fail(RL_EINVAL, "out is NULL");
+    *out = nullptr;
+    size_t bytes = 0;
+    rl_status s = rl_batch_workspace_bytes(bp, &bytes);
+    if (s != RL_OK) return s;
+    if (!ws || ((uintptr_t)ws & 255)) return fail(RL_EINVAL, "workspace must be a 256-byte aligned device buffer");
+    rl_batch* b = new rl_batch();
+    b->bp = *bp;
+    b->ws = reinterpret_cast<char*>(ws);
+    b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    b->TP = score_tile(bp->max_modes_per_pixel);
+    b->rows = bp->max_modes_per_pixel;
+    b->score_lds = (size_t)b->TP * b->rows * 72;
+    Carver c;
+    b->jobs_off = c.take((size_t)bp->max_frames * sizeof(Job));
+    b->results_off = c.take((size_t)bp->max_frames * sizeof(rl_result));
+    const FrameLayout proto = frame_layout(bp->max_width * bp->max_height, bp->max_hypotheses, bp->max_eta,
+                                           batch_rounds(*bp), b->TP, 0);
+    for (int i = 0; i < bp->max_frames; ++i) {
+        const size_t base = c.take(proto.total);
+        b->slots.push_back(frame_layout(bp->max_width * bp->max_height, bp->max_hypotheses, bp->max_eta,
+                                        batch_rounds(*bp), b->TP, base));
+    }
+    hipError_t e = hipEventCreateWithFlags(&b->ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->job_host), (size_t)bp->max_frames * sizeof(Job), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->res_host), (size_t)bp->max_frames * sizeof(rl_result), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        rl_batch_destroy(b);
+        return fail(RL_ENOMEM, "batch host allocation failed: %s", hipGetErrorString(e));
+    }
+    *out = b;
+    return RL_OK;
+}
+
+RL_API rl_status rl_batch_destroy(rl_batch* b)
+{
+    if (!b) return RL_OK;
+    for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (b->job_host) (void)hipHostFree(b->job_host);
+    if (b->res_host) (void)hipHostFree(b->res_host);
+    if (b->ev) (void)hipEventDestroy(b->ev);
+    delete b;
+    return RL_OK;
+}
+
+RL_API rl_status rl_batch_relocalise_async(rl_batch* b, const rl_request* reqs, int32_t n, rl_result* dev_results,
+                                           int32_t use_graph)
+{
+    if (!b || !reqs || !dev_results) return fail(RL_EINVAL, "NULL argument");
+    if (n < 1 || n > b->bp.max_frames) return fail(RL_EINVAL, "batch of %d requests (1..%d allowed)", n, b->bp.max_frames);
+    int maxP = 0, maxN = 0, maxIters = 0, maxEta = 0;
+    std::vector<int> entering;
+    for (int i = 0; i < n; ++i) {
+        const rl_request& q = reqs[i];
+        rl_room* r = q.room;
+        if (!r) return fail(RL_EINVAL, "request %d: room is NULL", i);
+        rl_status s = validate_frame(&q.frame, b->bp.max_width, b->bp.max_height);
+        if (s != RL_OK) return fail(s, "request %d: %s", i, g_err.c_str());
+        if (r->T != b->bp.n_trees) return fail(RL_EINVAL, "request %d: room has %d trees, batch %d", i, r->T, b->bp.n_trees);
+        if (r->T * r->M > b->rows) return fail(RL_EINVAL, "request %d: room has up to %d modes per pixel, batch %d", i, r->T * r->M, b->rows);
+        const int N = q.n_hypotheses > 0 ? q.n_hypotheses : r->N;
+        if (N > b->bp.max_hypotheses || N > 4096) return fail(RL_EINVAL, "request %d: %d hypotheses exceed the batch maximum", i, N);
+        if (r->eta > b->bp.max_eta) return fail(RL_EINVAL, "request %d: eta exceeds the batch maximum", i);
+        std::vector<int> ent;
+        const int R = rounds_for(N, r->p.max_pose_candidates_after_cull, r->p.max_relocalisations_to_output, &ent);
+        if (R > b->bp.max_rounds) return fail(RL_EINVAL, "request %d: %d rounds exceed the batch maximum", i, R);
+        if (ent.size() > entering.size()) entering.resize(ent.size(), 0);
+        for (size_t k = 0; k < ent.size(); ++k) entering[k] = std::max(entering[k], ent[k]);
+        maxP = std::max(maxP, q.frame.width * q.frame.height);
+        maxN = std::max(maxN, N);
+        maxIters = std::max(maxIters, r->p.max_candidate_generation_iterations);
+        maxEta = std::max(maxEta, r->eta);
+    }
+    // order every room's pending work before the batch, bring modes up to date
+    for (int i = 0; i < n; ++i) {
+        rl_room* r = reqs[i].room;
+        if (r->stream != b->stream) {
+            hipError_t e = hipEventRecord(r->ev, r->stream);
+            if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, r->ev, 0);
+            if (e != hipSuccess) return hip_fail(e, "batch ordering");
+        }
+        rl_status s = ensure_modes(r, b->stream);
+        if (s != RL_OK) return s;
+    }
+    for (int i = 0; i < n; ++i) {
+        const rl_request& q = reqs[i];
+        const int N = q.n_hypotheses > 0 ? q.n_hypotheses : q.room->N;
+        Job J = make_job(q.room, b->ws, b->slots[i], &q.frame, q.request_seed, N);
+        J.TP = b->TP;
+        J.trace = 0;
+        J.result = dev_results + i;
+        b->job_host[i] = J;
+    }
+    Job* jd = reinterpret_cast<Job*>(b->ws + b->jobs_off);
+    hipError_t e = hipMemcpyAsync(jd, b->job_host, (size_t)n * sizeof(Job), hipMemcpyHostToDevice, b->stream);
+    if (e != hipSuccess) return hip_fail(e, "job upload");
+    const int nptiles = (maxEta + b->TP - 1) / b->TP;
+    if (use_graph && b->stream == nullptr)
+        return fail(RL_EINVAL, "graph replay needs a batch created on a non-default stream");
+    if (use_graph) {
+        std::vector<long long> key = {n, maxP, maxN, maxIters, nptiles, (long long)b->score_lds, b->bp.n_trees,
+                                      b->timer.kernel, (long long)(uintptr_t)b->timer.start,
+                                      (long long)(uintptr_t)b->timer.stop};
+        for (int v : entering) key.push_back(v);
+        auto it = b->graphs.find(key);
+        if (it == b->graphs.end()) {
+            e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return hip_fail(e, "begin capture");
+            const hipError_t le = launch_sequence(jd, n, maxP, maxN, maxIters, b->bp.n_trees, entering, nptiles,
+                                                  b->score_lds, b->timer, b->stream);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(b->stream, &g);
+            if (le != hipSuccess || e != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return hip_fail(le != hipSuccess ? le : e, "capture");
+            }
+            hipGraphExec_t ex = nullptr;
+            e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+            it = b->graphs.emplace(key, ex).first;
+        }
+        e = hipGraphLaunch(it->second, b->stream);
+        if (e != hipSuccess) return hip_fail(e, "graph launch");
+    } else {
+        e = launch_sequence(jd, n, maxP, maxN, maxIters, b->bp.n_trees, entering, nptiles, b->score_lds, b->timer,
+                            b->stream);
+        if (e != hipSuccess) return hip_fail(e, "batch launch");
+    }
+    // later work on the rooms' own streams is ordered after the batch
+    e = hipEventRecord(b->ev, b->stream);
+    if (e != hipSuccess) return hip_fail(e, "batch event");
+    for (int i = 0; i < n; ++i) {
+        rl_room* r = reqs[i].room;
+        if (r->stream != b->stream) {
+            e = hipStreamWaitEvent(r->stream, b->ev, 0);
+            if (e != hipSuccess) return hip_fail(e, "batch ordering");
+        }
+    }
+    return RL_OK;
+}
+
+RL_API rl_status rl_batch_relocalise(rl_batch* b, const rl_request* reqs, int32_t n, rl_result* results,
+                                     int32_t use_graph)
+{
+    if (!b || !results) return fail(RL_EINVAL, "NULL argument");
+    rl_result* dres = reinterpret_cast<rl_result*>(b->ws + b->results_off);
+    rl_status s = rl_batch_relocalise_async(b, reqs, n, dres, use_graph);
+    if (s != RL_OK) return s;
+    hipError_t e = hipMemcpyAsync(b->res_host, dres, (size_t)n * sizeof(rl_result), hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(e, "batch relocalise");
+    std::memcpy(results, b->res_host, (size_t)n * sizeof(rl_result));
+    return RL_OK;
+}
+
+static rl_status set_timer(Timer* t, int32_t kernel, void* start_event, void* stop_event)
+{
+    if (kernel < RL_TIMER_NONE || kernel > RL_TIMER_RANSAC) return fail(RL_EINVAL, "unknown timer kernel %d", kernel);
+    if (kernel != RL_TIMER_NONE && (!start_event || !stop_event)) return fail(RL_EINVAL, "timer events are NULL");
+    t->kernel = kernel;
+    t->start = reinterpret_cast<hipEvent_t>(start_event);
+    t->stop = reinterpret_cast<hipEvent_t>(stop_event);
+    return RL_OK;
+}
+
+RL_API rl_status relocaliser_set_timer(rl_room* r, int32_t kernel, void* start_event, void* stop_event)
+{
+    if (!r) return fail(RL_EINVAL, "room is NULL");
+    return set_timer(&r->timer, kernel, start_event, stop_event);
+}
+
+RL_API rl_status rl_batch_set_timer(rl_batch* b, int32_t kernel, void* start_event, void* stop_event)
+{
+    if (!b) return fail(RL_EINVAL, "batch is NULL");
+    return set_timer(&b->timer, kernel, start_event, stop_event);
+}

@@ -62,19 +62,24 @@ def decimate(fr: Frame) -> Frame:
 
 
 def c1(room_id: int = 0, n_queries: int = 1) -> Workload:
+    """160x120 frames; 4 adaptation frames within 10 cm / 10 degrees of the
+    first query; further queries within 10 cm / 10 degrees of an adaptation
+    frame."""
     params = _presets.preset("c1")
     room = _scene.make_room(room_id)
     nodes = _forest.make_forest(1000 + room_id, **_presets.FOREST["c1"])
     rng = np.random.default_rng(frame_seed(room_id, 9, 0))
     w, h = 160, 120
     queries, adapt = [], []
-    for q in range(n_queries):
-        qpose = _scene.random_pose(room, rng)
-        queries.append(_frame(room, qpose, w, h, frame_seed(room_id, 1, q)))
-        if q == 0:
-            for i in range(4):
-                ap = _scene.near_pose(room, qpose, rng, 0.10, 10.0)
-                adapt.append(_frame(room, ap, w, h, frame_seed(room_id, 0, i)))
+    qpose = _scene.random_pose(room, rng)
+    queries.append(_frame(room, qpose, w, h, frame_seed(room_id, 1, 0)))
+    for i in range(4):
+        ap = _scene.near_pose(room, qpose, rng, 0.10, 10.0)
+        adapt.append(_frame(room, ap, w, h, frame_seed(room_id, 0, i)))
+    for q in range(1, n_queries):
+        base = adapt[int(rng.integers(len(adapt)))].pose
+        queries.append(_frame(room, _scene.near_pose(room, base, rng, 0.10, 10.0), w, h,
+                              frame_seed(room_id, 1, q)))
     return Workload("c1", params, room, nodes, adapt, queries)
 
 

@@ -1,0 +1,134 @@
+"""The C-ABI library loads and exports every entry point include/rl.h declares;
+the ctypes layouts match the header; host-side validation (no GPU work)."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rl.h")
+
+rl = pytest.importorskip("paper_1810_12163_amd")
+
+
+def built():
+    return os.path.exists(rl.LIB_PATH)
+
+
+pytestmark = pytest.mark.skipif(not built(), reason="librl.so not built (run __graft_entry__.build())")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z_0-9]*\s*\*?\s*([a-z_][a-z_0-9]*)\s*\(", src, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "sizeof")))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 15
+    assert sorted(names) == sorted(rl.EXPORTS)
+    out = subprocess.run(["nm", "-D", "--defined-only", rl.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    exported = set(line.split()[-1] for line in out.splitlines() if " T " in line)
+    for n in names:
+        assert n in exported, n
+    L = rl.lib()
+    for n in names:
+        assert getattr(L, n) is not None
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    prog = tmp_path / "layout.c"
+    prog.write_text('''
+#include <stdio.h>
+#include <stddef.h>
+#include "rl.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(rl_params), sizeof(rl_frame), sizeof(rl_result),
+         sizeof(rl_request), sizeof(rl_batch_params), sizeof(rl_hypothesis), sizeof(rl_node));
+  printf("%zu %zu %zu %zu\\n", offsetof(rl_params, seed), offsetof(rl_frame, K), offsetof(rl_result, n_out),
+         offsetof(rl_request, request_seed));
+  return 0;
+}
+''')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(prog)], check=True)
+    a, b = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.strip().splitlines()
+    sizes = [int(v) for v in a.split()]
+    offs = [int(v) for v in b.split()]
+    assert sizes == [ctypes.sizeof(rl.Params), ctypes.sizeof(rl.Frame), ctypes.sizeof(rl.Result),
+                     ctypes.sizeof(rl.Request), ctypes.sizeof(rl.BatchParams), rl.HYP_DTYPE.itemsize,
+                     rl.NODE_DTYPE.itemsize]
+    assert offs == [rl.Params.seed.offset, rl.Frame.K.offset, rl.Result.n_out.offset,
+                    rl.Request.request_seed.offset]
+
+
+def test_presets_match_the_shared_presets():
+    from rlsynth import presets
+    for name in ["default", "fast", "intermediate", "slow", "c1", "c2"]:
+        got = rl.preset(name)
+        want = presets.preset(name)
+        for k, v in got.items():
+            assert k in want
+            if isinstance(v, float):
+                assert abs(v - want[k]) <= 1e-6 * max(1.0, abs(want[k])), (name, k)
+            else:
+                assert v == want[k], (name, k, v, want[k])
+    with pytest.raises(rl.RlError):
+        rl.preset("nope")
+
+
+def validate(**over):
+    p = rl.preset("c2")
+    p.update(over)
+    return rl.lib().rl_params_validate(ctypes.byref(rl.params_struct(p)))
+
+
+def test_parameter_validation():
+    assert validate() == rl.RL_OK
+    assert validate(pose_update=1) == rl.RL_EINVAL
+    assert "pose_update" in rl.lib().rl_last_error().decode()
+    for bad in [dict(n_trees=0), dict(n_trees=9), dict(depth=16), dict(depth=0),
+                dict(max_cluster_count=65), dict(n_trees=8, max_cluster_count=40),
+                dict(reservoir_capacity=0), dict(reservoir_capacity=5000),
+                dict(max_pose_candidates=0), dict(max_pose_candidates=5000),
+                dict(ransac_inliers_per_iteration=0), dict(max_relocalisations_to_output=0),
+                dict(clusterer_sigma=0.0), dict(max_colour_linf=float("nan")),
+                dict(inlier_threshold=-1.0), dict(min_cluster_size=0)]:
+        assert validate(**bad) == rl.RL_EINVAL, bad
+
+
+def test_state_sizes():
+    p = rl.params_struct(rl.preset("c2"))
+    pb, sb = ctypes.c_size_t(), ctypes.c_size_t()
+    assert rl.lib().relocaliser_state_bytes(ctypes.byref(p), 640, 480, ctypes.byref(pb), ctypes.byref(sb)) == 0
+    # reservoirs: 5 trees x 32768 leaves x 1024 entries x 16 B
+    assert pb.value >= 5 * 32768 * 1024 * 16
+    assert pb.value < 5 * 32768 * 1024 * 16 + 200 * 2**20
+    assert 0 < sb.value < 64 * 2**20
+    for w, h in [(642, 480), (640, 0), (4, 4)]:
+        assert rl.lib().relocaliser_state_bytes(ctypes.byref(p), w, h, ctypes.byref(pb), ctypes.byref(sb)) == rl.RL_EINVAL
+    bp = rl.BatchParams(64, 640, 480, 1024, 500, 10, 5, 50)
+    nb = ctypes.c_size_t()
+    assert rl.lib().rl_batch_workspace_bytes(ctypes.byref(bp), ctypes.byref(nb)) == 0
+    assert nb.value > 64 * 640 * 480 * 24
+    bp.max_hypotheses = 5000
+    assert rl.lib().rl_batch_workspace_bytes(ctypes.byref(bp), ctypes.byref(nb)) == rl.RL_EINVAL
+
+
+def test_rounds_formula():
+    assert rl.rounds_for(1024, 1024, 1) == 10
+    assert rl.rounds_for(64, 64, 1) == 6
+    assert rl.rounds_for(4096, 4096, 16) == 8
+    assert rl.rounds_for(256, 256, 1) == 8
+    assert rl.rounds_for(1024, 64, 16) == 3
+    assert rl.rounds_for(1, 1, 1) == 1
+
+
+def test_version():
+    assert b"librl" in rl.lib().rl_version()

@@ -1,0 +1,197 @@
+"""HIP path vs the oracle on identical seeded inputs (small config: 160x120,
+one depth-8 tree, kappa 64, 64 hypotheses, eta 100).
+
+Bar: leaf indices, eligible pixels, reservoir contents and counters,
+sampled triplets and accepted iterations bit-exact; mode counts exact and
+mode rows to float32 rounding; hypothesis poses to 1e-5; energies to 1e-4
+relative; the final pose to 1e-5 (and within 1 cm / 1 degree).  Stage parity
+feeds the GPU's own upstream arrays to the oracle."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+import paper_1810_12163_amd as rl  # noqa: E402
+from rlsynth import scene, workloads  # noqa: E402
+from tests.gpu_util import compare_modes, dev, gpu_state, pose_diff, reservoir_mismatches  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def c1():
+    print("\n[c1 fixture] building workload, oracle and GPU room", flush=True)
+    w = workloads.c1(n_queries=3)
+    o = oracle.Oracle(w.params, w.nodes)
+    room = rl.Room(w.params, w.nodes, 160, 120)
+    for f in w.adapt:
+        o.adapt(f.depth, f.rgb, f.K, f.pose)
+        d, c = dev(f)
+        room.adapt(d, c, f.K, f.pose)
+    torch.cuda.synchronize()
+    return w, o, room
+
+
+def test_c1_reservoirs_bit_exact(c1):
+    w, o, room = c1
+    T, L, kappa, M = o.T, o.L, o.kappa, o.M
+    seen, res, _, _ = gpu_state(room, T, L, kappa, M)
+    np.testing.assert_array_equal(seen, o.seen)
+    bad, total = reservoir_mismatches(seen, res, o.reservoir, kappa)
+    assert total > 1000 and bad == 0, (bad, total)
+    dirty = room.buffer_np(rl.BUF_DIRTY, np.uint32)
+    np.testing.assert_array_equal(dirty != 0, o.dirty != 0)
+
+
+def test_c1_modes(c1):
+    w, o, room = c1
+    room.update_modes()
+    o.update_modes()
+    _, _, nm_g, modes_g = gpu_state(room, o.T, o.L, o.kappa, o.M)
+    assert int(o.nmodes.sum()) > 20
+    bad, worst = compare_modes(nm_g, modes_g, o.nmodes, o.modes, o.M, range(o.T * o.L))
+    assert bad == 0 and worst < 1e-5, (bad, worst)
+    assert not np.any(room.buffer_np(rl.BUF_DIRTY, np.uint32))
+
+
+@pytest.mark.parametrize("qi", [0, 1, 2])
+def test_c1_relocalise_stage_parity(c1, qi):
+    w, o, room = c1
+    q = w.queries[qi]
+    room.set_trace(True)
+    d, c = dev(q)
+    seed = 11 + qi
+    res = room.relocalise(d, c, q.K, request_seed=seed)
+    h, wd = q.depth.shape
+    P = h * wd
+    T = o.T
+    # leaves: bit-exact against the oracle's own traversal
+    leaves_g = room.buffer_np(rl.BUF_LEAVES, np.uint16).reshape(-1, 8)[:P, :T]
+    leaves_o = o.traverse(q.depth, q.rgb)
+    np.testing.assert_array_equal(leaves_g, leaves_o)
+    # modes used by the GPU (identical to the oracle's, checked above)
+    _, _, nm_g, modes_g = gpu_state(room, o.T, o.L, o.kappa, o.M)
+    ref = oracle.estimate_pose(q.depth, q.rgb, q.K, leaves_g, nm_g, modes_g.reshape(-1), T, o.D, o.M,
+                               w.params, seed)
+    n_el = res["n_eligible"]
+    assert n_el == len(ref["eligible"]) > 1000
+    el_g = room.buffer_np(rl.BUF_ELIGIBLE, np.int32)[:n_el]
+    np.testing.assert_array_equal(el_g, ref["eligible"])
+    nm_px = room.buffer_np(rl.BUF_NM, np.uint8)[:P]
+    np.testing.assert_array_equal(nm_px.astype(np.int32), ref["nm"])
+    # hypotheses: triplets, modes and iterations bit-exact, poses to 1e-5
+    N = w.params["max_pose_candidates"]
+    hy = room.buffer_np(rl.BUF_HYPS, rl.HYP_DTYPE)[:N]
+    np.testing.assert_array_equal(hy["valid"].astype(bool), ref["hyp_valid"].astype(bool))
+    v = ref["hyp_valid"].astype(bool)
+    if not v.any():
+        assert res["status"] == ref["status"] == "no_pose" and res["n_valid"] == 0
+        return
+    np.testing.assert_array_equal(hy["iter"][v], ref["hyp_iter"][v])
+    np.testing.assert_array_equal(hy["pix"][v], ref["hyp_pix"][v])
+    np.testing.assert_array_equal(hy["mode"][v], ref["hyp_mode"][v])
+    np.testing.assert_allclose(hy["R"][v], ref["hyp_pose"][v][:, :9], atol=1e-5)
+    np.testing.assert_allclose(hy["t"][v], ref["hyp_pose"][v][:, 9:], atol=1e-5)
+    # RANSAC rounds: survivors per round equal, energies to 1e-4 relative
+    assert res["rounds"] == ref["rounds"]
+    eta = w.params["ransac_inliers_per_iteration"]
+    Ig = room.buffer_np(rl.BUF_ILIST, np.int32)[:ref["rounds"] * eta]
+    np.testing.assert_array_equal(Ig, ref["I"])
+    ts = room.buffer_np(rl.BUF_TRACE_SLOTS, np.int32).reshape(-1, N)
+    te = room.buffer_np(rl.BUF_TRACE_ENERGY, np.float64).reshape(-1, N)
+    for r in range(ref["rounds"]):
+        k = len(ref["round_slots"][r])
+        np.testing.assert_array_equal(ts[r, :k], ref["round_slots"][r])
+        np.testing.assert_allclose(te[r, :k], ref["round_energy"][r], rtol=1e-4)
+    # result
+    assert res["status"] == ref["status"] == "ok"
+    assert res["winner"] == ref["winner"]
+    assert pose_diff(res["pose"], ref["pose"]) < 1e-5
+    assert abs(res["energy"] - ref["energy"]) <= 1e-4 * abs(ref["energy"])
+    dt, dr = scene.pose_error(res["pose"].astype(np.float64), ref["pose"])
+    assert dt < 0.01 and dr < 1.0
+    room.set_trace(False)
+
+
+def test_c1_deterministic(c1):
+    w, o, room = c1
+    q = w.queries[0]
+    d, c = dev(q)
+    a = room.relocalise(d, c, q.K, request_seed=5)
+    hy_a = room.buffer_np(rl.BUF_HYPS, rl.HYP_DTYPE).copy()
+    b = room.relocalise(d, c, q.K, request_seed=5)
+    hy_b = room.buffer_np(rl.BUF_HYPS, rl.HYP_DTYPE).copy()
+    assert np.array_equal(a["pose"], b["pose"]) and a["energy"] == b["energy"]
+    assert hy_a.tobytes() == hy_b.tobytes()
+    room.relocalise(d, c, q.K, request_seed=6)
+    hy_c = room.buffer_np(rl.BUF_HYPS, rl.HYP_DTYPE).copy()
+    assert hy_c.tobytes() != hy_a.tobytes()          # another request seed, another stream
+
+
+def test_no_pose_cases(c1):
+    w, o, room = c1
+    q = w.queries[0]
+    d, c = dev(q)
+    res = room.relocalise(torch.zeros_like(d), c, q.K)
+    assert res["status"] == "no_pose" and res["n_eligible"] == 0 and res["energy"] == float("inf")
+    assert np.array_equal(res["pose"], np.eye(4, dtype=np.float32))
+    fresh = rl.Room(w.params, w.nodes, 160, 120)          # no adaptation: no modes anywhere
+    res = fresh.relocalise(d, c, q.K)
+    assert res["status"] == "no_pose" and res["n_eligible"] == 0
+    fresh.close()
+
+
+def test_invalid_arguments_rejected_before_launch(c1):
+    w, o, room = c1
+    q = w.queries[0]
+    d, c = dev(q)
+    with pytest.raises(rl.RlError):
+        room.relocalise(d[:, :158].contiguous(), c[:, :158].contiguous(), q.K)     # width not /4
+    big = torch.zeros((240, 320), dtype=torch.float32, device="cuda")
+    with pytest.raises(rl.RlError):
+        room.relocalise(big, torch.zeros((240, 320, 3), dtype=torch.uint8, device="cuda"), q.K)
+    with pytest.raises(rl.RlError):
+        room.adapt(d, c, q.K, np.diag([2.0, 1, 1, 1]))                              # not rigid
+    with pytest.raises(rl.RlError):
+        room.relocalise(d, c, (0.0, 1.0, 80.0, 60.0))                               # bad intrinsics
+    bad_nodes = w.nodes.copy()
+    bad_nodes["kind"][0, 3] = 7
+    with pytest.raises(rl.RlError):
+        rl.Room(w.params, bad_nodes, 160, 120)
+    p = dict(w.params, pose_update=1)
+    with pytest.raises(rl.RlError):
+        rl.Room(p, w.nodes, 160, 120)
+    # unreliable frames are not inserted
+    before = room.buffer_np(rl.BUF_SEEN, np.uint32).copy()
+    room.adapt(d, c, q.K, q.pose, reliable=False)
+    np.testing.assert_array_equal(room.buffer_np(rl.BUF_SEEN, np.uint32), before)
+
+
+def test_batch_equals_plain(c1):
+    """Batched relocalisation (graph replay and direct launches) gives exactly
+    the plain path's result for every (room, frame, seed), whatever the mix."""
+    w, o, room = c1
+    w2 = workloads.c1(room_id=1, n_queries=2)
+    room2 = rl.Room(w2.params, w2.nodes, 160, 120)
+    for f in w2.adapt:
+        d, c = dev(f)
+        room2.adapt(d, c, f.K, f.pose)
+    frames = [(room, w.queries[i], 100 + i) for i in range(3)] + [(room2, w2.queries[i], 7 + i) for i in range(2)]
+    frames = frames + [(room, w.queries[0], 999)]
+    devf = [(r, *dev(q), q.K, s) for (r, q, s) in frames]
+    plain = [r.relocalise(d, c, K, request_seed=s) for (r, d, c, K, s) in devf]
+    batch = rl.Batch(8, 160, 120, 64, 100, 6, 1, 5)
+    for use_graph in (False, True, True):
+        got = batch.relocalise(devf, use_graph=use_graph)
+        for a, b in zip(got, plain):
+            assert a["status"] == b["status"] and a["winner"] == b["winner"]
+            assert np.array_equal(a["pose"], b["pose"]) and a["energy"] == b["energy"]
+    # a different mix and order reuses nothing it should not
+    got = batch.relocalise(devf[::-1][:4], use_graph=True)
+    for a, b in zip(got, plain[::-1][:4]):
+        assert np.array_equal(a["pose"], b["pose"]) and a["energy"] == b["energy"]
+    batch.close()
+    room2.close()

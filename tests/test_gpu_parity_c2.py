@@ -1,0 +1,116 @@
+"""HIP path vs the oracle at the full size of the 640x480 workload: five
+depth-15 trees, reservoirs of 1024 entries, 50 adaptation frames (every
+4th-grid pixel), 1024 hypotheses, eta 500, ten halving rounds and the final
+inlier refit.  Everything the oracle can afford is compared in full:
+arrival counters and every filled reservoir entry (bit-exact), leaves of every
+pixel, the eligible list, every hypothesis, every round; modes on sampled
+leaves (the fullest reservoirs plus a random sample)."""
+import numpy as np
+import pytest
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(600)]
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+import paper_1810_12163_amd as rl  # noqa: E402
+from rlsynth import scene, workloads  # noqa: E402
+from tests.gpu_util import compare_modes, dev, pose_diff, reservoir_mismatches  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def c2():
+    print("\n[c2 fixture] rendering 50 adaptation frames + 2 queries", flush=True)
+    w = workloads.c2(n_adapt=50, n_queries=2)
+    o = oracle.Oracle(w.params, w.nodes)
+    room = rl.Room(w.params, w.nodes, 640, 480)
+    for f in w.adapt:
+        o.adapt(f.depth, f.rgb, f.K, f.pose)
+        d, c = dev(f)
+        room.adapt(d, c, f.K, f.pose)
+    torch.cuda.synchronize()
+    print("[c2 fixture] adapted", flush=True)
+    return w, o, room
+
+
+def test_c2_reservoirs_bit_exact(c2):
+    w, o, room = c2
+    seen = room.buffer_np(rl.BUF_SEEN, np.uint32).copy()
+    np.testing.assert_array_equal(seen, o.seen)
+    assert int(seen.sum()) > 4_000_000
+    res = room.buffer_np(rl.BUF_RESERVOIR, np.float32).reshape(o.T * o.L, o.kappa, 4)
+    bad, total = reservoir_mismatches(seen, res, o.reservoir, o.kappa)
+    assert bad == 0, (bad, total)
+    assert total > 2_000_000
+    del res
+
+
+def test_c2_modes_sampled_leaves(c2):
+    w, o, room = c2
+    room.update_modes()
+    nm_g = room.buffer_np(rl.BUF_NMODES, np.uint8).copy()
+    modes_g = room.buffer_np(rl.BUF_MODES, np.float32).reshape(o.T * o.L, o.M, 16)
+    seen = o.seen
+    order = np.argsort(-seen.astype(np.int64), kind="stable")
+    rng = np.random.default_rng(0)
+    nonempty = np.flatnonzero(seen > 0)
+    sample = np.unique(np.concatenate([order[:300], rng.choice(nonempty, 1500, replace=False)]))
+    p = w.params
+    nm_o = np.zeros_like(nm_g)
+    modes_o = np.zeros((o.T * o.L, o.M, 16), np.float32)
+    for tl in sample:
+        t, leaf = divmod(int(tl), o.L)
+        rows, _ = oracle.rqs_leaf(o.reservoir_of(t, leaf), p["clusterer_sigma"], p["clusterer_tau"],
+                                  p["min_cluster_size"], o.M, p["cov_regulariser"])
+        nm_o[tl] = rows.shape[0]
+        modes_o[tl, :rows.shape[0]] = rows
+    assert int(nm_o[sample].sum()) > 500
+    bad, worst = compare_modes(nm_g, modes_g, nm_o, modes_o.reshape(-1), o.M, sample)
+    assert bad == 0 and worst < 1e-5, (bad, worst)
+
+
+def test_c2_relocalise_full_stage_parity(c2):
+    w, o, room = c2
+    q = w.queries[0]
+    room.set_trace(True)
+    d, c = dev(q)
+    seed = 3
+    res = room.relocalise(d, c, q.K, request_seed=seed)
+    P = q.depth.size
+    leaves_g = room.buffer_np(rl.BUF_LEAVES, np.uint16).reshape(-1, 8)[:P, :o.T].copy()
+    np.testing.assert_array_equal(leaves_g, o.traverse(q.depth, q.rgb))
+    nm_g = room.buffer_np(rl.BUF_NMODES, np.uint8).copy()
+    modes_g = room.buffer_np(rl.BUF_MODES, np.float32).copy()
+    ref = oracle.estimate_pose(q.depth, q.rgb, q.K, leaves_g, nm_g, modes_g, o.T, o.D, o.M, w.params, seed)
+    n_el = res["n_eligible"]
+    assert n_el == len(ref["eligible"]) > 100_000
+    np.testing.assert_array_equal(room.buffer_np(rl.BUF_ELIGIBLE, np.int32)[:n_el], ref["eligible"])
+    N = w.params["max_pose_candidates"]
+    hy = room.buffer_np(rl.BUF_HYPS, rl.HYP_DTYPE)[:N]
+    v = ref["hyp_valid"].astype(bool)
+    np.testing.assert_array_equal(hy["valid"].astype(bool), v)
+    assert v.sum() >= 8
+    np.testing.assert_array_equal(hy["iter"][v], ref["hyp_iter"][v])
+    np.testing.assert_array_equal(hy["pix"][v], ref["hyp_pix"][v])
+    np.testing.assert_array_equal(hy["mode"][v], ref["hyp_mode"][v])
+    np.testing.assert_allclose(hy["R"][v], ref["hyp_pose"][v][:, :9], atol=1e-5)
+    np.testing.assert_allclose(hy["t"][v], ref["hyp_pose"][v][:, 9:], atol=1e-5)
+    assert res["rounds"] == ref["rounds"]
+    eta = w.params["ransac_inliers_per_iteration"]
+    np.testing.assert_array_equal(room.buffer_np(rl.BUF_ILIST, np.int32)[:ref["rounds"] * eta], ref["I"])
+    ts = room.buffer_np(rl.BUF_TRACE_SLOTS, np.int32).reshape(-1, N)
+    te = room.buffer_np(rl.BUF_TRACE_ENERGY, np.float64).reshape(-1, N)
+    for r in range(ref["rounds"]):
+        k = len(ref["round_slots"][r])
+        np.testing.assert_array_equal(ts[r, :k], ref["round_slots"][r])
+        np.testing.assert_allclose(te[r, :k], ref["round_energy"][r], rtol=1e-4)
+    assert res["status"] == "ok" and res["winner"] == ref["winner"]
+    assert res["refitted"] == ref["refitted"] and res["n_inliers"] == ref["n_inliers"]
+    assert pose_diff(res["pose"], ref["pose"]) < 1e-5
+    assert abs(res["energy"] - ref["energy"]) <= 1e-4 * abs(ref["energy"])
+    dt, dr = scene.pose_error(res["pose"].astype(np.float64), q.pose)
+    print(f"[c2] pose error vs ground truth: {dt * 100:.2f} cm, {dr:.2f} deg; "
+          f"valid hypotheses {int(v.sum())}", flush=True)
+    room.set_trace(False)
