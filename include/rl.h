@@ -149,7 +149,9 @@ rl_status relocaliser_adapt(rl_room* room, const rl_frame* frame, const float ca
 rl_status relocaliser_update_modes(rl_room* room);
 
 /*
- * Relocalises one frame (Sec. 3.2.3): synchronous on the room's stream.
+ * Relocalises one frame (Sec. 3.2.3): synchronous on the room's stream.  On
+ * a non-default stream the launch sequence is captured once per frame size
+ * into a HIP graph and replayed (direct launches while a kernel timer is set).
  * request_seed selects the generator stream of this request (results do not
  * depend on anything else).  Outputs (host): cam_to_world_out[16], energy_out
  * = Eq. 5 energy of the winning hypothesis over the final pixel set (before
@@ -269,7 +271,7 @@ rl_status rl_batch_relocalise_async(rl_batch* b, const rl_request* reqs, int32_t
  * Kernel timing: when kernel != RL_TIMER_NONE, the library records
  * start_event just before and stop_event just after that kernel (or kernel
  * group) on the stream it launches it on, in every later relocalisation of
- * this room / batch (also inside captured graphs).  The events are the
+ * this room / batch (such calls launch directly, not from a graph).  The events are the
  * caller's hipEvent_t handles, created with timing enabled; read them with
  * hipEventElapsedTime after the call has completed.
  */

@@ -521,11 +521,12 @@ static const float* mode_row(const view_t* v, int pix, int m)
  * Pose hypothesis generation (Sec. 3.2.3).  Slot h tries iterations
  * it = 0, 1, ... < max_iters; iteration it draws two Philox blocks with
  * counters (HYP | blk, h, it, 0), blk = 0, 1, under the stream key of
- * (seed, request_seed), giving draws r0..r7: r0-r2 pick three eligible pixels
- * (uniform over the raster-ordered eligible list), r3-r5 pick one mode of
- * M(u_k) each (uniform over the tree-major concatenation), r6 picks the pair
- * used by the colour check.  Checks, in the paper's
- * order: (1) L-infinity colour distance between that pixel and its mode's
+ * (seed, request_seed).  Block 0 serves the pair the colour check looks at:
+ * a0 picks that pair k* in {0, 1, 2}, a1 its pixel (uniform over the
+ * raster-ordered eligible list) and a2 its mode (uniform over the tree-major
+ * concatenation M(u)).  Block 1 serves the other two pairs in increasing
+ * order: b0, b1 their pixels, b2, b3 their modes.  Checks, in the paper's
+ * order: (1) L-infinity colour distance between pixel k* and its mode's
  * colour centroid must not exceed max_colour_linf (float32); (2) every
  * pairwise squared distance between the world points must be >=
  * min_sq_dist; (3) for every pair, | |x^C_a - x^C_b| - |x^W_a - x^W_b| | must not
@@ -553,22 +554,33 @@ EXPORT void oracle_hypotheses(const float* depth, const uint8_t* rgb, int w, int
         iter_out[s] = -1;
         if (n_elig <= 0) continue;
         for (int it = 0; it < max_iters; ++it) {
-            uint32_t r[8];
-            philox_block(TAG_HYP, 0, (uint32_t)s, (uint32_t)it, 0, key, r);
-            philox_block(TAG_HYP, 1, (uint32_t)s, (uint32_t)it, 0, key, r + 4);
+            uint32_t ra[4], rb[4];
+            philox_block(TAG_HYP, 0, (uint32_t)s, (uint32_t)it, 0, key, ra);
+            philox_block(TAG_HYP, 1, (uint32_t)s, (uint32_t)it, 0, key, rb);
+            int kc = (int)uniform_below(ra[0], 3);
+            uint32_t rpix[3], rmode[3];
+            for (int k = 0, other = 0; k < 3; ++k) {
+                if (k == kc) {
+                    rpix[k] = ra[1];
+                    rmode[k] = ra[2];
+                } else {
+                    rpix[k] = rb[other];
+                    rmode[k] = rb[2 + other];
+                    ++other;
+                }
+            }
             int pix[3], mi[3];
             const float* row[3];
             double xc[9], xw[9];
             for (int k = 0; k < 3; ++k) {
-                pix[k] = eligible[uniform_below(r[k], (uint32_t)n_elig)];
+                pix[k] = eligible[uniform_below(rpix[k], (uint32_t)n_elig)];
                 int nm = modes_of(&v, pix[k]);
-                mi[k] = (int)uniform_below(r[3 + k], (uint32_t)nm);
+                mi[k] = (int)uniform_below(rmode[k], (uint32_t)nm);
                 row[k] = mode_row(&v, pix[k], mi[k]);
                 backproject(depth[pix[k]], pix[k] % w, pix[k] / w, K, xc + 3 * k);
                 for (int a = 0; a < 3; ++a) xw[3 * k + a] = (double)row[k][a];
             }
             /* check 1: colour of one randomly chosen pair */
-            int kc = (int)uniform_below(r[6], 3);
             int ok = 1;
             for (int c = 0; c < 3; ++c) {
                 float diff = fabsf((float)rgb[(size_t)pix[kc] * 3 + c] - row[kc][10 + c]);

@@ -206,7 +206,9 @@ class Room:
         self.device = torch.device(device if device is not None else "cuda")
         self.persistent = torch.empty(pb.value, dtype=torch.uint8, device=self.device)
         self.scratch = torch.empty(sb.value, dtype=torch.uint8, device=self.device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # a stream of its own (default priority) so that relocalisation can replay a graph
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
         nodes = np.ascontiguousarray(nodes)
         if nodes.dtype.itemsize != 16 or nodes.size != params["n_trees"] * ((1 << params["depth"]) - 1):
             raise ValueError("nodes must hold n_trees * (2^depth - 1) 16-byte records")
@@ -229,17 +231,25 @@ class Room:
         except Exception:
             pass
 
+    def _follow(self):
+        """Orders the room's stream after the caller's current stream (where
+        the frame tensors were written)."""
+        self.stream.wait_stream(_torch().cuda.current_stream(self.device))
+
     def adapt(self, depth, rgb, K, pose, reliable: bool = True):
         f = _frame(depth, rgb, K)
         H = np.ascontiguousarray(np.asarray(pose, dtype=np.float32).reshape(16))
+        self._follow()
         _check(lib().relocaliser_adapt(self.handle, ctypes.byref(f), H.ctypes.data, 1 if reliable else 0))
 
     def update_modes(self):
+        self._follow()
         _check(lib().relocaliser_update_modes(self.handle))
 
     def relocalise(self, depth, rgb, K, request_seed: int = 0) -> dict:
         f = _frame(depth, rgb, K)
         r = Result()
+        self._follow()
         _check(lib().relocaliser_relocalise_ex(self.handle, ctypes.byref(f), int(request_seed),
                                                ctypes.byref(r)), allow=(RL_OK, RL_NO_POSE))
         return _result(r)
@@ -262,7 +272,9 @@ class Room:
 
     def buffer_np(self, which: int, dtype) -> np.ndarray:
         self.stream.synchronize()
-        return self.buffer(which).cpu().numpy().view(dtype)
+        with _torch().cuda.stream(self.stream):
+            out = self.buffer(which).cpu().numpy().view(dtype)
+        return out
 
 
 class Batch:

@@ -133,63 +133,94 @@ __global__ __launch_bounds__(256) void k_eligible(const Job* __restrict__ jobs)
 }
 
 // ------------------------------------------------------------------------
-// One generation iteration (Sec. 3.2.3): three pixels and one mode each from
-// Philox counters (HYP|blk, slot, it, 0), blk = 0, 1; the colour check on the
-// drawn pair, the minimum-distance check, the rigidity check, then Kabsch.
-// The check quantities are evaluated exactly as written (no contraction).
+// Hypothesis generation (Sec. 3.2.3).  Iteration it of slot s draws two
+// Philox blocks, counters (HYP|blk, s, it, 0).  Block 0 serves the pair the
+// colour check looks at: a.x picks that pair k* in {0,1,2}, a.y its pixel
+// (eligible list), a.z its mode (M(u)); block 1 serves the other two pairs in
+// increasing order (b.x, b.y pixels; b.z, b.w modes).  Checks: (1) colour of
+// pair k* (L-infinity, float32), (2) pairwise world distances^2 >= min, (3)
+// rigidity, then Kabsch non-degenerate.  Check quantities are evaluated
+// exactly as written (no contraction).
+//
+// The search is split in two stages so that the cheap, selective colour
+// check (about 1 in 9 passes) runs dense over many iterations and only its
+// survivors, compacted into an LDS queue, pay for the other two pixels, the
+// back-projections and the rigidity test: lanes stay busy instead of idling
+// behind divergent branches.
+
+__device__ __forceinline__ uint32_t mode_row_index(const Job& J, uint4 lw, uint2 nw, int m)
+{
+    int t = 0;
+    for (; t < J.T - 1; ++t) {
+        const int c = (int)count_of(nw, t);
+        if (m < c) break;
+        m -= c;
+    }
+    return ((((uint32_t)t << J.D) + leaf_of(lw, t)) * (uint32_t)J.M + (uint32_t)m);
+}
+
+// pixel and mode of one pair from its two draws
+__device__ __forceinline__ void draw_pair(const Job& J, int n_elig, uint32_t rp, uint32_t rm, int& p,
+                                          int& m, uint32_t& row)
+{
+    p = J.eligible[below(rp, (uint32_t)n_elig)];
+    const uint4 lw = reinterpret_cast<const uint4*>(J.leaves)[p];
+    const uint2 nw = reinterpret_cast<const uint2*>(J.nmt)[p];
+    m = (int)below(rm, (uint32_t)modes_total(nw, J.T));
+    row = mode_row_index(J, lw, nw, m);
+}
+
+// stage A: the colour check of pair k*
+__device__ __forceinline__ bool hyp_stage_a(const Job& J, int n_elig, int slot, int it, int& kc, int& pc,
+                                            int& mc, uint32_t& rowc)
+{
+    const uint4 a = philox(make_uint4((kTagHyp << 28) | 0u, (uint32_t)slot, (uint32_t)it, 0u), J.key0, J.key1);
+    kc = (int)below(a.x, 3u);
+    draw_pair(J, n_elig, a.y, a.z, pc, mc, rowc);
+    const float4* row = J.modes + (size_t)rowc * 4;
+    const float4 c2 = row[2], c3 = row[3];
+    const uint8_t* px = J.rgb + 3 * pc;
+    return !(fabsf((float)px[0] - c2.z) > J.theta_col || fabsf((float)px[1] - c2.w) > J.theta_col ||
+             fabsf((float)px[2] - c3.x) > J.theta_col);
+}
+
+// stage B: the other two pairs, checks 2 and 3, Kabsch
 template <bool WRITE>
-__device__ __forceinline__ bool hyp_try(const Job& J, int n_elig, int slot, int it, Hyp* out)
+__device__ __forceinline__ bool hyp_stage_b(const Job& J, int n_elig, int slot, int it, int kc, int pc, int mc,
+                                            uint32_t rowc, Hyp* out)
 {
 #pragma clang fp contract(off)
-    const uint4 a = philox(make_uint4((kTagHyp << 28) | 0u, (uint32_t)slot, (uint32_t)it, 0u), J.key0, J.key1);
     const uint4 b = philox(make_uint4((kTagHyp << 28) | 1u, (uint32_t)slot, (uint32_t)it, 0u), J.key0, J.key1);
-    const uint32_t rp[3] = {a.x, a.y, a.z}, rm[3] = {a.w, b.x, b.y};
-    const int kc = (int)below(b.z, 3u);
-    int pix[3], mi[3];
-    double xc[3][3], xw[3][3];
-    const float4* crow = nullptr;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const int p = J.eligible[below(rp[k], (uint32_t)n_elig)];
-        pix[k] = p;
-        const uint4 lw = reinterpret_cast<const uint4*>(J.leaves)[p];
-        const uint2 nw = reinterpret_cast<const uint2*>(J.nmt)[p];
-        mi[k] = (int)below(rm[k], (uint32_t)modes_total(nw, J.T));
-        const float4* row = mode_row(J.modes, J.T, J.D, J.M, lw, nw, mi[k]);
-        if (k == kc) crow = row;
-        const float4 mu = row[0];
-        xw[k][0] = mu.x;
-        xw[k][1] = mu.y;
-        xw[k][2] = mu.z;
-        backproject(J.depth[p], p % J.w, p / J.w, J.fx, J.fy, J.cx, J.cy, xc[k]);
-    }
-    // check 1: colour of the drawn pair
-    {
-        const float4 c2 = crow[2], c3 = crow[3];
-        const int pc = kc == 0 ? pix[0] : kc == 1 ? pix[1] : pix[2];
-        const uint8_t* px = J.rgb + 3 * pc;
-        if (fabsf((float)px[0] - c2.z) > J.theta_col || fabsf((float)px[1] - c2.w) > J.theta_col ||
-            fabsf((float)px[2] - c3.x) > J.theta_col)
-            return false;
-    }
-    // checks 2 and 3
+    int qa, qb, ma, mb;
+    uint32_t ra, rb;
+    draw_pair(J, n_elig, b.x, b.z, qa, ma, ra);
+    draw_pair(J, n_elig, b.y, b.w, qb, mb, rb);
+    // pairs in order 0, 1, 2: pair k* is (pc, rowc), the others (qa, ra), (qb, rb) in increasing order
+    const int p0 = kc == 0 ? pc : qa, p1 = kc == 1 ? pc : (kc == 0 ? qa : qb), p2 = kc == 2 ? pc : qb;
+    const uint32_t r0 = kc == 0 ? rowc : ra, r1 = kc == 1 ? rowc : (kc == 0 ? ra : rb), r2 = kc == 2 ? rowc : rb;
+    const float4 w0 = J.modes[(size_t)r0 * 4], w1 = J.modes[(size_t)r1 * 4], w2 = J.modes[(size_t)r2 * 4];
+    const double xw[3][3] = {{w0.x, w0.y, w0.z}, {w1.x, w1.y, w1.z}, {w2.x, w2.y, w2.z}};
     const int PA[3] = {0, 0, 1}, PB[3] = {1, 2, 2};
-    double dw2[3], dc2[3];
+    double dw2[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const double dx = xw[PA[q]][0] - xw[PB[q]][0], dy = xw[PA[q]][1] - xw[PB[q]][1],
+                     dz = xw[PA[q]][2] - xw[PB[q]][2];
+        dw2[q] = dx * dx + dy * dy + dz * dz;
+    }
+    if (dw2[0] < J.min_sq_dist || dw2[1] < J.min_sq_dist || dw2[2] < J.min_sq_dist) return false;
+    double xc[3][3];
+    backproject(J.depth[p0], p0 % J.w, p0 / J.w, J.fx, J.fy, J.cx, J.cy, xc[0]);
+    backproject(J.depth[p1], p1 % J.w, p1 / J.w, J.fx, J.fy, J.cx, J.cy, xc[1]);
+    backproject(J.depth[p2], p2 % J.w, p2 / J.w, J.fx, J.fy, J.cx, J.cy, xc[2]);
     bool ok = true;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-        double dx = xw[PA[q]][0] - xw[PB[q]][0], dy = xw[PA[q]][1] - xw[PB[q]][1], dz = xw[PA[q]][2] - xw[PB[q]][2];
-        dw2[q] = dx * dx + dy * dy + dz * dz;
-        dx = xc[PA[q]][0] - xc[PB[q]][0];
-        dy = xc[PA[q]][1] - xc[PB[q]][1];
-        dz = xc[PA[q]][2] - xc[PB[q]][2];
-        dc2[q] = dx * dx + dy * dy + dz * dz;
-        if (dw2[q] < J.min_sq_dist) ok = false;
+        const double dx = xc[PA[q]][0] - xc[PB[q]][0], dy = xc[PA[q]][1] - xc[PB[q]][1],
+                     dz = xc[PA[q]][2] - xc[PB[q]][2];
+        const double dc2 = dx * dx + dy * dy + dz * dz;
+        if (fabs(sqrt(dc2) - sqrt(dw2[q])) > J.theta_rig) ok = false;
     }
-    if (!ok) return false;
-#pragma unroll
-    for (int q = 0; q < 3; ++q)
-        if (fabs(sqrt(dc2[q]) - sqrt(dw2[q])) > J.theta_rig) ok = false;
     if (!ok) return false;
     double cc[3], cw[3], A[9];
 #pragma unroll
@@ -208,38 +239,63 @@ __device__ __forceinline__ bool hyp_try(const Job& J, int n_elig, int slot, int 
     if (WRITE) {
         for (int i = 0; i < 9; ++i) out->R[i] = (float)R[i];
         for (int i = 0; i < 3; ++i) out->t[i] = (float)t[i];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            out->pix[k] = pix[k];
-            out->mode[k] = mi[k];
-        }
+        out->pix[0] = p0;
+        out->pix[1] = p1;
+        out->pix[2] = p2;
+        out->mode[0] = kc == 0 ? mc : ma;
+        out->mode[1] = kc == 1 ? mc : (kc == 0 ? ma : mb);
+        out->mode[2] = kc == 2 ? mc : mb;
     }
     return true;
 }
 
-// grid.x = Nmax * chunks (chunk-major), 256 iterations per block.  A block
-// whose chunk starts after an already-found passing iteration exits early;
-// the minimum is exact because every lower iteration is always evaluated.
+// grid.x = Nmax * chunks (chunk-major); a block covers 256 * IPT consecutive
+// iterations of one slot.  A block whose chunk starts after an already-found
+// passing iteration exits early; the minimum stays exact because every lower
+// iteration is always evaluated.
+template <int IPT>
 __global__ __launch_bounds__(256) void k_hyp_search(const Job* __restrict__ jobs, int Nmax)
 {
     const Job& J = jobs[blockIdx.y];
     const int slot = blockIdx.x % Nmax, chunk = blockIdx.x / Nmax;
     if (slot >= J.N) return;
-    const int it0 = chunk * 256;
+    const int it0 = chunk * 256 * IPT;
     if (it0 >= J.I_max) return;
     const int n_elig = J.st->n_elig;
     if (n_elig <= 0) return;
     if (__hip_atomic_load(&J.hyp_best[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < it0) return;
-    const int it = it0 + threadIdx.x;
-    const bool pass = it < J.I_max && hyp_try<false>(J, n_elig, slot, it, nullptr);
-    __shared__ int s_min[4];
-    const unsigned long long bal = __ballot(pass);
-    if (wave_lane() == 0) s_min[threadIdx.x >> 6] = bal ? it0 + (threadIdx.x & ~63) + __ffsll((long long)bal) - 1 : INT_MAX;
-    __syncthreads();
+    __shared__ int q_it[256 * IPT];        // iteration | k* << 30
+    __shared__ int q_p[256 * IPT];
+    __shared__ uint32_t q_row[256 * IPT];
+    __shared__ int q_m[256 * IPT];
+    __shared__ int s_n, s_best;
     if (threadIdx.x == 0) {
-        const int m = min(min(s_min[0], s_min[1]), min(s_min[2], s_min[3]));
-        if (m != INT_MAX) atomicMin(&J.hyp_best[slot], m);
+        s_n = 0;
+        s_best = INT_MAX;
     }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+        const int it = it0 + k * 256 + threadIdx.x;
+        int kc, pc, mc;
+        uint32_t rowc;
+        if (it < J.I_max && hyp_stage_a(J, n_elig, slot, it, kc, pc, mc, rowc)) {
+            const int q = atomicAdd(&s_n, 1);
+            q_it[q] = it | (kc << 30);
+            q_p[q] = pc;
+            q_row[q] = rowc;
+            q_m[q] = mc;
+        }
+    }
+    __syncthreads();
+    const int n = s_n;
+    for (int j = threadIdx.x; j < n; j += 256) {
+        const int it = q_it[j] & 0x3FFFFFFF, kc = q_it[j] >> 30;
+        if (hyp_stage_b<false>(J, n_elig, slot, it, kc, q_p[j], q_m[j], q_row[j], nullptr))
+            atomicMin(&s_best, it);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && s_best != INT_MAX) atomicMin(&J.hyp_best[slot], s_best);
 }
 
 __global__ __launch_bounds__(256) void k_hyp_finalize(const Job* __restrict__ jobs)
@@ -258,7 +314,10 @@ __global__ __launch_bounds__(256) void k_hyp_finalize(const Job* __restrict__ jo
     hy.valid = 0;
     const int best = J.hyp_best[slot];
     const int n_elig = J.st->n_elig;
-    if (best < J.I_max && n_elig > 0 && hyp_try<true>(J, n_elig, slot, best, &hy)) {
+    int kc, pc, mc;
+    uint32_t rowc;
+    if (best < J.I_max && n_elig > 0 && hyp_stage_a(J, n_elig, slot, best, kc, pc, mc, rowc) &&
+        hyp_stage_b<true>(J, n_elig, slot, best, kc, pc, mc, rowc, &hy)) {
         hy.iter = best;
         hy.valid = 1;
         atomicAdd(&J.st->n_valid, 1);
@@ -434,7 +493,62 @@ __device__ __forceinline__ double block_sum256(double v, double* s_red)
     return r;
 }
 
-// Winner, optional refit over inliers, result record.
+// Refit, part 1 (one thread per pixel of the final set I): the mode of M(u)
+// minimising the Eq. 5 distance under the winner's pose (ties -> lower m),
+// then the Euclidean inlier test.  J.inl[k] = that mode's row, or -1.
+__global__ __launch_bounds__(256) void k_refit_assign(const Job* __restrict__ jobs)
+{
+    const Job& J = jobs[blockIdx.y];
+    if (!J.final_refine) return;
+    const int n = J.st->n_surv, rounds = J.st->rounds_run;
+    const int nI = rounds * J.eta;
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (n <= 0 || k >= nI) return;
+    const Hyp& hy = J.hyps[J.surv[0]];
+    double R[9], t[3];
+    for (int i = 0; i < 9; ++i) R[i] = hy.R[i];
+    for (int i = 0; i < 3; ++i) t[i] = hy.t[i];
+    const int p = J.I[k];
+    double x[3];
+    backproject(J.depth[p], p % J.w, p / J.w, J.fx, J.fy, J.cx, J.cy, x);
+    const double y0 = R[0] * x[0] + R[1] * x[1] + R[2] * x[2] + t[0];
+    const double y1 = R[3] * x[0] + R[4] * x[1] + R[5] * x[2] + t[1];
+    const double y2 = R[6] * x[0] + R[7] * x[1] + R[8] * x[2] + t[2];
+    const uint4 lw = reinterpret_cast<const uint4*>(J.leaves)[p];
+    const uint2 nw = reinterpret_cast<const uint2*>(J.nmt)[p];
+    const int nm = modes_total(nw, J.T);
+    double best = INFINITY;
+    int bm = -1;
+    for (int m = 0; m < nm; ++m) {
+        const float4* row = mode_row(J.modes, J.T, J.D, J.M, lw, nw, m);
+        const float4 a = row[0];
+        const double d0 = y0 - a.x, d1 = y1 - a.y, d2 = y2 - a.z;
+        double q;
+        if (J.use_cov) {
+            const float4 b = row[1], c = row[2];
+            q = d0 * (b.x * d0 + b.y * d1 + b.z * d2) + d1 * (b.y * d0 + b.w * d1 + c.x * d2)
+              + d2 * (b.z * d0 + c.x * d1 + c.y * d2);
+        } else {
+            q = d0 * d0 + d1 * d1 + d2 * d2;
+        }
+        q = fmax(q, 0.0);
+        if (q < best) {
+            best = q;
+            bm = m;
+        }
+    }
+    int flag = -1;
+    if (bm >= 0) {
+        const uint32_t ri = mode_row_index(J, lw, nw, bm);
+        const float4 a = J.modes[(size_t)ri * 4];
+        const double d0 = y0 - a.x, d1 = y1 - a.y, d2 = y2 - a.z;
+        if (sqrt(d0 * d0 + d1 * d1 + d2 * d2) <= J.theta_in) flag = (int)ri;
+    }
+    J.inl[k] = flag;
+}
+
+// Refit, part 2 and the result record: centroids and cross-covariance of the
+// inlier pairs (x^C, mode mean), Kabsch over all of them (>= 3 inliers).
 __global__ __launch_bounds__(256) void k_finalize(const Job* __restrict__ jobs)
 {
     const Job& J = jobs[blockIdx.y];
@@ -469,52 +583,17 @@ __global__ __launch_bounds__(256) void k_finalize(const Job* __restrict__ jobs)
     const int nI = rounds * J.eta;
     int n_inl = 0;
     if (J.final_refine) {
-        double R[9], t[3];
-        for (int i = 0; i < 9; ++i) R[i] = s_pose[i];
-        for (int i = 0; i < 3; ++i) t[i] = s_pose[9 + i];
         double sc[3] = {0, 0, 0}, sw[3] = {0, 0, 0}, cnt = 0;
         for (int k = threadIdx.x; k < nI; k += 256) {
+            const int ri = J.inl[k];
+            if (ri < 0) continue;
             const int p = J.I[k];
             double x[3];
             backproject(J.depth[p], p % J.w, p / J.w, J.fx, J.fy, J.cx, J.cy, x);
-            const double y0 = R[0] * x[0] + R[1] * x[1] + R[2] * x[2] + t[0];
-            const double y1 = R[3] * x[0] + R[4] * x[1] + R[5] * x[2] + t[1];
-            const double y2 = R[6] * x[0] + R[7] * x[1] + R[8] * x[2] + t[2];
-            const uint4 lw = reinterpret_cast<const uint4*>(J.leaves)[p];
-            const uint2 nw = reinterpret_cast<const uint2*>(J.nmt)[p];
-            const int nm = modes_total(nw, J.T);
-            double best = INFINITY;
-            int bm = -1;
-            for (int m = 0; m < nm; ++m) {
-                const float4* row = mode_row(J.modes, J.T, J.D, J.M, lw, nw, m);
-                const float4 a = row[0];
-                const double d0 = y0 - a.x, d1 = y1 - a.y, d2 = y2 - a.z;
-                double q;
-                if (J.use_cov) {
-                    const float4 b = row[1], c = row[2];
-                    q = d0 * (b.x * d0 + b.y * d1 + b.z * d2) + d1 * (b.y * d0 + b.w * d1 + c.x * d2)
-                      + d2 * (b.z * d0 + c.x * d1 + c.y * d2);
-                } else {
-                    q = d0 * d0 + d1 * d1 + d2 * d2;
-                }
-                q = fmax(q, 0.0);
-                if (q < best) {
-                    best = q;
-                    bm = m;
-                }
-            }
-            int flag = -1;
-            if (bm >= 0) {
-                const float4 a = mode_row(J.modes, J.T, J.D, J.M, lw, nw, bm)[0];
-                const double d0 = y0 - a.x, d1 = y1 - a.y, d2 = y2 - a.z;
-                if (sqrt(d0 * d0 + d1 * d1 + d2 * d2) <= J.theta_in) {
-                    flag = bm;
-                    cnt += 1.0;
-                    sc[0] += x[0]; sc[1] += x[1]; sc[2] += x[2];
-                    sw[0] += a.x; sw[1] += a.y; sw[2] += a.z;
-                }
-            }
-            J.inl[k] = flag;
+            const float4 a = J.modes[(size_t)ri * 4];
+            cnt += 1.0;
+            sc[0] += x[0]; sc[1] += x[1]; sc[2] += x[2];
+            sw[0] += a.x; sw[1] += a.y; sw[2] += a.z;
         }
         const double tc = block_sum256(cnt, s_red);
         double cc[3], cw[3];
@@ -530,14 +609,12 @@ __global__ __launch_bounds__(256) void k_finalize(const Job* __restrict__ jobs)
             }
             double A[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
             for (int k = threadIdx.x; k < nI; k += 256) {
-                const int m = J.inl[k];
-                if (m < 0) continue;
+                const int ri = J.inl[k];
+                if (ri < 0) continue;
                 const int p = J.I[k];
                 double x[3];
                 backproject(J.depth[p], p % J.w, p / J.w, J.fx, J.fy, J.cx, J.cy, x);
-                const uint4 lw = reinterpret_cast<const uint4*>(J.leaves)[p];
-                const uint2 nw = reinterpret_cast<const uint2*>(J.nmt)[p];
-                const float4 a = mode_row(J.modes, J.T, J.D, J.M, lw, nw, m)[0];
+                const float4 a = J.modes[(size_t)ri * 4];
                 const double wv[3] = {(double)a.x - cw[0], (double)a.y - cw[1], (double)a.z - cw[2]};
                 for (int i = 0; i < 3; ++i)
                     for (int j = 0; j < 3; ++j) A[i * 3 + j] += (x[i] - cc[i]) * wv[j];
@@ -612,12 +689,14 @@ hipError_t launch_eligible(const Job* jobs, int njobs, int maxP, hipStream_t st)
     return hipSuccess;
 }
 
+constexpr int kHypIPT = 8;      // iterations per thread in one search block
+
 hipError_t launch_hyp_search(const Job* jobs, int njobs, int maxN, int maxIters, hipStream_t st)
 {
-    const long long chunks = (maxIters + 255) / 256;
+    const long long chunks = (maxIters + 256 * kHypIPT - 1) / (256 * kHypIPT);
     const long long gx = chunks * (long long)maxN;
     if (gx > 0x7fffffffLL) return hipErrorInvalidValue;
-    k_hyp_search<<<dim3((unsigned)gx, njobs), dim3(256), 0, st>>>(jobs, maxN);
+    k_hyp_search<kHypIPT><<<dim3((unsigned)gx, njobs), dim3(256), 0, st>>>(jobs, maxN);
     RL_CHECK_LAUNCH();
     return hipSuccess;
 }
@@ -648,8 +727,10 @@ hipError_t launch_select(const Job* jobs, int njobs, int round, int nptiles, int
     return hipSuccess;
 }
 
-hipError_t launch_finalize(const Job* jobs, int njobs, hipStream_t st)
+hipError_t launch_finalize(const Job* jobs, int njobs, int maxIlen, hipStream_t st)
 {
+    k_refit_assign<<<dim3((maxIlen + 255) / 256, njobs), dim3(256), 0, st>>>(jobs);
+    RL_CHECK_LAUNCH();
     k_finalize<<<dim3(1, njobs), dim3(256), 0, st>>>(jobs);
     RL_CHECK_LAUNCH();
     return hipSuccess;

@@ -28,7 +28,7 @@ hipError_t launch_hyp_finalize(const Job* jobs, int njobs, int maxN, hipStream_t
 hipError_t launch_score(const Job* jobs, int njobs, int round, int nptiles, int maxSurv,
                         size_t score_lds, hipStream_t st);
 hipError_t launch_select(const Job* jobs, int njobs, int round, int nptiles, int maxN, hipStream_t st);
-hipError_t launch_finalize(const Job* jobs, int njobs, hipStream_t st);
+hipError_t launch_finalize(const Job* jobs, int njobs, int maxIlen, hipStream_t st);
 hipError_t launch_adapt(const AdaptArgs& a, hipStream_t st);
 hipError_t launch_rqs(const RqsArgs& a, int blocks, hipStream_t st);
 
@@ -240,6 +240,7 @@ struct rl_room {
     bool modes_stale;
     std::vector<int> entering;
     Timer timer;
+    std::map<std::vector<long long>, hipGraphExec_t> graphs;
 };
 
 struct rl_batch {
@@ -335,7 +336,8 @@ RL_API rl_status rl_params_validate(const rl_params* p)
     if (p->n_trees * p->max_cluster_count > 255) return fail(RL_EINVAL, "n_trees * max_cluster_count must be <= 255");
     if (p->min_cluster_size < 1) return fail(RL_EINVAL, "min_cluster_size must be >= 1");
     if (p->reservoir_capacity < 1 || p->reservoir_capacity > 4096) return fail(RL_EINVAL, "reservoir_capacity must be in 1..4096");
-    if (p->max_candidate_generation_iterations < 1) return fail(RL_EINVAL, "max_candidate_generation_iterations must be >= 1");
+    if (p->max_candidate_generation_iterations < 1 || p->max_candidate_generation_iterations >= (1 << 30))
+        return fail(RL_EINVAL, "max_candidate_generation_iterations must be in 1..2^30-1");
     if (p->max_pose_candidates < 1 || p->max_pose_candidates > 4096) return fail(RL_EINVAL, "max_pose_candidates must be in 1..4096");
     if (p->max_pose_candidates_after_cull < 1) return fail(RL_EINVAL, "max_pose_candidates_after_cull must be >= 1");
     if (p->ransac_inliers_per_iteration < 1 || p->ransac_inliers_per_iteration > 4096) return fail(RL_EINVAL, "ransac_inliers_per_iteration must be in 1..4096");
@@ -550,6 +552,7 @@ RL_API rl_status relocaliser_create(const rl_params* p, const rl_node* host_node
 RL_API rl_status relocaliser_destroy(rl_room* r)
 {
     if (!r) return RL_OK;
+    for (auto& kv : r->graphs) (void)hipGraphExecDestroy(kv.second);
     if (r->job_host) (void)hipHostFree(r->job_host);
     if (r->res_host) (void)hipHostFree(r->res_host);
     if (r->ev) (void)hipEventDestroy(r->ev);
@@ -639,7 +642,7 @@ RL_API rl_status relocaliser_update_modes(rl_room* r)
 }
 
 static hipError_t launch_sequence(const Job* jobs, int njobs, int maxP, int maxN, int maxIters, int T,
-                                  const std::vector<int>& entering, int nptiles, size_t score_lds,
+                                  const std::vector<int>& entering, int nptiles, int maxEta, size_t score_lds,
                                   const Timer& tm, hipStream_t st)
 {
     hipError_t e;
@@ -660,10 +663,38 @@ static hipError_t launch_sequence(const Job* jobs, int njobs, int maxP, int maxN
         RL_TRY(launch_select(jobs, njobs, r, nptiles, maxN, st));
     }
     RL_MARK(RL_TIMER_RANSAC, stop);
-    RL_TRY(launch_finalize(jobs, njobs, st));
+    RL_TRY(launch_finalize(jobs, njobs, (int)entering.size() * maxEta, st));
 #undef RL_MARK
 #undef RL_TRY
     return hipSuccess;
+}
+
+// Replays the launch sequence from a graph cached under `key` (captured on
+// first use).  Streams that cannot be captured (the legacy default stream)
+// and active kernel timers use direct launches.
+template <class F>
+static hipError_t run_sequence(std::map<std::vector<long long>, hipGraphExec_t>& cache,
+                               const std::vector<long long>& key, bool graph_ok, hipStream_t st, F&& launch)
+{
+    if (!graph_ok || st == nullptr) return launch();
+    auto it = cache.find(key);
+    if (it == cache.end()) {
+        hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return e;
+        const hipError_t le = launch();
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(st, &g);
+        if (le != hipSuccess || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return le != hipSuccess ? le : e;
+        }
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return e;
+        it = cache.emplace(key, ex).first;
+    }
+    return hipGraphLaunch(it->second, st);
 }
 
 RL_API rl_status relocaliser_relocalise_ex(rl_room* r, const rl_frame* f, uint64_t request_seed, rl_result* out)
@@ -679,8 +710,11 @@ RL_API rl_status relocaliser_relocalise_ex(rl_room* r, const rl_frame* f, uint64
     if (e != hipSuccess) return hip_fail(e, "job upload");
     const int nptiles = (r->eta + r->TP - 1) / r->TP;
     const size_t score_lds = (size_t)r->TP * r->T * r->M * 72;
-    e = launch_sequence(jd, 1, f->width * f->height, r->N, r->p.max_candidate_generation_iterations, r->T,
-                        r->entering, nptiles, score_lds, r->timer, r->stream);
+    const int P = f->width * f->height;
+    e = run_sequence(r->graphs, {P}, r->timer.kernel == RL_TIMER_NONE, r->stream, [&]() {
+        return launch_sequence(jd, 1, P, r->N, r->p.max_candidate_generation_iterations, r->T, r->entering,
+                               nptiles, r->eta, score_lds, r->timer, r->stream);
+    });
     if (e != hipSuccess) return hip_fail(e, "relocalise launch");
     e = hipMemcpyAsync(r->res_host, r->scr + r->FL.result, sizeof(rl_result), hipMemcpyDeviceToHost, r->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
@@ -853,36 +887,13 @@ RL_API rl_status rl_batch_relocalise_async(rl_batch* b, const rl_request* reqs, 
     const int nptiles = (maxEta + b->TP - 1) / b->TP;
     if (use_graph && b->stream == nullptr)
         return fail(RL_EINVAL, "graph replay needs a batch created on a non-default stream");
-    if (use_graph) {
-        std::vector<long long> key = {n, maxP, maxN, maxIters, nptiles, (long long)b->score_lds, b->bp.n_trees,
-                                      b->timer.kernel, (long long)(uintptr_t)b->timer.start,
-                                      (long long)(uintptr_t)b->timer.stop};
-        for (int v : entering) key.push_back(v);
-        auto it = b->graphs.find(key);
-        if (it == b->graphs.end()) {
-            e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
-            if (e != hipSuccess) return hip_fail(e, "begin capture");
-            const hipError_t le = launch_sequence(jd, n, maxP, maxN, maxIters, b->bp.n_trees, entering, nptiles,
-                                                  b->score_lds, b->timer, b->stream);
-            hipGraph_t g = nullptr;
-            e = hipStreamEndCapture(b->stream, &g);
-            if (le != hipSuccess || e != hipSuccess) {
-                if (g) (void)hipGraphDestroy(g);
-                return hip_fail(le != hipSuccess ? le : e, "capture");
-            }
-            hipGraphExec_t ex = nullptr;
-            e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            if (e != hipSuccess) return hip_fail(e, "graph instantiate");
-            it = b->graphs.emplace(key, ex).first;
-        }
-        e = hipGraphLaunch(it->second, b->stream);
-        if (e != hipSuccess) return hip_fail(e, "graph launch");
-    } else {
-        e = launch_sequence(jd, n, maxP, maxN, maxIters, b->bp.n_trees, entering, nptiles, b->score_lds, b->timer,
-                            b->stream);
-        if (e != hipSuccess) return hip_fail(e, "batch launch");
-    }
+    std::vector<long long> key = {n, maxP, maxN, maxIters, nptiles, maxEta, b->bp.n_trees};
+    for (int v : entering) key.push_back(v);
+    e = run_sequence(b->graphs, key, use_graph && b->timer.kernel == RL_TIMER_NONE, b->stream, [&]() {
+        return launch_sequence(jd, n, maxP, maxN, maxIters, b->bp.n_trees, entering, nptiles, maxEta,
+                               b->score_lds, b->timer, b->stream);
+    });
+    if (e != hipSuccess) return hip_fail(e, "batch launch");
     // later work on the rooms' own streams is ordered after the batch
     e = hipEventRecord(b->ev, b->stream);
     if (e != hipSuccess) return hip_fail(e, "batch event");

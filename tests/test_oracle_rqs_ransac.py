@@ -200,12 +200,15 @@ def test_hypothesis_draws_follow_the_documented_mapping(ideal):
     key = [seed & 0xFFFFFFFF, seed >> 32]
     for s in range(8):
         it = int(out["hyp_iter"][s])
-        r0 = oracle.philox4x32([(2 << 28) | 0, s, it, 0], key)
-        r1 = oracle.philox4x32([(2 << 28) | 1, s, it, 0], key)
-        r = np.concatenate([r0, r1]).astype(np.uint64)
-        pix = [int(el[(int(r[k]) * n) >> 32]) for k in range(3)]
+        a = [int(v) for v in oracle.philox4x32([(2 << 28) | 0, s, it, 0], key)]
+        b = [int(v) for v in oracle.philox4x32([(2 << 28) | 1, s, it, 0], key)]
+        kc = (a[0] * 3) >> 32
+        others = [k for k in range(3) if k != kc]
+        rp = {kc: a[1], others[0]: b[0], others[1]: b[1]}
+        rm = {kc: a[2], others[0]: b[2], others[1]: b[3]}
+        pix = [int(el[(rp[k] * n) >> 32]) for k in range(3)]
         assert pix == list(out["hyp_pix"][s])
-        modes_idx = [(int(r[3 + k]) * sc["M"]) >> 32 for k in range(3)]
+        modes_idx = [(rm[k] * sc["M"]) >> 32 for k in range(3)]
         assert modes_idx == list(out["hyp_mode"][s])
 
 
