@@ -60,8 +60,20 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=4, help="oracle relocalisations (0 = skip)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--timer", default="hyp_search", choices=["traverse", "hyp_search", "ransac"])
+    ap.add_argument("--serve-seconds", type=float, default=0.0,
+                    help="measured seconds per arrival rate; the served leg is switched off (see below)")
+    ap.add_argument("--serve-rates", default="200,500,1000")
+    ap.add_argument("--serve-rooms", type=int, default=16)
     args = ap.parse_args()
 
+    if args.serve_seconds > 0:
+        # The served leg at full scale (16 five-tree rooms, mixed resolutions and
+        # hypothesis counts in one batch, two batches in flight, interleaved
+        # adaptations) ended twice in a GPU memory fault whose cause is not yet
+        # found; it stays off until it is.  Continuous batching itself is covered
+        # at small scale by tests/test_gpu_serve.py.
+        raise SystemExit("the served benchmark leg is switched off: it faulted the GPU at full scale "
+                         "and its cause is not found yet")
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}, WORLD_SIZE {world}): "
@@ -69,16 +81,25 @@ def main():
               "share is measured here.", file=sys.stderr)
         sys.exit(2)
 
-    import torch
-
-    import paper_1810_12163_amd as rl
     from rlsynth import scene, workloads
 
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
+    # every CPU-side input is generated before the GPU runtime is initialised
     t_setup = time.time()
     log(f"[bench] rendering {args.adapt_frames} adaptation frames and {args.queries} queries (640x480)")
     w = workloads.c2(n_adapt=args.adapt_frames, n_queries=args.queries)
+    serve_inputs = None
+    if args.serve_seconds > 0:
+        procs = max(1, min(16, os.cpu_count() or 1))
+        serve_inputs = workloads.serving_setup(n_rooms=args.serve_rooms, n_adapt=20, n_cameras=32,
+                                               frames_per_camera=4, processes=procs)
+    log(f"[bench] inputs ready ({time.time() - t_setup:.1f} s)")
+
+    import torch
+
+    import paper_1810_12163_amd as rl
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
     p = w.params
     room = rl.Room(p, w.nodes, 640, 480, device=dev)
     for i, f in enumerate(w.adapt):
@@ -195,6 +216,8 @@ def main():
                           f"hypotheses, RANSAC, refit; modes taken from the room), 1 thread, {ct:.1f} s")
         log(f"[bench] oracle: {cpu['value']:.3f} reloc/s over {ct:.1f} s")
 
+    served = serve_leg(args, rl, dev, serve_inputs) if serve_inputs is not None else None
+
     out = {
         "metric": METRIC, "value": value, "unit": "relocalisations/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
@@ -211,12 +234,62 @@ def main():
         "plain": plain,
         "batched": dict(relocs_per_s=value, step_p50_ms=percentile(step_ms, 50),
                         step_p99_ms=percentile(step_ms, 99), identical_to_plain=bool(same)),
+        "served": served,
         "accuracy": dict(frac_within_5cm_5deg=float(np.mean(ok)),
                          median_cm=float(np.median([e[0] for e in errs]) * 100),
                          median_deg=float(np.median([e[1] for e in errs]))),
         "paper_context": "Fast relocaliser 25.1 ms/frame on a GTX 1080 Ti (Table 3)",
     }
     print(json.dumps(out), flush=True)
+
+
+def serve_leg(args, rl, dev, inputs):
+    """Open-loop Poisson arrivals from 32 cameras over resident rooms; 75%
+    relocalise / 25% adapt; resolutions 160x120, 320x240, 640x480 with 256, 512,
+    1024 hypotheses.  Continuous batching, two batches in flight."""
+    import torch
+
+    from paper_1810_12163_amd import serve
+    from rlsynth import presets, workloads
+
+    t0 = time.time()
+    specs, cams = inputs
+    p = presets.preset("c5")
+    rooms = []
+    for sp in specs:
+        room = rl.Room(p, sp["nodes"], 640, 480, device=dev)
+        for f in sp["adapt"]:
+            room.adapt(torch.from_numpy(f.depth).to(dev), torch.from_numpy(f.rgb).to(dev), f.K, f.pose)
+        room.update_modes()
+        rooms.append(room)
+    torch.cuda.synchronize()
+    camf = [[(torch.from_numpy(f.depth).to(dev), torch.from_numpy(f.rgb).to(dev), f) for f in c["frames"]]
+            for c in cams]
+    log(f"[bench] serving: {len(rooms)} rooms resident "
+        f"({sum(r.persistent.numel() for r in rooms) / 2**30:.1f} GiB), setup {time.time() - t0:.1f} s")
+    out = {}
+    warm = 1.0
+    for rate in [float(v) for v in args.serve_rates.split(",")]:
+        server = serve.Server(max_batch=64, max_width=640, max_height=480, max_hypotheses=1024, max_eta=500,
+                              max_rounds=10, n_trees=5, max_modes_per_pixel=50, contexts=2, device=dev)
+        arr = serve.poisson_arrivals(rate, warm + args.serve_seconds, seed=int(rate))
+        rng = np.random.default_rng(int(rate) + 1)
+        reqs = []
+        for i in range(len(arr)):
+            c = int(rng.integers(len(cams)))
+            d, rgb, f = camf[c][int(rng.integers(len(camf[c])))]
+            kind = "adapt" if rng.uniform() < 0.25 else "relocalise"
+            reqs.append(serve.Request(rid=i, kind=kind, room=rooms[cams[c]["room"]], depth=d, rgb=rgb, K=f.K,
+                                      pose=f.pose if kind == "adapt" else None,
+                                      n_hypotheses=workloads.HYPOTHESES[f.w]))
+        st = serve.run_open_loop(server, reqs, arr, warmup_s=warm)
+        server.close()
+        out[f"{int(rate)}/s"] = st
+        log(f"[bench] served {int(rate)}/s: {st['relocs_per_s']:.1f} reloc/s, p50 {st['p50_ms']:.2f} ms, "
+            f"p99 {st['p99_ms']:.2f} ms, mean batch {st['mean_batch']:.1f}, refused {st['refused']}")
+    for r in rooms:
+        r.close()
+    return out
 
 
 if __name__ == "__main__":

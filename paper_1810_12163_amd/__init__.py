@@ -222,6 +222,7 @@ class Room:
 
     def close(self):
         if getattr(self, "handle", None):
+            self.stream.synchronize()          # nothing of this room may still be in flight
             lib().relocaliser_destroy(self.handle)
             self.handle = None
 
@@ -231,15 +232,18 @@ class Room:
         except Exception:
             pass
 
-    def _follow(self):
+    def _follow(self, *tensors):
         """Orders the room's stream after the caller's current stream (where
-        the frame tensors were written)."""
+        the frame tensors were written), and keeps the caching allocator from
+        reusing those tensors' memory before the room's stream has read them."""
         self.stream.wait_stream(_torch().cuda.current_stream(self.device))
+        for t in tensors:
+            t.record_stream(self.stream)
 
     def adapt(self, depth, rgb, K, pose, reliable: bool = True):
         f = _frame(depth, rgb, K)
         H = np.ascontiguousarray(np.asarray(pose, dtype=np.float32).reshape(16))
-        self._follow()
+        self._follow(depth, rgb)
         _check(lib().relocaliser_adapt(self.handle, ctypes.byref(f), H.ctypes.data, 1 if reliable else 0))
 
     def update_modes(self):
@@ -249,7 +253,7 @@ class Room:
     def relocalise(self, depth, rgb, K, request_seed: int = 0) -> dict:
         f = _frame(depth, rgb, K)
         r = Result()
-        self._follow()
+        self._follow(depth, rgb)
         _check(lib().relocaliser_relocalise_ex(self.handle, ctypes.byref(f), int(request_seed),
                                                ctypes.byref(r)), allow=(RL_OK, RL_NO_POSE))
         return _result(r)
@@ -301,6 +305,7 @@ class Batch:
 
     def close(self):
         if getattr(self, "handle", None):
+            self.stream.synchronize()
             lib().rl_batch_destroy(self.handle)
             self.handle = None
 
@@ -315,10 +320,13 @@ class Batch:
         _check(lib().rl_batch_set_timer(self.handle, kernel, start.cuda_event if start else None,
                                         stop.cuda_event if stop else None))
 
-    @staticmethod
-    def _requests(reqs):
+    def _requests(self, reqs):
+        torch = _torch()
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))   # frames were made there
         arr = (Request * len(reqs))()
         for i, q in enumerate(reqs):
+            q[1].record_stream(self.stream)
+            q[2].record_stream(self.stream)
             room, depth, rgb, K = q[0], q[1], q[2], q[3]
             seed = q[4] if len(q) > 4 else 0
             nh = q[5] if len(q) > 5 else 0
@@ -332,14 +340,13 @@ class Batch:
         """reqs: sequence of (room, depth, rgb, K[, request_seed[, n_hypotheses]])."""
         arr = self._requests(reqs)
         res = (Result * len(reqs))()
-        self.stream.wait_stream(_torch().cuda.current_stream(self.device))   # frames were made there
         _check(lib().rl_batch_relocalise(self.handle, arr, len(reqs), res, 1 if use_graph else 0))
         return [_result(r) for r in res]
 
     def relocalise_async(self, reqs, dev_results, use_graph: bool = True):
         """Queues the batch; dev_results: torch uint8 CUDA tensor of >= len(reqs) * sizeof(Result) bytes."""
         arr = self._requests(reqs)
-        self.stream.wait_stream(_torch().cuda.current_stream(self.device))
+        dev_results.record_stream(self.stream)
         _check(lib().rl_batch_relocalise_async(self.handle, arr, len(reqs), dev_results.data_ptr(),
                                                1 if use_graph else 0))
 

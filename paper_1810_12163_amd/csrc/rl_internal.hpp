@@ -184,8 +184,10 @@ __device__ __forceinline__ void route(const float4* __restrict__ nodes, int NT, 
             if (kind == 0u) {
                 f = d - depth[q];
             } else {
-                const int c = (int)kind - 1;
-                f = cc[c] - (float)rgb[3 * q + c];
+                // nodes are validated at creation (kind <= 3); the clamp keeps
+                // this read inside the pixel whatever the device memory holds
+                const uint32_t c = min(kind - 1u, 2u);
+                f = (c == 0u ? cc[0] : c == 1u ? cc[1] : cc[2]) - (float)rgb[3 * q + c];
             }
             idx[t] = 2 * idx[t] + 1 + (f >= nd[t].z ? 1 : 0);
         }

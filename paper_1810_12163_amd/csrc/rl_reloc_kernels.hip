@@ -264,7 +264,7 @@ __global__ __launch_bounds__(256) void k_hyp_search(const Job* __restrict__ jobs
     const int n_elig = J.st->n_elig;
     if (n_elig <= 0) return;
     if (__hip_atomic_load(&J.hyp_best[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < it0) return;
-    __shared__ int q_it[256 * IPT];        // iteration | k* << 30
+    __shared__ uint32_t q_it[256 * IPT];   // iteration | k* << 30
     __shared__ int q_p[256 * IPT];
     __shared__ uint32_t q_row[256 * IPT];
     __shared__ int q_m[256 * IPT];
@@ -281,7 +281,7 @@ __global__ __launch_bounds__(256) void k_hyp_search(const Job* __restrict__ jobs
         uint32_t rowc;
         if (it < J.I_max && hyp_stage_a(J, n_elig, slot, it, kc, pc, mc, rowc)) {
             const int q = atomicAdd(&s_n, 1);
-            q_it[q] = it | (kc << 30);
+            q_it[q] = (uint32_t)it | ((uint32_t)kc << 30);
             q_p[q] = pc;
             q_row[q] = rowc;
             q_m[q] = mc;
@@ -290,7 +290,7 @@ __global__ __launch_bounds__(256) void k_hyp_search(const Job* __restrict__ jobs
     __syncthreads();
     const int n = s_n;
     for (int j = threadIdx.x; j < n; j += 256) {
-        const int it = q_it[j] & 0x3FFFFFFF, kc = q_it[j] >> 30;
+        const int it = (int)(q_it[j] & 0x3FFFFFFFu), kc = (int)(q_it[j] >> 30);
         if (hyp_stage_b<false>(J, n_elig, slot, it, kc, q_p[j], q_m[j], q_row[j], nullptr))
             atomicMin(&s_best, it);
     }

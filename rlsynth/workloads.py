@@ -118,3 +118,60 @@ def c2(room_id: int = 0, n_adapt: int = 50, n_queries: int = 8) -> Workload:
     room, nodes, adapt = room_setup(room_id, n_adapt)
     queries = queries_for(room, [f.pose for f in adapt], n_queries, room_id=room_id)
     return Workload("c2", params, room, nodes, adapt, queries)
+
+
+# --- parallel rendering (several rooms / many frames) ----------------------
+
+def _render_job(job):
+    room_id, pose, w, h, seed = job
+    room = _scene.make_room(room_id)
+    return _frame(room, pose, w, h, seed)
+
+
+def render_many(jobs, processes=None):
+    """Renders (room_id, pose, w, h, seed) jobs, in worker processes when
+    processes > 1.  Results are identical to rendering them one by one.
+    Workers are spawned (fresh interpreters), never forked: a forked copy of a
+    process that has initialised the GPU runtime is not safe."""
+    if not processes or processes <= 1 or len(jobs) < 4:
+        return [_render_job(j) for j in jobs]
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(processes) as pool:
+        return pool.map(_render_job, jobs, chunksize=max(1, len(jobs) // (4 * processes)))
+
+
+RESOLUTIONS = [(160, 120), (320, 240), (640, 480)]
+HYPOTHESES = {160: 256, 320: 512, 640: 1024}
+
+
+def serving_setup(n_rooms=16, n_adapt=20, n_cameras=32, frames_per_camera=4, processes=16):
+    """Rooms for the serving workload: room r has the 640x480 forest of seed
+    1000 + r, adapted from n_adapt frames.  Camera c watches room c % n_rooms at
+    resolution RESOLUTIONS[c % 3]; its frames lie within 20 cm / 20 degrees of
+    that room's adaptation poses (ground-truth poses kept for adaptation)."""
+    rooms, adapt_jobs, cam_jobs = [], [], []
+    for r in range(n_rooms):
+        room = _scene.make_room(r)
+        rng = np.random.default_rng(frame_seed(r, 8, 0))
+        poses = [_scene.random_pose(room, rng) for _ in range(n_adapt)]
+        nodes = _forest.make_forest(1000 + r, **_presets.FOREST["c2"])
+        rooms.append(dict(room_id=r, nodes=nodes, poses=poses))
+        adapt_jobs += [(r, p, 640, 480, frame_seed(r, 0, i)) for i, p in enumerate(poses)]
+    for c in range(n_cameras):
+        r = c % n_rooms
+        w, h = RESOLUTIONS[c % 3]
+        room = _scene.make_room(r)
+        rng = np.random.default_rng(frame_seed(r, 6, c))
+        for k in range(frames_per_camera):
+            base = rooms[r]["poses"][int(rng.integers(n_adapt))]
+            p = _scene.near_pose(room, base, rng, 0.20, 20.0)
+            cam_jobs.append((r, p, w, h, frame_seed(r, 5, c * 100 + k)))
+    frames = render_many(adapt_jobs + cam_jobs, processes)
+    na = len(adapt_jobs)
+    for r in range(n_rooms):
+        rooms[r]["adapt"] = frames[r * n_adapt:(r + 1) * n_adapt]
+    cams = []
+    for c in range(n_cameras):
+        cams.append(dict(room=c % n_rooms, frames=frames[na + c * frames_per_camera: na + (c + 1) * frames_per_camera]))
+    return rooms, cams

@@ -195,3 +195,23 @@ def test_batch_equals_plain(c1):
         assert np.array_equal(a["pose"], b["pose"]) and a["energy"] == b["energy"]
     batch.close()
     room2.close()
+
+
+def test_adapt_from_back_to_back_temporaries():
+    """Frames uploaded into short-lived tensors and adapted with no host wait
+    in between: the room must read every frame before its memory is reused."""
+    w = workloads.c1(room_id=2, n_queries=1)
+    o = oracle.Oracle(w.params, w.nodes)
+    room = rl.Room(w.params, w.nodes, 160, 120)
+    frames = w.adapt * 6
+    for f in frames:
+        room.adapt(torch.from_numpy(f.depth).cuda(), torch.from_numpy(f.rgb).cuda(), f.K, f.pose)
+        junk = torch.full((120 * 160 * 8,), 7, dtype=torch.uint8, device="cuda")   # churn the allocator
+        del junk
+    for f in frames:
+        o.adapt(f.depth, f.rgb, f.K, f.pose)
+    seen, res, _, _ = gpu_state(room, o.T, o.L, o.kappa, o.M)
+    np.testing.assert_array_equal(seen, o.seen)
+    bad, total = reservoir_mismatches(seen, res, o.reservoir, o.kappa)
+    assert total > 1000 and bad == 0, (bad, total)
+    room.close()
