@@ -64,6 +64,8 @@ def main():
                     help="measured seconds per arrival rate; the served leg is switched off (see below)")
     ap.add_argument("--serve-rates", default="200,500,1000")
     ap.add_argument("--serve-rooms", type=int, default=16)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run a plain device-to-device copy of this size (counter calibration)")
     args = ap.parse_args()
 
     if args.serve_seconds > 0:
@@ -100,6 +102,16 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_probe_mib > 0:
+        # a copy of known size: the hardware byte counters of this dispatch give
+        # the scale between counted and moved bytes
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)          # one elementwise kernel: reads and writes the size
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: 3 copies of {args.copy_probe_mib} MiB")
+        del src, dst
     p = w.params
     room = rl.Room(p, w.nodes, 640, 480, device=dev)
     for i, f in enumerate(w.adapt):
@@ -114,17 +126,19 @@ def main():
 
     # ---- plain path: one frame per synchronous call -----------------------
     lat = []
-    for k in range(3 + args.plain):
+    for k in range((3 + args.plain) if args.plain > 0 else 0):
         qi = k % len(w.queries)
         t0 = time.perf_counter()
         room.relocalise(qd[qi], qc[qi], w.queries[qi].K, request_seed=k)
         dt = time.perf_counter() - t0
         if k >= 3:
             lat.append(dt)
-    plain = dict(relocs_per_s=len(lat) / sum(lat), p50_ms=percentile(lat, 50) * 1e3,
-                 p99_ms=percentile(lat, 99) * 1e3, mean_ms=float(np.mean(lat)) * 1e3, frames=len(lat))
-    log(f"[bench] plain: {plain['relocs_per_s']:.1f} reloc/s, p50 {plain['p50_ms']:.2f} ms, "
-        f"p99 {plain['p99_ms']:.2f} ms")
+    plain = None
+    if lat:
+        plain = dict(relocs_per_s=len(lat) / sum(lat), p50_ms=percentile(lat, 50) * 1e3,
+                     p99_ms=percentile(lat, 99) * 1e3, mean_ms=float(np.mean(lat)) * 1e3, frames=len(lat))
+        log(f"[bench] plain: {plain['relocs_per_s']:.1f} reloc/s, p50 {plain['p50_ms']:.2f} ms, "
+            f"p99 {plain['p99_ms']:.2f} ms")
 
     # algorithmic work of one batch, from the plain path on the same (frame, seed) pairs
     iters = 0

@@ -162,6 +162,15 @@ rl_status relocaliser_relocalise(rl_room* room, const rl_frame* frame, uint64_t 
                                  float cam_to_world_out[16], float* energy_out,
                                  float* mean_energy_out);
 
+/* Per-call RANSAC settings (0 = the room's own value).  n_hypotheses may not
+ * exceed the room's max_pose_candidates, which sizes its scratch. */
+typedef struct {
+    int32_t n_hypotheses;     /* N_max for this call                          */
+    int32_t n_cull;           /* N_cull for this call                         */
+    int32_t n_out;            /* maxRelocalisationsToOutput for this call     */
+    int32_t final_refine;     /* -1 = room's value, 0 = off, 1 = on           */
+} rl_reloc_opts;
+
 /* Result record (also the device-side layout written by the batch path). */
 typedef struct {
     float cam_to_world[16];
@@ -180,6 +189,35 @@ typedef struct {
 /* Like relocaliser_relocalise but returns the full result record (host). */
 rl_status relocaliser_relocalise_ex(rl_room* room, const rl_frame* frame, uint64_t request_seed,
                                     rl_result* out);
+
+/* relocaliser_relocalise_ex with per-call RANSAC settings (opts may be NULL).
+ * The cascade of the paper (Sec. 3.2.5) runs differently-tuned relocalisers
+ * backed by the same forest: one room, one call per stage. */
+rl_status relocaliser_relocalise_opts(rl_room* room, const rl_frame* frame, uint64_t request_seed,
+                                      const rl_reloc_opts* opts, rl_result* out);
+
+/*
+ * Analytic scene surface: a point p0, unit normal n, in-plane unit axes e1,
+ * e2 and half-extents (half_a <= 0 marks an infinite plane).  64 bytes.
+ */
+typedef struct {
+    float p0[3], n[3], e1[3], e2[3];
+    float half_a, half_b, pad[2];
+} rl_surface;
+
+/*
+ * Model-based pose score on an analytic scene model, the stand-in here for the
+ * paper's depth-raycast comparison of Sec. 3.2.4 (used to rank the final
+ * hypotheses and to decide cascade fallbacks): for each pose (host, 12 floats
+ * per pose: R row-major, t; camera -> world), the mean over pixels with valid
+ * depth of the distance from H x^C(u) to the nearest surface (FP64).
+ * n_surfaces <= 64, n_poses <= 64; host_scores receives n_poses doubles
+ * (+inf when the frame has no valid depth).  Synchronous on the room's stream;
+ * uses the room's scratch.
+ */
+rl_status rl_plane_scores(rl_room* room, const rl_frame* frame, const rl_surface* host_surfaces,
+                          int32_t n_surfaces, const float* host_poses, int32_t n_poses,
+                          double* host_scores);
 
 /*
  * Introspection for tests and tools: byte offset and size of an internal

@@ -80,6 +80,7 @@ def _declare(L):
     L.oracle_ransac.restype = I32
     L.oracle_refine.argtypes = [P, I32, I32, P, P, P, P, I32, I32, I32, P, P, I32, F64, I32, P, P]
     L.oracle_refine.restype = I32
+    L.oracle_plane_scores.argtypes = [P, I32, I32, P, P, I32, P, I32, P]
 
 
 def _p(a):
@@ -317,3 +318,29 @@ def pixel_energy(depth, K, leaves, nmodes, modes, T, D, M, pose12, pix, use_cov=
     return lib().oracle_pixel_energy(_p(depth), w, h, _p(Kf), _p(_c(leaves, np.uint16)),
                                      _p(_c(nmodes, np.uint8)), _p(_c(modes, np.float32)), T, D, M,
                                      _p(pose), int(pix), int(use_cov))
+
+
+def surfaces_of(room) -> np.ndarray:
+    """Surface records (16 float32 each) of an rlsynth room: p0, n, e1, e2,
+    half-extents (a <= 0: infinite plane)."""
+    out = np.zeros((len(room.surfaces), 16), dtype=np.float32)
+    for i, s in enumerate(room.surfaces):
+        out[i, 0:3] = s.p0
+        out[i, 3:6] = s.n
+        out[i, 6:9] = s.e1
+        out[i, 9:12] = s.e2
+        if s.half is not None:
+            out[i, 12:14] = s.half
+    return out
+
+
+def plane_scores(depth, K, poses12, surfaces):
+    """Mean distance of back-projected valid depth to the nearest surface, per pose."""
+    depth = _c(depth, np.float32)
+    h, w = depth.shape
+    Kf = _c(np.asarray(K, dtype=np.float32), np.float32)
+    P = _c(np.asarray(poses12, dtype=np.float32).reshape(-1, 12), np.float32)
+    S = _c(surfaces, np.float32)
+    out = np.zeros(P.shape[0])
+    lib().oracle_plane_scores(_p(depth), w, h, _p(Kf), _p(P), P.shape[0], _p(S), S.shape[0], _p(out))
+    return out

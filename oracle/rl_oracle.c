@@ -814,3 +814,58 @@ EXPORT int oracle_refine(const float* depth, int w, int h, const float K[4],
     free(xc); free(xw);
     return ni;
 }
+
+/* ------------------------------------------------------------------------ */
+/*
+ * Model-based score of a pose (the analogue, on an analytic scene model, of
+ * the paper's depth-raycast comparison used to rank the final hypotheses and
+ * to decide cascade fallbacks, Sec. 3.2.4-3.2.5): the mean, over pixels with
+ * valid depth, of the distance from H x^C(u) to the nearest scene surface.
+ * Surface record (16 floats): point p0 (3), unit normal n (3), in-plane axes
+ * e1, e2 (3 + 3), half-extents a, b (2; a <= 0 marks an infinite plane),
+ * 0, 0.  Distance to an infinite plane: |n . (y - p0)|; to a rectangle:
+ * sqrt(c^2 + max(|a'| - a, 0)^2 + max(|b'| - b, 0)^2) with (a', b', c) the
+ * coordinates of y - p0 on (e1, e2, n).
+ * Parity: noise-free frame at its true pose => score 0 (up to float32 depth).
+ */
+EXPORT void oracle_plane_scores(const float* depth, int w, int h, const float K[4], const float* poses,
+                                int n_poses, const float* surfaces, int n_surf, double* scores)
+{
+    for (int k = 0; k < n_poses; ++k) {
+        const float* P = poses + 12 * (size_t)k;
+        double R[9], t[3];
+        for (int a = 0; a < 9; ++a) R[a] = P[a];
+        for (int a = 0; a < 3; ++a) t[a] = P[9 + a];
+        double acc = 0.0;
+        long cnt = 0;
+        for (int p = 0; p < w * h; ++p) {
+            float d = depth[p];
+            if (!depth_valid(d)) continue;
+            double x[3], y[3];
+            backproject(d, p % w, p / w, K, x);
+            for (int a = 0; a < 3; ++a)
+                y[a] = R[3 * a] * x[0] + R[3 * a + 1] * x[1] + R[3 * a + 2] * x[2] + t[a];
+            double best = INFINITY;
+            for (int s = 0; s < n_surf; ++s) {
+                const float* S = surfaces + 16 * (size_t)s;
+                double r0 = y[0] - S[0], r1 = y[1] - S[1], r2 = y[2] - S[2];
+                double c = r0 * S[3] + r1 * S[4] + r2 * S[5];
+                double dist;
+                if (S[12] <= 0.0f) {
+                    dist = fabs(c);
+                } else {
+                    double a = r0 * S[6] + r1 * S[7] + r2 * S[8];
+                    double b = r0 * S[9] + r1 * S[10] + r2 * S[11];
+                    double da = fabs(a) - S[12], db = fabs(b) - S[13];
+                    if (da < 0) da = 0;
+                    if (db < 0) db = 0;
+                    dist = sqrt(c * c + da * da + db * db);
+                }
+                if (dist < best) best = dist;
+            }
+            acc += best;
+            ++cnt;
+        }
+        scores[k] = cnt > 0 ? acc / (double)cnt : INFINITY;
+    }
+}

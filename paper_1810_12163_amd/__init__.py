@@ -76,6 +76,11 @@ class Result(ctypes.Structure):
                 ("n_out", ctypes.c_int32), ("pad", ctypes.c_int32 * 2)]
 
 
+class RelocOpts(ctypes.Structure):
+    _fields_ = [("n_hypotheses", ctypes.c_int32), ("n_cull", ctypes.c_int32), ("n_out", ctypes.c_int32),
+                ("final_refine", ctypes.c_int32)]
+
+
 class Request(ctypes.Structure):
     _fields_ = [("room", ctypes.c_void_p), ("frame", Frame), ("request_seed", ctypes.c_uint64),
                 ("n_hypotheses", ctypes.c_int32), ("pad", ctypes.c_int32)]
@@ -95,7 +100,7 @@ EXPORTS = [
     "relocaliser_relocalise", "relocaliser_relocalise_ex", "relocaliser_buffer",
     "relocaliser_set_trace", "rl_batch_workspace_bytes", "rl_batch_create", "rl_batch_destroy",
     "rl_batch_relocalise", "rl_batch_relocalise_async", "rl_last_error", "rl_version",
-    "relocaliser_set_timer", "rl_batch_set_timer",
+    "relocaliser_set_timer", "rl_batch_set_timer", "relocaliser_relocalise_opts", "rl_plane_scores",
 ]
 
 TIMER_NONE, TIMER_TRAVERSE, TIMER_HYP_SEARCH, TIMER_RANSAC = 0, 1, 2, 3
@@ -132,6 +137,9 @@ def lib():
         L.rl_batch_relocalise.argtypes = [P, P, I32, P, I32]
         L.rl_batch_relocalise_async.argtypes = [P, P, I32, P, I32]
         L.relocaliser_set_timer.argtypes = [P, I32, P, P]
+        L.relocaliser_relocalise_opts.argtypes = [P, ctypes.POINTER(Frame), U64, ctypes.POINTER(RelocOpts),
+                                                  ctypes.POINTER(Result)]
+        L.rl_plane_scores.argtypes = [P, ctypes.POINTER(Frame), P, I32, P, I32, P]
         L.rl_batch_set_timer.argtypes = [P, I32, P, P]
         L.rl_last_error.restype = ctypes.c_char_p
         L.rl_version.restype = ctypes.c_char_p
@@ -250,13 +258,34 @@ class Room:
         self._follow()
         _check(lib().relocaliser_update_modes(self.handle))
 
-    def relocalise(self, depth, rgb, K, request_seed: int = 0) -> dict:
+    def relocalise(self, depth, rgb, K, request_seed: int = 0, n_hypotheses: int = 0, n_cull: int = 0,
+                   n_out: int = 0, final_refine: int = -1) -> dict:
+        """One frame; the optional RANSAC settings override the room's for this call."""
         f = _frame(depth, rgb, K)
         r = Result()
         self._follow(depth, rgb)
-        _check(lib().relocaliser_relocalise_ex(self.handle, ctypes.byref(f), int(request_seed),
-                                               ctypes.byref(r)), allow=(RL_OK, RL_NO_POSE))
+        opts = RelocOpts(int(n_hypotheses), int(n_cull), int(n_out), int(final_refine))
+        _check(lib().relocaliser_relocalise_opts(self.handle, ctypes.byref(f), int(request_seed),
+                                                 ctypes.byref(opts), ctypes.byref(r)), allow=(RL_OK, RL_NO_POSE))
         return _result(r)
+
+    def plane_scores(self, depth, rgb, K, surfaces: np.ndarray, poses12: np.ndarray) -> np.ndarray:
+        """Model-based score (mean nearest-surface distance) of each pose."""
+        f = _frame(depth, rgb, K)
+        S = np.ascontiguousarray(surfaces, dtype=np.float32).reshape(-1, 16)
+        P = np.ascontiguousarray(poses12, dtype=np.float32).reshape(-1, 12)
+        out = np.zeros(P.shape[0], dtype=np.float64)
+        self._follow(depth, rgb)
+        _check(lib().rl_plane_scores(self.handle, ctypes.byref(f), S.ctypes.data, S.shape[0], P.ctypes.data,
+                                     P.shape[0], out.ctypes.data))
+        return out
+
+    def survivors(self, k: int):
+        """(slots, poses (k, 12)) of the best k hypotheses of the last relocalisation."""
+        slots = self.buffer_np(BUF_SURVIVORS, np.int32)[:k].copy()
+        hy = self.buffer_np(BUF_HYPS, HYP_DTYPE)
+        poses = np.concatenate([hy["R"][slots], hy["t"][slots]], axis=1).astype(np.float32)
+        return slots, poses
 
     def set_trace(self, on: bool):
         _check(lib().relocaliser_set_trace(self.handle, 1 if on else 0))

@@ -654,6 +654,88 @@ __global__ __launch_bounds__(256) void k_finalize(const Job* __restrict__ jobs)
 }
 
 // ------------------------------------------------------------------------
+// Model-based pose score on an analytic scene (surfaces of 16 floats: p0, n,
+// e1, e2, half-extents; half_a <= 0 = infinite plane): per (tile of 1024
+// pixels, pose) the sum of nearest-surface distances of H x^C(u) over valid
+// pixels, reduced in a fixed order; then the per-pose means.
+__global__ __launch_bounds__(256) void k_plane_partial(const float* __restrict__ depth, int w, int h, float fx,
+                                                       float fy, float cx, float cy,
+                                                       const float* __restrict__ surfaces, int n_surf,
+                                                       const float* __restrict__ poses,
+                                                       double* __restrict__ partial, int* __restrict__ cnt)
+{
+    __shared__ float s_surf[64 * 16];
+    __shared__ double s_red[256];
+    __shared__ int s_cnt[256];
+    const int tile = blockIdx.x, pose = blockIdx.y;
+    for (int i = threadIdx.x; i < n_surf * 16; i += 256) s_surf[i] = surfaces[i];
+    double R[9], t[3];
+    for (int i = 0; i < 9; ++i) R[i] = poses[12 * pose + i];
+    for (int i = 0; i < 3; ++i) t[i] = poses[12 * pose + 9 + i];
+    __syncthreads();
+    const int P = w * h;
+    double acc = 0.0;
+    int c = 0;
+    for (int k = 0; k < 4; ++k) {
+        const int p = tile * 1024 + k * 256 + threadIdx.x;
+        if (p >= P) break;
+        const float d = depth[p];
+        if (!depth_ok(d)) continue;
+        double x[3];
+        backproject(d, p % w, p / w, fx, fy, cx, cy, x);
+        const double y0 = R[0] * x[0] + R[1] * x[1] + R[2] * x[2] + t[0];
+        const double y1 = R[3] * x[0] + R[4] * x[1] + R[5] * x[2] + t[1];
+        const double y2 = R[6] * x[0] + R[7] * x[1] + R[8] * x[2] + t[2];
+        double best = INFINITY;
+        for (int s = 0; s < n_surf; ++s) {
+            const float* S = s_surf + 16 * s;
+            const double r0 = y0 - S[0], r1 = y1 - S[1], r2 = y2 - S[2];
+            const double cc = r0 * S[3] + r1 * S[4] + r2 * S[5];
+            double dist;
+            if (S[12] <= 0.0f) {
+                dist = fabs(cc);
+            } else {
+                const double a = r0 * S[6] + r1 * S[7] + r2 * S[8];
+                const double b = r0 * S[9] + r1 * S[10] + r2 * S[11];
+                const double da = fmax(fabs(a) - (double)S[12], 0.0), db = fmax(fabs(b) - (double)S[13], 0.0);
+                dist = sqrt(cc * cc + da * da + db * db);
+            }
+            best = fmin(best, dist);
+        }
+        acc += best;
+        ++c;
+    }
+    s_red[threadIdx.x] = acc;
+    s_cnt[threadIdx.x] = c;
+    __syncthreads();
+    for (int stride = 128; stride > 0; stride >>= 1) {
+        if ((int)threadIdx.x < stride) {
+            s_red[threadIdx.x] += s_red[threadIdx.x + stride];
+            s_cnt[threadIdx.x] += s_cnt[threadIdx.x + stride];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[(size_t)tile * 64 + pose] = s_red[0];
+        if (pose == 0) cnt[tile] = s_cnt[0];
+    }
+}
+
+__global__ void k_plane_final(const double* __restrict__ partial, const int* __restrict__ cnt, int ntiles,
+                              int n_poses, double* __restrict__ scores)
+{
+    const int pose = threadIdx.x;
+    if (pose >= n_poses) return;
+    double acc = 0.0;
+    long long c = 0;
+    for (int tI = 0; tI < ntiles; ++tI) {
+        acc += partial[(size_t)tI * 64 + pose];
+        c += cnt[tI];
+    }
+    scores[pose] = c > 0 ? acc / (double)c : INFINITY;
+}
+
+// ------------------------------------------------------------------------
 // host-side launchers (called by the runtime)
 #define RL_CHECK_LAUNCH() do { hipError_t e_ = hipGetLastError(); if (e_ != hipSuccess) return e_; } while (0)
 
@@ -723,6 +805,19 @@ hipError_t launch_select(const Job* jobs, int njobs, int round, int nptiles, int
 {
     const size_t sel_lds = (sizeof(double) + sizeof(int)) * (size_t)maxN;
     k_select<<<dim3(1, njobs), dim3(1024), sel_lds, st>>>(jobs, round, nptiles);
+    RL_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_plane_scores(const float* depth, int w, int h, float fx, float fy, float cx, float cy,
+                               const float* surfaces, int n_surf, const float* poses, int n_poses,
+                               double* partial, int* cnt, double* scores, hipStream_t st)
+{
+    const int ntiles = (w * h + 1023) / 1024;
+    k_plane_partial<<<dim3(ntiles, n_poses), dim3(256), 0, st>>>(depth, w, h, fx, fy, cx, cy, surfaces, n_surf,
+                                                                  poses, partial, cnt);
+    RL_CHECK_LAUNCH();
+    k_plane_final<<<dim3(1), dim3(64), 0, st>>>(partial, cnt, ntiles, n_poses, scores);
     RL_CHECK_LAUNCH();
     return hipSuccess;
 }

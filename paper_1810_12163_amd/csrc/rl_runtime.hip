@@ -6,6 +6,7 @@
 // can be captured into a HIP graph per batch shape and replayed.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -29,6 +30,9 @@ hipError_t launch_score(const Job* jobs, int njobs, int round, int nptiles, int 
                         size_t score_lds, hipStream_t st);
 hipError_t launch_select(const Job* jobs, int njobs, int round, int nptiles, int maxN, hipStream_t st);
 hipError_t launch_finalize(const Job* jobs, int njobs, int maxIlen, hipStream_t st);
+hipError_t launch_plane_scores(const float* depth, int w, int h, float fx, float fy, float cx, float cy,
+                               const float* surfaces, int n_surf, const float* poses, int n_poses,
+                               double* partial, int* cnt, double* scores, hipStream_t st);
 hipError_t launch_adapt(const AdaptArgs& a, hipStream_t st);
 hipError_t launch_rqs(const RqsArgs& a, int blocks, hipStream_t st);
 
@@ -95,6 +99,15 @@ int rounds_for(int N, int n_cull, int n_out, std::vector<int>* entering = nullpt
     return rounds;
 }
 
+// Rounds any call on a room may need: N' <= N hypotheses, any cull, any
+// n_out >= 1 take at most the rounds of N without cull down to one.
+int rounds_capacity(const rl_params& p)
+{
+    return std::max(rounds_for(p.max_pose_candidates, p.max_pose_candidates_after_cull,
+                               p.max_relocalisations_to_output),
+                    rounds_for(p.max_pose_candidates, p.max_pose_candidates, 1));
+}
+
 int score_tile(int rows_per_pixel)
 {
     int tp = kScoreLdsBytes / (rows_per_pixel * 72);
@@ -154,6 +167,28 @@ PersistLayout persist_layout(const rl_params& p)
     P.nmodes = c.take(T * L);
     P.total = c.cur;
     return P;
+}
+
+constexpr int kMaxModelSurfaces = 64, kMaxModelPoses = 64;
+
+// Scratch of the model-based score: surfaces, poses, per-tile partials, scores.
+struct ModelLayout {
+    size_t surfaces, poses, partial, cnt, scores, total;
+};
+
+ModelLayout model_layout(int maxP, size_t base)
+{
+    Carver c;
+    c.cur = base;
+    ModelLayout L;
+    const size_t ntiles = (size_t)(maxP + 1023) / 1024;
+    L.surfaces = c.take((size_t)kMaxModelSurfaces * 64);
+    L.poses = c.take((size_t)kMaxModelPoses * 48);
+    L.partial = c.take(ntiles * kMaxModelPoses * 8);
+    L.cnt = c.take(ntiles * 4);
+    L.scores = c.take((size_t)kMaxModelPoses * 8);
+    L.total = c.cur - base;
+    return L;
 }
 
 struct AdaptLayout {
@@ -231,7 +266,10 @@ struct rl_room {
     PersistLayout PL;
     FrameLayout FL;
     AdaptLayout AL;
+    ModelLayout ML;
     size_t job_off;
+    char* model_host;
+    int rounds_cap;
     hipStream_t stream;
     hipEvent_t ev;
     Job* job_host;
@@ -363,13 +401,14 @@ RL_API rl_status relocaliser_state_bytes(const rl_params* p, int32_t max_width, 
         return fail(RL_EINVAL, "max frame size must be multiples of 4, at least 8x8");
     if (!persistent || !scratch) return fail(RL_EINVAL, "NULL output");
     const int N = p->max_pose_candidates, eta = p->ransac_inliers_per_iteration;
-    const int R = rounds_for(N, p->max_pose_candidates_after_cull, p->max_relocalisations_to_output);
+    const int R = rounds_capacity(*p);
     const int TP = score_tile(p->n_trees * p->max_cluster_count);
     *persistent = persist_layout(*p).total;
     const size_t job = align256(sizeof(Job));
     const FrameLayout FL = frame_layout(max_width * max_height, N, eta, R, TP, job);
     const AdaptLayout AL = adapt_layout(*p, grid_items(max_width, max_height), job + FL.total);
-    *scratch = job + FL.total + AL.total;
+    const ModelLayout ML = model_layout(max_width * max_height, job + FL.total + AL.total);
+    *scratch = job + FL.total + AL.total + ML.total;
     return RL_OK;
 }
 
@@ -504,8 +543,10 @@ RL_API rl_status relocaliser_create(const rl_params* p, const rl_node* host_node
     r->scr = reinterpret_cast<char*>(dev_scratch);
     r->PL = persist_layout(*p);
     r->job_off = 0;
-    r->FL = frame_layout(r->maxP, r->N, r->eta, r->rounds, r->TP, align256(sizeof(Job)));
+    r->rounds_cap = rounds_capacity(*p);
+    r->FL = frame_layout(r->maxP, r->N, r->eta, r->rounds_cap, r->TP, align256(sizeof(Job)));
     r->AL = adapt_layout(*p, r->G, align256(sizeof(Job)) + r->FL.total);
+    r->ML = model_layout(r->maxP, align256(sizeof(Job)) + r->FL.total + r->AL.total);
     r->stream = reinterpret_cast<hipStream_t>(hip_stream);
     r->trace = 0;
     r->modes_stale = false;
@@ -516,6 +557,9 @@ RL_API rl_status relocaliser_create(const rl_params* p, const rl_node* host_node
     }
     e = hipHostMalloc(reinterpret_cast<void**>(&r->job_host), sizeof(Job), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&r->res_host), sizeof(rl_result), hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void**>(&r->model_host),
+                          (size_t)kMaxModelSurfaces * 64 + (size_t)kMaxModelPoses * (48 + 8), hipHostMallocDefault);
     if (e != hipSuccess) {
         (void)hipEventDestroy(r->ev);
         delete r;
@@ -555,6 +599,7 @@ RL_API rl_status relocaliser_destroy(rl_room* r)
     for (auto& kv : r->graphs) (void)hipGraphExecDestroy(kv.second);
     if (r->job_host) (void)hipHostFree(r->job_host);
     if (r->res_host) (void)hipHostFree(r->res_host);
+    if (r->model_host) (void)hipHostFree(r->model_host);
     if (r->ev) (void)hipEventDestroy(r->ev);
     delete r;
     return RL_OK;
@@ -697,22 +742,37 @@ static hipError_t run_sequence(std::map<std::vector<long long>, hipGraphExec_t>&
     return hipGraphLaunch(it->second, st);
 }
 
-RL_API rl_status relocaliser_relocalise_ex(rl_room* r, const rl_frame* f, uint64_t request_seed, rl_result* out)
+RL_API rl_status relocaliser_relocalise_opts(rl_room* r, const rl_frame* f, uint64_t request_seed,
+                                             const rl_reloc_opts* opts, rl_result* out)
 {
     if (!r || !out) return fail(RL_EINVAL, "NULL argument");
     rl_status s = validate_frame(f, r->max_w, r->max_h);
     if (s != RL_OK) return s;
+    const int N = opts && opts->n_hypotheses > 0 ? opts->n_hypotheses : r->N;
+    const int n_cull = opts && opts->n_cull > 0 ? opts->n_cull : r->p.max_pose_candidates_after_cull;
+    const int n_out = opts && opts->n_out > 0 ? opts->n_out : r->p.max_relocalisations_to_output;
+    const int refine = opts && opts->final_refine >= 0 ? (opts->final_refine ? 1 : 0) : r->p.final_refine;
+    if (N > r->N) return fail(RL_EINVAL, "%d hypotheses exceed the room's maximum %d", N, r->N);
+    std::vector<int> entering;
+    const int R = rounds_for(N, n_cull, n_out, &entering);
+    if (R > r->rounds_cap) return fail(RL_EINVAL, "%d rounds exceed the room's capacity %d", R, r->rounds_cap);
     s = ensure_modes(r, r->stream);
     if (s != RL_OK) return s;
-    *r->job_host = make_job(r, r->scr, r->FL, f, request_seed, r->N);
+    Job J = make_job(r, r->scr, r->FL, f, request_seed, N);
+    J.n_cull = n_cull;
+    J.n_out = n_out;
+    J.final_refine = refine;
+    *r->job_host = J;
     Job* jd = reinterpret_cast<Job*>(r->scr + r->job_off);
     hipError_t e = hipMemcpyAsync(jd, r->job_host, sizeof(Job), hipMemcpyHostToDevice, r->stream);
     if (e != hipSuccess) return hip_fail(e, "job upload");
     const int nptiles = (r->eta + r->TP - 1) / r->TP;
     const size_t score_lds = (size_t)r->TP * r->T * r->M * 72;
     const int P = f->width * f->height;
-    e = run_sequence(r->graphs, {P}, r->timer.kernel == RL_TIMER_NONE, r->stream, [&]() {
-        return launch_sequence(jd, 1, P, r->N, r->p.max_candidate_generation_iterations, r->T, r->entering,
+    std::vector<long long> key = {P, N};
+    for (int v : entering) key.push_back(v);
+    e = run_sequence(r->graphs, key, r->timer.kernel == RL_TIMER_NONE, r->stream, [&]() {
+        return launch_sequence(jd, 1, P, N, r->p.max_candidate_generation_iterations, r->T, entering,
                                nptiles, r->eta, score_lds, r->timer, r->stream);
     });
     if (e != hipSuccess) return hip_fail(e, "relocalise launch");
@@ -721,6 +781,46 @@ RL_API rl_status relocaliser_relocalise_ex(rl_room* r, const rl_frame* f, uint64
     if (e != hipSuccess) return hip_fail(e, "relocalise");
     *out = *r->res_host;
     return out->status == RL_OK ? RL_OK : RL_NO_POSE;
+}
+
+RL_API rl_status relocaliser_relocalise_ex(rl_room* r, const rl_frame* f, uint64_t request_seed, rl_result* out)
+{
+    return relocaliser_relocalise_opts(r, f, request_seed, nullptr, out);
+}
+
+RL_API rl_status rl_plane_scores(rl_room* r, const rl_frame* f, const rl_surface* surfaces, int32_t n_surf,
+                                 const float* poses, int32_t n_poses, double* scores)
+{
+    if (!r || !surfaces || !poses || !scores) return fail(RL_EINVAL, "NULL argument");
+    rl_status s = validate_frame(f, r->max_w, r->max_h);
+    if (s != RL_OK) return s;
+    if (n_surf < 1 || n_surf > kMaxModelSurfaces) return fail(RL_EINVAL, "n_surfaces must be in 1..%d", kMaxModelSurfaces);
+    if (n_poses < 1 || n_poses > kMaxModelPoses) return fail(RL_EINVAL, "n_poses must be in 1..%d", kMaxModelPoses);
+    for (int i = 0; i < n_surf * 16; ++i)
+        if (!finite_f(reinterpret_cast<const float*>(surfaces)[i])) return fail(RL_EINVAL, "non-finite surface");
+    for (int i = 0; i < n_poses * 12; ++i)
+        if (!finite_f(poses[i])) return fail(RL_EINVAL, "non-finite pose");
+    char* hs = r->model_host;
+    std::memcpy(hs, surfaces, (size_t)n_surf * 64);
+    std::memcpy(hs + kMaxModelSurfaces * 64, poses, (size_t)n_poses * 48);
+    hipError_t e = hipMemcpyAsync(r->scr + r->ML.surfaces, hs, (size_t)n_surf * 64, hipMemcpyHostToDevice, r->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(r->scr + r->ML.poses, hs + kMaxModelSurfaces * 64, (size_t)n_poses * 48,
+                           hipMemcpyHostToDevice, r->stream);
+    if (e == hipSuccess)
+        e = launch_plane_scores(f->depth, f->width, f->height, f->K.fx, f->K.fy, f->K.cx, f->K.cy,
+                                reinterpret_cast<const float*>(r->scr + r->ML.surfaces), n_surf,
+                                reinterpret_cast<const float*>(r->scr + r->ML.poses), n_poses,
+                                reinterpret_cast<double*>(r->scr + r->ML.partial),
+                                reinterpret_cast<int*>(r->scr + r->ML.cnt),
+                                reinterpret_cast<double*>(r->scr + r->ML.scores), r->stream);
+    double* hscores = reinterpret_cast<double*>(hs + kMaxModelSurfaces * 64 + kMaxModelPoses * 48);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hscores, r->scr + r->ML.scores, (size_t)n_poses * 8, hipMemcpyDeviceToHost, r->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
+    if (e != hipSuccess) return hip_fail(e, "plane scores");
+    std::memcpy(scores, hscores, (size_t)n_poses * 8);
+    return RL_OK;
 }
 
 RL_API rl_status relocaliser_relocalise(rl_room* r, const rl_frame* f, uint64_t request_seed, float H[16],
@@ -750,9 +850,9 @@ RL_API rl_status relocaliser_buffer(const rl_room* r, int32_t which, size_t* off
         case RL_BUF_NM: *offset = r->FL.nm; *bytes = (size_t)r->maxP; *region = 1; break;
         case RL_BUF_ELIGIBLE: *offset = r->FL.eligible; *bytes = (size_t)r->maxP * 4; *region = 1; break;
         case RL_BUF_HYPS: *offset = r->FL.hyps; *bytes = (size_t)r->N * sizeof(Hyp); *region = 1; break;
-        case RL_BUF_ILIST: *offset = r->FL.I; *bytes = (size_t)r->rounds * r->eta * 4; *region = 1; break;
-        case RL_BUF_TRACE_SLOTS: *offset = r->FL.trace_slots; *bytes = (size_t)r->rounds * r->N * 4; *region = 1; break;
-        case RL_BUF_TRACE_ENERGY: *offset = r->FL.trace_E; *bytes = (size_t)r->rounds * r->N * 8; *region = 1; break;
+        case RL_BUF_ILIST: *offset = r->FL.I; *bytes = (size_t)r->rounds_cap * r->eta * 4; *region = 1; break;
+        case RL_BUF_TRACE_SLOTS: *offset = r->FL.trace_slots; *bytes = (size_t)r->rounds_cap * r->N * 4; *region = 1; break;
+        case RL_BUF_TRACE_ENERGY: *offset = r->FL.trace_E; *bytes = (size_t)r->rounds_cap * r->N * 8; *region = 1; break;
         case RL_BUF_SURVIVORS: *offset = r->FL.surv; *bytes = (size_t)r->N * 4; *region = 1; break;
         case RL_BUF_ENERGY: *offset = r->FL.E; *bytes = (size_t)r->N * 8; *region = 1; break;
         default: return fail(RL_EINVAL, "unknown buffer %d", which);

@@ -114,3 +114,82 @@ def test_c2_relocalise_full_stage_parity(c2):
     print(f"[c2] pose error vs ground truth: {dt * 100:.2f} cm, {dr:.2f} deg; "
           f"valid hypotheses {int(v.sum())}", flush=True)
     room.set_trace(False)
+
+
+# ---------------------------------------------------------------------------
+# cascade pieces: per-call RANSAC settings, decimated stage, model score
+
+@pytest.fixture(scope="module")
+def c3_room(c2):
+    w, o, room = c2
+    from rlsynth import presets
+    p3 = presets.preset("c3c")            # room sized for 4096 hypotheses, 16 outputs
+    r3 = rl.Room(p3, w.nodes, 640, 480)
+    for f in w.adapt:
+        d, c = dev(f)
+        r3.adapt(d, c, f.K, f.pose)
+    r3.update_modes()
+    return p3, r3
+
+
+def _stage_ref(room, q, params, seed, T, D, M, nodes, ref_width):
+    leaves = oracle.traverse(q.depth, q.rgb, None, nodes, T, D, ref_width)
+    nm = room.buffer_np(rl.BUF_NMODES, np.uint8).copy()
+    modes = room.buffer_np(rl.BUF_MODES, np.float32).copy()
+    return oracle.estimate_pose(q.depth, q.rgb, q.K, leaves, nm, modes, T, D, M, params, seed)
+
+
+def test_c3_decimated_stage_matches_oracle(c2, c3_room):
+    w, o, _ = c2
+    p3, r3 = c3_room
+    q = workloads.decimate(w.queries[1])
+    d, c = dev(q)
+    res = r3.relocalise(d, c, q.K, request_seed=21, n_hypotheses=256, n_cull=256, n_out=1, final_refine=1)
+    params = dict(p3, max_pose_candidates=256, max_pose_candidates_after_cull=256,
+                  max_relocalisations_to_output=1, final_refine=1)
+    ref = _stage_ref(r3, q, params, 21, o.T, o.D, o.M, w.nodes, p3["ref_width"])
+    assert res["rounds"] == ref["rounds"] == 8
+    assert res["n_valid"] == int(ref["hyp_valid"].sum()) and res["winner"] == ref["winner"]
+    assert pose_diff(res["pose"], ref["pose"]) < 1e-5
+    assert abs(res["energy"] - ref["energy"]) <= 1e-4 * abs(ref["energy"])
+
+
+def test_c3_wide_stage_keeps_16_and_model_score_matches(c2, c3_room):
+    w, o, _ = c2
+    p3, r3 = c3_room
+    q = w.queries[1]
+    d, c = dev(q)
+    res = r3.relocalise(d, c, q.K, request_seed=22, n_hypotheses=4096, n_cull=4096, n_out=16, final_refine=0)
+    ref = _stage_ref(r3, q, dict(p3, final_refine=0), 22, o.T, o.D, o.M, w.nodes, p3["ref_width"])
+    assert res["rounds"] == ref["rounds"] == 8 and res["n_out"] == len(ref["out_slots"])
+    slots, poses = r3.survivors(res["n_out"])
+    np.testing.assert_array_equal(slots, ref["out_slots"])
+    S = oracle.surfaces_of(w.room)
+    got = r3.plane_scores(d, c, q.K, S, poses)
+    want = oracle.plane_scores(q.depth, q.K, poses, S)
+    np.testing.assert_allclose(got, want, rtol=1e-9, atol=1e-12)
+    gt = np.concatenate([q.pose[:3, :3].reshape(-1), q.pose[:3, 3]]).astype(np.float32)
+    s_gt = r3.plane_scores(d, c, q.K, S, gt[None])[0]
+    assert s_gt < 0.005                     # noisy depth: a few mm at the true pose
+
+
+def test_cascade_fallback_and_ranking(c2, c3_room):
+    from paper_1810_12163_amd.cascade import Cascade, Stage
+    w, o, _ = c2
+    p3, r3 = c3_room
+    S = oracle.surfaces_of(w.room)
+    q = w.queries[0]
+    d, c = dev(q)
+    stages = [Stage("a", 256, decimate=True), Stage("b", 1024, final_refine=1), Stage("c", 4096, n_out=16)]
+    accept = Cascade(r3, [dataclasses_replace(s, threshold=float("inf")) for s in stages], S)
+    out = accept.relocalise(d, c, q.K, request_seed=3)
+    assert out["stage"] == "a" and len(out["trail"]) == 1
+    full = Cascade(r3, [dataclasses_replace(s, threshold=0.0) for s in stages], S)
+    out = full.relocalise(d, c, q.K, request_seed=3)
+    assert [t[0] for t in out["trail"]] == ["a", "b", "c"] and out["stage"] == "c"
+    assert out["model_score"] == float(np.min(out["ranked"]))
+
+
+def dataclasses_replace(s, **kw):
+    import dataclasses
+    return dataclasses.replace(s, **kw)

@@ -260,3 +260,45 @@ def test_refit_over_noise_free_inliers_is_exact():
     assert out["refitted"] and out["n_inliers"] == len(out["I"])
     dt, dr = scene.pose_error(out["pose"], sc["H"])
     assert dt < 2e-6 and dr < 1e-4
+
+
+# ---------------------------------------------------------------------------
+# model-based score (analytic scene) used by the cascade
+
+def test_plane_score_is_zero_at_the_true_pose_and_grows_with_error():
+    room = scene.make_room(4)
+    H = scene.random_pose(room, np.random.default_rng(9))
+    w, h = 80, 60
+    K = scene.intrinsics(w, h)
+    depth, _ = scene.render(room, H, w, h, seed=3, noise_sigma=0.0, dropout=0.0)
+    S = oracle.surfaces_of(room)
+    pose = np.concatenate([H[:3, :3].reshape(-1), H[:3, 3]]).astype(np.float32)
+    shifted = pose.copy()
+    shifted[9] += 0.05
+    s = oracle.plane_scores(depth, K, np.stack([pose, shifted]), S)
+    assert s[0] < 1e-5                       # float32 depth and pose only
+    # a 5 cm shift moves every point at most 5 cm from the surface it lay on,
+    # and points on surfaces not parallel to the shift strictly off it
+    assert s[0] + 1e-3 < s[1] <= 0.05 + 1e-6
+
+
+def test_plane_score_rectangle_distance_closed_form():
+    # one quad in the z = 0 plane, half-extents (1, 1); a camera at the origin
+    # looking down +z sees points at depth d; pose chosen so the points land
+    # at known offsets from the quad
+    S = np.zeros((1, 16), np.float32)
+    S[0, 3:6] = [0, 0, 1]
+    S[0, 6:9] = [1, 0, 0]
+    S[0, 9:12] = [0, 1, 0]
+    S[0, 12:14] = [1, 1]
+    depth = np.zeros((1, 4), np.float32)
+    depth[0, 1] = 2.0                          # pixel (1, 0): K maps it to x = d * (1 - 0) / 1
+    K = (np.float32(1.0), np.float32(1.0), np.float32(0.0), np.float32(0.0))
+    pose = np.array([1, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, -2.0], np.float32)   # x^W = x^C - (0, 0, 2)
+    # x^C = (2, 0, 2) -> y = (2, 0, 0): in plane, 1 beyond the edge in a -> distance 1
+    assert abs(oracle.plane_scores(depth, K, pose[None], S)[0] - 1.0) < 1e-12
+    pose2 = pose.copy()
+    pose2[11] = -1.0                          # y = (2, 0, 1): sqrt(1 + 1)
+    assert abs(oracle.plane_scores(depth, K, pose2[None], S)[0] - np.sqrt(2.0)) < 1e-12
+    S[0, 12:14] = 0                           # infinite plane: only the normal offset counts
+    assert abs(oracle.plane_scores(depth, K, pose2[None], S)[0] - 1.0) < 1e-12
