@@ -113,7 +113,8 @@ rl_status rl_params_validate(const rl_params* p);
 /*
  * Device bytes a room needs.  persistent: forest, reservoirs, counters and
  * modes (must outlive the room).  scratch: per-frame work space for frames up
- * to max_width x max_height.  Both must be 256-byte aligned.
+ * to max_width x max_height (multiples of 4, at least 8x8, fewer than 2^24
+ * pixels; RL_EINVAL otherwise).  Both must be 256-byte aligned.
  */
 rl_status relocaliser_state_bytes(const rl_params* p, int32_t max_width, int32_t max_height,
                                   size_t* persistent, size_t* scratch);
@@ -282,7 +283,8 @@ typedef struct {
     int32_t pad;
 } rl_request;
 
-/* Device workspace bytes of a batch context (256-byte aligned buffer). */
+/* Device workspace bytes of a batch context (256-byte aligned buffer); the
+ * frame limits are those of relocaliser_state_bytes. */
 rl_status rl_batch_workspace_bytes(const rl_batch_params* bp, size_t* bytes);
 
 rl_status rl_batch_create(const rl_batch_params* bp, void* dev_workspace, void* hip_stream,

@@ -17,6 +17,7 @@
 namespace rl {
 
 constexpr int kMaxTrees = 8;
+constexpr long long kMaxPixels = 1LL << 24;   // pixel indices are packed in 24 bits
 constexpr int kLeafNone = 0xFFFF;
 constexpr uint32_t kTagRes = 1, kTagHyp = 2, kTagScore = 3;
 constexpr int kScoreLdsBytes = 64 * 1024;     // mode rows staged per scoring block
@@ -65,6 +66,9 @@ struct Job {
     uint8_t* nm;              // [P] |M(u)|
     int* tile_count;          // [ceil(P/256)]
     int* eligible;            // [P]
+    uint64_t* erec;           // [P][ew] eligible-pixel records (see erec_* below)
+    int ew;                   // words per record: 2 for |M(u)| <= 64, else 4 or 6
+    int pad1;
     int* hyp_best;            // [N]
     Hyp* hyps;                // [N]
     int* surv;                // [N]
@@ -320,6 +324,18 @@ __device__ __forceinline__ uint32_t count_of(uint2 nw, int t)
     const uint64_t v = ((uint64_t)nw.y << 32) | nw.x;
     return (uint32_t)(v >> (8 * t)) & 0xFFu;
 }
+
+// Eligible-pixel record, one per entry of the eligible list (ew 64-bit words,
+// ew even so that a record starts on a 16-byte boundary):
+//   word 0: pixel index (bits 0-23) | |M(u)| (bits 24-31) | depth bits (32-63)
+//   words 1..: bit m = outcome of the colour check for mode m of M(u).
+// The colour check of a (pixel, mode) pair does not depend on the iteration
+// that draws it, so it is evaluated once per pair when the list is built and
+// a generation iteration reads one record instead of gathering the pixel,
+// its leaves, its colour and the mode row.
+__device__ __forceinline__ int erec_pixel(uint64_t h) { return (int)((uint32_t)h & 0xFFFFFFu); }
+__device__ __forceinline__ uint32_t erec_total(uint64_t h) { return ((uint32_t)h) >> 24; }
+__device__ __forceinline__ float erec_depth(uint64_t h) { return __uint_as_float((uint32_t)(h >> 32)); }
 
 __device__ __forceinline__ int modes_total(uint2 nw, int T)
 {

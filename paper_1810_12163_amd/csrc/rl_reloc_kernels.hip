@@ -3,10 +3,13 @@
 // Pipeline per frame (Sec. 3.2.3 of Cavallari et al., TPAMI 2019):
 //   k_prep          clear per-frame state
 //   k_traverse      features + routing of every pixel through every tree (Eq. 1-3)
-//   k_eligible      raster-order list of pixels with depth and >= 1 mode
-//   k_hyp_search    hypothesis generation: all (slot, 256-iteration chunk)
-//                   pairs in parallel, first passing iteration by atomicMin
-//   k_hyp_finalize  rebuild each slot's winning triplet, Kabsch pose
+//   k_eligible      raster-order list of pixels with depth and >= 1 mode,
+//                   with per-pixel records (colour-check bits of M(u))
+//   k_hyp_search    hypothesis generation: all (slot, iteration chunk)
+//                   pairs in parallel, first iteration passing checks 1-3
+//                   by atomicMin
+//   k_hyp_finalize  rebuild each slot's triplet, Kabsch pose (continuing
+//                   the scan past a degenerate fit)
 //   k_ransac_init   survivors = valid slots in slot order
 //   k_score/k_select  one preemptive-RANSAC round each (Eq. 5, halving)
 //   k_finalize      winner, optional refit over inliers, result record
@@ -106,7 +109,42 @@ __global__ __launch_bounds__(256) void k_traverse(const Job* __restrict__ jobs)
     if (threadIdx.x == 0) J.tile_count[blockIdx.x] = tot;
 }
 
-// Raster-order compaction of eligible pixels over the traversal's tiles.
+// Colour check of pair (pixel, mode) (check 1 of Sec. 3.2.3): L-infinity
+// distance between the pixel's colour and the mode's mean colour, float32.
+__device__ __forceinline__ bool colour_ok(const uint8_t* px, const float4* row, float theta)
+{
+    const float4 c2 = row[2], c3 = row[3];
+    return !(fabsf((float)px[0] - c2.z) > theta || fabsf((float)px[1] - c2.w) > theta ||
+             fabsf((float)px[2] - c3.x) > theta);
+}
+
+// Record of eligible pixel p at list position e: header and the colour-check
+// bit of every mode of M(u), in M(u) order.
+__device__ __forceinline__ void write_erec(const Job& J, int e, int p)
+{
+    const uint4 lw = reinterpret_cast<const uint4*>(J.leaves)[p];
+    const uint2 nw = reinterpret_cast<const uint2*>(J.nmt)[p];
+    const uint8_t* px = J.rgb + 3 * p;
+    uint64_t* rec = J.erec + (size_t)e * J.ew;
+    uint32_t m = 0;
+    uint64_t cur = 0;
+    for (int t = 0; t < J.T; ++t) {
+        const int c = (int)count_of(nw, t);
+        const float4* row = J.modes + ((((size_t)t << J.D) + leaf_of(lw, t)) * (size_t)J.M) * 4;
+        for (int j = 0; j < c; ++j, ++m) {
+            cur |= (uint64_t)colour_ok(px, row + 4 * j, J.theta_col) << (m & 63);
+            if ((m & 63) == 63) {
+                rec[1 + (m >> 6)] = cur;
+                cur = 0;
+            }
+        }
+    }
+    if (m & 63) rec[1 + (m >> 6)] = cur;
+    rec[0] = (uint64_t)((uint32_t)p | (m << 24)) | ((uint64_t)__float_as_uint(J.depth[p]) << 32);
+}
+
+// Raster-order compaction of eligible pixels over the traversal's tiles, and
+// their records.
 __global__ __launch_bounds__(256) void k_eligible(const Job* __restrict__ jobs)
 {
     const Job& J = jobs[blockIdx.y];
@@ -128,7 +166,10 @@ __global__ __launch_bounds__(256) void k_eligible(const Job* __restrict__ jobs)
     const bool e = p < P && J.nm[p] > 0;
     int tot;
     const int pre = block_prefix256(e, s_wave, &tot);
-    if (e) J.eligible[base + pre] = p;
+    if (e) {
+        J.eligible[base + pre] = p;
+        write_erec(J, base + pre, p);
+    }
     if ((int)blockIdx.x == ntiles - 1 && threadIdx.x == 0) J.st->n_elig = base + tot;
 }
 
@@ -146,7 +187,8 @@ __global__ __launch_bounds__(256) void k_eligible(const Job* __restrict__ jobs)
 // check (about 1 in 9 passes) runs dense over many iterations and only its
 // survivors, compacted into an LDS queue, pay for the other two pixels, the
 // back-projections and the rigidity test: lanes stay busy instead of idling
-// behind divergent branches.
+// behind divergent branches.  The colour check itself is a bit test in the
+// eligible-pixel record (its outcome per (pixel, mode) is fixed per frame).
 
 __device__ __forceinline__ uint32_t mode_row_index(const Job& J, uint4 lw, uint2 nw, int m)
 {
@@ -159,44 +201,65 @@ __device__ __forceinline__ uint32_t mode_row_index(const Job& J, uint4 lw, uint2
     return ((((uint32_t)t << J.D) + leaf_of(lw, t)) * (uint32_t)J.M + (uint32_t)m);
 }
 
-// pixel and mode of one pair from its two draws
-__device__ __forceinline__ void draw_pair(const Job& J, int n_elig, uint32_t rp, uint32_t rm, int& p,
-                                          int& m, uint32_t& row)
+// record header (and first mask word) of list entry e
+__device__ __forceinline__ ulonglong2 erec_head(const Job& J, uint32_t e)
 {
-    p = J.eligible[below(rp, (uint32_t)n_elig)];
+    return *reinterpret_cast<const ulonglong2*>(J.erec + (size_t)e * J.ew);
+}
+
+// pixel, mode, depth and mode row of one pair from its two draws
+__device__ __forceinline__ void draw_pair(const Job& J, int n_elig, uint32_t rp, uint32_t rm, int& p,
+                                          int& m, float& d, uint32_t& row)
+{
+    const uint64_t h = erec_head(J, below(rp, (uint32_t)n_elig)).x;
+    p = erec_pixel(h);
+    d = erec_depth(h);
+    m = (int)below(rm, erec_total(h));
     const uint4 lw = reinterpret_cast<const uint4*>(J.leaves)[p];
     const uint2 nw = reinterpret_cast<const uint2*>(J.nmt)[p];
-    m = (int)below(rm, (uint32_t)modes_total(nw, J.T));
     row = mode_row_index(J, lw, nw, m);
 }
 
-// stage A: the colour check of pair k*
-__device__ __forceinline__ bool hyp_stage_a(const Job& J, int n_elig, int slot, int it, int& kc, int& pc,
-                                            int& mc, uint32_t& rowc)
+// stage A: the colour check of pair k* (list entry ec, mode mc of M(u))
+__device__ __forceinline__ bool hyp_stage_a(const Job& J, int n_elig, int slot, int it, int& kc, int& ec,
+                                            int& mc)
 {
     const uint4 a = philox(make_uint4((kTagHyp << 28) | 0u, (uint32_t)slot, (uint32_t)it, 0u), J.key0, J.key1);
     kc = (int)below(a.x, 3u);
-    draw_pair(J, n_elig, a.y, a.z, pc, mc, rowc);
-    const float4* row = J.modes + (size_t)rowc * 4;
-    const float4 c2 = row[2], c3 = row[3];
-    const uint8_t* px = J.rgb + 3 * pc;
-    return !(fabsf((float)px[0] - c2.z) > J.theta_col || fabsf((float)px[1] - c2.w) > J.theta_col ||
-             fabsf((float)px[2] - c3.x) > J.theta_col);
+    ec = (int)below(a.y, (uint32_t)n_elig);
+    const ulonglong2 hw = erec_head(J, (uint32_t)ec);
+    const uint32_t m = below(a.z, erec_total(hw.x));
+    mc = (int)m;
+    const uint64_t word = m < 64 ? hw.y : J.erec[(size_t)ec * J.ew + 1 + (m >> 6)];
+    return (word >> (m & 63)) & 1u;
 }
 
-// stage B: the other two pairs, checks 2 and 3, Kabsch
-template <bool WRITE>
-__device__ __forceinline__ bool hyp_stage_b(const Job& J, int n_elig, int slot, int it, int kc, int pc, int mc,
-                                            uint32_t rowc, Hyp* out)
+// stage B: the other two pairs, checks 2 and 3; with KABSCH also the
+// non-degeneracy of the Kabsch fit, and the hypothesis record is written.
+// The search runs without KABSCH: triplets passing check 3 are rare, and the
+// FP64 eigen-solver would otherwise set the search kernel's register budget.
+template <bool KABSCH>
+__device__ __forceinline__ bool hyp_stage_b(const Job& J, int n_elig, int slot, int it, int kc, int ec, int mc,
+                                            Hyp* out)
 {
 #pragma clang fp contract(off)
     const uint4 b = philox(make_uint4((kTagHyp << 28) | 1u, (uint32_t)slot, (uint32_t)it, 0u), J.key0, J.key1);
-    int qa, qb, ma, mb;
-    uint32_t ra, rb;
-    draw_pair(J, n_elig, b.x, b.z, qa, ma, ra);
-    draw_pair(J, n_elig, b.y, b.w, qb, mb, rb);
+    int pc, qa, qb, ma, mb;
+    float dc, da, db;
+    uint32_t rowc, ra, rb;
+    {
+        const uint64_t h = erec_head(J, (uint32_t)ec).x;
+        pc = erec_pixel(h);
+        dc = erec_depth(h);
+        const uint4 lw = reinterpret_cast<const uint4*>(J.leaves)[pc];
+        const uint2 nw = reinterpret_cast<const uint2*>(J.nmt)[pc];
+        rowc = mode_row_index(J, lw, nw, mc);
+    }
+    draw_pair(J, n_elig, b.x, b.z, qa, ma, da, ra);
+    draw_pair(J, n_elig, b.y, b.w, qb, mb, db, rb);
     // pairs in order 0, 1, 2: pair k* is (pc, rowc), the others (qa, ra), (qb, rb) in increasing order
     const int p0 = kc == 0 ? pc : qa, p1 = kc == 1 ? pc : (kc == 0 ? qa : qb), p2 = kc == 2 ? pc : qb;
+    const float d0 = kc == 0 ? dc : da, d1 = kc == 1 ? dc : (kc == 0 ? da : db), d2 = kc == 2 ? dc : db;
     const uint32_t r0 = kc == 0 ? rowc : ra, r1 = kc == 1 ? rowc : (kc == 0 ? ra : rb), r2 = kc == 2 ? rowc : rb;
     const float4 w0 = J.modes[(size_t)r0 * 4], w1 = J.modes[(size_t)r1 * 4], w2 = J.modes[(size_t)r2 * 4];
     const double xw[3][3] = {{w0.x, w0.y, w0.z}, {w1.x, w1.y, w1.z}, {w2.x, w2.y, w2.z}};
@@ -210,9 +273,9 @@ __device__ __forceinline__ bool hyp_stage_b(const Job& J, int n_elig, int slot, 
     }
     if (dw2[0] < J.min_sq_dist || dw2[1] < J.min_sq_dist || dw2[2] < J.min_sq_dist) return false;
     double xc[3][3];
-    backproject(J.depth[p0], p0 % J.w, p0 / J.w, J.fx, J.fy, J.cx, J.cy, xc[0]);
-    backproject(J.depth[p1], p1 % J.w, p1 / J.w, J.fx, J.fy, J.cx, J.cy, xc[1]);
-    backproject(J.depth[p2], p2 % J.w, p2 / J.w, J.fx, J.fy, J.cx, J.cy, xc[2]);
+    backproject(d0, p0 % J.w, p0 / J.w, J.fx, J.fy, J.cx, J.cy, xc[0]);
+    backproject(d1, p1 % J.w, p1 / J.w, J.fx, J.fy, J.cx, J.cy, xc[1]);
+    backproject(d2, p2 % J.w, p2 / J.w, J.fx, J.fy, J.cx, J.cy, xc[2]);
     bool ok = true;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
@@ -222,6 +285,7 @@ __device__ __forceinline__ bool hyp_stage_b(const Job& J, int n_elig, int slot, 
         if (fabs(sqrt(dc2) - sqrt(dw2[q])) > J.theta_rig) ok = false;
     }
     if (!ok) return false;
+    if (!KABSCH) return true;
     double cc[3], cw[3], A[9];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -236,7 +300,7 @@ __device__ __forceinline__ bool hyp_stage_b(const Job& J, int n_elig, int slot, 
                          + (xc[2][i] - cc[i]) * (xw[2][j] - cw[j]);
     double R[9], t[3];
     if (!rigid_from_cov(A, cc, cw, R, t)) return false;
-    if (WRITE) {
+    {
         for (int i = 0; i < 9; ++i) out->R[i] = (float)R[i];
         for (int i = 0; i < 3; ++i) out->t[i] = (float)t[i];
         out->pix[0] = p0;
@@ -249,12 +313,26 @@ __device__ __forceinline__ bool hyp_stage_b(const Job& J, int n_elig, int slot, 
     return true;
 }
 
+// Tuning of the search kernel: iterations per thread per block, and an
+// optional minimum of resident waves per SIMD (caps registers; 0 = none).
+#ifndef RL_HYP_IPT
+#define RL_HYP_IPT 8
+#endif
+#ifndef RL_HYP_WAVES
+#define RL_HYP_WAVES 0
+#endif
+#if RL_HYP_WAVES > 0
+#define RL_HYP_BOUNDS __launch_bounds__(256, RL_HYP_WAVES)
+#else
+#define RL_HYP_BOUNDS __launch_bounds__(256)
+#endif
+
 // grid.x = Nmax * chunks (chunk-major); a block covers 256 * IPT consecutive
 // iterations of one slot.  A block whose chunk starts after an already-found
 // passing iteration exits early; the minimum stays exact because every lower
 // iteration is always evaluated.
 template <int IPT>
-__global__ __launch_bounds__(256) void k_hyp_search(const Job* __restrict__ jobs, int Nmax)
+__global__ RL_HYP_BOUNDS void k_hyp_search(const Job* __restrict__ jobs, int Nmax)
 {
     const Job& J = jobs[blockIdx.y];
     const int slot = blockIdx.x % Nmax, chunk = blockIdx.x / Nmax;
@@ -263,36 +341,35 @@ __global__ __launch_bounds__(256) void k_hyp_search(const Job* __restrict__ jobs
     if (it0 >= J.I_max) return;
     const int n_elig = J.st->n_elig;
     if (n_elig <= 0) return;
-    if (__hip_atomic_load(&J.hyp_best[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < it0) return;
     __shared__ uint32_t q_it[256 * IPT];   // iteration | k* << 30
-    __shared__ int q_p[256 * IPT];
-    __shared__ uint32_t q_row[256 * IPT];
-    __shared__ int q_m[256 * IPT];
-    __shared__ int s_n, s_best;
+    __shared__ uint32_t q_em[256 * IPT];   // list entry | mode << 24
+    __shared__ int s_n, s_best, s_skip;
+    // The early-exit test reads a value other blocks lower concurrently, so
+    // one thread takes it for the whole block: every wave leaves together,
+    // and no wave runs on without the shared counters initialised.
     if (threadIdx.x == 0) {
         s_n = 0;
         s_best = INT_MAX;
+        s_skip = __hip_atomic_load(&J.hyp_best[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < it0;
     }
     __syncthreads();
+    if (s_skip) return;
 #pragma unroll
     for (int k = 0; k < IPT; ++k) {
         const int it = it0 + k * 256 + threadIdx.x;
-        int kc, pc, mc;
-        uint32_t rowc;
-        if (it < J.I_max && hyp_stage_a(J, n_elig, slot, it, kc, pc, mc, rowc)) {
+        int kc, ec, mc;
+        if (it < J.I_max && hyp_stage_a(J, n_elig, slot, it, kc, ec, mc)) {
             const int q = atomicAdd(&s_n, 1);
             q_it[q] = (uint32_t)it | ((uint32_t)kc << 30);
-            q_p[q] = pc;
-            q_row[q] = rowc;
-            q_m[q] = mc;
+            q_em[q] = (uint32_t)ec | ((uint32_t)mc << 24);
         }
     }
     __syncthreads();
-    const int n = s_n;
+    const int n = min(s_n, 256 * IPT);
     for (int j = threadIdx.x; j < n; j += 256) {
         const int it = (int)(q_it[j] & 0x3FFFFFFFu), kc = (int)(q_it[j] >> 30);
-        if (hyp_stage_b<false>(J, n_elig, slot, it, kc, q_p[j], q_m[j], q_row[j], nullptr))
-            atomicMin(&s_best, it);
+        const int ec = (int)(q_em[j] & 0xFFFFFFu), mc = (int)(q_em[j] >> 24);
+        if (hyp_stage_b<false>(J, n_elig, slot, it, kc, ec, mc, nullptr)) atomicMin(&s_best, it);
     }
     __syncthreads();
     if (threadIdx.x == 0 && s_best != INT_MAX) atomicMin(&J.hyp_best[slot], s_best);
@@ -312,15 +389,21 @@ __global__ __launch_bounds__(256) void k_hyp_finalize(const Job* __restrict__ jo
     }
     hy.iter = -1;
     hy.valid = 0;
-    const int best = J.hyp_best[slot];
+    // hyp_best = first iteration passing checks 1-3.  If its Kabsch fit is
+    // degenerate the answer is the first later iteration passing everything,
+    // found by continuing the scan here (triplets that pass the distance and
+    // rigidity checks and are still collinear are practically absent).
     const int n_elig = J.st->n_elig;
-    int kc, pc, mc;
-    uint32_t rowc;
-    if (best < J.I_max && n_elig > 0 && hyp_stage_a(J, n_elig, slot, best, kc, pc, mc, rowc) &&
-        hyp_stage_b<true>(J, n_elig, slot, best, kc, pc, mc, rowc, &hy)) {
-        hy.iter = best;
-        hy.valid = 1;
-        atomicAdd(&J.st->n_valid, 1);
+    if (n_elig > 0) {
+        for (int it = max(J.hyp_best[slot], 0); it < J.I_max; ++it) {
+            int kc, ec, mc;
+            if (hyp_stage_a(J, n_elig, slot, it, kc, ec, mc) && hyp_stage_b<true>(J, n_elig, slot, it, kc, ec, mc, &hy)) {
+                hy.iter = it;
+                hy.valid = 1;
+                atomicAdd(&J.st->n_valid, 1);
+                break;
+            }
+        }
     }
     J.hyps[slot] = hy;
 }
@@ -771,7 +854,7 @@ hipError_t launch_eligible(const Job* jobs, int njobs, int maxP, hipStream_t st)
     return hipSuccess;
 }
 
-constexpr int kHypIPT = 8;      // iterations per thread in one search block
+constexpr int kHypIPT = RL_HYP_IPT;
 
 hipError_t launch_hyp_search(const Job* jobs, int njobs, int maxN, int maxIters, hipStream_t st)
 {

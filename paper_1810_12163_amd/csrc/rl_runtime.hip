@@ -118,11 +118,20 @@ int score_tile(int rows_per_pixel)
 
 // Per-frame (relocalisation) scratch of one job slot.
 struct FrameLayout {
-    size_t state, result, leaves, nmt, nm, tile_count, eligible, hyp_best, hyps, surv, E, partial,
+    size_t state, result, leaves, nmt, nm, tile_count, eligible, erec, hyp_best, hyps, surv, E, partial,
         I, inl, trace_slots, trace_E, total;
+    int ew;
 };
 
-FrameLayout frame_layout(int maxP, int N, int eta, int rounds, int TP, size_t base)
+// 64-bit words per eligible-pixel record: a header and one colour-check bit
+// per mode of M(u), rounded up to an even count (16-byte aligned records).
+int erec_words(int rows_per_pixel)
+{
+    const int w = 1 + (rows_per_pixel + 63) / 64;
+    return (w + 1) & ~1;
+}
+
+FrameLayout frame_layout(int maxP, int N, int eta, int rounds, int TP, int rows_per_pixel, size_t base)
 {
     Carver c;
     c.cur = base;
@@ -134,6 +143,8 @@ FrameLayout frame_layout(int maxP, int N, int eta, int rounds, int TP, size_t ba
     L.nm = c.take((size_t)maxP);
     L.tile_count = c.take((size_t)((maxP + 255) / 256) * 4);
     L.eligible = c.take((size_t)maxP * 4);
+    L.ew = erec_words(rows_per_pixel);
+    L.erec = c.take((size_t)maxP * L.ew * 8);
     L.hyp_best = c.take((size_t)N * 4);
     L.hyps = c.take((size_t)N * sizeof(Hyp));
     L.surv = c.take((size_t)N * 4);
@@ -399,13 +410,14 @@ RL_API rl_status relocaliser_state_bytes(const rl_params* p, int32_t max_width, 
     if (s != RL_OK) return s;
     if (max_width < 8 || max_height < 8 || max_width % 4 || max_height % 4)
         return fail(RL_EINVAL, "max frame size must be multiples of 4, at least 8x8");
+    if ((long long)max_width * max_height >= kMaxPixels) return fail(RL_EINVAL, "max frame must have fewer than 2^24 pixels");
     if (!persistent || !scratch) return fail(RL_EINVAL, "NULL output");
     const int N = p->max_pose_candidates, eta = p->ransac_inliers_per_iteration;
     const int R = rounds_capacity(*p);
     const int TP = score_tile(p->n_trees * p->max_cluster_count);
     *persistent = persist_layout(*p).total;
     const size_t job = align256(sizeof(Job));
-    const FrameLayout FL = frame_layout(max_width * max_height, N, eta, R, TP, job);
+    const FrameLayout FL = frame_layout(max_width * max_height, N, eta, R, TP, p->n_trees * p->max_cluster_count, job);
     const AdaptLayout AL = adapt_layout(*p, grid_items(max_width, max_height), job + FL.total);
     const ModelLayout ML = model_layout(max_width * max_height, job + FL.total + AL.total);
     *scratch = job + FL.total + AL.total + ML.total;
@@ -453,6 +465,8 @@ static Job make_job(const rl_room* r, char* scr, const FrameLayout& FL, const rl
     J.nm = reinterpret_cast<uint8_t*>(scr + FL.nm);
     J.tile_count = reinterpret_cast<int*>(scr + FL.tile_count);
     J.eligible = reinterpret_cast<int*>(scr + FL.eligible);
+    J.erec = reinterpret_cast<uint64_t*>(scr + FL.erec);
+    J.ew = FL.ew;
     J.hyp_best = reinterpret_cast<int*>(scr + FL.hyp_best);
     J.hyps = reinterpret_cast<Hyp*>(scr + FL.hyps);
     J.surv = reinterpret_cast<int*>(scr + FL.surv);
@@ -544,7 +558,7 @@ RL_API rl_status relocaliser_create(const rl_params* p, const rl_node* host_node
     r->PL = persist_layout(*p);
     r->job_off = 0;
     r->rounds_cap = rounds_capacity(*p);
-    r->FL = frame_layout(r->maxP, r->N, r->eta, r->rounds_cap, r->TP, align256(sizeof(Job)));
+    r->FL = frame_layout(r->maxP, r->N, r->eta, r->rounds_cap, r->TP, r->T * r->M, align256(sizeof(Job)));
     r->AL = adapt_layout(*p, r->G, align256(sizeof(Job)) + r->FL.total);
     r->ML = model_layout(r->maxP, align256(sizeof(Job)) + r->FL.total + r->AL.total);
     r->stream = reinterpret_cast<hipStream_t>(hip_stream);
@@ -871,6 +885,7 @@ RL_API rl_status rl_batch_workspace_bytes(const rl_batch_params* bp, size_t* byt
     if (bp->max_frames < 1 || bp->max_frames > 4096) return fail(RL_EINVAL, "max_frames must be in 1..4096");
     if (bp->max_width < 8 || bp->max_height < 8 || bp->max_width % 4 || bp->max_height % 4)
         return fail(RL_EINVAL, "max frame size must be multiples of 4, at least 8x8");
+    if ((long long)bp->max_width * bp->max_height >= kMaxPixels) return fail(RL_EINVAL, "max frame must have fewer than 2^24 pixels");
     if (bp->max_hypotheses < 1 || bp->max_hypotheses > 4096) return fail(RL_EINVAL, "max_hypotheses must be in 1..4096");
     if (bp->max_eta < 1 || bp->max_eta > 4096) return fail(RL_EINVAL, "max_eta must be in 1..4096");
     if (bp->max_rounds < 1 || bp->max_rounds > 64) return fail(RL_EINVAL, "max_rounds must be in 1..64");
@@ -881,7 +896,7 @@ RL_API rl_status rl_batch_workspace_bytes(const rl_batch_params* bp, size_t* byt
     c.take((size_t)bp->max_frames * sizeof(Job));
     c.take((size_t)bp->max_frames * sizeof(rl_result));
     const FrameLayout FL = frame_layout(bp->max_width * bp->max_height, bp->max_hypotheses, bp->max_eta,
-                                        batch_rounds(*bp), TP, 0);
+                                        batch_rounds(*bp), TP, bp->max_modes_per_pixel, 0);
     *bytes = c.cur + (size_t)bp->max_frames * align256(FL.total);
     return RL_OK;
 }
@@ -905,11 +920,11 @@ RL_API rl_status rl_batch_create(const rl_batch_params* bp, void* ws, void* hip_
     b->jobs_off = c.take((size_t)bp->max_frames * sizeof(Job));
     b->results_off = c.take((size_t)bp->max_frames * sizeof(rl_result));
     const FrameLayout proto = frame_layout(bp->max_width * bp->max_height, bp->max_hypotheses, bp->max_eta,
-                                           batch_rounds(*bp), b->TP, 0);
+                                           batch_rounds(*bp), b->TP, bp->max_modes_per_pixel, 0);
     for (int i = 0; i < bp->max_frames; ++i) {
         const size_t base = c.take(proto.total);
         b->slots.push_back(frame_layout(bp->max_width * bp->max_height, bp->max_hypotheses, bp->max_eta,
-                                        batch_rounds(*bp), b->TP, base));
+                                        batch_rounds(*bp), b->TP, bp->max_modes_per_pixel, base));
     }
     hipError_t e = hipEventCreateWithFlags(&b->ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->job_host), (size_t)bp->max_frames * sizeof(Job), hipHostMallocDefault);

@@ -148,8 +148,9 @@ def test_c3_decimated_stage_matches_oracle(c2, c3_room):
     params = dict(p3, max_pose_candidates=256, max_pose_candidates_after_cull=256,
                   max_relocalisations_to_output=1, final_refine=1)
     ref = _stage_ref(r3, q, params, 21, o.T, o.D, o.M, w.nodes, p3["ref_width"])
-    assert res["rounds"] == ref["rounds"] == 8
-    assert res["n_valid"] == int(ref["hyp_valid"].sum()) and res["winner"] == ref["winner"]
+    print(f"[c3 stage a] valid {res['n_valid']}, rounds {res['rounds']} (oracle {ref['rounds']})", flush=True)
+    assert res["n_valid"] == int(ref["hyp_valid"].sum()) > 0
+    assert res["rounds"] == ref["rounds"] >= 1 and res["winner"] == ref["winner"]
     assert pose_diff(res["pose"], ref["pose"]) < 1e-5
     assert abs(res["energy"] - ref["energy"]) <= 1e-4 * abs(ref["energy"])
 
@@ -161,7 +162,10 @@ def test_c3_wide_stage_keeps_16_and_model_score_matches(c2, c3_room):
     d, c = dev(q)
     res = r3.relocalise(d, c, q.K, request_seed=22, n_hypotheses=4096, n_cull=4096, n_out=16, final_refine=0)
     ref = _stage_ref(r3, q, dict(p3, final_refine=0), 22, o.T, o.D, o.M, w.nodes, p3["ref_width"])
-    assert res["rounds"] == ref["rounds"] == 8 and res["n_out"] == len(ref["out_slots"])
+    print(f"[c3 stage c] valid {res['n_valid']}, rounds {res['rounds']} (oracle {ref['rounds']}), "
+          f"kept {res['n_out']}", flush=True)
+    assert res["n_valid"] == int(ref["hyp_valid"].sum()) > 0
+    assert res["rounds"] == ref["rounds"] and res["n_out"] == len(ref["out_slots"]) >= min(2, res["n_valid"])
     slots, poses = r3.survivors(res["n_out"])
     np.testing.assert_array_equal(slots, ref["out_slots"])
     S = oracle.surfaces_of(w.room)
