@@ -67,7 +67,7 @@ struct Job {
     int* tile_count;          // [ceil(P/256)]
     int* eligible;            // [P]
     uint64_t* erec;           // [P][ew] eligible-pixel records (see erec_* below)
-    int ew;                   // words per record: 2 for |M(u)| <= 64, else 4 or 6
+    int ew;                   // words per record: 1 for |M(u)| <= 56
     int pad1;
     int* hyp_best;            // [N]
     Hyp* hyps;                // [N]
@@ -325,17 +325,24 @@ __device__ __forceinline__ uint32_t count_of(uint2 nw, int t)
     return (uint32_t)(v >> (8 * t)) & 0xFFu;
 }
 
-// Eligible-pixel record, one per entry of the eligible list (ew 64-bit words,
-// ew even so that a record starts on a 16-byte boundary):
-//   word 0: pixel index (bits 0-23) | |M(u)| (bits 24-31) | depth bits (32-63)
-//   words 1..: bit m = outcome of the colour check for mode m of M(u).
+// Eligible-pixel record, one per entry of the eligible list, ew 64-bit words:
+//   word 0: |M(u)| (bits 0-7) and the colour-check bits of modes 0..55 of
+//           M(u) (bits 8-63)
+//   word k >= 1: colour-check bits of modes 56 + 64 (k - 1) ... (only when a
+//           pixel can have more than 56 modes)
 // The colour check of a (pixel, mode) pair does not depend on the iteration
-// that draws it, so it is evaluated once per pair when the list is built and
-// a generation iteration reads one record instead of gathering the pixel,
-// its leaves, its colour and the mode row.
-__device__ __forceinline__ int erec_pixel(uint64_t h) { return (int)((uint32_t)h & 0xFFFFFFu); }
-__device__ __forceinline__ uint32_t erec_total(uint64_t h) { return ((uint32_t)h) >> 24; }
-__device__ __forceinline__ float erec_depth(uint64_t h) { return __uint_as_float((uint32_t)(h >> 32)); }
+// that draws it, so it is evaluated once per pair when the list is built; a
+// generation iteration then reads one 8-byte word instead of gathering the
+// pixel, its leaves, its colour and the mode row, and a frame's table (8 B
+// per eligible pixel) stays resident in one XCD's L2.
+__device__ __forceinline__ uint32_t erec_total(uint64_t h) { return (uint32_t)h & 0xFFu; }
+
+__device__ __forceinline__ bool erec_bit(const uint64_t* rec, uint64_t h, uint32_t m)
+{
+    if (m < 56) return (h >> (8 + m)) & 1u;
+    const uint32_t k = m - 56;
+    return (rec[1 + (k >> 6)] >> (k & 63)) & 1u;
+}
 
 __device__ __forceinline__ int modes_total(uint2 nw, int T)
 {

@@ -118,7 +118,7 @@ __device__ __forceinline__ bool colour_ok(const uint8_t* px, const float4* row, 
              fabsf((float)px[2] - c3.x) > theta);
 }
 
-// Record of eligible pixel p at list position e: header and the colour-check
+// Record of eligible pixel p at list position e: |M(u)| and the colour-check
 // bit of every mode of M(u), in M(u) order.
 __device__ __forceinline__ void write_erec(const Job& J, int e, int p)
 {
@@ -127,20 +127,26 @@ __device__ __forceinline__ void write_erec(const Job& J, int e, int p)
     const uint8_t* px = J.rgb + 3 * p;
     uint64_t* rec = J.erec + (size_t)e * J.ew;
     uint32_t m = 0;
-    uint64_t cur = 0;
+    uint64_t w0 = 0, cur = 0;
     for (int t = 0; t < J.T; ++t) {
         const int c = (int)count_of(nw, t);
         const float4* row = J.modes + ((((size_t)t << J.D) + leaf_of(lw, t)) * (size_t)J.M) * 4;
         for (int j = 0; j < c; ++j, ++m) {
-            cur |= (uint64_t)colour_ok(px, row + 4 * j, J.theta_col) << (m & 63);
-            if ((m & 63) == 63) {
-                rec[1 + (m >> 6)] = cur;
-                cur = 0;
+            const uint64_t b = colour_ok(px, row + 4 * j, J.theta_col) ? 1u : 0u;
+            if (m < 56) {
+                w0 |= b << (8 + m);
+            } else {
+                const uint32_t k = m - 56;
+                cur |= b << (k & 63);
+                if ((k & 63) == 63) {
+                    rec[1 + (k >> 6)] = cur;
+                    cur = 0;
+                }
             }
         }
     }
-    if (m & 63) rec[1 + (m >> 6)] = cur;
-    rec[0] = (uint64_t)((uint32_t)p | (m << 24)) | ((uint64_t)__float_as_uint(J.depth[p]) << 32);
+    if (m > 56 && ((m - 56) & 63)) rec[1 + ((m - 56) >> 6)] = cur;
+    rec[0] = w0 | m;
 }
 
 // Raster-order compaction of eligible pixels over the traversal's tiles, and
@@ -201,22 +207,15 @@ __device__ __forceinline__ uint32_t mode_row_index(const Job& J, uint4 lw, uint2
     return ((((uint32_t)t << J.D) + leaf_of(lw, t)) * (uint32_t)J.M + (uint32_t)m);
 }
 
-// record header (and first mask word) of list entry e
-__device__ __forceinline__ ulonglong2 erec_head(const Job& J, uint32_t e)
-{
-    return *reinterpret_cast<const ulonglong2*>(J.erec + (size_t)e * J.ew);
-}
-
 // pixel, mode, depth and mode row of one pair from its two draws
 __device__ __forceinline__ void draw_pair(const Job& J, int n_elig, uint32_t rp, uint32_t rm, int& p,
                                           int& m, float& d, uint32_t& row)
 {
-    const uint64_t h = erec_head(J, below(rp, (uint32_t)n_elig)).x;
-    p = erec_pixel(h);
-    d = erec_depth(h);
-    m = (int)below(rm, erec_total(h));
+    p = J.eligible[below(rp, (uint32_t)n_elig)];
     const uint4 lw = reinterpret_cast<const uint4*>(J.leaves)[p];
     const uint2 nw = reinterpret_cast<const uint2*>(J.nmt)[p];
+    d = J.depth[p];
+    m = (int)below(rm, (uint32_t)modes_total(nw, J.T));
     row = mode_row_index(J, lw, nw, m);
 }
 
@@ -227,17 +226,46 @@ __device__ __forceinline__ bool hyp_stage_a(const Job& J, int n_elig, int slot, 
     const uint4 a = philox(make_uint4((kTagHyp << 28) | 0u, (uint32_t)slot, (uint32_t)it, 0u), J.key0, J.key1);
     kc = (int)below(a.x, 3u);
     ec = (int)below(a.y, (uint32_t)n_elig);
-    const ulonglong2 hw = erec_head(J, (uint32_t)ec);
-    const uint32_t m = below(a.z, erec_total(hw.x));
+    const uint64_t* rec = J.erec + (size_t)ec * J.ew;
+    const uint64_t h = rec[0];
+    const uint32_t m = below(a.z, erec_total(h));
     mc = (int)m;
-    const uint64_t word = m < 64 ? hw.y : J.erec[(size_t)ec * J.ew + 1 + (m >> 6)];
-    return (word >> (m & 63)) & 1u;
+    return erec_bit(rec, h, m);
 }
 
-// stage B: the other two pairs, checks 2 and 3; with KABSCH also the
-// non-degeneracy of the Kabsch fit, and the hypothesis record is written.
-// The search runs without KABSCH: triplets passing check 3 are rare, and the
-// FP64 eigen-solver would otherwise set the search kernel's register budget.
+// Degeneracy test of the Kabsch fit without an eigen-solver: for a triplet A
+// has rank <= 2, so the eigenvalues l1 >= l2 of A^T A follow from
+// e1 = l1 + l2 = |A|_F^2 and e2 = l1 l2 = sum of squared 2x2 minors of A.
+// The search rejects a triplet only when l2 < 1e-8 l1 holds with a relative
+// margin of 1e-6, far beyond the rounding of either computation, so it never
+// rejects a triplet the exact test (rigid_from_cov) accepts.
+__device__ __forceinline__ bool clearly_degenerate(const double A[9])
+{
+    double e1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) e1 += A[i] * A[i];
+    double e2 = 0.0;
+#pragma unroll
+    for (int r1 = 0; r1 < 2; ++r1)
+#pragma unroll
+        for (int r2 = r1 + 1; r2 < 3; ++r2)
+#pragma unroll
+            for (int c1 = 0; c1 < 2; ++c1)
+#pragma unroll
+                for (int c2 = c1 + 1; c2 < 3; ++c2) {
+                    const double mnr = A[r1 * 3 + c1] * A[r2 * 3 + c2] - A[r1 * 3 + c2] * A[r2 * 3 + c1];
+                    e2 += mnr * mnr;
+                }
+    if (!(e1 > 0.0)) return true;
+    const double l1 = 0.5 * (e1 + sqrt(fmax(e1 * e1 - 4.0 * e2, 0.0)));
+    const double l2 = e2 / l1;
+    return l2 < 1e-8 * (1.0 - 1e-6) * l1;
+}
+
+// stage B: the other two pairs, checks 2 and 3; with KABSCH the Kabsch fit
+// (rejecting degenerate triplets) and the hypothesis record.  The search runs
+// without KABSCH and rejects only clearly degenerate triplets: the FP64
+// eigen-solver would otherwise set the search kernel's register budget.
 template <bool KABSCH>
 __device__ __forceinline__ bool hyp_stage_b(const Job& J, int n_elig, int slot, int it, int kc, int ec, int mc,
                                             Hyp* out)
@@ -248,9 +276,8 @@ __device__ __forceinline__ bool hyp_stage_b(const Job& J, int n_elig, int slot, 
     float dc, da, db;
     uint32_t rowc, ra, rb;
     {
-        const uint64_t h = erec_head(J, (uint32_t)ec).x;
-        pc = erec_pixel(h);
-        dc = erec_depth(h);
+        pc = J.eligible[ec];
+        dc = J.depth[pc];
         const uint4 lw = reinterpret_cast<const uint4*>(J.leaves)[pc];
         const uint2 nw = reinterpret_cast<const uint2*>(J.nmt)[pc];
         rowc = mode_row_index(J, lw, nw, mc);
@@ -285,7 +312,6 @@ __device__ __forceinline__ bool hyp_stage_b(const Job& J, int n_elig, int slot, 
         if (fabs(sqrt(dc2) - sqrt(dw2[q])) > J.theta_rig) ok = false;
     }
     if (!ok) return false;
-    if (!KABSCH) return true;
     double cc[3], cw[3], A[9];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -298,6 +324,7 @@ __device__ __forceinline__ bool hyp_stage_b(const Job& J, int n_elig, int slot, 
         for (int j = 0; j < 3; ++j)
             A[i * 3 + j] = (xc[0][i] - cc[i]) * (xw[0][j] - cw[j]) + (xc[1][i] - cc[i]) * (xw[1][j] - cw[j])
                          + (xc[2][i] - cc[i]) * (xw[2][j] - cw[j]);
+    if (!KABSCH) return !clearly_degenerate(A);
     double R[9], t[3];
     if (!rigid_from_cov(A, cc, cw, R, t)) return false;
     {
@@ -327,15 +354,32 @@ __device__ __forceinline__ bool hyp_stage_b(const Job& J, int n_elig, int slot, 
 #define RL_HYP_BOUNDS __launch_bounds__(256)
 #endif
 
-// grid.x = Nmax * chunks (chunk-major); a block covers 256 * IPT consecutive
-// iterations of one slot.  A block whose chunk starts after an already-found
-// passing iteration exits early; the minimum stays exact because every lower
-// iteration is always evaluated.
-template <int IPT>
-__global__ RL_HYP_BOUNDS void k_hyp_search(const Job* __restrict__ jobs, int Nmax)
+// XCD-aware placement of a one-dimensional grid over (job, x < X): workgroup
+// w is dispatched to XCD w % 8.  Jobs are dealt round-robin to groups of s
+// XCDs (s = 8 for one job, 1 for eight or more), so that each XCD's L2 holds
+// the tables of the few jobs it works on instead of every XCD caching all.
+// Returns false for the grid's padding.
+__device__ __forceinline__ bool xcd_place(int w, int X, int njobs, int s, int& job, int& x)
 {
-    const Job& J = jobs[blockIdx.y];
-    const int slot = blockIdx.x % Nmax, chunk = blockIdx.x / Nmax;
+    const int e = w & 7, groups = 8 / s;
+    const int q = (w >> 3) * s + e % s;
+    const int js = q / X;
+    x = q - js * X;
+    job = e / s + groups * js;
+    return job < njobs;
+}
+
+// Per job, x = chunk * Nmax + slot (chunk-major); a block covers 256 * IPT
+// consecutive iterations of one slot.  A block whose chunk starts after an
+// already-found passing iteration exits early; the minimum stays exact
+// because every lower iteration is always evaluated.
+template <int IPT>
+__global__ RL_HYP_BOUNDS void k_hyp_search(const Job* __restrict__ jobs, int Nmax, int njobs, int X, int s)
+{
+    int job, x;
+    if (!xcd_place((int)blockIdx.x, X, njobs, s, job, x)) return;
+    const Job& J = jobs[job];
+    const int slot = x % Nmax, chunk = x / Nmax;
     if (slot >= J.N) return;
     const int it0 = chunk * 256 * IPT;
     if (it0 >= J.I_max) return;
@@ -859,9 +903,12 @@ constexpr int kHypIPT = RL_HYP_IPT;
 hipError_t launch_hyp_search(const Job* jobs, int njobs, int maxN, int maxIters, hipStream_t st)
 {
     const long long chunks = (maxIters + 256 * kHypIPT - 1) / (256 * kHypIPT);
-    const long long gx = chunks * (long long)maxN;
-    if (gx > 0x7fffffffLL) return hipErrorInvalidValue;
-    k_hyp_search<kHypIPT><<<dim3((unsigned)gx, njobs), dim3(256), 0, st>>>(jobs, maxN);
+    const long long X = chunks * (long long)maxN;
+    const int s = njobs >= 8 ? 1 : njobs >= 4 ? 2 : njobs >= 2 ? 4 : 8;
+    const long long per_group = X * ((njobs + 8 / s - 1) / (8 / s));
+    const long long grid = 8 * ((per_group + s - 1) / s);
+    if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
+    k_hyp_search<kHypIPT><<<dim3((unsigned)grid), dim3(256), 0, st>>>(jobs, maxN, njobs, (int)X, s);
     RL_CHECK_LAUNCH();
     return hipSuccess;
 }

@@ -123,12 +123,11 @@ struct FrameLayout {
     int ew;
 };
 
-// 64-bit words per eligible-pixel record: a header and one colour-check bit
-// per mode of M(u), rounded up to an even count (16-byte aligned records).
+// 64-bit words per eligible-pixel record: |M(u)| and 56 colour-check bits in
+// the first, 64 more bits per further word.
 int erec_words(int rows_per_pixel)
 {
-    const int w = 1 + (rows_per_pixel + 63) / 64;
-    return (w + 1) & ~1;
+    return 1 + (std::max(rows_per_pixel - 56, 0) + 63) / 64;
 }
 
 FrameLayout frame_layout(int maxP, int N, int eta, int rounds, int TP, int rows_per_pixel, size_t base)
