@@ -66,6 +66,7 @@ struct Job {
     uint8_t* nm;              // [P] |M(u)|
     int* tile_count;          // [ceil(P/256)]
     int* eligible;            // [P]
+    uint4* ecold;             // [P][2] per list entry: (pixel, depth bits, mode counts), leaves
     uint64_t* erec;           // [P][ew] eligible-pixel records (see erec_* below)
     int ew;                   // words per record: 1 for |M(u)| <= 56
     int pad1;
@@ -139,6 +140,39 @@ __device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1)
     return c;
 }
 
+// Load through the global address space.  Pointers read from the job table
+// are generic to the compiler; generic (flat) loads wait on both the memory
+// and LDS counters and cannot be reordered around LDS stores, which
+// serialises independent gathers.
+template <class T>
+__device__ __forceinline__ T ldg(const T* p)
+{
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+// HIP's vector structs would be copied through a generic reference: load
+// them as native vectors instead.
+typedef uint32_t rl_u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t rl_u32x4 __attribute__((ext_vector_type(4)));
+typedef float rl_f32x4 __attribute__((ext_vector_type(4)));
+template <>
+__device__ __forceinline__ uint2 ldg<uint2>(const uint2* p)
+{
+    const rl_u32x2 v = *(const __attribute__((address_space(1))) rl_u32x2*)p;
+    return make_uint2(v.x, v.y);
+}
+template <>
+__device__ __forceinline__ uint4 ldg<uint4>(const uint4* p)
+{
+    const rl_u32x4 v = *(const __attribute__((address_space(1))) rl_u32x4*)p;
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+template <>
+__device__ __forceinline__ float4 ldg<float4>(const float4* p)
+{
+    const rl_f32x4 v = *(const __attribute__((address_space(1))) rl_f32x4*)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
 // integer in [0, n): floor(r * n / 2^32)
 __device__ __forceinline__ uint32_t below(uint32_t r, uint32_t n) { return __umulhi(r, n); }
 
@@ -166,14 +200,14 @@ __device__ __forceinline__ void route(const float4* __restrict__ nodes, int NT, 
 {
     const float inv = 1.0f / d;
     const int pc = y * w + x;
-    const float cc[3] = {(float)rgb[3 * pc], (float)rgb[3 * pc + 1], (float)rgb[3 * pc + 2]};
+    const float cc[3] = {(float)ldg(rgb + 3 * pc), (float)ldg(rgb + 3 * pc + 1), (float)ldg(rgb + 3 * pc + 2)};
     int idx[T];
 #pragma unroll
     for (int t = 0; t < T; ++t) idx[t] = 0;
     for (int lvl = 0; lvl < D; ++lvl) {
         float4 nd[T];
 #pragma unroll
-        for (int t = 0; t < T; ++t) nd[t] = nodes[t * NT + idx[t]];
+        for (int t = 0; t < T; ++t) nd[t] = ldg(nodes + t * NT + idx[t]);
 #pragma unroll
         for (int t = 0; t < T; ++t) {
             float fox = rintf((nd[t].x * s) * inv);
@@ -184,15 +218,13 @@ __device__ __forceinline__ void route(const float4* __restrict__ nodes, int NT, 
             const int qy = min(max(y + (int)foy, 0), h - 1);
             const int q = qy * w + qx;
             const uint32_t kind = __float_as_uint(nd[t].w);
-            float f;
-            if (kind == 0u) {
-                f = d - depth[q];
-            } else {
-                // nodes are validated at creation (kind <= 3); the clamp keeps
-                // this read inside the pixel whatever the device memory holds
-                const uint32_t c = min(kind - 1u, 2u);
-                f = (c == 0u ? cc[0] : c == 1u ? cc[1] : cc[2]) - (float)rgb[3 * q + c];
-            }
+            // both probes are read (no divergent branch around the loads);
+            // kinds are validated at creation (<= 3) and the clamp keeps the
+            // colour read inside the pixel whatever the device memory holds
+            const uint32_t c = min(kind - 1u, 2u);
+            const float dq = ldg(depth + q);
+            const float cq = (float)ldg(rgb + 3 * q + c);
+            const float f = kind == 0u ? d - dq : (c == 0u ? cc[0] : c == 1u ? cc[1] : cc[2]) - cq;
             idx[t] = 2 * idx[t] + 1 + (f >= nd[t].z ? 1 : 0);
         }
     }
@@ -341,7 +373,7 @@ __device__ __forceinline__ bool erec_bit(const uint64_t* rec, uint64_t h, uint32
 {
     if (m < 56) return (h >> (8 + m)) & 1u;
     const uint32_t k = m - 56;
-    return (rec[1 + (k >> 6)] >> (k & 63)) & 1u;
+    return (ldg(rec + 1 + (k >> 6)) >> (k & 63)) & 1u;
 }
 
 __device__ __forceinline__ int modes_total(uint2 nw, int T)

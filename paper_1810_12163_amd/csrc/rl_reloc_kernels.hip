@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256) void k_traverse(const Job* __restrict__ jobs)
     bool elig = false;
     if (p < P) {
         const int x = p % w, y = p / w;
-        const float d = J.depth[p];
+        const float d = ldg(J.depth + p);
         uint16_t lf[8];
         uint8_t nmt[8];
 #pragma unroll
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(256) void k_traverse(const Job* __restrict__ jobs)
 #pragma unroll
             for (int t = 0; t < T; ++t) {
                 lf[t] = (uint16_t)leaf[t];
-                const int c = J.nmodes[((size_t)t << J.D) + leaf[t]];
+                const int c = ldg(J.nmodes + ((size_t)t << J.D) + leaf[t]);
                 nmt[t] = (uint8_t)c;
                 total += c;
             }
@@ -111,20 +111,19 @@ __global__ __launch_bounds__(256) void k_traverse(const Job* __restrict__ jobs)
 
 // Colour check of pair (pixel, mode) (check 1 of Sec. 3.2.3): L-infinity
 // distance between the pixel's colour and the mode's mean colour, float32.
-__device__ __forceinline__ bool colour_ok(const uint8_t* px, const float4* row, float theta)
+__device__ __forceinline__ bool colour_ok(const float px[3], const float4* row, float theta)
 {
-    const float4 c2 = row[2], c3 = row[3];
-    return !(fabsf((float)px[0] - c2.z) > theta || fabsf((float)px[1] - c2.w) > theta ||
-             fabsf((float)px[2] - c3.x) > theta);
+    const float4 c2 = ldg(row + 2), c3 = ldg(row + 3);
+    return !(fabsf(px[0] - c2.z) > theta || fabsf(px[1] - c2.w) > theta || fabsf(px[2] - c3.x) > theta);
 }
 
 // Record of eligible pixel p at list position e: |M(u)| and the colour-check
 // bit of every mode of M(u), in M(u) order.
 __device__ __forceinline__ void write_erec(const Job& J, int e, int p)
 {
-    const uint4 lw = reinterpret_cast<const uint4*>(J.leaves)[p];
-    const uint2 nw = reinterpret_cast<const uint2*>(J.nmt)[p];
-    const uint8_t* px = J.rgb + 3 * p;
+    const uint4 lw = ldg(reinterpret_cast<const uint4*>(J.leaves) + p);
+    const uint2 nw = ldg(reinterpret_cast<const uint2*>(J.nmt) + p);
+    const float px[3] = {(float)ldg(J.rgb + 3 * p), (float)ldg(J.rgb + 3 * p + 1), (float)ldg(J.rgb + 3 * p + 2)};
     uint64_t* rec = J.erec + (size_t)e * J.ew;
     uint32_t m = 0;
     uint64_t w0 = 0, cur = 0;
@@ -169,12 +168,17 @@ __global__ __launch_bounds__(256) void k_eligible(const Job* __restrict__ jobs)
     }
     const int base = s_red[0];
     const int p = blockIdx.x * 256 + threadIdx.x;
-    const bool e = p < P && J.nm[p] > 0;
+    const bool e = p < P && ldg(J.nm + p) > 0;
     int tot;
     const int pre = block_prefix256(e, s_wave, &tot);
     if (e) {
-        J.eligible[base + pre] = p;
-        write_erec(J, base + pre, p);
+        const int k = base + pre;
+        J.eligible[k] = p;
+        const uint4 lw = ldg(reinterpret_cast<const uint4*>(J.leaves) + p);
+        const uint2 nw = ldg(reinterpret_cast<const uint2*>(J.nmt) + p);
+        J.ecold[2 * k] = make_uint4((uint32_t)p, __float_as_uint(ldg(J.depth + p)), nw.x, nw.y);
+        J.ecold[2 * k + 1] = lw;
+        write_erec(J, k, p);
     }
     if ((int)blockIdx.x == ntiles - 1 && threadIdx.x == 0) J.st->n_elig = base + tot;
 }
@@ -207,16 +211,59 @@ __device__ __forceinline__ uint32_t mode_row_index(const Job& J, uint4 lw, uint2
     return ((((uint32_t)t << J.D) + leaf_of(lw, t)) * (uint32_t)J.M + (uint32_t)m);
 }
 
-// pixel, mode, depth and mode row of one pair from its two draws
-__device__ __forceinline__ void draw_pair(const Job& J, int n_elig, uint32_t rp, uint32_t rm, int& p,
-                                          int& m, float& d, uint32_t& row)
+// One (pixel, mode) pair of a triplet, from list entry e and mode index m of
+// M(u): the entry's 32-byte record holds the pixel, its depth and its leaf
+// record, so the pair costs two gathers (record, mode row).
+struct Pair {
+    int p, m;
+    float d;
+    uint32_t row;
+    double xw[3], xc[3];
+};
+
+__device__ __forceinline__ void pair_at(const Job& J, uint32_t e, int m, Pair& q)
 {
-    p = J.eligible[below(rp, (uint32_t)n_elig)];
-    const uint4 lw = reinterpret_cast<const uint4*>(J.leaves)[p];
-    const uint2 nw = reinterpret_cast<const uint2*>(J.nmt)[p];
-    d = J.depth[p];
-    m = (int)below(rm, (uint32_t)modes_total(nw, J.T));
-    row = mode_row_index(J, lw, nw, m);
+    const uint4 c0 = ldg(J.ecold + 2 * e), c1 = ldg(J.ecold + 2 * e + 1);
+    q.p = (int)c0.x;
+    q.d = __uint_as_float(c0.y);
+    q.m = m;
+    q.row = mode_row_index(J, c1, make_uint2(c0.z, c0.w), m);
+    const float4 w = ldg(J.modes + (size_t)q.row * 4);
+    q.xw[0] = w.x;
+    q.xw[1] = w.y;
+    q.xw[2] = w.z;
+}
+
+// the pair drawn by (rp, rm): entry from rp, mode from rm over |M(u)|
+__device__ __forceinline__ void draw_pair(const Job& J, int n_elig, uint32_t rp, uint32_t rm, Pair& q)
+{
+    const uint32_t e = below(rp, (uint32_t)n_elig);
+    const uint4 c0 = ldg(J.ecold + 2 * e);
+    const uint2 nw = make_uint2(c0.z, c0.w);
+    pair_at(J, e, (int)below(rm, (uint32_t)modes_total(nw, J.T)), q);
+}
+
+__device__ __forceinline__ void pair_backproject(const Job& J, Pair& q)
+{
+    backproject(q.d, q.p % J.w, q.p / J.w, J.fx, J.fy, J.cx, J.cy, q.xc);
+}
+
+// checks 2 and 3 on one pair of pairs: world distance^2 >= min, and the
+// camera and world distances agree within the rigidity tolerance
+__device__ __forceinline__ bool world_far(const Job& J, const Pair& a, const Pair& b, double& dw2)
+{
+#pragma clang fp contract(off)
+    const double dx = a.xw[0] - b.xw[0], dy = a.xw[1] - b.xw[1], dz = a.xw[2] - b.xw[2];
+    dw2 = dx * dx + dy * dy + dz * dz;
+    return !(dw2 < J.min_sq_dist);
+}
+
+__device__ __forceinline__ bool rigid_pair(const Job& J, const Pair& a, const Pair& b, double dw2)
+{
+#pragma clang fp contract(off)
+    const double dx = a.xc[0] - b.xc[0], dy = a.xc[1] - b.xc[1], dz = a.xc[2] - b.xc[2];
+    const double dc2 = dx * dx + dy * dy + dz * dz;
+    return !(fabs(sqrt(dc2) - sqrt(dw2)) > J.theta_rig);
 }
 
 // stage A: the colour check of pair k* (list entry ec, mode mc of M(u))
@@ -226,8 +273,8 @@ __device__ __forceinline__ bool hyp_stage_a(const Job& J, int n_elig, int slot, 
     const uint4 a = philox(make_uint4((kTagHyp << 28) | 0u, (uint32_t)slot, (uint32_t)it, 0u), J.key0, J.key1);
     kc = (int)below(a.x, 3u);
     ec = (int)below(a.y, (uint32_t)n_elig);
-    const uint64_t* rec = J.erec + (size_t)ec * J.ew;
-    const uint64_t h = rec[0];
+    const uint64_t* rec = J.erec + (uint32_t)ec * (uint32_t)J.ew;
+    const uint64_t h = ldg(rec);
     const uint32_t m = below(a.z, erec_total(h));
     mc = (int)m;
     return erec_bit(rec, h, m);
@@ -266,52 +313,34 @@ __device__ __forceinline__ bool clearly_degenerate(const double A[9])
 // (rejecting degenerate triplets) and the hypothesis record.  The search runs
 // without KABSCH and rejects only clearly degenerate triplets: the FP64
 // eigen-solver would otherwise set the search kernel's register budget.
+// The checks are a conjunction over the three unordered pairs of pairs, so
+// they are evaluated pair by pair and the third pair is only gathered when
+// the first two agree; each quantity is computed as in the canonical order
+// (a squared difference does not depend on its sign).
 template <bool KABSCH>
 __device__ __forceinline__ bool hyp_stage_b(const Job& J, int n_elig, int slot, int it, int kc, int ec, int mc,
                                             Hyp* out)
 {
 #pragma clang fp contract(off)
     const uint4 b = philox(make_uint4((kTagHyp << 28) | 1u, (uint32_t)slot, (uint32_t)it, 0u), J.key0, J.key1);
-    int pc, qa, qb, ma, mb;
-    float dc, da, db;
-    uint32_t rowc, ra, rb;
-    {
-        pc = J.eligible[ec];
-        dc = J.depth[pc];
-        const uint4 lw = reinterpret_cast<const uint4*>(J.leaves)[pc];
-        const uint2 nw = reinterpret_cast<const uint2*>(J.nmt)[pc];
-        rowc = mode_row_index(J, lw, nw, mc);
-    }
-    draw_pair(J, n_elig, b.x, b.z, qa, ma, da, ra);
-    draw_pair(J, n_elig, b.y, b.w, qb, mb, db, rb);
-    // pairs in order 0, 1, 2: pair k* is (pc, rowc), the others (qa, ra), (qb, rb) in increasing order
-    const int p0 = kc == 0 ? pc : qa, p1 = kc == 1 ? pc : (kc == 0 ? qa : qb), p2 = kc == 2 ? pc : qb;
-    const float d0 = kc == 0 ? dc : da, d1 = kc == 1 ? dc : (kc == 0 ? da : db), d2 = kc == 2 ? dc : db;
-    const uint32_t r0 = kc == 0 ? rowc : ra, r1 = kc == 1 ? rowc : (kc == 0 ? ra : rb), r2 = kc == 2 ? rowc : rb;
-    const float4 w0 = J.modes[(size_t)r0 * 4], w1 = J.modes[(size_t)r1 * 4], w2 = J.modes[(size_t)r2 * 4];
-    const double xw[3][3] = {{w0.x, w0.y, w0.z}, {w1.x, w1.y, w1.z}, {w2.x, w2.y, w2.z}};
-    const int PA[3] = {0, 0, 1}, PB[3] = {1, 2, 2};
-    double dw2[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        const double dx = xw[PA[q]][0] - xw[PB[q]][0], dy = xw[PA[q]][1] - xw[PB[q]][1],
-                     dz = xw[PA[q]][2] - xw[PB[q]][2];
-        dw2[q] = dx * dx + dy * dy + dz * dz;
-    }
-    if (dw2[0] < J.min_sq_dist || dw2[1] < J.min_sq_dist || dw2[2] < J.min_sq_dist) return false;
-    double xc[3][3];
-    backproject(d0, p0 % J.w, p0 / J.w, J.fx, J.fy, J.cx, J.cy, xc[0]);
-    backproject(d1, p1 % J.w, p1 / J.w, J.fx, J.fy, J.cx, J.cy, xc[1]);
-    backproject(d2, p2 % J.w, p2 / J.w, J.fx, J.fy, J.cx, J.cy, xc[2]);
-    bool ok = true;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        const double dx = xc[PA[q]][0] - xc[PB[q]][0], dy = xc[PA[q]][1] - xc[PB[q]][1],
-                     dz = xc[PA[q]][2] - xc[PB[q]][2];
-        const double dc2 = dx * dx + dy * dy + dz * dz;
-        if (fabs(sqrt(dc2) - sqrt(dw2[q])) > J.theta_rig) ok = false;
-    }
-    if (!ok) return false;
+    Pair pk, pa, pb;
+    pair_at(J, (uint32_t)ec, mc, pk);
+    draw_pair(J, n_elig, b.x, b.z, pa);
+    double dka, dkb, dab;
+    if (!world_far(J, pk, pa, dka)) return false;
+    pair_backproject(J, pk);
+    pair_backproject(J, pa);
+    if (!rigid_pair(J, pk, pa, dka)) return false;
+    draw_pair(J, n_elig, b.y, b.w, pb);
+    if (!world_far(J, pk, pb, dkb) || !world_far(J, pa, pb, dab)) return false;
+    pair_backproject(J, pb);
+    if (!rigid_pair(J, pk, pb, dkb) || !rigid_pair(J, pa, pb, dab)) return false;
+    // canonical order: pair k* at position kc, the other two in draw order
+    const Pair& q0 = kc == 0 ? pk : pa;
+    const Pair& q1 = kc == 1 ? pk : (kc == 0 ? pa : pb);
+    const Pair& q2 = kc == 2 ? pk : pb;
+    const double* xc[3] = {q0.xc, q1.xc, q2.xc};
+    const double* xw[3] = {q0.xw, q1.xw, q2.xw};
     double cc[3], cw[3], A[9];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -327,16 +356,14 @@ __device__ __forceinline__ bool hyp_stage_b(const Job& J, int n_elig, int slot, 
     if (!KABSCH) return !clearly_degenerate(A);
     double R[9], t[3];
     if (!rigid_from_cov(A, cc, cw, R, t)) return false;
-    {
-        for (int i = 0; i < 9; ++i) out->R[i] = (float)R[i];
-        for (int i = 0; i < 3; ++i) out->t[i] = (float)t[i];
-        out->pix[0] = p0;
-        out->pix[1] = p1;
-        out->pix[2] = p2;
-        out->mode[0] = kc == 0 ? mc : ma;
-        out->mode[1] = kc == 1 ? mc : (kc == 0 ? ma : mb);
-        out->mode[2] = kc == 2 ? mc : mb;
-    }
+    for (int i = 0; i < 9; ++i) out->R[i] = (float)R[i];
+    for (int i = 0; i < 3; ++i) out->t[i] = (float)t[i];
+    out->pix[0] = q0.p;
+    out->pix[1] = q1.p;
+    out->pix[2] = q2.p;
+    out->mode[0] = q0.m;
+    out->mode[1] = q1.m;
+    out->mode[2] = q2.m;
     return true;
 }
 
@@ -398,14 +425,27 @@ __global__ RL_HYP_BOUNDS void k_hyp_search(const Job* __restrict__ jobs, int Nma
     }
     __syncthreads();
     if (s_skip) return;
+    // stage A in two passes: all IPT draws and record loads are issued before
+    // any of them is consumed, so the gathers overlap
+    uint32_t ka[IPT], ea[IPT], za[IPT];
+    uint64_t ha[IPT];
 #pragma unroll
     for (int k = 0; k < IPT; ++k) {
-        const int it = it0 + k * 256 + threadIdx.x;
-        int kc, ec, mc;
-        if (it < J.I_max && hyp_stage_a(J, n_elig, slot, it, kc, ec, mc)) {
+        const uint32_t it = (uint32_t)(it0 + k * 256 + (int)threadIdx.x);
+        const uint4 a = philox(make_uint4((kTagHyp << 28) | 0u, (uint32_t)slot, it, 0u), J.key0, J.key1);
+        ka[k] = below(a.x, 3u);
+        ea[k] = below(a.y, (uint32_t)n_elig);
+        za[k] = a.z;
+        ha[k] = ldg(J.erec + ea[k] * (uint32_t)J.ew);
+    }
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+        const int it = it0 + k * 256 + (int)threadIdx.x;
+        const uint32_t m = below(za[k], erec_total(ha[k]));
+        if (it < J.I_max && erec_bit(J.erec + ea[k] * (uint32_t)J.ew, ha[k], m)) {
             const int q = atomicAdd(&s_n, 1);
-            q_it[q] = (uint32_t)it | ((uint32_t)kc << 30);
-            q_em[q] = (uint32_t)ec | ((uint32_t)mc << 24);
+            q_it[q] = (uint32_t)it | (ka[k] << 30);
+            q_em[q] = ea[k] | (m << 24);
         }
     }
     __syncthreads();
@@ -499,11 +539,13 @@ __global__ __launch_bounds__(256) void k_score(const Job* __restrict__ jobs, int
         const int k = k0 + tid;
         const uint4 rb = philox(make_uint4(kTagScore << 28, (uint32_t)round, (uint32_t)(k >> 2), 0u), J.key0, J.key1);
         const uint32_t rv = (k & 3) == 0 ? rb.x : (k & 3) == 1 ? rb.y : (k & 3) == 2 ? rb.z : rb.w;
-        const int p = J.eligible[below(rv, (uint32_t)J.st->n_elig)];
+        const uint32_t e = below(rv, (uint32_t)J.st->n_elig);
+        const uint4 c0 = ldg(J.ecold + 2 * e);
+        const int p = (int)c0.x;
         if (htile == 0) J.I[round * J.eta + k] = p;
-        backproject(J.depth[p], p % J.w, p / J.w, J.fx, J.fy, J.cx, J.cy, s_x[tid]);
-        s_lw[tid] = reinterpret_cast<const uint4*>(J.leaves)[p];
-        s_nw[tid] = reinterpret_cast<const uint2*>(J.nmt)[p];
+        backproject(__uint_as_float(c0.y), p % J.w, p / J.w, J.fx, J.fy, J.cx, J.cy, s_x[tid]);
+        s_lw[tid] = ldg(J.ecold + 2 * e + 1);
+        s_nw[tid] = make_uint2(c0.z, c0.w);
     }
     __syncthreads();
     if (tid == 0) {
@@ -520,7 +562,7 @@ __global__ __launch_bounds__(256) void k_score(const Job* __restrict__ jobs, int
         int i = 0;
         while (s_off[i + 1] <= j) ++i;
         const float4* row = mode_row(J.modes, J.T, J.D, J.M, s_lw[i], s_nw[i], j - s_off[i]);
-        const float4 a = row[0], b = row[1], c = row[2];
+        const float4 a = ldg(row), b = ldg(row + 1), c = ldg(row + 2);
         double* o = s_rows + 9 * j;
         o[0] = a.x; o[1] = a.y; o[2] = a.z;
         o[3] = b.x; o[4] = b.y; o[5] = b.z; o[6] = b.w; o[7] = c.x; o[8] = c.y;

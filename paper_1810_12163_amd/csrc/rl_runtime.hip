@@ -118,7 +118,7 @@ int score_tile(int rows_per_pixel)
 
 // Per-frame (relocalisation) scratch of one job slot.
 struct FrameLayout {
-    size_t state, result, leaves, nmt, nm, tile_count, eligible, erec, hyp_best, hyps, surv, E, partial,
+    size_t state, result, leaves, nmt, nm, tile_count, eligible, ecold, erec, hyp_best, hyps, surv, E, partial,
         I, inl, trace_slots, trace_E, total;
     int ew;
 };
@@ -142,6 +142,7 @@ FrameLayout frame_layout(int maxP, int N, int eta, int rounds, int TP, int rows_
     L.nm = c.take((size_t)maxP);
     L.tile_count = c.take((size_t)((maxP + 255) / 256) * 4);
     L.eligible = c.take((size_t)maxP * 4);
+    L.ecold = c.take((size_t)maxP * 32);
     L.ew = erec_words(rows_per_pixel);
     L.erec = c.take((size_t)maxP * L.ew * 8);
     L.hyp_best = c.take((size_t)N * 4);
@@ -464,6 +465,7 @@ static Job make_job(const rl_room* r, char* scr, const FrameLayout& FL, const rl
     J.nm = reinterpret_cast<uint8_t*>(scr + FL.nm);
     J.tile_count = reinterpret_cast<int*>(scr + FL.tile_count);
     J.eligible = reinterpret_cast<int*>(scr + FL.eligible);
+    J.ecold = reinterpret_cast<uint4*>(scr + FL.ecold);
     J.erec = reinterpret_cast<uint64_t*>(scr + FL.erec);
     J.ew = FL.ew;
     J.hyp_best = reinterpret_cast<int*>(scr + FL.hyp_best);
