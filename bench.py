@@ -44,6 +44,34 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_source_hash() -> str:
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1810_12163_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(name: str):
+    """HBM bytes per launch from a committed counter summary under profiles/
+    (FETCH_SIZE and WRITE_SIZE scaled by a copy kernel's readings), or None
+    when the summary was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    taken_on, traffic = None, None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("# kernel sources sha256"):
+                taken_on = line.split()[-1]
+            elif line.startswith("traffic_bytes_per_launch"):
+                traffic = float(line.split()[1])
+    return traffic if taken_on == kernel_source_hash() else None
+
+
 def percentile(v, q):
     return float(np.percentile(np.asarray(v, dtype=np.float64), q))
 
@@ -199,10 +227,13 @@ def main():
     kavg = float(np.mean(kern_ms)) * 1e-3
     if timer == rl.TIMER_HYP_SEARCH:
         ops = iters * HYP_ITER_OPS
+        traffic = profiled_traffic("k_hyp_search_640x480_batch64_counters.txt") if B == 64 else None
         roof = dict(kernel="k_hyp_search", bound="alu", achieved=ops / kavg / 1e12,
                     peak=MI355X_VALU_OPS / 1e12, unit="TOP/s (VALU lane-ops)",
-                    frac=ops / kavg / MI355X_VALU_OPS, traffic=None, launch_ms=kavg * 1e3,
-                    work=f"{iters} generation iterations x {HYP_ITER_OPS} ops")
+                    frac=ops / kavg / MI355X_VALU_OPS, traffic=traffic, launch_ms=kavg * 1e3,
+                    work=f"{iters} generation iterations x {HYP_ITER_OPS} ops",
+                    traffic_unit="HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                    traffic_GBps=(traffic / kavg / 1e9) if traffic else None)
     elif timer == rl.TIMER_TRAVERSE:
         by = node_tests * NODE_TEST_BYTES
         roof = dict(kernel="k_traverse", bound="hbm", achieved=by / kavg / 1e9, peak=MI355X_HBM / 1e9,
