@@ -20,8 +20,7 @@ constexpr int kMaxTrees = 8;
 constexpr long long kMaxPixels = 1LL << 24;   // pixel indices are packed in 24 bits
 constexpr int kLeafNone = 0xFFFF;
 constexpr uint32_t kTagRes = 1, kTagHyp = 2, kTagScore = 3;
-constexpr int kScoreLdsBytes = 64 * 1024;     // mode rows staged per scoring block
-constexpr int kMaxScoreTile = 16;             // pixels per scoring block
+constexpr int kScoreTile = 8;                 // pixels per scoring wave
 
 struct JobState {
     int n_elig;
@@ -123,6 +122,10 @@ struct RqsArgs {
 };
 
 // ---------------------------------------------------------------------------
+#ifndef RL_PHILOX_WIDE
+#define RL_PHILOX_WIDE 0
+#endif
+
 // Philox4x32-10 (Salmon et al., SC'11): two 32x32->64 multiplies per round
 // on counter words 0 and 2, round keys bumped by the Weyl constants.
 __device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1)
@@ -133,9 +136,16 @@ __device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1)
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
+#if RL_PHILOX_WIDE
+        // one 32x32->64 multiply each (v_mad_u64_u32): fewer instructions,
+        // more registers held across an unrolled search
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+#else
         const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
         const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
         c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+#endif
     }
     return c;
 }

@@ -370,7 +370,7 @@ __device__ __forceinline__ bool hyp_stage_b(const Job& J, int n_elig, int slot, 
 // Tuning of the search kernel: iterations per thread per block, and an
 // optional minimum of resident waves per SIMD (caps registers; 0 = none).
 #ifndef RL_HYP_IPT
-#define RL_HYP_IPT 8
+#define RL_HYP_IPT 4
 #endif
 #ifndef RL_HYP_WAVES
 #define RL_HYP_WAVES 0
@@ -515,88 +515,69 @@ __global__ __launch_bounds__(256) void k_ransac_init(const Job* __restrict__ job
 }
 
 // ------------------------------------------------------------------------
-// One scoring round: grid.x = ptiles * htiles.  A block stages TP of this
-// round's pixels (back-projection and every mode of M(u) in FP64) in LDS and
-// each thread accumulates one survivor's Eq. 5 terms over them; all lanes
-// read the same mode row, so LDS reads are broadcasts.
-__global__ __launch_bounds__(256) void k_score(const Job* __restrict__ jobs, int round, int nptiles)
+// One scoring round: grid.x = ptiles * htiles, one wave per block.  The wave
+// takes TP of this round's pixels and 64 survivors: every lane walks the same
+// pixels and the same mode rows of M(u) (so each row read is one broadcast
+// request for the wave) and accumulates its own hypothesis's Eq. 5 terms, in
+// pixel order, in FP64.  No LDS: occupancy is not tied to |M(u)|.
+__global__ __launch_bounds__(64) void k_score(const Job* __restrict__ jobs, int round, int nptiles)
 {
+#pragma clang fp contract(off)
     const Job& J = jobs[blockIdx.y];
     if (J.st->done) return;
     const int n = J.st->n_surv;
     const int ptile = blockIdx.x % nptiles, htile = blockIdx.x / nptiles;
     const int TP = J.TP;
     const int k0 = ptile * TP;
-    if (k0 >= J.eta || htile * 256 >= n) return;
+    if (k0 >= J.eta || htile * 64 >= n) return;
     const int tp = min(TP, J.eta - k0);
-    extern __shared__ double s_rows[];               // 9 doubles per mode row
-    __shared__ double s_x[kMaxScoreTile][3];
-    __shared__ uint4 s_lw[kMaxScoreTile];
-    __shared__ uint2 s_nw[kMaxScoreTile];
-    __shared__ int s_off[kMaxScoreTile + 1];
-    const int tid = threadIdx.x;
-    if (tid < tp) {
-        const int k = k0 + tid;
-        const uint4 rb = philox(make_uint4(kTagScore << 28, (uint32_t)round, (uint32_t)(k >> 2), 0u), J.key0, J.key1);
-        const uint32_t rv = (k & 3) == 0 ? rb.x : (k & 3) == 1 ? rb.y : (k & 3) == 2 ? rb.z : rb.w;
-        const uint32_t e = below(rv, (uint32_t)J.st->n_elig);
-        const uint4 c0 = ldg(J.ecold + 2 * e);
-        const int p = (int)c0.x;
-        if (htile == 0) J.I[round * J.eta + k] = p;
-        backproject(__uint_as_float(c0.y), p % J.w, p / J.w, J.fx, J.fy, J.cx, J.cy, s_x[tid]);
-        s_lw[tid] = ldg(J.ecold + 2 * e + 1);
-        s_nw[tid] = make_uint2(c0.z, c0.w);
-    }
-    __syncthreads();
-    if (tid == 0) {
-        int o = 0;
-        for (int i = 0; i < tp; ++i) {
-            s_off[i] = o;
-            o += modes_total(s_nw[i], J.T);
-        }
-        s_off[tp] = o;
-    }
-    __syncthreads();
-    const int nrows = s_off[tp];
-    for (int j = tid; j < nrows; j += 256) {
-        int i = 0;
-        while (s_off[i + 1] <= j) ++i;
-        const float4* row = mode_row(J.modes, J.T, J.D, J.M, s_lw[i], s_nw[i], j - s_off[i]);
-        const float4 a = ldg(row), b = ldg(row + 1), c = ldg(row + 2);
-        double* o = s_rows + 9 * j;
-        o[0] = a.x; o[1] = a.y; o[2] = a.z;
-        o[3] = b.x; o[4] = b.y; o[5] = b.z; o[6] = b.w; o[7] = c.x; o[8] = c.y;
-    }
-    __syncthreads();
-    const int pos = htile * 256 + tid;
-    if (pos >= n) return;
-    const int slot = J.surv[pos];
-    const Hyp& hy = J.hyps[slot];
+    const int pos = htile * 64 + (int)threadIdx.x;
+    const bool active = pos < n;
     double R[9], t[3];
-    for (int i = 0; i < 9; ++i) R[i] = hy.R[i];
-    for (int i = 0; i < 3; ++i) t[i] = hy.t[i];
+    {
+        const Hyp& hy = J.hyps[active ? J.surv[pos] : J.surv[0]];
+        for (int i = 0; i < 9; ++i) R[i] = hy.R[i];
+        for (int i = 0; i < 3; ++i) t[i] = hy.t[i];
+    }
     const bool cov = J.use_cov != 0;
+    const uint32_t n_elig = (uint32_t)J.st->n_elig;
     double acc = 0.0;
     for (int i = 0; i < tp; ++i) {
-        const double x0 = s_x[i][0], x1 = s_x[i][1], x2 = s_x[i][2];
-        const double y0 = R[0] * x0 + R[1] * x1 + R[2] * x2 + t[0];
-        const double y1 = R[3] * x0 + R[4] * x1 + R[5] * x2 + t[1];
-        const double y2 = R[6] * x0 + R[7] * x1 + R[8] * x2 + t[2];
+        const int k = k0 + i;
+        const uint4 rb = philox(make_uint4(kTagScore << 28, (uint32_t)round, (uint32_t)(k >> 2), 0u), J.key0, J.key1);
+        const uint32_t rv = (k & 3) == 0 ? rb.x : (k & 3) == 1 ? rb.y : (k & 3) == 2 ? rb.z : rb.w;
+        const uint32_t e = below(rv, n_elig);
+        const uint4 c0 = ldg(J.ecold + 2 * e), lw = ldg(J.ecold + 2 * e + 1);
+        const int p = (int)c0.x;
+        if (htile == 0 && threadIdx.x == 0) J.I[round * J.eta + k] = p;
+        double x[3];
+        backproject(__uint_as_float(c0.y), p % J.w, p / J.w, J.fx, J.fy, J.cx, J.cy, x);
+        const double y0 = R[0] * x[0] + R[1] * x[1] + R[2] * x[2] + t[0];
+        const double y1 = R[3] * x[0] + R[4] * x[1] + R[5] * x[2] + t[1];
+        const double y2 = R[6] * x[0] + R[7] * x[1] + R[8] * x[2] + t[2];
+        const uint2 nw = make_uint2(c0.z, c0.w);
         double best = INFINITY;
-        for (int j = s_off[i]; j < s_off[i + 1]; ++j) {
-            const double* m = s_rows + 9 * j;
-            const double d0 = y0 - m[0], d1 = y1 - m[1], d2 = y2 - m[2];
-            double q;
-            if (cov)
-                q = d0 * (m[3] * d0 + m[4] * d1 + m[5] * d2) + d1 * (m[4] * d0 + m[6] * d1 + m[7] * d2)
-                  + d2 * (m[5] * d0 + m[7] * d1 + m[8] * d2);
-            else
-                q = d0 * d0 + d1 * d1 + d2 * d2;
-            best = fmin(best, q);
+        for (int tr = 0; tr < J.T; ++tr) {
+            const int c = (int)count_of(nw, tr);
+            const float4* row = J.modes + ((((size_t)tr << J.D) + leaf_of(lw, tr)) * (size_t)J.M) * 4;
+            for (int j = 0; j < c; ++j) {
+                const float4 a = ldg(row + 4 * j);
+                const double d0 = y0 - (double)a.x, d1 = y1 - (double)a.y, d2 = y2 - (double)a.z;
+                double q;
+                if (cov) {
+                    const float4 b = ldg(row + 4 * j + 1), cc = ldg(row + 4 * j + 2);
+                    const double m3 = b.x, m4 = b.y, m5 = b.z, m6 = b.w, m7 = cc.x, m8 = cc.y;
+                    q = d0 * (m3 * d0 + m4 * d1 + m5 * d2) + d1 * (m4 * d0 + m6 * d1 + m7 * d2)
+                      + d2 * (m5 * d0 + m7 * d1 + m8 * d2);
+                } else {
+                    q = d0 * d0 + d1 * d1 + d2 * d2;
+                }
+                best = fmin(best, q);
+            }
         }
         acc += sqrt(fmax(best, 0.0));
     }
-    J.partial[(size_t)ptile * J.N + pos] = acc;
+    if (active) J.partial[(size_t)ptile * J.N + pos] = acc;
 }
 
 // Adds the round's partial sums (tile order), ranks survivors by
@@ -964,11 +945,10 @@ hipError_t launch_hyp_finalize(const Job* jobs, int njobs, int maxN, hipStream_t
     return hipSuccess;
 }
 
-hipError_t launch_score(const Job* jobs, int njobs, int round, int nptiles, int maxSurv,
-                        size_t score_lds, hipStream_t st)
+hipError_t launch_score(const Job* jobs, int njobs, int round, int nptiles, int maxSurv, hipStream_t st)
 {
-    const int htiles = (maxSurv + 255) / 256;
-    k_score<<<dim3(nptiles * htiles, njobs), dim3(256), score_lds, st>>>(jobs, round, nptiles);
+    const int htiles = (maxSurv + 63) / 64;
+    k_score<<<dim3(nptiles * htiles, njobs), dim3(64), 0, st>>>(jobs, round, nptiles);
     RL_CHECK_LAUNCH();
     return hipSuccess;
 }

@@ -27,7 +27,7 @@ hipError_t launch_eligible(const Job* jobs, int njobs, int maxP, hipStream_t st)
 hipError_t launch_hyp_search(const Job* jobs, int njobs, int maxN, int maxIters, hipStream_t st);
 hipError_t launch_hyp_finalize(const Job* jobs, int njobs, int maxN, hipStream_t st);
 hipError_t launch_score(const Job* jobs, int njobs, int round, int nptiles, int maxSurv,
-                        size_t score_lds, hipStream_t st);
+                        hipStream_t st);
 hipError_t launch_select(const Job* jobs, int njobs, int round, int nptiles, int maxN, hipStream_t st);
 hipError_t launch_finalize(const Job* jobs, int njobs, int maxIlen, hipStream_t st);
 hipError_t launch_plane_scores(const float* depth, int w, int h, float fx, float fy, float cx, float cy,
@@ -108,13 +108,9 @@ int rounds_capacity(const rl_params& p)
                     rounds_for(p.max_pose_candidates, p.max_pose_candidates, 1));
 }
 
-int score_tile(int rows_per_pixel)
-{
-    int tp = kScoreLdsBytes / (rows_per_pixel * 72);
-    if (tp < 1) tp = 1;
-    if (tp > kMaxScoreTile) tp = kMaxScoreTile;
-    return tp;
-}
+// Pixels per scoring wave: every lane of a wave reads the same mode rows, so
+// no shared memory is staged and the tile size does not depend on |M(u)|.
+int score_tile(int) { return kScoreTile; }
 
 // Per-frame (relocalisation) scratch of one job slot.
 struct FrameLayout {
@@ -298,7 +294,6 @@ struct rl_batch {
     hipStream_t stream;
     hipEvent_t ev;
     int TP, rows;
-    size_t score_lds;
     size_t jobs_off, results_off;
     std::vector<FrameLayout> slots;
     Timer timer;
@@ -702,7 +697,7 @@ RL_API rl_status relocaliser_update_modes(rl_room* r)
 }
 
 static hipError_t launch_sequence(const Job* jobs, int njobs, int maxP, int maxN, int maxIters, int T,
-                                  const std::vector<int>& entering, int nptiles, int maxEta, size_t score_lds,
+                                  const std::vector<int>& entering, int nptiles, int maxEta,
                                   const Timer& tm, hipStream_t st)
 {
     hipError_t e;
@@ -719,7 +714,7 @@ static hipError_t launch_sequence(const Job* jobs, int njobs, int maxP, int maxN
     RL_TRY(launch_hyp_finalize(jobs, njobs, maxN, st));
     RL_MARK(RL_TIMER_RANSAC, start);
     for (int r = 0; r < (int)entering.size(); ++r) {
-        RL_TRY(launch_score(jobs, njobs, r, nptiles, entering[r], score_lds, st));
+        RL_TRY(launch_score(jobs, njobs, r, nptiles, entering[r], st));
         RL_TRY(launch_select(jobs, njobs, r, nptiles, maxN, st));
     }
     RL_MARK(RL_TIMER_RANSAC, stop);
@@ -782,13 +777,12 @@ RL_API rl_status relocaliser_relocalise_opts(rl_room* r, const rl_frame* f, uint
     hipError_t e = hipMemcpyAsync(jd, r->job_host, sizeof(Job), hipMemcpyHostToDevice, r->stream);
     if (e != hipSuccess) return hip_fail(e, "job upload");
     const int nptiles = (r->eta + r->TP - 1) / r->TP;
-    const size_t score_lds = (size_t)r->TP * r->T * r->M * 72;
     const int P = f->width * f->height;
     std::vector<long long> key = {P, N};
     for (int v : entering) key.push_back(v);
     e = run_sequence(r->graphs, key, r->timer.kernel == RL_TIMER_NONE, r->stream, [&]() {
         return launch_sequence(jd, 1, P, N, r->p.max_candidate_generation_iterations, r->T, entering,
-                               nptiles, r->eta, score_lds, r->timer, r->stream);
+                               nptiles, r->eta, r->timer, r->stream);
     });
     if (e != hipSuccess) return hip_fail(e, "relocalise launch");
     e = hipMemcpyAsync(r->res_host, r->scr + r->FL.result, sizeof(rl_result), hipMemcpyDeviceToHost, r->stream);
@@ -916,7 +910,6 @@ RL_API rl_status rl_batch_create(const rl_batch_params* bp, void* ws, void* hip_
     b->stream = reinterpret_cast<hipStream_t>(hip_stream);
     b->TP = score_tile(bp->max_modes_per_pixel);
     b->rows = bp->max_modes_per_pixel;
-    b->score_lds = (size_t)b->TP * b->rows * 72;
     Carver c;
     b->jobs_off = c.take((size_t)bp->max_frames * sizeof(Job));
     b->results_off = c.take((size_t)bp->max_frames * sizeof(rl_result));
@@ -1007,7 +1000,7 @@ RL_API rl_status rl_batch_relocalise_async(rl_batch* b, const rl_request* reqs, 
     for (int v : entering) key.push_back(v);
     e = run_sequence(b->graphs, key, use_graph && b->timer.kernel == RL_TIMER_NONE, b->stream, [&]() {
         return launch_sequence(jd, n, maxP, maxN, maxIters, b->bp.n_trees, entering, nptiles, maxEta,
-                               b->score_lds, b->timer, b->stream);
+                               b->timer, b->stream);
     });
     if (e != hipSuccess) return hip_fail(e, "batch launch");
     // later work on the rooms' own streams is ordered after the batch

@@ -194,6 +194,38 @@ def test_cascade_fallback_and_ranking(c2, c3_room):
     assert out["model_score"] == float(np.min(out["ranked"]))
 
 
+def test_mixed_batch_equals_plain(c2, c3_room):
+    """Batches mixing two rooms (different cull / output / refit settings),
+    three resolutions (640x480, 320x240, 160x120) and hypothesis counts
+    (1024, 512, 256) give exactly the plain path's result for every request,
+    with direct launches and graph replay, in any order."""
+    w, o, room = c2
+    p3, r3 = c3_room
+    q0, q1 = w.queries[0], w.queries[1]
+    dec = workloads.decimate
+    plan = [(room, q0, 1), (r3, q1, 2), (room, dec(q1), 3), (r3, dec(q0), 4),
+            (room, dec(dec(q0)), 5), (r3, dec(dec(q1)), 6), (room, q1, 7)]
+    reqs = []
+    for rm, q, s in plan:
+        d, c = dev(q)
+        reqs.append((rm, d, c, q.K, s, workloads.HYPOTHESES[q.depth.shape[1]]))
+    plain = [rm.relocalise(d, c, K, request_seed=s, n_hypotheses=N) for (rm, d, c, K, s, N) in reqs]
+    print(f"[mixed batch] plain statuses {[r['status'] for r in plain]}, rounds {[r['rounds'] for r in plain]}",
+          flush=True)
+    batch = rl.Batch(8, 640, 480, 1024, 500, 12, 5, 50)
+
+    def same(got, want):
+        for a, b in zip(got, want):
+            assert a["status"] == b["status"] and a["winner"] == b["winner"]
+            assert a["rounds"] == b["rounds"] and a["n_out"] == b["n_out"] and a["n_valid"] == b["n_valid"]
+            assert np.array_equal(a["pose"], b["pose"]) and a["energy"] == b["energy"]
+
+    for use_graph in (False, True, True):
+        same(batch.relocalise(reqs, use_graph=use_graph), plain)
+    same(batch.relocalise(reqs[::-1], use_graph=True), plain[::-1])
+    batch.close()
+
+
 def dataclasses_replace(s, **kw):
     import dataclasses
     return dataclasses.replace(s, **kw)
