@@ -89,21 +89,15 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--timer", default="hyp_search", choices=["traverse", "hyp_search", "ransac"])
     ap.add_argument("--serve-seconds", type=float, default=0.0,
-                    help="measured seconds per arrival rate; the served leg is switched off (see below)")
+                    help="measured seconds per arrival rate of the served leg (0 = skip it)")
     ap.add_argument("--serve-rates", default="200,500,1000")
     ap.add_argument("--serve-rooms", type=int, default=16)
+    ap.add_argument("--serve-leaves-per-frame", type=int, default=256,
+                    help="mode update schedule of the served rooms: 0 exact, K leaves per adapted frame")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device-to-device copy of this size (counter calibration)")
     args = ap.parse_args()
 
-    if args.serve_seconds > 0:
-        # The served leg at full scale (16 five-tree rooms, mixed resolutions and
-        # hypothesis counts in one batch, two batches in flight, interleaved
-        # adaptations) ended twice in a GPU memory fault whose cause is not yet
-        # found; it stays off until it is.  Continuous batching itself is covered
-        # at small scale by tests/test_gpu_serve.py.
-        raise SystemExit("the served benchmark leg is switched off: it faulted the GPU at full scale "
-                         "and its cause is not found yet")
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}, WORLD_SIZE {world}): "
@@ -306,6 +300,7 @@ def serve_leg(args, rl, dev, inputs):
         for f in sp["adapt"]:
             room.adapt(torch.from_numpy(f.depth).to(dev), torch.from_numpy(f.rgb).to(dev), f.K, f.pose)
         room.update_modes()
+        room.set_mode_schedule(args.serve_leaves_per_frame)
         rooms.append(room)
     torch.cuda.synchronize()
     camf = [[(torch.from_numpy(f.depth).to(dev), torch.from_numpy(f.rgb).to(dev), f) for f in c["frames"]]

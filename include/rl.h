@@ -146,8 +146,21 @@ rl_status relocaliser_adapt(rl_room* room, const rl_frame* frame, const float ca
                             int32_t reliable);
 
 /* Re-clusters every leaf whose reservoir changed since the last call (RQS).
- * relocaliser_relocalise does this implicitly.  Asynchronous. */
+ * Under the exact schedule (the default) every relocalisation does this
+ * implicitly.  Asynchronous. */
 rl_status relocaliser_update_modes(rl_room* room);
+
+/*
+ * Mode-update schedule (Sec. 3.2.2).  leaves_per_frame = 0 (default): exact,
+ * every adapted leaf is re-clustered before the next relocalisation, so modes
+ * are a function of the reservoirs.  leaves_per_frame = K > 0: amortised as
+ * in the paper, each adapted frame is followed by RQS of the next K leaves of
+ * the forest (leaf index t * 2^D + leaf, in order, wrapping around; the first
+ * call starts at leaf 0), and relocalisation uses the modes as they are.
+ * K <= n_trees * 2^depth, else RL_EINVAL.  Takes effect at the next adapt;
+ * relocaliser_update_modes still performs an exact update when called.
+ */
+rl_status relocaliser_set_mode_schedule(rl_room* room, int32_t leaves_per_frame);
 
 /*
  * Relocalises one frame (Sec. 3.2.3): synchronous on the room's stream.  On

@@ -69,6 +69,9 @@ def _declare(L):
     L.oracle_rqs_leaf.restype = I32
     L.oracle_update_modes.argtypes = [P, P, P, I32, I32, I32, F64, F64, I32, I32, F64, P, P, I32]
     L.oracle_update_modes.restype = ctypes.c_long
+    L.oracle_update_modes_range.argtypes = [P, P, I32, I32, I32, F64, F64, I32, I32, F64, P, P,
+                                            ctypes.c_long, ctypes.c_long]
+    L.oracle_update_modes_range.restype = ctypes.c_long
     L.oracle_kabsch.argtypes = [P, P, I32, P, P, P]
     L.oracle_kabsch.restype = I32
     L.oracle_hypotheses.argtypes = [P, P, I32, I32, P, P, P, P, I32, I32, I32, P, I32, I32, I32,
@@ -160,6 +163,7 @@ class Oracle:
         self.dirty = np.zeros(TL, dtype=np.uint8)
         self.modes = np.zeros(TL * self.M * 16, dtype=np.float32)
         self.nmodes = np.zeros(TL, dtype=np.uint8)
+        self.rr_cursor = 0
 
     # -- adaptation ---------------------------------------------------------
     def adapt(self, depth, rgb, K, pose, reliable=True):
@@ -182,6 +186,16 @@ class Oracle:
                                          float(p["clusterer_tau"]), int(p["min_cluster_size"]),
                                          self.M, float(p["cov_regulariser"]), _p(self.modes),
                                          _p(self.nmodes), 1 if all_leaves else 0)
+
+    def update_modes_round_robin(self, count: int):
+        """Amortised schedule (Sec. 3.2.2): re-cluster the next `count` leaves
+        in leaf-index order (t * 2^D + leaf), wrapping around."""
+        p = self.p
+        self.rr_cursor = lib().oracle_update_modes_range(
+            _p(self.reservoir), _p(self.seen), self.T, self.D, self.kappa, float(p["clusterer_sigma"]),
+            float(p["clusterer_tau"]), int(p["min_cluster_size"]), self.M, float(p["cov_regulariser"]),
+            _p(self.modes), _p(self.nmodes), int(self.rr_cursor), int(count))
+        return self.rr_cursor
 
     def reservoir_of(self, t, leaf):
         tl = t * self.L + leaf

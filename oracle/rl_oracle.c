@@ -365,6 +365,25 @@ EXPORT long oracle_update_modes(const float* reservoir, const uint32_t* seen, ui
     return done;
 }
 
+/*
+ * Amortised mode update (Sec. 3.2.2): re-cluster `count` leaves in leaf-index
+ * order starting at `first`, wrapping around the T * 2^D leaves of the
+ * forest; dirty flags are not used or changed.  Returns the next first leaf.
+ */
+EXPORT long oracle_update_modes_range(const float* reservoir, const uint32_t* seen, int T, int D, int kappa,
+                                      double sigma, double tau_c, int min_size, int max_modes, double lambda,
+                                      float* modes, uint8_t* nmodes, long first, long count)
+{
+    const long n_leaves = (long)T << D;
+    for (long i = 0; i < count; ++i) {
+        const size_t tl = (size_t)((first + i) % n_leaves);
+        int n = seen[tl] < (uint32_t)kappa ? (int)seen[tl] : kappa;
+        nmodes[tl] = (uint8_t)oracle_rqs_leaf(reservoir + tl * (size_t)kappa * 4, n, sigma, tau_c, min_size,
+                                              max_modes, lambda, modes + tl * (size_t)max_modes * 16, NULL);
+    }
+    return (first + count) % n_leaves;
+}
+
 /* ------------------------------------------------------------------------ */
 /*
  * Singular value decomposition of a 3x3 matrix by one-sided (Hestenes)

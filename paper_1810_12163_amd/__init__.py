@@ -101,6 +101,7 @@ EXPORTS = [
     "relocaliser_set_trace", "rl_batch_workspace_bytes", "rl_batch_create", "rl_batch_destroy",
     "rl_batch_relocalise", "rl_batch_relocalise_async", "rl_last_error", "rl_version",
     "relocaliser_set_timer", "rl_batch_set_timer", "relocaliser_relocalise_opts", "rl_plane_scores",
+    "relocaliser_set_mode_schedule",
 ]
 
 TIMER_NONE, TIMER_TRAVERSE, TIMER_HYP_SEARCH, TIMER_RANSAC = 0, 1, 2, 3
@@ -141,6 +142,7 @@ def lib():
                                                   ctypes.POINTER(Result)]
         L.rl_plane_scores.argtypes = [P, ctypes.POINTER(Frame), P, I32, P, I32, P]
         L.rl_batch_set_timer.argtypes = [P, I32, P, P]
+        L.relocaliser_set_mode_schedule.argtypes = [P, I32]
         L.rl_last_error.restype = ctypes.c_char_p
         L.rl_version.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -257,6 +259,11 @@ class Room:
     def update_modes(self):
         self._follow()
         _check(lib().relocaliser_update_modes(self.handle))
+
+    def set_mode_schedule(self, leaves_per_frame: int):
+        """0: exact mode update before each relocalisation; K > 0: RQS of the
+        next K leaves (round robin) after each adapted frame."""
+        _check(lib().relocaliser_set_mode_schedule(self.handle, int(leaves_per_frame)))
 
     def relocalise(self, depth, rgb, K, request_seed: int = 0, n_hypotheses: int = 0, n_cull: int = 0,
                    n_out: int = 0, final_refine: int = -1) -> dict:

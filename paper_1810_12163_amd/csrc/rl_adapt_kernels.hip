@@ -186,11 +186,11 @@ __global__ __launch_bounds__(256) void k_rqs(RqsArgs a)
     __shared__ int s_chosen[64];
     __shared__ int s_ncand;
     const int tid = threadIdx.x;
-    const uint32_t ndirty = a.counters[0];
+    const uint32_t ndirty = a.rr_count ? a.rr_count : a.counters[0];
     const double two_s2 = 2.0 * a.sigma * a.sigma;
     const double tau2 = a.tau * a.tau;
     for (uint32_t li = blockIdx.x; li < ndirty; li += gridDim.x) {
-        const uint32_t tl = a.dirty_list[li];
+        const uint32_t tl = a.rr_count ? (a.rr_first + li) % a.n_leaves : a.dirty_list[li];
         const int n = (int)min(a.seen[tl], (uint32_t)a.kappa);
         const float4* src = a.reservoir + (size_t)tl * a.kappa;
         for (int k = tid; k < n; k += 256) {
@@ -291,7 +291,7 @@ __global__ __launch_bounds__(256) void k_rqs(RqsArgs a)
         }
         if (tid == 0) {
             a.nmodes[tl] = (uint8_t)nm;
-            a.dirty[tl] = 0u;
+            if (!a.rr_count) a.dirty[tl] = 0u;
         }
         __syncthreads();
     }
@@ -339,6 +339,7 @@ hipError_t launch_rqs(const RqsArgs& a, int blocks, hipStream_t st)
     const size_t lds = 36 * (size_t)a.kappa;
     k_rqs<<<dim3(blocks), dim3(256), lds, st>>>(a);
     RL_CHECK_LAUNCH();
+    if (a.rr_count) return hipSuccess;      // the dirty list is left for an exact update
     k_rqs_done<<<dim3(1), dim3(64), 0, st>>>(a);
     RL_CHECK_LAUNCH();
     return hipSuccess;

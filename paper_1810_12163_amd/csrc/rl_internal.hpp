@@ -119,6 +119,10 @@ struct RqsArgs {
     uint8_t* nmodes;
     int kappa, M, min_size;
     double sigma, tau, lambda;
+    // round-robin schedule: when rr_count > 0, the leaves rr_first ...
+    // rr_first + rr_count - 1 (mod n_leaves) are clustered instead of the
+    // dirty list, whose state is left as it is
+    uint32_t rr_first, rr_count, n_leaves;
 };
 
 // ---------------------------------------------------------------------------

@@ -279,10 +279,20 @@ struct rl_room {
     int rounds_cap;
     hipStream_t stream;
     hipEvent_t ev;
+    // Access order of the room's persistent state by batches on other
+    // streams: batches only read it (forest, modes); the mode update (RQS) is
+    // the only writer they can race with.  wev marks the last mode update;
+    // readers are events the room recorded on batch streams after batches
+    // that read it since then (a pool, reused).
+    hipEvent_t wev;
+    bool wrote;
+    std::vector<hipEvent_t> readers, spare;
     Job* job_host;
     rl_result* res_host;
     int trace;
-    bool modes_stale;
+    bool modes_stale;         // leaves adapted since the last exact mode update
+    int rr_leaves;            // 0: exact mode update before relocalising; K: K leaves per adapted frame
+    uint32_t rr_cursor;       // next leaf of the round-robin schedule
     std::vector<int> entering;
     Timer timer;
     std::map<std::vector<long long>, hipGraphExec_t> graphs;
@@ -493,6 +503,9 @@ static RqsArgs rqs_args(rl_room* r)
     a.sigma = r->p.clusterer_sigma;
     a.tau = r->p.clusterer_tau;
     a.lambda = r->p.cov_regulariser;
+    a.rr_first = 0;
+    a.rr_count = 0;
+    a.n_leaves = (uint32_t)(r->T * r->L);
     return a;
 }
 
@@ -560,11 +573,16 @@ RL_API rl_status relocaliser_create(const rl_params* p, const rl_node* host_node
     r->stream = reinterpret_cast<hipStream_t>(hip_stream);
     r->trace = 0;
     r->modes_stale = false;
+    r->rr_leaves = 0;
+    r->rr_cursor = 0;
     hipError_t e = hipEventCreateWithFlags(&r->ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&r->wev, hipEventDisableTiming);
     if (e != hipSuccess) {
+        if (r->ev) (void)hipEventDestroy(r->ev);
         delete r;
         return hip_fail(e, "hipEventCreate");
     }
+    r->wrote = false;
     e = hipHostMalloc(reinterpret_cast<void**>(&r->job_host), sizeof(Job), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&r->res_host), sizeof(rl_result), hipHostMallocDefault);
     if (e == hipSuccess)
@@ -611,6 +629,12 @@ RL_API rl_status relocaliser_destroy(rl_room* r)
     if (r->res_host) (void)hipHostFree(r->res_host);
     if (r->model_host) (void)hipHostFree(r->model_host);
     if (r->ev) (void)hipEventDestroy(r->ev);
+    if (r->wev) (void)hipEventDestroy(r->wev);
+    for (hipEvent_t ev : r->readers) {
+        (void)hipEventSynchronize(ev);      // recorded on a batch stream that may still run
+        (void)hipEventDestroy(ev);
+    }
+    for (hipEvent_t ev : r->spare) (void)hipEventDestroy(ev);
     delete r;
     return RL_OK;
 }
@@ -621,6 +645,8 @@ RL_API rl_status relocaliser_set_trace(rl_room* r, int32_t on)
     r->trace = on ? 1 : 0;
     return RL_OK;
 }
+
+static rl_status round_robin_step(rl_room* r);
 
 RL_API rl_status relocaliser_adapt(rl_room* r, const rl_frame* f, const float H[16], int32_t reliable)
 {
@@ -678,22 +704,103 @@ RL_API rl_status relocaliser_adapt(rl_room* r, const rl_frame* f, const float H[
     const hipError_t e = launch_adapt(a, r->stream);
     if (e != hipSuccess) return hip_fail(e, "adapt launch");
     r->modes_stale = true;
+    return r->rr_leaves ? round_robin_step(r) : RL_OK;
+}
+
+// Brings the modes up to date on the room's stream: after every batch that
+// read the old modes (write-after-read), and marked by wev for batches that
+// read the new ones.
+static rl_status write_modes(rl_room* r, const RqsArgs& a)
+{
+    hipError_t e = hipSuccess;
+    for (hipEvent_t ev : r->readers) {
+        if (e == hipSuccess) e = hipStreamWaitEvent(r->stream, ev, 0);
+        r->spare.push_back(ev);
+    }
+    r->readers.clear();
+    if (e == hipSuccess) e = launch_rqs(a, 1024, r->stream);
+    if (e == hipSuccess) e = hipEventRecord(r->wev, r->stream);
+    if (e != hipSuccess) return hip_fail(e, "mode update launch");
+    r->wrote = true;
     return RL_OK;
 }
 
-static rl_status ensure_modes(rl_room* r, hipStream_t st)
+// exact update: every leaf adapted since the last one
+static rl_status update_dirty_modes(rl_room* r)
 {
     if (!r->modes_stale) return RL_OK;
-    const hipError_t e = launch_rqs(rqs_args(r), 1024, st);
-    if (e != hipSuccess) return hip_fail(e, "mode update launch");
-    r->modes_stale = false;
+    const rl_status s = write_modes(r, rqs_args(r));
+    if (s == RL_OK) r->modes_stale = false;
+    return s;
+}
+
+// Before a relocalisation: the exact schedule brings every adapted leaf up
+// to date; the round-robin schedule uses the modes as they are.
+static rl_status ensure_modes(rl_room* r)
+{
+    return r->rr_leaves ? RL_OK : update_dirty_modes(r);
+}
+
+// Round-robin schedule (Sec. 3.2.2): after each adapted frame, the next K
+// leaves of the forest in index order, wrapping around.
+static rl_status round_robin_step(rl_room* r)
+{
+    RqsArgs a = rqs_args(r);
+    a.rr_first = r->rr_cursor;
+    a.rr_count = (uint32_t)r->rr_leaves;
+    const rl_status s = write_modes(r, a);
+    if (s == RL_OK) r->rr_cursor = (uint32_t)((r->rr_cursor + (uint64_t)r->rr_leaves) % a.n_leaves);
+    return s;
+}
+
+// A batch on stream st is about to read the room: order it after the last
+// mode update.
+static rl_status room_read_begin(rl_room* r, hipStream_t st)
+{
+    rl_status s = ensure_modes(r);
+    if (s != RL_OK) return s;
+    if (r->wrote && st != r->stream) {
+        const hipError_t e = hipStreamWaitEvent(st, r->wev, 0);
+        if (e != hipSuccess) return hip_fail(e, "batch ordering");
+    }
+    return RL_OK;
+}
+
+// ... and has been queued: remember it as a reader of the current modes.
+static rl_status room_read_end(rl_room* r, hipStream_t st)
+{
+    if (st == r->stream) return RL_OK;
+    hipEvent_t ev = nullptr;
+    hipError_t e = hipSuccess;
+    if (!r->spare.empty()) {
+        ev = r->spare.back();
+        r->spare.pop_back();
+    } else {
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventRecord(ev, st);
+    if (e != hipSuccess) {
+        if (ev) (void)hipEventDestroy(ev);
+        return hip_fail(e, "batch ordering");
+    }
+    r->readers.push_back(ev);
     return RL_OK;
 }
 
 RL_API rl_status relocaliser_update_modes(rl_room* r)
 {
     if (!r) return fail(RL_EINVAL, "room is NULL");
-    return ensure_modes(r, r->stream);
+    return update_dirty_modes(r);
+}
+
+RL_API rl_status relocaliser_set_mode_schedule(rl_room* r, int32_t leaves_per_frame)
+{
+    if (!r) return fail(RL_EINVAL, "room is NULL");
+    const long long TL = (long long)r->T * (long long)r->L;
+    if (leaves_per_frame < 0 || leaves_per_frame > TL)
+        return fail(RL_EINVAL, "leaves_per_frame must be in 0..%lld", TL);
+    r->rr_leaves = leaves_per_frame;
+    return RL_OK;
 }
 
 static hipError_t launch_sequence(const Job* jobs, int njobs, int maxP, int maxN, int maxIters, int T,
@@ -766,7 +873,7 @@ RL_API rl_status relocaliser_relocalise_opts(rl_room* r, const rl_frame* f, uint
     std::vector<int> entering;
     const int R = rounds_for(N, n_cull, n_out, &entering);
     if (R > r->rounds_cap) return fail(RL_EINVAL, "%d rounds exceed the room's capacity %d", R, r->rounds_cap);
-    s = ensure_modes(r, r->stream);
+    s = ensure_modes(r);
     if (s != RL_OK) return s;
     Job J = make_job(r, r->scr, r->FL, f, request_seed, N);
     J.n_cull = n_cull;
@@ -970,48 +1077,59 @@ RL_API rl_status rl_batch_relocalise_async(rl_batch* b, const rl_request* reqs, 
         maxIters = std::max(maxIters, r->p.max_candidate_generation_iterations);
         maxEta = std::max(maxEta, r->eta);
     }
-    // order every room's pending work before the batch, bring modes up to date
-    for (int i = 0; i < n; ++i) {
-        rl_room* r = reqs[i].room;
-        if (r->stream != b->stream) {
-            hipError_t e = hipEventRecord(r->ev, r->stream);
-            if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, r->ev, 0);
-            if (e != hipSuccess) return hip_fail(e, "batch ordering");
-        }
-        rl_status s = ensure_modes(r, b->stream);
+    // Launch shapes come in few classes so that few graphs are captured:
+    // grids cover the batch's largest frame, and the job count is padded to
+    // a power of two with empty jobs (no pixels, no hypotheses), which every
+    // kernel leaves at once.
+    maxP = b->bp.max_width * b->bp.max_height;
+    int nq = 1;
+    while (nq < n) nq *= 2;
+    nq = std::min(nq, b->bp.max_frames);
+    // each room: mode update if stale (on the room's stream, after the batches
+    // that read the old modes), and this batch after the last update
+    std::vector<rl_room*> rooms;
+    for (int i = 0; i < n; ++i)
+        if (std::find(rooms.begin(), rooms.end(), reqs[i].room) == rooms.end()) rooms.push_back(reqs[i].room);
+    for (rl_room* r : rooms) {
+        rl_status s = room_read_begin(r, b->stream);
         if (s != RL_OK) return s;
     }
-    for (int i = 0; i < n; ++i) {
-        const rl_request& q = reqs[i];
-        const int N = q.n_hypotheses > 0 ? q.n_hypotheses : q.room->N;
-        Job J = make_job(q.room, b->ws, b->slots[i], &q.frame, q.request_seed, N);
+    for (int i = 0; i < nq; ++i) {
+        Job J;
+        if (i < n) {
+            const rl_request& q = reqs[i];
+            const int N = q.n_hypotheses > 0 ? q.n_hypotheses : q.room->N;
+            J = make_job(q.room, b->ws, b->slots[i], &q.frame, q.request_seed, N);
+            J.result = dev_results + i;
+        } else {
+            std::memset(&J, 0, sizeof(J));
+            J.T = b->bp.n_trees;
+            J.st = reinterpret_cast<JobState*>(b->ws + b->slots[i].state);
+            J.result = reinterpret_cast<rl_result*>(b->ws + b->slots[i].result);
+        }
         J.TP = b->TP;
         J.trace = 0;
-        J.result = dev_results + i;
         b->job_host[i] = J;
     }
     Job* jd = reinterpret_cast<Job*>(b->ws + b->jobs_off);
-    hipError_t e = hipMemcpyAsync(jd, b->job_host, (size_t)n * sizeof(Job), hipMemcpyHostToDevice, b->stream);
+    hipError_t e = hipMemcpyAsync(jd, b->job_host, (size_t)nq * sizeof(Job), hipMemcpyHostToDevice, b->stream);
     if (e != hipSuccess) return hip_fail(e, "job upload");
     const int nptiles = (maxEta + b->TP - 1) / b->TP;
     if (use_graph && b->stream == nullptr)
         return fail(RL_EINVAL, "graph replay needs a batch created on a non-default stream");
-    std::vector<long long> key = {n, maxP, maxN, maxIters, nptiles, maxEta, b->bp.n_trees};
+    std::vector<long long> key = {nq, maxN, maxIters, nptiles, maxEta, b->bp.n_trees};
     for (int v : entering) key.push_back(v);
     e = run_sequence(b->graphs, key, use_graph && b->timer.kernel == RL_TIMER_NONE, b->stream, [&]() {
-        return launch_sequence(jd, n, maxP, maxN, maxIters, b->bp.n_trees, entering, nptiles, maxEta,
+        return launch_sequence(jd, nq, maxP, maxN, maxIters, b->bp.n_trees, entering, nptiles, maxEta,
                                b->timer, b->stream);
     });
     if (e != hipSuccess) return hip_fail(e, "batch launch");
-    // later work on the rooms' own streams is ordered after the batch
     e = hipEventRecord(b->ev, b->stream);
     if (e != hipSuccess) return hip_fail(e, "batch event");
-    for (int i = 0; i < n; ++i) {
-        rl_room* r = reqs[i].room;
-        if (r->stream != b->stream) {
-            e = hipStreamWaitEvent(r->stream, b->ev, 0);
-            if (e != hipSuccess) return hip_fail(e, "batch ordering");
-        }
+    // the next mode update of each room waits for this batch
+    for (rl_room* r : rooms) {
+        rl_status s = room_read_end(r, b->stream);
+        if (s != RL_OK) return s;
     }
     return RL_OK;
 }

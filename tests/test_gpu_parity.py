@@ -215,3 +215,43 @@ def test_adapt_from_back_to_back_temporaries():
     bad, total = reservoir_mismatches(seen, res, o.reservoir, o.kappa)
     assert total > 1000 and bad == 0, (bad, total)
     room.close()
+
+
+def test_round_robin_mode_schedule_matches_oracle():
+    """Amortised mode update (K leaves per adapted frame, round robin): after
+    every adapted frame the GPU's modes equal the oracle's schedule (counts
+    exact, rows to float32 rounding); relocalising does not update them."""
+    w = workloads.c1(room_id=4, n_queries=1)
+    o = oracle.Oracle(w.params, w.nodes)
+    room = rl.Room(w.params, w.nodes, 160, 120)
+    K = 48
+    room.set_mode_schedule(K)
+    TL = o.T * o.L
+    frames = w.adapt * 2                      # 8 frames: 384 leaves, wraps past 256
+    for i, f in enumerate(frames):
+        o.adapt(f.depth, f.rgb, f.K, f.pose)
+        o.update_modes_round_robin(K)
+        d, c = dev(f)
+        room.adapt(d, c, f.K, f.pose)
+        _, _, nm_g, modes_g = gpu_state(room, o.T, o.L, o.kappa, o.M)
+        bad, worst = compare_modes(nm_g, modes_g, o.nmodes, o.modes, o.M, range(TL))
+        assert bad == 0 and worst < 1e-5, (i, bad, worst)
+    assert int((o.nmodes > 0).sum()) > 50
+    q = w.queries[0]
+    d, c = dev(q)
+    res = room.relocalise(d, c, q.K, request_seed=5)
+    _, _, nm_g, modes_g = gpu_state(room, o.T, o.L, o.kappa, o.M)
+    np.testing.assert_array_equal(nm_g, o.nmodes)            # no exact update happened
+    leaves = o.traverse(q.depth, q.rgb)
+    ref = oracle.estimate_pose(q.depth, q.rgb, q.K, leaves, nm_g, modes_g.reshape(-1), o.T, o.D, o.M,
+                               w.params, 5)
+    assert res["status"] == ref["status"] and res["winner"] == ref["winner"]
+    if res["status"] == "ok":
+        assert pose_diff(res["pose"], ref["pose"]) < 1e-5
+    # the exact update is still available on request and reaches the exact modes
+    room.update_modes()
+    o.update_modes(all_leaves=False)
+    _, _, nm_g, modes_g = gpu_state(room, o.T, o.L, o.kappa, o.M)
+    bad, worst = compare_modes(nm_g, modes_g, o.nmodes, o.modes, o.M, range(TL))
+    assert bad == 0 and worst < 1e-5
+    room.close()

@@ -16,13 +16,16 @@ from rlsynth import workloads  # noqa: E402
 from tests.gpu_util import dev  # noqa: E402
 
 
-def test_served_equals_alone():
+@pytest.mark.parametrize("leaves_per_frame", [0, 64])
+def test_served_equals_alone(leaves_per_frame):
+    """Under the exact mode schedule and under the amortised one."""
     specs = [workloads.c1(room_id=r, n_queries=3) for r in (0, 1, 2)]
 
     def make_rooms():
         out = []
         for w in specs:
             room = rl.Room(w.params, w.nodes, 160, 120)
+            room.set_mode_schedule(leaves_per_frame)
             for f in w.adapt:
                 d, c = dev(f)
                 room.adapt(d, c, f.K, f.pose)

@@ -302,3 +302,51 @@ def test_plane_score_rectangle_distance_closed_form():
     assert abs(oracle.plane_scores(depth, K, pose2[None], S)[0] - np.sqrt(2.0)) < 1e-12
     S[0, 12:14] = 0                           # infinite plane: only the normal offset counts
     assert abs(oracle.plane_scores(depth, K, pose2[None], S)[0] - 1.0) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# amortised mode update (Sec. 3.2.2): K leaves per frame, round robin
+
+def _adapted_c1_oracle():
+    from rlsynth import workloads
+    w = workloads.c1(room_id=3, n_queries=1)
+    o = oracle.Oracle(w.params, w.nodes)
+    for f in w.adapt:
+        o.adapt(f.depth, f.rgb, f.K, f.pose)
+    return w, o
+
+
+def test_round_robin_touches_exactly_its_range_and_wraps():
+    w, o = _adapted_c1_oracle()
+    ref = oracle.Oracle(w.params, w.nodes)
+    ref.reservoir[:], ref.seen[:] = o.reservoir, o.seen
+    ref.update_modes(all_leaves=True)            # the exact definition, pinned above
+    TL = o.T * o.L
+    assert int((ref.nmodes > 0).sum()) > 50
+    o.rr_cursor = TL - 20                          # a range that wraps: last 20 leaves, first 30
+    nxt = o.update_modes_round_robin(50)
+    assert nxt == 30
+    inside = np.zeros(TL, bool)
+    inside[TL - 20:] = True
+    inside[:30] = True
+    np.testing.assert_array_equal(o.nmodes[inside], ref.nmodes[inside])
+    assert not o.nmodes[~inside].any()             # nothing outside the range was written
+    M = o.M
+    for tl in np.flatnonzero(inside):
+        n = int(ref.nmodes[tl])
+        np.testing.assert_array_equal(o.modes[tl * M * 16:(tl * M + n) * 16], ref.modes[tl * M * 16:(tl * M + n) * 16])
+
+
+def test_round_robin_over_the_whole_forest_equals_the_exact_update():
+    w, o = _adapted_c1_oracle()
+    ref = oracle.Oracle(w.params, w.nodes)
+    ref.reservoir[:], ref.seen[:] = o.reservoir, o.seen
+    ref.update_modes(all_leaves=True)
+    TL = o.T * o.L
+    steps = 0
+    while steps * 48 < TL:
+        o.update_modes_round_robin(48)
+        steps += 1
+    assert o.rr_cursor == (steps * 48) % TL
+    np.testing.assert_array_equal(o.nmodes, ref.nmodes)
+    np.testing.assert_array_equal(o.modes, ref.modes)
