@@ -21,6 +21,14 @@ constexpr long long kMaxPixels = 1LL << 24;   // pixel indices are packed in 24 
 constexpr int kLeafNone = 0xFFFF;
 constexpr uint32_t kTagRes = 1, kTagHyp = 2, kTagScore = 3;
 constexpr int kScoreTile = 8;                 // pixels per scoring wave
+#ifndef RL_FAST_WAVES
+#define RL_FAST_WAVES 1
+#endif
+// All-rounds scoring for jobs with at most kFastMax valid hypotheses (waves
+// of 64): it scores every valid hypothesis in every round, which costs no
+// extra wave while they fit one wave and a growing factor beyond.
+constexpr int kFastWaves = RL_FAST_WAVES;
+constexpr int kFastMax = 64 * kFastWaves;
 
 struct JobState {
     int n_elig;
@@ -28,7 +36,8 @@ struct JobState {
     int n_surv;
     int rounds_run;
     int done;
-    int pad[3];
+    int fast;                 // <= kFastMax valid hypotheses: all rounds scored in one launch
+    int pad[2];
 };
 
 struct Hyp {                 // == rl_hypothesis
@@ -74,6 +83,7 @@ struct Job {
     int* surv;                // [N]
     double* E;                // [N] energy per slot
     double* partial;          // [ptiles][N]
+    double* partial_all;      // [rounds][ptiles][kFastMax] per-round partials of the valid hypotheses
     int* I;                   // [rounds_max * eta]
     int* inl;                 // [rounds_max * eta] refit scratch
     int* trace_slots;         // [rounds_max][N]

@@ -53,6 +53,7 @@ __global__ __launch_bounds__(256) void k_prep(const Job* __restrict__ jobs)
         J.st->n_surv = 0;
         J.st->rounds_run = 0;
         J.st->done = 1;
+        J.st->fast = 0;
     }
 }
 
@@ -511,34 +512,32 @@ __global__ __launch_bounds__(256) void k_ransac_init(const Job* __restrict__ job
         J.st->n_surv = base;
         J.st->rounds_run = 0;
         J.st->done = (base == 0 || J.st->n_elig <= 0) ? 1 : 0;
+        J.st->fast = (!J.st->done && base <= kFastMax) ? 1 : 0;
     }
 }
 
 // ------------------------------------------------------------------------
-// One scoring round: grid.x = ptiles * htiles, one wave per block.  The wave
-// takes TP of this round's pixels and 64 survivors: every lane walks the same
-// pixels and the same mode rows of M(u) (so each row read is one broadcast
-// request for the wave) and accumulates its own hypothesis's Eq. 5 terms, in
-// pixel order, in FP64.  No LDS: occupancy is not tied to |M(u)|.
-__global__ __launch_bounds__(64) void k_score(const Job* __restrict__ jobs, int round, int nptiles)
+// Eq. 5 terms of one hypothesis (R, t) over the pixels k0 .. k0 + tp - 1 of
+// round `round`, summed in pixel order in FP64.  Every lane of a wave walks
+// the same pixels and the same mode rows of M(u) (one broadcast request per
+// row for the wave); rows are loaded four at a time.  Lane 0 of a wave with
+// write_I records the pixels in I.
+__device__ __forceinline__ double mode_q(const float4* row, double y0, double y1, double y2, bool cov)
 {
 #pragma clang fp contract(off)
-    const Job& J = jobs[blockIdx.y];
-    if (J.st->done) return;
-    const int n = J.st->n_surv;
-    const int ptile = blockIdx.x % nptiles, htile = blockIdx.x / nptiles;
-    const int TP = J.TP;
-    const int k0 = ptile * TP;
-    if (k0 >= J.eta || htile * 64 >= n) return;
-    const int tp = min(TP, J.eta - k0);
-    const int pos = htile * 64 + (int)threadIdx.x;
-    const bool active = pos < n;
-    double R[9], t[3];
-    {
-        const Hyp& hy = J.hyps[active ? J.surv[pos] : J.surv[0]];
-        for (int i = 0; i < 9; ++i) R[i] = hy.R[i];
-        for (int i = 0; i < 3; ++i) t[i] = hy.t[i];
-    }
+    const float4 a = ldg(row);
+    const double d0 = y0 - (double)a.x, d1 = y1 - (double)a.y, d2 = y2 - (double)a.z;
+    if (!cov) return d0 * d0 + d1 * d1 + d2 * d2;
+    const float4 b = ldg(row + 1), c = ldg(row + 2);
+    const double m3 = b.x, m4 = b.y, m5 = b.z, m6 = b.w, m7 = c.x, m8 = c.y;
+    return d0 * (m3 * d0 + m4 * d1 + m5 * d2) + d1 * (m4 * d0 + m6 * d1 + m7 * d2)
+         + d2 * (m5 * d0 + m7 * d1 + m8 * d2);
+}
+
+__device__ __forceinline__ double score_pixels(const Job& J, int round, int k0, int tp, bool write_I,
+                                               const double R[9], const double t[3])
+{
+#pragma clang fp contract(off)
     const bool cov = J.use_cov != 0;
     const uint32_t n_elig = (uint32_t)J.st->n_elig;
     double acc = 0.0;
@@ -549,7 +548,7 @@ __global__ __launch_bounds__(64) void k_score(const Job* __restrict__ jobs, int 
         const uint32_t e = below(rv, n_elig);
         const uint4 c0 = ldg(J.ecold + 2 * e), lw = ldg(J.ecold + 2 * e + 1);
         const int p = (int)c0.x;
-        if (htile == 0 && threadIdx.x == 0) J.I[round * J.eta + k] = p;
+        if (write_I && threadIdx.x == 0) J.I[round * J.eta + k] = p;
         double x[3];
         backproject(__uint_as_float(c0.y), p % J.w, p / J.w, J.fx, J.fy, J.cx, J.cy, x);
         const double y0 = R[0] * x[0] + R[1] * x[1] + R[2] * x[2] + t[0];
@@ -560,24 +559,141 @@ __global__ __launch_bounds__(64) void k_score(const Job* __restrict__ jobs, int 
         for (int tr = 0; tr < J.T; ++tr) {
             const int c = (int)count_of(nw, tr);
             const float4* row = J.modes + ((((size_t)tr << J.D) + leaf_of(lw, tr)) * (size_t)J.M) * 4;
-            for (int j = 0; j < c; ++j) {
-                const float4 a = ldg(row + 4 * j);
-                const double d0 = y0 - (double)a.x, d1 = y1 - (double)a.y, d2 = y2 - (double)a.z;
-                double q;
-                if (cov) {
-                    const float4 b = ldg(row + 4 * j + 1), cc = ldg(row + 4 * j + 2);
-                    const double m3 = b.x, m4 = b.y, m5 = b.z, m6 = b.w, m7 = cc.x, m8 = cc.y;
-                    q = d0 * (m3 * d0 + m4 * d1 + m5 * d2) + d1 * (m4 * d0 + m6 * d1 + m7 * d2)
-                      + d2 * (m5 * d0 + m7 * d1 + m8 * d2);
-                } else {
-                    q = d0 * d0 + d1 * d1 + d2 * d2;
-                }
-                best = fmin(best, q);
+            int j = 0;
+            for (; j + 4 <= c; j += 4) {
+                const double q0 = mode_q(row + 4 * j, y0, y1, y2, cov), q1 = mode_q(row + 4 * j + 4, y0, y1, y2, cov);
+                const double q2 = mode_q(row + 4 * j + 8, y0, y1, y2, cov), q3 = mode_q(row + 4 * j + 12, y0, y1, y2, cov);
+                best = fmin(fmin(fmin(fmin(best, q0), q1), q2), q3);
             }
+            for (; j < c; ++j) best = fmin(best, mode_q(row + 4 * j, y0, y1, y2, cov));
         }
         acc += sqrt(fmax(best, 0.0));
     }
+    return acc;
+}
+
+__device__ __forceinline__ void hyp_pose(const Hyp& hy, double R[9], double t[3])
+{
+    for (int i = 0; i < 9; ++i) R[i] = hy.R[i];
+    for (int i = 0; i < 3; ++i) t[i] = hy.t[i];
+}
+
+// One scoring round (jobs with more than kFastMax valid hypotheses): grid.x =
+// ptiles * htiles, one wave per block; the wave takes TP of this round's
+// pixels and 64 survivors, one per lane.
+__global__ __launch_bounds__(64) void k_score(const Job* __restrict__ jobs, int round, int nptiles)
+{
+    const Job& J = jobs[blockIdx.y];
+    if (J.st->done || J.st->fast) return;
+    const int n = J.st->n_surv;
+    const int ptile = blockIdx.x % nptiles, htile = blockIdx.x / nptiles;
+    const int TP = J.TP;
+    const int k0 = ptile * TP;
+    if (k0 >= J.eta || htile * 64 >= n) return;
+    const int tp = min(TP, J.eta - k0);
+    const int pos = htile * 64 + (int)threadIdx.x;
+    const bool active = pos < n;
+    double R[9], t[3];
+    hyp_pose(J.hyps[active ? J.surv[pos] : J.surv[0]], R, t);
+    const double acc = score_pixels(J, round, k0, tp, htile == 0, R, t);
     if (active) J.partial[(size_t)ptile * J.N + pos] = acc;
+}
+
+// Rounds of a job with n valid hypotheses (initial cull, then halving to
+// n_out; at least one round).
+__device__ __forceinline__ int rounds_of(int n, int n_cull, int n_out)
+{
+    int r = 0;
+    bool first = true;
+    while (first || n > n_out) {
+        n = (first && n_cull < n) ? n_cull : (n > n_out ? (n + 1) / 2 : n);
+        ++r;
+        first = false;
+    }
+    return r;
+}
+
+// Every round at once for jobs with at most kFastMax valid hypotheses: which
+// pixels a round adds does not depend on the survivors, so each (round,
+// pixel tile, 64 hypotheses) wave scores valid hypotheses whether or not
+// they survive to that round; the selection below uses only the survivors'
+// values.  grid.x = rounds * ptiles * kFastWaves.
+__global__ __launch_bounds__(64) void k_score_all(const Job* __restrict__ jobs, int nptiles)
+{
+    const Job& J = jobs[blockIdx.y];
+    if (!J.st->fast) return;
+    const int n = J.st->n_surv;
+    const int htile = blockIdx.x % kFastWaves, rt = blockIdx.x / kFastWaves;
+    const int round = rt / nptiles, ptile = rt % nptiles;
+    if (htile * 64 >= n || round >= rounds_of(n, J.n_cull, J.n_out)) return;
+    const int k0 = ptile * J.TP;
+    if (k0 >= J.eta) return;
+    const int tp = min(J.TP, J.eta - k0);
+    const int pos = htile * 64 + (int)threadIdx.x;
+    double R[9], t[3];
+    hyp_pose(J.hyps[ldg(J.surv + (pos < n ? pos : 0))], R, t);
+    const double acc = score_pixels(J, round, k0, tp, htile == 0, R, t);
+    if (pos < n) J.partial_all[((size_t)round * nptiles + ptile) * kFastMax + pos] = acc;
+}
+
+// The rounds' selections for those jobs, one block per job, thread =
+// position in the list of valid hypotheses: same accumulation (tile order,
+// rounds in order), ranking by (energy, slot), initial cull and halving as
+// k_select.
+__global__ __launch_bounds__(kFastMax) void k_select_all(const Job* __restrict__ jobs, int nptiles)
+{
+    const Job& J = jobs[blockIdx.x];
+    if (!J.st->fast) return;
+    __shared__ double sE[kFastMax];
+    __shared__ int sS[kFastMax], sA[kFastMax];
+    const int n0 = J.st->n_surv;
+    const int lane = (int)threadIdx.x;
+    const bool valid = lane < n0;
+    const int slot = valid ? ldg(J.surv + lane) : INT_MAX;
+    const int ptiles = min(nptiles, (J.eta + J.TP - 1) / J.TP);
+    double E = 0.0;
+    bool alive = valid;
+    int n = n0, round = 0, rank = 0;
+    bool first = true;
+    while (first || n > J.n_out) {
+        if (alive) {
+            double acc = 0.0;
+            for (int tI = 0; tI < ptiles; ++tI)
+                acc += ldg(J.partial_all + ((size_t)round * nptiles + tI) * kFastMax + lane);
+            E = E + acc;
+        }
+        const double key = isnan(E) ? INFINITY : E;
+        sE[lane] = key;
+        sS[lane] = slot;
+        sA[lane] = alive ? 1 : 0;
+        __syncthreads();
+        const int keep = (first && J.n_cull < n) ? J.n_cull : (n > J.n_out ? (n + 1) / 2 : n);
+        rank = 0;
+        if (alive)
+            for (int q = 0; q < n0; ++q)
+                rank += (sA[q] && (sE[q] < key || (sE[q] == key && sS[q] < slot))) ? 1 : 0;
+        if (alive && rank < keep) {
+            if (J.trace) {
+                J.trace_slots[(size_t)round * J.N + rank] = slot;
+                J.trace_E[(size_t)round * J.N + rank] = key;
+            }
+        } else {
+            alive = false;
+        }
+        __syncthreads();
+        n = keep;
+        ++round;
+        first = false;
+    }
+    if (alive) {
+        J.surv[rank] = slot;
+        J.E[slot] = E;
+    }
+    if (lane == 0) {
+        J.st->n_surv = n;
+        J.st->rounds_run = round;
+        J.st->done = 1;
+    }
 }
 
 // Adds the round's partial sums (tile order), ranks survivors by
@@ -585,7 +701,7 @@ __global__ __launch_bounds__(64) void k_score(const Job* __restrict__ jobs, int 
 __global__ __launch_bounds__(1024) void k_select(const Job* __restrict__ jobs, int round, int nptiles)
 {
     const Job& J = jobs[blockIdx.y];
-    if (J.st->done) return;
+    if (J.st->done || J.st->fast) return;
     extern __shared__ unsigned char s_raw[];
     const int n = J.st->n_surv;
     double* sE = reinterpret_cast<double*>(s_raw);
@@ -594,7 +710,7 @@ __global__ __launch_bounds__(1024) void k_select(const Job* __restrict__ jobs, i
     for (int p = threadIdx.x; p < n; p += blockDim.x) {
         const int s = J.surv[p];
         double acc = 0.0;
-        for (int tI = 0; tI < ptiles; ++tI) acc += J.partial[(size_t)tI * J.N + p];
+        for (int tI = 0; tI < ptiles; ++tI) acc += ldg(J.partial + (size_t)tI * J.N + p);
         const double e = J.E[s] + acc;
         J.E[s] = e;
         sE[p] = isnan(e) ? INFINITY : e;
@@ -949,6 +1065,15 @@ hipError_t launch_score(const Job* jobs, int njobs, int round, int nptiles, int 
 {
     const int htiles = (maxSurv + 63) / 64;
     k_score<<<dim3(nptiles * htiles, njobs), dim3(64), 0, st>>>(jobs, round, nptiles);
+    RL_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_score_all(const Job* jobs, int njobs, int rounds, int nptiles, hipStream_t st)
+{
+    k_score_all<<<dim3(rounds * nptiles * kFastWaves, njobs), dim3(64), 0, st>>>(jobs, nptiles);
+    RL_CHECK_LAUNCH();
+    k_select_all<<<dim3(njobs), dim3(kFastMax), 0, st>>>(jobs, nptiles);
     RL_CHECK_LAUNCH();
     return hipSuccess;
 }

@@ -28,6 +28,7 @@ hipError_t launch_hyp_search(const Job* jobs, int njobs, int maxN, int maxIters,
 hipError_t launch_hyp_finalize(const Job* jobs, int njobs, int maxN, hipStream_t st);
 hipError_t launch_score(const Job* jobs, int njobs, int round, int nptiles, int maxSurv,
                         hipStream_t st);
+hipError_t launch_score_all(const Job* jobs, int njobs, int rounds, int nptiles, hipStream_t st);
 hipError_t launch_select(const Job* jobs, int njobs, int round, int nptiles, int maxN, hipStream_t st);
 hipError_t launch_finalize(const Job* jobs, int njobs, int maxIlen, hipStream_t st);
 hipError_t launch_plane_scores(const float* depth, int w, int h, float fx, float fy, float cx, float cy,
@@ -115,6 +116,7 @@ int score_tile(int) { return kScoreTile; }
 // Per-frame (relocalisation) scratch of one job slot.
 struct FrameLayout {
     size_t state, result, leaves, nmt, nm, tile_count, eligible, ecold, erec, hyp_best, hyps, surv, E, partial,
+        partial_all,
         I, inl, trace_slots, trace_E, total;
     int ew;
 };
@@ -147,6 +149,7 @@ FrameLayout frame_layout(int maxP, int N, int eta, int rounds, int TP, int rows_
     L.E = c.take((size_t)N * 8);
     const int ptiles = (eta + TP - 1) / TP;
     L.partial = c.take((size_t)ptiles * N * 8);
+    L.partial_all = c.take((size_t)rounds * ptiles * kFastMax * 8);
     L.I = c.take((size_t)rounds * eta * 4);
     L.inl = c.take((size_t)rounds * eta * 4);
     L.trace_slots = c.take((size_t)rounds * N * 4);
@@ -478,6 +481,7 @@ static Job make_job(const rl_room* r, char* scr, const FrameLayout& FL, const rl
     J.surv = reinterpret_cast<int*>(scr + FL.surv);
     J.E = reinterpret_cast<double*>(scr + FL.E);
     J.partial = reinterpret_cast<double*>(scr + FL.partial);
+    J.partial_all = reinterpret_cast<double*>(scr + FL.partial_all);
     J.I = reinterpret_cast<int*>(scr + FL.I);
     J.inl = reinterpret_cast<int*>(scr + FL.inl);
     J.trace_slots = reinterpret_cast<int*>(scr + FL.trace_slots);
@@ -820,6 +824,7 @@ static hipError_t launch_sequence(const Job* jobs, int njobs, int maxP, int maxN
     RL_MARK(RL_TIMER_HYP_SEARCH, stop);
     RL_TRY(launch_hyp_finalize(jobs, njobs, maxN, st));
     RL_MARK(RL_TIMER_RANSAC, start);
+    RL_TRY(launch_score_all(jobs, njobs, (int)entering.size(), nptiles, st));
     for (int r = 0; r < (int)entering.size(); ++r) {
         RL_TRY(launch_score(jobs, njobs, r, nptiles, entering[r], st));
         RL_TRY(launch_select(jobs, njobs, r, nptiles, maxN, st));
