@@ -88,9 +88,9 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=4, help="oracle relocalisations (0 = skip)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--timer", default="hyp_search", choices=["traverse", "hyp_search", "ransac"])
-    ap.add_argument("--serve-seconds", type=float, default=0.0,
+    ap.add_argument("--serve-seconds", type=float, default=3.0,
                     help="measured seconds per arrival rate of the served leg (0 = skip it)")
-    ap.add_argument("--serve-rates", default="200,500,1000")
+    ap.add_argument("--serve-rates", default="500,1000,2000")
     ap.add_argument("--serve-rooms", type=int, default=16)
     ap.add_argument("--serve-leaves-per-frame", type=int, default=256,
                     help="mode update schedule of the served rooms: 0 exact, K leaves per adapted frame")

@@ -25,7 +25,7 @@ RL_OK, RL_NO_POSE, RL_EINVAL, RL_ENOMEM, RL_EDEVICE, RL_EBUSY = 0, 1, -1, -2, -3
 
 (BUF_NODES, BUF_RESERVOIR, BUF_SEEN, BUF_MODES, BUF_NMODES, BUF_LEAVES, BUF_NM, BUF_ELIGIBLE,
  BUF_HYPS, BUF_ILIST, BUF_TRACE_SLOTS, BUF_TRACE_ENERGY, BUF_SURVIVORS, BUF_ENERGY,
- BUF_DIRTY) = range(15)
+ BUF_DIRTY, BUF_CBOX, BUF_EREC) = range(17)
 
 HYP_DTYPE = np.dtype([("R", "<f4", (9,)), ("t", "<f4", (3,)), ("pix", "<i4", (3,)),
                       ("mode", "<i4", (3,)), ("iter", "<i4"), ("valid", "<i4")])

@@ -36,7 +36,8 @@ __global__ __launch_bounds__(256) void k_ad_items(AdaptArgs a)
         return;
     }
     int leaf[T];
-    route<T>(a.nodes, a.L - 1, a.D, a.depth, a.rgb, a.w, a.h, x, y, d, a.s, leaf);
+    const PlanarProbe pr{a.depth, a.rgb, a.w};
+    route<T>(a.nodes, a.L - 1, a.D, pr, a.w, a.h, x, y, d, a.s, leaf);
     double xc[3];
     backproject(d, x, y, a.fx, a.fy, a.cx, a.cy, xc);
     float xw[3];
@@ -287,6 +288,7 @@ __global__ __launch_bounds__(256) void k_rqs(RqsArgs a)
                 row[1] = make_float4((float)(ca / det), (float)(cb2 / det), (float)(cc / det), (float)(cd / det));
                 row[2] = make_float4((float)(ce / det), (float)(cf / det), (float)mr, (float)mg);
                 row[3] = make_float4((float)mb, 0.0f, 0.0f, 0.0f);
+                a.cbox[(size_t)tl * a.M + m] = colour_box((float)mr, (float)mg, (float)mb, a.theta_col);
             }
         }
         if (tid == 0) {

@@ -20,7 +20,10 @@ constexpr int kMaxTrees = 8;
 constexpr long long kMaxPixels = 1LL << 24;   // pixel indices are packed in 24 bits
 constexpr int kLeafNone = 0xFFFF;
 constexpr uint32_t kTagRes = 1, kTagHyp = 2, kTagScore = 3;
-constexpr int kScoreTile = 8;                 // pixels per scoring wave
+#ifndef RL_SCORE_TILE
+#define RL_SCORE_TILE 4
+#endif
+constexpr int kScoreTile = RL_SCORE_TILE;     // pixels per scoring wave
 #ifndef RL_FAST_WAVES
 #define RL_FAST_WAVES 1
 #endif
@@ -55,10 +58,12 @@ struct Job {
     const float4* nodes;      // [T][NT] (dx, dy, tau, kind bits)
     const float4* modes;      // [T][L][M] rows of 4 float4
     const uint8_t* nmodes;    // [T][L]
+    const uint2* cbox;        // [T][L][M] colour box per mode row (see colour_box)
     int T, D, M, pad0;
     // frame
     const float* depth;
     const uint8_t* rgb;
+    uint2* probe;             // [P] interleaved probe image (depth bits, RGB bytes), built per frame
     int w, h;
     float fx, fy, cx, cy;
     float s;                  // w / ref_width (float32 division)
@@ -129,6 +134,8 @@ struct RqsArgs {
     uint8_t* nmodes;
     int kappa, M, min_size;
     double sigma, tau, lambda;
+    uint2* cbox;              // [T][L][M] colour boxes of the mode rows
+    float theta_col;
     // round-robin schedule: when rr_count > 0, the leaves rr_first ...
     // rr_first + rr_count - 1 (mod n_leaves) are clustered instead of the
     // dirty list, whose state is left as it is
@@ -216,15 +223,57 @@ __device__ __forceinline__ void backproject(float d, int x, int y, float fx, flo
 // every level all T node fetches and probe fetches are in flight together.
 // Float32 definition: offset = rint(delta * s * (1/d)), probe clamped to the
 // image, f = D(p) - D(q) or C(p,c) - C(q,c), right child iff f >= tau.
-template <int T>
-__device__ __forceinline__ void route(const float4* __restrict__ nodes, int NT, int D,
-                                      const float* __restrict__ depth,
-                                      const uint8_t* __restrict__ rgb, int w, int h, int x, int y,
-                                      float d, float s, int leaf[T])
+// Probe reads of the routing: from the caller's planar depth and RGB8, or
+// from the interleaved probe image (one 8-byte word per pixel: depth bits,
+// then R, G, B bytes) that a relocalisation builds first, so that a probe is
+// one load with no branch on the feature kind.  Both give the same values.
+struct PlanarProbe {
+    const float* depth;
+    const uint8_t* rgb;
+    int w;
+    __device__ __forceinline__ void centre(int pc, float cc[3]) const
+    {
+        cc[0] = (float)ldg(rgb + 3 * pc);
+        cc[1] = (float)ldg(rgb + 3 * pc + 1);
+        cc[2] = (float)ldg(rgb + 3 * pc + 2);
+    }
+    typedef float2 Word;
+    __device__ __forceinline__ Word load(int q, uint32_t c) const
+    {
+        return make_float2(ldg(depth + q), (float)ldg(rgb + 3 * q + c));
+    }
+    __device__ __forceinline__ void decode(Word v, uint32_t, float& dq, float& cq) const
+    {
+        dq = v.x;
+        cq = v.y;
+    }
+};
+
+struct PackedProbe {
+    const uint2* img;
+    __device__ __forceinline__ void centre(int pc, float cc[3]) const
+    {
+        const uint2 v = ldg(img + pc);
+        cc[0] = (float)(v.y & 0xFFu);
+        cc[1] = (float)((v.y >> 8) & 0xFFu);
+        cc[2] = (float)((v.y >> 16) & 0xFFu);
+    }
+    typedef uint2 Word;
+    __device__ __forceinline__ Word load(int q, uint32_t) const { return ldg(img + q); }
+    __device__ __forceinline__ void decode(Word v, uint32_t c, float& dq, float& cq) const
+    {
+        dq = __uint_as_float(v.x);
+        cq = (float)((v.y >> (8 * c)) & 0xFFu);
+    }
+};
+
+template <int T, class Probe>
+__device__ __forceinline__ void route(const float4* __restrict__ nodes, int NT, int D, const Probe& pr, int w,
+                                      int h, int x, int y, float d, float s, int leaf[T])
 {
     const float inv = 1.0f / d;
-    const int pc = y * w + x;
-    const float cc[3] = {(float)ldg(rgb + 3 * pc), (float)ldg(rgb + 3 * pc + 1), (float)ldg(rgb + 3 * pc + 2)};
+    float cc[3];
+    pr.centre(y * w + x, cc);
     int idx[T];
 #pragma unroll
     for (int t = 0; t < T; ++t) idx[t] = 0;
@@ -232,6 +281,9 @@ __device__ __forceinline__ void route(const float4* __restrict__ nodes, int NT, 
         float4 nd[T];
 #pragma unroll
         for (int t = 0; t < T; ++t) nd[t] = ldg(nodes + t * NT + idx[t]);
+        // every tree's probe is issued before any is used
+        typename Probe::Word pv[T];
+        uint32_t ch[T];
 #pragma unroll
         for (int t = 0; t < T; ++t) {
             float fox = rintf((nd[t].x * s) * inv);
@@ -240,15 +292,19 @@ __device__ __forceinline__ void route(const float4* __restrict__ nodes, int NT, 
             foy = fminf(fmaxf(foy, -1048576.0f), 1048576.0f);
             const int qx = min(max(x + (int)fox, 0), w - 1);
             const int qy = min(max(y + (int)foy, 0), h - 1);
-            const int q = qy * w + qx;
-            const uint32_t kind = __float_as_uint(nd[t].w);
-            // both probes are read (no divergent branch around the loads);
-            // kinds are validated at creation (<= 3) and the clamp keeps the
+            const int q = (int)__umul24((uint32_t)qy, (uint32_t)w) + qx;    // w * h < 2^24
+            // kinds are validated at creation (<= 3); the clamp keeps the
             // colour read inside the pixel whatever the device memory holds
-            const uint32_t c = min(kind - 1u, 2u);
-            const float dq = ldg(depth + q);
-            const float cq = (float)ldg(rgb + 3 * q + c);
-            const float f = kind == 0u ? d - dq : (c == 0u ? cc[0] : c == 1u ? cc[1] : cc[2]) - cq;
+            ch[t] = min(__float_as_uint(nd[t].w) - 1u, 2u);
+            pv[t] = pr.load(q, ch[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            float dq, cq;
+            pr.decode(pv[t], ch[t], dq, cq);
+            const uint32_t c = ch[t];
+            const float fc = (c == 0u ? cc[0] : c == 1u ? cc[1] : cc[2]) - cq;
+            const float f = __float_as_uint(nd[t].w) == 0u ? d - dq : fc;
             idx[t] = 2 * idx[t] + 1 + (f >= nd[t].z ? 1 : 0);
         }
     }
@@ -398,6 +454,56 @@ __device__ __forceinline__ bool erec_bit(const uint64_t* rec, uint64_t h, uint32
     if (m < 56) return (h >> (8 + m)) & 1u;
     const uint32_t k = m - 56;
     return (ldg(rec + 1 + (k >> 6)) >> (k & 63)) & 1u;
+}
+
+// Colour box of a mode: per channel, the range [lo, hi] of integer pixel
+// values v in 0..255 that pass the colour check !(|v - c| > theta) in float32
+// (lo > hi: none).  (float)v - c is monotone in v and so is the rounding, so
+// the passing values form an interval, found by testing the few integers
+// around c - theta and c + theta.  Packed as lo bytes (R, G, B) in x, hi in y.
+__device__ __forceinline__ bool colour_pass(float v, float c, float theta) { return !(fabsf(v - c) > theta); }
+
+__device__ __forceinline__ void colour_range(float c, float theta, uint32_t& lo, uint32_t& hi)
+{
+    const int s = (int)fminf(fmaxf(floorf(c - theta) - 1.0f, 0.0f), 255.0f);
+    const int e = (int)fminf(fmaxf(ceilf(c + theta) + 1.0f, 0.0f), 255.0f);
+    lo = 1u;
+    hi = 0u;
+    for (int v = s; v <= min(s + 3, 255); ++v)
+        if (colour_pass((float)v, c, theta)) {
+            lo = (uint32_t)v;
+            break;
+        }
+    for (int v = e; v >= max(e - 3, 0); --v)
+        if (colour_pass((float)v, c, theta)) {
+            hi = (uint32_t)v;
+            break;
+        }
+    if (hi < lo) {
+        lo = 1u;
+        hi = 0u;
+    }
+}
+
+__device__ __forceinline__ uint2 colour_box(float r, float g, float b, float theta)
+{
+    uint32_t l0, h0, l1, h1, l2, h2;
+    colour_range(r, theta, l0, h0);
+    colour_range(g, theta, l1, h1);
+    colour_range(b, theta, l2, h2);
+    return make_uint2(l0 | (l1 << 8) | (l2 << 16), h0 | (h1 << 8) | (h2 << 16));
+}
+
+// rgb: R | G << 8 | B << 16
+__device__ __forceinline__ bool box_pass(uint2 box, uint32_t rgb)
+{
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const uint32_t v = (rgb >> (8 * k)) & 0xFFu;
+        ok = ok && v >= ((box.x >> (8 * k)) & 0xFFu) && v <= ((box.y >> (8 * k)) & 0xFFu);
+    }
+    return ok;
 }
 
 __device__ __forceinline__ int modes_total(uint2 nw, int T)

@@ -58,6 +58,19 @@ __global__ __launch_bounds__(256) void k_prep(const Job* __restrict__ jobs)
 }
 
 // ------------------------------------------------------------------------
+// Frame ingest: the interleaved probe image (depth bits, R, G, B bytes) that
+// routing reads, one coalesced pass over the caller's planar buffers.
+__global__ __launch_bounds__(256) void k_pack(const Job* __restrict__ jobs)
+{
+    const Job& J = jobs[blockIdx.y];
+    const int P = J.w * J.h;
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= P) return;
+    const uint32_t r = ldg(J.rgb + 3 * p), g = ldg(J.rgb + 3 * p + 1), b = ldg(J.rgb + 3 * p + 2);
+    J.probe[p] = make_uint2(__float_as_uint(ldg(J.depth + p)), r | (g << 8) | (b << 16));
+}
+
+// ------------------------------------------------------------------------
 // One thread per pixel, all trees in lockstep.  Writes leaves (16 B/pixel),
 // per-tree mode counts (8 B/pixel), |M(u)| and the tile's eligible count.
 template <int T>
@@ -71,7 +84,7 @@ __global__ __launch_bounds__(256) void k_traverse(const Job* __restrict__ jobs)
     bool elig = false;
     if (p < P) {
         const int x = p % w, y = p / w;
-        const float d = ldg(J.depth + p);
+        const float d = __uint_as_float(ldg(J.probe + p).x);
         uint16_t lf[8];
         uint8_t nmt[8];
 #pragma unroll
@@ -83,7 +96,8 @@ __global__ __launch_bounds__(256) void k_traverse(const Job* __restrict__ jobs)
         if (depth_ok(d)) {
             const int NT = (1 << J.D) - 1;
             int leaf[T];
-            route<T>(J.nodes, NT, J.D, J.depth, J.rgb, w, h, x, y, d, J.s, leaf);
+            const PackedProbe pr{J.probe};
+            route<T>(J.nodes, NT, J.D, pr, w, h, x, y, d, J.s, leaf);
 #pragma unroll
             for (int t = 0; t < T; ++t) {
                 lf[t] = (uint16_t)leaf[t];
@@ -110,43 +124,70 @@ __global__ __launch_bounds__(256) void k_traverse(const Job* __restrict__ jobs)
     if (threadIdx.x == 0) J.tile_count[blockIdx.x] = tot;
 }
 
-// Colour check of pair (pixel, mode) (check 1 of Sec. 3.2.3): L-infinity
-// distance between the pixel's colour and the mode's mean colour, float32.
-__device__ __forceinline__ bool colour_ok(const float px[3], const float4* row, float theta)
-{
-    const float4 c2 = ldg(row + 2), c3 = ldg(row + 3);
-    return !(fabsf(px[0] - c2.z) > theta || fabsf(px[1] - c2.w) > theta || fabsf(px[2] - c3.x) > theta);
-}
-
 // Record of eligible pixel p at list position e: |M(u)| and the colour-check
-// bit of every mode of M(u), in M(u) order.
-__device__ __forceinline__ void write_erec(const Job& J, int e, int p)
+// bit of every mode of M(u), in M(u) order, from the modes' colour boxes.
+__device__ __forceinline__ void write_erec(const Job& J, int e, uint4 lw, uint2 nw, uint32_t rgb)
 {
-    const uint4 lw = ldg(reinterpret_cast<const uint4*>(J.leaves) + p);
-    const uint2 nw = ldg(reinterpret_cast<const uint2*>(J.nmt) + p);
-    const float px[3] = {(float)ldg(J.rgb + 3 * p), (float)ldg(J.rgb + 3 * p + 1), (float)ldg(J.rgb + 3 * p + 2)};
     uint64_t* rec = J.erec + (size_t)e * J.ew;
     uint32_t m = 0;
     uint64_t w0 = 0, cur = 0;
     for (int t = 0; t < J.T; ++t) {
         const int c = (int)count_of(nw, t);
-        const float4* row = J.modes + ((((size_t)t << J.D) + leaf_of(lw, t)) * (size_t)J.M) * 4;
-        for (int j = 0; j < c; ++j, ++m) {
-            const uint64_t b = colour_ok(px, row + 4 * j, J.theta_col) ? 1u : 0u;
-            if (m < 56) {
-                w0 |= b << (8 + m);
-            } else {
-                const uint32_t k = m - 56;
-                cur |= b << (k & 63);
-                if ((k & 63) == 63) {
-                    rec[1 + (k >> 6)] = cur;
-                    cur = 0;
+        const uint2* box = J.cbox + (((size_t)t << J.D) + leaf_of(lw, t)) * (size_t)J.M;
+        for (int j0 = 0; j0 < c; j0 += 4) {
+            // four modes' boxes loaded ahead of their checks
+            const int nj = min(4, c - j0);
+            uint2 bx[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) bx[u] = u < nj ? ldg(box + j0 + u) : make_uint2(1u, 0u);
+            for (int u = 0; u < nj; ++u, ++m) {
+                const uint64_t b = box_pass(bx[u], rgb) ? 1u : 0u;
+                if (m < 56) {
+                    w0 |= b << (8 + m);
+                } else {
+                    const uint32_t k = m - 56;
+                    cur |= b << (k & 63);
+                    if ((k & 63) == 63) {
+                        rec[1 + (k >> 6)] = cur;
+                        cur = 0;
+                    }
                 }
             }
         }
     }
     if (m > 56 && ((m - 56) & 63)) rec[1 + ((m - 56) >> 6)] = cur;
     rec[0] = w0 | m;
+}
+
+// Raster-order compaction of eligible pixels over the traversal's tiles, and
+// their records.
+// Exclusive scan of the traversal's per-tile eligible counts (in place) and
+// the list length; one block per job.
+__global__ __launch_bounds__(1024) void k_tile_scan(const Job* __restrict__ jobs)
+{
+    const Job& J = jobs[blockIdx.x];
+    const int P = J.w * J.h;
+    const int ntiles = (P + 255) / 256;
+    __shared__ int s_sum[1024];
+    const int per = (ntiles + 1023) / 1024;
+    const int t0 = (int)threadIdx.x * per, t1 = min(t0 + per, ntiles);
+    int sum = 0;
+    for (int i = t0; i < t1; ++i) sum += J.tile_count[i];
+    s_sum[threadIdx.x] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {          // inclusive scan of the thread sums
+        const int v = (int)threadIdx.x >= off ? s_sum[threadIdx.x - off] : 0;
+        __syncthreads();
+        s_sum[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int run = s_sum[threadIdx.x] - sum;
+    for (int i = t0; i < t1; ++i) {
+        const int c = J.tile_count[i];
+        J.tile_count[i] = run;
+        run += c;
+    }
+    if (threadIdx.x == 1023) J.st->n_elig = s_sum[1023];
 }
 
 // Raster-order compaction of eligible pixels over the traversal's tiles, and
@@ -158,16 +199,7 @@ __global__ __launch_bounds__(256) void k_eligible(const Job* __restrict__ jobs)
     const int ntiles = (P + 255) / 256;
     if ((int)blockIdx.x >= ntiles) return;
     __shared__ int s_wave[4];
-    __shared__ int s_red[256];
-    int acc = 0;
-    for (int j = threadIdx.x; j < (int)blockIdx.x; j += 256) acc += J.tile_count[j];
-    s_red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int stride = 128; stride > 0; stride >>= 1) {
-        if ((int)threadIdx.x < stride) s_red[threadIdx.x] += s_red[threadIdx.x + stride];
-        __syncthreads();
-    }
-    const int base = s_red[0];
+    const int base = J.tile_count[blockIdx.x];
     const int p = blockIdx.x * 256 + threadIdx.x;
     const bool e = p < P && ldg(J.nm + p) > 0;
     int tot;
@@ -177,11 +209,11 @@ __global__ __launch_bounds__(256) void k_eligible(const Job* __restrict__ jobs)
         J.eligible[k] = p;
         const uint4 lw = ldg(reinterpret_cast<const uint4*>(J.leaves) + p);
         const uint2 nw = ldg(reinterpret_cast<const uint2*>(J.nmt) + p);
-        J.ecold[2 * k] = make_uint4((uint32_t)p, __float_as_uint(ldg(J.depth + p)), nw.x, nw.y);
+        const uint2 pv = ldg(J.probe + p);
+        J.ecold[2 * k] = make_uint4((uint32_t)p, pv.x, nw.x, nw.y);
         J.ecold[2 * k + 1] = lw;
-        write_erec(J, k, p);
+        write_erec(J, k, lw, nw, pv.y);
     }
-    if ((int)blockIdx.x == ntiles - 1 && threadIdx.x == 0) J.st->n_elig = base + tot;
 }
 
 // ------------------------------------------------------------------------
@@ -578,6 +610,23 @@ __device__ __forceinline__ void hyp_pose(const Hyp& hy, double R[9], double t[3]
     for (int i = 0; i < 3; ++i) t[i] = hy.t[i];
 }
 
+// sum of n values p[0], p[stride], ... in index order; loads are issued 16 at
+// a time ahead of the additions
+__device__ __forceinline__ double sum_in_order(const double* p, size_t stride, int n)
+{
+    double acc = 0.0;
+    int i = 0;
+    for (; i + 16 <= n; i += 16) {
+        double v[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = ldg(p + (size_t)(i + k) * stride);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) acc += v[k];
+    }
+    for (; i < n; ++i) acc += ldg(p + (size_t)i * stride);
+    return acc;
+}
+
 // One scoring round (jobs with more than kFastMax valid hypotheses): grid.x =
 // ptiles * htiles, one wave per block; the wave takes TP of this round's
 // pixels and 64 survivors, one per lane.
@@ -657,10 +706,7 @@ __global__ __launch_bounds__(kFastMax) void k_select_all(const Job* __restrict__
     bool first = true;
     while (first || n > J.n_out) {
         if (alive) {
-            double acc = 0.0;
-            for (int tI = 0; tI < ptiles; ++tI)
-                acc += ldg(J.partial_all + ((size_t)round * nptiles + tI) * kFastMax + lane);
-            E = E + acc;
+            E = E + sum_in_order(J.partial_all + (size_t)round * nptiles * kFastMax + lane, kFastMax, ptiles);
         }
         const double key = isnan(E) ? INFINITY : E;
         sE[lane] = key;
@@ -709,8 +755,7 @@ __global__ __launch_bounds__(1024) void k_select(const Job* __restrict__ jobs, i
     const int ptiles = min(nptiles, (J.eta + J.TP - 1) / J.TP);
     for (int p = threadIdx.x; p < n; p += blockDim.x) {
         const int s = J.surv[p];
-        double acc = 0.0;
-        for (int tI = 0; tI < ptiles; ++tI) acc += ldg(J.partial + (size_t)tI * J.N + p);
+        const double acc = sum_in_order(J.partial + p, (size_t)J.N, ptiles);
         const double e = J.E[s] + acc;
         J.E[s] = e;
         sE[p] = isnan(e) ? INFINITY : e;
@@ -1015,6 +1060,8 @@ hipError_t launch_prep(const Job* jobs, int njobs, int maxN, hipStream_t st)
 hipError_t launch_traverse(const Job* jobs, int njobs, int maxP, int T, hipStream_t st)
 {
     const dim3 blk(256), gp((maxP + 255) / 256, njobs);
+    k_pack<<<gp, blk, 0, st>>>(jobs);
+    RL_CHECK_LAUNCH();
     switch (T) {
         case 1: k_traverse<1><<<gp, blk, 0, st>>>(jobs); break;
         case 2: k_traverse<2><<<gp, blk, 0, st>>>(jobs); break;
@@ -1032,6 +1079,8 @@ hipError_t launch_traverse(const Job* jobs, int njobs, int maxP, int T, hipStrea
 
 hipError_t launch_eligible(const Job* jobs, int njobs, int maxP, hipStream_t st)
 {
+    k_tile_scan<<<dim3(njobs), dim3(1024), 0, st>>>(jobs);
+    RL_CHECK_LAUNCH();
     k_eligible<<<dim3((maxP + 255) / 256, njobs), dim3(256), 0, st>>>(jobs);
     RL_CHECK_LAUNCH();
     return hipSuccess;

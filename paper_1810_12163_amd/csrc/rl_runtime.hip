@@ -115,7 +115,7 @@ int score_tile(int) { return kScoreTile; }
 
 // Per-frame (relocalisation) scratch of one job slot.
 struct FrameLayout {
-    size_t state, result, leaves, nmt, nm, tile_count, eligible, ecold, erec, hyp_best, hyps, surv, E, partial,
+    size_t state, result, probe, leaves, nmt, nm, tile_count, eligible, ecold, erec, hyp_best, hyps, surv, E, partial,
         partial_all,
         I, inl, trace_slots, trace_E, total;
     int ew;
@@ -135,6 +135,7 @@ FrameLayout frame_layout(int maxP, int N, int eta, int rounds, int TP, int rows_
     FrameLayout L;
     L.state = c.take(sizeof(JobState));
     L.result = c.take(sizeof(rl_result));
+    L.probe = c.take((size_t)maxP * 8);
     L.leaves = c.take((size_t)maxP * 16);
     L.nmt = c.take((size_t)maxP * 8);
     L.nm = c.take((size_t)maxP);
@@ -159,7 +160,7 @@ FrameLayout frame_layout(int maxP, int N, int eta, int rounds, int TP, int rows_
 }
 
 struct PersistLayout {
-    size_t nodes, reservoir, seen, dirty, dirty_list, counters, modes, nmodes, total;
+    size_t nodes, reservoir, seen, dirty, dirty_list, counters, modes, nmodes, cbox, total;
 };
 
 PersistLayout persist_layout(const rl_params& p)
@@ -175,6 +176,7 @@ PersistLayout persist_layout(const rl_params& p)
     P.counters = c.take(256);
     P.modes = c.take(T * L * (size_t)p.max_cluster_count * 64);
     P.nmodes = c.take(T * L);
+    P.cbox = c.take(T * L * (size_t)p.max_cluster_count * 8);
     P.total = c.cur;
     return P;
 }
@@ -440,6 +442,7 @@ static Job make_job(const rl_room* r, char* scr, const FrameLayout& FL, const rl
     J.nodes = reinterpret_cast<const float4*>(r->pers + r->PL.nodes);
     J.modes = reinterpret_cast<const float4*>(r->pers + r->PL.modes);
     J.nmodes = reinterpret_cast<const uint8_t*>(r->pers + r->PL.nmodes);
+    J.cbox = reinterpret_cast<const uint2*>(r->pers + r->PL.cbox);
     J.T = r->T;
     J.D = r->D;
     J.M = r->M;
@@ -468,6 +471,7 @@ static Job make_job(const rl_room* r, char* scr, const FrameLayout& FL, const rl
     const uint64_t k = stream_key64(r->p.seed, request_seed);
     J.key0 = (uint32_t)k;
     J.key1 = (uint32_t)(k >> 32);
+    J.probe = reinterpret_cast<uint2*>(scr + FL.probe);
     J.leaves = reinterpret_cast<uint16_t*>(scr + FL.leaves);
     J.nmt = reinterpret_cast<uint8_t*>(scr + FL.nmt);
     J.nm = reinterpret_cast<uint8_t*>(scr + FL.nm);
@@ -507,6 +511,8 @@ static RqsArgs rqs_args(rl_room* r)
     a.sigma = r->p.clusterer_sigma;
     a.tau = r->p.clusterer_tau;
     a.lambda = r->p.cov_regulariser;
+    a.cbox = reinterpret_cast<uint2*>(r->pers + r->PL.cbox);
+    a.theta_col = r->p.max_colour_linf;
     a.rr_first = 0;
     a.rr_count = 0;
     a.n_leaves = (uint32_t)(r->T * r->L);
@@ -976,6 +982,8 @@ RL_API rl_status relocaliser_buffer(const rl_room* r, int32_t which, size_t* off
         case RL_BUF_TRACE_ENERGY: *offset = r->FL.trace_E; *bytes = (size_t)r->rounds_cap * r->N * 8; *region = 1; break;
         case RL_BUF_SURVIVORS: *offset = r->FL.surv; *bytes = (size_t)r->N * 4; *region = 1; break;
         case RL_BUF_ENERGY: *offset = r->FL.E; *bytes = (size_t)r->N * 8; *region = 1; break;
+        case RL_BUF_CBOX: *offset = r->PL.cbox; *bytes = TL * r->M * 8; *region = 0; break;
+        case RL_BUF_EREC: *offset = r->FL.erec; *bytes = (size_t)r->maxP * r->FL.ew * 8; *region = 1; break;
         default: return fail(RL_EINVAL, "unknown buffer %d", which);
     }
     return RL_OK;

@@ -229,3 +229,41 @@ def test_mixed_batch_equals_plain(c2, c3_room):
 def dataclasses_replace(s, **kw):
     import dataclasses
     return dataclasses.replace(s, **kw)
+
+
+def test_c2_colour_check_bits_equal_the_float_test(c2):
+    """Every eligible pixel's record holds |M(u)| and, for every mode of M(u),
+    the outcome of the colour check as the oracle evaluates it (L-infinity in
+    float32 against the mode's mean colour), for the full 640x480 frame."""
+    w, o, room = c2
+    q = w.queries[1]
+    d, c = dev(q)
+    res = room.relocalise(d, c, q.K, request_seed=9)
+    n_el = res["n_eligible"]
+    P = q.depth.size
+    el = room.buffer_np(rl.BUF_ELIGIBLE, np.int32)[:n_el].copy()
+    rec = room.buffer_np(rl.BUF_EREC, np.uint64)[:n_el].copy()        # one word per entry (|M(u)| <= 56)
+    leaves = room.buffer_np(rl.BUF_LEAVES, np.uint16).reshape(-1, 8)[:P, :o.T].astype(np.int64)
+    nmodes = room.buffer_np(rl.BUF_NMODES, np.uint8).reshape(o.T, o.L)
+    modes = room.buffer_np(rl.BUF_MODES, np.float32).reshape(o.T, o.L, o.M, 16)
+    theta = np.float32(w.params["max_colour_linf"])
+    lv = leaves[el]                                               # (n, T)
+    cnt = nmodes[np.arange(o.T)[None, :], lv].astype(np.int64)    # (n, T)
+    total = cnt.sum(1)
+    np.testing.assert_array_equal((rec & np.uint64(0xFF)).astype(np.int64), total)
+    px = q.rgb.reshape(-1, 3)[el].astype(np.float32)              # (n, 3)
+    checked = 0
+    m0 = np.zeros(n_el, np.int64)
+    for t in range(o.T):
+        for j in range(o.M):
+            has = j < cnt[:, t]
+            col = modes[t, lv[:, t], j, 10:13]                        # (n, 3) float32
+            ok = ~np.any(np.abs(px - col) > theta, axis=1)
+            m = m0 + j
+            bit = ((rec >> (np.uint64(8) + m.astype(np.uint64))) & np.uint64(1)).astype(bool)
+            sel = has & (m < 56)
+            np.testing.assert_array_equal(bit[sel], ok[sel])
+            checked += int(sel.sum())
+        m0 = m0 + cnt[:, t]
+    print(f"[colour bits] {n_el} entries, {checked} (pixel, mode) checks", flush=True)
+    assert checked > 1_000_000
