@@ -39,8 +39,7 @@ struct JobState {
     int n_surv;
     int rounds_run;
     int done;
-    int fast;                 // <= kFastMax valid hypotheses: all rounds scored in one launch
-    int pad[2];
+    int pad[3];
 };
 
 struct Hyp {                 // == rl_hypothesis
@@ -88,7 +87,7 @@ struct Job {
     int* surv;                // [N]
     double* E;                // [N] energy per slot
     double* partial;          // [ptiles][N]
-    double* partial_all;      // [rounds][ptiles][kFastMax] per-round partials of the valid hypotheses
+    double* partial_all;      // [rounds][ptiles][kFastMax] per-round partials once survivors fit kFastMax
     int* I;                   // [rounds_max * eta]
     int* inl;                 // [rounds_max * eta] refit scratch
     int* trace_slots;         // [rounds_max][N]

@@ -53,7 +53,6 @@ __global__ __launch_bounds__(256) void k_prep(const Job* __restrict__ jobs)
         J.st->n_surv = 0;
         J.st->rounds_run = 0;
         J.st->done = 1;
-        J.st->fast = 0;
     }
 }
 
@@ -544,7 +543,6 @@ __global__ __launch_bounds__(256) void k_ransac_init(const Job* __restrict__ job
         J.st->n_surv = base;
         J.st->rounds_run = 0;
         J.st->done = (base == 0 || J.st->n_elig <= 0) ? 1 : 0;
-        J.st->fast = (!J.st->done && base <= kFastMax) ? 1 : 0;
     }
 }
 
@@ -627,14 +625,14 @@ __device__ __forceinline__ double sum_in_order(const double* p, size_t stride, i
     return acc;
 }
 
-// One scoring round (jobs with more than kFastMax valid hypotheses): grid.x =
+// One scoring round (while a job has more than kFastMax survivors): grid.x =
 // ptiles * htiles, one wave per block; the wave takes TP of this round's
 // pixels and 64 survivors, one per lane.
 __global__ __launch_bounds__(64) void k_score(const Job* __restrict__ jobs, int round, int nptiles)
 {
     const Job& J = jobs[blockIdx.y];
-    if (J.st->done || J.st->fast) return;
     const int n = J.st->n_surv;
+    if (J.st->done || n <= kFastMax) return;
     const int ptile = blockIdx.x % nptiles, htile = blockIdx.x / nptiles;
     const int TP = J.TP;
     const int k0 = ptile * TP;
@@ -650,10 +648,9 @@ __global__ __launch_bounds__(64) void k_score(const Job* __restrict__ jobs, int 
 
 // Rounds of a job with n valid hypotheses (initial cull, then halving to
 // n_out; at least one round).
-__device__ __forceinline__ int rounds_of(int n, int n_cull, int n_out)
+__device__ __forceinline__ int rounds_of(int n, int n_cull, int n_out, int r = 0)
 {
-    int r = 0;
-    bool first = true;
+    bool first = r == 0;
     while (first || n > n_out) {
         n = (first && n_cull < n) ? n_cull : (n > n_out ? (n + 1) / 2 : n);
         ++r;
@@ -662,19 +659,21 @@ __device__ __forceinline__ int rounds_of(int n, int n_cull, int n_out)
     return r;
 }
 
-// Every round at once for jobs with at most kFastMax valid hypotheses: which
-// pixels a round adds does not depend on the survivors, so each (round,
-// pixel tile, 64 hypotheses) wave scores valid hypotheses whether or not
-// they survive to that round; the selection below uses only the survivors'
-// values.  grid.x = rounds * ptiles * kFastWaves.
+// The remaining rounds at once, once a job's survivors fit kFastMax lanes
+// (from its first round when it has at most kFastMax valid hypotheses, else
+// after the per-round kernels have halved it that far): which pixels a round
+// adds does not depend on the survivors, so each (round, pixel tile, 64
+// hypotheses) wave scores every current survivor, whether or not it lives to
+// that round; the selection below uses only the survivors' values.
+// grid.x = rounds * ptiles * kFastWaves (absolute round index).
 __global__ __launch_bounds__(64) void k_score_all(const Job* __restrict__ jobs, int nptiles)
 {
     const Job& J = jobs[blockIdx.y];
-    if (!J.st->fast) return;
-    const int n = J.st->n_surv;
+    if (J.st->done) return;
+    const int n = J.st->n_surv, r0 = J.st->rounds_run;
     const int htile = blockIdx.x % kFastWaves, rt = blockIdx.x / kFastWaves;
     const int round = rt / nptiles, ptile = rt % nptiles;
-    if (htile * 64 >= n || round >= rounds_of(n, J.n_cull, J.n_out)) return;
+    if (htile * 64 >= n || round < r0 || round >= rounds_of(n, J.n_cull, J.n_out, r0)) return;
     const int k0 = ptile * J.TP;
     if (k0 >= J.eta) return;
     const int tp = min(J.TP, J.eta - k0);
@@ -685,14 +684,14 @@ __global__ __launch_bounds__(64) void k_score_all(const Job* __restrict__ jobs, 
     if (pos < n) J.partial_all[((size_t)round * nptiles + ptile) * kFastMax + pos] = acc;
 }
 
-// The rounds' selections for those jobs, one block per job, thread =
-// position in the list of valid hypotheses: same accumulation (tile order,
-// rounds in order), ranking by (energy, slot), initial cull and halving as
-// k_select.
+// Those rounds' selections, one block per job, thread = position in the
+// survivor list: same accumulation (tile order, rounds in order, onto the
+// energies of earlier rounds), ranking by (energy, slot), initial cull and
+// halving as k_select.
 __global__ __launch_bounds__(kFastMax) void k_select_all(const Job* __restrict__ jobs, int nptiles)
 {
     const Job& J = jobs[blockIdx.x];
-    if (!J.st->fast) return;
+    if (J.st->done) return;
     __shared__ double sE[kFastMax];
     __shared__ int sS[kFastMax], sA[kFastMax];
     const int n0 = J.st->n_surv;
@@ -700,14 +699,13 @@ __global__ __launch_bounds__(kFastMax) void k_select_all(const Job* __restrict__
     const bool valid = lane < n0;
     const int slot = valid ? ldg(J.surv + lane) : INT_MAX;
     const int ptiles = min(nptiles, (J.eta + J.TP - 1) / J.TP);
-    double E = 0.0;
+    double E = valid ? J.E[slot] : 0.0;
     bool alive = valid;
-    int n = n0, round = 0, rank = 0;
-    bool first = true;
+    int n = n0, round = J.st->rounds_run, rank = 0;
+    bool first = round == 0;
     while (first || n > J.n_out) {
-        if (alive) {
+        if (alive)
             E = E + sum_in_order(J.partial_all + (size_t)round * nptiles * kFastMax + lane, kFastMax, ptiles);
-        }
         const double key = isnan(E) ? INFINITY : E;
         sE[lane] = key;
         sS[lane] = slot;
@@ -747,7 +745,7 @@ __global__ __launch_bounds__(kFastMax) void k_select_all(const Job* __restrict__
 __global__ __launch_bounds__(1024) void k_select(const Job* __restrict__ jobs, int round, int nptiles)
 {
     const Job& J = jobs[blockIdx.y];
-    if (J.st->done || J.st->fast) return;
+    if (J.st->done || J.st->n_surv <= kFastMax) return;
     extern __shared__ unsigned char s_raw[];
     const int n = J.st->n_surv;
     double* sE = reinterpret_cast<double*>(s_raw);

@@ -830,11 +830,12 @@ static hipError_t launch_sequence(const Job* jobs, int njobs, int maxP, int maxN
     RL_MARK(RL_TIMER_HYP_SEARCH, stop);
     RL_TRY(launch_hyp_finalize(jobs, njobs, maxN, st));
     RL_MARK(RL_TIMER_RANSAC, start);
-    RL_TRY(launch_score_all(jobs, njobs, (int)entering.size(), nptiles, st));
-    for (int r = 0; r < (int)entering.size(); ++r) {
+    // rounds with more than kFastMax survivors one at a time, the rest at once
+    for (int r = 0; r < (int)entering.size() && entering[r] > kFastMax; ++r) {
         RL_TRY(launch_score(jobs, njobs, r, nptiles, entering[r], st));
         RL_TRY(launch_select(jobs, njobs, r, nptiles, maxN, st));
     }
+    RL_TRY(launch_score_all(jobs, njobs, (int)entering.size(), nptiles, st));
     RL_MARK(RL_TIMER_RANSAC, stop);
     RL_TRY(launch_finalize(jobs, njobs, (int)entering.size() * maxEta, st));
 #undef RL_MARK
