@@ -36,8 +36,25 @@ MI355X_HBM = 8.0e12
 # (3 sub + 3 mul + 2 add each), six square roots, three rigidity differences
 # (sub + abs + compare) and three distance compares.
 HYP_ITER_OPS = 2 * 98 + 6 + 3 * 6 + 9 + 6 * 8 + 6 + 3 * 3 + 3
-# Algorithmic bytes of one node test: the 16-byte node record and the 4-byte probe.
-NODE_TEST_BYTES = 20
+# Bytes one node test gathers: the 16-byte node record and the 8-byte probe
+# word (depth and colour of the offset pixel).  Nearly all of them come from
+# the vector L1 and L2 (the top levels of every tree and the neighbourhood of
+# each pixel are shared), so the traversal is priced against the L1 return
+# rate, taken as 64 B per clock per CU (the CDNA3 vector-L1 figure):
+# 256 CUs x 64 B x 2.4 GHz.
+NODE_TEST_BYTES = 24
+MI355X_L1 = 256 * 64 * 2.4e9
+# HBM bytes per pixel of the traversal stage that no cache can avoid: depth
+# (4) and colour (3) read and the probe word (8) written by the packing
+# kernel, the probe word read back (8) and the leaf indices written (16).
+TRAVERSE_PIXEL_HBM = 4 + 3 + 8 + 8 + 16
+# FP64 flops of Eq. 5 scoring: per mode evaluation d = y - mu (3), Sigma^-1 d
+# (9 mul + 6 add), d . (Sigma^-1 d) (3 mul + 2 add) and the running minimum (1);
+# per (hypothesis, pixel) the rigid transform (9 mul + 9 add) and the square
+# root with its accumulation (2).
+SCORE_MODE_FLOPS = 24
+SCORE_PAIR_FLOPS = 20
+MI355X_FP64 = 78.6e12
 
 
 def log(*a):
@@ -94,6 +111,8 @@ def main():
     ap.add_argument("--serve-rooms", type=int, default=16)
     ap.add_argument("--serve-leaves-per-frame", type=int, default=256,
                     help="mode update schedule of the served rooms: 0 exact, K leaves per adapted frame")
+    ap.add_argument("--schedule", default="auto",
+                    help="launch schedule 'ipt,fast_waves' (e.g. 4,1), or 'auto' to time every one first")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device-to-device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -146,6 +165,17 @@ def main():
     B = args.batch
     frames = [(i % len(w.queries), i // len(w.queries)) for i in range(B)]   # (query, seed)
 
+    # ---- launch schedule (result-invariant) -------------------------------
+    from paper_1810_12163_amd import autotune
+    fixed = None if args.schedule == "auto" else tuple(int(v) for v in args.schedule.split(","))
+    tuning = {}
+    if fixed:
+        room.set_schedule(*fixed)
+    elif args.plain > 0:
+        best, t = autotune.tune_room(room, qd[0], qc[0], w.queries[0].K, reps=5)
+        tuning["plain"] = {f"{k[0]},{k[1]}": float(np.median(v)) for k, v in t.items()}
+        log(f"[bench] plain schedule {best} (median ms {tuning['plain']})")
+
     # ---- plain path: one frame per synchronous call -----------------------
     lat = []
     for k in range((3 + args.plain) if args.plain > 0 else 0):
@@ -165,7 +195,10 @@ def main():
     # algorithmic work of one batch, from the plain path on the same (frame, seed) pairs
     iters = 0
     node_tests = 0
+    mode_evals = 0
+    pairs = 0
     Imax = p["max_candidate_generation_iterations"]
+    eta = p["ransac_inliers_per_iteration"]
     plain_res = []
     for (qi, s) in frames:
         r = room.relocalise(qd[qi], qc[qi], w.queries[qi].K, request_seed=s)
@@ -174,6 +207,16 @@ def main():
         it = np.where(hy["valid"] != 0, hy["iter"] + 1, Imax)
         iters += int(it.sum())
         node_tests += int(np.count_nonzero(w.queries[qi].depth > 0)) * p["n_trees"] * p["depth"]
+        # scoring work as defined: survivors entering each round x that round's pixels x |M(u)|
+        if r["rounds"] > 0:
+            I = room.buffer_np(rl.BUF_ILIST, np.int32)[:r["rounds"] * eta].reshape(r["rounds"], eta)
+            nm = room.buffer_np(rl.BUF_NM, np.uint8).astype(np.int64)
+            n = r["n_valid"]
+            for rr in range(r["rounds"]):
+                mode_evals += n * int(nm[I[rr]].sum())
+                pairs += n * eta
+                cull = p["max_pose_candidates_after_cull"]
+                n = cull if (rr == 0 and cull < n) else ((n + 1) // 2 if n > p["max_relocalisations_to_output"] else n)
 
     # ---- batched path ----------------------------------------------------
     rounds = rl.rounds_for(p["max_pose_candidates"], p["max_pose_candidates_after_cull"],
@@ -181,6 +224,12 @@ def main():
     batch = rl.Batch(B, 640, 480, p["max_pose_candidates"], p["ransac_inliers_per_iteration"], rounds,
                      p["n_trees"], p["n_trees"] * p["max_cluster_count"], device=dev)
     reqs = [(room, qd[qi], qc[qi], w.queries[qi].K, s) for (qi, s) in frames]
+    if fixed:
+        batch.set_schedule(*fixed)
+    else:
+        best, t = autotune.tune_batch(batch, reqs, reps=5, use_graph=not args.no_graph)
+        tuning["batched"] = {f"{k[0]},{k[1]}": float(np.median(v)) for k, v in t.items()}
+        log(f"[bench] batched schedule {best} (median ms {tuning['batched']})")
     timer = {"traverse": rl.TIMER_TRAVERSE, "hyp_search": rl.TIMER_HYP_SEARCH, "ransac": rl.TIMER_RANSAC}[args.timer]
     use_graph = not args.no_graph
     for _ in range(args.warmup):
@@ -198,44 +247,61 @@ def main():
     log(f"[bench] batched: {value:.1f} reloc/s ({elapsed / args.steps * 1e3:.2f} ms per {B}-frame step)")
 
     # kernel timing: the same steps with direct launches, HIP events recorded by
-    # the library around the chosen kernel on the stream it launches it on
+    # the library around each timed stage on the stream it launches it on
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record()
     ev1.record()               # torch creates the underlying hipEvent on first record
     torch.cuda.synchronize()
-    batch.set_timer(timer, ev0, ev1)
-    kern_ms = []
-    for _ in range(args.steps):
-        batch.relocalise(reqs, use_graph=False)
-        kern_ms.append(ev0.elapsed_time(ev1))
-    batch.set_timer(rl.TIMER_NONE)
-    log(f"[bench] {args.timer}: {np.mean(kern_ms):.3f} ms per launch ({B} frames)")
+    stage_ms = {}
+    for name, t in (("hyp_search", rl.TIMER_HYP_SEARCH), ("traverse", rl.TIMER_TRAVERSE), ("ransac", rl.TIMER_RANSAC)):
+        batch.set_timer(t, ev0, ev1)
+        ms = []
+        for _ in range(args.steps):
+            batch.relocalise(reqs, use_graph=False)
+            ms.append(ev0.elapsed_time(ev1))
+        batch.set_timer(rl.TIMER_NONE)
+        stage_ms[name] = float(np.mean(ms))
+        log(f"[bench] {name}: {stage_ms[name]:.3f} ms per launch ({B} frames)")
 
     same = all(np.array_equal(a["pose"], b["pose"]) and a["energy"] == b["energy"]
                for a, b in zip(res, plain_res))
     errs = [scene.pose_error(r["pose"].astype(np.float64), w.queries[qi].pose) for r, (qi, _) in zip(res, frames)]
     ok = [e[0] <= 0.05 and e[1] <= 5.0 for e in errs]
 
-    # ---- roofline of the timed kernel --------------------------------------
-    kavg = float(np.mean(kern_ms)) * 1e-3
-    if timer == rl.TIMER_HYP_SEARCH:
+    # ---- rooflines -------------------------------------------------------------
+    def roof_search(ms):
+        k = ms * 1e-3
         ops = iters * HYP_ITER_OPS
         traffic = profiled_traffic("k_hyp_search_640x480_batch64_counters.txt") if B == 64 else None
-        roof = dict(kernel="k_hyp_search", bound="alu", achieved=ops / kavg / 1e12,
-                    peak=MI355X_VALU_OPS / 1e12, unit="TOP/s (VALU lane-ops)",
-                    frac=ops / kavg / MI355X_VALU_OPS, traffic=traffic, launch_ms=kavg * 1e3,
-                    work=f"{iters} generation iterations x {HYP_ITER_OPS} ops",
+        return dict(kernel="k_hyp_search", bound="alu", achieved=ops / k / 1e12, peak=MI355X_VALU_OPS / 1e12,
+                    unit="TOP/s (VALU lane-ops)", frac=ops / k / MI355X_VALU_OPS, traffic=traffic,
+                    launch_ms=ms, work=f"{iters} generation iterations x {HYP_ITER_OPS} ops",
                     traffic_unit="HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                    traffic_GBps=(traffic / kavg / 1e9) if traffic else None)
-    elif timer == rl.TIMER_TRAVERSE:
+                    traffic_GBps=(traffic / k / 1e9) if traffic else None)
+
+    def roof_traverse(ms):
+        k = ms * 1e-3
         by = node_tests * NODE_TEST_BYTES
-        roof = dict(kernel="k_traverse", bound="hbm", achieved=by / kavg / 1e9, peak=MI355X_HBM / 1e9,
-                    unit="GB/s", frac=by / kavg / MI355X_HBM, traffic=None, launch_ms=kavg * 1e3,
-                    work=f"{node_tests} node tests x {NODE_TEST_BYTES} B")
-    else:
-        roof = dict(kernel="k_score+k_select", bound="alu", achieved=None, peak=MI355X_VALU_OPS / 1e12,
-                    unit="TOP/s", frac=None, traffic=None, launch_ms=kavg * 1e3)
+        hbm = B * 640 * 480 * TRAVERSE_PIXEL_HBM
+        return dict(kernel="k_pack+k_traverse", bound="l1", achieved=by / k / 1e9, peak=MI355X_L1 / 1e9,
+                    unit="GB/s", frac=by / k / MI355X_L1, traffic=None, launch_ms=ms,
+                    hbm_unavoidable_GBps=hbm / k / 1e9, hbm_frac=hbm / k / MI355X_HBM,
+                    work=f"{node_tests} node tests x {NODE_TEST_BYTES} B gathered through the vector L1 "
+                         f"(peak derived: 256 CUs x 64 B/clk x 2.4 GHz); {B} frames x 307200 px x "
+                         f"{TRAVERSE_PIXEL_HBM} B unavoidable HBM traffic")
+
+    def roof_scoring(ms):
+        k = ms * 1e-3
+        fl = mode_evals * SCORE_MODE_FLOPS + pairs * SCORE_PAIR_FLOPS
+        return dict(kernel="k_score+k_select+k_score_all+k_select_all", bound="alu", achieved=fl / k / 1e12,
+                    peak=MI355X_FP64 / 1e12, unit="TFLOP/s (FP64)", frac=fl / k / MI355X_FP64, traffic=None,
+                    launch_ms=ms, work=f"{mode_evals} mode evaluations x {SCORE_MODE_FLOPS} + {pairs} "
+                                       f"(hypothesis, pixel) pairs x {SCORE_PAIR_FLOPS} FP64 flops")
+
+    rooflines = {"hyp_search": roof_search(stage_ms["hyp_search"]), "traverse": roof_traverse(stage_ms["traverse"]),
+                 "ransac": roof_scoring(stage_ms["ransac"])}
+    roof = rooflines[args.timer]
 
     # ---- CPU baseline: the oracle on a bounded sample ----------------------
     cpu = None
@@ -266,9 +332,13 @@ def main():
                                "<=10 modes/leaf; 50 adaptation frames; 1024 hypotheses; eta 500; "
                                "10 halving rounds; inlier refit",
                    "form": "batched" + (" (hipGraph replay)" if use_graph else ""), "batch": B,
-                   "distinct_frames": len(w.queries)},
+                   "distinct_frames": len(w.queries),
+                   "schedule": {"plain": list(room.schedule), "batched": list(batch.schedule),
+                                "tuned": not fixed}},
+        "schedule_tuning_ms": tuning or None,
         "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
         "roofline_kernel": {k: v for k, v in roof.items() if k not in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
+        "rooflines_other": {n: r for n, r in rooflines.items() if r is not roof},
         "cpu_baseline": cpu,
         "plain": plain,
         "batched": dict(relocs_per_s=value, step_p50_ms=percentile(step_ms, 50),

@@ -342,6 +342,20 @@ enum {
 rl_status relocaliser_set_timer(rl_room* room, int32_t kernel, void* start_event, void* stop_event);
 rl_status rl_batch_set_timer(rl_batch* b, int32_t kernel, void* start_event, void* stop_event);
 
+/*
+ * Launch schedule (for callers that tune it to their device and workload):
+ * ipt = hypothesis-search iterations per thread (2, 4 or 8); fast_waves =
+ * width in 64-lane waves (1, 2 or 4) of the scoring that, once a request has
+ * at most 64 * fast_waves surviving hypotheses, scores all its remaining
+ * rounds at once.  Neither changes any result: each hypothesis draws from its
+ * own Philox counters whichever thread runs it, and every energy is summed in
+ * the same order.  Defaults: ipt 4, fast_waves 1.  Applies to later calls;
+ * RL_EINVAL for other values.  Not thread-safe against concurrent calls on
+ * the same room / batch.
+ */
+rl_status relocaliser_set_schedule(rl_room* room, int32_t ipt, int32_t fast_waves);
+rl_status rl_batch_set_schedule(rl_batch* b, int32_t ipt, int32_t fast_waves);
+
 /* Thread-local message of the last error. */
 const char* rl_last_error(void);
 

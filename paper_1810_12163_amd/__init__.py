@@ -101,8 +101,12 @@ EXPORTS = [
     "relocaliser_set_trace", "rl_batch_workspace_bytes", "rl_batch_create", "rl_batch_destroy",
     "rl_batch_relocalise", "rl_batch_relocalise_async", "rl_last_error", "rl_version",
     "relocaliser_set_timer", "rl_batch_set_timer", "relocaliser_relocalise_opts", "rl_plane_scores",
-    "relocaliser_set_mode_schedule",
+    "relocaliser_set_mode_schedule", "relocaliser_set_schedule", "rl_batch_set_schedule",
 ]
+
+# launch schedules the library accepts (iterations per thread, fast waves)
+SCHEDULE_IPT = (2, 4, 8)
+SCHEDULE_FAST_WAVES = (1, 2, 4)
 
 TIMER_NONE, TIMER_TRAVERSE, TIMER_HYP_SEARCH, TIMER_RANSAC = 0, 1, 2, 3
 
@@ -143,6 +147,8 @@ def lib():
         L.rl_plane_scores.argtypes = [P, ctypes.POINTER(Frame), P, I32, P, I32, P]
         L.rl_batch_set_timer.argtypes = [P, I32, P, P]
         L.relocaliser_set_mode_schedule.argtypes = [P, I32]
+        L.relocaliser_set_schedule.argtypes = [P, I32, I32]
+        L.rl_batch_set_schedule.argtypes = [P, I32, I32]
         L.rl_last_error.restype = ctypes.c_char_p
         L.rl_version.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -228,6 +234,7 @@ class Room:
                                     self.persistent.data_ptr(), self.scratch.data_ptr(),
                                     self.stream.cuda_stream, ctypes.byref(h)))
         self.handle = h.value
+        self.schedule = (4, 1)
         self.max_width, self.max_height = max_width, max_height
 
     def close(self):
@@ -264,6 +271,12 @@ class Room:
         """0: exact mode update before each relocalisation; K > 0: RQS of the
         next K leaves (round robin) after each adapted frame."""
         _check(lib().relocaliser_set_mode_schedule(self.handle, int(leaves_per_frame)))
+
+    def set_schedule(self, ipt: int, fast_waves: int):
+        """Result-invariant launch schedule: search iterations per thread
+        (2, 4, 8) and all-rounds scoring width in waves (1, 2, 4)."""
+        _check(lib().relocaliser_set_schedule(self.handle, int(ipt), int(fast_waves)))
+        self.schedule = (int(ipt), int(fast_waves))
 
     def relocalise(self, depth, rgb, K, request_seed: int = 0, n_hypotheses: int = 0, n_cull: int = 0,
                    n_out: int = 0, final_refine: int = -1) -> dict:
@@ -337,6 +350,7 @@ class Batch:
         _check(L.rl_batch_create(ctypes.byref(self._bp), self.workspace.data_ptr(),
                                  self.stream.cuda_stream, ctypes.byref(h)))
         self.handle = h.value
+        self.schedule = (4, 1)
         self.max_frames = max_frames
 
     def close(self):
@@ -355,6 +369,12 @@ class Batch:
         """Record torch.cuda.Event pair (enable_timing=True) around a kernel."""
         _check(lib().rl_batch_set_timer(self.handle, kernel, start.cuda_event if start else None,
                                         stop.cuda_event if stop else None))
+
+    def set_schedule(self, ipt: int, fast_waves: int):
+        """Result-invariant launch schedule: search iterations per thread
+        (2, 4, 8) and all-rounds scoring width in waves (1, 2, 4)."""
+        _check(lib().rl_batch_set_schedule(self.handle, int(ipt), int(fast_waves)))
+        self.schedule = (int(ipt), int(fast_waves))
 
     def _requests(self, reqs):
         torch = _torch()

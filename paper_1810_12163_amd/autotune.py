@@ -1,0 +1,90 @@
+"""Chooses the launch schedule of a batch or a room by timing it on the
+caller's own requests.
+
+The schedule (search iterations per thread, width of the all-rounds scoring)
+changes no result: every hypothesis draws its samples from its own Philox
+counters whichever thread runs it, and every energy is summed in the same
+order.  So the choice is a pure timing decision, made on the device and
+workload that will use it.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import time
+
+import numpy as np
+
+from . import SCHEDULE_FAST_WAVES, SCHEDULE_IPT, Result
+
+DEFAULT = (4, 1)
+
+
+def candidates(ipts=SCHEDULE_IPT, fast_waves=SCHEDULE_FAST_WAVES) -> list:
+    """Every (iterations per thread, fast waves) pair, the default first."""
+    out = [DEFAULT] if DEFAULT[0] in ipts and DEFAULT[1] in fast_waves else []
+    out += [(i, f) for i in ipts for f in fast_waves if (i, f) != DEFAULT]
+    return out
+
+
+def pick(timings: dict, default=DEFAULT, margin: float = 0.02):
+    """The schedule with the lowest median time.  The default stays unless
+    another beats it by more than `margin` (a fraction of its time), so that
+    timing noise does not move the choice; ties go to the earlier key."""
+    if not timings:
+        raise ValueError("no timings")
+    med = {k: float(np.median(v)) for k, v in timings.items()}
+    best = min(med, key=lambda k: (med[k], list(med).index(k)))
+    if default in med and med[best] >= med[default] * (1.0 - margin):
+        return default
+    return best
+
+
+def tune_batch(batch, reqs, schedules=None, reps: int = 5, warmup: int = 2, use_graph: bool = True):
+    """Times `reqs` (the Batch.relocalise request list) under each schedule,
+    sets the fastest on `batch` and returns (schedule, {schedule: [ms]}).
+    Each time is the GPU time between events on the batch's stream around
+    one queued batch (graph replays after the warm-up capture)."""
+    import torch
+
+    schedules = schedules or candidates()
+    out = torch.empty(len(reqs) * ctypes.sizeof(Result), dtype=torch.uint8, device=batch.device)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    timings = {}
+    for sc in schedules:
+        batch.set_schedule(*sc)
+        for _ in range(warmup):
+            batch.relocalise_async(reqs, out, use_graph=use_graph)
+        ms = []
+        for _ in range(reps):
+            ev0.record(batch.stream)
+            batch.relocalise_async(reqs, out, use_graph=use_graph)
+            ev1.record(batch.stream)
+            ev1.synchronize()
+            ms.append(ev0.elapsed_time(ev1))
+        timings[sc] = ms
+    best = pick(timings)
+    batch.set_schedule(*best)
+    return best, timings
+
+
+def tune_room(room, depth, rgb, K, schedules=None, reps: int = 7, warmup: int = 2, request_seed: int = 0):
+    """Times one synchronous relocalisation of (depth, rgb, K) under each
+    schedule (host wall clock, as a caller of the synchronous call sees it),
+    sets the fastest on `room` and returns (schedule, {schedule: [ms]})."""
+    schedules = schedules or candidates()
+    timings = {}
+    for sc in schedules:
+        room.set_schedule(*sc)
+        for _ in range(warmup):
+            room.relocalise(depth, rgb, K, request_seed=request_seed)
+        ms = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            room.relocalise(depth, rgb, K, request_seed=request_seed)
+            ms.append((time.perf_counter() - t0) * 1e3)
+        timings[sc] = ms
+    best = pick(timings)
+    room.set_schedule(*best)
+    return best, timings

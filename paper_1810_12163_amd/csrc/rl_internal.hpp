@@ -24,14 +24,10 @@ constexpr uint32_t kTagRes = 1, kTagHyp = 2, kTagScore = 3;
 #define RL_SCORE_TILE 4
 #endif
 constexpr int kScoreTile = RL_SCORE_TILE;     // pixels per scoring wave
-#ifndef RL_FAST_WAVES
-#define RL_FAST_WAVES 1
-#endif
-// All-rounds scoring for jobs with at most kFastMax valid hypotheses (waves
-// of 64): it scores every valid hypothesis in every round, which costs no
-// extra wave while they fit one wave and a growing factor beyond.
-constexpr int kFastWaves = RL_FAST_WAVES;
-constexpr int kFastMax = 64 * kFastWaves;
+// All-rounds scoring (once a job's survivors fit fast_max = 64 * fast waves
+// lanes) keeps its partials with this stride: up to 4 waves of hypotheses.
+constexpr int kMaxFastWaves = 4;
+constexpr int kFastStride = 64 * kMaxFastWaves;
 
 struct JobState {
     int n_elig;
@@ -70,6 +66,7 @@ struct Job {
     int N, I_max, eta, n_cull, n_out, use_cov, final_refine, trace;
     float theta_col;
     int TP;                   // pixels per scoring block
+    int fast_max;             // survivors scored round by round while above this (64 * fast waves)
     double min_sq_dist, theta_rig, theta_in;
     uint32_t key0, key1;
     // scratch
@@ -87,7 +84,7 @@ struct Job {
     int* surv;                // [N]
     double* E;                // [N] energy per slot
     double* partial;          // [ptiles][N]
-    double* partial_all;      // [rounds][ptiles][kFastMax] per-round partials once survivors fit kFastMax
+    double* partial_all;      // [rounds][ptiles][kFastStride] per-round partials once survivors fit fast_max
     int* I;                   // [rounds_max * eta]
     int* inl;                 // [rounds_max * eta] refit scratch
     int* trace_slots;         // [rounds_max][N]

@@ -399,13 +399,14 @@ __device__ __forceinline__ bool hyp_stage_b(const Job& J, int n_elig, int slot, 
     return true;
 }
 
-// Tuning of the search kernel: iterations per thread per block, and an
-// optional minimum of resident waves per SIMD (caps registers; 0 = none).
-#ifndef RL_HYP_IPT
-#define RL_HYP_IPT 4
-#endif
+// Tuning of the search kernel: an optional minimum of resident waves per
+// SIMD (caps registers; 0 = none) and the early exit; the iterations per
+// thread are chosen at run time (rl_batch_set_schedule).
 #ifndef RL_HYP_WAVES
 #define RL_HYP_WAVES 0
+#endif
+#ifndef RL_HYP_EARLY_EXIT
+#define RL_HYP_EARLY_EXIT 1
 #endif
 #if RL_HYP_WAVES > 0
 #define RL_HYP_BOUNDS __launch_bounds__(256, RL_HYP_WAVES)
@@ -453,7 +454,11 @@ __global__ RL_HYP_BOUNDS void k_hyp_search(const Job* __restrict__ jobs, int Nma
     if (threadIdx.x == 0) {
         s_n = 0;
         s_best = INT_MAX;
+#if RL_HYP_EARLY_EXIT
         s_skip = __hip_atomic_load(&J.hyp_best[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < it0;
+#else
+        s_skip = 0;
+#endif
     }
     __syncthreads();
     if (s_skip) return;
@@ -625,14 +630,14 @@ __device__ __forceinline__ double sum_in_order(const double* p, size_t stride, i
     return acc;
 }
 
-// One scoring round (while a job has more than kFastMax survivors): grid.x =
+// One scoring round (while a job has more than fast_max survivors): grid.x =
 // ptiles * htiles, one wave per block; the wave takes TP of this round's
 // pixels and 64 survivors, one per lane.
 __global__ __launch_bounds__(64) void k_score(const Job* __restrict__ jobs, int round, int nptiles)
 {
     const Job& J = jobs[blockIdx.y];
     const int n = J.st->n_surv;
-    if (J.st->done || n <= kFastMax) return;
+    if (J.st->done || n <= J.fast_max) return;
     const int ptile = blockIdx.x % nptiles, htile = blockIdx.x / nptiles;
     const int TP = J.TP;
     const int k0 = ptile * TP;
@@ -659,19 +664,19 @@ __device__ __forceinline__ int rounds_of(int n, int n_cull, int n_out, int r = 0
     return r;
 }
 
-// The remaining rounds at once, once a job's survivors fit kFastMax lanes
-// (from its first round when it has at most kFastMax valid hypotheses, else
+// The remaining rounds at once, once a job's survivors fit fast_max lanes
+// (from its first round when it has at most fast_max valid hypotheses, else
 // after the per-round kernels have halved it that far): which pixels a round
 // adds does not depend on the survivors, so each (round, pixel tile, 64
 // hypotheses) wave scores every current survivor, whether or not it lives to
 // that round; the selection below uses only the survivors' values.
-// grid.x = rounds * ptiles * kFastWaves (absolute round index).
-__global__ __launch_bounds__(64) void k_score_all(const Job* __restrict__ jobs, int nptiles)
+// grid.x = rounds * ptiles * fw (absolute round index), fw = fast_max / 64.
+__global__ __launch_bounds__(64) void k_score_all(const Job* __restrict__ jobs, int nptiles, int fw)
 {
     const Job& J = jobs[blockIdx.y];
     if (J.st->done) return;
     const int n = J.st->n_surv, r0 = J.st->rounds_run;
-    const int htile = blockIdx.x % kFastWaves, rt = blockIdx.x / kFastWaves;
+    const int htile = blockIdx.x % fw, rt = blockIdx.x / fw;
     const int round = rt / nptiles, ptile = rt % nptiles;
     if (htile * 64 >= n || round < r0 || round >= rounds_of(n, J.n_cull, J.n_out, r0)) return;
     const int k0 = ptile * J.TP;
@@ -681,19 +686,19 @@ __global__ __launch_bounds__(64) void k_score_all(const Job* __restrict__ jobs, 
     double R[9], t[3];
     hyp_pose(J.hyps[ldg(J.surv + (pos < n ? pos : 0))], R, t);
     const double acc = score_pixels(J, round, k0, tp, htile == 0, R, t);
-    if (pos < n) J.partial_all[((size_t)round * nptiles + ptile) * kFastMax + pos] = acc;
+    if (pos < n) J.partial_all[((size_t)round * nptiles + ptile) * kFastStride + pos] = acc;
 }
 
 // Those rounds' selections, one block per job, thread = position in the
 // survivor list: same accumulation (tile order, rounds in order, onto the
 // energies of earlier rounds), ranking by (energy, slot), initial cull and
 // halving as k_select.
-__global__ __launch_bounds__(kFastMax) void k_select_all(const Job* __restrict__ jobs, int nptiles)
+__global__ __launch_bounds__(kFastStride) void k_select_all(const Job* __restrict__ jobs, int nptiles)
 {
     const Job& J = jobs[blockIdx.x];
     if (J.st->done) return;
-    __shared__ double sE[kFastMax];
-    __shared__ int sS[kFastMax], sA[kFastMax];
+    __shared__ double sE[kFastStride];
+    __shared__ int sS[kFastStride], sA[kFastStride];
     const int n0 = J.st->n_surv;
     const int lane = (int)threadIdx.x;
     const bool valid = lane < n0;
@@ -705,7 +710,7 @@ __global__ __launch_bounds__(kFastMax) void k_select_all(const Job* __restrict__
     bool first = round == 0;
     while (first || n > J.n_out) {
         if (alive)
-            E = E + sum_in_order(J.partial_all + (size_t)round * nptiles * kFastMax + lane, kFastMax, ptiles);
+            E = E + sum_in_order(J.partial_all + (size_t)round * nptiles * kFastStride + lane, kFastStride, ptiles);
         const double key = isnan(E) ? INFINITY : E;
         sE[lane] = key;
         sS[lane] = slot;
@@ -745,7 +750,7 @@ __global__ __launch_bounds__(kFastMax) void k_select_all(const Job* __restrict__
 __global__ __launch_bounds__(1024) void k_select(const Job* __restrict__ jobs, int round, int nptiles)
 {
     const Job& J = jobs[blockIdx.y];
-    if (J.st->done || J.st->n_surv <= kFastMax) return;
+    if (J.st->done || J.st->n_surv <= J.fast_max) return;
     extern __shared__ unsigned char s_raw[];
     const int n = J.st->n_surv;
     double* sE = reinterpret_cast<double*>(s_raw);
@@ -1084,17 +1089,21 @@ hipError_t launch_eligible(const Job* jobs, int njobs, int maxP, hipStream_t st)
     return hipSuccess;
 }
 
-constexpr int kHypIPT = RL_HYP_IPT;
-
-hipError_t launch_hyp_search(const Job* jobs, int njobs, int maxN, int maxIters, hipStream_t st)
+hipError_t launch_hyp_search(const Job* jobs, int njobs, int maxN, int maxIters, int ipt, hipStream_t st)
 {
-    const long long chunks = (maxIters + 256 * kHypIPT - 1) / (256 * kHypIPT);
+    const long long chunks = (maxIters + 256LL * ipt - 1) / (256LL * ipt);
     const long long X = chunks * (long long)maxN;
     const int s = njobs >= 8 ? 1 : njobs >= 4 ? 2 : njobs >= 2 ? 4 : 8;
     const long long per_group = X * ((njobs + 8 / s - 1) / (8 / s));
     const long long grid = 8 * ((per_group + s - 1) / s);
     if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
-    k_hyp_search<kHypIPT><<<dim3((unsigned)grid), dim3(256), 0, st>>>(jobs, maxN, njobs, (int)X, s);
+    const dim3 g((unsigned)grid), b(256);
+    switch (ipt) {
+        case 2: k_hyp_search<2><<<g, b, 0, st>>>(jobs, maxN, njobs, (int)X, s); break;
+        case 4: k_hyp_search<4><<<g, b, 0, st>>>(jobs, maxN, njobs, (int)X, s); break;
+        case 8: k_hyp_search<8><<<g, b, 0, st>>>(jobs, maxN, njobs, (int)X, s); break;
+        default: return hipErrorInvalidValue;
+    }
     RL_CHECK_LAUNCH();
     return hipSuccess;
 }
@@ -1116,11 +1125,12 @@ hipError_t launch_score(const Job* jobs, int njobs, int round, int nptiles, int 
     return hipSuccess;
 }
 
-hipError_t launch_score_all(const Job* jobs, int njobs, int rounds, int nptiles, hipStream_t st)
+hipError_t launch_score_all(const Job* jobs, int njobs, int rounds, int nptiles, int fw, hipStream_t st)
 {
-    k_score_all<<<dim3(rounds * nptiles * kFastWaves, njobs), dim3(64), 0, st>>>(jobs, nptiles);
+    if (fw < 1 || fw > kMaxFastWaves) return hipErrorInvalidValue;
+    k_score_all<<<dim3(rounds * nptiles * fw, njobs), dim3(64), 0, st>>>(jobs, nptiles, fw);
     RL_CHECK_LAUNCH();
-    k_select_all<<<dim3(njobs), dim3(kFastMax), 0, st>>>(jobs, nptiles);
+    k_select_all<<<dim3(njobs), dim3(64 * fw), 0, st>>>(jobs, nptiles);
     RL_CHECK_LAUNCH();
     return hipSuccess;
 }

@@ -24,11 +24,11 @@ namespace rl {
 hipError_t launch_prep(const Job* jobs, int njobs, int maxN, hipStream_t st);
 hipError_t launch_traverse(const Job* jobs, int njobs, int maxP, int T, hipStream_t st);
 hipError_t launch_eligible(const Job* jobs, int njobs, int maxP, hipStream_t st);
-hipError_t launch_hyp_search(const Job* jobs, int njobs, int maxN, int maxIters, hipStream_t st);
+hipError_t launch_hyp_search(const Job* jobs, int njobs, int maxN, int maxIters, int ipt, hipStream_t st);
 hipError_t launch_hyp_finalize(const Job* jobs, int njobs, int maxN, hipStream_t st);
 hipError_t launch_score(const Job* jobs, int njobs, int round, int nptiles, int maxSurv,
                         hipStream_t st);
-hipError_t launch_score_all(const Job* jobs, int njobs, int rounds, int nptiles, hipStream_t st);
+hipError_t launch_score_all(const Job* jobs, int njobs, int rounds, int nptiles, int fw, hipStream_t st);
 hipError_t launch_select(const Job* jobs, int njobs, int round, int nptiles, int maxN, hipStream_t st);
 hipError_t launch_finalize(const Job* jobs, int njobs, int maxIlen, hipStream_t st);
 hipError_t launch_plane_scores(const float* depth, int w, int h, float fx, float fy, float cx, float cy,
@@ -150,7 +150,7 @@ FrameLayout frame_layout(int maxP, int N, int eta, int rounds, int TP, int rows_
     L.E = c.take((size_t)N * 8);
     const int ptiles = (eta + TP - 1) / TP;
     L.partial = c.take((size_t)ptiles * N * 8);
-    L.partial_all = c.take((size_t)rounds * ptiles * kFastMax * 8);
+    L.partial_all = c.take((size_t)rounds * ptiles * kFastStride * 8);
     L.I = c.take((size_t)rounds * eta * 4);
     L.inl = c.take((size_t)rounds * eta * 4);
     L.trace_slots = c.take((size_t)rounds * N * 4);
@@ -268,6 +268,14 @@ struct Timer {
 
 }  // namespace
 
+// Launch shapes that leave every result unchanged (the search's and the
+// scoring's arithmetic and summation orders do not depend on them): search
+// iterations per thread, and the width in waves of the all-rounds scoring.
+struct Schedule {
+    int ipt = 4;
+    int fw = 1;
+};
+
 struct rl_room {
     rl_params p;
     int T, D, M, kappa, N, eta, rounds, TP;
@@ -299,6 +307,7 @@ struct rl_room {
     int rr_leaves;            // 0: exact mode update before relocalising; K: K leaves per adapted frame
     uint32_t rr_cursor;       // next leaf of the round-robin schedule
     std::vector<int> entering;
+    Schedule sched;
     Timer timer;
     std::map<std::vector<long long>, hipGraphExec_t> graphs;
 };
@@ -311,6 +320,7 @@ struct rl_batch {
     int TP, rows;
     size_t jobs_off, results_off;
     std::vector<FrameLayout> slots;
+    Schedule sched;
     Timer timer;
     Job* job_host;
     rl_result* res_host;
@@ -465,6 +475,7 @@ static Job make_job(const rl_room* r, char* scr, const FrameLayout& FL, const rl
     J.trace = r->trace;
     J.theta_col = r->p.max_colour_linf;
     J.TP = r->TP;
+    J.fast_max = 64 * r->sched.fw;
     J.min_sq_dist = r->p.min_squared_distance_between_sampled_modes;
     J.theta_rig = r->p.max_translation_error_for_correct_pose;
     J.theta_in = r->p.inlier_threshold;
@@ -813,9 +824,36 @@ RL_API rl_status relocaliser_set_mode_schedule(rl_room* r, int32_t leaves_per_fr
     return RL_OK;
 }
 
+static rl_status check_schedule(int ipt, int fast_waves)
+{
+    if (ipt != 2 && ipt != 4 && ipt != 8) return fail(RL_EINVAL, "iterations per thread must be 2, 4 or 8");
+    if (fast_waves != 1 && fast_waves != 2 && fast_waves != 4) return fail(RL_EINVAL, "fast_waves must be 1, 2 or 4");
+    return RL_OK;
+}
+
+RL_API rl_status relocaliser_set_schedule(rl_room* r, int32_t ipt, int32_t fast_waves)
+{
+    if (!r) return fail(RL_EINVAL, "room is NULL");
+    rl_status s = check_schedule(ipt, fast_waves);
+    if (s != RL_OK) return s;
+    r->sched.ipt = ipt;
+    r->sched.fw = fast_waves;
+    return RL_OK;
+}
+
+RL_API rl_status rl_batch_set_schedule(rl_batch* b, int32_t ipt, int32_t fast_waves)
+{
+    if (!b) return fail(RL_EINVAL, "batch is NULL");
+    rl_status s = check_schedule(ipt, fast_waves);
+    if (s != RL_OK) return s;
+    b->sched.ipt = ipt;
+    b->sched.fw = fast_waves;
+    return RL_OK;
+}
+
 static hipError_t launch_sequence(const Job* jobs, int njobs, int maxP, int maxN, int maxIters, int T,
                                   const std::vector<int>& entering, int nptiles, int maxEta,
-                                  const Timer& tm, hipStream_t st)
+                                  const Schedule& sc, const Timer& tm, hipStream_t st)
 {
     hipError_t e;
 #define RL_TRY(x) do { e = (x); if (e != hipSuccess) return e; } while (0)
@@ -826,16 +864,16 @@ static hipError_t launch_sequence(const Job* jobs, int njobs, int maxP, int maxN
     RL_MARK(RL_TIMER_TRAVERSE, stop);
     RL_TRY(launch_eligible(jobs, njobs, maxP, st));
     RL_MARK(RL_TIMER_HYP_SEARCH, start);
-    RL_TRY(launch_hyp_search(jobs, njobs, maxN, maxIters, st));
+    RL_TRY(launch_hyp_search(jobs, njobs, maxN, maxIters, sc.ipt, st));
     RL_MARK(RL_TIMER_HYP_SEARCH, stop);
     RL_TRY(launch_hyp_finalize(jobs, njobs, maxN, st));
     RL_MARK(RL_TIMER_RANSAC, start);
-    // rounds with more than kFastMax survivors one at a time, the rest at once
-    for (int r = 0; r < (int)entering.size() && entering[r] > kFastMax; ++r) {
+    // rounds with more than 64 * fw survivors one at a time, the rest at once
+    for (int r = 0; r < (int)entering.size() && entering[r] > 64 * sc.fw; ++r) {
         RL_TRY(launch_score(jobs, njobs, r, nptiles, entering[r], st));
         RL_TRY(launch_select(jobs, njobs, r, nptiles, maxN, st));
     }
-    RL_TRY(launch_score_all(jobs, njobs, (int)entering.size(), nptiles, st));
+    RL_TRY(launch_score_all(jobs, njobs, (int)entering.size(), nptiles, sc.fw, st));
     RL_MARK(RL_TIMER_RANSAC, stop);
     RL_TRY(launch_finalize(jobs, njobs, (int)entering.size() * maxEta, st));
 #undef RL_MARK
@@ -897,11 +935,11 @@ RL_API rl_status relocaliser_relocalise_opts(rl_room* r, const rl_frame* f, uint
     if (e != hipSuccess) return hip_fail(e, "job upload");
     const int nptiles = (r->eta + r->TP - 1) / r->TP;
     const int P = f->width * f->height;
-    std::vector<long long> key = {P, N};
+    std::vector<long long> key = {P, N, r->sched.ipt, r->sched.fw};
     for (int v : entering) key.push_back(v);
     e = run_sequence(r->graphs, key, r->timer.kernel == RL_TIMER_NONE, r->stream, [&]() {
         return launch_sequence(jd, 1, P, N, r->p.max_candidate_generation_iterations, r->T, entering,
-                               nptiles, r->eta, r->timer, r->stream);
+                               nptiles, r->eta, r->sched, r->timer, r->stream);
     });
     if (e != hipSuccess) return hip_fail(e, "relocalise launch");
     e = hipMemcpyAsync(r->res_host, r->scr + r->FL.result, sizeof(rl_result), hipMemcpyDeviceToHost, r->stream);
@@ -1122,6 +1160,7 @@ RL_API rl_status rl_batch_relocalise_async(rl_batch* b, const rl_request* reqs, 
             J.result = reinterpret_cast<rl_result*>(b->ws + b->slots[i].result);
         }
         J.TP = b->TP;
+        J.fast_max = 64 * b->sched.fw;
         J.trace = 0;
         b->job_host[i] = J;
     }
@@ -1131,11 +1170,11 @@ RL_API rl_status rl_batch_relocalise_async(rl_batch* b, const rl_request* reqs, 
     const int nptiles = (maxEta + b->TP - 1) / b->TP;
     if (use_graph && b->stream == nullptr)
         return fail(RL_EINVAL, "graph replay needs a batch created on a non-default stream");
-    std::vector<long long> key = {nq, maxN, maxIters, nptiles, maxEta, b->bp.n_trees};
+    std::vector<long long> key = {nq, maxN, maxIters, nptiles, maxEta, b->bp.n_trees, b->sched.ipt, b->sched.fw};
     for (int v : entering) key.push_back(v);
     e = run_sequence(b->graphs, key, use_graph && b->timer.kernel == RL_TIMER_NONE, b->stream, [&]() {
         return launch_sequence(jd, nq, maxP, maxN, maxIters, b->bp.n_trees, entering, nptiles, maxEta,
-                               b->timer, b->stream);
+                               b->sched, b->timer, b->stream);
     });
     if (e != hipSuccess) return hip_fail(e, "batch launch");
     e = hipEventRecord(b->ev, b->stream);

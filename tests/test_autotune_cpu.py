@@ -1,0 +1,34 @@
+"""Launch-schedule tuner without a GPU: the candidate list and the choice
+from timings (median, default kept within the noise margin, ties to the
+earlier schedule)."""
+import pytest
+
+from paper_1810_12163_amd import SCHEDULE_FAST_WAVES, SCHEDULE_IPT, autotune
+
+
+def test_candidates_cover_every_accepted_pair_default_first():
+    c = autotune.candidates()
+    assert c[0] == autotune.DEFAULT
+    assert sorted(c) == sorted((i, f) for i in SCHEDULE_IPT for f in SCHEDULE_FAST_WAVES)
+    assert len(set(c)) == len(c)
+    assert autotune.candidates(ipts=(2,), fast_waves=(4,)) == [(2, 4)]
+
+
+def test_pick_uses_the_median():
+    t = {(4, 1): [10.0, 10.0, 10.0], (2, 1): [1.0, 9.0, 9.0], (8, 1): [20.0, 8.0, 8.0]}
+    assert autotune.pick(t) == (8, 1)         # medians 10, 9, 8
+
+
+def test_pick_keeps_the_default_within_the_margin():
+    t = {(4, 1): [10.0], (8, 2): [9.9]}
+    assert autotune.pick(t) == (4, 1)
+    assert autotune.pick(t, margin=0.0) == (8, 2)
+    t = {(4, 1): [10.0], (8, 2): [9.7]}
+    assert autotune.pick(t) == (8, 2)
+
+
+def test_pick_ties_go_to_the_earlier_schedule_and_empty_is_an_error():
+    assert autotune.pick({(2, 2): [5.0], (8, 4): [5.0]}) == (2, 2)
+    assert autotune.pick({(8, 4): [5.0], (2, 2): [5.0]}) == (8, 4)
+    with pytest.raises(ValueError):
+        autotune.pick({})

@@ -226,6 +226,53 @@ def test_mixed_batch_equals_plain(c2, c3_room):
     batch.close()
 
 
+def test_every_schedule_gives_identical_results(c2, c3_room):
+    """Every launch schedule (search iterations per thread 2/4/8, all-rounds
+    scoring width 1/2/4 waves) gives bit-identical results, batched (graph
+    replay and direct launches) and plain; a request of 256 hypotheses enters
+    the all-rounds scoring at its first round under the 4-wave width.  The
+    tuner then leaves one of them set."""
+    from paper_1810_12163_amd import autotune
+    w, o, room = c2
+    p3, r3 = c3_room
+    q0, q1 = w.queries[0], w.queries[1]
+    dec = workloads.decimate
+    plan = [(room, q0, 11), (r3, dec(q1), 12), (room, dec(dec(q0)), 13), (r3, q1, 14)]
+    reqs = []
+    for rm, q, s in plan:
+        d, c = dev(q)
+        reqs.append((rm, d, c, q.K, s, workloads.HYPOTHESES[q.depth.shape[1]]))
+    want = [rm.relocalise(d, c, K, request_seed=s, n_hypotheses=N) for (rm, d, c, K, s, N) in reqs]
+
+    def same(got, ref, tag):
+        for a, b in zip(got, ref):
+            assert a["status"] == b["status"] and a["winner"] == b["winner"], tag
+            assert a["rounds"] == b["rounds"] and a["n_out"] == b["n_out"] and a["n_valid"] == b["n_valid"], tag
+            assert np.array_equal(a["pose"], b["pose"]) and a["energy"] == b["energy"], tag
+
+    batch = rl.Batch(4, 640, 480, 1024, 500, 12, 5, 50)
+    for sc in autotune.candidates():
+        print(f"[schedule] batch ipt={sc[0]} fast_waves={sc[1]}", flush=True)
+        batch.set_schedule(*sc)
+        same(batch.relocalise(reqs, use_graph=True), want, sc)
+        same(batch.relocalise(reqs, use_graph=sc == (8, 4)), want, sc)
+    for sc in ((2, 4), (8, 2), (4, 4)):
+        print(f"[schedule] plain ipt={sc[0]} fast_waves={sc[1]}", flush=True)
+        for rm in (room, r3):
+            rm.set_schedule(*sc)
+        same([rm.relocalise(d, c, K, request_seed=s, n_hypotheses=N) for (rm, d, c, K, s, N) in reqs], want, sc)
+    for rm in (room, r3):
+        rm.set_schedule(*autotune.DEFAULT)
+    best, timings = autotune.tune_batch(batch, reqs, reps=2, warmup=1)
+    assert best in timings and batch.schedule == best
+    same(batch.relocalise(reqs, use_graph=True), want, best)
+    with pytest.raises(rl.RlError):
+        batch.set_schedule(3, 1)
+    with pytest.raises(rl.RlError):
+        room.set_schedule(4, 8)
+    batch.close()
+
+
 def dataclasses_replace(s, **kw):
     import dataclasses
     return dataclasses.replace(s, **kw)
