@@ -84,6 +84,7 @@ def _declare(L):
     L.oracle_refine.argtypes = [P, I32, I32, P, P, P, P, I32, I32, I32, P, P, I32, F64, I32, P, P]
     L.oracle_refine.restype = I32
     L.oracle_plane_scores.argtypes = [P, I32, I32, P, P, I32, P, I32, P]
+    L.oracle_depth_scores.argtypes = [P, I32, I32, P, P, I32, P, I32, F32, F32, P, P, P]
 
 
 def _p(a):
@@ -358,3 +359,19 @@ def plane_scores(depth, K, poses12, surfaces):
     out = np.zeros(P.shape[0])
     lib().oracle_plane_scores(_p(depth), w, h, _p(Kf), _p(P), P.shape[0], _p(S), S.shape[0], _p(out))
     return out
+
+
+def depth_scores(depth, K, poses12, surfaces, min_depth: float, max_depth: float):
+    """Depth-raycast scores of Eq. 6-7 per pose: (s, mu, counts) with counts
+    (n_poses, 2) = (valid raycast pixels, pixels valid in both)."""
+    depth = _c(depth, np.float32)
+    h, w = depth.shape
+    Kf = _c(np.asarray(K, dtype=np.float32), np.float32)
+    P = _c(np.asarray(poses12, dtype=np.float32).reshape(-1, 12), np.float32)
+    S = _c(surfaces, np.float32)
+    s = np.zeros(P.shape[0])
+    mu = np.zeros(P.shape[0])
+    cnt = np.zeros((P.shape[0], 2), dtype=np.int64)
+    lib().oracle_depth_scores(_p(depth), w, h, _p(Kf), _p(P), P.shape[0], _p(S), S.shape[0],
+                              float(min_depth), float(max_depth), _p(s), _p(mu), _p(cnt))
+    return s, mu, cnt

@@ -888,3 +888,82 @@ EXPORT void oracle_plane_scores(const float* depth, int w, int h, const float K[
         scores[k] = cnt > 0 ? acc / (double)cnt : INFINITY;
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/*
+ * Model-based hypothesis score, Sec. 3.2.4, Eq. 6-7, with the scene model
+ * given analytically (the surface records of oracle_plane_scores).
+ *
+ * Synthetic depth raycast D~_xi from pose xi = (R, t), camera -> world: pixel
+ * u = (x, y) on integer coordinates casts the camera ray
+ * d^C = ((x - cx) / fx, (y - cy) / fy, 1) from o = t along d^W = R d^C; a
+ * surface is hit at ray parameter z = ((p0 - o) . n) / (n . d^W) when
+ * n . d^W != 0, z > 0 and, for a rectangle, |e1 . q| <= a and |e2 . q| <= b
+ * with q = o + z d^W - p0.  D~(u) is the smallest hit z, which is the
+ * camera-space depth because d^C has unit z.  Readings: D~(u) is valid when
+ * some surface is hit at min_depth <= z <= max_depth (max_depth <= 0: no
+ * upper limit), the stand-in for the range the model is rendered over; a
+ * live depth is valid when positive and finite.
+ *
+ * mu(xi) (Eq. 6) = sum over pixels valid in both of |D_l(u) - D~(u)|,
+ * divided by their number; s(xi) (Eq. 7) = mu(xi) when the valid fraction of
+ * the raycast is at least 0.1, taken exactly as 10 * |valid| >= w * h, and
+ * +inf otherwise, and also +inf when no pixel is valid in both.
+ * Outputs per pose: scores[k] = s, mu[k] (NaN when no pixel is valid in
+ * both), counts[2k] = |valid raycast pixels|, counts[2k+1] = |both valid|.
+ * All arithmetic FP64 from the float32 inputs.
+ */
+static double raycast_depth(double ox, double oy, double oz, double dx, double dy, double dz,
+                            const float* surfaces, int n_surf)
+{
+    double best = INFINITY;
+    for (int s = 0; s < n_surf; ++s) {
+        const float* S = surfaces + 16 * (size_t)s;
+        const double nx = S[3], ny = S[4], nz = S[5];
+        const double den = dx * nx + dy * ny + dz * nz;
+        if (den == 0.0) continue;
+        const double num = ((double)S[0] - ox) * nx + ((double)S[1] - oy) * ny + ((double)S[2] - oz) * nz;
+        const double z = num / den;
+        if (!(z > 0.0)) continue;
+        if (S[12] > 0.0f) {
+            const double qx = (ox + z * dx) - (double)S[0];
+            const double qy = (oy + z * dy) - (double)S[1];
+            const double qz = (oz + z * dz) - (double)S[2];
+            const double a = qx * (double)S[6] + qy * (double)S[7] + qz * (double)S[8];
+            const double b = qx * (double)S[9] + qy * (double)S[10] + qz * (double)S[11];
+            if (!(fabs(a) <= (double)S[12] && fabs(b) <= (double)S[13])) continue;
+        }
+        if (z < best) best = z;
+    }
+    return best;
+}
+
+EXPORT void oracle_depth_scores(const float* depth, int w, int h, const float K[4], const float* poses,
+                                int n_poses, const float* surfaces, int n_surf, float min_depth,
+                                float max_depth, double* scores, double* mu, long long* counts)
+{
+    for (int k = 0; k < n_poses; ++k) {
+        const float* P = poses + 12 * (size_t)k;
+        double acc = 0.0;
+        long long n_model = 0, n_both = 0;
+        for (int p = 0; p < w * h; ++p) {
+            const int x = p % w, y = p / w;
+            const double cx = ((double)x - (double)K[2]) / (double)K[0];
+            const double cy = ((double)y - (double)K[3]) / (double)K[1];
+            const double dx = (double)P[0] * cx + (double)P[1] * cy + (double)P[2];
+            const double dy = (double)P[3] * cx + (double)P[4] * cy + (double)P[5];
+            const double dz = (double)P[6] * cx + (double)P[7] * cy + (double)P[8];
+            const double z = raycast_depth(P[9], P[10], P[11], dx, dy, dz, surfaces, n_surf);
+            if (!(z >= (double)min_depth && (max_depth <= 0.0f || z <= (double)max_depth))) continue;
+            ++n_model;
+            const float d = depth[p];
+            if (!depth_valid(d)) continue;
+            acc += fabs((double)d - z);
+            ++n_both;
+        }
+        counts[2 * k] = n_model;
+        counts[2 * k + 1] = n_both;
+        mu[k] = n_both > 0 ? acc / (double)n_both : NAN;
+        scores[k] = (n_both > 0 && 10 * n_model >= (long long)w * h) ? mu[k] : INFINITY;
+    }
+}
