@@ -234,6 +234,28 @@ rl_status rl_plane_scores(rl_room* room, const rl_frame* frame, const rl_surface
                           double* host_scores);
 
 /*
+ * Model-based hypothesis score of Sec. 3.2.4 (Eq. 6-7), with the scene model
+ * given as analytic surfaces.  For each pose (host, 12 floats: R row-major,
+ * t; camera -> world) the library raycasts the surfaces through every pixel
+ * u = (x, y) (integer coordinates; camera ray ((x-cx)/fx, (y-cy)/fy, 1)) and
+ * takes the nearest hit's camera-space depth D~(u), valid when
+ * min_depth <= D~(u) <= max_depth (max_depth <= 0: no upper limit).  With
+ * live depth valid when positive:
+ *   mu(xi) = mean over pixels valid in both of |D_l(u) - D~(u)|   (Eq. 6)
+ *   s(xi)  = mu(xi) if 10 * |valid D~| >= w * h, else +inf       (Eq. 7)
+ * and s = +inf when no pixel is valid in both.  The caller takes the argmin
+ * (Eq. 8).  FP64; hit tests in a fixed operation order without contraction.
+ * n_surfaces <= 64, n_poses <= 64.  host_scores: n_poses doubles; host_mu
+ * (may be NULL): n_poses doubles (NaN when no pixel is valid in both);
+ * host_counts (may be NULL): 2 per pose, (|valid D~|, |valid in both|).
+ * Synchronous on the room's stream; uses the room's scratch.  RL_EINVAL for
+ * NULL, out-of-range counts, non-finite inputs or min_depth < 0.
+ */
+rl_status rl_depth_scores(rl_room* room, const rl_frame* frame, const rl_surface* host_surfaces,
+                          int32_t n_surfaces, const float* host_poses, int32_t n_poses, float min_depth,
+                          float max_depth, double* host_scores, double* host_mu, int64_t* host_counts);
+
+/*
  * Introspection for tests and tools: byte offset and size of an internal
  * array inside the caller's persistent (*region = 0) or scratch (*region = 1)
  * buffer.  which: see RL_BUF_* below.  Contents are valid after the stream

@@ -102,6 +102,7 @@ EXPORTS = [
     "rl_batch_relocalise", "rl_batch_relocalise_async", "rl_last_error", "rl_version",
     "relocaliser_set_timer", "rl_batch_set_timer", "relocaliser_relocalise_opts", "rl_plane_scores",
     "relocaliser_set_mode_schedule", "relocaliser_set_schedule", "rl_batch_set_schedule",
+    "rl_depth_scores",
 ]
 
 # launch schedules the library accepts (iterations per thread, fast waves)
@@ -149,6 +150,8 @@ def lib():
         L.relocaliser_set_mode_schedule.argtypes = [P, I32]
         L.relocaliser_set_schedule.argtypes = [P, I32, I32]
         L.rl_batch_set_schedule.argtypes = [P, I32, I32]
+        L.rl_depth_scores.argtypes = [P, ctypes.POINTER(Frame), P, I32, P, I32, ctypes.c_float, ctypes.c_float,
+                                      P, P, P]
         L.rl_last_error.restype = ctypes.c_char_p
         L.rl_version.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -299,6 +302,21 @@ class Room:
         _check(lib().rl_plane_scores(self.handle, ctypes.byref(f), S.ctypes.data, S.shape[0], P.ctypes.data,
                                      P.shape[0], out.ctypes.data))
         return out
+
+    def depth_scores(self, depth, rgb, K, surfaces: np.ndarray, poses12: np.ndarray, min_depth: float = 0.5,
+                     max_depth: float = 4.0):
+        """Depth-raycast scores of Eq. 6-7 per pose: (s, mu, counts (n, 2))."""
+        f = _frame(depth, rgb, K)
+        S = np.ascontiguousarray(surfaces, dtype=np.float32).reshape(-1, 16)
+        P = np.ascontiguousarray(poses12, dtype=np.float32).reshape(-1, 12)
+        s = np.zeros(P.shape[0], dtype=np.float64)
+        mu = np.zeros(P.shape[0], dtype=np.float64)
+        cnt = np.zeros((P.shape[0], 2), dtype=np.int64)
+        self._follow(depth, rgb)
+        _check(lib().rl_depth_scores(self.handle, ctypes.byref(f), S.ctypes.data, S.shape[0], P.ctypes.data,
+                                     P.shape[0], float(min_depth), float(max_depth), s.ctypes.data,
+                                     mu.ctypes.data, cnt.ctypes.data))
+        return s, mu, cnt
 
     def survivors(self, k: int):
         """(slots, poses (k, 12)) of the best k hypotheses of the last relocalisation."""

@@ -8,7 +8,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["rl_reloc_kernels.hip", "rl_adapt_kernels.hip", "rl_runtime.hip"]
+SOURCES = ["rl_reloc_kernels.hip", "rl_adapt_kernels.hip", "rl_rank_kernels.hip", "rl_runtime.hip"]
 LIB = os.path.join(HERE, "librl.so")
 ARCH = os.environ.get("RL_OFFLOAD_ARCH", "gfx950")
 

@@ -3,16 +3,17 @@ by the same forest run one after another until one produces an acceptable
 pose.
 
 Stages run on one room (forest, reservoirs and modes are shared) with
-per-call RANSAC settings.  A stage's pose is accepted unless its score is
-above the stage's threshold, in which case the next stage runs.  The last
-stage keeps several hypotheses and ranks them with the model-based score
-(the analytic-model stand-in for the paper's depth-raycast ranking,
-Sec. 3.2.4); its best is returned.
+per-call RANSAC settings.  A stage that keeps several hypotheses ranks them
+with the model-based score and returns the best (Eq. 8).  Its pose is
+accepted unless its score is above the stage's threshold, in which case the
+next stage runs (the last stage's pose is always returned).
 
-Score used for the fallback decision: the winner's mean Eq. 5 energy over
-the final pixel set (E/|I|).  The paper falls back on the ranking score of
-the stage's output; that variant needs the model score of every stage, which
-``fallback_on_model`` enables.
+Model-based score (``model``): "depth", the depth-raycast comparison of
+Eq. 6-7 on the analytic scene model (the paper's; raycast valid over
+[min_depth, max_depth]), or "plane", the mean distance of the back-projected
+live depth to the nearest surface.  Fallback score (``fallback``): "model",
+the stage output's model score (the paper's), or "energy", the winner's mean
+Eq. 5 energy over the final pixel set (E/|I|), which needs no scene model.
 """
 from __future__ import annotations
 
@@ -41,11 +42,22 @@ def decimate(depth, rgb, K):
 
 
 class Cascade:
-    def __init__(self, room, stages, surfaces: np.ndarray, fallback_on_model: bool = False):
+    def __init__(self, room, stages, surfaces: np.ndarray, model: str = "depth", fallback: str = "model",
+                 min_depth: float = 0.5, max_depth: float = 4.0):
+        if model not in ("depth", "plane") or fallback not in ("model", "energy"):
+            raise ValueError("model must be 'depth' or 'plane', fallback 'model' or 'energy'")
         self.room = room
         self.stages = list(stages)
         self.surfaces = np.ascontiguousarray(surfaces, dtype=np.float32)
-        self.fallback_on_model = fallback_on_model
+        self.model = model
+        self.fallback = fallback
+        self.min_depth, self.max_depth = float(min_depth), float(max_depth)
+
+    def scores(self, depth, rgb, K, poses12) -> np.ndarray:
+        """Model-based score of each pose (lower is better; +inf: unverifiable)."""
+        if self.model == "depth":
+            return self.room.depth_scores(depth, rgb, K, self.surfaces, poses12, self.min_depth, self.max_depth)[0]
+        return self.room.plane_scores(depth, rgb, K, self.surfaces, poses12)
 
     def relocalise(self, depth, rgb, K, request_seed: int = 0) -> dict:
         t0 = time.perf_counter()
@@ -65,17 +77,17 @@ class Cascade:
             if st.n_out > 1:
                 k = res["n_out"]
                 slots, poses = self.room.survivors(k)
-                scores = self.room.plane_scores(depth, rgb, K, self.surfaces, poses)
+                scores = self.scores(depth, rgb, K, poses)
                 best = int(np.argmin(scores))          # ties -> the better-energy hypothesis
                 H = np.eye(4, dtype=np.float32)
                 H[:3, :3] = poses[best, :9].reshape(3, 3)
                 H[:3, 3] = poses[best, 9:]
                 res = dict(res, pose=H, winner=int(slots[best]), model_score=float(scores[best]),
                            ranked=scores)
-                score = float(scores[best])
-            elif self.fallback_on_model:
+                score = float(scores[best]) if self.fallback == "model" else res["mean_energy"]
+            elif self.fallback == "model":
                 p12 = np.concatenate([res["pose"][:3, :3].reshape(-1), res["pose"][:3, 3]])
-                score = float(self.room.plane_scores(depth, rgb, K, self.surfaces, p12[None])[0])
+                score = float(self.scores(depth, rgb, K, p12[None])[0])
                 res = dict(res, model_score=score)
             else:
                 score = res["mean_energy"]

@@ -26,6 +26,9 @@ constexpr uint32_t kTagRes = 1, kTagHyp = 2, kTagScore = 3;
 constexpr int kScoreTile = RL_SCORE_TILE;     // pixels per scoring wave
 // All-rounds scoring (once a job's survivors fit fast_max = 64 * fast waves
 // lanes) keeps its partials with this stride: up to 4 waves of hypotheses.
+// analytic scene models for the model-based scores
+constexpr int kMaxModelSurfaces = 64, kMaxModelPoses = 64;
+
 constexpr int kMaxFastWaves = 4;
 constexpr int kFastStride = 64 * kMaxFastWaves;
 

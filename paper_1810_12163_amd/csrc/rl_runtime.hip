@@ -31,6 +31,10 @@ hipError_t launch_score(const Job* jobs, int njobs, int round, int nptiles, int 
 hipError_t launch_score_all(const Job* jobs, int njobs, int rounds, int nptiles, int fw, hipStream_t st);
 hipError_t launch_select(const Job* jobs, int njobs, int round, int nptiles, int maxN, hipStream_t st);
 hipError_t launch_finalize(const Job* jobs, int njobs, int maxIlen, hipStream_t st);
+hipError_t launch_depth_scores(const float* depth, int w, int h, float fx, float fy, float cx, float cy,
+                               const float* surfaces, int n_surf, const float* poses, int n_poses, float zmin,
+                               float zmax, double* partial, int* cnt, double* out, long long* counts,
+                               hipStream_t st);
 hipError_t launch_plane_scores(const float* depth, int w, int h, float fx, float fy, float cx, float cy,
                                const float* surfaces, int n_surf, const float* poses, int n_poses,
                                double* partial, int* cnt, double* scores, hipStream_t st);
@@ -181,11 +185,14 @@ PersistLayout persist_layout(const rl_params& p)
     return P;
 }
 
-constexpr int kMaxModelSurfaces = 64, kMaxModelPoses = 64;
 
 // Scratch of the model-based score: surfaces, poses, per-tile partials, scores.
+// host staging of the model scores: surfaces, poses, plane scores, depth
+// scores (s, mu) and counts
+constexpr size_t kModelHostBytes = (size_t)kMaxModelSurfaces * 64 + (size_t)kMaxModelPoses * (48 + 8 + 16 + 16);
+
 struct ModelLayout {
-    size_t surfaces, poses, partial, cnt, scores, total;
+    size_t surfaces, poses, partial, cnt, scores, dpartial, dcnt, dout, dcounts, total;
 };
 
 ModelLayout model_layout(int maxP, size_t base)
@@ -199,6 +206,10 @@ ModelLayout model_layout(int maxP, size_t base)
     L.partial = c.take(ntiles * kMaxModelPoses * 8);
     L.cnt = c.take(ntiles * 4);
     L.scores = c.take((size_t)kMaxModelPoses * 8);
+    L.dpartial = c.take(ntiles * kMaxModelPoses * 8);
+    L.dcnt = c.take(ntiles * kMaxModelPoses * 2 * 4);
+    L.dout = c.take((size_t)kMaxModelPoses * 2 * 8);
+    L.dcounts = c.take((size_t)kMaxModelPoses * 2 * 8);
     L.total = c.cur - base;
     return L;
 }
@@ -608,7 +619,7 @@ RL_API rl_status relocaliser_create(const rl_params* p, const rl_node* host_node
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&r->res_host), sizeof(rl_result), hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipHostMalloc(reinterpret_cast<void**>(&r->model_host),
-                          (size_t)kMaxModelSurfaces * 64 + (size_t)kMaxModelPoses * (48 + 8), hipHostMallocDefault);
+                          kModelHostBytes, hipHostMallocDefault);
     if (e != hipSuccess) {
         (void)hipEventDestroy(r->ev);
         delete r;
@@ -986,6 +997,57 @@ RL_API rl_status rl_plane_scores(rl_room* r, const rl_frame* f, const rl_surface
     if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
     if (e != hipSuccess) return hip_fail(e, "plane scores");
     std::memcpy(scores, hscores, (size_t)n_poses * 8);
+    return RL_OK;
+}
+
+RL_API rl_status rl_depth_scores(rl_room* r, const rl_frame* f, const rl_surface* surfaces, int32_t n_surf,
+                                 const float* poses, int32_t n_poses, float min_depth, float max_depth,
+                                 double* scores, double* mu, int64_t* counts)
+{
+    if (!r || !surfaces || !poses || !scores) return fail(RL_EINVAL, "NULL argument");
+    rl_status s = validate_frame(f, r->max_w, r->max_h);
+    if (s != RL_OK) return s;
+    if (n_surf < 1 || n_surf > kMaxModelSurfaces) return fail(RL_EINVAL, "n_surfaces must be in 1..%d", kMaxModelSurfaces);
+    if (n_poses < 1 || n_poses > kMaxModelPoses) return fail(RL_EINVAL, "n_poses must be in 1..%d", kMaxModelPoses);
+    if (!finite_f(min_depth) || !finite_f(max_depth) || min_depth < 0.0f)
+        return fail(RL_EINVAL, "min_depth must be finite and >= 0, max_depth finite");
+    for (int i = 0; i < n_surf * 16; ++i)
+        if (!finite_f(reinterpret_cast<const float*>(surfaces)[i])) return fail(RL_EINVAL, "non-finite surface");
+    for (int i = 0; i < n_poses * 12; ++i)
+        if (!finite_f(poses[i])) return fail(RL_EINVAL, "non-finite pose");
+    char* hs = r->model_host;
+    char* hp = hs + kMaxModelSurfaces * 64;
+    char* hout = hp + kMaxModelPoses * (48 + 8);
+    char* hcnt = hout + kMaxModelPoses * 16;
+    std::memcpy(hs, surfaces, (size_t)n_surf * 64);
+    std::memcpy(hp, poses, (size_t)n_poses * 48);
+    hipError_t e = hipMemcpyAsync(r->scr + r->ML.surfaces, hs, (size_t)n_surf * 64, hipMemcpyHostToDevice, r->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(r->scr + r->ML.poses, hp, (size_t)n_poses * 48, hipMemcpyHostToDevice, r->stream);
+    if (e == hipSuccess)
+        e = launch_depth_scores(f->depth, f->width, f->height, f->K.fx, f->K.fy, f->K.cx, f->K.cy,
+                                reinterpret_cast<const float*>(r->scr + r->ML.surfaces), n_surf,
+                                reinterpret_cast<const float*>(r->scr + r->ML.poses), n_poses, min_depth, max_depth,
+                                reinterpret_cast<double*>(r->scr + r->ML.dpartial),
+                                reinterpret_cast<int*>(r->scr + r->ML.dcnt),
+                                reinterpret_cast<double*>(r->scr + r->ML.dout),
+                                reinterpret_cast<long long*>(r->scr + r->ML.dcounts), r->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hout, r->scr + r->ML.dout, (size_t)n_poses * 16, hipMemcpyDeviceToHost, r->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hcnt, r->scr + r->ML.dcounts, (size_t)n_poses * 16, hipMemcpyDeviceToHost, r->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
+    if (e != hipSuccess) return hip_fail(e, "depth scores");
+    const double* o = reinterpret_cast<const double*>(hout);
+    const long long* c = reinterpret_cast<const long long*>(hcnt);
+    for (int k = 0; k < n_poses; ++k) {
+        scores[k] = o[2 * k];
+        if (mu) mu[k] = o[2 * k + 1];
+        if (counts) {
+            counts[2 * k] = c[2 * k];
+            counts[2 * k + 1] = c[2 * k + 1];
+        }
+    }
     return RL_OK;
 }
 

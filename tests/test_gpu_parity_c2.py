@@ -177,6 +177,62 @@ def test_c3_wide_stage_keeps_16_and_model_score_matches(c2, c3_room):
     assert s_gt < 0.005                     # noisy depth: a few mm at the true pose
 
 
+def _same_depth_scores(got, want):
+    (s, mu, cnt), (s_o, mu_o, cnt_o) = got, want
+    np.testing.assert_array_equal(cnt, cnt_o)
+    np.testing.assert_array_equal(np.isinf(s), np.isinf(s_o))
+    np.testing.assert_array_equal(np.isnan(mu), np.isnan(mu_o))
+    f = np.isfinite(s_o)
+    np.testing.assert_allclose(s[f], s_o[f], rtol=1e-12, atol=0)
+    m = ~np.isnan(mu_o)
+    np.testing.assert_allclose(mu[m], mu_o[m], rtol=1e-12, atol=0)
+
+
+def test_depth_scores_match_oracle(c2):
+    """Eq. 6-7 depth-raycast scores at 640x480 for the true pose, 2 cm / 2 degree
+    perturbations, poses below the floor looking away from the room (one with
+    too few valid raycast pixels: +inf) and a ragged 324x244 crop: both counts bit-exact,
+    s and mu to 1e-12 relative; an all-invalid live frame gives +inf / NaN."""
+    w, o, room = c2
+    S = oracle.surfaces_of(w.room)
+    q = w.queries[1]
+    R0, t0 = q.pose[:3, :3], q.pose[:3, 3]
+    poses = [np.concatenate([R0.reshape(-1), t0])]
+    rng = np.random.default_rng(4)
+    for k in range(13):
+        ax = rng.normal(size=3)
+        ax *= np.radians(2.0) * rng.uniform() / np.linalg.norm(ax)
+        th = np.linalg.norm(ax)
+        Kx = np.array([[0, -ax[2], ax[1]], [ax[2], 0, -ax[0]], [-ax[1], ax[0], 0]])
+        dR = np.eye(3) + np.sin(th) / th * Kx + (1 - np.cos(th)) / th**2 * Kx @ Kx
+        poses.append(np.concatenate([(R0 @ dR).reshape(-1), t0 + rng.normal(size=3) * 0.02]))
+    # below the floor looking down, away from the room: the wall planes leave
+    # 32% of the raycast valid from (1, 1.5, -0.5) and 8.6% (+inf) from (2, 2, -1)
+    down = np.array([[0, 1, 0], [1, 0, 0], [0, 0, -1]], np.float64)
+    for t in ([1.0, 1.5, -0.5], [2.0, 2.0, -1.0]):
+        poses.append(np.concatenate([down.reshape(-1), t]))
+    P = np.asarray(poses, np.float32)
+    d, c = dev(q)
+    got = room.depth_scores(d, c, q.K, S, P, 0.5, 4.0)
+    want = oracle.depth_scores(q.depth, q.K, P, S, 0.5, 4.0)
+    print(f"[depth scores] s {np.round(want[0], 4)}", flush=True)
+    _same_depth_scores(got, want)
+    assert int(np.argmin(got[0])) == 0 and got[0][0] < 0.01
+    assert np.isinf(got[0][-1])
+    # ragged crop (79056 pixels: 77 full tiles and a partial one), no upper depth limit
+    dc = q.depth[:244, :324].copy()
+    cc = q.rgb[:244, :324].copy()
+    Kc = q.K
+    got = room.depth_scores(torch.from_numpy(dc).cuda(), torch.from_numpy(cc).cuda(), Kc, S, P, 0.5, 0.0)
+    _same_depth_scores(got, oracle.depth_scores(dc, Kc, P, S, 0.5, 0.0))
+    # no valid live depth
+    z = np.zeros_like(dc)
+    got = room.depth_scores(torch.from_numpy(z).cuda(), torch.from_numpy(cc).cuda(), Kc, S, P[:3], 0.5, 4.0)
+    assert np.all(np.isinf(got[0])) and np.all(np.isnan(got[1])) and np.all(got[2][:, 1] == 0)
+    with pytest.raises(rl.RlError):
+        room.depth_scores(d, c, q.K, S, P, -1.0, 4.0)
+
+
 def test_cascade_fallback_and_ranking(c2, c3_room):
     from paper_1810_12163_amd.cascade import Cascade, Stage
     w, o, _ = c2
@@ -192,6 +248,18 @@ def test_cascade_fallback_and_ranking(c2, c3_room):
     out = full.relocalise(d, c, q.K, request_seed=3)
     assert [t[0] for t in out["trail"]] == ["a", "b", "c"] and out["stage"] == "c"
     assert out["model_score"] == float(np.min(out["ranked"]))
+    # stage c ranked its survivors by the Eq. 6-7 depth score, as the oracle scores them
+    slots, poses = r3.survivors(len(out["ranked"]))
+    np.testing.assert_allclose(out["ranked"], oracle.depth_scores(q.depth, q.K, poses, S, 0.5, 4.0)[0],
+                               rtol=1e-12, atol=0)
+    # the paper's fallback thresholds: 5 cm after stage a, 7.5 cm after stage b
+    th = [0.05, 0.075, float("inf")]
+    paper = Cascade(r3, [dataclasses_replace(s, threshold=t) for s, t in zip(stages, th)], S)
+    out = paper.relocalise(d, c, q.K, request_seed=3)
+    print(f"[cascade 5cm/7.5cm] trail {out['trail']}", flush=True)
+    for (name, sc), t in zip(out["trail"][:-1], th):
+        assert sc > t
+    assert out["trail"][-1][1] <= th[len(out["trail"]) - 1] or out["stage"] == "c"
 
 
 def test_mixed_batch_equals_plain(c2, c3_room):
