@@ -79,7 +79,13 @@ def _declare(L):
     L.oracle_pixel_energy.argtypes = [P, I32, I32, P, P, P, P, I32, I32, I32, P, I32, I32]
     L.oracle_pixel_energy.restype = F64
     L.oracle_ransac.argtypes = [P, I32, I32, P, P, P, P, I32, I32, I32, P, I32, P, P, I32,
-                                I32, I32, I32, I32, U64, U64, P, P, P, P, I32, P, I32, P, P]
+                                I32, I32, I32, I32, U64, U64, P, P, P, P, I32, P, I32, P, P,
+                                I32, I32, P]
+    L.oracle_lm_refine.argtypes = [P, I32, I32, P, P, P, P, I32, I32, I32, P, I32, I32, I32, P]
+    L.oracle_lm_refine.restype = F64
+    L.oracle_lm_linearise.argtypes = [P, I32, I32, P, P, P, P, I32, I32, I32, P, I32, I32, P, P, P]
+    L.oracle_lm_linearise.restype = F64
+    L.oracle_se3_exp.argtypes = [P, P, P]
     L.oracle_ransac.restype = I32
     L.oracle_refine.argtypes = [P, I32, I32, P, P, P, P, I32, I32, I32, P, P, I32, F64, I32, P, P]
     L.oracle_refine.restype = I32
@@ -286,11 +292,13 @@ def estimate_pose(depth, rgb, K, leaves, nmodes, modes, T, D, M, p, request_seed
     round_n = np.zeros(rcap, dtype=np.int32)
     round_slots = np.zeros((rcap, N), dtype=np.int32) if trace else None
     round_energy = np.zeros((rcap, N), dtype=np.float64) if trace else None
+    pose_update = int(p.get("pose_update", 0))
+    refined = np.zeros((N, 12), dtype=np.float64)
     rounds = L.oracle_ransac(_p(depth), w, h, _p(Kf), _p(leaves), _p(nmodes), _p(modes), T, D, M,
                              _p(eligible), len(eligible), _p(hv), _p(hpose), N, eta, n_cull, n_out,
                              use_cov, int(p["seed"]), int(request_seed), _p(slots), _p(energy),
                              _p(cnt), _p(Ilist), Icap, _p(round_n), rcap, _p(round_slots),
-                             _p(round_energy))
+                             _p(round_energy), pose_update, int(p.get("lm_iterations", 0)), _p(refined))
     k = int(cnt[0])
     nI = rounds * eta
     out.update(rounds=rounds, out_slots=slots[:k], out_energy=energy[:k],
@@ -303,7 +311,9 @@ def estimate_pose(depth, rgb, K, leaves, nmodes, modes, T, D, M, p, request_seed
                    n_inliers=0, refitted=False, winner=-1)
         return out
     win = int(slots[0])
-    pose12 = hpose[win].copy()
+    out.update(refined_pose64=refined)
+    # the refined pose (FP64) rounded to float32, as a hypothesis pose is kept
+    pose12 = refined[win].astype(np.float32) if pose_update else hpose[win].copy()
     n_inl, refitted = 0, False
     if int(p["final_refine"]):
         po = np.zeros(12)
@@ -375,3 +385,40 @@ def depth_scores(depth, K, poses12, surfaces, min_depth: float, max_depth: float
     lib().oracle_depth_scores(_p(depth), w, h, _p(Kf), _p(P), P.shape[0], _p(S), S.shape[0],
                               float(min_depth), float(max_depth), _p(s), _p(mu), _p(cnt))
     return s, mu, cnt
+
+
+def se3_exp(xi):
+    """exp of xi = (omega, v) in se(3): (R 3x3, t 3)."""
+    xi = _c(xi, np.float64)
+    R = np.zeros(9)
+    t = np.zeros(3)
+    lib().oracle_se3_exp(_p(xi), _p(R), _p(t))
+    return R.reshape(3, 3), t
+
+
+def _lm_args(depth, K, leaves, nmodes, modes, I):
+    depth = _c(depth, np.float32)
+    h, w = depth.shape
+    return (depth, w, h, _c(np.asarray(K, dtype=np.float32), np.float32), _c(leaves, np.uint16),
+            _c(nmodes, np.uint8), _c(modes, np.float32), _c(I, np.int32))
+
+
+def lm_refine(depth, K, leaves, nmodes, modes, T, D, M, I, pose12, use_cov=1, iters=10):
+    """Levenberg-Marquardt refinement in se(3) of one pose on E over the pixel
+    list I; returns (energy, refined pose12 FP64)."""
+    d, w, h, Kf, lv, nm, md, Ii = _lm_args(depth, K, leaves, nmodes, modes, I)
+    pose = _c(np.array(pose12, dtype=np.float64), np.float64).copy()
+    E = lib().oracle_lm_refine(_p(d), w, h, _p(Kf), _p(lv), _p(nm), _p(md), T, D, M, _p(Ii), len(Ii),
+                               int(use_cov), int(iters), _p(pose))
+    return E, pose
+
+
+def lm_linearise(depth, K, leaves, nmodes, modes, T, D, M, I, pose12, use_cov=1):
+    """(E, N 6x6, g 6) of the weighted normal equations at pose12."""
+    d, w, h, Kf, lv, nm, md, Ii = _lm_args(depth, K, leaves, nmodes, modes, I)
+    pose = _c(np.array(pose12, dtype=np.float64), np.float64)
+    N = np.zeros(36)
+    g = np.zeros(6)
+    E = lib().oracle_lm_linearise(_p(d), w, h, _p(Kf), _p(lv), _p(nm), _p(md), T, D, M, _p(Ii), len(Ii),
+                                  int(use_cov), _p(pose), _p(N), _p(g))
+    return E, N.reshape(6, 6), g

@@ -691,8 +691,195 @@ EXPORT double oracle_pixel_energy(const float* depth, int w, int h, const float 
 }
 
 /*
- * Preemptive RANSAC (Sec. 3.2.3), without the Levenberg-Marquardt step.
- * Hypotheses = the valid slots in slot order.  Every round draws eta pixels
+ * Levenberg-Marquardt refinement of one pose in se(3) on the energy E of
+ * Eq. 5 over a pixel set (Sec. 3.2.3, step (ii) of each preemptive-RANSAC
+ * iteration).  The paper names the method and the parametrisation only;
+ * the readings here:
+ *  - the minimised function is E itself over the cumulative set I (with
+ *    multiplicity), in the metric of Eq. 5 (Sigma^-1 when the covariance is
+ *    used, else Euclidean);
+ *  - update H <- exp(xi^) H with xi = (omega, v), acting on world points;
+ *  - each iteration linearises at the current pose: per pixel its nearest
+ *    mode m_i (ties to the lower m), r_i = H x_i - mu_{m_i}, e_i = |r_i|_A,
+ *    the Jacobian J_i = [-[y_i]x | I] of exp(xi^) y_i at xi = 0 (y_i = H x_i),
+ *    and the weight w_i = 1 / max(e_i, 1e-6), which makes
+ *    sum_i w_i |r_i + J_i d|_A^2 / 2 share E's gradient at d = 0:
+ *    N = sum_i w_i J_i^T A J_i, g = sum_i w_i J_i^T A r_i;
+ *  - the step d solves (N + lambda diag(N)) d = -g by Cholesky (a
+ *    non-positive or non-finite pivot rejects the step); the candidate
+ *    exp(d^) H is accepted iff its energy (nearest modes chosen afresh) is
+ *    lower; lambda starts at 1e-3, is divided by 10 on acceptance and
+ *    multiplied by 10 on rejection;
+ *  - a fixed number of iterations.
+ * Returns the energy at the final pose; R, t are updated in place.
+ */
+static void se3_exp(const double xi[6], double Rd[9], double td[3])
+{
+    const double wx = xi[0], wy = xi[1], wz = xi[2];
+    const double th2 = wx * wx + wy * wy + wz * wz;
+    const double th = sqrt(th2);
+    double A, B, C;
+    if (th < 1e-2) {   /* Taylor series of sin(th)/th, (1-cos th)/th^2, (th-sin th)/th^3 to th^4 */
+        A = 1.0 - th2 / 6.0 + th2 * th2 / 120.0;
+        B = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
+        C = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0;
+    } else {
+        A = sin(th) / th;
+        B = (1.0 - cos(th)) / th2;
+        C = (1.0 - A) / th2;
+    }
+    const double W[9] = {0.0, -wz, wy, wz, 0.0, -wx, -wy, wx, 0.0};
+    double W2[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            W2[3 * i + j] = W[3 * i] * W[j] + W[3 * i + 1] * W[3 + j] + W[3 * i + 2] * W[6 + j];
+    double V[9];
+    for (int i = 0; i < 9; ++i) {
+        const double id = (i % 4 == 0) ? 1.0 : 0.0;
+        Rd[i] = id + A * W[i] + B * W2[i];
+        V[i] = id + B * W[i] + C * W2[i];
+    }
+    for (int i = 0; i < 3; ++i) td[i] = V[3 * i] * xi[3] + V[3 * i + 1] * xi[4] + V[3 * i + 2] * xi[5];
+}
+
+/* E over I at (R, t); with N, g non-NULL also the weighted normal equations */
+static double lm_linearise(const view_t* v, const int* I, int nI, int use_cov, const double R[9],
+                           const double t[3], double N[36], double g[6])
+{
+    if (N) {
+        for (int i = 0; i < 36; ++i) N[i] = 0.0;
+        for (int i = 0; i < 6; ++i) g[i] = 0.0;
+    }
+    double E = 0.0;
+    for (int k = 0; k < nI; ++k) {
+        const int pix = I[k];
+        int m = -1;
+        const double e = pixel_energy(v, R, t, pix, use_cov, &m);
+        E += e;
+        if (!N || m < 0) continue;
+        double x[3], y[3];
+        backproject(v->depth[pix], pix % v->w, pix / v->w, v->K, x);
+        for (int a = 0; a < 3; ++a)
+            y[a] = R[3 * a] * x[0] + R[3 * a + 1] * x[1] + R[3 * a + 2] * x[2] + t[a];
+        const float* row = mode_row(v, pix, m);
+        const double r[3] = {y[0] - (double)row[0], y[1] - (double)row[1], y[2] - (double)row[2]};
+        double A[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+        if (use_cov) {
+            A[0] = row[4]; A[1] = row[5]; A[2] = row[6];
+            A[3] = row[5]; A[4] = row[7]; A[5] = row[8];
+            A[6] = row[6]; A[7] = row[8]; A[8] = row[9];
+        }
+        /* J = [-[y]x | I] */
+        const double J[18] = {0.0, y[2], -y[1], 1.0, 0.0, 0.0,
+                              -y[2], 0.0, y[0], 0.0, 1.0, 0.0,
+                              y[1], -y[0], 0.0, 0.0, 0.0, 1.0};
+        double AJ[18], Ar[3];
+        for (int a = 0; a < 3; ++a) {
+            Ar[a] = A[3 * a] * r[0] + A[3 * a + 1] * r[1] + A[3 * a + 2] * r[2];
+            for (int j = 0; j < 6; ++j)
+                AJ[6 * a + j] = A[3 * a] * J[j] + A[3 * a + 1] * J[6 + j] + A[3 * a + 2] * J[12 + j];
+        }
+        const double wgt = 1.0 / (e > 1e-6 ? e : 1e-6);
+        for (int i = 0; i < 6; ++i) {
+            g[i] += wgt * (J[i] * Ar[0] + J[6 + i] * Ar[1] + J[12 + i] * Ar[2]);
+            for (int j = 0; j < 6; ++j)
+                N[6 * i + j] += wgt * (J[i] * AJ[j] + J[6 + i] * AJ[6 + j] + J[12 + i] * AJ[12 + j]);
+        }
+    }
+    return E;
+}
+
+/* solves M d = b for symmetric positive definite M (6x6); 0 when a pivot is
+ * not positive and finite */
+static int cholesky_solve6(const double M[36], const double b[6], double d[6])
+{
+    double L[36] = {0};
+    for (int j = 0; j < 6; ++j) {
+        double s = M[6 * j + j];
+        for (int k = 0; k < j; ++k) s -= L[6 * j + k] * L[6 * j + k];
+        if (!(s > 0.0) || !isfinite(s)) return 0;
+        L[6 * j + j] = sqrt(s);
+        for (int i = j + 1; i < 6; ++i) {
+            double u = M[6 * i + j];
+            for (int k = 0; k < j; ++k) u -= L[6 * i + k] * L[6 * j + k];
+            L[6 * i + j] = u / L[6 * j + j];
+        }
+    }
+    double z[6];
+    for (int i = 0; i < 6; ++i) {
+        double u = b[i];
+        for (int k = 0; k < i; ++k) u -= L[6 * i + k] * z[k];
+        z[i] = u / L[6 * i + i];
+    }
+    for (int i = 5; i >= 0; --i) {
+        double u = z[i];
+        for (int k = i + 1; k < 6; ++k) u -= L[6 * k + i] * d[k];
+        d[i] = u / L[6 * i + i];
+    }
+    return 1;
+}
+
+static double lm_refine(const view_t* v, const int* I, int nI, int use_cov, int iters, double R[9], double t[3])
+{
+    double N[36], g[6];
+    double E = lm_linearise(v, I, nI, use_cov, R, t, N, g);
+    double lambda = 1e-3;
+    for (int it = 0; it < iters; ++it) {
+        double M[36], b[6], d[6];
+        for (int i = 0; i < 36; ++i) M[i] = N[i];
+        for (int i = 0; i < 6; ++i) {
+            M[6 * i + i] = N[6 * i + i] + lambda * N[6 * i + i];
+            b[i] = -g[i];
+        }
+        if (!cholesky_solve6(M, b, d)) {
+            lambda *= 10.0;
+            continue;
+        }
+        double Rd[9], td[3], Rc[9], tc[3];
+        se3_exp(d, Rd, td);
+        for (int i = 0; i < 3; ++i) {
+            for (int j = 0; j < 3; ++j)
+                Rc[3 * i + j] = Rd[3 * i] * R[j] + Rd[3 * i + 1] * R[3 + j] + Rd[3 * i + 2] * R[6 + j];
+            tc[i] = Rd[3 * i] * t[0] + Rd[3 * i + 1] * t[1] + Rd[3 * i + 2] * t[2] + td[i];
+        }
+        double Nc[36], gc[6];
+        const double Ec = lm_linearise(v, I, nI, use_cov, Rc, tc, Nc, gc);
+        if (Ec < E) {
+            E = Ec;
+            for (int i = 0; i < 9; ++i) R[i] = Rc[i];
+            for (int i = 0; i < 3; ++i) t[i] = tc[i];
+            for (int i = 0; i < 36; ++i) N[i] = Nc[i];
+            for (int i = 0; i < 6; ++i) g[i] = gc[i];
+            lambda /= 10.0;
+        } else {
+            lambda *= 10.0;
+        }
+    }
+    return E;
+}
+
+EXPORT double oracle_lm_refine(const float* depth, int w, int h, const float K[4],
+                               const uint16_t* leaves, const uint8_t* nmodes, const float* modes,
+                               int T, int D, int M, const int32_t* I, int nI, int use_cov, int iters,
+                               double pose[12])
+{
+    view_t v = {depth, NULL, w, h, {K[0], K[1], K[2], K[3]}, leaves, nmodes, modes, T, D, M, NULL, 0};
+    return lm_refine(&v, I, nI, use_cov, iters, pose, pose + 9);
+}
+
+EXPORT void oracle_se3_exp(const double xi[6], double Rd[9], double td[3]) { se3_exp(xi, Rd, td); }
+
+EXPORT double oracle_lm_linearise(const float* depth, int w, int h, const float K[4],
+                                  const uint16_t* leaves, const uint8_t* nmodes, const float* modes,
+                                  int T, int D, int M, const int32_t* I, int nI, int use_cov,
+                                  const double pose[12], double N[36], double g[6])
+{
+    view_t v = {depth, NULL, w, h, {K[0], K[1], K[2], K[3]}, leaves, nmodes, modes, T, D, M, NULL, 0};
+    return lm_linearise(&v, I, nI, use_cov, pose, pose + 9, N, g);
+}
+
+/*
+ * Preemptive RANSAC (Sec. 3.2.3).  Hypotheses = the valid slots in slot order.  Every round draws eta pixels
  * from the eligible list (with replacement; round r, pixel k uses draw k%4
  * of the Philox block with counter (SCORE, r, k/4, 0) under the stream key of
  * (seed, request_seed)) and appends them to the
@@ -701,6 +888,11 @@ EXPORT double oracle_pixel_energy(const float* depth, int w, int h, const float 
  * initial cull to the n_cull lowest energies; every later round keeps the
  * ceil(n/2) lowest.  Rounds repeat while more than n_out hypotheses remain
  * (at least one round is always scored).  Order is (energy, slot) ascending.
+ * With pose_update, every round after the first (the initial scoring or cull)
+ * refines each survivor by lm_refine over the whole cumulative I, starting
+ * from its pose so far (FP64, the float32 pose at first), and its energy
+ * becomes E over the cumulative I at the refined pose; pose64_out (may be
+ * NULL) receives every slot's final pose.
  * Outputs: survivors in final order (k = min(n, n_out) of them) with
  * energies; trace arrays (optional): I list, per-round survivor count.
  * Returns the number of rounds run (0 if there is no valid hypothesis).
@@ -725,16 +917,25 @@ EXPORT int oracle_ransac(const float* depth, int w, int h, const float K[4],
                          uint64_t seed, uint64_t request_seed,
                          int32_t* out_slots, double* out_energy, int32_t* out_count,
                          int32_t* I_out, int I_cap, int32_t* round_n, int round_cap,
-                         int32_t* round_slots, double* round_energy)
+                         int32_t* round_slots, double* round_energy, int pose_update,
+                         int lm_iterations, double* pose64_out)
 {
     view_t v = {depth, NULL, w, h, {K[0], K[1], K[2], K[3]}, leaves, nmodes, modes, T, D, M,
                 eligible, n_elig};
     es_t* hs = (es_t*)malloc((size_t)(n_slots > 0 ? n_slots : 1) * sizeof(es_t));
+    double* P64 = (double*)malloc((size_t)(n_slots > 0 ? n_slots : 1) * 12 * sizeof(double));
+    for (size_t i = 0; i < (size_t)n_slots * 12; ++i) P64[i] = (double)poses[i];
+    int* Iall = NULL;
     int n = 0;
     for (int s = 0; s < n_slots; ++s)
         if (valid[s]) { hs[n].e = 0.0; hs[n].slot = s; ++n; }
     *out_count = 0;
-    if (n == 0 || n_elig <= 0) { free(hs); return 0; }
+    if (n == 0 || n_elig <= 0) {
+        if (pose64_out) memcpy(pose64_out, P64, (size_t)n_slots * 12 * sizeof(double));
+        free(hs);
+        free(P64);
+        return 0;
+    }
     int round = 0, nI = 0;
     int first = 1;
     uint32_t key[2];
@@ -746,15 +947,18 @@ EXPORT int oracle_ransac(const float* depth, int w, int h, const float K[4],
             philox_block(TAG_SCORE, 0, (uint32_t)round, (uint32_t)(k / 4), 0, key, r);
             newpix[k] = eligible[uniform_below(r[k % 4], (uint32_t)n_elig)];
             if (I_out && nI < I_cap) I_out[nI] = newpix[k];
+            Iall = (int*)realloc(Iall, (size_t)(nI + 1) * sizeof(int));
+            Iall[nI] = newpix[k];
             ++nI;
         }
         for (int i = 0; i < n; ++i) {
-            const float* P = poses + 12 * (size_t)hs[i].slot;
-            double R[9], t[3];
-            for (int a = 0; a < 9; ++a) R[a] = P[a];
-            for (int a = 0; a < 3; ++a) t[a] = P[9 + a];
+            double* P = P64 + 12 * (size_t)hs[i].slot;
+            if (pose_update && !first) {
+                hs[i].e = lm_refine(&v, Iall, nI, use_cov, lm_iterations, P, P + 9);
+                continue;
+            }
             double acc = 0.0;
-            for (int k = 0; k < eta; ++k) acc += pixel_energy(&v, R, t, newpix[k], use_cov, NULL);
+            for (int k = 0; k < eta; ++k) acc += pixel_energy(&v, P, P + 9, newpix[k], use_cov, NULL);
             hs[i].e += acc;
         }
         free(newpix);
@@ -777,7 +981,10 @@ EXPORT int oracle_ransac(const float* depth, int w, int h, const float K[4],
     int k = n < n_out ? n : n_out;
     for (int i = 0; i < k; ++i) { out_slots[i] = hs[i].slot; out_energy[i] = hs[i].e; }
     *out_count = k;
+    if (pose64_out) memcpy(pose64_out, P64, (size_t)n_slots * 12 * sizeof(double));
     free(hs);
+    free(P64);
+    free(Iall);
     return round;
 }
 
