@@ -80,8 +80,9 @@ typedef struct {
     int32_t ransac_inliers_per_iteration;    /* eta, 1..4096                             */
     int32_t max_relocalisations_to_output;   /* >= 1                                     */
     int32_t use_prediction_covariance;       /* Mahalanobis (1) or Euclidean (0) Eq. 5   */
-    int32_t pose_update;                     /* LM refinement: must be 0 (not provided)  */
+    int32_t pose_update;                     /* 1: LM refinement in se(3) every round    */
     int32_t final_refine;                    /* 1: Kabsch refit over the inliers         */
+    int32_t lm_iterations;                   /* LM iterations per survivor per round, 0..64 */
     float min_squared_distance_between_sampled_modes;   /* check 2 (m^2)                */
     float max_translation_error_for_correct_pose;       /* check 3 tolerance (m)        */
     float max_colour_linf;           /* check 1 threshold, 0..255 scale                  */
@@ -183,6 +184,7 @@ typedef struct {
     int32_t n_cull;           /* N_cull for this call                         */
     int32_t n_out;            /* maxRelocalisationsToOutput for this call     */
     int32_t final_refine;     /* -1 = room's value, 0 = off, 1 = on           */
+    int32_t pose_update;      /* LM refinement: -1 = room's value, 0 = off, 1 = on */
 } rl_reloc_opts;
 
 /* Result record (also the device-side layout written by the batch path). */
@@ -279,9 +281,11 @@ enum {
     RL_BUF_DIRTY = 14,     /* uint8[T][L] leaves awaiting re-clustering             persistent */
     RL_BUF_CBOX = 15,      /* uint32[T][L][M][2] per mode: lowest R,G,B bytes passing the colour
                               check, then highest (lo > hi: none)                   persistent */
-    RL_BUF_EREC = 16       /* uint64[w*h][ew] per eligible-list entry: |M(u)| in bits 0-7, the
+    RL_BUF_EREC = 16,      /* uint64[w*h][ew] per eligible-list entry: |M(u)| in bits 0-7, the
                               colour-check bit of mode m of M(u) in bit 8 + m (m < 56), then 64
                               bits per further word                                 scratch    */
+    RL_BUF_POSE64 = 17     /* double[N][12] per slot: pose after LM refinement (R row-major, t);
+                              valid for the survivors of the last call with pose_update scratch */
 };
 rl_status relocaliser_buffer(const rl_room* room, int32_t which, size_t* offset, size_t* bytes,
                              int32_t* region);

@@ -25,7 +25,7 @@ RL_OK, RL_NO_POSE, RL_EINVAL, RL_ENOMEM, RL_EDEVICE, RL_EBUSY = 0, 1, -1, -2, -3
 
 (BUF_NODES, BUF_RESERVOIR, BUF_SEEN, BUF_MODES, BUF_NMODES, BUF_LEAVES, BUF_NM, BUF_ELIGIBLE,
  BUF_HYPS, BUF_ILIST, BUF_TRACE_SLOTS, BUF_TRACE_ENERGY, BUF_SURVIVORS, BUF_ENERGY,
- BUF_DIRTY, BUF_CBOX, BUF_EREC) = range(17)
+ BUF_DIRTY, BUF_CBOX, BUF_EREC, BUF_POSE64) = range(18)
 
 HYP_DTYPE = np.dtype([("R", "<f4", (9,)), ("t", "<f4", (3,)), ("pix", "<i4", (3,)),
                       ("mode", "<i4", (3,)), ("iter", "<i4"), ("valid", "<i4")])
@@ -59,7 +59,7 @@ class Params(ctypes.Structure):
         ("ransac_inliers_per_iteration", ctypes.c_int32),
         ("max_relocalisations_to_output", ctypes.c_int32),
         ("use_prediction_covariance", ctypes.c_int32), ("pose_update", ctypes.c_int32),
-        ("final_refine", ctypes.c_int32),
+        ("final_refine", ctypes.c_int32), ("lm_iterations", ctypes.c_int32),
         ("min_squared_distance_between_sampled_modes", ctypes.c_float),
         ("max_translation_error_for_correct_pose", ctypes.c_float),
         ("max_colour_linf", ctypes.c_float), ("inlier_threshold", ctypes.c_float),
@@ -78,7 +78,7 @@ class Result(ctypes.Structure):
 
 class RelocOpts(ctypes.Structure):
     _fields_ = [("n_hypotheses", ctypes.c_int32), ("n_cull", ctypes.c_int32), ("n_out", ctypes.c_int32),
-                ("final_refine", ctypes.c_int32)]
+                ("final_refine", ctypes.c_int32), ("pose_update", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -282,12 +282,12 @@ class Room:
         self.schedule = (int(ipt), int(fast_waves))
 
     def relocalise(self, depth, rgb, K, request_seed: int = 0, n_hypotheses: int = 0, n_cull: int = 0,
-                   n_out: int = 0, final_refine: int = -1) -> dict:
+                   n_out: int = 0, final_refine: int = -1, pose_update: int = -1) -> dict:
         """One frame; the optional RANSAC settings override the room's for this call."""
         f = _frame(depth, rgb, K)
         r = Result()
         self._follow(depth, rgb)
-        opts = RelocOpts(int(n_hypotheses), int(n_cull), int(n_out), int(final_refine))
+        opts = RelocOpts(int(n_hypotheses), int(n_cull), int(n_out), int(final_refine), int(pose_update))
         _check(lib().relocaliser_relocalise_opts(self.handle, ctypes.byref(f), int(request_seed),
                                                  ctypes.byref(opts), ctypes.byref(r)), allow=(RL_OK, RL_NO_POSE))
         return _result(r)

@@ -70,6 +70,7 @@ struct Job {
     float theta_col;
     int TP;                   // pixels per scoring block
     int fast_max;             // survivors scored round by round while above this (64 * fast waves)
+    int lm, lm_iters;         // LM refinement of the survivors in every round after the first
     double min_sq_dist, theta_rig, theta_in;
     uint32_t key0, key1;
     // scratch
@@ -86,6 +87,7 @@ struct Job {
     Hyp* hyps;                // [N]
     int* surv;                // [N]
     double* E;                // [N] energy per slot
+    double* pose64;           // [N][12] LM-refined poses (R row-major, t), FP64
     double* partial;          // [ptiles][N]
     double* partial_all;      // [rounds][ptiles][kFastStride] per-round partials once survivors fit fast_max
     int* I;                   // [rounds_max * eta]

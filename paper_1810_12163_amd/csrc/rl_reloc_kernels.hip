@@ -637,7 +637,8 @@ __global__ __launch_bounds__(64) void k_score(const Job* __restrict__ jobs, int 
 {
     const Job& J = jobs[blockIdx.y];
     const int n = J.st->n_surv;
-    if (J.st->done || n <= J.fast_max) return;
+    // jobs with LM refinement: this kernel scores their first round only
+    if (J.st->done || (J.lm ? round > 0 : n <= J.fast_max)) return;
     const int ptile = blockIdx.x % nptiles, htile = blockIdx.x / nptiles;
     const int TP = J.TP;
     const int k0 = ptile * TP;
@@ -674,7 +675,7 @@ __device__ __forceinline__ int rounds_of(int n, int n_cull, int n_out, int r = 0
 __global__ __launch_bounds__(64) void k_score_all(const Job* __restrict__ jobs, int nptiles, int fw)
 {
     const Job& J = jobs[blockIdx.y];
-    if (J.st->done) return;
+    if (J.st->done || J.lm) return;
     const int n = J.st->n_surv, r0 = J.st->rounds_run;
     const int htile = blockIdx.x % fw, rt = blockIdx.x / fw;
     const int round = rt / nptiles, ptile = rt % nptiles;
@@ -696,7 +697,7 @@ __global__ __launch_bounds__(64) void k_score_all(const Job* __restrict__ jobs, 
 __global__ __launch_bounds__(kFastStride) void k_select_all(const Job* __restrict__ jobs, int nptiles)
 {
     const Job& J = jobs[blockIdx.x];
-    if (J.st->done) return;
+    if (J.st->done || J.lm) return;
     __shared__ double sE[kFastStride];
     __shared__ int sS[kFastStride], sA[kFastStride];
     const int n0 = J.st->n_surv;
@@ -745,12 +746,264 @@ __global__ __launch_bounds__(kFastStride) void k_select_all(const Job* __restric
     }
 }
 
+// ------------------------------------------------------------------------
+// Levenberg-Marquardt refinement in se(3) (Sec. 3.2.3, step (ii) of every
+// preemptive-RANSAC iteration after the first): one block per (survivor,
+// job) minimises E of Eq. 5 over the whole cumulative I, from the
+// survivor's pose so far.  Each iteration linearises at the current pose:
+// per pixel the nearest mode (ties to the lower index in M(u)), residual
+// r = H x - mu, e = |r|_A (A = Sigma^-1, or I without the covariance), the
+// Jacobian J = [-[y]x | I] of exp(xi^) y at xi = 0 and the weight
+// 1 / max(e, 1e-6), whose normal equations N d = -g share E's gradient.  The
+// step solves (N + lambda diag N) d = -g by Cholesky (a non-positive pivot
+// rejects it); exp(d^) H is accepted iff its energy is lower (lambda / 10),
+// else lambda * 10; lambda starts at 1e-3.  Sums run per thread in
+// pixel-stride order, then across each wave and the four waves in a fixed
+// order.  The survivor's energy becomes E at the final pose.
+constexpr int kLmVals = 28;      // E, g (6), upper triangle of N (21, row-major)
+
+__device__ void lm_pass(const Job& J, int nI, const double* P, bool write_I, int round, double v[kLmVals])
+{
+#pragma clang fp contract(off)
+    for (int i = 0; i < kLmVals; ++i) v[i] = 0.0;
+    const bool cov = J.use_cov != 0;
+    const uint32_t n_elig = (uint32_t)J.st->n_elig;
+    for (int k = threadIdx.x; k < nI; k += 256) {
+        const int rk = k / J.eta, kk = k - rk * J.eta;
+        const uint4 rb = philox(make_uint4(kTagScore << 28, (uint32_t)rk, (uint32_t)(kk >> 2), 0u), J.key0, J.key1);
+        const uint32_t rv = (kk & 3) == 0 ? rb.x : (kk & 3) == 1 ? rb.y : (kk & 3) == 2 ? rb.z : rb.w;
+        const uint32_t e = below(rv, n_elig);
+        const uint4 c0 = ldg(J.ecold + 2 * e), lw = ldg(J.ecold + 2 * e + 1);
+        const int p = (int)c0.x;
+        if (write_I && rk == round) J.I[k] = p;
+        double x[3];
+        backproject(__uint_as_float(c0.y), p % J.w, p / J.w, J.fx, J.fy, J.cx, J.cy, x);
+        const double y0 = P[0] * x[0] + P[1] * x[1] + P[2] * x[2] + P[9];
+        const double y1 = P[3] * x[0] + P[4] * x[1] + P[5] * x[2] + P[10];
+        const double y2 = P[6] * x[0] + P[7] * x[1] + P[8] * x[2] + P[11];
+        const uint2 nw = make_uint2(c0.z, c0.w);
+        double best = INFINITY;
+        const float4* brow = nullptr;
+        for (int tr = 0; tr < J.T; ++tr) {
+            const int c = (int)count_of(nw, tr);
+            const float4* row = J.modes + ((((size_t)tr << J.D) + leaf_of(lw, tr)) * (size_t)J.M) * 4;
+            for (int j = 0; j < c; ++j) {
+                double q = mode_q(row + 4 * j, y0, y1, y2, cov);
+                if (q < 0.0) q = 0.0;
+                if (q < best) {
+                    best = q;
+                    brow = row + 4 * j;
+                }
+            }
+        }
+        const double en = sqrt(best);
+        v[0] += en;
+        if (brow == nullptr) continue;
+        const float4 a = ldg(brow);
+        const double r0 = y0 - (double)a.x, r1 = y1 - (double)a.y, r2 = y2 - (double)a.z;
+        double A[9] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0};
+        if (cov) {
+            const float4 b = ldg(brow + 1), c = ldg(brow + 2);
+            A[0] = b.x; A[1] = b.y; A[2] = b.z;
+            A[3] = b.y; A[4] = b.w; A[5] = c.x;
+            A[6] = b.z; A[7] = c.x; A[8] = c.y;
+        }
+        const double Jm[18] = {0.0, y2, -y1, 1.0, 0.0, 0.0,
+                               -y2, 0.0, y0, 0.0, 1.0, 0.0,
+                               y1, -y0, 0.0, 0.0, 0.0, 1.0};
+        double AJ[18], Ar[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            Ar[q] = A[3 * q] * r0 + A[3 * q + 1] * r1 + A[3 * q + 2] * r2;
+#pragma unroll
+            for (int j = 0; j < 6; ++j)
+                AJ[6 * q + j] = A[3 * q] * Jm[j] + A[3 * q + 1] * Jm[6 + j] + A[3 * q + 2] * Jm[12 + j];
+        }
+        const double wgt = 1.0 / (en > 1e-6 ? en : 1e-6);
+        int o = 7;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            v[1 + i] += wgt * (Jm[i] * Ar[0] + Jm[6 + i] * Ar[1] + Jm[12 + i] * Ar[2]);
+#pragma unroll
+            for (int j = i; j < 6; ++j)
+                v[o++] += wgt * (Jm[i] * AJ[j] + Jm[6 + i] * AJ[6 + j] + Jm[12 + i] * AJ[12 + j]);
+        }
+    }
+}
+
+// block sum of v (256 threads): the result is valid in thread 0
+__device__ void lm_reduce(double v[kLmVals], double (*s_part)[kLmVals])
+{
+#pragma unroll
+    for (int i = 0; i < kLmVals; ++i) {
+        double x = v[i];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+        v[i] = x;
+    }
+    if ((threadIdx.x & 63) == 0)
+        for (int i = 0; i < kLmVals; ++i) s_part[threadIdx.x >> 6][i] = v[i];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kLmVals; ++i) v[i] = ((s_part[0][i] + s_part[1][i]) + s_part[2][i]) + s_part[3][i];
+    __syncthreads();
+}
+
+// M d = b for a symmetric positive definite 6x6 M; false on a pivot that is
+// not positive and finite
+__device__ bool chol6_solve(const double M[36], const double b[6], double d[6])
+{
+    double L[36];
+    for (int i = 0; i < 36; ++i) L[i] = 0.0;
+    for (int j = 0; j < 6; ++j) {
+        double s = M[6 * j + j];
+        for (int k = 0; k < j; ++k) s -= L[6 * j + k] * L[6 * j + k];
+        if (!(s > 0.0) || !isfinite(s)) return false;
+        L[6 * j + j] = sqrt(s);
+        for (int i = j + 1; i < 6; ++i) {
+            double u = M[6 * i + j];
+            for (int k = 0; k < j; ++k) u -= L[6 * i + k] * L[6 * j + k];
+            L[6 * i + j] = u / L[6 * j + j];
+        }
+    }
+    double z[6];
+    for (int i = 0; i < 6; ++i) {
+        double u = b[i];
+        for (int k = 0; k < i; ++k) u -= L[6 * i + k] * z[k];
+        z[i] = u / L[6 * i + i];
+    }
+    for (int i = 5; i >= 0; --i) {
+        double u = z[i];
+        for (int k = i + 1; k < 6; ++k) u -= L[6 * k + i] * d[k];
+        d[i] = u / L[6 * i + i];
+    }
+    return true;
+}
+
+// exp of xi = (omega, v): R = I + A W + B W^2, t = (I + B W + C W^2) v, with
+// A = sin(th)/th, B = (1 - cos th)/th^2, C = (th - sin th)/th^3 (Taylor
+// series to th^4 below th = 1e-2)
+__device__ void se3_exp(const double xi[6], double Rd[9], double td[3])
+{
+#pragma clang fp contract(off)
+    const double wx = xi[0], wy = xi[1], wz = xi[2];
+    const double th2 = wx * wx + wy * wy + wz * wz;
+    const double th = sqrt(th2);
+    double A, B, C;
+    if (th < 1e-2) {
+        A = 1.0 - th2 / 6.0 + th2 * th2 / 120.0;
+        B = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
+        C = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0;
+    } else {
+        A = sin(th) / th;
+        B = (1.0 - cos(th)) / th2;
+        C = (1.0 - A) / th2;
+    }
+    const double W[9] = {0.0, -wz, wy, wz, 0.0, -wx, -wy, wx, 0.0};
+    double W2[9], V[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            W2[3 * i + j] = W[3 * i] * W[j] + W[3 * i + 1] * W[3 + j] + W[3 * i + 2] * W[6 + j];
+    for (int i = 0; i < 9; ++i) {
+        const double id = (i % 4 == 0) ? 1.0 : 0.0;
+        Rd[i] = id + A * W[i] + B * W2[i];
+        V[i] = id + B * W[i] + C * W2[i];
+    }
+    for (int i = 0; i < 3; ++i) td[i] = V[3 * i] * xi[3] + V[3 * i + 1] * xi[4] + V[3 * i + 2] * xi[5];
+}
+
+// grid (survivors entering the round, jobs), 256 threads
+__global__ __launch_bounds__(256) void k_lm(const Job* __restrict__ jobs, int round)
+{
+#pragma clang fp contract(off)
+    const Job& J = jobs[blockIdx.y];
+    if (!J.lm || J.st->done) return;
+    const int pos = blockIdx.x;
+    if (pos >= J.st->n_surv) return;
+    __shared__ double s_part[4][kLmVals];
+    __shared__ double s_P[12];
+    __shared__ int s_go;
+    const int slot = J.surv[pos];
+    const int nI = (round + 1) * J.eta;
+    if (threadIdx.x < 12) {
+        const int i = threadIdx.x;
+        s_P[i] = round == 1 ? (double)(i < 9 ? J.hyps[slot].R[i] : J.hyps[slot].t[i - 9]) : J.pose64[12 * slot + i];
+    }
+    __syncthreads();
+    double P[12];
+    for (int i = 0; i < 12; ++i) P[i] = s_P[i];
+    double v[kLmVals];
+    lm_pass(J, nI, P, pos == 0, round, v);
+    lm_reduce(v, s_part);
+    // thread 0 keeps the iteration state
+    double E = v[0], g[6], N[36], cur[12], lambda = 1e-3;
+    if (threadIdx.x == 0) {
+        int o = 7;
+        for (int i = 0; i < 6; ++i) {
+            g[i] = v[1 + i];
+            for (int j = i; j < 6; ++j) N[6 * i + j] = N[6 * j + i] = v[o++];
+        }
+        for (int i = 0; i < 12; ++i) cur[i] = P[i];
+    }
+    for (int it = 0; it < J.lm_iters; ++it) {
+        if (threadIdx.x == 0) {
+            double M[36], b[6], d[6];
+            for (int i = 0; i < 36; ++i) M[i] = N[i];
+            for (int i = 0; i < 6; ++i) {
+                M[6 * i + i] = N[6 * i + i] + lambda * N[6 * i + i];
+                b[i] = -g[i];
+            }
+            const bool ok = chol6_solve(M, b, d);
+            s_go = ok ? 1 : 0;
+            if (ok) {
+                double Rd[9], td[3];
+                se3_exp(d, Rd, td);
+                for (int i = 0; i < 3; ++i) {
+                    for (int j = 0; j < 3; ++j)
+                        s_P[3 * i + j] = Rd[3 * i] * cur[j] + Rd[3 * i + 1] * cur[3 + j] + Rd[3 * i + 2] * cur[6 + j];
+                    s_P[9 + i] = Rd[3 * i] * cur[9] + Rd[3 * i + 1] * cur[10] + Rd[3 * i + 2] * cur[11] + td[i];
+                }
+            } else {
+                lambda *= 10.0;
+            }
+        }
+        __syncthreads();
+        const bool go = s_go != 0;
+        for (int i = 0; i < 12; ++i) P[i] = s_P[i];
+        __syncthreads();
+        if (!go) continue;
+        lm_pass(J, nI, P, false, round, v);
+        lm_reduce(v, s_part);
+        if (threadIdx.x == 0) {
+            if (v[0] < E) {
+                E = v[0];
+                int o = 7;
+                for (int i = 0; i < 6; ++i) {
+                    g[i] = v[1 + i];
+                    for (int j = i; j < 6; ++j) N[6 * i + j] = N[6 * j + i] = v[o++];
+                }
+                for (int i = 0; i < 12; ++i) cur[i] = P[i];
+                lambda /= 10.0;
+            } else {
+                lambda *= 10.0;
+            }
+        }
+    }
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < 12; ++i) J.pose64[12 * slot + i] = cur[i];
+        for (int i = 0; i < 9; ++i) J.hyps[slot].R[i] = (float)cur[i];
+        for (int i = 0; i < 3; ++i) J.hyps[slot].t[i] = (float)cur[9 + i];
+        J.E[slot] = E;
+    }
+}
+
 // Adds the round's partial sums (tile order), ranks survivors by
 // (energy, slot) and keeps the initial cull or the better half.
 __global__ __launch_bounds__(1024) void k_select(const Job* __restrict__ jobs, int round, int nptiles)
 {
     const Job& J = jobs[blockIdx.y];
-    if (J.st->done || J.st->n_surv <= J.fast_max) return;
+    if (J.st->done || (!J.lm && J.st->n_surv <= J.fast_max)) return;
+    // after an LM round the energies are already over the whole cumulative I
+    const bool add = !(J.lm && round > 0);
     extern __shared__ unsigned char s_raw[];
     const int n = J.st->n_surv;
     double* sE = reinterpret_cast<double*>(s_raw);
@@ -758,8 +1011,7 @@ __global__ __launch_bounds__(1024) void k_select(const Job* __restrict__ jobs, i
     const int ptiles = min(nptiles, (J.eta + J.TP - 1) / J.TP);
     for (int p = threadIdx.x; p < n; p += blockDim.x) {
         const int s = J.surv[p];
-        const double acc = sum_in_order(J.partial + p, (size_t)J.N, ptiles);
-        const double e = J.E[s] + acc;
+        const double e = add ? J.E[s] + sum_in_order(J.partial + p, (size_t)J.N, ptiles) : J.E[s];
         J.E[s] = e;
         sE[p] = isnan(e) ? INFINITY : e;
         sS[p] = s;
@@ -1121,6 +1373,14 @@ hipError_t launch_score(const Job* jobs, int njobs, int round, int nptiles, int 
 {
     const int htiles = (maxSurv + 63) / 64;
     k_score<<<dim3(nptiles * htiles, njobs), dim3(64), 0, st>>>(jobs, round, nptiles);
+    RL_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_lm(const Job* jobs, int njobs, int round, int maxSurv, hipStream_t st)
+{
+    if (maxSurv < 1) return hipSuccess;
+    k_lm<<<dim3(maxSurv, njobs), dim3(256), 0, st>>>(jobs, round);
     RL_CHECK_LAUNCH();
     return hipSuccess;
 }

@@ -29,6 +29,7 @@ hipError_t launch_hyp_finalize(const Job* jobs, int njobs, int maxN, hipStream_t
 hipError_t launch_score(const Job* jobs, int njobs, int round, int nptiles, int maxSurv,
                         hipStream_t st);
 hipError_t launch_score_all(const Job* jobs, int njobs, int rounds, int nptiles, int fw, hipStream_t st);
+hipError_t launch_lm(const Job* jobs, int njobs, int round, int maxSurv, hipStream_t st);
 hipError_t launch_select(const Job* jobs, int njobs, int round, int nptiles, int maxN, hipStream_t st);
 hipError_t launch_finalize(const Job* jobs, int njobs, int maxIlen, hipStream_t st);
 hipError_t launch_depth_scores(const float* depth, int w, int h, float fx, float fy, float cx, float cy,
@@ -120,7 +121,7 @@ int score_tile(int) { return kScoreTile; }
 // Per-frame (relocalisation) scratch of one job slot.
 struct FrameLayout {
     size_t state, result, probe, leaves, nmt, nm, tile_count, eligible, ecold, erec, hyp_best, hyps, surv, E, partial,
-        partial_all,
+        partial_all, pose64,
         I, inl, trace_slots, trace_E, total;
     int ew;
 };
@@ -152,6 +153,7 @@ FrameLayout frame_layout(int maxP, int N, int eta, int rounds, int TP, int rows_
     L.hyps = c.take((size_t)N * sizeof(Hyp));
     L.surv = c.take((size_t)N * 4);
     L.E = c.take((size_t)N * 8);
+    L.pose64 = c.take((size_t)N * 96);
     const int ptiles = (eta + TP - 1) / TP;
     L.partial = c.take((size_t)ptiles * N * 8);
     L.partial_all = c.take((size_t)rounds * ptiles * kFastStride * 8);
@@ -356,6 +358,7 @@ RL_API rl_status rl_params_preset(const char* name, rl_params* out)
     p.clusterer_sigma = 0.1f;
     p.max_cluster_count = 50;
     p.max_pose_candidates_after_cull = 64;
+    p.lm_iterations = 10;
     const std::string n(name);
     if (n == "default") {
         p.clusterer_tau = 0.05f; p.min_cluster_size = 20; p.reservoir_capacity = 1024;
@@ -422,7 +425,10 @@ RL_API rl_status rl_params_validate(const rl_params* p)
     if (p->max_pose_candidates_after_cull < 1) return fail(RL_EINVAL, "max_pose_candidates_after_cull must be >= 1");
     if (p->ransac_inliers_per_iteration < 1 || p->ransac_inliers_per_iteration > 4096) return fail(RL_EINVAL, "ransac_inliers_per_iteration must be in 1..4096");
     if (p->max_relocalisations_to_output < 1) return fail(RL_EINVAL, "max_relocalisations_to_output must be >= 1");
-    if (p->pose_update != 0) return fail(RL_EINVAL, "pose_update (Levenberg-Marquardt refinement) is not provided; set it to 0");
+    if (p->pose_update != 0 && p->pose_update != 1) return fail(RL_EINVAL, "pose_update must be 0 or 1");
+    if (p->lm_iterations < 0 || p->lm_iterations > 64) return fail(RL_EINVAL, "lm_iterations must be in 0..64");
+    if (p->use_prediction_covariance != 0 && p->use_prediction_covariance != 1)
+        return fail(RL_EINVAL, "use_prediction_covariance must be 0 or 1");
     const float fs[] = {p->clusterer_sigma, p->clusterer_tau, p->min_squared_distance_between_sampled_modes,
                         p->max_translation_error_for_correct_pose, p->max_colour_linf, p->inlier_threshold,
                         p->cov_regulariser};
@@ -487,6 +493,8 @@ static Job make_job(const rl_room* r, char* scr, const FrameLayout& FL, const rl
     J.theta_col = r->p.max_colour_linf;
     J.TP = r->TP;
     J.fast_max = 64 * r->sched.fw;
+    J.lm = r->p.pose_update;
+    J.lm_iters = r->p.lm_iterations;
     J.min_sq_dist = r->p.min_squared_distance_between_sampled_modes;
     J.theta_rig = r->p.max_translation_error_for_correct_pose;
     J.theta_in = r->p.inlier_threshold;
@@ -506,6 +514,7 @@ static Job make_job(const rl_room* r, char* scr, const FrameLayout& FL, const rl
     J.hyps = reinterpret_cast<Hyp*>(scr + FL.hyps);
     J.surv = reinterpret_cast<int*>(scr + FL.surv);
     J.E = reinterpret_cast<double*>(scr + FL.E);
+    J.pose64 = reinterpret_cast<double*>(scr + FL.pose64);
     J.partial = reinterpret_cast<double*>(scr + FL.partial);
     J.partial_all = reinterpret_cast<double*>(scr + FL.partial_all);
     J.I = reinterpret_cast<int*>(scr + FL.I);
@@ -863,7 +872,7 @@ RL_API rl_status rl_batch_set_schedule(rl_batch* b, int32_t ipt, int32_t fast_wa
 }
 
 static hipError_t launch_sequence(const Job* jobs, int njobs, int maxP, int maxN, int maxIters, int T,
-                                  const std::vector<int>& entering, int nptiles, int maxEta,
+                                  const std::vector<int>& entering, int nptiles, int maxEta, bool any_lm,
                                   const Schedule& sc, const Timer& tm, hipStream_t st)
 {
     hipError_t e;
@@ -879,9 +888,12 @@ static hipError_t launch_sequence(const Job* jobs, int njobs, int maxP, int maxN
     RL_MARK(RL_TIMER_HYP_SEARCH, stop);
     RL_TRY(launch_hyp_finalize(jobs, njobs, maxN, st));
     RL_MARK(RL_TIMER_RANSAC, start);
-    // rounds with more than 64 * fw survivors one at a time, the rest at once
-    for (int r = 0; r < (int)entering.size() && entering[r] > 64 * sc.fw; ++r) {
+    // rounds with more than 64 * fw survivors one at a time, the rest at once;
+    // with LM refinement (which re-scores every round after the first) all
+    // rounds one at a time
+    for (int r = 0; r < (int)entering.size() && (any_lm || entering[r] > 64 * sc.fw); ++r) {
         RL_TRY(launch_score(jobs, njobs, r, nptiles, entering[r], st));
+        if (any_lm && r > 0) RL_TRY(launch_lm(jobs, njobs, r, entering[r], st));
         RL_TRY(launch_select(jobs, njobs, r, nptiles, maxN, st));
     }
     RL_TRY(launch_score_all(jobs, njobs, (int)entering.size(), nptiles, sc.fw, st));
@@ -930,6 +942,7 @@ RL_API rl_status relocaliser_relocalise_opts(rl_room* r, const rl_frame* f, uint
     const int n_cull = opts && opts->n_cull > 0 ? opts->n_cull : r->p.max_pose_candidates_after_cull;
     const int n_out = opts && opts->n_out > 0 ? opts->n_out : r->p.max_relocalisations_to_output;
     const int refine = opts && opts->final_refine >= 0 ? (opts->final_refine ? 1 : 0) : r->p.final_refine;
+    const int lm = opts && opts->pose_update >= 0 ? (opts->pose_update ? 1 : 0) : r->p.pose_update;
     if (N > r->N) return fail(RL_EINVAL, "%d hypotheses exceed the room's maximum %d", N, r->N);
     std::vector<int> entering;
     const int R = rounds_for(N, n_cull, n_out, &entering);
@@ -940,17 +953,18 @@ RL_API rl_status relocaliser_relocalise_opts(rl_room* r, const rl_frame* f, uint
     J.n_cull = n_cull;
     J.n_out = n_out;
     J.final_refine = refine;
+    J.lm = lm;
     *r->job_host = J;
     Job* jd = reinterpret_cast<Job*>(r->scr + r->job_off);
     hipError_t e = hipMemcpyAsync(jd, r->job_host, sizeof(Job), hipMemcpyHostToDevice, r->stream);
     if (e != hipSuccess) return hip_fail(e, "job upload");
     const int nptiles = (r->eta + r->TP - 1) / r->TP;
     const int P = f->width * f->height;
-    std::vector<long long> key = {P, N, r->sched.ipt, r->sched.fw};
+    std::vector<long long> key = {P, N, r->sched.ipt, r->sched.fw, lm};
     for (int v : entering) key.push_back(v);
     e = run_sequence(r->graphs, key, r->timer.kernel == RL_TIMER_NONE, r->stream, [&]() {
         return launch_sequence(jd, 1, P, N, r->p.max_candidate_generation_iterations, r->T, entering,
-                               nptiles, r->eta, r->sched, r->timer, r->stream);
+                               nptiles, r->eta, lm != 0, r->sched, r->timer, r->stream);
     });
     if (e != hipSuccess) return hip_fail(e, "relocalise launch");
     e = hipMemcpyAsync(r->res_host, r->scr + r->FL.result, sizeof(rl_result), hipMemcpyDeviceToHost, r->stream);
@@ -1085,6 +1099,7 @@ RL_API rl_status relocaliser_buffer(const rl_room* r, int32_t which, size_t* off
         case RL_BUF_ENERGY: *offset = r->FL.E; *bytes = (size_t)r->N * 8; *region = 1; break;
         case RL_BUF_CBOX: *offset = r->PL.cbox; *bytes = TL * r->M * 8; *region = 0; break;
         case RL_BUF_EREC: *offset = r->FL.erec; *bytes = (size_t)r->maxP * r->FL.ew * 8; *region = 1; break;
+        case RL_BUF_POSE64: *offset = r->FL.pose64; *bytes = (size_t)r->N * 96; *region = 1; break;
         default: return fail(RL_EINVAL, "unknown buffer %d", which);
     }
     return RL_OK;
@@ -1169,6 +1184,7 @@ RL_API rl_status rl_batch_relocalise_async(rl_batch* b, const rl_request* reqs, 
     if (!b || !reqs || !dev_results) return fail(RL_EINVAL, "NULL argument");
     if (n < 1 || n > b->bp.max_frames) return fail(RL_EINVAL, "batch of %d requests (1..%d allowed)", n, b->bp.max_frames);
     int maxP = 0, maxN = 0, maxIters = 0, maxEta = 0;
+    bool any_lm = false;
     std::vector<int> entering;
     for (int i = 0; i < n; ++i) {
         const rl_request& q = reqs[i];
@@ -1190,6 +1206,7 @@ RL_API rl_status rl_batch_relocalise_async(rl_batch* b, const rl_request* reqs, 
         maxN = std::max(maxN, N);
         maxIters = std::max(maxIters, r->p.max_candidate_generation_iterations);
         maxEta = std::max(maxEta, r->eta);
+        any_lm = any_lm || r->p.pose_update != 0;
     }
     // Launch shapes come in few classes so that few graphs are captured:
     // grids cover the batch's largest frame, and the job count is padded to
@@ -1232,10 +1249,11 @@ RL_API rl_status rl_batch_relocalise_async(rl_batch* b, const rl_request* reqs, 
     const int nptiles = (maxEta + b->TP - 1) / b->TP;
     if (use_graph && b->stream == nullptr)
         return fail(RL_EINVAL, "graph replay needs a batch created on a non-default stream");
-    std::vector<long long> key = {nq, maxN, maxIters, nptiles, maxEta, b->bp.n_trees, b->sched.ipt, b->sched.fw};
+    std::vector<long long> key = {nq, maxN, maxIters, nptiles, maxEta, b->bp.n_trees, b->sched.ipt, b->sched.fw,
+                                  any_lm ? 1 : 0};
     for (int v : entering) key.push_back(v);
     e = run_sequence(b->graphs, key, use_graph && b->timer.kernel == RL_TIMER_NONE, b->stream, [&]() {
-        return launch_sequence(jd, nq, maxP, maxN, maxIters, b->bp.n_trees, entering, nptiles, maxEta,
+        return launch_sequence(jd, nq, maxP, maxN, maxIters, b->bp.n_trees, entering, nptiles, maxEta, any_lm,
                                b->sched, b->timer, b->stream);
     });
     if (e != hipSuccess) return hip_fail(e, "batch launch");

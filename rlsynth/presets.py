@@ -13,6 +13,8 @@ Readings where the paper gives no value:
 * cov_regulariser = 1e-6 m^2 is added to each mode covariance before
   inversion;
 * inlier_threshold = 0.05 m for the optional final refit over inliers;
+* lm_iterations = 10 Levenberg-Marquardt iterations per survivor and round
+  when pose_update is on;
 * max_pose_candidates_after_cull >= max_pose_candidates disables the initial
   cull, giving pure halving rounds.
 """
@@ -26,7 +28,7 @@ FIELDS_INT = [
     "max_candidate_generation_iterations", "max_pose_candidates",
     "max_pose_candidates_after_cull", "ransac_inliers_per_iteration",
     "max_relocalisations_to_output", "use_prediction_covariance", "pose_update",
-    "final_refine",
+    "final_refine", "lm_iterations",
 ]
 FIELDS_FLOAT = [
     "clusterer_sigma", "clusterer_tau",
@@ -39,7 +41,7 @@ FIELDS_U64 = ["seed"]
 _COMMON = dict(
     n_trees=5, depth=15, ref_width=640,
     max_colour_linf=30.0, inlier_threshold=0.05, cov_regulariser=1e-6,
-    final_refine=0, seed=0,
+    final_refine=0, seed=0, lm_iterations=10,
 )
 
 PAPER = {

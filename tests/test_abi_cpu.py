@@ -91,8 +91,11 @@ def validate(**over):
 
 def test_parameter_validation():
     assert validate() == rl.RL_OK
-    assert validate(pose_update=1) == rl.RL_EINVAL
+    assert validate(pose_update=1) == rl.RL_OK
+    assert validate(pose_update=2) == rl.RL_EINVAL
     assert "pose_update" in rl.lib().rl_last_error().decode()
+    assert validate(lm_iterations=65) == rl.RL_EINVAL
+    assert validate(lm_iterations=-1) == rl.RL_EINVAL
     for bad in [dict(n_trees=0), dict(n_trees=9), dict(depth=16), dict(depth=0),
                 dict(max_cluster_count=65), dict(n_trees=8, max_cluster_count=40),
                 dict(reservoir_capacity=0), dict(reservoir_capacity=5000),

@@ -161,7 +161,7 @@ def test_invalid_arguments_rejected_before_launch(c1):
     bad_nodes["kind"][0, 3] = 7
     with pytest.raises(rl.RlError):
         rl.Room(w.params, bad_nodes, 160, 120)
-    p = dict(w.params, pose_update=1)
+    p = dict(w.params, pose_update=2)
     with pytest.raises(rl.RlError):
         rl.Room(p, w.nodes, 160, 120)
     # unreliable frames are not inserted

@@ -155,6 +155,41 @@ def test_c3_decimated_stage_matches_oracle(c2, c3_room):
     assert abs(res["energy"] - ref["energy"]) <= 1e-4 * abs(ref["energy"])
 
 
+def test_lm_640x480_matches_oracle(c2, c3_room):
+    """LM refinement at 640x480 (1024 hypothesis slots, cull to 64, halving
+    to one) in every round after the first, over up to (rounds x 500) pixels:
+    survivors of every round, the survivors' refined poses (1e-5), energies
+    (1e-4 relative) and the winner."""
+    w, o, _ = c2
+    p3, r3 = c3_room
+    q = w.queries[0]
+    d, c = dev(q)
+    r3.set_trace(True)
+    res = r3.relocalise(d, c, q.K, request_seed=41, n_hypotheses=1024, n_cull=64, n_out=1, final_refine=0,
+                        pose_update=1)
+    params = dict(p3, max_pose_candidates=1024, max_pose_candidates_after_cull=64,
+                  max_relocalisations_to_output=1, final_refine=0, pose_update=1)
+    ref = _stage_ref(r3, q, params, 41, o.T, o.D, o.M, w.nodes, p3["ref_width"])
+    print(f"[lm 640x480] valid {res['n_valid']}, rounds {res['rounds']} (oracle {ref['rounds']}), "
+          f"winner {res['winner']} (oracle {ref['winner']})", flush=True)
+    assert res["n_valid"] == int(ref["hyp_valid"].sum())
+    assert res["rounds"] == ref["rounds"] >= 2
+    N = 1024                                 # trace rows are strided by the call's hypothesis count
+    ts = r3.buffer_np(rl.BUF_TRACE_SLOTS, np.int32).reshape(-1, N)
+    te = r3.buffer_np(rl.BUF_TRACE_ENERGY, np.float64).reshape(-1, N)
+    P64 = r3.buffer_np(rl.BUF_POSE64, np.float64).reshape(-1, 12)
+    for r in range(ref["rounds"]):
+        k = len(ref["round_slots"][r])
+        np.testing.assert_array_equal(ts[r, :k], ref["round_slots"][r])
+        np.testing.assert_allclose(te[r, :k], ref["round_energy"][r], rtol=1e-4)
+    outs = ref["round_slots"][-1]
+    dp = float(np.abs(P64[outs] - ref["refined_pose64"][outs]).max())
+    print(f"[lm 640x480] refined pose diff {dp:.2e}", flush=True)
+    assert dp < 1e-5
+    assert res["winner"] == ref["winner"] and pose_diff(res["pose"], ref["pose"]) < 1e-5
+    r3.set_trace(False)
+
+
 def test_c3_wide_stage_keeps_16_and_model_score_matches(c2, c3_room):
     w, o, _ = c2
     p3, r3 = c3_room
