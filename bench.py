@@ -55,6 +55,11 @@ TRAVERSE_PIXEL_HBM = 4 + 3 + 8 + 8 + 16
 SCORE_MODE_FLOPS = 24
 SCORE_PAIR_FLOPS = 20
 MI355X_FP64 = 78.6e12
+# FP64 flops per pixel of one Levenberg-Marquardt pass besides its mode
+# evaluations: the transform (18), the residual's A r (15), A J (90), the
+# gradient (42) and the normal matrix's upper triangle (147), the root and
+# the weight (3), and the energy sum (1).
+LM_PIXEL_FLOPS = 316
 
 
 def log(*a):
@@ -111,6 +116,8 @@ def main():
     ap.add_argument("--serve-rooms", type=int, default=16)
     ap.add_argument("--serve-leaves-per-frame", type=int, default=256,
                     help="mode update schedule of the served rooms: 0 exact, K leaves per adapted frame")
+    ap.add_argument("--lm-steps", type=int, default=5,
+                    help="steps of the batch with LM refinement (0 = skip that leg)")
     ap.add_argument("--schedule", default="auto",
                     help="launch schedule 'ipt,fast_waves' (e.g. 4,1), or 'auto' to time every one first")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -269,6 +276,8 @@ def main():
     errs = [scene.pose_error(r["pose"].astype(np.float64), w.queries[qi].pose) for r, (qi, _) in zip(res, frames)]
     ok = [e[0] <= 0.05 and e[1] <= 5.0 for e in errs]
 
+    lm = lm_leg(args, rl, room, batch, reqs, frames, w, qd, qc, use_graph) if args.lm_steps > 0 else None
+
     # ---- rooflines -------------------------------------------------------------
     def roof_search(ms):
         k = ms * 1e-3
@@ -344,12 +353,82 @@ def main():
         "batched": dict(relocs_per_s=value, step_p50_ms=percentile(step_ms, 50),
                         step_p99_ms=percentile(step_ms, 99), identical_to_plain=bool(same)),
         "served": served,
+        "lm": lm,
         "accuracy": dict(frac_within_5cm_5deg=float(np.mean(ok)),
                          median_cm=float(np.median([e[0] for e in errs]) * 100),
                          median_deg=float(np.median([e[1] for e in errs]))),
         "paper_context": "Fast relocaliser 25.1 ms/frame on a GTX 1080 Ti (Table 3)",
     }
     print(json.dumps(out), flush=True)
+
+
+def lm_leg(args, rl, room, batch, reqs, frames, w, qd, qc, use_graph):
+    """The same batch with Levenberg-Marquardt refinement in se(3) in every
+    round after the first (the paper's pose update), through the batched
+    path: throughput, the RANSAC stage's FP64 rate, equality with the plain
+    path and accuracy."""
+    import torch
+
+    from rlsynth import scene
+    p = w.params
+    eta = p["ransac_inliers_per_iteration"]
+    iters = p["lm_iterations"]
+    plain = []
+    flops = 0
+    for (qi, s) in frames:
+        r = room.relocalise(qd[qi], qc[qi], w.queries[qi].K, request_seed=s, pose_update=1)
+        plain.append(r)
+        if r["rounds"] == 0:
+            continue
+        I = room.buffer_np(rl.BUF_ILIST, np.int32)[:r["rounds"] * eta]
+        nm = room.buffer_np(rl.BUF_NM, np.uint8).astype(np.int64)
+        per_px = nm[I] * SCORE_MODE_FLOPS
+        n, first = r["n_valid"], True
+        for rr in range(r["rounds"]):
+            if rr == 0:
+                flops += n * int(per_px[:eta].sum() + eta * SCORE_PAIR_FLOPS)
+            else:
+                flops += n * (iters + 1) * int(per_px[:(rr + 1) * eta].sum() + (rr + 1) * eta * LM_PIXEL_FLOPS)
+            cull = p["max_pose_candidates_after_cull"]
+            n = cull if (first and cull < n) else ((n + 1) // 2 if n > p["max_relocalisations_to_output"] else n)
+            first = False
+    lreqs = [q + (0, 1) for q in reqs]            # n_hypotheses: the room's; pose_update: on
+    for _ in range(args.warmup):
+        res = batch.relocalise(lreqs, use_graph=use_graph)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.lm_steps):
+        res = batch.relocalise(lreqs, use_graph=use_graph)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    ev1.record()
+    torch.cuda.synchronize()
+    batch.set_timer(rl.TIMER_RANSAC, ev0, ev1)
+    ms = []
+    for _ in range(args.lm_steps):
+        batch.relocalise(lreqs, use_graph=False)
+        ms.append(ev0.elapsed_time(ev1))
+    batch.set_timer(rl.TIMER_NONE)
+    rms = float(np.mean(ms))
+    same = all(np.array_equal(a["pose"], b["pose"]) and a["energy"] == b["energy"] for a, b in zip(res, plain))
+    errs = [scene.pose_error(r["pose"].astype(np.float64), w.queries[qi].pose) for r, (qi, _) in zip(res, frames)]
+    B = len(reqs)
+    out = dict(relocs_per_s=B * args.lm_steps / el, ms_per_step=el / args.lm_steps * 1e3, lm_iterations=iters,
+               identical_to_plain=bool(same),
+               frac_within_5cm_5deg=float(np.mean([e[0] <= 0.05 and e[1] <= 5.0 for e in errs])),
+               median_cm=float(np.median([e[0] for e in errs]) * 100),
+               roofline=dict(kernel="k_score+k_lm+k_select (RANSAC stage)", bound="alu",
+                             achieved=flops / (rms * 1e-3) / 1e12, peak=MI355X_FP64 / 1e12, unit="TFLOP/s (FP64)",
+                             frac=flops / (rms * 1e-3) / MI355X_FP64, launch_ms=rms,
+                             work=f"{flops} FP64 flops (first-round scoring; LM passes x pixels x "
+                                  f"(|M(u)| x {SCORE_MODE_FLOPS} + {LM_PIXEL_FLOPS}))"))
+    log(f"[bench] LM: {out['relocs_per_s']:.1f} reloc/s ({out['ms_per_step']:.2f} ms per {B}-frame step), "
+        f"RANSAC stage {rms:.3f} ms, {out['roofline']['achieved']:.2f} TFLOP/s FP64, "
+        f"within 5cm/5deg {out['frac_within_5cm_5deg']:.3f}, identical to plain {same}")
+    return out
 
 
 def serve_leg(args, rl, dev, inputs):

@@ -324,7 +324,7 @@ typedef struct {
     rl_frame frame;
     uint64_t request_seed;
     int32_t n_hypotheses;    /* 0 = the room's max_pose_candidates              */
-    int32_t pad;
+    int32_t pose_update;     /* LM refinement: 0 = the room's value, 1 = on, -1 = off */
 } rl_request;
 
 /* Device workspace bytes of a batch context (256-byte aligned buffer); the

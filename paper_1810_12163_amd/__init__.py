@@ -83,7 +83,7 @@ class RelocOpts(ctypes.Structure):
 
 class Request(ctypes.Structure):
     _fields_ = [("room", ctypes.c_void_p), ("frame", Frame), ("request_seed", ctypes.c_uint64),
-                ("n_hypotheses", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("n_hypotheses", ctypes.c_int32), ("pose_update", ctypes.c_int32)]
 
 
 class BatchParams(ctypes.Structure):
@@ -404,14 +404,17 @@ class Batch:
             room, depth, rgb, K = q[0], q[1], q[2], q[3]
             seed = q[4] if len(q) > 4 else 0
             nh = q[5] if len(q) > 5 else 0
+            pu = q[6] if len(q) > 6 else 0
             arr[i].room = room.handle
             arr[i].frame = _frame(depth, rgb, K)
             arr[i].request_seed = int(seed)
             arr[i].n_hypotheses = int(nh)
+            arr[i].pose_update = int(pu)
         return arr
 
     def relocalise(self, reqs, use_graph: bool = True) -> list:
-        """reqs: sequence of (room, depth, rgb, K[, request_seed[, n_hypotheses]])."""
+        """reqs: sequence of (room, depth, rgb, K[, request_seed[, n_hypotheses[, pose_update]]]);
+        pose_update 0 = the room's value, 1 = LM on, -1 = off."""
         arr = self._requests(reqs)
         res = (Result * len(reqs))()
         _check(lib().rl_batch_relocalise(self.handle, arr, len(reqs), res, 1 if use_graph else 0))

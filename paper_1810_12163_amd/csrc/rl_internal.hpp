@@ -30,6 +30,10 @@ constexpr int kScoreTile = RL_SCORE_TILE;     // pixels per scoring wave
 constexpr int kMaxModelSurfaces = 64, kMaxModelPoses = 64;
 
 constexpr int kMaxFastWaves = 4;
+
+// LM refinement: pixels per pass wave, doubles of per-slot state
+constexpr int kLmTile = 256;
+constexpr int kLmStateDoubles = 56;
 constexpr int kFastStride = 64 * kMaxFastWaves;
 
 struct JobState {
@@ -88,6 +92,10 @@ struct Job {
     int* surv;                // [N]
     double* E;                // [N] energy per slot
     double* pose64;           // [N][12] LM-refined poses (R row-major, t), FP64
+    double* lm_state;         // [N][kLmStateDoubles] LM iteration state per slot
+    double* lm_part;          // [N][lm_tiles][28] LM pass partial sums per (survivor position, tile)
+    int* Ie;                  // [rounds_max * eta] eligible-list entries of I
+    int lm_tiles, pad2;       // tiles of the largest cumulative I
     double* partial;          // [ptiles][N]
     double* partial_all;      // [rounds][ptiles][kFastStride] per-round partials once survivors fit fast_max
     int* I;                   // [rounds_max * eta]

@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 #include <limits.h>
 
+#include <algorithm>
+
 #include "rl_internal.hpp"
 
 namespace rl {
@@ -748,34 +750,96 @@ __global__ __launch_bounds__(kFastStride) void k_select_all(const Job* __restric
 
 // ------------------------------------------------------------------------
 // Levenberg-Marquardt refinement in se(3) (Sec. 3.2.3, step (ii) of every
-// preemptive-RANSAC iteration after the first): one block per (survivor,
-// job) minimises E of Eq. 5 over the whole cumulative I, from the
-// survivor's pose so far.  Each iteration linearises at the current pose:
-// per pixel the nearest mode (ties to the lower index in M(u)), residual
-// r = H x - mu, e = |r|_A (A = Sigma^-1, or I without the covariance), the
-// Jacobian J = [-[y]x | I] of exp(xi^) y at xi = 0 and the weight
-// 1 / max(e, 1e-6), whose normal equations N d = -g share E's gradient.  The
-// step solves (N + lambda diag N) d = -g by Cholesky (a non-positive pivot
-// rejects it); exp(d^) H is accepted iff its energy is lower (lambda / 10),
-// else lambda * 10; lambda starts at 1e-3.  Sums run per thread in
-// pixel-stride order, then across each wave and the four waves in a fixed
-// order.  The survivor's energy becomes E at the final pose.
+// preemptive-RANSAC iteration after the first): each survivor's E of Eq. 5
+// over the whole cumulative I is minimised from its pose so far.  Each
+// iteration linearises at the current pose: per pixel the nearest mode
+// (ties to the lower index in M(u)), residual r = H x - mu, e = |r|_A
+// (A = Sigma^-1, or I without the covariance), the Jacobian J = [-[y]x | I]
+// of exp(xi^) y at xi = 0 and the weight 1 / max(e, 1e-6), whose normal
+// equations N d = -g share E's gradient.  The step solves
+// (N + lambda diag N) d = -g by Cholesky (a non-positive pivot rejects it);
+// exp(d^) H is accepted iff its energy is lower (lambda / 10), else
+// lambda * 10; lambda starts at 1e-3.  The survivor's energy becomes E at
+// the final pose.
+//
+// The work is spread over the grid: a pass evaluates (E, g, N) for every
+// survivor of every job at once, one wave per (survivor, 256-pixel tile)
+// writing its partial sums; a step kernel (one thread per survivor) adds
+// the tiles in order, takes the accept/reject decision and the next damped
+// step.  Per round: k_lm_draw, k_lm_init, then (iterations + 1) x
+// (k_lm_pass, k_lm_step).
 constexpr int kLmVals = 28;      // E, g (6), upper triangle of N (21, row-major)
 
-__device__ void lm_pass(const Job& J, int nI, const double* P, bool write_I, int round, double v[kLmVals])
+// per-slot state (doubles): current pose, candidate pose, N (upper), g, E,
+// lambda, go (the candidate awaits evaluation)
+enum { kLmCur = 0, kLmCand = 12, kLmN = 24, kLmG = 45, kLmE = 51, kLmLambda = 52, kLmGo = 53 };
+
+// list entries of the cumulative I: all of rounds 0 and 1 in round 1, the
+// round's own afterwards (the pixels are those the scoring draws)
+__global__ __launch_bounds__(256) void k_lm_draw(const Job* __restrict__ jobs, int round)
+{
+    const Job& J = jobs[blockIdx.y];
+    if (!J.lm || J.st->done || J.st->n_elig <= 0) return;
+    const int k = (round == 1 ? 0 : round * J.eta) + (int)(blockIdx.x * 256 + threadIdx.x);
+    if (k >= (round + 1) * J.eta) return;
+    const int rk = k / J.eta, kk = k - rk * J.eta;
+    const uint4 rb = philox(make_uint4(kTagScore << 28, (uint32_t)rk, (uint32_t)(kk >> 2), 0u), J.key0, J.key1);
+    const uint32_t rv = (kk & 3) == 0 ? rb.x : (kk & 3) == 1 ? rb.y : (kk & 3) == 2 ? rb.z : rb.w;
+    const uint32_t e = below(rv, (uint32_t)J.st->n_elig);
+    J.Ie[k] = (int)e;
+    J.I[k] = (int)ldg(J.ecold + 2 * e).x;
+}
+
+__global__ __launch_bounds__(256) void k_lm_init(const Job* __restrict__ jobs, int round)
+{
+    const Job& J = jobs[blockIdx.y];
+    const int pos = blockIdx.x * 256 + threadIdx.x;
+    if (!J.lm || J.st->done || pos >= J.st->n_surv) return;
+    const int slot = J.surv[pos];
+    double* S = J.lm_state + (size_t)slot * kLmStateDoubles;
+    for (int i = 0; i < 12; ++i) {
+        const double v = round == 1 ? (double)(i < 9 ? J.hyps[slot].R[i] : J.hyps[slot].t[i - 9])
+                                    : J.pose64[12 * (size_t)slot + i];
+        S[kLmCur + i] = v;
+        S[kLmCand + i] = v;
+    }
+    S[kLmLambda] = 1e-3;
+    S[kLmGo] = 1.0;
+}
+
+__device__ void lm_pass_item(const Job& J, int pos, int tile, int nI);
+
+// grid (waves per job, jobs), one wave per block; the waves of a job stride
+// over its (survivor, tile) items
+__global__ __launch_bounds__(64) void k_lm_pass(const Job* __restrict__ jobs, int round)
 {
 #pragma clang fp contract(off)
+    const Job& J = jobs[blockIdx.y];
+    if (!J.lm || J.st->done) return;
+    const int nI = (round + 1) * J.eta;
+    const int tiles = (nI + kLmTile - 1) / kLmTile;
+    const int items = J.st->n_surv * tiles;
+    for (int item = blockIdx.x; item < items; item += gridDim.x)
+        lm_pass_item(J, item / tiles, item % tiles, nI);
+}
+
+__device__ void lm_pass_item(const Job& J, int pos, int tile, int nI)
+{
+#pragma clang fp contract(off)
+    const int slot = J.surv[pos];
+    const double* S = J.lm_state + (size_t)slot * kLmStateDoubles;
+    if (S[kLmGo] == 0.0) return;
+    double P[12];
+    for (int i = 0; i < 12; ++i) P[i] = S[kLmCand + i];
+    double v[kLmVals];
     for (int i = 0; i < kLmVals; ++i) v[i] = 0.0;
     const bool cov = J.use_cov != 0;
-    const uint32_t n_elig = (uint32_t)J.st->n_elig;
-    for (int k = threadIdx.x; k < nI; k += 256) {
-        const int rk = k / J.eta, kk = k - rk * J.eta;
-        const uint4 rb = philox(make_uint4(kTagScore << 28, (uint32_t)rk, (uint32_t)(kk >> 2), 0u), J.key0, J.key1);
-        const uint32_t rv = (kk & 3) == 0 ? rb.x : (kk & 3) == 1 ? rb.y : (kk & 3) == 2 ? rb.z : rb.w;
-        const uint32_t e = below(rv, n_elig);
+    for (int j = 0; j < kLmTile / 64; ++j) {
+        const int k = tile * kLmTile + j * 64 + (int)threadIdx.x;
+        if (k >= nI) break;
+        const uint32_t e = (uint32_t)ldg(J.Ie + k);
         const uint4 c0 = ldg(J.ecold + 2 * e), lw = ldg(J.ecold + 2 * e + 1);
         const int p = (int)c0.x;
-        if (write_I && rk == round) J.I[k] = p;
         double x[3];
         backproject(__uint_as_float(c0.y), p % J.w, p / J.w, J.fx, J.fy, J.cx, J.cy, x);
         const double y0 = P[0] * x[0] + P[1] * x[1] + P[2] * x[2] + P[9];
@@ -787,12 +851,26 @@ __device__ void lm_pass(const Job& J, int nI, const double* P, bool write_I, int
         for (int tr = 0; tr < J.T; ++tr) {
             const int c = (int)count_of(nw, tr);
             const float4* row = J.modes + ((((size_t)tr << J.D) + leaf_of(lw, tr)) * (size_t)J.M) * 4;
-            for (int j = 0; j < c; ++j) {
-                double q = mode_q(row + 4 * j, y0, y1, y2, cov);
-                if (q < 0.0) q = 0.0;
-                if (q < best) {
-                    best = q;
-                    brow = row + 4 * j;
+            int m = 0;
+            for (; m + 4 <= c; m += 4) {           // four rows in flight, compared in order
+                double q[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) q[u] = mode_q(row + 4 * (m + u), y0, y1, y2, cov);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const double qq = q[u] < 0.0 ? 0.0 : q[u];
+                    if (qq < best) {
+                        best = qq;
+                        brow = row + 4 * (m + u);
+                    }
+                }
+            }
+            for (; m < c; ++m) {
+                double qq = mode_q(row + 4 * m, y0, y1, y2, cov);
+                if (qq < 0.0) qq = 0.0;
+                if (qq < best) {
+                    best = qq;
+                    brow = row + 4 * m;
                 }
             }
         }
@@ -816,8 +894,8 @@ __device__ void lm_pass(const Job& J, int nI, const double* P, bool write_I, int
         for (int q = 0; q < 3; ++q) {
             Ar[q] = A[3 * q] * r0 + A[3 * q + 1] * r1 + A[3 * q + 2] * r2;
 #pragma unroll
-            for (int j = 0; j < 6; ++j)
-                AJ[6 * q + j] = A[3 * q] * Jm[j] + A[3 * q + 1] * Jm[6 + j] + A[3 * q + 2] * Jm[12 + j];
+            for (int jj = 0; jj < 6; ++jj)
+                AJ[6 * q + jj] = A[3 * q] * Jm[jj] + A[3 * q + 1] * Jm[6 + jj] + A[3 * q + 2] * Jm[12 + jj];
         }
         const double wgt = 1.0 / (en > 1e-6 ? en : 1e-6);
         int o = 7;
@@ -825,27 +903,20 @@ __device__ void lm_pass(const Job& J, int nI, const double* P, bool write_I, int
         for (int i = 0; i < 6; ++i) {
             v[1 + i] += wgt * (Jm[i] * Ar[0] + Jm[6 + i] * Ar[1] + Jm[12 + i] * Ar[2]);
 #pragma unroll
-            for (int j = i; j < 6; ++j)
-                v[o++] += wgt * (Jm[i] * AJ[j] + Jm[6 + i] * AJ[6 + j] + Jm[12 + i] * AJ[12 + j]);
+            for (int jj = i; jj < 6; ++jj)
+                v[o++] += wgt * (Jm[i] * AJ[jj] + Jm[6 + i] * AJ[6 + jj] + Jm[12 + i] * AJ[12 + jj]);
         }
     }
-}
-
-// block sum of v (256 threads): the result is valid in thread 0
-__device__ void lm_reduce(double v[kLmVals], double (*s_part)[kLmVals])
-{
 #pragma unroll
     for (int i = 0; i < kLmVals; ++i) {
         double x = v[i];
         for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
         v[i] = x;
     }
-    if ((threadIdx.x & 63) == 0)
-        for (int i = 0; i < kLmVals; ++i) s_part[threadIdx.x >> 6][i] = v[i];
-    __syncthreads();
-    if (threadIdx.x == 0)
-        for (int i = 0; i < kLmVals; ++i) v[i] = ((s_part[0][i] + s_part[1][i]) + s_part[2][i]) + s_part[3][i];
-    __syncthreads();
+    if (threadIdx.x == 0) {
+        double* out = J.lm_part + ((size_t)pos * J.lm_tiles + tile) * kLmVals;
+        for (int i = 0; i < kLmVals; ++i) out[i] = v[i];
+    }
 }
 
 // M d = b for a symmetric positive definite 6x6 M; false on a pivot that is
@@ -911,89 +982,70 @@ __device__ void se3_exp(const double xi[6], double Rd[9], double td[3])
     for (int i = 0; i < 3; ++i) td[i] = V[3 * i] * xi[3] + V[3 * i + 1] * xi[4] + V[3 * i + 2] * xi[5];
 }
 
-// grid (survivors entering the round, jobs), 256 threads
-__global__ __launch_bounds__(256) void k_lm(const Job* __restrict__ jobs, int round)
+// one thread per (survivor, job).  it = -1 follows the pass at the starting
+// pose; it >= 0 follows iteration it's candidate pass.  The last iteration
+// writes the refined pose (FP64, and rounded into the hypothesis table)
+// and the energy.
+__global__ __launch_bounds__(256) void k_lm_step(const Job* __restrict__ jobs, int round, int it)
 {
 #pragma clang fp contract(off)
     const Job& J = jobs[blockIdx.y];
-    if (!J.lm || J.st->done) return;
-    const int pos = blockIdx.x;
-    if (pos >= J.st->n_surv) return;
-    __shared__ double s_part[4][kLmVals];
-    __shared__ double s_P[12];
-    __shared__ int s_go;
+    const int pos = blockIdx.x * 256 + threadIdx.x;
+    if (!J.lm || J.st->done || pos >= J.st->n_surv || it >= J.lm_iters) return;
     const int slot = J.surv[pos];
-    const int nI = (round + 1) * J.eta;
-    if (threadIdx.x < 12) {
-        const int i = threadIdx.x;
-        s_P[i] = round == 1 ? (double)(i < 9 ? J.hyps[slot].R[i] : J.hyps[slot].t[i - 9]) : J.pose64[12 * slot + i];
-    }
-    __syncthreads();
-    double P[12];
-    for (int i = 0; i < 12; ++i) P[i] = s_P[i];
-    double v[kLmVals];
-    lm_pass(J, nI, P, pos == 0, round, v);
-    lm_reduce(v, s_part);
-    // thread 0 keeps the iteration state
-    double E = v[0], g[6], N[36], cur[12], lambda = 1e-3;
-    if (threadIdx.x == 0) {
-        int o = 7;
-        for (int i = 0; i < 6; ++i) {
-            g[i] = v[1 + i];
-            for (int j = i; j < 6; ++j) N[6 * i + j] = N[6 * j + i] = v[o++];
-        }
-        for (int i = 0; i < 12; ++i) cur[i] = P[i];
-    }
-    for (int it = 0; it < J.lm_iters; ++it) {
-        if (threadIdx.x == 0) {
-            double M[36], b[6], d[6];
-            for (int i = 0; i < 36; ++i) M[i] = N[i];
-            for (int i = 0; i < 6; ++i) {
-                M[6 * i + i] = N[6 * i + i] + lambda * N[6 * i + i];
-                b[i] = -g[i];
-            }
-            const bool ok = chol6_solve(M, b, d);
-            s_go = ok ? 1 : 0;
-            if (ok) {
-                double Rd[9], td[3];
-                se3_exp(d, Rd, td);
-                for (int i = 0; i < 3; ++i) {
-                    for (int j = 0; j < 3; ++j)
-                        s_P[3 * i + j] = Rd[3 * i] * cur[j] + Rd[3 * i + 1] * cur[3 + j] + Rd[3 * i + 2] * cur[6 + j];
-                    s_P[9 + i] = Rd[3 * i] * cur[9] + Rd[3 * i + 1] * cur[10] + Rd[3 * i + 2] * cur[11] + td[i];
-                }
-            } else {
-                lambda *= 10.0;
-            }
-        }
-        __syncthreads();
-        const bool go = s_go != 0;
-        for (int i = 0; i < 12; ++i) P[i] = s_P[i];
-        __syncthreads();
-        if (!go) continue;
-        lm_pass(J, nI, P, false, round, v);
-        lm_reduce(v, s_part);
-        if (threadIdx.x == 0) {
-            if (v[0] < E) {
-                E = v[0];
-                int o = 7;
-                for (int i = 0; i < 6; ++i) {
-                    g[i] = v[1 + i];
-                    for (int j = i; j < 6; ++j) N[6 * i + j] = N[6 * j + i] = v[o++];
-                }
-                for (int i = 0; i < 12; ++i) cur[i] = P[i];
-                lambda /= 10.0;
-            } else {
-                lambda *= 10.0;
-            }
+    double* S = J.lm_state + (size_t)slot * kLmStateDoubles;
+    const int tiles = ((round + 1) * J.eta + kLmTile - 1) / kLmTile;
+    double lambda = S[kLmLambda];
+    if (S[kLmGo] != 0.0) {
+        double v[kLmVals];
+        for (int i = 0; i < kLmVals; ++i) v[i] = 0.0;
+        const double* part = J.lm_part + (size_t)pos * J.lm_tiles * kLmVals;
+        for (int t = 0; t < tiles; ++t)
+            for (int i = 0; i < kLmVals; ++i) v[i] += part[(size_t)t * kLmVals + i];
+        if (it < 0 || v[0] < S[kLmE]) {
+            S[kLmE] = v[0];
+            for (int i = 0; i < 21; ++i) S[kLmN + i] = v[7 + i];
+            for (int i = 0; i < 6; ++i) S[kLmG + i] = v[1 + i];
+            for (int i = 0; i < 12; ++i) S[kLmCur + i] = S[kLmCand + i];
+            if (it >= 0) lambda /= 10.0;
+        } else {
+            lambda *= 10.0;
         }
     }
-    if (threadIdx.x == 0) {
-        for (int i = 0; i < 12; ++i) J.pose64[12 * slot + i] = cur[i];
-        for (int i = 0; i < 9; ++i) J.hyps[slot].R[i] = (float)cur[i];
-        for (int i = 0; i < 3; ++i) J.hyps[slot].t[i] = (float)cur[9 + i];
-        J.E[slot] = E;
+    if (it == J.lm_iters - 1) {
+        for (int i = 0; i < 12; ++i) J.pose64[12 * (size_t)slot + i] = S[kLmCur + i];
+        for (int i = 0; i < 9; ++i) J.hyps[slot].R[i] = (float)S[kLmCur + i];
+        for (int i = 0; i < 3; ++i) J.hyps[slot].t[i] = (float)S[kLmCur + 9 + i];
+        J.E[slot] = S[kLmE];
+        S[kLmGo] = 0.0;
+        S[kLmLambda] = lambda;
+        return;
     }
+    // the next damped step from the current pose
+    double N[36], M[36], b[6], d[6];
+    int o = 0;
+    for (int i = 0; i < 6; ++i)
+        for (int j = i; j < 6; ++j) N[6 * i + j] = N[6 * j + i] = S[kLmN + o++];
+    for (int i = 0; i < 36; ++i) M[i] = N[i];
+    for (int i = 0; i < 6; ++i) {
+        M[6 * i + i] = N[6 * i + i] + lambda * N[6 * i + i];
+        b[i] = -S[kLmG + i];
+    }
+    if (chol6_solve(M, b, d)) {
+        double Rd[9], td[3];
+        se3_exp(d, Rd, td);
+        const double* C = S + kLmCur;
+        for (int i = 0; i < 3; ++i) {
+            for (int j = 0; j < 3; ++j)
+                S[kLmCand + 3 * i + j] = Rd[3 * i] * C[j] + Rd[3 * i + 1] * C[3 + j] + Rd[3 * i + 2] * C[6 + j];
+            S[kLmCand + 9 + i] = Rd[3 * i] * C[9] + Rd[3 * i + 1] * C[10] + Rd[3 * i + 2] * C[11] + td[i];
+        }
+        S[kLmGo] = 1.0;
+    } else {
+        lambda *= 10.0;
+        S[kLmGo] = 0.0;
+    }
+    S[kLmLambda] = lambda;
 }
 
 // Adds the round's partial sums (tile order), ranks survivors by
@@ -1377,11 +1429,22 @@ hipError_t launch_score(const Job* jobs, int njobs, int round, int nptiles, int 
     return hipSuccess;
 }
 
-hipError_t launch_lm(const Job* jobs, int njobs, int round, int maxSurv, hipStream_t st)
+hipError_t launch_lm(const Job* jobs, int njobs, int round, int maxSurv, int maxEta, int maxIters, hipStream_t st)
 {
     if (maxSurv < 1) return hipSuccess;
-    k_lm<<<dim3(maxSurv, njobs), dim3(256), 0, st>>>(jobs, round);
+    const dim3 thr((maxSurv + 255) / 256, njobs);
+    k_lm_draw<<<dim3((2 * maxEta + 255) / 256, njobs), dim3(256), 0, st>>>(jobs, round);
     RL_CHECK_LAUNCH();
+    k_lm_init<<<thr, dim3(256), 0, st>>>(jobs, round);
+    RL_CHECK_LAUNCH();
+    const int tiles = ((round + 1) * maxEta + kLmTile - 1) / kLmTile;
+    const int waves = maxSurv * tiles;
+    for (int it = -1; it < maxIters; ++it) {
+        k_lm_pass<<<dim3(waves, njobs), dim3(64), 0, st>>>(jobs, round);
+        RL_CHECK_LAUNCH();
+        k_lm_step<<<thr, dim3(256), 0, st>>>(jobs, round, it);
+        RL_CHECK_LAUNCH();
+    }
     return hipSuccess;
 }
 

@@ -29,7 +29,7 @@ hipError_t launch_hyp_finalize(const Job* jobs, int njobs, int maxN, hipStream_t
 hipError_t launch_score(const Job* jobs, int njobs, int round, int nptiles, int maxSurv,
                         hipStream_t st);
 hipError_t launch_score_all(const Job* jobs, int njobs, int rounds, int nptiles, int fw, hipStream_t st);
-hipError_t launch_lm(const Job* jobs, int njobs, int round, int maxSurv, hipStream_t st);
+hipError_t launch_lm(const Job* jobs, int njobs, int round, int maxSurv, int maxEta, int maxIters, hipStream_t st);
 hipError_t launch_select(const Job* jobs, int njobs, int round, int nptiles, int maxN, hipStream_t st);
 hipError_t launch_finalize(const Job* jobs, int njobs, int maxIlen, hipStream_t st);
 hipError_t launch_depth_scores(const float* depth, int w, int h, float fx, float fy, float cx, float cy,
@@ -121,9 +121,10 @@ int score_tile(int) { return kScoreTile; }
 // Per-frame (relocalisation) scratch of one job slot.
 struct FrameLayout {
     size_t state, result, probe, leaves, nmt, nm, tile_count, eligible, ecold, erec, hyp_best, hyps, surv, E, partial,
-        partial_all, pose64,
+        partial_all, pose64, lm_state, lm_part, Ie,
         I, inl, trace_slots, trace_E, total;
     int ew;
+    int lm_tiles;
 };
 
 // 64-bit words per eligible-pixel record: |M(u)| and 56 colour-check bits in
@@ -154,6 +155,10 @@ FrameLayout frame_layout(int maxP, int N, int eta, int rounds, int TP, int rows_
     L.surv = c.take((size_t)N * 4);
     L.E = c.take((size_t)N * 8);
     L.pose64 = c.take((size_t)N * 96);
+    L.lm_tiles = (rounds * eta + kLmTile - 1) / kLmTile;
+    L.lm_state = c.take((size_t)N * kLmStateDoubles * 8);
+    L.lm_part = c.take((size_t)N * L.lm_tiles * 28 * 8);
+    L.Ie = c.take((size_t)rounds * eta * 4);
     const int ptiles = (eta + TP - 1) / TP;
     L.partial = c.take((size_t)ptiles * N * 8);
     L.partial_all = c.take((size_t)rounds * ptiles * kFastStride * 8);
@@ -515,6 +520,10 @@ static Job make_job(const rl_room* r, char* scr, const FrameLayout& FL, const rl
     J.surv = reinterpret_cast<int*>(scr + FL.surv);
     J.E = reinterpret_cast<double*>(scr + FL.E);
     J.pose64 = reinterpret_cast<double*>(scr + FL.pose64);
+    J.lm_state = reinterpret_cast<double*>(scr + FL.lm_state);
+    J.lm_part = reinterpret_cast<double*>(scr + FL.lm_part);
+    J.Ie = reinterpret_cast<int*>(scr + FL.Ie);
+    J.lm_tiles = FL.lm_tiles;
     J.partial = reinterpret_cast<double*>(scr + FL.partial);
     J.partial_all = reinterpret_cast<double*>(scr + FL.partial_all);
     J.I = reinterpret_cast<int*>(scr + FL.I);
@@ -873,7 +882,7 @@ RL_API rl_status rl_batch_set_schedule(rl_batch* b, int32_t ipt, int32_t fast_wa
 
 static hipError_t launch_sequence(const Job* jobs, int njobs, int maxP, int maxN, int maxIters, int T,
                                   const std::vector<int>& entering, int nptiles, int maxEta, bool any_lm,
-                                  const Schedule& sc, const Timer& tm, hipStream_t st)
+                                  int lm_iters, const Schedule& sc, const Timer& tm, hipStream_t st)
 {
     hipError_t e;
 #define RL_TRY(x) do { e = (x); if (e != hipSuccess) return e; } while (0)
@@ -893,7 +902,7 @@ static hipError_t launch_sequence(const Job* jobs, int njobs, int maxP, int maxN
     // rounds one at a time
     for (int r = 0; r < (int)entering.size() && (any_lm || entering[r] > 64 * sc.fw); ++r) {
         RL_TRY(launch_score(jobs, njobs, r, nptiles, entering[r], st));
-        if (any_lm && r > 0) RL_TRY(launch_lm(jobs, njobs, r, entering[r], st));
+        if (any_lm && r > 0) RL_TRY(launch_lm(jobs, njobs, r, entering[r], maxEta, lm_iters, st));
         RL_TRY(launch_select(jobs, njobs, r, nptiles, maxN, st));
     }
     RL_TRY(launch_score_all(jobs, njobs, (int)entering.size(), nptiles, sc.fw, st));
@@ -960,11 +969,11 @@ RL_API rl_status relocaliser_relocalise_opts(rl_room* r, const rl_frame* f, uint
     if (e != hipSuccess) return hip_fail(e, "job upload");
     const int nptiles = (r->eta + r->TP - 1) / r->TP;
     const int P = f->width * f->height;
-    std::vector<long long> key = {P, N, r->sched.ipt, r->sched.fw, lm};
+    std::vector<long long> key = {P, N, r->sched.ipt, r->sched.fw, lm, r->p.lm_iterations};
     for (int v : entering) key.push_back(v);
     e = run_sequence(r->graphs, key, r->timer.kernel == RL_TIMER_NONE, r->stream, [&]() {
         return launch_sequence(jd, 1, P, N, r->p.max_candidate_generation_iterations, r->T, entering,
-                               nptiles, r->eta, lm != 0, r->sched, r->timer, r->stream);
+                               nptiles, r->eta, lm != 0, r->p.lm_iterations, r->sched, r->timer, r->stream);
     });
     if (e != hipSuccess) return hip_fail(e, "relocalise launch");
     e = hipMemcpyAsync(r->res_host, r->scr + r->FL.result, sizeof(rl_result), hipMemcpyDeviceToHost, r->stream);
@@ -1185,6 +1194,7 @@ RL_API rl_status rl_batch_relocalise_async(rl_batch* b, const rl_request* reqs, 
     if (n < 1 || n > b->bp.max_frames) return fail(RL_EINVAL, "batch of %d requests (1..%d allowed)", n, b->bp.max_frames);
     int maxP = 0, maxN = 0, maxIters = 0, maxEta = 0;
     bool any_lm = false;
+    int lm_iters = 0;
     std::vector<int> entering;
     for (int i = 0; i < n; ++i) {
         const rl_request& q = reqs[i];
@@ -1206,7 +1216,10 @@ RL_API rl_status rl_batch_relocalise_async(rl_batch* b, const rl_request* reqs, 
         maxN = std::max(maxN, N);
         maxIters = std::max(maxIters, r->p.max_candidate_generation_iterations);
         maxEta = std::max(maxEta, r->eta);
-        any_lm = any_lm || r->p.pose_update != 0;
+        if (q.pose_update < -1 || q.pose_update > 1) return fail(RL_EINVAL, "request %d: pose_update must be -1, 0 or 1", i);
+        const bool lm = q.pose_update == 0 ? r->p.pose_update != 0 : q.pose_update > 0;
+        any_lm = any_lm || lm;
+        if (lm) lm_iters = std::max(lm_iters, r->p.lm_iterations);
     }
     // Launch shapes come in few classes so that few graphs are captured:
     // grids cover the batch's largest frame, and the job count is padded to
@@ -1232,6 +1245,7 @@ RL_API rl_status rl_batch_relocalise_async(rl_batch* b, const rl_request* reqs, 
             const int N = q.n_hypotheses > 0 ? q.n_hypotheses : q.room->N;
             J = make_job(q.room, b->ws, b->slots[i], &q.frame, q.request_seed, N);
             J.result = dev_results + i;
+            if (q.pose_update != 0) J.lm = q.pose_update > 0 ? 1 : 0;
         } else {
             std::memset(&J, 0, sizeof(J));
             J.T = b->bp.n_trees;
@@ -1250,11 +1264,11 @@ RL_API rl_status rl_batch_relocalise_async(rl_batch* b, const rl_request* reqs, 
     if (use_graph && b->stream == nullptr)
         return fail(RL_EINVAL, "graph replay needs a batch created on a non-default stream");
     std::vector<long long> key = {nq, maxN, maxIters, nptiles, maxEta, b->bp.n_trees, b->sched.ipt, b->sched.fw,
-                                  any_lm ? 1 : 0};
+                                  any_lm ? 1 : 0, lm_iters};
     for (int v : entering) key.push_back(v);
     e = run_sequence(b->graphs, key, use_graph && b->timer.kernel == RL_TIMER_NONE, b->stream, [&]() {
         return launch_sequence(jd, nq, maxP, maxN, maxIters, b->bp.n_trees, entering, nptiles, maxEta, any_lm,
-                               b->sched, b->timer, b->stream);
+                               lm_iters, b->sched, b->timer, b->stream);
     });
     if (e != hipSuccess) return hip_fail(e, "batch launch");
     e = hipEventRecord(b->ev, b->stream);
