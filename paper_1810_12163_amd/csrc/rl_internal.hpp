@@ -29,10 +29,13 @@ constexpr int kScoreTile = RL_SCORE_TILE;     // pixels per scoring wave
 // analytic scene models for the model-based scores
 constexpr int kMaxModelSurfaces = 64, kMaxModelPoses = 64;
 
+// frames of one batched launch
+constexpr int kMaxBatchFrames = 4096;
+
 constexpr int kMaxFastWaves = 4;
 
 // LM refinement: pixels per pass wave, doubles of per-slot state
-constexpr int kLmTile = 256;
+constexpr int kLmTile = 128;
 constexpr int kLmStateDoubles = 56;
 constexpr int kFastStride = 64 * kMaxFastWaves;
 
@@ -95,6 +98,7 @@ struct Job {
     double* lm_state;         // [N][kLmStateDoubles] LM iteration state per slot
     double* lm_part;          // [N][lm_tiles][28] LM pass partial sums per (survivor position, tile)
     int* Ie;                  // [rounds_max * eta] eligible-list entries of I
+    int* lm_plan;             // [jobs + 1] LM work plan of the launch (shared by its jobs)
     int lm_tiles, pad2;       // tiles of the largest cumulative I
     double* partial;          // [ptiles][N]
     double* partial_all;      // [rounds][ptiles][kFastStride] per-round partials once survivors fit fast_max

@@ -807,23 +807,80 @@ __global__ __launch_bounds__(256) void k_lm_init(const Job* __restrict__ jobs, i
     S[kLmGo] = 1.0;
 }
 
-__device__ void lm_pass_item(const Job& J, int pos, int tile, int nI);
+template <bool COV>
+__device__ __forceinline__ void lm_pass_item(const Job& J, int pos, int tile, int nI);
 
 // grid (waves per job, jobs), one wave per block; the waves of a job stride
 // over its (survivor, tile) items
-__global__ __launch_bounds__(64) void k_lm_pass(const Job* __restrict__ jobs, int round)
+// Work plan of a round (one block): the (survivor, tile) items of every job
+// with LM, numbered job after job; plan[j] = first item of job j,
+// plan[njobs] = their total.
+__global__ __launch_bounds__(1024) void k_lm_plan(const Job* __restrict__ jobs, int njobs, int round)
 {
-#pragma clang fp contract(off)
-    const Job& J = jobs[blockIdx.y];
-    if (!J.lm || J.st->done) return;
-    const int nI = (round + 1) * J.eta;
-    const int tiles = (nI + kLmTile - 1) / kLmTile;
-    const int items = J.st->n_surv * tiles;
-    for (int item = blockIdx.x; item < items; item += gridDim.x)
-        lm_pass_item(J, item / tiles, item % tiles, nI);
+    __shared__ int s_x[1024];
+    int* plan = jobs[0].lm_plan;
+    int carry = 0;
+    for (int base = 0; base < njobs; base += 1024) {
+        const int j = base + (int)threadIdx.x;
+        int items = 0;
+        if (j < njobs) {
+            const Job& J = jobs[j];
+            if (J.lm && !J.st->done) items = J.st->n_surv * (((round + 1) * J.eta + kLmTile - 1) / kLmTile);
+        }
+        s_x[threadIdx.x] = items;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {           // inclusive scan
+            const int add = (int)threadIdx.x >= o ? s_x[threadIdx.x - o] : 0;
+            __syncthreads();
+            s_x[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (j < njobs) plan[j] = carry + s_x[threadIdx.x] - items;
+        carry += s_x[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) plan[njobs] = carry;
 }
 
-__device__ void lm_pass_item(const Job& J, int pos, int tile, int nI)
+// 1-D grid of waves striding over the plan's items of all jobs, so that a
+// job with many survivors gets as many waves as its items need.
+__global__ __launch_bounds__(64) void k_lm_pass(const Job* __restrict__ jobs, int njobs, int round)
+{
+#pragma clang fp contract(off)
+    const int* plan = jobs[0].lm_plan;
+    const int total = plan[njobs];
+    for (int gi = blockIdx.x; gi < total; gi += gridDim.x) {
+        int lo = 0, hi = njobs - 1;                    // last job whose first item is <= gi
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (plan[mid] <= gi) lo = mid;
+            else hi = mid - 1;
+        }
+        const Job& J = jobs[lo];
+        const int nI = (round + 1) * J.eta;
+        const int tiles = (nI + kLmTile - 1) / kLmTile;
+        const int item = gi - plan[lo];
+        if (J.use_cov) lm_pass_item<true>(J, item / tiles, item % tiles, nI);
+        else lm_pass_item<false>(J, item / tiles, item % tiles, nI);
+    }
+}
+
+// q = d^T A d for d = y - mu (A = the row's Sigma^-1, or I), as mode_q
+// evaluates it, from rows already loaded
+template <bool COV>
+__device__ __forceinline__ double row_q(const float4& a, const float4& b, const float4& c, double y0, double y1,
+                                        double y2)
+{
+#pragma clang fp contract(off)
+    const double d0 = y0 - (double)a.x, d1 = y1 - (double)a.y, d2 = y2 - (double)a.z;
+    if (!COV) return d0 * d0 + d1 * d1 + d2 * d2;
+    const double m3 = b.x, m4 = b.y, m5 = b.z, m6 = b.w, m7 = c.x, m8 = c.y;
+    return d0 * (m3 * d0 + m4 * d1 + m5 * d2) + d1 * (m4 * d0 + m6 * d1 + m7 * d2)
+         + d2 * (m5 * d0 + m7 * d1 + m8 * d2);
+}
+
+template <bool COV>
+__device__ __forceinline__ void lm_pass_item(const Job& J, int pos, int tile, int nI)
 {
 #pragma clang fp contract(off)
     const int slot = J.surv[pos];
@@ -846,45 +903,60 @@ __device__ void lm_pass_item(const Job& J, int pos, int tile, int nI)
         const double y1 = P[3] * x[0] + P[4] * x[1] + P[5] * x[2] + P[10];
         const double y2 = P[6] * x[0] + P[7] * x[1] + P[8] * x[2] + P[11];
         const uint2 nw = make_uint2(c0.z, c0.w);
+        // nearest mode (ties to the lower index); the rows of M(u) are taken
+        // four at a time across tree boundaries, and the best row stays in
+        // registers
+        int pre[kMaxTrees + 1];
+        pre[0] = 0;
+#pragma unroll
+        for (int t = 0; t < kMaxTrees; ++t) pre[t + 1] = pre[t] + (t < J.T ? (int)count_of(nw, t) : 0);
+        const int nm = pre[kMaxTrees];
         double best = INFINITY;
-        const float4* brow = nullptr;
-        for (int tr = 0; tr < J.T; ++tr) {
-            const int c = (int)count_of(nw, tr);
-            const float4* row = J.modes + ((((size_t)tr << J.D) + leaf_of(lw, tr)) * (size_t)J.M) * 4;
-            int m = 0;
-            for (; m + 4 <= c; m += 4) {           // four rows in flight, compared in order
-                double q[4];
+        bool found = false;
+        float4 ba = make_float4(0.f, 0.f, 0.f, 0.f), bb = ba, bc = ba;
+        for (int j0 = 0; j0 < nm; j0 += 4) {
+            float4 ra[4], rb[4], rc[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) q[u] = mode_q(row + 4 * (m + u), y0, y1, y2, cov);
+            for (int u = 0; u < 4; ++u) {
+                const int j = min(j0 + u, nm - 1);
+                int t = 0;
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const double qq = q[u] < 0.0 ? 0.0 : q[u];
-                    if (qq < best) {
-                        best = qq;
-                        brow = row + 4 * (m + u);
-                    }
+                for (int q = 1; q < kMaxTrees; ++q) t += j >= pre[q] ? 1 : 0;
+                int first = 0;
+#pragma unroll
+                for (int q = 1; q < kMaxTrees; ++q) first = t == q ? pre[q] : first;
+                const float4* row = J.modes + ((((size_t)t << J.D) + leaf_of(lw, t)) * (size_t)J.M + (size_t)(j - first)) * 4;
+                ra[u] = ldg(row);
+                if (COV) {
+                    rb[u] = ldg(row + 1);
+                    rc[u] = ldg(row + 2);
+                } else {
+                    rb[u] = rc[u] = ra[u];
                 }
             }
-            for (; m < c; ++m) {
-                double qq = mode_q(row + 4 * m, y0, y1, y2, cov);
-                if (qq < 0.0) qq = 0.0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (j0 + u >= nm) break;
+                double qq = row_q<COV>(ra[u], rb[u], rc[u], y0, y1, y2);
+                qq = qq < 0.0 ? 0.0 : qq;
                 if (qq < best) {
                     best = qq;
-                    brow = row + 4 * m;
+                    found = true;
+                    ba = ra[u];
+                    bb = rb[u];
+                    bc = rc[u];
                 }
             }
         }
         const double en = sqrt(best);
         v[0] += en;
-        if (brow == nullptr) continue;
-        const float4 a = ldg(brow);
-        const double r0 = y0 - (double)a.x, r1 = y1 - (double)a.y, r2 = y2 - (double)a.z;
+        if (!found) continue;
+        const double r0 = y0 - (double)ba.x, r1 = y1 - (double)ba.y, r2 = y2 - (double)ba.z;
         double A[9] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0};
-        if (cov) {
-            const float4 b = ldg(brow + 1), c = ldg(brow + 2);
-            A[0] = b.x; A[1] = b.y; A[2] = b.z;
-            A[3] = b.y; A[4] = b.w; A[5] = c.x;
-            A[6] = b.z; A[7] = c.x; A[8] = c.y;
+        if (COV) {
+            A[0] = bb.x; A[1] = bb.y; A[2] = bb.z;
+            A[3] = bb.y; A[4] = bb.w; A[5] = bc.x;
+            A[6] = bb.z; A[7] = bc.x; A[8] = bc.y;
         }
         const double Jm[18] = {0.0, y2, -y1, 1.0, 0.0, 0.0,
                                -y2, 0.0, y0, 0.0, 1.0, 0.0,
@@ -982,26 +1054,34 @@ __device__ void se3_exp(const double xi[6], double Rd[9], double td[3])
     for (int i = 0; i < 3; ++i) td[i] = V[3 * i] * xi[3] + V[3 * i + 1] * xi[4] + V[3 * i + 2] * xi[5];
 }
 
-// one thread per (survivor, job).  it = -1 follows the pass at the starting
+// one wave per (survivor, job): lanes 0..27 add one value each over the
+// tiles in order, lane 0 decides.  it = -1 follows the pass at the starting
 // pose; it >= 0 follows iteration it's candidate pass.  The last iteration
 // writes the refined pose (FP64, and rounded into the hypothesis table)
 // and the energy.
-__global__ __launch_bounds__(256) void k_lm_step(const Job* __restrict__ jobs, int round, int it)
+__global__ __launch_bounds__(64) void k_lm_step(const Job* __restrict__ jobs, int round, int it)
 {
 #pragma clang fp contract(off)
     const Job& J = jobs[blockIdx.y];
-    const int pos = blockIdx.x * 256 + threadIdx.x;
+    const int pos = blockIdx.x;
     if (!J.lm || J.st->done || pos >= J.st->n_surv || it >= J.lm_iters) return;
     const int slot = J.surv[pos];
     double* S = J.lm_state + (size_t)slot * kLmStateDoubles;
-    const int tiles = ((round + 1) * J.eta + kLmTile - 1) / kLmTile;
+    __shared__ double s_v[kLmVals];
+    const bool go = S[kLmGo] != 0.0;
+    if (go && threadIdx.x < kLmVals) {
+        const int tiles = ((round + 1) * J.eta + kLmTile - 1) / kLmTile;
+        const double* part = J.lm_part + (size_t)pos * J.lm_tiles * kLmVals + threadIdx.x;
+        double acc = 0.0;
+        for (int t = 0; t < tiles; ++t) acc += ldg(part + (size_t)t * kLmVals);
+        s_v[threadIdx.x] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
     double lambda = S[kLmLambda];
-    if (S[kLmGo] != 0.0) {
+    if (go) {
         double v[kLmVals];
-        for (int i = 0; i < kLmVals; ++i) v[i] = 0.0;
-        const double* part = J.lm_part + (size_t)pos * J.lm_tiles * kLmVals;
-        for (int t = 0; t < tiles; ++t)
-            for (int i = 0; i < kLmVals; ++i) v[i] += part[(size_t)t * kLmVals + i];
+        for (int i = 0; i < kLmVals; ++i) v[i] = s_v[i];
         if (it < 0 || v[0] < S[kLmE]) {
             S[kLmE] = v[0];
             for (int i = 0; i < 21; ++i) S[kLmN + i] = v[7 + i];
@@ -1432,17 +1512,19 @@ hipError_t launch_score(const Job* jobs, int njobs, int round, int nptiles, int 
 hipError_t launch_lm(const Job* jobs, int njobs, int round, int maxSurv, int maxEta, int maxIters, hipStream_t st)
 {
     if (maxSurv < 1) return hipSuccess;
-    const dim3 thr((maxSurv + 255) / 256, njobs);
+    const dim3 thr((maxSurv + 255) / 256, njobs), per_surv(maxSurv, njobs);
     k_lm_draw<<<dim3((2 * maxEta + 255) / 256, njobs), dim3(256), 0, st>>>(jobs, round);
     RL_CHECK_LAUNCH();
     k_lm_init<<<thr, dim3(256), 0, st>>>(jobs, round);
     RL_CHECK_LAUNCH();
-    const int tiles = ((round + 1) * maxEta + kLmTile - 1) / kLmTile;
-    const int waves = maxSurv * tiles;
+    k_lm_plan<<<dim3(1), dim3(1024), 0, st>>>(jobs, njobs, round);
+    RL_CHECK_LAUNCH();
+    const long long tiles = ((round + 1) * (long long)maxEta + kLmTile - 1) / kLmTile;
+    const int waves = (int)std::min<long long>((long long)maxSurv * tiles * njobs, 8192);
     for (int it = -1; it < maxIters; ++it) {
-        k_lm_pass<<<dim3(waves, njobs), dim3(64), 0, st>>>(jobs, round);
+        k_lm_pass<<<dim3(waves), dim3(64), 0, st>>>(jobs, njobs, round);
         RL_CHECK_LAUNCH();
-        k_lm_step<<<thr, dim3(256), 0, st>>>(jobs, round, it);
+        k_lm_step<<<per_surv, dim3(64), 0, st>>>(jobs, round, it);
         RL_CHECK_LAUNCH();
     }
     return hipSuccess;

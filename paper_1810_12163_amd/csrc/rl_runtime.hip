@@ -121,7 +121,7 @@ int score_tile(int) { return kScoreTile; }
 // Per-frame (relocalisation) scratch of one job slot.
 struct FrameLayout {
     size_t state, result, probe, leaves, nmt, nm, tile_count, eligible, ecold, erec, hyp_best, hyps, surv, E, partial,
-        partial_all, pose64, lm_state, lm_part, Ie,
+        partial_all, pose64, lm_state, lm_part, Ie, lm_plan,
         I, inl, trace_slots, trace_E, total;
     int ew;
     int lm_tiles;
@@ -159,6 +159,7 @@ FrameLayout frame_layout(int maxP, int N, int eta, int rounds, int TP, int rows_
     L.lm_state = c.take((size_t)N * kLmStateDoubles * 8);
     L.lm_part = c.take((size_t)N * L.lm_tiles * 28 * 8);
     L.Ie = c.take((size_t)rounds * eta * 4);
+    L.lm_plan = c.take((size_t)(kMaxBatchFrames + 1) * 4);
     const int ptiles = (eta + TP - 1) / TP;
     L.partial = c.take((size_t)ptiles * N * 8);
     L.partial_all = c.take((size_t)rounds * ptiles * kFastStride * 8);
@@ -523,6 +524,7 @@ static Job make_job(const rl_room* r, char* scr, const FrameLayout& FL, const rl
     J.lm_state = reinterpret_cast<double*>(scr + FL.lm_state);
     J.lm_part = reinterpret_cast<double*>(scr + FL.lm_part);
     J.Ie = reinterpret_cast<int*>(scr + FL.Ie);
+    J.lm_plan = reinterpret_cast<int*>(scr + FL.lm_plan);
     J.lm_tiles = FL.lm_tiles;
     J.partial = reinterpret_cast<double*>(scr + FL.partial);
     J.partial_all = reinterpret_cast<double*>(scr + FL.partial_all);
@@ -1122,7 +1124,7 @@ static int batch_rounds(const rl_batch_params& bp) { return bp.max_rounds; }
 RL_API rl_status rl_batch_workspace_bytes(const rl_batch_params* bp, size_t* bytes)
 {
     if (!bp || !bytes) return fail(RL_EINVAL, "NULL argument");
-    if (bp->max_frames < 1 || bp->max_frames > 4096) return fail(RL_EINVAL, "max_frames must be in 1..4096");
+    if (bp->max_frames < 1 || bp->max_frames > kMaxBatchFrames) return fail(RL_EINVAL, "max_frames must be in 1..%d", kMaxBatchFrames);
     if (bp->max_width < 8 || bp->max_height < 8 || bp->max_width % 4 || bp->max_height % 4)
         return fail(RL_EINVAL, "max frame size must be multiples of 4, at least 8x8");
     if ((long long)bp->max_width * bp->max_height >= kMaxPixels) return fail(RL_EINVAL, "max frame must have fewer than 2^24 pixels");
@@ -1254,6 +1256,7 @@ RL_API rl_status rl_batch_relocalise_async(rl_batch* b, const rl_request* reqs, 
         }
         J.TP = b->TP;
         J.fast_max = 64 * b->sched.fw;
+        J.lm_plan = reinterpret_cast<int*>(b->ws + b->slots[0].lm_plan);   // one plan per launch
         J.trace = 0;
         b->job_host[i] = J;
     }
