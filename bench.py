@@ -116,6 +116,8 @@ def main():
     ap.add_argument("--serve-rooms", type=int, default=16)
     ap.add_argument("--serve-leaves-per-frame", type=int, default=256,
                     help="mode update schedule of the served rooms: 0 exact, K leaves per adapted frame")
+    ap.add_argument("--cascade-frames", type=int, default=16,
+                    help="frames relocalised by the paper's Fast -> Intermediate -> Slow cascade (0 = skip)")
     ap.add_argument("--lm-steps", type=int, default=5,
                     help="steps of the batch with LM refinement (0 = skip that leg)")
     ap.add_argument("--schedule", default="auto",
@@ -277,6 +279,7 @@ def main():
     ok = [e[0] <= 0.05 and e[1] <= 5.0 for e in errs]
 
     lm = lm_leg(args, rl, room, batch, reqs, frames, w, qd, qc, use_graph) if args.lm_steps > 0 else None
+    cascade = cascade_leg(args, rl, w, dev, qd, qc) if args.cascade_frames > 0 else None
 
     # ---- rooflines -------------------------------------------------------------
     def roof_search(ms):
@@ -354,6 +357,7 @@ def main():
                         step_p99_ms=percentile(step_ms, 99), identical_to_plain=bool(same)),
         "served": served,
         "lm": lm,
+        "cascade": cascade,
         "accuracy": dict(frac_within_5cm_5deg=float(np.mean(ok)),
                          median_cm=float(np.median([e[0] for e in errs]) * 100),
                          median_deg=float(np.median([e[1] for e in errs]))),
@@ -429,6 +433,45 @@ def lm_leg(args, rl, room, batch, reqs, frames, w, qd, qc, use_graph):
         f"RANSAC stage {rms:.3f} ms, {out['roofline']['achieved']:.2f} TFLOP/s FP64, "
         f"within 5cm/5deg {out['frac_within_5cm_5deg']:.3f}, identical to plain {same}")
     return out
+
+
+def cascade_leg(args, rl, w, dev, qd, qc):
+    """The paper's cascade (Sec. 3.2.5): Fast -> Intermediate -> Slow with
+    Table 8's RANSAC settings on one shared forest, falling back when the
+    depth-raycast score (Eq. 6-7) of a stage's pose exceeds 5 cm, then
+    7.5 cm; the slow stage ranks its 16 outputs by that score (Eq. 8).
+    Frames one at a time: latency per frame, stage reached, accuracy."""
+    import torch
+
+    from paper_1810_12163_amd.cascade import Cascade, paper_stages
+    from rlsynth import scene
+    p = dict(w.params, max_pose_candidates=2048, max_pose_candidates_after_cull=64)
+    room = rl.Room(p, w.nodes, 640, 480, device=dev)
+    for f in w.adapt:
+        room.adapt(torch.from_numpy(f.depth).to(dev), torch.from_numpy(f.rgb).to(dev), f.K, f.pose)
+    room.update_modes()
+    cas = Cascade(room, paper_stages(), scene.surface_records(w.room), min_depth=scene.DEPTH_MIN,
+                  max_depth=scene.DEPTH_MAX)
+    for k in range(2):                                   # graph capture of each stage's shape
+        qi = k % len(w.queries)
+        cas.relocalise(qd[qi], qc[qi], w.queries[qi].K, request_seed=1000 + k)
+    torch.cuda.synchronize()
+    ms, stages, errs = [], [], []
+    for k in range(args.cascade_frames):
+        qi = k % len(w.queries)
+        out = cas.relocalise(qd[qi], qc[qi], w.queries[qi].K, request_seed=k)
+        ms.append(out["ms"])
+        stages.append(out["stage"])
+        errs.append(scene.pose_error(out["pose"].astype(np.float64), w.queries[qi].pose))
+    room.close()
+    res = dict(frames=len(ms), mean_ms=float(np.mean(ms)), p50_ms=percentile(ms, 50), p99_ms=percentile(ms, 99),
+               stage_counts={s.name: stages.count(s.name) for s in cas.stages},
+               frac_within_5cm_5deg=float(np.mean([e[0] <= 0.05 and e[1] <= 5.0 for e in errs])),
+               median_cm=float(np.median([e[0] for e in errs]) * 100),
+               thresholds_m=[s.threshold for s in cas.stages[:-1]])
+    log(f"[bench] cascade: {res['mean_ms']:.2f} ms per frame (p50 {res['p50_ms']:.2f}), stages {res['stage_counts']}, "
+        f"within 5cm/5deg {res['frac_within_5cm_5deg']:.3f}")
+    return res
 
 
 def serve_leg(args, rl, dev, inputs):

@@ -177,14 +177,22 @@ rl_status relocaliser_relocalise(rl_room* room, const rl_frame* frame, uint64_t 
                                  float cam_to_world_out[16], float* energy_out,
                                  float* mean_energy_out);
 
-/* Per-call RANSAC settings (0 = the room's own value).  n_hypotheses may not
- * exceed the room's max_pose_candidates, which sizes its scratch. */
+/* Per-call hypothesis-generation and RANSAC settings (the parameters of
+ * Table 8 that differ between the relocalisers of a cascade sharing one
+ * forest).  0 (or a negative value where stated) keeps the room's own value.
+ * n_hypotheses may not exceed the room's max_pose_candidates, nor eta the
+ * room's ransac_inliers_per_iteration, which size its scratch. */
 typedef struct {
     int32_t n_hypotheses;     /* N_max for this call                          */
     int32_t n_cull;           /* N_cull for this call                         */
     int32_t n_out;            /* maxRelocalisationsToOutput for this call     */
     int32_t final_refine;     /* -1 = room's value, 0 = off, 1 = on           */
     int32_t pose_update;      /* LM refinement: -1 = room's value, 0 = off, 1 = on */
+    int32_t max_iterations;   /* maxCandidateGenerationIterations             */
+    int32_t eta;              /* ransacInliersPerIteration                    */
+    int32_t use_covariance;   /* -1 = room's value, 0 = Euclidean, 1 = Mahalanobis */
+    float min_squared_distance;   /* minSquaredDistanceBetweenSampledModes; < 0 = room's */
+    float max_translation_error;  /* maxTranslationErrorForCorrectPose; < 0 = room's     */
 } rl_reloc_opts;
 
 /* Result record (also the device-side layout written by the batch path). */

@@ -78,7 +78,9 @@ class Result(ctypes.Structure):
 
 class RelocOpts(ctypes.Structure):
     _fields_ = [("n_hypotheses", ctypes.c_int32), ("n_cull", ctypes.c_int32), ("n_out", ctypes.c_int32),
-                ("final_refine", ctypes.c_int32), ("pose_update", ctypes.c_int32)]
+                ("final_refine", ctypes.c_int32), ("pose_update", ctypes.c_int32),
+                ("max_iterations", ctypes.c_int32), ("eta", ctypes.c_int32), ("use_covariance", ctypes.c_int32),
+                ("min_squared_distance", ctypes.c_float), ("max_translation_error", ctypes.c_float)]
 
 
 class Request(ctypes.Structure):
@@ -282,12 +284,16 @@ class Room:
         self.schedule = (int(ipt), int(fast_waves))
 
     def relocalise(self, depth, rgb, K, request_seed: int = 0, n_hypotheses: int = 0, n_cull: int = 0,
-                   n_out: int = 0, final_refine: int = -1, pose_update: int = -1) -> dict:
-        """One frame; the optional RANSAC settings override the room's for this call."""
+                   n_out: int = 0, final_refine: int = -1, pose_update: int = -1, max_iterations: int = 0,
+                   eta: int = 0, use_covariance: int = -1, min_squared_distance: float = -1.0,
+                   max_translation_error: float = -1.0) -> dict:
+        """One frame; the optional hypothesis and RANSAC settings override the room's for this call."""
         f = _frame(depth, rgb, K)
         r = Result()
         self._follow(depth, rgb)
-        opts = RelocOpts(int(n_hypotheses), int(n_cull), int(n_out), int(final_refine), int(pose_update))
+        opts = RelocOpts(int(n_hypotheses), int(n_cull), int(n_out), int(final_refine), int(pose_update),
+                         int(max_iterations), int(eta), int(use_covariance), float(min_squared_distance),
+                         float(max_translation_error))
         _check(lib().relocaliser_relocalise_opts(self.handle, ctypes.byref(f), int(request_seed),
                                                  ctypes.byref(opts), ctypes.byref(r)), allow=(RL_OK, RL_NO_POSE))
         return _result(r)

@@ -25,12 +25,43 @@ import numpy as np
 
 @dataclasses.dataclass
 class Stage:
+    """One relocaliser of the cascade: its hypothesis and RANSAC settings
+    (Table 8's RANSAC rows; 0 or negative = the room's own value)."""
     name: str
     n_hypotheses: int
     n_out: int = 1
     decimate: bool = False        # run on the 2x decimated frame
     final_refine: int = -1
     threshold: float = float("inf")   # fall back when the stage score exceeds it
+    n_cull: int = 0               # 0: no initial cull (N_cull = n_hypotheses)
+    pose_update: int = -1
+    max_iterations: int = 0
+    eta: int = 0
+    use_covariance: int = -1
+    min_squared_distance: float = -1.0
+    max_translation_error: float = -1.0
+
+    def call_settings(self) -> dict:
+        return dict(n_hypotheses=self.n_hypotheses, n_cull=self.n_cull or self.n_hypotheses, n_out=self.n_out,
+                    final_refine=self.final_refine, pose_update=self.pose_update,
+                    max_iterations=self.max_iterations, eta=self.eta, use_covariance=self.use_covariance,
+                    min_squared_distance=self.min_squared_distance,
+                    max_translation_error=self.max_translation_error)
+
+
+def paper_stages(thresholds=(0.05, 0.075)) -> list:
+    """The Fast -> Intermediate -> Slow cascade with Table 8's RANSAC settings
+    and the tuned depth-difference thresholds (5 cm, then 7.5 cm).  The
+    covariance is not used for Intermediate and Slow (Table 8); for Fast the
+    table gives none, so the room's setting is kept."""
+    return [
+        Stage("fast", 2048, n_cull=64, n_out=1, max_iterations=500, eta=256, pose_update=0,
+              min_squared_distance=0.0, max_translation_error=0.05, threshold=thresholds[0]),
+        Stage("intermediate", 2048, n_cull=64, n_out=1, max_iterations=1000, eta=256, pose_update=1,
+              use_covariance=0, min_squared_distance=0.09, max_translation_error=0.1, threshold=thresholds[1]),
+        Stage("slow", 2048, n_cull=64, n_out=16, max_iterations=250, eta=256, pose_update=1, use_covariance=0,
+              min_squared_distance=0.0225, max_translation_error=0.1),
+    ]
 
 
 def decimate(depth, rgb, K):
@@ -66,8 +97,7 @@ class Cascade:
         for si, st in enumerate(self.stages):
             d, c, Kk = decimate(depth, rgb, K) if st.decimate else (depth, rgb, K)
             seed = request_seed * 8 + si
-            res = self.room.relocalise(d, c, Kk, request_seed=seed, n_hypotheses=st.n_hypotheses,
-                                       n_cull=st.n_hypotheses, n_out=st.n_out, final_refine=st.final_refine)
+            res = self.room.relocalise(d, c, Kk, request_seed=seed, **st.call_settings())
             last = si == len(self.stages) - 1
             if res["status"] != "ok":
                 trail.append((st.name, float("inf")))

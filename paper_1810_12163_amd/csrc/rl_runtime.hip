@@ -954,6 +954,17 @@ RL_API rl_status relocaliser_relocalise_opts(rl_room* r, const rl_frame* f, uint
     const int n_out = opts && opts->n_out > 0 ? opts->n_out : r->p.max_relocalisations_to_output;
     const int refine = opts && opts->final_refine >= 0 ? (opts->final_refine ? 1 : 0) : r->p.final_refine;
     const int lm = opts && opts->pose_update >= 0 ? (opts->pose_update ? 1 : 0) : r->p.pose_update;
+    const int iters = opts && opts->max_iterations > 0 ? opts->max_iterations : r->p.max_candidate_generation_iterations;
+    const int eta = opts && opts->eta > 0 ? opts->eta : r->eta;
+    const int cov = opts && opts->use_covariance >= 0 ? (opts->use_covariance ? 1 : 0) : r->p.use_prediction_covariance;
+    if (opts && (!finite_f(opts->min_squared_distance) || !finite_f(opts->max_translation_error)))
+        return fail(RL_EINVAL, "non-finite per-call threshold");
+    const double min_sq = opts && opts->min_squared_distance >= 0.0f ? opts->min_squared_distance
+                                                                     : r->p.min_squared_distance_between_sampled_modes;
+    const double rig = opts && opts->max_translation_error >= 0.0f ? opts->max_translation_error
+                                                                   : r->p.max_translation_error_for_correct_pose;
+    if (eta > r->eta) return fail(RL_EINVAL, "eta %d exceeds the room's %d", eta, r->eta);
+    if (iters >= (1 << 30)) return fail(RL_EINVAL, "max_iterations must be below 2^30");
     if (N > r->N) return fail(RL_EINVAL, "%d hypotheses exceed the room's maximum %d", N, r->N);
     std::vector<int> entering;
     const int R = rounds_for(N, n_cull, n_out, &entering);
@@ -965,17 +976,22 @@ RL_API rl_status relocaliser_relocalise_opts(rl_room* r, const rl_frame* f, uint
     J.n_out = n_out;
     J.final_refine = refine;
     J.lm = lm;
+    J.I_max = iters;
+    J.eta = eta;
+    J.use_cov = cov;
+    J.min_sq_dist = min_sq;
+    J.theta_rig = rig;
     *r->job_host = J;
     Job* jd = reinterpret_cast<Job*>(r->scr + r->job_off);
     hipError_t e = hipMemcpyAsync(jd, r->job_host, sizeof(Job), hipMemcpyHostToDevice, r->stream);
     if (e != hipSuccess) return hip_fail(e, "job upload");
-    const int nptiles = (r->eta + r->TP - 1) / r->TP;
+    const int nptiles = (eta + r->TP - 1) / r->TP;
     const int P = f->width * f->height;
-    std::vector<long long> key = {P, N, r->sched.ipt, r->sched.fw, lm, r->p.lm_iterations};
+    std::vector<long long> key = {P, N, r->sched.ipt, r->sched.fw, lm, r->p.lm_iterations, iters, eta};
     for (int v : entering) key.push_back(v);
     e = run_sequence(r->graphs, key, r->timer.kernel == RL_TIMER_NONE, r->stream, [&]() {
-        return launch_sequence(jd, 1, P, N, r->p.max_candidate_generation_iterations, r->T, entering,
-                               nptiles, r->eta, lm != 0, r->p.lm_iterations, r->sched, r->timer, r->stream);
+        return launch_sequence(jd, 1, P, N, iters, r->T, entering, nptiles, eta, lm != 0, r->p.lm_iterations,
+                               r->sched, r->timer, r->stream);
     });
     if (e != hipSuccess) return hip_fail(e, "relocalise launch");
     e = hipMemcpyAsync(r->res_host, r->scr + r->FL.result, sizeof(rl_result), hipMemcpyDeviceToHost, r->stream);

@@ -133,6 +133,18 @@ def make_room(seed: int, n_quads: int = 6) -> Room:
     return Room(seed=seed, surfaces=surfaces)
 
 
+def surface_records(room: Room) -> np.ndarray:
+    """The room's geometry as the library's analytic scene model: 16 float32
+    per surface (point, unit normal, in-plane axes, half-extents; 0 for the
+    infinite walls), the layout of rl_surface."""
+    out = np.zeros((len(room.surfaces), 16), dtype=np.float32)
+    for i, s in enumerate(room.surfaces):
+        out[i, 0:3], out[i, 3:6], out[i, 6:9], out[i, 9:12] = s.p0, s.n, s.e1, s.e2
+        if s.half is not None:
+            out[i, 12:14] = s.half
+    return out
+
+
 def intrinsics(w: int, h: int):
     """fx = fy = 585 * w / 640, principal point at the image centre."""
     f = 585.0 * w / 640.0

@@ -268,6 +268,36 @@ def test_depth_scores_match_oracle(c2):
         room.depth_scores(d, c, q.K, S, P, -1.0, 4.0)
 
 
+def test_paper_stage_settings_match_oracle(c2, c3_room):
+    """Each relocaliser of the paper's cascade (Table 8's RANSAC settings:
+    2048 hypotheses, cull to 64, eta 256, per-stage iterations, thresholds,
+    covariance and LM), run on the shared forest through per-call settings,
+    equals the oracle run with the same settings."""
+    from paper_1810_12163_amd.cascade import paper_stages
+    w, o, _ = c2
+    p3, r3 = c3_room
+    q = w.queries[1]
+    d, c = dev(q)
+    for i, st in enumerate(paper_stages()):
+        cs = st.call_settings()
+        res = r3.relocalise(d, c, q.K, request_seed=60 + i, **cs)
+        params = dict(p3, max_pose_candidates=cs["n_hypotheses"], max_pose_candidates_after_cull=cs["n_cull"],
+                      max_relocalisations_to_output=cs["n_out"], pose_update=cs["pose_update"],
+                      max_candidate_generation_iterations=cs["max_iterations"],
+                      ransac_inliers_per_iteration=cs["eta"],
+                      min_squared_distance_between_sampled_modes=float(np.float32(cs["min_squared_distance"])),
+                      max_translation_error_for_correct_pose=float(np.float32(cs["max_translation_error"])))
+        if cs["use_covariance"] >= 0:
+            params["use_prediction_covariance"] = cs["use_covariance"]
+        ref = _stage_ref(r3, q, params, 60 + i, o.T, o.D, o.M, w.nodes, p3["ref_width"])
+        print(f"[paper stage {st.name}] valid {res['n_valid']} (oracle {int(ref['hyp_valid'].sum())}), "
+              f"rounds {res['rounds']}, winner {res['winner']} (oracle {ref['winner']})", flush=True)
+        assert res["n_valid"] == int(ref["hyp_valid"].sum()) > 0
+        assert res["rounds"] == ref["rounds"] and res["winner"] == ref["winner"]
+        assert pose_diff(res["pose"], ref["pose"]) < 1e-5
+        assert abs(res["energy"] - ref["energy"]) <= 1e-4 * abs(ref["energy"])
+
+
 def test_cascade_fallback_and_ranking(c2, c3_room):
     from paper_1810_12163_amd.cascade import Cascade, Stage
     w, o, _ = c2
