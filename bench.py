@@ -116,6 +116,9 @@ def main():
     ap.add_argument("--serve-rooms", type=int, default=16)
     ap.add_argument("--serve-leaves-per-frame", type=int, default=256,
                     help="mode update schedule of the served rooms: 0 exact, K leaves per adapted frame")
+    ap.add_argument("--robustness", action="store_true",
+                    help="also run the missing-depth and depth-noise sweeps (Default RANSAC settings)")
+    ap.add_argument("--robustness-queries", type=int, default=32)
     ap.add_argument("--cascade-frames", type=int, default=16,
                     help="frames relocalised by the paper's Fast -> Intermediate -> Slow cascade (0 = skip)")
     ap.add_argument("--lm-steps", type=int, default=5,
@@ -280,6 +283,7 @@ def main():
 
     lm = lm_leg(args, rl, room, batch, reqs, frames, w, qd, qc, use_graph) if args.lm_steps > 0 else None
     cascade = cascade_leg(args, rl, w, dev, qd, qc) if args.cascade_frames > 0 else None
+    robustness = robustness_leg(args, rl, dev) if args.robustness else None
 
     # ---- rooflines -------------------------------------------------------------
     def roof_search(ms):
@@ -358,6 +362,7 @@ def main():
         "served": served,
         "lm": lm,
         "cascade": cascade,
+        "robustness": robustness,
         "accuracy": dict(frac_within_5cm_5deg=float(np.mean(ok)),
                          median_cm=float(np.median([e[0] for e in errs]) * 100),
                          median_deg=float(np.median([e[1] for e in errs]))),
@@ -472,6 +477,43 @@ def cascade_leg(args, rl, w, dev, qd, qc):
     log(f"[bench] cascade: {res['mean_ms']:.2f} ms per frame (p50 {res['p50_ms']:.2f}), stages {res['stage_counts']}, "
         f"within 5cm/5deg {res['frac_within_5cm_5deg']:.3f}")
     return res
+
+
+def robustness_leg(args, rl, dev):
+    """The paper's robustness protocols on the 640x480 workload: every
+    adaptation and query frame re-rendered with a fraction p of the depth
+    pixels zeroed (r <= p, r ~ U[0,1]), or with depth-dependent noise
+    d + n d, n ~ N(0, sigma^2); relocalised with the Default relocaliser's
+    RANSAC settings (1024 hypotheses, cull to 64, eta 512, LM with the
+    covariance, one output).  Fraction of queries within 5 cm / 5 deg."""
+    import torch
+
+    from rlsynth import scene, workloads
+    levels = [("missing", p) for p in (0.1, 0.3, 0.5, 0.7, 0.9, 0.95)] + \
+             [("noise", s) for s in (0.0, 0.025, 0.05, 0.075, 0.1)]
+    out = {}
+    for kind, v in levels:
+        t0 = time.time()
+        kw = dict(dropout=v) if kind == "missing" else dict(depth_rel_sigma=v)
+        w = workloads.c2_corrupted(0, n_adapt=50, n_queries=args.robustness_queries, processes=16, **kw)
+        room = rl.Room(dict(w.params, max_pose_candidates_after_cull=64, ransac_inliers_per_iteration=512),
+                       w.nodes, 640, 480, device=dev)
+        for f in w.adapt:
+            room.adapt(torch.from_numpy(f.depth).to(dev), torch.from_numpy(f.rgb).to(dev), f.K, f.pose)
+        room.update_modes()
+        errs = []
+        for k, q in enumerate(w.queries):
+            r = room.relocalise(torch.from_numpy(q.depth).to(dev), torch.from_numpy(q.rgb).to(dev), q.K,
+                                request_seed=k, pose_update=1, final_refine=0)
+            errs.append(scene.pose_error(r["pose"].astype(np.float64), q.pose) if r["status"] == "ok"
+                        else (np.inf, np.inf))
+        room.close()
+        key = f"{kind}_{v:g}"
+        out[key] = dict(frac_within_5cm_5deg=float(np.mean([e[0] <= 0.05 and e[1] <= 5.0 for e in errs])),
+                        median_cm=float(np.median([e[0] for e in errs]) * 100), queries=len(errs))
+        log(f"[bench] robustness {key}: within 5cm/5deg {out[key]['frac_within_5cm_5deg']:.3f}, "
+            f"median {out[key]['median_cm']:.1f} cm ({time.time() - t0:.1f} s)")
+    return out
 
 
 def serve_leg(args, rl, dev, inputs):

@@ -83,11 +83,15 @@ def c1(room_id: int = 0, n_queries: int = 1) -> Workload:
     return Workload("c1", params, room, nodes, adapt, queries)
 
 
+def adapt_poses_for(room, room_id: int, n_adapt: int):
+    rng = np.random.default_rng(frame_seed(room_id, 8, 0))
+    return [_scene.random_pose(room, rng) for _ in range(n_adapt)]
+
+
 def room_setup(room_id: int, n_adapt: int, w: int = 640, h: int = 480, forest_cfg: str = "c2"):
     room = _scene.make_room(room_id)
     nodes = _forest.make_forest(1000 + room_id, **_presets.FOREST[forest_cfg])
-    rng = np.random.default_rng(frame_seed(room_id, 8, 0))
-    poses = [_scene.random_pose(room, rng) for _ in range(n_adapt)]
+    poses = adapt_poses_for(room, room_id, n_adapt)
     adapt = [_frame(room, p, w, h, frame_seed(room_id, 0, i)) for i, p in enumerate(poses)]
     return room, nodes, adapt
 
@@ -96,6 +100,11 @@ def queries_for(room, adapt_poses, n, w=640, h=480, room_id=0, novel_fraction=0.
     """Query frames near random adaptation poses; a ``novel_fraction`` of them
     are instead drawn >= 50 cm or >= 50 degrees away from every adaptation
     pose (the paper's hardest novelty bin)."""
+    poses = query_poses(room, adapt_poses, n, room_id, novel_fraction, start)
+    return [_frame(room, p, w, h, frame_seed(room_id, 1, start + q)) for q, p in enumerate(poses)]
+
+
+def query_poses(room, adapt_poses, n, room_id=0, novel_fraction=0.0, start=0):
     rng = np.random.default_rng(frame_seed(room_id, 7, start))
     out = []
     for q in range(n):
@@ -109,7 +118,7 @@ def queries_for(room, adapt_poses, n, w=640, h=480, room_id=0, novel_fraction=0.
         else:
             base = adapt_poses[int(rng.integers(len(adapt_poses)))]
             p = _scene.near_pose(room, base, rng, 0.20, 20.0)
-        out.append(_frame(room, p, w, h, frame_seed(room_id, 1, start + q)))
+        out.append(p)
     return out
 
 
@@ -120,16 +129,34 @@ def c2(room_id: int = 0, n_adapt: int = 50, n_queries: int = 8) -> Workload:
     return Workload("c2", params, room, nodes, adapt, queries)
 
 
+def c2_corrupted(room_id: int = 0, n_adapt: int = 50, n_queries: int = 16, dropout: float = 0.05,
+                 depth_rel_sigma: float = 0.0, processes: int = 0) -> Workload:
+    """The 640x480 workload (same room, forest, poses and noise seeds) with
+    every adaptation and query frame rendered under the paper's robustness
+    protocols: each pixel's depth zeroed iff r <= dropout, r ~ U[0, 1], and
+    depth d replaced by d + n d, n ~ N(0, depth_rel_sigma^2)."""
+    room = _scene.make_room(room_id)
+    nodes = _forest.make_forest(1000 + room_id, **_presets.FOREST["c2"])
+    ap = adapt_poses_for(room, room_id, n_adapt)
+    qp = query_poses(room, ap, n_queries, room_id)
+    kw = dict(dropout=dropout, depth_rel_sigma=depth_rel_sigma)
+    jobs = [(room_id, p, 640, 480, frame_seed(room_id, 0, i), kw) for i, p in enumerate(ap)]
+    jobs += [(room_id, p, 640, 480, frame_seed(room_id, 1, q), kw) for q, p in enumerate(qp)]
+    frames = render_many(jobs, processes)
+    return Workload("c2", _presets.preset("c2"), room, nodes, frames[:n_adapt], frames[n_adapt:])
+
+
 # --- parallel rendering (several rooms / many frames) ----------------------
 
 def _render_job(job):
-    room_id, pose, w, h, seed = job
+    room_id, pose, w, h, seed = job[:5]
+    kw = job[5] if len(job) > 5 else {}
     room = _scene.make_room(room_id)
-    return _frame(room, pose, w, h, seed)
+    return _frame(room, pose, w, h, seed, **kw)
 
 
 def render_many(jobs, processes=None):
-    """Renders (room_id, pose, w, h, seed) jobs, in worker processes when
+    """Renders (room_id, pose, w, h, seed[, render keywords]) jobs, in worker processes when
     processes > 1.  Results are identical to rendering them one by one.
     Workers are spawned (fresh interpreters), never forked: a forked copy of a
     process that has initialised the GPU runtime is not safe."""
