@@ -37,7 +37,8 @@ __global__ __launch_bounds__(256) void k_ad_items(AdaptArgs a)
     }
     int leaf[T];
     const PlanarProbe pr{a.depth, a.rgb, a.w};
-    route<T>(a.nodes, a.L - 1, a.D, pr, a.w, a.h, x, y, d, a.s, leaf);
+    if (a.s == 1.0f) route<T, true>(a.nodes, a.L - 1, a.D, pr, a.w, a.h, x, y, d, a.s, leaf);
+    else route<T, false>(a.nodes, a.L - 1, a.D, pr, a.w, a.h, x, y, d, a.s, leaf);
     double xc[3];
     backproject(d, x, y, a.fx, a.fy, a.cx, a.cy, xc);
     float xw[3];

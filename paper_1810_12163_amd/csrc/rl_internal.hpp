@@ -244,7 +244,8 @@ struct PlanarProbe {
     const float* depth;
     const uint8_t* rgb;
     int w;
-    __device__ __forceinline__ void centre(int pc, float cc[3]) const
+    typedef float Centre[3];
+    __device__ __forceinline__ void centre(int pc, Centre cc) const
     {
         cc[0] = (float)ldg(rgb + 3 * pc);
         cc[1] = (float)ldg(rgb + 3 * pc + 1);
@@ -255,57 +256,70 @@ struct PlanarProbe {
     {
         return make_float2(ldg(depth + q), (float)ldg(rgb + 3 * q + c));
     }
-    __device__ __forceinline__ void decode(Word v, uint32_t, float& dq, float& cq) const
+    // the split feature: depth kind D(p) - D(q); colour kind C(p,c) - C(q,c)
+    __device__ __forceinline__ float feature(Word v, bool is_depth, uint32_t c, float d, const Centre cc) const
     {
-        dq = v.x;
-        cq = v.y;
+        const float fc = (c == 0u ? cc[0] : c == 1u ? cc[1] : cc[2]) - v.y;
+        return is_depth ? d - v.x : fc;
     }
 };
 
 struct PackedProbe {
     const uint2* img;
-    __device__ __forceinline__ void centre(int pc, float cc[3]) const
-    {
-        const uint2 v = ldg(img + pc);
-        cc[0] = (float)(v.y & 0xFFu);
-        cc[1] = (float)((v.y >> 8) & 0xFFu);
-        cc[2] = (float)((v.y >> 16) & 0xFFu);
-    }
+    typedef uint32_t Centre[1];
+    __device__ __forceinline__ void centre(int pc, Centre cw) const { cw[0] = ldg(img + pc).y; }
     typedef uint2 Word;
-    __device__ __forceinline__ Word load(int q, uint32_t) const { return ldg(img + q); }
-    __device__ __forceinline__ void decode(Word v, uint32_t c, float& dq, float& cq) const
+    // 32-bit byte offset from the image base (below 2^27 bytes)
+    __device__ __forceinline__ Word load(int q, uint32_t) const
     {
-        dq = __uint_as_float(v.x);
-        cq = (float)((v.y >> (8 * c)) & 0xFFu);
+        return ldg(reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(img) + (uint32_t)q * 8u));
+    }
+    // colour bytes are subtracted as integers: the difference of two bytes
+    // converts to the same float as the difference of their conversions
+    __device__ __forceinline__ float feature(Word v, bool is_depth, uint32_t c, float d, const Centre cw) const
+    {
+        const int ci = (int)__builtin_amdgcn_ubfe(cw[0], 8u * c, 8u);
+        const int qi = (int)__builtin_amdgcn_ubfe(v.y, 8u * c, 8u);
+        const float fc = (float)(ci - qi);
+        const float fd = d - __uint_as_float(v.x);
+        // both features are computed; a bit select picks one without a branch
+        const uint32_t m = is_depth ? 0xFFFFFFFFu : 0u;
+        return __uint_as_float((__float_as_uint(fd) & m) | (__float_as_uint(fc) & ~m));
     }
 };
 
-template <int T, class Probe>
+// route: T trees in lockstep, as described above.  UNIT: the frame is at
+// the forest's reference width (s = 1), so
+// the offsets need no scaling (a product with 1.0f is exact).  The offset
+// is clamped in float to the image's span around the pixel, which lands on
+// the same probe as clamping the probe coordinate.
+template <int T, bool UNIT, class Probe>
 __device__ __forceinline__ void route(const float4* __restrict__ nodes, int NT, int D, const Probe& pr, int w,
                                       int h, int x, int y, float d, float s, int leaf[T])
 {
     const float inv = 1.0f / d;
-    float cc[3];
-    pr.centre(y * w + x, cc);
+    typename Probe::Centre cen;
+    pr.centre(y * w + x, cen);
+    const float lox = (float)(-x), hix = (float)(w - 1 - x), loy = (float)(-y), hiy = (float)(h - 1 - y);
     int idx[T];
 #pragma unroll
     for (int t = 0; t < T; ++t) idx[t] = 0;
     for (int lvl = 0; lvl < D; ++lvl) {
         float4 nd[T];
 #pragma unroll
-        for (int t = 0; t < T; ++t) nd[t] = ldg(nodes + t * NT + idx[t]);
+        for (int t = 0; t < T; ++t)       // 32-bit byte offsets (the forest is below 2^23 bytes)
+            nd[t] = ldg(reinterpret_cast<const float4*>(reinterpret_cast<const char*>(nodes) +
+                                                        (uint32_t)(t * NT + idx[t]) * 16u));
         // every tree's probe is issued before any is used
         typename Probe::Word pv[T];
         uint32_t ch[T];
 #pragma unroll
         for (int t = 0; t < T; ++t) {
-            float fox = rintf((nd[t].x * s) * inv);
-            float foy = rintf((nd[t].y * s) * inv);
-            fox = fminf(fmaxf(fox, -1048576.0f), 1048576.0f);
-            foy = fminf(fmaxf(foy, -1048576.0f), 1048576.0f);
-            const int qx = min(max(x + (int)fox, 0), w - 1);
-            const int qy = min(max(y + (int)foy, 0), h - 1);
-            const int q = (int)__umul24((uint32_t)qy, (uint32_t)w) + qx;    // w * h < 2^24
+            float fox = rintf((UNIT ? nd[t].x : nd[t].x * s) * inv);
+            float foy = rintf((UNIT ? nd[t].y : nd[t].y * s) * inv);
+            fox = fminf(fmaxf(fox, lox), hix);
+            foy = fminf(fmaxf(foy, loy), hiy);
+            const int q = (int)__umul24((uint32_t)(y + (int)foy), (uint32_t)w) + x + (int)fox;   // w * h < 2^24
             // kinds are validated at creation (<= 3); the clamp keeps the
             // colour read inside the pixel whatever the device memory holds
             ch[t] = min(__float_as_uint(nd[t].w) - 1u, 2u);
@@ -313,11 +327,7 @@ __device__ __forceinline__ void route(const float4* __restrict__ nodes, int NT, 
         }
 #pragma unroll
         for (int t = 0; t < T; ++t) {
-            float dq, cq;
-            pr.decode(pv[t], ch[t], dq, cq);
-            const uint32_t c = ch[t];
-            const float fc = (c == 0u ? cc[0] : c == 1u ? cc[1] : cc[2]) - cq;
-            const float f = __float_as_uint(nd[t].w) == 0u ? d - dq : fc;
+            const float f = pr.feature(pv[t], __float_as_uint(nd[t].w) == 0u, ch[t], d, cen);
             idx[t] = 2 * idx[t] + 1 + (f >= nd[t].z ? 1 : 0);
         }
     }

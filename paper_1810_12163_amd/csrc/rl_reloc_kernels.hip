@@ -98,7 +98,8 @@ __global__ __launch_bounds__(256) void k_traverse(const Job* __restrict__ jobs)
             const int NT = (1 << J.D) - 1;
             int leaf[T];
             const PackedProbe pr{J.probe};
-            route<T>(J.nodes, NT, J.D, pr, w, h, x, y, d, J.s, leaf);
+            if (J.s == 1.0f) route<T, true>(J.nodes, NT, J.D, pr, w, h, x, y, d, J.s, leaf);
+            else route<T, false>(J.nodes, NT, J.D, pr, w, h, x, y, d, J.s, leaf);
 #pragma unroll
             for (int t = 0; t < T; ++t) {
                 lf[t] = (uint16_t)leaf[t];
