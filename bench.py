@@ -141,10 +141,11 @@ def main():
     # every CPU-side input is generated before the GPU runtime is initialised
     t_setup = time.time()
     log(f"[bench] rendering {args.adapt_frames} adaptation frames and {args.queries} queries (640x480)")
-    w = workloads.c2(n_adapt=args.adapt_frames, n_queries=args.queries)
+    procs = max(1, min(16, os.cpu_count() or 1))
+    # the standard 640x480 workload, rendered in worker processes
+    w = workloads.c2_corrupted(0, n_adapt=args.adapt_frames, n_queries=args.queries, processes=procs)
     serve_inputs = None
     if args.serve_seconds > 0:
-        procs = max(1, min(16, os.cpu_count() or 1))
         serve_inputs = workloads.serving_setup(n_rooms=args.serve_rooms, n_adapt=20, n_cameras=32,
                                                frames_per_camera=4, processes=procs)
     log(f"[bench] inputs ready ({time.time() - t_setup:.1f} s)")

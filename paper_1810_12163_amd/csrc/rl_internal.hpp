@@ -34,6 +34,13 @@ constexpr int kMaxBatchFrames = 4096;
 
 constexpr int kMaxFastWaves = 4;
 
+// levels of every tree the traversal reads from LDS (T x (2^levels - 1)
+// node records per block)
+#ifndef RL_TOP_LEVELS
+#define RL_TOP_LEVELS 6
+#endif
+constexpr int kTopLevels = RL_TOP_LEVELS;
+
 // LM refinement: pixels per pass wave, doubles of per-slot state
 constexpr int kLmTile = 128;
 constexpr int kLmStateDoubles = 56;
@@ -289,13 +296,16 @@ struct PackedProbe {
 };
 
 // route: T trees in lockstep, as described above.  UNIT: the frame is at
-// the forest's reference width (s = 1), so
-// the offsets need no scaling (a product with 1.0f is exact).  The offset
-// is clamped in float to the image's span around the pixel, which lands on
-// the same probe as clamping the probe coordinate.
+// the forest's reference width (s = 1), so the offsets need no scaling (a
+// product with 1.0f is exact).  The offset is clamped in float to the
+// image's span around the pixel, which lands on the same probe as clamping
+// the probe coordinate.  The first ktop levels may be read from a copy of
+// the trees' top nodes (top: T x (2^ktop - 1) records, e.g. in LDS; ktop = 0
+// reads every level from nodes).
 template <int T, bool UNIT, class Probe>
 __device__ __forceinline__ void route(const float4* __restrict__ nodes, int NT, int D, const Probe& pr, int w,
-                                      int h, int x, int y, float d, float s, int leaf[T])
+                                      int h, int x, int y, float d, float s, int leaf[T],
+                                      const float4* top = nullptr, int ktop = 0)
 {
     const float inv = 1.0f / d;
     typename Probe::Centre cen;
@@ -306,10 +316,16 @@ __device__ __forceinline__ void route(const float4* __restrict__ nodes, int NT, 
     for (int t = 0; t < T; ++t) idx[t] = 0;
     for (int lvl = 0; lvl < D; ++lvl) {
         float4 nd[T];
+        if (lvl < ktop) {
+            const int ntop = (1 << ktop) - 1;
 #pragma unroll
-        for (int t = 0; t < T; ++t)       // 32-bit byte offsets (the forest is below 2^23 bytes)
-            nd[t] = ldg(reinterpret_cast<const float4*>(reinterpret_cast<const char*>(nodes) +
-                                                        (uint32_t)(t * NT + idx[t]) * 16u));
+            for (int t = 0; t < T; ++t) nd[t] = top[t * ntop + idx[t]];
+        } else {
+#pragma unroll
+            for (int t = 0; t < T; ++t)   // 32-bit byte offsets (the forest is below 2^23 bytes)
+                nd[t] = ldg(reinterpret_cast<const float4*>(reinterpret_cast<const char*>(nodes) +
+                                                            (uint32_t)(t * NT + idx[t]) * 16u));
+        }
         // every tree's probe is issued before any is used
         typename Probe::Word pv[T];
         uint32_t ch[T];

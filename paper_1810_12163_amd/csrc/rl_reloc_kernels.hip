@@ -81,6 +81,14 @@ __global__ __launch_bounds__(256) void k_traverse(const Job* __restrict__ jobs)
     const int w = J.w, h = J.h, P = w * h;
     if ((int)blockIdx.x * 256 >= P) return;
     __shared__ int s_wave[4];
+    // the top levels of every tree, shared by the block's pixels
+    __shared__ float4 s_top[T * ((1 << kTopLevels) - 1)];
+    const int ktop = min(J.D, kTopLevels), ntop = (1 << ktop) - 1;
+    for (int i = threadIdx.x; i < T * ntop; i += 256) {
+        const int t = i / ntop;
+        s_top[i] = ldg(J.nodes + t * ((1 << J.D) - 1) + (i - t * ntop));
+    }
+    __syncthreads();
     const int p = blockIdx.x * 256 + threadIdx.x;
     bool elig = false;
     if (p < P) {
@@ -98,8 +106,8 @@ __global__ __launch_bounds__(256) void k_traverse(const Job* __restrict__ jobs)
             const int NT = (1 << J.D) - 1;
             int leaf[T];
             const PackedProbe pr{J.probe};
-            if (J.s == 1.0f) route<T, true>(J.nodes, NT, J.D, pr, w, h, x, y, d, J.s, leaf);
-            else route<T, false>(J.nodes, NT, J.D, pr, w, h, x, y, d, J.s, leaf);
+            if (J.s == 1.0f) route<T, true>(J.nodes, NT, J.D, pr, w, h, x, y, d, J.s, leaf, s_top, ktop);
+            else route<T, false>(J.nodes, NT, J.D, pr, w, h, x, y, d, J.s, leaf, s_top, ktop);
 #pragma unroll
             for (int t = 0; t < T; ++t) {
                 lf[t] = (uint16_t)leaf[t];
