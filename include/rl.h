@@ -287,8 +287,9 @@ enum {
     RL_BUF_SURVIVORS = 12, /* int32[N] current survivor slots, best first           scratch    */
     RL_BUF_ENERGY = 13,    /* double[N] energy per slot                             scratch    */
     RL_BUF_DIRTY = 14,     /* uint8[T][L] leaves awaiting re-clustering             persistent */
-    RL_BUF_CBOX = 15,      /* uint32[T][L][M][2] per mode: lowest R,G,B bytes passing the colour
-                              check, then highest (lo > hi: none)                   persistent */
+    RL_BUF_CBOX = 15,      /* uint32[T][L][M][2] per mode: lowest R,G,B values passing the colour
+                              check, then highest, as R | G << 10 | B << 20 (a channel with
+                              lo > hi passes nothing)                               persistent */
     RL_BUF_EREC = 16,      /* uint64[w*h][ew] per eligible-list entry: |M(u)| in bits 0-7, the
                               colour-check bit of mode m of M(u) in bit 8 + m (m < 56), then 64
                               bits per further word                                 scratch    */

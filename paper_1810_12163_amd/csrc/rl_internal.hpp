@@ -524,25 +524,34 @@ __device__ __forceinline__ void colour_range(float c, float theta, uint32_t& lo,
     }
 }
 
+// Colour boxes hold their three channel bounds in 10-bit fields
+// (c0 | c1 << 10 | c2 << 20), so that all three comparisons of a box are two
+// subtractions: with a guard bit 9 set in every field of the minuend, field
+// k of (x | G) - lo keeps its guard bit iff x_k >= lo_k, and likewise for
+// (hi | G) - x (no field borrows: every operand byte is below 256).
+constexpr uint32_t kBoxGuard = (1u << 9) | (1u << 19) | (1u << 29);
+
+__device__ __forceinline__ uint32_t spread3(uint32_t c0, uint32_t c1, uint32_t c2) { return c0 | (c1 << 10) | (c2 << 20); }
+
 __device__ __forceinline__ uint2 colour_box(float r, float g, float b, float theta)
 {
     uint32_t l0, h0, l1, h1, l2, h2;
     colour_range(r, theta, l0, h0);
     colour_range(g, theta, l1, h1);
     colour_range(b, theta, l2, h2);
-    return make_uint2(l0 | (l1 << 8) | (l2 << 16), h0 | (h1 << 8) | (h2 << 16));
+    return make_uint2(spread3(l0, l1, l2), spread3(h0, h1, h2));
 }
 
-// rgb: R | G << 8 | B << 16
-__device__ __forceinline__ bool box_pass(uint2 box, uint32_t rgb)
+// the pixel's colour in box form, from R | G << 8 | B << 16
+__device__ __forceinline__ uint32_t box_colour(uint32_t rgb)
 {
-    bool ok = true;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const uint32_t v = (rgb >> (8 * k)) & 0xFFu;
-        ok = ok && v >= ((box.x >> (8 * k)) & 0xFFu) && v <= ((box.y >> (8 * k)) & 0xFFu);
-    }
-    return ok;
+    return spread3(rgb & 0xFFu, (rgb >> 8) & 0xFFu, (rgb >> 16) & 0xFFu);
+}
+
+// x: box_colour of the pixel
+__device__ __forceinline__ bool box_pass(uint2 box, uint32_t x)
+{
+    return (((x | kBoxGuard) - box.x) & ((box.y | kBoxGuard) - x) & kBoxGuard) == kBoxGuard;
 }
 
 __device__ __forceinline__ int modes_total(uint2 nw, int T)

@@ -139,6 +139,7 @@ __global__ __launch_bounds__(256) void k_traverse(const Job* __restrict__ jobs)
 __device__ __forceinline__ void write_erec(const Job& J, int e, uint4 lw, uint2 nw, uint32_t rgb)
 {
     uint64_t* rec = J.erec + (size_t)e * J.ew;
+    const uint32_t x = box_colour(rgb);
     uint32_t m = 0;
     uint64_t w0 = 0, cur = 0;
     for (int t = 0; t < J.T; ++t) {
@@ -149,9 +150,9 @@ __device__ __forceinline__ void write_erec(const Job& J, int e, uint4 lw, uint2 
             const int nj = min(4, c - j0);
             uint2 bx[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) bx[u] = u < nj ? ldg(box + j0 + u) : make_uint2(1u, 0u);
+            for (int u = 0; u < 4; ++u) bx[u] = u < nj ? ldg(box + j0 + u) : make_uint2(kBoxGuard, 0u);
             for (int u = 0; u < nj; ++u, ++m) {
-                const uint64_t b = box_pass(bx[u], rgb) ? 1u : 0u;
+                const uint64_t b = box_pass(bx[u], x) ? 1u : 0u;
                 if (m < 56) {
                     w0 |= b << (8 + m);
                 } else {
