@@ -119,6 +119,8 @@ def main():
     ap.add_argument("--robustness", action="store_true",
                     help="also run the missing-depth and depth-noise sweeps (Default RANSAC settings)")
     ap.add_argument("--robustness-queries", type=int, default=32)
+    ap.add_argument("--render-procs", type=int, default=16,
+                    help="worker processes rendering the inputs before the GPU is used (1 = in this process)")
     ap.add_argument("--cascade-frames", type=int, default=16,
                     help="frames relocalised by the paper's Fast -> Intermediate -> Slow cascade (0 = skip)")
     ap.add_argument("--lm-steps", type=int, default=5,
@@ -141,9 +143,12 @@ def main():
     # every CPU-side input is generated before the GPU runtime is initialised
     t_setup = time.time()
     log(f"[bench] rendering {args.adapt_frames} adaptation frames and {args.queries} queries (640x480)")
-    procs = max(1, min(16, os.cpu_count() or 1))
-    # the standard 640x480 workload, rendered in worker processes
+    # the standard 640x480 workload, rendered in worker processes.  Workers
+    # are started only here, before this process touches the GPU (a profiler
+    # that initialises the GPU first needs --render-procs 1).
+    procs = max(1, min(args.render_procs, os.cpu_count() or 1))
     w = workloads.c2_corrupted(0, n_adapt=args.adapt_frames, n_queries=args.queries, processes=procs)
+    robust_inputs = robustness_inputs(args, procs) if args.robustness else None
     serve_inputs = None
     if args.serve_seconds > 0:
         serve_inputs = workloads.serving_setup(n_rooms=args.serve_rooms, n_adapt=20, n_cameras=32,
@@ -284,7 +289,7 @@ def main():
 
     lm = lm_leg(args, rl, room, batch, reqs, frames, w, qd, qc, use_graph) if args.lm_steps > 0 else None
     cascade = cascade_leg(args, rl, w, dev, qd, qc) if args.cascade_frames > 0 else None
-    robustness = robustness_leg(args, rl, dev) if args.robustness else None
+    robustness = robustness_leg(args, rl, dev, robust_inputs) if robust_inputs is not None else None
 
     # ---- rooflines -------------------------------------------------------------
     def roof_search(ms):
@@ -480,7 +485,23 @@ def cascade_leg(args, rl, w, dev, qd, qc):
     return res
 
 
-def robustness_leg(args, rl, dev):
+ROBUSTNESS_LEVELS = [("missing", p) for p in (0.1, 0.3, 0.5, 0.7, 0.9, 0.95)] + \
+                    [("noise", s) for s in (0.0, 0.025, 0.05, 0.075, 0.1)]
+
+
+def robustness_inputs(args, procs):
+    """Frames of every sweep level, rendered before the GPU is used."""
+    from rlsynth import workloads
+    out = []
+    for kind, v in ROBUSTNESS_LEVELS:
+        kw = dict(dropout=v) if kind == "missing" else dict(depth_rel_sigma=v)
+        out.append((kind, v, workloads.c2_corrupted(0, n_adapt=50, n_queries=args.robustness_queries,
+                                                    processes=procs, **kw)))
+    log(f"[bench] robustness inputs rendered ({len(out)} levels)")
+    return out
+
+
+def robustness_leg(args, rl, dev, inputs):
     """The paper's robustness protocols on the 640x480 workload: every
     adaptation and query frame re-rendered with a fraction p of the depth
     pixels zeroed (r <= p, r ~ U[0,1]), or with depth-dependent noise
@@ -489,14 +510,10 @@ def robustness_leg(args, rl, dev):
     covariance, one output).  Fraction of queries within 5 cm / 5 deg."""
     import torch
 
-    from rlsynth import scene, workloads
-    levels = [("missing", p) for p in (0.1, 0.3, 0.5, 0.7, 0.9, 0.95)] + \
-             [("noise", s) for s in (0.0, 0.025, 0.05, 0.075, 0.1)]
+    from rlsynth import scene
     out = {}
-    for kind, v in levels:
+    for kind, v, w in inputs:
         t0 = time.time()
-        kw = dict(dropout=v) if kind == "missing" else dict(depth_rel_sigma=v)
-        w = workloads.c2_corrupted(0, n_adapt=50, n_queries=args.robustness_queries, processes=16, **kw)
         room = rl.Room(dict(w.params, max_pose_candidates_after_cull=64, ransac_inliers_per_iteration=512),
                        w.nodes, 640, 480, device=dev)
         for f in w.adapt:
