@@ -106,6 +106,9 @@ struct Job {
     double* lm_part;          // [N][lm_tiles][28] LM pass partial sums per (survivor position, tile)
     int* Ie;                  // [rounds_max * eta] eligible-list entries of I
     int* lm_plan;             // [jobs + 1] LM work plan of the launch (shared by its jobs)
+    double4* lm_px;           // [rounds_max * eta] camera point and |M(u)| of each pixel of I
+    float4* lm_rows;          // [rows per pixel][rounds_max * eta][3] staged rows of M(u) (mean, Sigma^-1)
+    int lm_icap, pad3;        // rounds_max * eta: stride of lm_rows
     int lm_tiles, pad2;       // tiles of the largest cumulative I
     double* partial;          // [ptiles][N]
     double* partial_all;      // [rounds][ptiles][kFastStride] per-round partials once survivors fit fast_max
@@ -222,6 +225,13 @@ __device__ __forceinline__ float4 ldg<float4>(const float4* p)
 {
     const rl_f32x4 v = *(const __attribute__((address_space(1))) rl_f32x4*)p;
     return make_float4(v.x, v.y, v.z, v.w);
+}
+template <>
+__device__ __forceinline__ double4 ldg<double4>(const double4* p)
+{
+    const uint4 a = ldg(reinterpret_cast<const uint4*>(p)), b = ldg(reinterpret_cast<const uint4*>(p) + 1);
+    return make_double4(__hiloint2double((int)a.y, (int)a.x), __hiloint2double((int)a.w, (int)a.z),
+                        __hiloint2double((int)b.y, (int)b.x), __hiloint2double((int)b.w, (int)b.z));
 }
 
 // integer in [0, n): floor(r * n / 2^32)

@@ -796,8 +796,28 @@ __global__ __launch_bounds__(256) void k_lm_draw(const Job* __restrict__ jobs, i
     const uint4 rb = philox(make_uint4(kTagScore << 28, (uint32_t)rk, (uint32_t)(kk >> 2), 0u), J.key0, J.key1);
     const uint32_t rv = (kk & 3) == 0 ? rb.x : (kk & 3) == 1 ? rb.y : (kk & 3) == 2 ? rb.z : rb.w;
     const uint32_t e = below(rv, (uint32_t)J.st->n_elig);
+    const uint4 c0 = ldg(J.ecold + 2 * e), lw = ldg(J.ecold + 2 * e + 1);
+    const int p = (int)c0.x;
     J.Ie[k] = (int)e;
-    J.I[k] = (int)ldg(J.ecold + 2 * e).x;
+    J.I[k] = p;
+    // the pixel's camera point and its rows of M(u) (mean, Sigma^-1: the
+    // first 48 bytes of each mode row), flattened tree-major, in a
+    // row-major-by-index array the passes read coalesced across pixels
+    double x[3];
+    backproject(__uint_as_float(c0.y), p % J.w, p / J.w, J.fx, J.fy, J.cx, J.cy, x);
+    const uint2 nw = make_uint2(c0.z, c0.w);
+    int j = 0;
+    for (int t = 0; t < J.T; ++t) {
+        const int c = (int)count_of(nw, t);
+        const float4* row = J.modes + ((((size_t)t << J.D) + leaf_of(lw, t)) * (size_t)J.M) * 4;
+        for (int m = 0; m < c; ++m, ++j) {
+            float4* dst = J.lm_rows + ((size_t)j * J.lm_icap + k) * 3;
+            dst[0] = ldg(row + 4 * m);
+            dst[1] = ldg(row + 4 * m + 1);
+            dst[2] = ldg(row + 4 * m + 2);
+        }
+    }
+    J.lm_px[k] = make_double4(x[0], x[1], x[2], (double)j);
 }
 
 __global__ __launch_bounds__(256) void k_lm_init(const Job* __restrict__ jobs, int round)
@@ -904,23 +924,14 @@ __device__ __forceinline__ void lm_pass_item(const Job& J, int pos, int tile, in
     for (int j = 0; j < kLmTile / 64; ++j) {
         const int k = tile * kLmTile + j * 64 + (int)threadIdx.x;
         if (k >= nI) break;
-        const uint32_t e = (uint32_t)ldg(J.Ie + k);
-        const uint4 c0 = ldg(J.ecold + 2 * e), lw = ldg(J.ecold + 2 * e + 1);
-        const int p = (int)c0.x;
-        double x[3];
-        backproject(__uint_as_float(c0.y), p % J.w, p / J.w, J.fx, J.fy, J.cx, J.cy, x);
+        const double4 px = ldg(J.lm_px + k);
+        const double x[3] = {px.x, px.y, px.z};
+        const int nm = (int)px.w;
         const double y0 = P[0] * x[0] + P[1] * x[1] + P[2] * x[2] + P[9];
         const double y1 = P[3] * x[0] + P[4] * x[1] + P[5] * x[2] + P[10];
         const double y2 = P[6] * x[0] + P[7] * x[1] + P[8] * x[2] + P[11];
-        const uint2 nw = make_uint2(c0.z, c0.w);
-        // nearest mode (ties to the lower index); the rows of M(u) are taken
-        // four at a time across tree boundaries, and the best row stays in
-        // registers
-        int pre[kMaxTrees + 1];
-        pre[0] = 0;
-#pragma unroll
-        for (int t = 0; t < kMaxTrees; ++t) pre[t + 1] = pre[t] + (t < J.T ? (int)count_of(nw, t) : 0);
-        const int nm = pre[kMaxTrees];
+        // nearest mode (ties to the lower index) over the staged rows, four at
+        // a time; the best row stays in registers
         double best = INFINITY;
         bool found = false;
         float4 ba = make_float4(0.f, 0.f, 0.f, 0.f), bb = ba, bc = ba;
@@ -929,13 +940,7 @@ __device__ __forceinline__ void lm_pass_item(const Job& J, int pos, int tile, in
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int j = min(j0 + u, nm - 1);
-                int t = 0;
-#pragma unroll
-                for (int q = 1; q < kMaxTrees; ++q) t += j >= pre[q] ? 1 : 0;
-                int first = 0;
-#pragma unroll
-                for (int q = 1; q < kMaxTrees; ++q) first = t == q ? pre[q] : first;
-                const float4* row = J.modes + ((((size_t)t << J.D) + leaf_of(lw, t)) * (size_t)J.M + (size_t)(j - first)) * 4;
+                const float4* row = J.lm_rows + ((size_t)j * J.lm_icap + k) * 3;
                 ra[u] = ldg(row);
                 if (COV) {
                     rb[u] = ldg(row + 1);

@@ -121,10 +121,10 @@ int score_tile(int) { return kScoreTile; }
 // Per-frame (relocalisation) scratch of one job slot.
 struct FrameLayout {
     size_t state, result, probe, leaves, nmt, nm, tile_count, eligible, ecold, erec, hyp_best, hyps, surv, E, partial,
-        partial_all, pose64, lm_state, lm_part, Ie, lm_plan,
+        partial_all, pose64, lm_state, lm_part, Ie, lm_plan, lm_px, lm_rows,
         I, inl, trace_slots, trace_E, total;
     int ew;
-    int lm_tiles;
+    int lm_tiles, lm_icap;
 };
 
 // 64-bit words per eligible-pixel record: |M(u)| and 56 colour-check bits in
@@ -160,6 +160,9 @@ FrameLayout frame_layout(int maxP, int N, int eta, int rounds, int TP, int rows_
     L.lm_part = c.take((size_t)N * L.lm_tiles * 28 * 8);
     L.Ie = c.take((size_t)rounds * eta * 4);
     L.lm_plan = c.take((size_t)(kMaxBatchFrames + 1) * 4);
+    L.lm_icap = rounds * eta;
+    L.lm_px = c.take((size_t)rounds * eta * 32);
+    L.lm_rows = c.take((size_t)rounds * eta * rows_per_pixel * 48);
     const int ptiles = (eta + TP - 1) / TP;
     L.partial = c.take((size_t)ptiles * N * 8);
     L.partial_all = c.take((size_t)rounds * ptiles * kFastStride * 8);
@@ -525,6 +528,9 @@ static Job make_job(const rl_room* r, char* scr, const FrameLayout& FL, const rl
     J.lm_part = reinterpret_cast<double*>(scr + FL.lm_part);
     J.Ie = reinterpret_cast<int*>(scr + FL.Ie);
     J.lm_plan = reinterpret_cast<int*>(scr + FL.lm_plan);
+    J.lm_px = reinterpret_cast<double4*>(scr + FL.lm_px);
+    J.lm_rows = reinterpret_cast<float4*>(scr + FL.lm_rows);
+    J.lm_icap = FL.lm_icap;
     J.lm_tiles = FL.lm_tiles;
     J.partial = reinterpret_cast<double*>(scr + FL.partial);
     J.partial_all = reinterpret_cast<double*>(scr + FL.partial_all);
