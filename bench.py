@@ -486,7 +486,7 @@ def cascade_leg(args, rl, w, dev, qd, qc):
 
 
 ROBUSTNESS_LEVELS = [("missing", p) for p in (0.1, 0.3, 0.5, 0.7, 0.9, 0.95)] + \
-                    [("noise", s) for s in (0.0, 0.025, 0.05, 0.075, 0.1)]
+                    [("noise", s) for s in (0.0, 0.025, 0.05, 0.075, 0.1)] + [("novel", 1.0)]
 
 
 def robustness_inputs(args, procs):
@@ -494,7 +494,7 @@ def robustness_inputs(args, procs):
     from rlsynth import workloads
     out = []
     for kind, v in ROBUSTNESS_LEVELS:
-        kw = dict(dropout=v) if kind == "missing" else dict(depth_rel_sigma=v)
+        kw = {"missing": dict(dropout=v), "noise": dict(depth_rel_sigma=v), "novel": dict(novel_fraction=v)}[kind]
         out.append((kind, v, workloads.c2_corrupted(0, n_adapt=50, n_queries=args.robustness_queries,
                                                     processes=procs, **kw)))
     log(f"[bench] robustness inputs rendered ({len(out)} levels)")
@@ -507,7 +507,8 @@ def robustness_leg(args, rl, dev, inputs):
     pixels zeroed (r <= p, r ~ U[0,1]), or with depth-dependent noise
     d + n d, n ~ N(0, sigma^2); relocalised with the Default relocaliser's
     RANSAC settings (1024 hypotheses, cull to 64, eta 512, LM with the
-    covariance, one output).  Fraction of queries within 5 cm / 5 deg."""
+    covariance, one output).  Also queries all drawn >= 50 cm or >= 50 deg
+    from every adaptation pose.  Fraction of queries within 5 cm / 5 deg."""
     import torch
 
     from rlsynth import scene

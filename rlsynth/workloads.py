@@ -130,15 +130,17 @@ def c2(room_id: int = 0, n_adapt: int = 50, n_queries: int = 8) -> Workload:
 
 
 def c2_corrupted(room_id: int = 0, n_adapt: int = 50, n_queries: int = 16, dropout: float = 0.05,
-                 depth_rel_sigma: float = 0.0, processes: int = 0) -> Workload:
+                 depth_rel_sigma: float = 0.0, processes: int = 0, novel_fraction: float = 0.0) -> Workload:
     """The 640x480 workload (same room, forest, poses and noise seeds) with
     every adaptation and query frame rendered under the paper's robustness
     protocols: each pixel's depth zeroed iff r <= dropout, r ~ U[0, 1], and
-    depth d replaced by d + n d, n ~ N(0, depth_rel_sigma^2)."""
+    depth d replaced by d + n d, n ~ N(0, depth_rel_sigma^2).  A
+    novel_fraction of the queries is drawn >= 50 cm or >= 50 degrees away
+    from every adaptation pose."""
     room = _scene.make_room(room_id)
     nodes = _forest.make_forest(1000 + room_id, **_presets.FOREST["c2"])
     ap = adapt_poses_for(room, room_id, n_adapt)
-    qp = query_poses(room, ap, n_queries, room_id)
+    qp = query_poses(room, ap, n_queries, room_id, novel_fraction=novel_fraction)
     kw = dict(dropout=dropout, depth_rel_sigma=depth_rel_sigma)
     jobs = [(room_id, p, 640, 480, frame_seed(room_id, 0, i), kw) for i, p in enumerate(ap)]
     jobs += [(room_id, p, 640, 480, frame_seed(room_id, 1, q), kw) for q, p in enumerate(qp)]
