@@ -107,7 +107,7 @@ def main():
     ap.add_argument("--queries", type=int, default=16)
     ap.add_argument("--adapt-frames", type=int, default=50)
     ap.add_argument("--plain", type=int, default=32, help="plain relocalisations timed for latency")
-    ap.add_argument("--cpu-frames", type=int, default=4, help="oracle relocalisations (0 = skip)")
+    ap.add_argument("--cpu-frames", type=int, default=12, help="oracle relocalisations, about 11 s of host work (0 = skip)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--timer", default="hyp_search", choices=["traverse", "hyp_search", "ransac"])
     ap.add_argument("--serve-seconds", type=float, default=3.0,
