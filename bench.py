@@ -308,6 +308,7 @@ def main():
         hbm = B * 640 * 480 * TRAVERSE_PIXEL_HBM
         return dict(kernel="k_pack+k_traverse", bound="l1", achieved=by / k / 1e9, peak=MI355X_L1 / 1e9,
                     unit="GB/s", frac=by / k / MI355X_L1, traffic=None, launch_ms=ms,
+                    touched_vs_hbm_frac=by / k / MI355X_HBM,
                     hbm_unavoidable_GBps=hbm / k / 1e9, hbm_frac=hbm / k / MI355X_HBM,
                     work=f"{node_tests} node tests x {NODE_TEST_BYTES} B gathered through the vector L1 "
                          f"(peak derived: 256 CUs x 64 B/clk x 2.4 GHz); {B} frames x 307200 px x "
