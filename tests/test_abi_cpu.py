@@ -53,12 +53,14 @@ int main(void) {
          sizeof(rl_request), sizeof(rl_batch_params), sizeof(rl_hypothesis), sizeof(rl_node));
   printf("%zu %zu %zu %zu\\n", offsetof(rl_params, seed), offsetof(rl_frame, K), offsetof(rl_result, n_out),
          offsetof(rl_request, request_seed));
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(rl_reloc_opts), offsetof(rl_reloc_opts, max_translation_error),
+         offsetof(rl_params, lm_iterations), offsetof(rl_request, pose_update), sizeof(rl_surface));
   return 0;
 }
 ''')
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(prog)], check=True)
-    a, b = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.strip().splitlines()
+    a, b, c = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.strip().splitlines()
     sizes = [int(v) for v in a.split()]
     offs = [int(v) for v in b.split()]
     assert sizes == [ctypes.sizeof(rl.Params), ctypes.sizeof(rl.Frame), ctypes.sizeof(rl.Result),
@@ -66,6 +68,8 @@ int main(void) {
                      rl.NODE_DTYPE.itemsize]
     assert offs == [rl.Params.seed.offset, rl.Frame.K.offset, rl.Result.n_out.offset,
                     rl.Request.request_seed.offset]
+    assert [int(v) for v in c.split()] == [ctypes.sizeof(rl.RelocOpts), rl.RelocOpts.max_translation_error.offset,
+                                           rl.Params.lm_iterations.offset, rl.Request.pose_update.offset, 64]
 
 
 def test_presets_match_the_shared_presets():
