@@ -99,6 +99,31 @@ typedef struct rl_room rl_room;
 typedef struct { float dx, dy, tau; uint32_t kind; } rl_node;
 
 /*
+ * A random forest (the paper's "Is Pre-Training Necessary?" section: complete
+ * trees with random split functions, adapted online, relocalise as well as
+ * trained ones).  For every branch node: a Depth feature with probability
+ * p_depth, else a DA-RGB feature on a uniformly drawn channel; offsets
+ * uniform in +-offset_range (pixel-metres); thresholds uniform in
+ * +-tau_depth (metres) for Depth nodes, +-tau_colour (0..255 scale) for
+ * DA-RGB nodes.  Draws: Philox4x32-10 keyed by seed (two words, low first),
+ * counters (tree, node, 0, 0) -> (kind, channel, dx, dy) and (tree, node, 1, 0)
+ * -> tau; a uniform in [a, b) is a + (b - a) * (u + 0.5) * 2^-32 in double,
+ * rounded to float; channel = (u * 3) >> 32.
+ * host_nodes: n_trees * (2^depth - 1) records, tree-major (NULL: only *bytes
+ * is set).  RL_EINVAL for n_trees outside 1..8, depth outside 1..15, a
+ * probability outside [0, 1] or negative ranges.
+ */
+typedef struct {
+    int32_t n_trees, depth;
+    float p_depth;                   /* probability of a Depth feature (0.4 in the paper) */
+    float offset_range;              /* pixel-metres */
+    float tau_depth;                 /* metres */
+    float tau_colour;                /* 0..255 scale */
+    uint64_t seed;
+} rl_forest_params;
+rl_status rl_forest_generate(const rl_forest_params* fp, rl_node* host_nodes, size_t* bytes);
+
+/*
  * Fills *out with a named preset: "default", "fast", "intermediate", "slow"
  * (Table 8 of the paper) or "c1" (160x120, one depth-8 tree, kappa 64,
  * 64 hypotheses, eta 100) / "c2" (640x480, five depth-15 trees, kappa 1024,
@@ -133,6 +158,20 @@ rl_status relocaliser_create(const rl_params* p, const rl_node* host_nodes, int3
 
 /* Destroys the handle (the caller's buffers are left untouched). */
 rl_status relocaliser_destroy(rl_room* room);
+
+/*
+ * Room persistence.  relocaliser_save writes the room's whole persistent
+ * state (forest, reservoirs, arrival counters, dirty flags, modes, colour
+ * boxes) and its mode-schedule position to path, after the work queued on
+ * the room's stream; relocaliser_load reads such a file into a room created
+ * with the same forest shape (n_trees, depth, max_cluster_count,
+ * reservoir_capacity), after every batch that reads the room.  Both are
+ * synchronous; they stage through a 64 MiB pinned host buffer.  RL_EINVAL for
+ * a file that cannot be opened, read or written, a bad header or a shape
+ * mismatch (the room is unchanged then, except after a short read).
+ */
+rl_status relocaliser_save(rl_room* room, const char* path);
+rl_status relocaliser_load(rl_room* room, const char* path);
 
 /*
  * Online adaptation (Sec. 3.2.2): when reliable != 0, the pixels on the

@@ -88,6 +88,12 @@ class Request(ctypes.Structure):
                 ("n_hypotheses", ctypes.c_int32), ("pose_update", ctypes.c_int32)]
 
 
+class ForestParams(ctypes.Structure):
+    _fields_ = [("n_trees", ctypes.c_int32), ("depth", ctypes.c_int32), ("p_depth", ctypes.c_float),
+                ("offset_range", ctypes.c_float), ("tau_depth", ctypes.c_float), ("tau_colour", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
+
+
 class BatchParams(ctypes.Structure):
     _fields_ = [("max_frames", ctypes.c_int32), ("max_width", ctypes.c_int32),
                 ("max_height", ctypes.c_int32), ("max_hypotheses", ctypes.c_int32),
@@ -104,7 +110,7 @@ EXPORTS = [
     "rl_batch_relocalise", "rl_batch_relocalise_async", "rl_last_error", "rl_version",
     "relocaliser_set_timer", "rl_batch_set_timer", "relocaliser_relocalise_opts", "rl_plane_scores",
     "relocaliser_set_mode_schedule", "relocaliser_set_schedule", "rl_batch_set_schedule",
-    "rl_depth_scores",
+    "rl_depth_scores", "rl_forest_generate", "relocaliser_save", "relocaliser_load",
 ]
 
 # launch schedules the library accepts (iterations per thread, fast waves)
@@ -151,6 +157,9 @@ def lib():
         L.rl_batch_set_timer.argtypes = [P, I32, P, P]
         L.relocaliser_set_mode_schedule.argtypes = [P, I32]
         L.relocaliser_set_schedule.argtypes = [P, I32, I32]
+        L.rl_forest_generate.argtypes = [ctypes.POINTER(ForestParams), P, ctypes.POINTER(ctypes.c_size_t)]
+        L.relocaliser_save.argtypes = [P, ctypes.c_char_p]
+        L.relocaliser_load.argtypes = [P, ctypes.c_char_p]
         L.rl_batch_set_schedule.argtypes = [P, I32, I32]
         L.rl_depth_scores.argtypes = [P, ctypes.POINTER(Frame), P, I32, P, I32, ctypes.c_float, ctypes.c_float,
                                       P, P, P]
@@ -166,6 +175,19 @@ def _check(status, allow=(RL_OK,)):
     if status not in allow:
         raise RlError(status, lib().rl_last_error().decode())
     return status
+
+
+def forest_generate(n_trees: int, depth: int, seed: int, p_depth: float = 0.4, offset_range: float = 130.0,
+                    tau_depth: float = 0.2, tau_colour: float = 64.0) -> np.ndarray:
+    """A random forest (rl_forest_generate): (n_trees, 2^depth - 1) node records."""
+    fp = ForestParams(int(n_trees), int(depth), float(p_depth), float(offset_range), float(tau_depth),
+                      float(tau_colour), int(seed))
+    nb = ctypes.c_size_t()
+    _check(lib().rl_forest_generate(ctypes.byref(fp), None, ctypes.byref(nb)))
+    out = np.zeros((int(n_trees), (1 << int(depth)) - 1), dtype=NODE_DTYPE)
+    assert out.nbytes == nb.value
+    _check(lib().rl_forest_generate(ctypes.byref(fp), out.ctypes.data, ctypes.byref(nb)))
+    return out
 
 
 def params_struct(d: dict) -> Params:
@@ -276,6 +298,14 @@ class Room:
         """0: exact mode update before each relocalisation; K > 0: RQS of the
         next K leaves (round robin) after each adapted frame."""
         _check(lib().relocaliser_set_mode_schedule(self.handle, int(leaves_per_frame)))
+
+    def save(self, path: str):
+        """Writes the room's persistent state to a file (relocaliser_save)."""
+        _check(lib().relocaliser_save(self.handle, str(path).encode()))
+
+    def load(self, path: str):
+        """Reads a saved room of the same forest shape (relocaliser_load)."""
+        _check(lib().relocaliser_load(self.handle, str(path).encode()))
 
     def set_schedule(self, ipt: int, fast_waves: int):
         """Result-invariant launch schedule: search iterations per thread

@@ -697,6 +697,150 @@ RL_API rl_status relocaliser_destroy(rl_room* r)
     return RL_OK;
 }
 
+// ------------------------------------------------------------------------
+// random forest (host)
+
+// Philox4x32-10 on the host (the device version is in rl_internal.hpp)
+static void philox_host(const uint32_t in[4], uint32_t k0, uint32_t k1, uint32_t out[4])
+{
+    uint32_t c0 = in[0], c1 = in[1], c2 = in[2], c3 = in[3];
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0, n1 = (uint32_t)p1;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1, n3 = (uint32_t)p0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+static float uniform_range(uint32_t u, float a, float b)
+{
+    const double x = ((double)u + 0.5) * (1.0 / 4294967296.0);
+    return (float)((double)a + ((double)b - (double)a) * x);
+}
+
+RL_API rl_status rl_forest_generate(const rl_forest_params* fp, rl_node* nodes, size_t* bytes)
+{
+    if (!fp || !bytes) return fail(RL_EINVAL, "NULL argument");
+    if (fp->n_trees < 1 || fp->n_trees > kMaxTrees) return fail(RL_EINVAL, "n_trees must be in 1..%d", kMaxTrees);
+    if (fp->depth < 1 || fp->depth > 15) return fail(RL_EINVAL, "depth must be in 1..15");
+    if (!(fp->p_depth >= 0.0f && fp->p_depth <= 1.0f)) return fail(RL_EINVAL, "p_depth must be in [0, 1]");
+    if (!(fp->offset_range >= 0.0f) || !(fp->tau_depth >= 0.0f) || !(fp->tau_colour >= 0.0f) ||
+        !finite_f(fp->offset_range) || !finite_f(fp->tau_depth) || !finite_f(fp->tau_colour))
+        return fail(RL_EINVAL, "ranges must be finite and >= 0");
+    const size_t NT = ((size_t)1 << fp->depth) - 1;
+    *bytes = (size_t)fp->n_trees * NT * sizeof(rl_node);
+    if (!nodes) return RL_OK;
+    const uint32_t k0 = (uint32_t)fp->seed, k1 = (uint32_t)(fp->seed >> 32);
+    for (int t = 0; t < fp->n_trees; ++t)
+        for (size_t i = 0; i < NT; ++i) {
+            uint32_t a[4], b[4];
+            const uint32_t c0[4] = {(uint32_t)t, (uint32_t)i, 0u, 0u}, c1[4] = {(uint32_t)t, (uint32_t)i, 1u, 0u};
+            philox_host(c0, k0, k1, a);
+            philox_host(c1, k0, k1, b);
+            rl_node& n = nodes[(size_t)t * NT + i];
+            const bool depth = ((double)a[0] + 0.5) * (1.0 / 4294967296.0) < (double)fp->p_depth;
+            const uint32_t chan = (uint32_t)(((uint64_t)a[1] * 3u) >> 32);
+            n.kind = depth ? 0u : 1u + chan;
+            n.dx = uniform_range(a[2], -fp->offset_range, fp->offset_range);
+            n.dy = uniform_range(a[3], -fp->offset_range, fp->offset_range);
+            n.tau = depth ? uniform_range(b[0], -fp->tau_depth, fp->tau_depth)
+                          : uniform_range(b[0], -fp->tau_colour, fp->tau_colour);
+        }
+    return RL_OK;
+}
+
+// ------------------------------------------------------------------------
+// room persistence
+
+struct SaveHeader {
+    char magic[8];            // "RLROOM01"
+    int32_t n_trees, depth, max_cluster_count, reservoir_capacity;
+    uint64_t bytes;           // persistent state that follows
+    uint32_t rr_cursor;
+    int32_t modes_stale;
+};
+
+static const size_t kStageBytes = (size_t)64 << 20;
+
+RL_API rl_status relocaliser_save(rl_room* r, const char* path)
+{
+    if (!r || !path) return fail(RL_EINVAL, "NULL argument");
+    SaveHeader h;
+    std::memset(&h, 0, sizeof(h));
+    std::memcpy(h.magic, "RLROOM01", 8);
+    h.n_trees = r->p.n_trees;
+    h.depth = r->p.depth;
+    h.max_cluster_count = r->p.max_cluster_count;
+    h.reservoir_capacity = r->p.reservoir_capacity;
+    h.bytes = r->PL.total;
+    h.rr_cursor = r->rr_cursor;
+    h.modes_stale = r->modes_stale ? 1 : 0;
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return fail(RL_EINVAL, "cannot open %s for writing", path);
+    char* stage = nullptr;
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&stage), kStageBytes, hipHostMallocDefault);
+    bool ok = e == hipSuccess && std::fwrite(&h, sizeof(h), 1, f) == 1;
+    for (size_t off = 0; ok && off < h.bytes; off += kStageBytes) {
+        const size_t n = std::min(kStageBytes, (size_t)h.bytes - off);
+        e = hipMemcpyAsync(stage, r->pers + off, n, hipMemcpyDeviceToHost, r->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
+        ok = e == hipSuccess && std::fwrite(stage, 1, n, f) == n;
+    }
+    if (stage) (void)hipHostFree(stage);
+    ok = (std::fclose(f) == 0) && ok;
+    if (e != hipSuccess) return hip_fail(e, "room save");
+    if (!ok) return fail(RL_EINVAL, "writing %s failed", path);
+    return RL_OK;
+}
+
+RL_API rl_status relocaliser_load(rl_room* r, const char* path)
+{
+    if (!r || !path) return fail(RL_EINVAL, "NULL argument");
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(RL_EINVAL, "cannot open %s", path);
+    SaveHeader h;
+    if (std::fread(&h, sizeof(h), 1, f) != 1 || std::memcmp(h.magic, "RLROOM01", 8) != 0) {
+        std::fclose(f);
+        return fail(RL_EINVAL, "%s is not a saved room", path);
+    }
+    if (h.n_trees != r->p.n_trees || h.depth != r->p.depth || h.max_cluster_count != r->p.max_cluster_count ||
+        h.reservoir_capacity != r->p.reservoir_capacity || h.bytes != r->PL.total) {
+        std::fclose(f);
+        return fail(RL_EINVAL, "%s holds a room of another forest shape", path);
+    }
+    // the load writes everything batches read: after the batches that read the room
+    hipError_t e = hipSuccess;
+    for (hipEvent_t ev : r->readers) {
+        if (e == hipSuccess) e = hipStreamWaitEvent(r->stream, ev, 0);
+        r->spare.push_back(ev);
+    }
+    r->readers.clear();
+    char* stage = nullptr;
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&stage), kStageBytes, hipHostMallocDefault);
+    bool ok = e == hipSuccess;
+    for (size_t off = 0; ok && off < h.bytes; off += kStageBytes) {
+        const size_t n = std::min(kStageBytes, (size_t)h.bytes - off);
+        ok = std::fread(stage, 1, n, f) == n;
+        if (ok) e = hipMemcpyAsync(r->pers + off, stage, n, hipMemcpyHostToDevice, r->stream);
+        if (ok && e == hipSuccess) e = hipStreamSynchronize(r->stream);
+        ok = ok && e == hipSuccess;
+    }
+    std::fclose(f);
+    if (stage) (void)hipHostFree(stage);
+    if (e == hipSuccess) e = hipEventRecord(r->wev, r->stream);
+    if (e != hipSuccess) return hip_fail(e, "room load");
+    if (!ok) return fail(RL_EINVAL, "%s is truncated", path);
+    r->wrote = true;
+    r->rr_cursor = h.rr_cursor;
+    r->modes_stale = h.modes_stale != 0;
+    return RL_OK;
+}
+
 RL_API rl_status relocaliser_set_trace(rl_room* r, int32_t on)
 {
     if (!r) return fail(RL_EINVAL, "room is NULL");

@@ -255,3 +255,46 @@ def test_round_robin_mode_schedule_matches_oracle():
     bad, worst = compare_modes(nm_g, modes_g, o.nmodes, o.modes, o.M, range(TL))
     assert bad == 0 and worst < 1e-5
     room.close()
+
+
+def test_generated_forest_room_matches_oracle(c1, tmp_path):
+    """A room on the library's own random forest (rl_forest_generate) routes,
+    adapts and relocalises as the oracle does on the same nodes; a saved
+    room loaded into a fresh room of the same shape gives the same state and
+    the same result, and a room of another shape refuses the file."""
+    w, _, _ = c1
+    nodes = rl.forest_generate(1, 8, 4242)
+    o = oracle.Oracle(w.params, nodes)
+    room = rl.Room(w.params, nodes, 160, 120)
+    for f in w.adapt:
+        o.adapt(f.depth, f.rgb, f.K, f.pose)
+        d, c = dev(f)
+        room.adapt(d, c, f.K, f.pose)
+    room.update_modes()
+    q = w.queries[0]
+    d, c = dev(q)
+    res = room.relocalise(d, c, q.K, request_seed=3)
+    ref = o.relocalise(q.depth, q.rgb, q.K, 3)
+    leaves = room.buffer_np(rl.BUF_LEAVES, np.uint16).reshape(-1, 8)[:q.depth.size, :1]
+    np.testing.assert_array_equal(leaves, ref["leaves"])
+    assert res["status"] == ref["status"]
+    if ref["status"] == "ok":
+        assert res["winner"] == ref["winner"] and pose_diff(res["pose"], ref["pose"]) < 1e-5
+    # persistence
+    path = tmp_path / "room.bin"
+    room.save(path)
+    fresh = rl.Room(w.params, nodes, 160, 120)
+    fresh.load(path)
+    for which in (rl.BUF_NODES, rl.BUF_RESERVOIR, rl.BUF_SEEN, rl.BUF_MODES, rl.BUF_NMODES, rl.BUF_CBOX):
+        assert np.array_equal(fresh.buffer_np(which, np.uint8), room.buffer_np(which, np.uint8)), which
+    again = fresh.relocalise(d, c, q.K, request_seed=3)
+    assert again["status"] == res["status"] and np.array_equal(again["pose"], res["pose"])
+    assert again["energy"] == res["energy"] or (np.isinf(again["energy"]) and np.isinf(res["energy"]))
+    other = rl.Room(dict(w.params, max_cluster_count=4), nodes, 160, 120)
+    with pytest.raises(rl.RlError):
+        other.load(path)
+    (tmp_path / "junk.bin").write_bytes(b"not a room")
+    with pytest.raises(rl.RlError):
+        fresh.load(tmp_path / "junk.bin")
+    for r in (room, fresh, other):
+        r.close()
