@@ -67,11 +67,16 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
+    """SHA-256 of the device sources (kernels, their launchers and shared
+    device code); the host runtime (rl_runtime.hip) is left out, since it
+    changes no kernel."""
     import glob
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1810_12163_amd", "csrc")
     for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp"))):
+        if os.path.basename(f) == "rl_runtime.hip":
+            continue
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -87,7 +92,7 @@ def profiled_traffic(name: str):
     taken_on, traffic = None, None
     with open(path) as fh:
         for line in fh:
-            if line.startswith("# kernel sources sha256"):
+            if line.startswith("# device sources sha256"):
                 taken_on = line.split()[-1]
             elif line.startswith("traffic_bytes_per_launch"):
                 traffic = float(line.split()[1])
