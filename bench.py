@@ -12,6 +12,7 @@ synchronous call) is timed beside it for latency and reloc/s.
 Prints one JSON line on stdout; progress goes to stderr.
 """
 import argparse
+import collections
 import json
 import math
 import os
@@ -567,6 +568,41 @@ def serve_leg(args, rl, dev, inputs):
     log(f"[bench] serving: {len(rooms)} rooms resident "
         f"({sum(r.persistent.numel() for r in rooms) / 2**30:.1f} GiB), setup {time.time() - t0:.1f} s")
     out = {}
+    # a steady mixed batch: 64 frames over 8 rooms, resolutions and hypothesis
+    # counts drawn with the cameras' frames, and 16 adaptation frames applied
+    # after every batch's relocalisations
+    rng = np.random.default_rng(64)
+    near = [c for c in range(len(cams)) if cams[c]["room"] < 8]
+    picks = [(c, int(rng.integers(len(camf[c])))) for c in rng.choice(near, size=64)]
+    breqs = [(rooms[cams[c]["room"]], camf[c][k][0], camf[c][k][1], camf[c][k][2].K, i,
+              workloads.HYPOTHESES[camf[c][k][2].w]) for i, (c, k) in enumerate(picks)]
+    adapts = [(rooms[cams[c]["room"]], camf[c][k][0], camf[c][k][1], camf[c][k][2]) for (c, k) in picks[:16]]
+    mb = rl.Batch(64, 640, 480, 1024, 500, 10, 5, 50, device=dev)
+    for _ in range(2):
+        mb.relocalise(breqs)
+    torch.cuda.synchronize()
+    steps = max(3, args.steps)
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        mb.relocalise(breqs)
+    torch.cuda.synchronize()
+    el_r = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        mb.relocalise(breqs)
+        for room, d, rgb, f in adapts:
+            room.adapt(d, rgb, f.K, f.pose)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    mb.close()
+    mix = collections.Counter(camf[c][k][2].w for c, k in picks)
+    out["mixed_batch"] = dict(relocs_per_s=64 * steps / el_r, ms_per_batch=el_r / steps * 1e3,
+                              relocs_per_s_with_adapt=64 * steps / el, ms_per_step_with_adapt=el / steps * 1e3,
+                              rooms=8, widths={str(k): v for k, v in sorted(mix.items())}, adapts_per_step=16)
+    mbo = out["mixed_batch"]
+    log(f"[bench] mixed batch (8 rooms, {dict(mix)} by width): {mbo['relocs_per_s']:.1f} reloc/s "
+        f"({mbo['ms_per_batch']:.2f} ms per 64-frame batch); with 16 adaptations per step "
+        f"{mbo['relocs_per_s_with_adapt']:.1f} reloc/s ({mbo['ms_per_step_with_adapt']:.2f} ms)")
     warm = 1.0
     for rate in [float(v) for v in args.serve_rates.split(",")]:
         server = serve.Server(max_batch=64, max_width=640, max_height=480, max_hypotheses=1024, max_eta=500,
