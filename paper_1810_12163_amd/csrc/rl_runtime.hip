@@ -834,8 +834,8 @@ RL_API rl_status relocaliser_load(rl_room* r, const char* path)
     if (stage) (void)hipHostFree(stage);
     if (e == hipSuccess) e = hipEventRecord(r->wev, r->stream);
     if (e != hipSuccess) return hip_fail(e, "room load");
-    if (!ok) return fail(RL_EINVAL, "%s is truncated", path);
-    r->wrote = true;
+    r->wrote = true;      // also after a truncated file: later readers wait for what was copied
+    if (!ok) return fail(RL_EINVAL, "%s is truncated (the room's state is partly overwritten)", path);
     r->rr_cursor = h.rr_cursor;
     r->modes_stale = h.modes_stale != 0;
     return RL_OK;
