@@ -705,25 +705,42 @@ __global__ __launch_bounds__(64) void k_score_all(const Job* __restrict__ jobs, 
 // Those rounds' selections, one block per job, thread = position in the
 // survivor list: same accumulation (tile order, rounds in order, onto the
 // energies of earlier rounds), ranking by (energy, slot), initial cull and
-// halving as k_select.
+// halving as k_select.  A round's tile sum does not depend on the ranking,
+// so the whole block first forms every (round, position) sum at once, in
+// LDS (up to kSelSums of them; any beyond are summed in the ranking loop, to
+// the same value).
+constexpr int kSelSums = 4096;
+
 __global__ __launch_bounds__(kFastStride) void k_select_all(const Job* __restrict__ jobs, int nptiles)
 {
     const Job& J = jobs[blockIdx.x];
     if (J.st->done || J.lm) return;
     __shared__ double sE[kFastStride];
     __shared__ int sS[kFastStride], sA[kFastStride];
-    const int n0 = J.st->n_surv;
+    __shared__ double sSum[kSelSums];
+    const int n0 = J.st->n_surv, r0 = J.st->rounds_run;
     const int lane = (int)threadIdx.x;
+    const int ptiles = min(nptiles, (J.eta + J.TP - 1) / J.TP);
+    const int nsum = min((rounds_of(n0, J.n_cull, J.n_out, r0) - r0) * n0, kSelSums);
+    for (int i = lane; i < nsum; i += kFastStride) {
+        const int rr = i / n0, pos = i - rr * n0;
+        sSum[i] = sum_in_order(J.partial_all + (size_t)(r0 + rr) * nptiles * kFastStride + pos, kFastStride,
+                               ptiles);
+    }
+    __syncthreads();
     const bool valid = lane < n0;
     const int slot = valid ? ldg(J.surv + lane) : INT_MAX;
-    const int ptiles = min(nptiles, (J.eta + J.TP - 1) / J.TP);
     double E = valid ? J.E[slot] : 0.0;
     bool alive = valid;
-    int n = n0, round = J.st->rounds_run, rank = 0;
+    int n = n0, round = r0, rank = 0;
     bool first = round == 0;
     while (first || n > J.n_out) {
-        if (alive)
-            E = E + sum_in_order(J.partial_all + (size_t)round * nptiles * kFastStride + lane, kFastStride, ptiles);
+        if (alive) {
+            const int i = (round - r0) * n0 + lane;
+            E = E + (i < nsum ? sSum[i]
+                              : sum_in_order(J.partial_all + (size_t)round * nptiles * kFastStride + lane,
+                                             kFastStride, ptiles));
+        }
         const double key = isnan(E) ? INFINITY : E;
         sE[lane] = key;
         sS[lane] = slot;
@@ -920,7 +937,6 @@ __device__ __forceinline__ void lm_pass_item(const Job& J, int pos, int tile, in
     for (int i = 0; i < 12; ++i) P[i] = S[kLmCand + i];
     double v[kLmVals];
     for (int i = 0; i < kLmVals; ++i) v[i] = 0.0;
-    const bool cov = J.use_cov != 0;
     for (int j = 0; j < kLmTile / 64; ++j) {
         const int k = tile * kLmTile + j * 64 + (int)threadIdx.x;
         if (k >= nI) break;
@@ -1193,24 +1209,14 @@ __global__ __launch_bounds__(1024) void k_select(const Job* __restrict__ jobs, i
 }
 
 // ------------------------------------------------------------------------
-__device__ __forceinline__ double block_sum256(double v, double* s_red)
-{
-    s_red[threadIdx.x] = v;
-    __syncthreads();
-    for (int stride = 128; stride > 0; stride >>= 1) {
-        if ((int)threadIdx.x < stride) s_red[threadIdx.x] += s_red[threadIdx.x + stride];
-        __syncthreads();
-    }
-    const double r = s_red[0];
-    __syncthreads();
-    return r;
-}
-
 // Refit, part 1 (one thread per pixel of the final set I): the mode of M(u)
 // minimising the Eq. 5 distance under the winner's pose (ties -> lower m),
-// then the Euclidean inlier test.  J.inl[k] = that mode's row, or -1.
+// then the Euclidean inlier test.  J.inl[k] = that mode's row, or -1.  The
+// modes are walked tree by tree in M(u) order, four rows loaded ahead of
+// their comparisons.
 __global__ __launch_bounds__(256) void k_refit_assign(const Job* __restrict__ jobs)
 {
+#pragma clang fp contract(off)
     const Job& J = jobs[blockIdx.y];
     if (!J.final_refine) return;
     const int n = J.st->n_surv, rounds = J.st->rounds_run;
@@ -1229,43 +1235,104 @@ __global__ __launch_bounds__(256) void k_refit_assign(const Job* __restrict__ jo
     const double y2 = R[6] * x[0] + R[7] * x[1] + R[8] * x[2] + t[2];
     const uint4 lw = reinterpret_cast<const uint4*>(J.leaves)[p];
     const uint2 nw = reinterpret_cast<const uint2*>(J.nmt)[p];
-    const int nm = modes_total(nw, J.T);
+    const bool cov = J.use_cov != 0;
     double best = INFINITY;
-    int bm = -1;
-    for (int m = 0; m < nm; ++m) {
-        const float4* row = mode_row(J.modes, J.T, J.D, J.M, lw, nw, m);
-        const float4 a = row[0];
-        const double d0 = y0 - a.x, d1 = y1 - a.y, d2 = y2 - a.z;
-        double q;
-        if (J.use_cov) {
-            const float4 b = row[1], c = row[2];
-            q = d0 * (b.x * d0 + b.y * d1 + b.z * d2) + d1 * (b.y * d0 + b.w * d1 + c.x * d2)
-              + d2 * (b.z * d0 + c.x * d1 + c.y * d2);
-        } else {
-            q = d0 * d0 + d1 * d1 + d2 * d2;
-        }
-        q = fmax(q, 0.0);
-        if (q < best) {
-            best = q;
-            bm = m;
+    int bri = -1;
+    for (int tr = 0; tr < J.T; ++tr) {
+        const int c = (int)count_of(nw, tr);
+        const uint32_t base = (((uint32_t)tr << J.D) + leaf_of(lw, tr)) * (uint32_t)J.M;
+        for (int j0 = 0; j0 < c; j0 += 4) {
+            float4 ra[4], rb[4], rc[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float4* row = J.modes + (size_t)(base + (uint32_t)min(j0 + u, c - 1)) * 4;
+                ra[u] = ldg(row);
+                if (cov) {
+                    rb[u] = ldg(row + 1);
+                    rc[u] = ldg(row + 2);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (j0 + u >= c) break;
+                const float4 a = ra[u];
+                const double d0 = y0 - a.x, d1 = y1 - a.y, d2 = y2 - a.z;
+                double q;
+                if (cov) {
+                    const float4 b = rb[u], cc = rc[u];
+                    q = d0 * (b.x * d0 + b.y * d1 + b.z * d2) + d1 * (b.y * d0 + b.w * d1 + cc.x * d2)
+                      + d2 * (b.z * d0 + cc.x * d1 + cc.y * d2);
+                } else {
+                    q = d0 * d0 + d1 * d1 + d2 * d2;
+                }
+                q = fmax(q, 0.0);
+                if (q < best) {
+                    best = q;
+                    bri = (int)(base + (uint32_t)(j0 + u));
+                }
+            }
         }
     }
     int flag = -1;
-    if (bm >= 0) {
-        const uint32_t ri = mode_row_index(J, lw, nw, bm);
-        const float4 a = J.modes[(size_t)ri * 4];
+    if (bri >= 0) {
+        const float4 a = J.modes[(size_t)bri * 4];
         const double d0 = y0 - a.x, d1 = y1 - a.y, d2 = y2 - a.z;
-        if (sqrt(d0 * d0 + d1 * d1 + d2 * d2) <= J.theta_in) flag = (int)ri;
+        if (sqrt(d0 * d0 + d1 * d1 + d2 * d2) <= J.theta_in) flag = bri;
     }
     J.inl[k] = flag;
 }
 
+// Pairwise tree sums of NV values over a block of 256 threads, all values in
+// the same passes; each value is summed exactly as a separate tree would.
+template <int NV>
+__device__ __forceinline__ void block_sums256(double (&v)[NV], double* s_red)
+{
+#pragma unroll
+    for (int i = 0; i < NV; ++i) s_red[i * 256 + threadIdx.x] = v[i];
+    __syncthreads();
+    for (int stride = 128; stride > 0; stride >>= 1) {
+        if ((int)threadIdx.x < stride)
+#pragma unroll
+            for (int i = 0; i < NV; ++i) s_red[i * 256 + threadIdx.x] += s_red[i * 256 + threadIdx.x + stride];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = s_red[i * 256];
+    __syncthreads();
+}
+
+// The inlier pairs (x^C, mode mean) of kFinChunk consecutive positions of a
+// thread (k, k + 256, ...): every gather of the chunk is issued before the
+// pairs are used.  ok[u] = position k + 256 u is an inlier.
+constexpr int kFinChunk = 8;
+
+__device__ __forceinline__ void inlier_chunk(const Job& J, int k, int nI, bool ok[kFinChunk],
+                                             double x[kFinChunk][3], float4 a[kFinChunk])
+{
+    int ri[kFinChunk], p[kFinChunk];
+#pragma unroll
+    for (int u = 0; u < kFinChunk; ++u) ri[u] = k + 256 * u < nI ? J.inl[k + 256 * u] : -1;
+#pragma unroll
+    for (int u = 0; u < kFinChunk; ++u) p[u] = ri[u] >= 0 ? J.I[k + 256 * u] : 0;
+    float d[kFinChunk];
+#pragma unroll
+    for (int u = 0; u < kFinChunk; ++u) {
+        ok[u] = ri[u] >= 0;
+        d[u] = ok[u] ? J.depth[p[u]] : 0.0f;
+        a[u] = ok[u] ? J.modes[(size_t)ri[u] * 4] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < kFinChunk; ++u) backproject(d[u], p[u] % J.w, p[u] / J.w, J.fx, J.fy, J.cx, J.cy, x[u]);
+}
+
 // Refit, part 2 and the result record: centroids and cross-covariance of the
 // inlier pairs (x^C, mode mean), Kabsch over all of them (>= 3 inliers).
+// Each thread accumulates its positions in increasing order.
 __global__ __launch_bounds__(256) void k_finalize(const Job* __restrict__ jobs)
 {
+#pragma clang fp contract(off)
     const Job& J = jobs[blockIdx.y];
-    __shared__ double s_red[256];
+    __shared__ double s_red[9 * 256];
     __shared__ double s_pose[12];
     __shared__ int s_refit;
     rl_result* res = J.result;
@@ -1296,24 +1363,24 @@ __global__ __launch_bounds__(256) void k_finalize(const Job* __restrict__ jobs)
     const int nI = rounds * J.eta;
     int n_inl = 0;
     if (J.final_refine) {
-        double sc[3] = {0, 0, 0}, sw[3] = {0, 0, 0}, cnt = 0;
-        for (int k = threadIdx.x; k < nI; k += 256) {
-            const int ri = J.inl[k];
-            if (ri < 0) continue;
-            const int p = J.I[k];
-            double x[3];
-            backproject(J.depth[p], p % J.w, p / J.w, J.fx, J.fy, J.cx, J.cy, x);
-            const float4 a = J.modes[(size_t)ri * 4];
-            cnt += 1.0;
-            sc[0] += x[0]; sc[1] += x[1]; sc[2] += x[2];
-            sw[0] += a.x; sw[1] += a.y; sw[2] += a.z;
+        // count, sum of x^C, sum of the mode means
+        double c7[7] = {0, 0, 0, 0, 0, 0, 0};
+        for (int k = threadIdx.x; k < nI; k += 256 * kFinChunk) {
+            bool ok[kFinChunk];
+            double x[kFinChunk][3];
+            float4 a[kFinChunk];
+            inlier_chunk(J, k, nI, ok, x, a);
+#pragma unroll
+            for (int u = 0; u < kFinChunk; ++u) {
+                if (!ok[u]) continue;
+                c7[0] += 1.0;
+                c7[1] += x[u][0]; c7[2] += x[u][1]; c7[3] += x[u][2];
+                c7[4] += a[u].x; c7[5] += a[u].y; c7[6] += a[u].z;
+            }
         }
-        const double tc = block_sum256(cnt, s_red);
-        double cc[3], cw[3];
-        for (int i = 0; i < 3; ++i) {
-            cc[i] = block_sum256(sc[i], s_red);
-            cw[i] = block_sum256(sw[i], s_red);
-        }
+        block_sums256<7>(c7, s_red);
+        const double tc = c7[0];
+        double cc[3] = {c7[1], c7[2], c7[3]}, cw[3] = {c7[4], c7[5], c7[6]};
         n_inl = (int)tc;
         if (n_inl >= 3) {
             for (int i = 0; i < 3; ++i) {
@@ -1321,18 +1388,20 @@ __global__ __launch_bounds__(256) void k_finalize(const Job* __restrict__ jobs)
                 cw[i] /= tc;
             }
             double A[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-            for (int k = threadIdx.x; k < nI; k += 256) {
-                const int ri = J.inl[k];
-                if (ri < 0) continue;
-                const int p = J.I[k];
-                double x[3];
-                backproject(J.depth[p], p % J.w, p / J.w, J.fx, J.fy, J.cx, J.cy, x);
-                const float4 a = J.modes[(size_t)ri * 4];
-                const double wv[3] = {(double)a.x - cw[0], (double)a.y - cw[1], (double)a.z - cw[2]};
-                for (int i = 0; i < 3; ++i)
-                    for (int j = 0; j < 3; ++j) A[i * 3 + j] += (x[i] - cc[i]) * wv[j];
+            for (int k = threadIdx.x; k < nI; k += 256 * kFinChunk) {
+                bool ok[kFinChunk];
+                double x[kFinChunk][3];
+                float4 a[kFinChunk];
+                inlier_chunk(J, k, nI, ok, x, a);
+#pragma unroll
+                for (int u = 0; u < kFinChunk; ++u) {
+                    if (!ok[u]) continue;
+                    const double wv[3] = {(double)a[u].x - cw[0], (double)a[u].y - cw[1], (double)a[u].z - cw[2]};
+                    for (int i = 0; i < 3; ++i)
+                        for (int j = 0; j < 3; ++j) A[i * 3 + j] += (x[u][i] - cc[i]) * wv[j];
+                }
             }
-            for (int i = 0; i < 9; ++i) A[i] = block_sum256(A[i], s_red);
+            block_sums256<9>(A, s_red);
             if (threadIdx.x == 0) {
                 double R2[9], t2[3];
                 if (rigid_from_cov(A, cc, cw, R2, t2)) {
@@ -1550,7 +1619,7 @@ hipError_t launch_score_all(const Job* jobs, int njobs, int rounds, int nptiles,
     if (fw < 1 || fw > kMaxFastWaves) return hipErrorInvalidValue;
     k_score_all<<<dim3(rounds * nptiles * fw, njobs), dim3(64), 0, st>>>(jobs, nptiles, fw);
     RL_CHECK_LAUNCH();
-    k_select_all<<<dim3(njobs), dim3(64 * fw), 0, st>>>(jobs, nptiles);
+    k_select_all<<<dim3(njobs), dim3(kFastStride), 0, st>>>(jobs, nptiles);
     RL_CHECK_LAUNCH();
     return hipSuccess;
 }
