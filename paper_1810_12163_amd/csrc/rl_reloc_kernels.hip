@@ -136,38 +136,47 @@ __global__ __launch_bounds__(256) void k_traverse(const Job* __restrict__ jobs)
 
 // Record of eligible pixel p at list position e: |M(u)| and the colour-check
 // bit of every mode of M(u), in M(u) order, from the modes' colour boxes.
+// The boxes are walked tree by tree, eight loaded ahead of their checks.
 __device__ __forceinline__ void write_erec(const Job& J, int e, uint4 lw, uint2 nw, uint32_t rgb)
 {
     uint64_t* rec = J.erec + (size_t)e * J.ew;
     const uint32_t x = box_colour(rgb);
-    uint32_t m = 0;
+    const int total = modes_total(nw, J.T);
     uint64_t w0 = 0, cur = 0;
-    for (int t = 0; t < J.T; ++t) {
-        const int c = (int)count_of(nw, t);
-        const uint2* box = J.cbox + (((size_t)t << J.D) + leaf_of(lw, t)) * (size_t)J.M;
-        for (int j0 = 0; j0 < c; j0 += 4) {
-            // four modes' boxes loaded ahead of their checks
-            const int nj = min(4, c - j0);
-            uint2 bx[4];
+    int t = 0, j = 0;
+    while (t < J.T - 1 && count_of(nw, t) == 0) ++t;
+    for (int m0 = 0; m0 < total; m0 += 8) {
+        uint2 bx[8];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) bx[u] = u < nj ? ldg(box + j0 + u) : make_uint2(kBoxGuard, 0u);
-            for (int u = 0; u < nj; ++u, ++m) {
-                const uint64_t b = box_pass(bx[u], x) ? 1u : 0u;
-                if (m < 56) {
-                    w0 |= b << (8 + m);
-                } else {
-                    const uint32_t k = m - 56;
-                    cur |= b << (k & 63);
-                    if ((k & 63) == 63) {
-                        rec[1 + (k >> 6)] = cur;
-                        cur = 0;
-                    }
+        for (int u = 0; u < 8; ++u) {
+            bx[u] = ldg(J.cbox + (((size_t)t << J.D) + leaf_of(lw, t)) * (size_t)J.M + (size_t)j);
+            if (m0 + u + 1 < total) {           // the next mode of M(u)
+                ++j;
+                while (j >= (int)count_of(nw, t)) {
+                    ++t;
+                    j = 0;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t m = (uint32_t)(m0 + u);
+            if ((int)m >= total) break;
+            const uint64_t b = box_pass(bx[u], x) ? 1u : 0u;
+            if (m < 56) {
+                w0 |= b << (8 + m);
+            } else {
+                const uint32_t k = m - 56;
+                cur |= b << (k & 63);
+                if ((k & 63) == 63) {
+                    rec[1 + (k >> 6)] = cur;
+                    cur = 0;
                 }
             }
         }
     }
-    if (m > 56 && ((m - 56) & 63)) rec[1 + ((m - 56) >> 6)] = cur;
-    rec[0] = w0 | m;
+    if (total > 56 && ((total - 56) & 63)) rec[1 + ((total - 56) >> 6)] = cur;
+    rec[0] = w0 | (uint64_t)total;
 }
 
 // Raster-order compaction of eligible pixels over the traversal's tiles, and
@@ -564,21 +573,66 @@ __global__ __launch_bounds__(256) void k_ransac_init(const Job* __restrict__ job
 }
 
 // ------------------------------------------------------------------------
-// Eq. 5 terms of one hypothesis (R, t) over the pixels k0 .. k0 + tp - 1 of
-// round `round`, summed in pixel order in FP64.  Every lane of a wave walks
-// the same pixels and the same mode rows of M(u) (one broadcast request per
-// row for the wave); rows are loaded four at a time.  Lane 0 of a wave with
-// write_I records the pixels in I.
-__device__ __forceinline__ double mode_q(const float4* row, double y0, double y1, double y2, bool cov)
+// Eq. 5 distance q = d^T A d for d = y - mu (A = the row's Sigma^-1, or I)
+// from a mode row already loaded (mean in a.xyz; Sigma^-1 upper triangle in
+// b.xyzw, c.xy)
+template <bool COV>
+__device__ __forceinline__ double row_q(const float4& a, const float4& b, const float4& c, double y0, double y1,
+                                        double y2)
 {
 #pragma clang fp contract(off)
-    const float4 a = ldg(row);
     const double d0 = y0 - (double)a.x, d1 = y1 - (double)a.y, d2 = y2 - (double)a.z;
-    if (!cov) return d0 * d0 + d1 * d1 + d2 * d2;
-    const float4 b = ldg(row + 1), c = ldg(row + 2);
+    if (!COV) return d0 * d0 + d1 * d1 + d2 * d2;
     const double m3 = b.x, m4 = b.y, m5 = b.z, m6 = b.w, m7 = c.x, m8 = c.y;
     return d0 * (m3 * d0 + m4 * d1 + m5 * d2) + d1 * (m4 * d0 + m6 * d1 + m7 * d2)
          + d2 * (m5 * d0 + m7 * d1 + m8 * d2);
+}
+
+// Eq. 5 terms of one hypothesis (R, t) over the pixels k0 .. k0 + tp - 1 of
+// round `round`, summed in pixel order in FP64.  Every lane of a wave walks
+// the same pixels and the same mode rows of M(u) (one broadcast request per
+// row for the wave).  Lane 0 of a wave with write_I records the pixels in I.
+// The rows of M(u) (tree-major, as mode_row orders them) are visited
+// kScoreRows at a time, all loaded before their comparisons; the minimum is taken
+// in M(u) order.  The tile's list entries and records are loaded before its
+// first pixel is scored.
+#ifndef RL_SCORE_ROWS
+#define RL_SCORE_ROWS 2
+#endif
+constexpr int kScoreRows = RL_SCORE_ROWS;
+
+template <bool COV>
+__device__ __forceinline__ double nearest_q(const Job& J, uint4 lw, uint2 nw, double y0, double y1, double y2)
+{
+    const int total = modes_total(nw, J.T);
+    double best = INFINITY;
+    int t = 0, j = 0;
+    while (t < J.T - 1 && count_of(nw, t) == 0) ++t;
+    for (int m0 = 0; m0 < total; m0 += kScoreRows) {
+        float4 ra[kScoreRows], rb[kScoreRows], rc[kScoreRows];
+#pragma unroll
+        for (int u = 0; u < kScoreRows; ++u) {
+            const float4* row = J.modes + ((((size_t)t << J.D) + leaf_of(lw, t)) * (size_t)J.M + (size_t)j) * 4;
+            ra[u] = ldg(row);
+            if (COV) {
+                rb[u] = ldg(row + 1);
+                rc[u] = ldg(row + 2);
+            } else {
+                rb[u] = rc[u] = ra[u];
+            }
+            if (m0 + u + 1 < total) {           // the next row of M(u)
+                ++j;
+                while (j >= (int)count_of(nw, t)) {
+                    ++t;
+                    j = 0;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kScoreRows; ++u)
+            if (m0 + u < total) best = fmin(best, row_q<COV>(ra[u], rb[u], rc[u], y0, y1, y2));
+    }
+    return best;
 }
 
 __device__ __forceinline__ double score_pixels(const Job& J, int round, int k0, int tp, bool write_I,
@@ -587,33 +641,35 @@ __device__ __forceinline__ double score_pixels(const Job& J, int round, int k0, 
 #pragma clang fp contract(off)
     const bool cov = J.use_cov != 0;
     const uint32_t n_elig = (uint32_t)J.st->n_elig;
-    double acc = 0.0;
-    for (int i = 0; i < tp; ++i) {
-        const int k = k0 + i;
-        const uint4 rb = philox(make_uint4(kTagScore << 28, (uint32_t)round, (uint32_t)(k >> 2), 0u), J.key0, J.key1);
+    const uint32_t blk0 = (uint32_t)k0 >> 2;
+    const uint4 rb0 = philox(make_uint4(kTagScore << 28, (uint32_t)round, blk0, 0u), J.key0, J.key1);
+    uint4 c0[kScoreTile], lw[kScoreTile];
+#pragma unroll
+    for (int i = 0; i < kScoreTile; ++i) {
+        const int k = k0 + min(i, tp - 1);
+        const uint4 rb = ((uint32_t)k >> 2) == blk0
+                             ? rb0
+                             : philox(make_uint4(kTagScore << 28, (uint32_t)round, (uint32_t)(k >> 2), 0u), J.key0,
+                                      J.key1);
         const uint32_t rv = (k & 3) == 0 ? rb.x : (k & 3) == 1 ? rb.y : (k & 3) == 2 ? rb.z : rb.w;
         const uint32_t e = below(rv, n_elig);
-        const uint4 c0 = ldg(J.ecold + 2 * e), lw = ldg(J.ecold + 2 * e + 1);
-        const int p = (int)c0.x;
+        c0[i] = ldg(J.ecold + 2 * e);
+        lw[i] = ldg(J.ecold + 2 * e + 1);
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < kScoreTile; ++i) {
+        if (i >= tp) break;
+        const int k = k0 + i;
+        const int p = (int)c0[i].x;
         if (write_I && threadIdx.x == 0) J.I[round * J.eta + k] = p;
         double x[3];
-        backproject(__uint_as_float(c0.y), p % J.w, p / J.w, J.fx, J.fy, J.cx, J.cy, x);
+        backproject(__uint_as_float(c0[i].y), p % J.w, p / J.w, J.fx, J.fy, J.cx, J.cy, x);
         const double y0 = R[0] * x[0] + R[1] * x[1] + R[2] * x[2] + t[0];
         const double y1 = R[3] * x[0] + R[4] * x[1] + R[5] * x[2] + t[1];
         const double y2 = R[6] * x[0] + R[7] * x[1] + R[8] * x[2] + t[2];
-        const uint2 nw = make_uint2(c0.z, c0.w);
-        double best = INFINITY;
-        for (int tr = 0; tr < J.T; ++tr) {
-            const int c = (int)count_of(nw, tr);
-            const float4* row = J.modes + ((((size_t)tr << J.D) + leaf_of(lw, tr)) * (size_t)J.M) * 4;
-            int j = 0;
-            for (; j + 4 <= c; j += 4) {
-                const double q0 = mode_q(row + 4 * j, y0, y1, y2, cov), q1 = mode_q(row + 4 * j + 4, y0, y1, y2, cov);
-                const double q2 = mode_q(row + 4 * j + 8, y0, y1, y2, cov), q3 = mode_q(row + 4 * j + 12, y0, y1, y2, cov);
-                best = fmin(fmin(fmin(fmin(best, q0), q1), q2), q3);
-            }
-            for (; j < c; ++j) best = fmin(best, mode_q(row + 4 * j, y0, y1, y2, cov));
-        }
+        const uint2 nw = make_uint2(c0[i].z, c0[i].w);
+        const double best = cov ? nearest_q<true>(J, lw[i], nw, y0, y1, y2) : nearest_q<false>(J, lw[i], nw, y0, y1, y2);
         acc += sqrt(fmax(best, 0.0));
     }
     return acc;
@@ -625,20 +681,21 @@ __device__ __forceinline__ void hyp_pose(const Hyp& hy, double R[9], double t[3]
     for (int i = 0; i < 3; ++i) t[i] = hy.t[i];
 }
 
-// sum of n values p[0], p[stride], ... in index order; loads are issued 16 at
-// a time ahead of the additions
+// sum of n values p[0], p[stride], ... in index order; loads are issued W at
+// a time (the last group padded) ahead of the additions
+template <int W = 16>
 __device__ __forceinline__ double sum_in_order(const double* p, size_t stride, int n)
 {
     double acc = 0.0;
-    int i = 0;
-    for (; i + 16 <= n; i += 16) {
-        double v[16];
+    for (int i = 0; i < n; i += W) {
+        const int m = min(W, n - i);
+        double v[W];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) v[k] = ldg(p + (size_t)(i + k) * stride);
+        for (int k = 0; k < W; ++k) v[k] = k < m ? ldg(p + (size_t)(i + k) * stride) : 0.0;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) acc += v[k];
+        for (int k = 0; k < W; ++k)
+            if (k < m) acc += v[k];
     }
-    for (; i < n; ++i) acc += ldg(p + (size_t)i * stride);
     return acc;
 }
 
@@ -724,8 +781,8 @@ __global__ __launch_bounds__(kFastStride) void k_select_all(const Job* __restric
     const int nsum = min((rounds_of(n0, J.n_cull, J.n_out, r0) - r0) * n0, kSelSums);
     for (int i = lane; i < nsum; i += kFastStride) {
         const int rr = i / n0, pos = i - rr * n0;
-        sSum[i] = sum_in_order(J.partial_all + (size_t)(r0 + rr) * nptiles * kFastStride + pos, kFastStride,
-                               ptiles);
+        sSum[i] = sum_in_order<32>(J.partial_all + (size_t)(r0 + rr) * nptiles * kFastStride + pos, kFastStride,
+                                   ptiles);
     }
     __syncthreads();
     const bool valid = lane < n0;
@@ -910,20 +967,6 @@ __global__ __launch_bounds__(64) void k_lm_pass(const Job* __restrict__ jobs, in
         if (J.use_cov) lm_pass_item<true>(J, item / tiles, item % tiles, nI);
         else lm_pass_item<false>(J, item / tiles, item % tiles, nI);
     }
-}
-
-// q = d^T A d for d = y - mu (A = the row's Sigma^-1, or I), as mode_q
-// evaluates it, from rows already loaded
-template <bool COV>
-__device__ __forceinline__ double row_q(const float4& a, const float4& b, const float4& c, double y0, double y1,
-                                        double y2)
-{
-#pragma clang fp contract(off)
-    const double d0 = y0 - (double)a.x, d1 = y1 - (double)a.y, d2 = y2 - (double)a.z;
-    if (!COV) return d0 * d0 + d1 * d1 + d2 * d2;
-    const double m3 = b.x, m4 = b.y, m5 = b.z, m6 = b.w, m7 = c.x, m8 = c.y;
-    return d0 * (m3 * d0 + m4 * d1 + m5 * d2) + d1 * (m4 * d0 + m6 * d1 + m7 * d2)
-         + d2 * (m5 * d0 + m7 * d1 + m8 * d2);
 }
 
 template <bool COV>
@@ -1282,38 +1325,46 @@ __global__ __launch_bounds__(256) void k_refit_assign(const Job* __restrict__ jo
     J.inl[k] = flag;
 }
 
-// Pairwise tree sums of NV values over a block of 256 threads, all values in
-// the same passes; each value is summed exactly as a separate tree would.
+// Sums of NV values over a block of kFinThreads threads in a fixed order:
+// within each wave by an xor tree, then the waves' sums in wave order.
+constexpr int kFinThreads = 1024;
+
 template <int NV>
-__device__ __forceinline__ void block_sums256(double (&v)[NV], double* s_red)
+__device__ __forceinline__ void block_sums(double (&v)[NV], double* s_red)
 {
+    constexpr int W = kFinThreads / 64;
+    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
 #pragma unroll
-    for (int i = 0; i < NV; ++i) s_red[i * 256 + threadIdx.x] = v[i];
-    __syncthreads();
-    for (int stride = 128; stride > 0; stride >>= 1) {
-        if ((int)threadIdx.x < stride)
-#pragma unroll
-            for (int i = 0; i < NV; ++i) s_red[i * 256 + threadIdx.x] += s_red[i * 256 + threadIdx.x + stride];
-        __syncthreads();
+    for (int i = 0; i < NV; ++i) {
+        double x = v[i];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+        if (lane == 0) s_red[i * W + wave] = x;
     }
+    __syncthreads();
+    if ((int)threadIdx.x < NV) {
+        double x = 0.0;
+        for (int w = 0; w < W; ++w) x += s_red[threadIdx.x * W + w];
+        s_red[NV * W + threadIdx.x] = x;
+    }
+    __syncthreads();
 #pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = s_red[i * 256];
+    for (int i = 0; i < NV; ++i) v[i] = s_red[NV * W + i];
     __syncthreads();
 }
 
 // The inlier pairs (x^C, mode mean) of kFinChunk consecutive positions of a
-// thread (k, k + 256, ...): every gather of the chunk is issued before the
-// pairs are used.  ok[u] = position k + 256 u is an inlier.
-constexpr int kFinChunk = 8;
+// thread (k, k + kFinThreads, ...): every gather of the chunk is issued
+// before the pairs are used.  ok[u] = position k + kFinThreads u is an inlier.
+constexpr int kFinChunk = 4;
 
 __device__ __forceinline__ void inlier_chunk(const Job& J, int k, int nI, bool ok[kFinChunk],
                                              double x[kFinChunk][3], float4 a[kFinChunk])
 {
     int ri[kFinChunk], p[kFinChunk];
 #pragma unroll
-    for (int u = 0; u < kFinChunk; ++u) ri[u] = k + 256 * u < nI ? J.inl[k + 256 * u] : -1;
+    for (int u = 0; u < kFinChunk; ++u) ri[u] = k + kFinThreads * u < nI ? J.inl[k + kFinThreads * u] : -1;
 #pragma unroll
-    for (int u = 0; u < kFinChunk; ++u) p[u] = ri[u] >= 0 ? J.I[k + 256 * u] : 0;
+    for (int u = 0; u < kFinChunk; ++u) p[u] = ri[u] >= 0 ? J.I[k + kFinThreads * u] : 0;
     float d[kFinChunk];
 #pragma unroll
     for (int u = 0; u < kFinChunk; ++u) {
@@ -1328,11 +1379,11 @@ __device__ __forceinline__ void inlier_chunk(const Job& J, int k, int nI, bool o
 // Refit, part 2 and the result record: centroids and cross-covariance of the
 // inlier pairs (x^C, mode mean), Kabsch over all of them (>= 3 inliers).
 // Each thread accumulates its positions in increasing order.
-__global__ __launch_bounds__(256) void k_finalize(const Job* __restrict__ jobs)
+__global__ __launch_bounds__(kFinThreads) void k_finalize(const Job* __restrict__ jobs)
 {
 #pragma clang fp contract(off)
     const Job& J = jobs[blockIdx.y];
-    __shared__ double s_red[9 * 256];
+    __shared__ double s_red[9 * (kFinThreads / 64 + 1)];
     __shared__ double s_pose[12];
     __shared__ int s_refit;
     rl_result* res = J.result;
@@ -1365,7 +1416,7 @@ __global__ __launch_bounds__(256) void k_finalize(const Job* __restrict__ jobs)
     if (J.final_refine) {
         // count, sum of x^C, sum of the mode means
         double c7[7] = {0, 0, 0, 0, 0, 0, 0};
-        for (int k = threadIdx.x; k < nI; k += 256 * kFinChunk) {
+        for (int k = threadIdx.x; k < nI; k += kFinThreads * kFinChunk) {
             bool ok[kFinChunk];
             double x[kFinChunk][3];
             float4 a[kFinChunk];
@@ -1378,7 +1429,7 @@ __global__ __launch_bounds__(256) void k_finalize(const Job* __restrict__ jobs)
                 c7[4] += a[u].x; c7[5] += a[u].y; c7[6] += a[u].z;
             }
         }
-        block_sums256<7>(c7, s_red);
+        block_sums<7>(c7, s_red);
         const double tc = c7[0];
         double cc[3] = {c7[1], c7[2], c7[3]}, cw[3] = {c7[4], c7[5], c7[6]};
         n_inl = (int)tc;
@@ -1388,7 +1439,7 @@ __global__ __launch_bounds__(256) void k_finalize(const Job* __restrict__ jobs)
                 cw[i] /= tc;
             }
             double A[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-            for (int k = threadIdx.x; k < nI; k += 256 * kFinChunk) {
+            for (int k = threadIdx.x; k < nI; k += kFinThreads * kFinChunk) {
                 bool ok[kFinChunk];
                 double x[kFinChunk][3];
                 float4 a[kFinChunk];
@@ -1401,7 +1452,7 @@ __global__ __launch_bounds__(256) void k_finalize(const Job* __restrict__ jobs)
                         for (int j = 0; j < 3; ++j) A[i * 3 + j] += (x[u][i] - cc[i]) * wv[j];
                 }
             }
-            block_sums256<9>(A, s_red);
+            block_sums<9>(A, s_red);
             if (threadIdx.x == 0) {
                 double R2[9], t2[3];
                 if (rigid_from_cov(A, cc, cw, R2, t2)) {
@@ -1649,7 +1700,7 @@ hipError_t launch_finalize(const Job* jobs, int njobs, int maxIlen, hipStream_t 
 {
     k_refit_assign<<<dim3((maxIlen + 255) / 256, njobs), dim3(256), 0, st>>>(jobs);
     RL_CHECK_LAUNCH();
-    k_finalize<<<dim3(1, njobs), dim3(256), 0, st>>>(jobs);
+    k_finalize<<<dim3(1, njobs), dim3(kFinThreads), 0, st>>>(jobs);
     RL_CHECK_LAUNCH();
     return hipSuccess;
 }
