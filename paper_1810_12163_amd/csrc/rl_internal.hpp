@@ -105,7 +105,7 @@ struct Job {
     double* lm_state;         // [N][kLmStateDoubles] LM iteration state per slot
     double* lm_part;          // [N][lm_tiles][28] LM pass partial sums per (survivor position, tile)
     int* Ie;                  // [rounds_max * eta] eligible-list entries of I
-    int* lm_plan;             // [jobs + 1] LM work plan of the launch (shared by its jobs)
+    int* lm_plan;             // 2 x [kMaxBatchFrames + 1] LM item and survivor plans of the launch (shared by its jobs)
     double4* lm_px;           // [rounds_max * eta] camera point and |M(u)| of each pixel of I
     float4* lm_rows;          // [rows per pixel][rounds_max * eta][3] staged rows of M(u) (mean, Sigma^-1)
     int lm_icap, pad3;        // rounds_max * eta: stride of lm_rows

@@ -847,11 +847,13 @@ __global__ __launch_bounds__(kFastStride) void k_select_all(const Job* __restric
 // the final pose.
 //
 // The work is spread over the grid: a pass evaluates (E, g, N) for every
-// survivor of every job at once, one wave per (survivor, 256-pixel tile)
-// writing its partial sums; a step kernel (one thread per survivor) adds
-// the tiles in order, takes the accept/reject decision and the next damped
-// step.  Per round: k_lm_draw, k_lm_init, then (iterations + 1) x
-// (k_lm_pass, k_lm_step).
+// survivor of every job at once, one wave per (survivor, kLmTile-pixel
+// tile) writing its partial sums; a step kernel (one wave per survivor)
+// adds the tiles in order, takes the accept/reject decision and the next
+// damped step.  Both stride over the round's plan of the running jobs'
+// items and survivors, so their grids do not scale with the batch's
+// survivor bound.  Per round: k_lm_draw, k_lm_init, k_lm_plan, then
+// (iterations + 1) x (k_lm_pass, k_lm_step).
 constexpr int kLmVals = 28;      // E, g (6), upper triangle of N (21, row-major)
 
 // per-slot state (doubles): current pose, candidate pose, N (upper), g, E,
@@ -880,18 +882,35 @@ __global__ __launch_bounds__(256) void k_lm_draw(const Job* __restrict__ jobs, i
     double x[3];
     backproject(__uint_as_float(c0.y), p % J.w, p / J.w, J.fx, J.fy, J.cx, J.cy, x);
     const uint2 nw = make_uint2(c0.z, c0.w);
-    int j = 0;
-    for (int t = 0; t < J.T; ++t) {
-        const int c = (int)count_of(nw, t);
-        const float4* row = J.modes + ((((size_t)t << J.D) + leaf_of(lw, t)) * (size_t)J.M) * 4;
-        for (int m = 0; m < c; ++m, ++j) {
-            float4* dst = J.lm_rows + ((size_t)j * J.lm_icap + k) * 3;
-            dst[0] = ldg(row + 4 * m);
-            dst[1] = ldg(row + 4 * m + 1);
-            dst[2] = ldg(row + 4 * m + 2);
+    const int total = modes_total(nw, J.T);
+    int t = 0, jt = 0;
+    while (t < J.T - 1 && count_of(nw, t) == 0) ++t;
+    for (int m0 = 0; m0 < total; m0 += 4) {           // four rows loaded ahead of their stores
+        float4 r[4][3];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float4* row = J.modes + ((((size_t)t << J.D) + leaf_of(lw, t)) * (size_t)J.M + (size_t)jt) * 4;
+            r[u][0] = ldg(row);
+            r[u][1] = ldg(row + 1);
+            r[u][2] = ldg(row + 2);
+            if (m0 + u + 1 < total) {
+                ++jt;
+                while (jt >= (int)count_of(nw, t)) {
+                    ++t;
+                    jt = 0;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (m0 + u >= total) break;
+            float4* dst = J.lm_rows + ((size_t)(m0 + u) * J.lm_icap + k) * 3;
+            dst[0] = r[u][0];
+            dst[1] = r[u][1];
+            dst[2] = r[u][2];
         }
     }
-    J.lm_px[k] = make_double4(x[0], x[1], x[2], (double)j);
+    J.lm_px[k] = make_double4(x[0], x[1], x[2], (double)total);
 }
 
 __global__ __launch_bounds__(256) void k_lm_init(const Job* __restrict__ jobs, int round)
@@ -914,36 +933,60 @@ __global__ __launch_bounds__(256) void k_lm_init(const Job* __restrict__ jobs, i
 template <bool COV>
 __device__ __forceinline__ void lm_pass_item(const Job& J, int pos, int tile, int nI);
 
-// grid (waves per job, jobs), one wave per block; the waves of a job stride
-// over its (survivor, tile) items
-// Work plan of a round (one block): the (survivor, tile) items of every job
-// with LM, numbered job after job; plan[j] = first item of job j,
-// plan[njobs] = their total.
+// Work plan of a round (one block), over the jobs with LM still running:
+// plan[j] = first (survivor, tile) item of job j and plan[njobs] = their
+// total; splan = plan + kMaxBatchFrames + 1 likewise numbers the survivors.
 __global__ __launch_bounds__(1024) void k_lm_plan(const Job* __restrict__ jobs, int njobs, int round)
 {
-    __shared__ int s_x[1024];
+    __shared__ int s_x[1024], s_y[1024];
     int* plan = jobs[0].lm_plan;
-    int carry = 0;
+    int* splan = plan + kMaxBatchFrames + 1;
+    int carry = 0, scarry = 0;
     for (int base = 0; base < njobs; base += 1024) {
         const int j = base + (int)threadIdx.x;
-        int items = 0;
+        int items = 0, surv = 0;
         if (j < njobs) {
             const Job& J = jobs[j];
-            if (J.lm && !J.st->done) items = J.st->n_surv * (((round + 1) * J.eta + kLmTile - 1) / kLmTile);
+            if (J.lm && !J.st->done) {
+                surv = J.st->n_surv;
+                items = surv * (((round + 1) * J.eta + kLmTile - 1) / kLmTile);
+            }
         }
         s_x[threadIdx.x] = items;
+        s_y[threadIdx.x] = surv;
         __syncthreads();
-        for (int o = 1; o < 1024; o <<= 1) {           // inclusive scan
-            const int add = (int)threadIdx.x >= o ? s_x[threadIdx.x - o] : 0;
+        for (int o = 1; o < 1024; o <<= 1) {           // inclusive scans
+            const int ax = (int)threadIdx.x >= o ? s_x[threadIdx.x - o] : 0;
+            const int ay = (int)threadIdx.x >= o ? s_y[threadIdx.x - o] : 0;
             __syncthreads();
-            s_x[threadIdx.x] += add;
+            s_x[threadIdx.x] += ax;
+            s_y[threadIdx.x] += ay;
             __syncthreads();
         }
-        if (j < njobs) plan[j] = carry + s_x[threadIdx.x] - items;
+        if (j < njobs) {
+            plan[j] = carry + s_x[threadIdx.x] - items;
+            splan[j] = scarry + s_y[threadIdx.x] - surv;
+        }
         carry += s_x[1023];
+        scarry += s_y[1023];
         __syncthreads();
     }
-    if (threadIdx.x == 0) plan[njobs] = carry;
+    if (threadIdx.x == 0) {
+        plan[njobs] = carry;
+        splan[njobs] = scarry;
+    }
+}
+
+// index of the last job whose first plan entry is <= g (plan ascending)
+__device__ __forceinline__ int plan_job(const int* plan, int njobs, int g)
+{
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (plan[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
 }
 
 // 1-D grid of waves striding over the plan's items of all jobs, so that a
@@ -954,12 +997,7 @@ __global__ __launch_bounds__(64) void k_lm_pass(const Job* __restrict__ jobs, in
     const int* plan = jobs[0].lm_plan;
     const int total = plan[njobs];
     for (int gi = blockIdx.x; gi < total; gi += gridDim.x) {
-        int lo = 0, hi = njobs - 1;                    // last job whose first item is <= gi
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (plan[mid] <= gi) lo = mid;
-            else hi = mid - 1;
-        }
+        const int lo = plan_job(plan, njobs, gi);
         const Job& J = jobs[lo];
         const int nI = (round + 1) * J.eta;
         const int tiles = (nI + kLmTile - 1) / kLmTile;
@@ -1128,30 +1166,11 @@ __device__ void se3_exp(const double xi[6], double Rd[9], double td[3])
     for (int i = 0; i < 3; ++i) td[i] = V[3 * i] * xi[3] + V[3 * i + 1] * xi[4] + V[3 * i + 2] * xi[5];
 }
 
-// one wave per (survivor, job): lanes 0..27 add one value each over the
-// tiles in order, lane 0 decides.  it = -1 follows the pass at the starting
-// pose; it >= 0 follows iteration it's candidate pass.  The last iteration
-// writes the refined pose (FP64, and rounded into the hypothesis table)
-// and the energy.
-__global__ __launch_bounds__(64) void k_lm_step(const Job* __restrict__ jobs, int round, int it)
+// lane 0 of a survivor's step: accept or reject the evaluated candidate,
+// then the next damped step (or, after the last iteration, the outputs)
+__device__ __forceinline__ void lm_decide(const Job& J, int slot, double* S, bool go, int it, const double* s_v)
 {
 #pragma clang fp contract(off)
-    const Job& J = jobs[blockIdx.y];
-    const int pos = blockIdx.x;
-    if (!J.lm || J.st->done || pos >= J.st->n_surv || it >= J.lm_iters) return;
-    const int slot = J.surv[pos];
-    double* S = J.lm_state + (size_t)slot * kLmStateDoubles;
-    __shared__ double s_v[kLmVals];
-    const bool go = S[kLmGo] != 0.0;
-    if (go && threadIdx.x < kLmVals) {
-        const int tiles = ((round + 1) * J.eta + kLmTile - 1) / kLmTile;
-        const double* part = J.lm_part + (size_t)pos * J.lm_tiles * kLmVals + threadIdx.x;
-        double acc = 0.0;
-        for (int t = 0; t < tiles; ++t) acc += ldg(part + (size_t)t * kLmVals);
-        s_v[threadIdx.x] = acc;
-    }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
     double lambda = S[kLmLambda];
     if (go) {
         double v[kLmVals];
@@ -1200,6 +1219,41 @@ __global__ __launch_bounds__(64) void k_lm_step(const Job* __restrict__ jobs, in
         S[kLmGo] = 0.0;
     }
     S[kLmLambda] = lambda;
+}
+
+// One survivor's step: lanes 0..27 add one value each over the tiles in
+// order, lane 0 decides.  it = -1 follows the pass at the starting pose;
+// it >= 0 follows iteration it's candidate pass.  The last iteration writes
+// the refined pose (FP64, and rounded into the hypothesis table) and the
+// energy.
+__device__ __forceinline__ void lm_step_one(const Job& J, int pos, int round, int it, double* s_v)
+{
+#pragma clang fp contract(off)
+    const int slot = J.surv[pos];
+    double* S = J.lm_state + (size_t)slot * kLmStateDoubles;
+    const bool go = S[kLmGo] != 0.0;
+    if (go && threadIdx.x < kLmVals) {
+        const int tiles = ((round + 1) * J.eta + kLmTile - 1) / kLmTile;
+        s_v[threadIdx.x] = sum_in_order(J.lm_part + (size_t)pos * J.lm_tiles * kLmVals + threadIdx.x, kLmVals, tiles);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) lm_decide(J, slot, S, go, it, s_v);
+    __syncthreads();
+}
+
+// 1-D grid of waves striding over the survivors of every job with LM (the
+// round's survivor plan).
+__global__ __launch_bounds__(64) void k_lm_step(const Job* __restrict__ jobs, int njobs, int round, int it)
+{
+    __shared__ double s_v[kLmVals];
+    const int* splan = jobs[0].lm_plan + kMaxBatchFrames + 1;
+    const int total = splan[njobs];
+    for (int gi = blockIdx.x; gi < total; gi += gridDim.x) {
+        const int lo = plan_job(splan, njobs, gi);
+        const Job& J = jobs[lo];
+        if (it >= J.lm_iters) continue;
+        lm_step_one(J, gi - splan[lo], round, it, s_v);
+    }
 }
 
 // Adds the round's partial sums (tile order), ranks survivors by
@@ -1647,7 +1701,7 @@ hipError_t launch_score(const Job* jobs, int njobs, int round, int nptiles, int 
 hipError_t launch_lm(const Job* jobs, int njobs, int round, int maxSurv, int maxEta, int maxIters, hipStream_t st)
 {
     if (maxSurv < 1) return hipSuccess;
-    const dim3 thr((maxSurv + 255) / 256, njobs), per_surv(maxSurv, njobs);
+    const dim3 thr((maxSurv + 255) / 256, njobs);
     k_lm_draw<<<dim3((2 * maxEta + 255) / 256, njobs), dim3(256), 0, st>>>(jobs, round);
     RL_CHECK_LAUNCH();
     k_lm_init<<<thr, dim3(256), 0, st>>>(jobs, round);
@@ -1656,10 +1710,11 @@ hipError_t launch_lm(const Job* jobs, int njobs, int round, int maxSurv, int max
     RL_CHECK_LAUNCH();
     const long long tiles = ((round + 1) * (long long)maxEta + kLmTile - 1) / kLmTile;
     const int waves = (int)std::min<long long>((long long)maxSurv * tiles * njobs, 8192);
+    const int step_waves = (int)std::min<long long>((long long)maxSurv * njobs, 1024);
     for (int it = -1; it < maxIters; ++it) {
         k_lm_pass<<<dim3(waves), dim3(64), 0, st>>>(jobs, njobs, round);
         RL_CHECK_LAUNCH();
-        k_lm_step<<<per_surv, dim3(64), 0, st>>>(jobs, round, it);
+        k_lm_step<<<dim3(step_waves), dim3(64), 0, st>>>(jobs, njobs, round, it);
         RL_CHECK_LAUNCH();
     }
     return hipSuccess;

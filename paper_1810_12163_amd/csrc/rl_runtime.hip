@@ -159,7 +159,7 @@ FrameLayout frame_layout(int maxP, int N, int eta, int rounds, int TP, int rows_
     L.lm_state = c.take((size_t)N * kLmStateDoubles * 8);
     L.lm_part = c.take((size_t)N * L.lm_tiles * 28 * 8);
     L.Ie = c.take((size_t)rounds * eta * 4);
-    L.lm_plan = c.take((size_t)(kMaxBatchFrames + 1) * 4);
+    L.lm_plan = c.take((size_t)2 * (kMaxBatchFrames + 1) * 4);   // item plan, survivor plan
     L.lm_icap = rounds * eta;
     L.lm_px = c.take((size_t)rounds * eta * 32);
     L.lm_rows = c.take((size_t)rounds * eta * rows_per_pixel * 48);
