@@ -996,7 +996,12 @@ __global__ __launch_bounds__(64) void k_lm_pass(const Job* __restrict__ jobs, in
 #pragma clang fp contract(off)
     const int* plan = jobs[0].lm_plan;
     const int total = plan[njobs];
-    for (int gi = blockIdx.x; gi < total; gi += gridDim.x) {
+    // workgroup w runs on XCD w % 8 (gridDim.x is a multiple of 8): XCD e
+    // takes the e-th eighth of the items in order, so the mode rows of the
+    // few frames it works on stay in its L2 while their survivors read them
+    const int e = (int)blockIdx.x & 7, per = (int)gridDim.x >> 3;
+    const int chunk = (total + 7) >> 3, g1 = min(total, (e + 1) * chunk);
+    for (int gi = e * chunk + ((int)blockIdx.x >> 3); gi < g1; gi += per) {
         const int lo = plan_job(plan, njobs, gi);
         const Job& J = jobs[lo];
         const int nI = (round + 1) * J.eta;
@@ -1709,7 +1714,7 @@ hipError_t launch_lm(const Job* jobs, int njobs, int round, int maxSurv, int max
     k_lm_plan<<<dim3(1), dim3(1024), 0, st>>>(jobs, njobs, round);
     RL_CHECK_LAUNCH();
     const long long tiles = ((round + 1) * (long long)maxEta + kLmTile - 1) / kLmTile;
-    const int waves = (int)std::min<long long>((long long)maxSurv * tiles * njobs, 8192);
+    const int waves = (int)(std::min<long long>((long long)maxSurv * tiles * njobs, 8192) + 7) / 8 * 8;
     const int step_waves = (int)std::min<long long>((long long)maxSurv * njobs, 1024);
     for (int it = -1; it < maxIters; ++it) {
         k_lm_pass<<<dim3(waves), dim3(64), 0, st>>>(jobs, njobs, round);
