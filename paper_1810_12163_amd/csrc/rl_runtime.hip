@@ -647,7 +647,10 @@ RL_API rl_status relocaliser_create(const rl_params* p, const rl_node* host_node
         e = hipHostMalloc(reinterpret_cast<void**>(&r->model_host),
                           kModelHostBytes, hipHostMallocDefault);
     if (e != hipSuccess) {
+        for (void* hp : {(void*)r->job_host, (void*)r->res_host, (void*)r->model_host})
+            if (hp) (void)hipHostFree(hp);
         (void)hipEventDestroy(r->ev);
+        (void)hipEventDestroy(r->wev);
         delete r;
         return fail(RL_ENOMEM, "pinned host allocation failed: %s", hipGetErrorString(e));
     }
