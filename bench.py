@@ -578,6 +578,12 @@ def serve_leg(args, rl, dev, inputs):
               workloads.HYPOTHESES[camf[c][k][2].w]) for i, (c, k) in enumerate(picks)]
     adapts = [(rooms[cams[c]["room"]], camf[c][k][0], camf[c][k][1], camf[c][k][2]) for (c, k) in picks[:16]]
     mb = rl.Batch(64, 640, 480, 1024, 500, 10, 5, 50, device=dev)
+    from paper_1810_12163_amd import autotune
+    if args.schedule == "auto":
+        mb_sched, _ = autotune.tune_batch(mb, breqs, reps=3)
+    else:
+        mb_sched = tuple(int(v) for v in args.schedule.split(","))
+        mb.set_schedule(*mb_sched)
     for _ in range(2):
         mb.relocalise(breqs)
     torch.cuda.synchronize()
@@ -598,9 +604,10 @@ def serve_leg(args, rl, dev, inputs):
     mix = collections.Counter(camf[c][k][2].w for c, k in picks)
     out["mixed_batch"] = dict(relocs_per_s=64 * steps / el_r, ms_per_batch=el_r / steps * 1e3,
                               relocs_per_s_with_adapt=64 * steps / el, ms_per_step_with_adapt=el / steps * 1e3,
-                              rooms=8, widths={str(k): v for k, v in sorted(mix.items())}, adapts_per_step=16)
+                              rooms=8, widths={str(k): v for k, v in sorted(mix.items())}, adapts_per_step=16,
+                              schedule=list(mb_sched))
     mbo = out["mixed_batch"]
-    log(f"[bench] mixed batch (8 rooms, {dict(mix)} by width): {mbo['relocs_per_s']:.1f} reloc/s "
+    log(f"[bench] mixed batch (8 rooms, {dict(mix)} by width, schedule {mb_sched}): {mbo['relocs_per_s']:.1f} reloc/s "
         f"({mbo['ms_per_batch']:.2f} ms per 64-frame batch); with 16 adaptations per step "
         f"{mbo['relocs_per_s_with_adapt']:.1f} reloc/s ({mbo['ms_per_step_with_adapt']:.2f} ms)")
     warm = 1.0
