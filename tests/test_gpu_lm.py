@@ -125,11 +125,12 @@ def test_zero_iterations_and_the_per_call_switch(lm_rooms):
 
 
 def test_lm_batch_equals_plain(lm_rooms):
-    """A batch mixing LM rooms and a plain room gives exactly the plain path's
-    result for every request, with graph replay and direct launches."""
+    """A batch mixing LM rooms (10 iterations, and one with none) and a plain
+    room gives exactly the plain path's result for every request, with graph
+    replay and direct launches."""
     w, rooms = lm_rooms
     reqs = []
-    for i, kind in enumerate(["cov", "off", "l2", "cov", "off"]):
+    for i, kind in enumerate(["cov", "off", "l2", "zero", "cov", "off"]):
         q = w.queries[i % 3]
         d, c = dev(q)
         reqs.append((rooms[kind][1], d, c, q.K, 50 + i))
