@@ -134,6 +134,34 @@ __global__ __launch_bounds__(256) void k_traverse(const Job* __restrict__ jobs)
     if (threadIdx.x == 0) J.tile_count[blockIdx.x] = tot;
 }
 
+// A walk over M(u) in tree-major order (the order mode_row numbers it): the
+// row index of the current mode, advanced one mode at a time; the leaf's
+// base row is recomputed only when the walk moves on to another tree.
+// Rows fit 32 bits (T * 2^D * M <= 8 * 32768 * 64).
+struct ModeWalk {
+    uint4 lw;
+    uint2 nw;
+    int T, D, M, t, j, c;
+    uint32_t base;
+    __device__ __forceinline__ ModeWalk(const Job& J, uint4 lw_, uint2 nw_)
+        : lw(lw_), nw(nw_), T(J.T), D(J.D), M(J.M), t(0), j(0)
+    {
+        c = (int)count_of(nw, 0);
+        while (t < T - 1 && c == 0) c = (int)count_of(nw, ++t);
+        base = (((uint32_t)t << D) + leaf_of(lw, t)) * (uint32_t)M;
+    }
+    __device__ __forceinline__ uint32_t row() const { return base + (uint32_t)j; }
+    // called only while another mode of M(u) follows
+    __device__ __forceinline__ void next()
+    {
+        if (++j < c) return;
+        j = 0;
+        do c = (int)count_of(nw, ++t);
+        while (c == 0);
+        base = (((uint32_t)t << D) + leaf_of(lw, t)) * (uint32_t)M;
+    }
+};
+
 // Record of eligible pixel p at list position e: |M(u)| and the colour-check
 // bit of every mode of M(u), in M(u) order, from the modes' colour boxes.
 // The boxes are walked tree by tree, eight loaded ahead of their checks.
@@ -143,20 +171,13 @@ __device__ __forceinline__ void write_erec(const Job& J, int e, uint4 lw, uint2 
     const uint32_t x = box_colour(rgb);
     const int total = modes_total(nw, J.T);
     uint64_t w0 = 0, cur = 0;
-    int t = 0, j = 0;
-    while (t < J.T - 1 && count_of(nw, t) == 0) ++t;
+    ModeWalk mw(J, lw, nw);
     for (int m0 = 0; m0 < total; m0 += 8) {
         uint2 bx[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            bx[u] = ldg(J.cbox + (((size_t)t << J.D) + leaf_of(lw, t)) * (size_t)J.M + (size_t)j);
-            if (m0 + u + 1 < total) {           // the next mode of M(u)
-                ++j;
-                while (j >= (int)count_of(nw, t)) {
-                    ++t;
-                    j = 0;
-                }
-            }
+            bx[u] = ldg(J.cbox + mw.row());
+            if (m0 + u + 1 < total) mw.next();
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -606,13 +627,12 @@ __device__ __forceinline__ double nearest_q(const Job& J, uint4 lw, uint2 nw, do
 {
     const int total = modes_total(nw, J.T);
     double best = INFINITY;
-    int t = 0, j = 0;
-    while (t < J.T - 1 && count_of(nw, t) == 0) ++t;
+    ModeWalk mw(J, lw, nw);
     for (int m0 = 0; m0 < total; m0 += kScoreRows) {
         float4 ra[kScoreRows], rb[kScoreRows], rc[kScoreRows];
 #pragma unroll
         for (int u = 0; u < kScoreRows; ++u) {
-            const float4* row = J.modes + ((((size_t)t << J.D) + leaf_of(lw, t)) * (size_t)J.M + (size_t)j) * 4;
+            const float4* row = J.modes + (size_t)mw.row() * 4;
             ra[u] = ldg(row);
             if (COV) {
                 rb[u] = ldg(row + 1);
@@ -620,13 +640,7 @@ __device__ __forceinline__ double nearest_q(const Job& J, uint4 lw, uint2 nw, do
             } else {
                 rb[u] = rc[u] = ra[u];
             }
-            if (m0 + u + 1 < total) {           // the next row of M(u)
-                ++j;
-                while (j >= (int)count_of(nw, t)) {
-                    ++t;
-                    j = 0;
-                }
-            }
+            if (m0 + u + 1 < total) mw.next();
         }
 #pragma unroll
         for (int u = 0; u < kScoreRows; ++u)
@@ -883,23 +897,16 @@ __global__ __launch_bounds__(256) void k_lm_draw(const Job* __restrict__ jobs, i
     backproject(__uint_as_float(c0.y), p % J.w, p / J.w, J.fx, J.fy, J.cx, J.cy, x);
     const uint2 nw = make_uint2(c0.z, c0.w);
     const int total = modes_total(nw, J.T);
-    int t = 0, jt = 0;
-    while (t < J.T - 1 && count_of(nw, t) == 0) ++t;
+    ModeWalk mw(J, lw, nw);
     for (int m0 = 0; m0 < total; m0 += 4) {           // four rows loaded ahead of their stores
         float4 r[4][3];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const float4* row = J.modes + ((((size_t)t << J.D) + leaf_of(lw, t)) * (size_t)J.M + (size_t)jt) * 4;
+            const float4* row = J.modes + (size_t)mw.row() * 4;
             r[u][0] = ldg(row);
             r[u][1] = ldg(row + 1);
             r[u][2] = ldg(row + 2);
-            if (m0 + u + 1 < total) {
-                ++jt;
-                while (jt >= (int)count_of(nw, t)) {
-                    ++t;
-                    jt = 0;
-                }
-            }
+            if (m0 + u + 1 < total) mw.next();
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
