@@ -395,7 +395,11 @@ rl_status rl_batch_relocalise(rl_batch* b, const rl_request* reqs, int32_t n, rl
                               int32_t use_graph);
 
 /* Asynchronous form: results are written to dev_results (device, n records);
- * completion is ordered on the batch's stream. */
+ * completion is ordered on the batch's stream.  The requests are read during
+ * the call; calls may be queued back to back with different requests (each
+ * call's job table is kept until its upload has completed, and the batch's
+ * work space is reused in stream order).  Frame buffers and dev_results must
+ * stay valid until the batch has completed. */
 rl_status rl_batch_relocalise_async(rl_batch* b, const rl_request* reqs, int32_t n,
                                     rl_result* dev_results, int32_t use_graph);
 
@@ -429,6 +433,20 @@ rl_status rl_batch_set_timer(rl_batch* b, int32_t kernel, void* start_event, voi
  */
 rl_status relocaliser_set_schedule(rl_room* room, int32_t ipt, int32_t fast_waves);
 rl_status rl_batch_set_schedule(rl_batch* b, int32_t ipt, int32_t fast_waves);
+
+/*
+ * Degeneracy screen of the hypothesis search (result-invariant, on by
+ * default).  A hypothesis needs a non-degenerate Kabsch fit (Sec. 3.2.3): the
+ * exact test rejects a triplet whose cross-covariance has sigma_2 < 1e-4
+ * sigma_1.  With the screen on, the parallel search already skips triplets
+ * that are degenerate by a wide margin; with it off, every iteration passing
+ * checks 1-3 reaches the exact test, which rejects degenerate ones and
+ * continues the slot's scan from there.  Either way each slot keeps its first
+ * iteration passing every check, so results are identical; off only costs
+ * time (the exact test's scan is serial per slot).  Applies to later calls.
+ */
+rl_status relocaliser_set_degeneracy_screen(rl_room* room, int32_t on);
+rl_status rl_batch_set_degeneracy_screen(rl_batch* b, int32_t on);
 
 /* Thread-local message of the last error. */
 const char* rl_last_error(void);

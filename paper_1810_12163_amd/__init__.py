@@ -110,6 +110,7 @@ EXPORTS = [
     "rl_batch_relocalise", "rl_batch_relocalise_async", "rl_last_error", "rl_version",
     "relocaliser_set_timer", "rl_batch_set_timer", "relocaliser_relocalise_opts", "rl_plane_scores",
     "relocaliser_set_mode_schedule", "relocaliser_set_schedule", "rl_batch_set_schedule",
+    "relocaliser_set_degeneracy_screen", "rl_batch_set_degeneracy_screen",
     "rl_depth_scores", "rl_forest_generate", "relocaliser_save", "relocaliser_load",
 ]
 
@@ -161,6 +162,8 @@ def lib():
         L.relocaliser_save.argtypes = [P, ctypes.c_char_p]
         L.relocaliser_load.argtypes = [P, ctypes.c_char_p]
         L.rl_batch_set_schedule.argtypes = [P, I32, I32]
+        L.relocaliser_set_degeneracy_screen.argtypes = [P, I32]
+        L.rl_batch_set_degeneracy_screen.argtypes = [P, I32]
         L.rl_depth_scores.argtypes = [P, ctypes.POINTER(Frame), P, I32, P, I32, ctypes.c_float, ctypes.c_float,
                                       P, P, P]
         L.rl_last_error.restype = ctypes.c_char_p
@@ -313,6 +316,11 @@ class Room:
         _check(lib().relocaliser_set_schedule(self.handle, int(ipt), int(fast_waves)))
         self.schedule = (int(ipt), int(fast_waves))
 
+    def set_degeneracy_screen(self, on: bool):
+        """Result-invariant: with the screen off every triplet passing checks
+        1-3 reaches the exact degeneracy test (relocaliser_set_degeneracy_screen)."""
+        _check(lib().relocaliser_set_degeneracy_screen(self.handle, 1 if on else 0))
+
     def relocalise(self, depth, rgb, K, request_seed: int = 0, n_hypotheses: int = 0, n_cull: int = 0,
                    n_out: int = 0, final_refine: int = -1, pose_update: int = -1, max_iterations: int = 0,
                    eta: int = 0, use_covariance: int = -1, min_squared_distance: float = -1.0,
@@ -429,6 +437,10 @@ class Batch:
         (2, 4, 8) and all-rounds scoring width in waves (1, 2, 4)."""
         _check(lib().rl_batch_set_schedule(self.handle, int(ipt), int(fast_waves)))
         self.schedule = (int(ipt), int(fast_waves))
+
+    def set_degeneracy_screen(self, on: bool):
+        """Result-invariant degeneracy screen of the search (rl_batch_set_degeneracy_screen)."""
+        _check(lib().rl_batch_set_degeneracy_screen(self.handle, 1 if on else 0))
 
     def _requests(self, reqs):
         torch = _torch()

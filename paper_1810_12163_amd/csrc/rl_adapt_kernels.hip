@@ -2,19 +2,25 @@
 //
 // Adaptation (Sec. 3.2.2): grid pixels (4i, 4j), i, j >= 1, are routed
 // through every tree and their world points enter the reached leaves'
-// reservoirs by Algorithm R.  Arrivals at one leaf must be processed in the
+// reservoirs by Algorithm R.  Arrivals at one leaf are processed in the
 // canonical order (raster order within a frame), but each arrival's decision
 // depends only on its arrival number n (slot n-1 while n <= kappa, else a
 // Philox draw keyed by (tree, leaf, n)).  So the kernels compute every
-// arrival's n in parallel (rank of the pixel within its leaf's segment) and
-// resolve "later arrival wins" for slots hit twice in one frame, with no
-// per-slot atomics and a result independent of scheduling:
-//   k_ad_items   route, world point, per-leaf arrival counts
-//   k_ad_alloc   one segment per touched leaf
-//   k_ad_scatter items into their leaf segment (any order)
-//   k_ad_rank    rank by pixel index -> n -> slot or none
-//   k_ad_write   write unless a later arrival of the frame takes the same slot
-//   k_ad_cleanup clear the per-frame counters
+// arrival's n in parallel and resolve "the later arrival wins" for slots
+// drawn twice in one frame, with a result independent of scheduling, in time
+// linear in the arrivals (a leaf reached by every grid pixel costs no more
+// than spread-out leaves):
+//   k_ad_items    route, world point
+//   k_ad_sort     per (chunk of 1024 grid pixels, tree): stable sort by leaf
+//                 in LDS; each item's rank within its leaf's run of the
+//                 chunk; each run joins its leaf's list
+//   k_ad_runs     per run: the leaf's items in earlier chunks (its list has at
+//                 most one run per chunk)
+//   k_ad_claim    n = arrivals before the frame + earlier chunks + rank + 1;
+//                 the slot; the largest n drawing each (leaf, slot), by
+//                 atomicMax in an open-addressing table
+//   k_ad_write    the item holding that largest n writes its point
+//   k_ad_cleanup  arrival counters; leaf lists and table entries cleared
 // Mode finding (Really Quick Shift, one workgroup per dirty leaf): k_rqs.
 #include <hip/hip_runtime.h>
 
@@ -52,49 +58,101 @@ __global__ __launch_bounds__(256) void k_ad_items(AdaptArgs a)
     const uint32_t col = (uint32_t)c[0] | ((uint32_t)c[1] << 8) | ((uint32_t)c[2] << 16);
     a.item_pt[g] = make_float4(xw[0], xw[1], xw[2], __uint_as_float(col));
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
-        const size_t tl = ((size_t)t << a.D) + leaf[t];
-        a.item_leaf[(size_t)t * a.G + g] = (uint16_t)leaf[t];
-        const uint32_t old = atomicAdd(&a.cnt[tl], 1u);
-        a.item_flag[(size_t)t * a.G + g] = old == 0 ? 1 : 0;
+    for (int t = 0; t < T; ++t) a.item_leaf[(size_t)t * a.G + g] = (uint16_t)leaf[t];
+}
+
+// One block per (chunk, tree): the chunk's (leaf << 10 | position) keys are
+// sorted in LDS (bitonic; the position makes every key distinct, so equal
+// leaves stay in raster order), runs of equal leaves are delimited, and every
+// run heads a list entry of its leaf.  Positions of the sorted order index
+// the run arrays: run_cnt is the run's length at its head, 0 elsewhere.
+__global__ __launch_bounds__(kAdaptChunk) void k_ad_sort(AdaptArgs a)
+{
+    __shared__ uint32_t s_v[kAdaptChunk];
+    __shared__ int s_start[kAdaptChunk];
+    const int c = blockIdx.x, t = blockIdx.y, i = threadIdx.x;
+    const int g = c * kAdaptChunk + i;
+    const uint32_t leaf0 = g < a.G ? (uint32_t)a.item_leaf[(size_t)t * a.G + g] : (uint32_t)kLeafNone;
+    s_v[i] = (leaf0 << 10) | (uint32_t)i;
+    __syncthreads();
+    for (int k = 2; k <= kAdaptChunk; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const int p = i ^ j;
+            if (p > i) {
+                const uint32_t x = s_v[i], y = s_v[p];
+                if ((x > y) == ((i & k) == 0)) {
+                    s_v[i] = y;
+                    s_v[p] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const uint32_t v = s_v[i];
+    const uint32_t leaf = v >> 10;
+    const bool head = i == 0 || (s_v[i - 1] >> 10) != leaf;
+    const bool tail = i == kAdaptChunk - 1 || (s_v[i + 1] >> 10) != leaf;
+    s_start[i] = head ? i : 0;
+    __syncthreads();
+    for (int off = 1; off < kAdaptChunk; off <<= 1) {          // inclusive max-scan: run start
+        const int o = i >= off ? s_start[i - off] : 0;
+        __syncthreads();
+        s_start[i] = max(s_start[i], o);
+        __syncthreads();
+    }
+    const int start = s_start[i];
+    const uint32_t rbase = (uint32_t)t * (uint32_t)a.Gp + (uint32_t)c * kAdaptChunk;
+    const bool valid = leaf != (uint32_t)kLeafNone;
+    if (!head || !valid) a.run_cnt[rbase + i] = 0u;
+    if (!valid) return;
+    const size_t item = (size_t)t * a.G + (size_t)c * kAdaptChunk + (v & 1023u);
+    a.item_run[item] = rbase + (uint32_t)start;
+    a.item_lrank[item] = (uint16_t)(i - start);
+    if (tail) {
+        const uint32_t r = rbase + (uint32_t)start;
+        const uint32_t tl = ((uint32_t)t << a.D) + leaf;
+        a.run_cnt[r] = (uint32_t)(i - start + 1);
+        a.run_tl[r] = tl;
+        a.run_next[r] = atomicExch(&a.head[tl], r);
     }
 }
 
-__global__ __launch_bounds__(256) void k_ad_alloc(AdaptArgs a)
+// One thread per sorted position; each run adds up the runs of its leaf in
+// earlier chunks.  A leaf's list holds at most one run per chunk.
+__global__ __launch_bounds__(256) void k_ad_runs(AdaptArgs a, int n_chunks)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;       // i = t * G + g
+    const uint32_t r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= (uint32_t)a.T * (uint32_t)a.Gp) return;
+    const uint32_t cnt = a.run_cnt[r];
+    if (cnt == 0u) return;
+    const uint32_t tl = a.run_tl[r];
+    const uint32_t chunk = (r % (uint32_t)a.Gp) / kAdaptChunk;
+    uint32_t pre = 0, total = 0;
+    uint32_t q = a.head[tl];
+    for (int k = 0; k < n_chunks && q != kNone32; ++k) {
+        const uint32_t qc = a.run_cnt[q];
+        total += qc;
+        if ((q % (uint32_t)a.Gp) / kAdaptChunk < chunk) pre += qc;
+        q = a.run_next[q];
+    }
+    a.run_pre[r] = pre;
+    a.run_tot[r] = pre + cnt == total ? total : 0u;
+}
+
+__device__ __forceinline__ uint32_t slot_hash(uint32_t key, uint32_t mask)
+{
+    return (key * 0x9E3779B1u) & mask;
+}
+
+__global__ __launch_bounds__(256) void k_ad_claim(AdaptArgs a)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= a.T * a.G) return;
     const int t = i / a.G;
     const uint16_t lf = a.item_leaf[i];
-    if (lf == kLeafNone || !(a.item_flag[i] & 1)) return;
-    const size_t tl = ((size_t)t << a.D) + lf;
-    a.off[tl] = atomicAdd(&a.counters[1], a.cnt[tl]);
-}
-
-__global__ __launch_bounds__(256) void k_ad_scatter(AdaptArgs a)
-{
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= a.T * a.G) return;
-    const int t = i / a.G, g = i % a.G;
-    const uint16_t lf = a.item_leaf[i];
     if (lf == kLeafNone) return;
-    const size_t tl = ((size_t)t << a.D) + lf;
-    const uint32_t pos = a.off[tl] + atomicAdd(&a.cursor[tl], 1u);
-    a.seg[pos] = g;
-}
-
-__global__ __launch_bounds__(256) void k_ad_rank(AdaptArgs a)
-{
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= a.T * a.G) return;
-    const int t = i / a.G, g = i % a.G;
-    const uint16_t lf = a.item_leaf[i];
-    if (lf == kLeafNone) return;
-    const size_t tl = ((size_t)t << a.D) + lf;
-    const uint32_t c = a.cnt[tl], base = a.off[tl];
-    uint32_t rank = 0;
-    for (uint32_t k = 0; k < c; ++k) rank += a.seg[base + k] < g ? 1u : 0u;
-    const uint32_t n = a.seen[tl] + rank + 1u;
+    const uint32_t tl = ((uint32_t)t << a.D) + lf;
+    const uint32_t n = a.seen[tl] + a.run_pre[a.item_run[i]] + (uint32_t)a.item_lrank[i] + 1u;
     int slot;
     if (n <= (uint32_t)a.kappa) {
         slot = (int)n - 1;
@@ -105,27 +163,34 @@ __global__ __launch_bounds__(256) void k_ad_rank(AdaptArgs a)
     }
     a.item_n[i] = n;
     a.item_slot[i] = slot;
-    if (rank == c - 1) a.item_flag[i] |= 2;
+    if (slot < 0) return;
+    // the table holds at most T G keys in at least 2 T G entries, so a free
+    // or matching entry is found within hmask + 1 probes
+    const uint32_t key = (tl << 12) | (uint32_t)slot;
+    uint32_t h = slot_hash(key, a.hmask);
+    for (uint32_t probe = 0; probe <= a.hmask; ++probe) {
+        const uint32_t prev = atomicCAS(&a.hkey[h], kNone32, key);
+        if (prev == kNone32 || prev == key) {
+            atomicMax(&a.hval[h], n);
+            a.item_h[i] = h;
+            return;
+        }
+        h = (h + 1u) & a.hmask;
+    }
+    a.item_slot[i] = -1;                // unreachable: the table is never full
 }
 
 __global__ __launch_bounds__(256) void k_ad_write(AdaptArgs a)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= a.T * a.G) return;
-    const int t = i / a.G, g = i % a.G;
     const uint16_t lf = a.item_leaf[i];
     if (lf == kLeafNone) return;
-    const size_t tl = ((size_t)t << a.D) + lf;
     const int slot = a.item_slot[i];
-    const uint32_t n = a.item_n[i];
-    if (a.item_flag[i] & 2) a.seen[tl] = n;           // last arrival of the frame
     if (slot < 0) return;
-    const uint32_t c = a.cnt[tl], base = a.off[tl];
-    for (uint32_t k = 0; k < c; ++k) {
-        const int g2 = a.seg[base + k];
-        const size_t i2 = (size_t)t * a.G + g2;
-        if (a.item_slot[i2] == slot && a.item_n[i2] > n) return;   // overwritten later
-    }
+    if (a.hval[a.item_h[i]] != a.item_n[i]) return;          // a later arrival of the frame took the slot
+    const int t = i / a.G, g = i % a.G;
+    const size_t tl = ((size_t)t << a.D) + lf;
     a.reservoir[tl * (size_t)a.kappa + (size_t)slot] = a.item_pt[g];
     if (atomicExch(&a.dirty[tl], 1u) == 0u) {
         const uint32_t k = atomicAdd(&a.counters[0], 1u);
@@ -133,17 +198,23 @@ __global__ __launch_bounds__(256) void k_ad_write(AdaptArgs a)
     }
 }
 
+// One thread per sorted position (covering the items too): the leaf's
+// arrival counter from its last run, leaf lists and used table entries back
+// to their empty state.
 __global__ __launch_bounds__(256) void k_ad_cleanup(AdaptArgs a)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i == 0) a.counters[1] = 0u;
-    if (i >= a.T * a.G) return;
-    const int t = i / a.G;
-    const uint16_t lf = a.item_leaf[i];
-    if (lf == kLeafNone) return;
-    const size_t tl = ((size_t)t << a.D) + lf;
-    a.cnt[tl] = 0u;
-    a.cursor[tl] = 0u;
+    const uint32_t x = blockIdx.x * 256 + threadIdx.x;
+    if (x < (uint32_t)a.T * (uint32_t)a.G && a.item_leaf[x] != kLeafNone && a.item_slot[x] >= 0) {
+        const uint32_t h = a.item_h[x];
+        a.hkey[h] = kNone32;
+        a.hval[h] = 0u;
+    }
+    if (x < (uint32_t)a.T * (uint32_t)a.Gp && a.run_cnt[x] != 0u) {
+        const uint32_t tl = a.run_tl[x];
+        a.head[tl] = kNone32;
+        const uint32_t tot = a.run_tot[x];
+        if (tot) a.seen[tl] += tot;
+    }
 }
 
 // ------------------------------------------------------------------------
@@ -324,15 +395,17 @@ hipError_t launch_adapt(const AdaptArgs& a, hipStream_t st)
         default: return hipErrorInvalidValue;
     }
     RL_CHECK_LAUNCH();
-    k_ad_alloc<<<gT, blk, 0, st>>>(a);
+    const int n_chunks = a.Gp / kAdaptChunk;
+    const dim3 gR((a.T * a.Gp + 255) / 256);
+    k_ad_sort<<<dim3(n_chunks, a.T), dim3(kAdaptChunk), 0, st>>>(a);
     RL_CHECK_LAUNCH();
-    k_ad_scatter<<<gT, blk, 0, st>>>(a);
+    k_ad_runs<<<gR, blk, 0, st>>>(a, n_chunks);
     RL_CHECK_LAUNCH();
-    k_ad_rank<<<gT, blk, 0, st>>>(a);
+    k_ad_claim<<<gT, blk, 0, st>>>(a);
     RL_CHECK_LAUNCH();
     k_ad_write<<<gT, blk, 0, st>>>(a);
     RL_CHECK_LAUNCH();
-    k_ad_cleanup<<<gT, blk, 0, st>>>(a);
+    k_ad_cleanup<<<gR, blk, 0, st>>>(a);
     RL_CHECK_LAUNCH();
     return hipSuccess;
 }

@@ -71,7 +71,8 @@ struct Job {
     const float4* modes;      // [T][L][M] rows of 4 float4
     const uint8_t* nmodes;    // [T][L]
     const uint2* cbox;        // [T][L][M] colour box per mode row (see colour_box)
-    int T, D, M, pad0;
+    int T, D, M;
+    int screen;               // 1: the search rejects clearly degenerate triplets itself
     // frame
     const float* depth;
     const uint8_t* rgb;
@@ -134,18 +135,31 @@ struct AdaptArgs {
     uint32_t* seen;           // [T][L]
     uint32_t* dirty;          // [T][L]
     uint32_t* dirty_list;     // [T*L]
-    uint32_t* counters;       // [0] dirty count, [1] segment allocator
-    // scratch
-    uint16_t* item_leaf;      // [T][G]
-    float4* item_pt;          // [G]
-    uint8_t* item_flag;       // [T][G] bit0 first arrival at its leaf, bit1 last
+    uint32_t* counters;       // [0] dirty count
+    // scratch of one frame: items are (tree, grid pixel) arrivals; a run is
+    // the items of one leaf within one chunk of kAdaptChunk grid pixels
+    uint16_t* item_leaf;      // [T][G] leaf reached, kLeafNone for invalid depth
+    float4* item_pt;          // [G] world point and colour bits
+    uint32_t* item_run;       // [T][G] run (index into the run arrays)
+    uint16_t* item_lrank;     // [T][G] rank within its run (raster order)
     uint32_t* item_n;         // [T][G] arrival number n
-    int* item_slot;           // [T][G] reservoir slot written or -1
-    uint32_t* cnt;            // [T][L] arrivals this frame
-    uint32_t* cursor;         // [T][L]
-    uint32_t* off;            // [T][L] segment start
-    int* seg;                 // [T][G] items grouped by leaf
+    int* item_slot;           // [T][G] reservoir slot drawn, or -1
+    uint32_t* item_h;         // [T][G] hash-table entry of (leaf, slot)
+    uint32_t* run_cnt;        // [T][Gp] items of the run headed at this sorted position (0: no run)
+    uint32_t* run_tl;         // [T][Gp] leaf (t * L + leaf) of a run
+    uint32_t* run_next;       // [T][Gp] next run of the same leaf
+    uint32_t* run_pre;        // [T][Gp] the leaf's items in earlier chunks
+    uint32_t* run_tot;        // [T][Gp] the leaf's items this frame, on its last run (else 0)
+    // kept between frames in their cleared state
+    uint32_t* head;           // [T][L] first run of the leaf's list, kNone32 when empty
+    uint32_t* hkey;           // [hmask + 1] (leaf << 12 | slot), kNone32 when empty
+    uint32_t* hval;           // [hmask + 1] largest arrival number drawing that slot, 0 when empty
+    int Gp;                   // chunks * kAdaptChunk
+    uint32_t hmask;           // hash-table size - 1 (size a power of two >= 2 T G)
 };
+
+constexpr int kAdaptChunk = 1024;
+constexpr uint32_t kNone32 = 0xFFFFFFFFu;
 
 struct RqsArgs {
     const float4* reservoir;

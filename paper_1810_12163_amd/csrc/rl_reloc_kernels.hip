@@ -427,7 +427,7 @@ __device__ __forceinline__ bool hyp_stage_b(const Job& J, int n_elig, int slot, 
         for (int j = 0; j < 3; ++j)
             A[i * 3 + j] = (xc[0][i] - cc[i]) * (xw[0][j] - cw[j]) + (xc[1][i] - cc[i]) * (xw[1][j] - cw[j])
                          + (xc[2][i] - cc[i]) * (xw[2][j] - cw[j]);
-    if (!KABSCH) return !clearly_degenerate(A);
+    if (!KABSCH) return !(J.screen && clearly_degenerate(A));
     double R[9], t[3];
     if (!rigid_from_cov(A, cc, cw, R, t)) return false;
     for (int i = 0; i < 9; ++i) out->R[i] = (float)R[i];

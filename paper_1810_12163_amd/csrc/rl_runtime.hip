@@ -226,8 +226,19 @@ ModelLayout model_layout(int maxP, size_t base)
 }
 
 struct AdaptLayout {
-    size_t item_leaf, item_pt, item_flag, item_n, item_slot, cnt, cursor, off, seg, total;
+    size_t item_leaf, item_pt, item_run, item_lrank, item_n, item_slot, item_h, run_cnt, run_tl, run_next, run_pre,
+        run_tot, head, hkey, hval, total;
+    int Gp;
+    uint32_t hsize;
 };
+
+// adaptation table entries: a power of two >= 2 T G (at least 256)
+uint32_t adapt_table_size(int T, int G)
+{
+    uint32_t s = 256;
+    while (s < 2u * (uint32_t)T * (uint32_t)G) s <<= 1;
+    return s;
+}
 
 AdaptLayout adapt_layout(const rl_params& p, int G, size_t base)
 {
@@ -235,15 +246,24 @@ AdaptLayout adapt_layout(const rl_params& p, int G, size_t base)
     Carver c;
     c.cur = base;
     AdaptLayout A;
-    A.item_leaf = c.take(T * G * 2);
+    A.Gp = (G + kAdaptChunk - 1) / kAdaptChunk * kAdaptChunk;
+    A.hsize = adapt_table_size(p.n_trees, G);
+    const size_t TG = T * (size_t)G, TGp = T * (size_t)A.Gp;
+    A.item_leaf = c.take(TG * 2);
     A.item_pt = c.take((size_t)G * 16);
-    A.item_flag = c.take(T * G);
-    A.item_n = c.take(T * G * 4);
-    A.item_slot = c.take(T * G * 4);
-    A.cnt = c.take(T * L * 4);
-    A.cursor = c.take(T * L * 4);
-    A.off = c.take(T * L * 4);
-    A.seg = c.take(T * G * 4);
+    A.item_run = c.take(TG * 4);
+    A.item_lrank = c.take(TG * 2);
+    A.item_n = c.take(TG * 4);
+    A.item_slot = c.take(TG * 4);
+    A.item_h = c.take(TG * 4);
+    A.run_cnt = c.take(TGp * 4);
+    A.run_tl = c.take(TGp * 4);
+    A.run_next = c.take(TGp * 4);
+    A.run_pre = c.take(TGp * 4);
+    A.run_tot = c.take(TGp * 4);
+    A.head = c.take(T * L * 4);
+    A.hkey = c.take((size_t)A.hsize * 4);
+    A.hval = c.take((size_t)A.hsize * 4);
     A.total = c.cur - base;
     return A;
 }
@@ -296,6 +316,7 @@ struct Timer {
 struct Schedule {
     int ipt = 4;
     int fw = 1;
+    int screen = 1;   // the search rejects clearly degenerate triplets (else only the exact test does)
 };
 
 struct rl_room {
@@ -334,6 +355,11 @@ struct rl_room {
     std::map<std::vector<long long>, hipGraphExec_t> graphs;
 };
 
+// Pinned job tables of the batch path: a call fills one while the copies of
+// earlier calls may still be queued behind running batches, so they rotate,
+// and a table is refilled only after the event marking its last upload.
+constexpr int kJobRing = 4;
+
 struct rl_batch {
     rl_batch_params bp;
     char* ws;
@@ -344,7 +370,9 @@ struct rl_batch {
     std::vector<FrameLayout> slots;
     Schedule sched;
     Timer timer;
-    Job* job_host;
+    Job* job_ring[kJobRing];
+    hipEvent_t up_ev[kJobRing];
+    int ring;
     rl_result* res_host;
     std::map<std::vector<long long>, hipGraphExec_t> graphs;
 };
@@ -502,6 +530,7 @@ static Job make_job(const rl_room* r, char* scr, const FrameLayout& FL, const rl
     J.theta_col = r->p.max_colour_linf;
     J.TP = r->TP;
     J.fast_max = 64 * r->sched.fw;
+    J.screen = r->sched.screen;
     J.lm = r->p.pose_update;
     J.lm_iters = r->p.lm_iterations;
     J.min_sq_dist = r->p.min_squared_distance_between_sampled_modes;
@@ -666,8 +695,9 @@ RL_API rl_status relocaliser_create(const rl_params* p, const rl_node* host_node
     if (fs == RL_OK) fs = fill_u32(r->pers + r->PL.dirty, TL, 0, r->stream);
     if (fs == RL_OK) fs = fill_u32(r->pers + r->PL.counters, 64, 0, r->stream);
     if (fs == RL_OK) fs = fill_u8(r->pers + r->PL.nmodes, TL, 0, r->stream);
-    if (fs == RL_OK) fs = fill_u32(r->scr + r->AL.cnt, TL, 0, r->stream);
-    if (fs == RL_OK) fs = fill_u32(r->scr + r->AL.cursor, TL, 0, r->stream);
+    if (fs == RL_OK) fs = fill_u32(r->scr + r->AL.head, TL, kNone32, r->stream);
+    if (fs == RL_OK) fs = fill_u32(r->scr + r->AL.hkey, r->AL.hsize, kNone32, r->stream);
+    if (fs == RL_OK) fs = fill_u32(r->scr + r->AL.hval, r->AL.hsize, 0, r->stream);
     if (fs == RL_OK) fs = fill_u32(r->scr + r->FL.state, sizeof(JobState) / 4, 0, r->stream);
     if (fs != RL_OK) {
         relocaliser_destroy(r);
@@ -897,15 +927,25 @@ RL_API rl_status relocaliser_adapt(rl_room* r, const rl_frame* f, const float H[
     a.dirty = reinterpret_cast<uint32_t*>(r->pers + r->PL.dirty);
     a.dirty_list = reinterpret_cast<uint32_t*>(r->pers + r->PL.dirty_list);
     a.counters = reinterpret_cast<uint32_t*>(r->pers + r->PL.counters);
-    a.item_leaf = reinterpret_cast<uint16_t*>(r->scr + r->AL.item_leaf);
-    a.item_pt = reinterpret_cast<float4*>(r->scr + r->AL.item_pt);
-    a.item_flag = reinterpret_cast<uint8_t*>(r->scr + r->AL.item_flag);
-    a.item_n = reinterpret_cast<uint32_t*>(r->scr + r->AL.item_n);
-    a.item_slot = reinterpret_cast<int*>(r->scr + r->AL.item_slot);
-    a.cnt = reinterpret_cast<uint32_t*>(r->scr + r->AL.cnt);
-    a.cursor = reinterpret_cast<uint32_t*>(r->scr + r->AL.cursor);
-    a.off = reinterpret_cast<uint32_t*>(r->scr + r->AL.off);
-    a.seg = reinterpret_cast<int*>(r->scr + r->AL.seg);
+    char* sc = r->scr;
+    const AdaptLayout& A = r->AL;
+    a.item_leaf = reinterpret_cast<uint16_t*>(sc + A.item_leaf);
+    a.item_pt = reinterpret_cast<float4*>(sc + A.item_pt);
+    a.item_run = reinterpret_cast<uint32_t*>(sc + A.item_run);
+    a.item_lrank = reinterpret_cast<uint16_t*>(sc + A.item_lrank);
+    a.item_n = reinterpret_cast<uint32_t*>(sc + A.item_n);
+    a.item_slot = reinterpret_cast<int*>(sc + A.item_slot);
+    a.item_h = reinterpret_cast<uint32_t*>(sc + A.item_h);
+    a.run_cnt = reinterpret_cast<uint32_t*>(sc + A.run_cnt);
+    a.run_tl = reinterpret_cast<uint32_t*>(sc + A.run_tl);
+    a.run_next = reinterpret_cast<uint32_t*>(sc + A.run_next);
+    a.run_pre = reinterpret_cast<uint32_t*>(sc + A.run_pre);
+    a.run_tot = reinterpret_cast<uint32_t*>(sc + A.run_tot);
+    a.head = reinterpret_cast<uint32_t*>(sc + A.head);
+    a.hkey = reinterpret_cast<uint32_t*>(sc + A.hkey);
+    a.hval = reinterpret_cast<uint32_t*>(sc + A.hval);
+    a.Gp = (a.G + kAdaptChunk - 1) / kAdaptChunk * kAdaptChunk;
+    a.hmask = A.hsize - 1;
     const hipError_t e = launch_adapt(a, r->stream);
     if (e != hipSuccess) return hip_fail(e, "adapt launch");
     r->modes_stale = true;
@@ -1032,6 +1072,20 @@ RL_API rl_status rl_batch_set_schedule(rl_batch* b, int32_t ipt, int32_t fast_wa
     if (s != RL_OK) return s;
     b->sched.ipt = ipt;
     b->sched.fw = fast_waves;
+    return RL_OK;
+}
+
+RL_API rl_status relocaliser_set_degeneracy_screen(rl_room* r, int32_t on)
+{
+    if (!r) return fail(RL_EINVAL, "room is NULL");
+    r->sched.screen = on ? 1 : 0;
+    return RL_OK;
+}
+
+RL_API rl_status rl_batch_set_degeneracy_screen(rl_batch* b, int32_t on)
+{
+    if (!b) return fail(RL_EINVAL, "batch is NULL");
+    b->sched.screen = on ? 1 : 0;
     return RL_OK;
 }
 
@@ -1336,8 +1390,18 @@ RL_API rl_status rl_batch_create(const rl_batch_params* bp, void* ws, void* hip_
         b->slots.push_back(frame_layout(bp->max_width * bp->max_height, bp->max_hypotheses, bp->max_eta,
                                         batch_rounds(*bp), b->TP, bp->max_modes_per_pixel, base));
     }
+    b->ring = 0;
+    for (int k = 0; k < kJobRing; ++k) {
+        b->job_ring[k] = nullptr;
+        b->up_ev[k] = nullptr;
+    }
     hipError_t e = hipEventCreateWithFlags(&b->ev, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->job_host), (size_t)bp->max_frames * sizeof(Job), hipHostMallocDefault);
+    for (int k = 0; k < kJobRing && e == hipSuccess; ++k) {
+        e = hipEventCreateWithFlags(&b->up_ev[k], hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipHostMalloc(reinterpret_cast<void**>(&b->job_ring[k]), (size_t)bp->max_frames * sizeof(Job),
+                              hipHostMallocDefault);
+    }
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->res_host), (size_t)bp->max_frames * sizeof(rl_result), hipHostMallocDefault);
     if (e != hipSuccess) {
         rl_batch_destroy(b);
@@ -1351,7 +1415,13 @@ RL_API rl_status rl_batch_destroy(rl_batch* b)
 {
     if (!b) return RL_OK;
     for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
-    if (b->job_host) (void)hipHostFree(b->job_host);
+    for (int k = 0; k < kJobRing; ++k) {
+        if (b->up_ev[k]) {
+            (void)hipEventSynchronize(b->up_ev[k]);
+            (void)hipEventDestroy(b->up_ev[k]);
+        }
+        if (b->job_ring[k]) (void)hipHostFree(b->job_ring[k]);
+    }
     if (b->res_host) (void)hipHostFree(b->res_host);
     if (b->ev) (void)hipEventDestroy(b->ev);
     delete b;
@@ -1409,6 +1479,12 @@ RL_API rl_status rl_batch_relocalise_async(rl_batch* b, const rl_request* reqs, 
         rl_status s = room_read_begin(r, b->stream);
         if (s != RL_OK) return s;
     }
+    // the pinned table to fill: its previous upload (kJobRing calls ago) has
+    // to have been read by the copy engine first
+    const int slot_k = b->ring;
+    Job* job_host = b->job_ring[slot_k];
+    hipError_t e = hipEventSynchronize(b->up_ev[slot_k]);
+    if (e != hipSuccess) return hip_fail(e, "job table reuse");
     for (int i = 0; i < nq; ++i) {
         Job J;
         if (i < n) {
@@ -1425,13 +1501,16 @@ RL_API rl_status rl_batch_relocalise_async(rl_batch* b, const rl_request* reqs, 
         }
         J.TP = b->TP;
         J.fast_max = 64 * b->sched.fw;
+        J.screen = b->sched.screen;
         J.lm_plan = reinterpret_cast<int*>(b->ws + b->slots[0].lm_plan);   // one plan per launch
         J.trace = 0;
-        b->job_host[i] = J;
+        job_host[i] = J;
     }
     Job* jd = reinterpret_cast<Job*>(b->ws + b->jobs_off);
-    hipError_t e = hipMemcpyAsync(jd, b->job_host, (size_t)nq * sizeof(Job), hipMemcpyHostToDevice, b->stream);
+    e = hipMemcpyAsync(jd, job_host, (size_t)nq * sizeof(Job), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipEventRecord(b->up_ev[slot_k], b->stream);
     if (e != hipSuccess) return hip_fail(e, "job upload");
+    b->ring = (slot_k + 1) % kJobRing;
     const int nptiles = (maxEta + b->TP - 1) / b->TP;
     if (use_graph && b->stream == nullptr)
         return fail(RL_EINVAL, "graph replay needs a batch created on a non-default stream");

@@ -6,6 +6,8 @@ sampled triplets and accepted iterations bit-exact; mode counts exact and
 mode rows to float32 rounding; hypothesis poses to 1e-5; energies to 1e-4
 relative; the final pose to 1e-5 (and within 1 cm / 1 degree).  Stage parity
 feeds the GPU's own upstream arrays to the oracle."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -298,3 +300,139 @@ def test_generated_forest_room_matches_oracle(c1, tmp_path):
         fresh.load(tmp_path / "junk.bin")
     for r in (room, fresh, other):
         r.close()
+
+
+def _single_row_frame():
+    """A noise-free 160x120 frame of room 0 whose depth is kept on one image
+    row only, a row crossing exactly two surfaces (at least 50 pixels each).
+    Three pixels on one surface back-project to collinear camera points, so
+    their Kabsch fit is degenerate (Sec. 3.2.3); triplets spanning both
+    surfaces are not."""
+    w, h = 160, 120
+    room = scene.make_room(0)
+    rng = np.random.default_rng(123)
+    while True:
+        H = scene.random_pose(room, rng)
+        z, _, sid = scene.raycast(room, H, w, h)
+        for y in range(8, 113, 4):
+            ok = np.isfinite(z[y]) & (z[y] >= 0.5) & (z[y] <= 4.0)
+            ids, cnt = np.unique(sid[y], return_counts=True)
+            if ok.all() and len(ids) == 2 and cnt.min() >= 50:
+                depth, rgb = scene.render(room, H, w, h, seed=5, noise_sigma=0.0, dropout=0.0)
+                row = np.zeros_like(depth)
+                row[y] = depth[y]
+                return row, rgb, H, scene.intrinsics(w, h)
+
+
+def test_degenerate_triplets_skipped_as_the_oracle_does():
+    """A frame on which iterations pass checks 1-3 with collinear (degenerate)
+    triplets before the accepted one: the triplets, iterations and poses of
+    every slot equal the oracle's, with the search's degeneracy screen on and
+    with it off (then every such triplet reaches the exact test, which rejects
+    it and continues the slot's scan), and both give identical results."""
+    from tests.test_oracle_hypothesis_rejection import Frame, _key, evaluate
+    from rlsynth import forest, presets
+    p = presets.preset("c1")
+    nodes = forest.make_forest(1000, **presets.FOREST["c1"])
+    depth, rgb, H, K = _single_row_frame()
+    o = oracle.Oracle(p, nodes)
+    room = rl.Room(p, nodes, 160, 120)
+    d = torch.from_numpy(depth).cuda()
+    c = torch.from_numpy(rgb).cuda()
+    for _ in range(8):                        # eight identical adaptations: clusters of >= 5 points
+        o.adapt(depth, rgb, K, H)
+        room.adapt(d, c, K, H)
+    o.update_modes()
+    room.update_modes()
+    _, _, nm_g, modes_g = gpu_state(room, o.T, o.L, o.kappa, o.M)
+    bad, worst = compare_modes(nm_g, modes_g, o.nmodes, o.modes, o.M, range(o.T * o.L))
+    assert bad == 0 and worst < 1e-5, (bad, worst)
+    leaves = o.traverse(depth, rgb)
+    N = p["max_pose_candidates"]
+    seed = 0
+    ref = oracle.estimate_pose(depth, rgb, K, leaves, nm_g, modes_g.reshape(-1), o.T, o.D, o.M, p, seed)
+    v = ref["hyp_valid"].astype(bool)
+    assert v.sum() >= 32
+    # the construction's point: slots whose accepted iteration follows an
+    # iteration that passes checks 1-3 with a degenerate fit (numpy re-evaluation)
+    fr = Frame(depth, rgb, K, leaves, nm_g, modes_g.reshape(-1), o.T, o.D, o.M, ref["eligible"])
+    key = _key(p, seed)
+    degenerate_first = [s for s in np.flatnonzero(v)
+                        if any(evaluate(fr, key, int(s), it, p) == 4 for it in range(int(ref["hyp_iter"][s])))]
+    print(f"[degenerate] {int(v.sum())} valid slots, {len(degenerate_first)} accepted after a degenerate "
+          f"triplet passed checks 1-3", flush=True)
+    assert len(degenerate_first) >= 3
+    results = []
+    for screen in (True, False):
+        room.set_degeneracy_screen(screen)
+        res = room.relocalise(d, c, K, request_seed=seed)
+        hy = room.buffer_np(rl.BUF_HYPS, rl.HYP_DTYPE)[:N].copy()
+        np.testing.assert_array_equal(hy["valid"].astype(bool), v)
+        np.testing.assert_array_equal(hy["iter"][v], ref["hyp_iter"][v])
+        np.testing.assert_array_equal(hy["pix"][v], ref["hyp_pix"][v])
+        np.testing.assert_array_equal(hy["mode"][v], ref["hyp_mode"][v])
+        np.testing.assert_allclose(hy["R"][v], ref["hyp_pose"][v][:, :9], atol=1e-5)
+        np.testing.assert_allclose(hy["t"][v], ref["hyp_pose"][v][:, 9:], atol=1e-5)
+        assert res["status"] == ref["status"] == "ok" and res["winner"] == ref["winner"]
+        assert pose_diff(res["pose"], ref["pose"]) < 1e-5
+        results.append((res, hy))
+    (a, ha), (b, hb) = results
+    assert ha.tobytes() == hb.tobytes() and np.array_equal(a["pose"], b["pose"]) and a["energy"] == b["energy"]
+    room.set_degeneracy_screen(True)
+    room.close()
+
+
+def test_back_to_back_async_batches_equal_plain(c1):
+    """Two asynchronous batches with different requests queued back to back
+    (no host wait in between), then a third reusing the first's request list:
+    each result equals the plain path's."""
+    w, o, room = c1
+    frames = [(room, w.queries[i % 3], 300 + i) for i in range(5)]
+    devf = [(r, *dev(q), q.K, s) for (r, q, s) in frames]
+    plain = [r.relocalise(d, c, K, request_seed=s) for (r, d, c, K, s) in devf]
+    batch = rl.Batch(4, 160, 120, 64, 100, 6, 1, 5)
+    nbytes = ctypes.sizeof(rl.Result) * 4
+    outs = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(3)]
+    plans = [devf[:3], devf[3:], devf[:3][::-1]]
+    wants = [plain[:3], plain[3:], plain[:3][::-1]]
+    for reqs, out in zip(plans, outs):
+        batch.relocalise_async(reqs, out, use_graph=True)
+    batch.stream.synchronize()
+    for reqs, out, want in zip(plans, outs, wants):
+        got = rl.Batch.decode(out.cpu().numpy(), len(reqs))
+        for a, b in zip(got, want):
+            assert a["status"] == b["status"] and a["winner"] == b["winner"]
+            assert np.array_equal(a["pose"], b["pose"]) and a["energy"] == b["energy"]
+    batch.close()
+
+
+def test_adapt_every_grid_pixel_into_one_leaf_bit_exact():
+    """Adaptation when every grid pixel of a 640x480 frame reaches the same
+    leaf of each tree (constant depth and colour: every feature is 0): 18,921
+    arrivals per leaf and frame, spread over 19 chunks, most of them Algorithm
+    R replacements with several arrivals of a frame drawing the same slot
+    (the later one wins).  Three frames at different poses; arrival counters
+    and every reservoir entry equal the oracle's bit for bit."""
+    from rlsynth import forest, presets
+    p = dict(presets.preset("c2"), reservoir_capacity=64)
+    nodes = forest.make_forest(1000, **presets.FOREST["c2"])
+    o = oracle.Oracle(p, nodes)
+    room = rl.Room(p, nodes, 640, 480)
+    K = scene.intrinsics(640, 480)
+    depth = np.full((480, 640), 2.0, np.float32)
+    rgb = np.full((480, 640, 3), 90, np.uint8)
+    rng = np.random.default_rng(17)
+    geom = scene.make_room(0)
+    for k in range(3):
+        H = scene.random_pose(geom, rng)
+        o.adapt(depth, rgb, K, H)
+        room.adapt(torch.from_numpy(depth).cuda(), torch.from_numpy(rgb).cuda(), K, H)
+    seen = room.buffer_np(rl.BUF_SEEN, np.uint32).copy()
+    np.testing.assert_array_equal(seen, o.seen)
+    assert int(seen.max()) == 3 * 159 * 119 and int((seen > 0).sum()) == o.T
+    res = room.buffer_np(rl.BUF_RESERVOIR, np.float32).reshape(o.T * o.L, o.kappa, 4)
+    bad, total = reservoir_mismatches(seen, res, o.reservoir, o.kappa)
+    assert bad == 0 and total == o.T * o.kappa, (bad, total)
+    dirty = room.buffer_np(rl.BUF_DIRTY, np.uint32)
+    np.testing.assert_array_equal(dirty != 0, o.dirty != 0)
+    room.close()

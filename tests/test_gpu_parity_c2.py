@@ -195,12 +195,26 @@ def test_c3_wide_stage_keeps_16_and_model_score_matches(c2, c3_room):
     p3, r3 = c3_room
     q = w.queries[1]
     d, c = dev(q)
+    r3.set_trace(True)
     res = r3.relocalise(d, c, q.K, request_seed=22, n_hypotheses=4096, n_cull=4096, n_out=16, final_refine=0)
     ref = _stage_ref(r3, q, dict(p3, final_refine=0), 22, o.T, o.D, o.M, w.nodes, p3["ref_width"])
     print(f"[c3 stage c] valid {res['n_valid']}, rounds {res['rounds']} (oracle {ref['rounds']}), "
           f"kept {res['n_out']}", flush=True)
     assert res["n_valid"] == int(ref["hyp_valid"].sum()) > 0
     assert res["rounds"] == ref["rounds"] and res["n_out"] == len(ref["out_slots"]) >= min(2, res["n_valid"])
+    # every round, including those entered by more than 64 survivors (one
+    # scoring launch and one selection per round) and the rounds scored at once
+    N = 4096
+    ts = r3.buffer_np(rl.BUF_TRACE_SLOTS, np.int32).reshape(-1, N)
+    te = r3.buffer_np(rl.BUF_TRACE_ENERGY, np.float64).reshape(-1, N)
+    entering = [int(ref["hyp_valid"].sum())] + [len(s) for s in ref["round_slots"][:-1]]
+    assert entering[0] > 64, entering          # the per-round path runs
+    for r in range(ref["rounds"]):
+        k = len(ref["round_slots"][r])
+        np.testing.assert_array_equal(ts[r, :k], ref["round_slots"][r])
+        np.testing.assert_allclose(te[r, :k], ref["round_energy"][r], rtol=1e-4)
+    r3.set_trace(False)
+    print(f"[c3 stage c] survivors entering each round {entering}", flush=True)
     slots, poses = r3.survivors(res["n_out"])
     np.testing.assert_array_equal(slots, ref["out_slots"])
     S = oracle.surfaces_of(w.room)
@@ -447,3 +461,170 @@ def test_c2_colour_check_bits_equal_the_float_test(c2):
         m0 = m0 + cnt[:, t]
     print(f"[colour bits] {n_el} entries, {checked} (pixel, mode) checks", flush=True)
     assert checked > 1_000_000
+
+
+# ---------------------------------------------------------------------------
+# Table 8's Forest row of the Fast / Intermediate / Slow relocalisers
+# (reservoirs of 2048, up to 50 modes per leaf, link distance 0.2 m, clusters
+# of at least 5 points): five trees give up to 250 modes per pixel, so every
+# eligible-list record spans several 64-bit words and the tree-major walks of
+# M(u) cross many tree boundaries.
+
+@pytest.fixture(scope="module")
+def forest_row(c2):
+    from rlsynth import presets
+    w, _, _ = c2
+    p = presets.preset("fast")
+    print("\n[forest row] adapting a kappa 2048 / M 50 room from the 50 frames", flush=True)
+    o = oracle.Oracle(p, w.nodes)
+    room = rl.Room(p, w.nodes, 640, 480)
+    for f in w.adapt:
+        o.adapt(f.depth, f.rgb, f.K, f.pose)
+        d, c = dev(f)
+        room.adapt(d, c, f.K, f.pose)
+    room.update_modes()
+    torch.cuda.synchronize()
+    yield p, o, room
+    room.close()
+
+
+def test_forest_row_reservoirs_and_modes(forest_row):
+    p, o, room = forest_row
+    seen = room.buffer_np(rl.BUF_SEEN, np.uint32).copy()
+    np.testing.assert_array_equal(seen, o.seen)
+    res = room.buffer_np(rl.BUF_RESERVOIR, np.float32).reshape(o.T * o.L, o.kappa, 4)
+    bad, total = reservoir_mismatches(seen, res, o.reservoir, o.kappa)
+    assert bad == 0 and total > 2_000_000, (bad, total)
+    del res
+    nm_g = room.buffer_np(rl.BUF_NMODES, np.uint8).copy()
+    modes_g = room.buffer_np(rl.BUF_MODES, np.float32).reshape(o.T * o.L, o.M, 16)
+    order = np.argsort(-seen.astype(np.int64), kind="stable")
+    rng = np.random.default_rng(1)
+    sample = np.unique(np.concatenate([order[:60], rng.choice(np.flatnonzero(seen > 0), 400, replace=False)]))
+    nm_o = np.zeros_like(nm_g)
+    modes_o = np.zeros((o.T * o.L, o.M, 16), np.float32)
+    for tl in sample:
+        t, leaf = divmod(int(tl), o.L)
+        rows, _ = oracle.rqs_leaf(o.reservoir_of(t, leaf), p["clusterer_sigma"], p["clusterer_tau"],
+                                  p["min_cluster_size"], o.M, p["cov_regulariser"])
+        nm_o[tl] = rows.shape[0]
+        modes_o[tl, :rows.shape[0]] = rows
+    assert int(nm_o[sample].max()) == o.M                 # full leaves reach the 50-mode cap
+    bad, worst = compare_modes(nm_g, modes_g, nm_o, modes_o.reshape(-1), o.M, sample)
+    assert bad == 0 and worst < 1e-5, (bad, worst)
+
+
+def _colour_bits_equal_float_test(room, q, o, theta, el, rec):
+    """Every colour-check bit of every eligible entry (all record words)
+    against the float32 L-infinity test; returns (#checks, |M(u)| per entry)."""
+    P = q.depth.size
+    leaves = room.buffer_np(rl.BUF_LEAVES, np.uint16).reshape(-1, 8)[:P, :o.T].astype(np.int64)
+    nmodes = room.buffer_np(rl.BUF_NMODES, np.uint8).reshape(o.T, o.L)
+    modes = room.buffer_np(rl.BUF_MODES, np.float32).reshape(o.T, o.L, o.M, 16)
+    lv = leaves[el]
+    cnt = nmodes[np.arange(o.T)[None, :], lv].astype(np.int64)
+    total = cnt.sum(1)
+    np.testing.assert_array_equal((rec[:, 0] & np.uint64(0xFF)).astype(np.int64), total)
+    px = q.rgb.reshape(-1, 3)[el].astype(np.float32)
+    rows = np.arange(len(el))
+    checked = 0
+    m0 = np.zeros(len(el), np.int64)
+    for t in range(o.T):
+        for j in range(o.M):
+            has = j < cnt[:, t]
+            if not has.any():
+                continue
+            col = modes[t, lv[:, t], j, 10:13]
+            ok = ~np.any(np.abs(px - col) > np.float32(theta), axis=1)
+            m = m0 + j
+            word = np.where(m < 56, 0, 1 + (m - 56) // 64)
+            shift = np.where(m < 56, 8 + m, (m - 56) % 64).astype(np.uint64)
+            bit = ((rec[rows, word] >> shift) & np.uint64(1)).astype(bool)
+            np.testing.assert_array_equal(bit[has], ok[has], err_msg=f"tree {t} mode {j}")
+            checked += int(has.sum())
+        m0 = m0 + cnt[:, t]
+    return checked, total
+
+
+@pytest.mark.parametrize("stage", ["fast", "intermediate"])
+def test_forest_row_multiword_records_and_rounds(c2, forest_row, stage):
+    """640x480 frame on the Forest-row room with Table 8's RANSAC settings of
+    the Fast (no LM) and Intermediate (LM, Euclidean) relocalisers, except 6000
+    generation iterations (with about 200 modes per pixel, 500-1000 iterations
+    leave only a handful of the 2048 slots valid): leaves, eligible list,
+    every word of every eligible record, every hypothesis, every round's
+    survivors and energies, the LM-refined poses and the result equal the
+    oracle's."""
+    from rlsynth import presets
+    w, _, _ = c2
+    p, o, room = forest_row
+    sp = presets.preset(stage)
+    q = w.queries[0]
+    d, c = dev(q)
+    seed = 31 if stage == "fast" else 32
+    kw = dict(n_hypotheses=sp["max_pose_candidates"], n_cull=sp["max_pose_candidates_after_cull"],
+              n_out=sp["max_relocalisations_to_output"], final_refine=0, pose_update=sp["pose_update"],
+              max_iterations=6000, eta=sp["ransac_inliers_per_iteration"],
+              use_covariance=sp["use_prediction_covariance"],
+              min_squared_distance=sp["min_squared_distance_between_sampled_modes"],
+              max_translation_error=sp["max_translation_error_for_correct_pose"])
+    room.set_trace(True)
+    res = room.relocalise(d, c, q.K, request_seed=seed, **kw)
+    P = q.depth.size
+    leaves_g = room.buffer_np(rl.BUF_LEAVES, np.uint16).reshape(-1, 8)[:P, :o.T].copy()
+    np.testing.assert_array_equal(leaves_g, o.traverse(q.depth, q.rgb))
+    nm_g = room.buffer_np(rl.BUF_NMODES, np.uint8).copy()
+    modes_g = room.buffer_np(rl.BUF_MODES, np.float32).copy()
+    params = dict(p, max_pose_candidates=kw["n_hypotheses"], max_pose_candidates_after_cull=kw["n_cull"],
+                  max_relocalisations_to_output=kw["n_out"], final_refine=0, pose_update=kw["pose_update"],
+                  max_candidate_generation_iterations=kw["max_iterations"], ransac_inliers_per_iteration=kw["eta"],
+                  use_prediction_covariance=kw["use_covariance"],
+                  min_squared_distance_between_sampled_modes=float(np.float32(kw["min_squared_distance"])),
+                  max_translation_error_for_correct_pose=float(np.float32(kw["max_translation_error"])))
+    ref = oracle.estimate_pose(q.depth, q.rgb, q.K, leaves_g, nm_g, modes_g, o.T, o.D, o.M, params, seed)
+    n_el = res["n_eligible"]
+    assert n_el == len(ref["eligible"]) > 100_000
+    el = room.buffer_np(rl.BUF_ELIGIBLE, np.int32)[:n_el].copy()
+    np.testing.assert_array_equal(el, ref["eligible"])
+    ew = 1 + (o.T * o.M - 56 + 63) // 64
+    rec = room.buffer_np(rl.BUF_EREC, np.uint64).reshape(-1, ew)[:n_el].copy()
+    checked, total = _colour_bits_equal_float_test(room, q, o, p["max_colour_linf"], el, rec)
+    print(f"[forest row {stage}] {n_el} entries, |M(u)| max {total.max()}, > 56 on {(total > 56).sum()}, "
+          f"> 184 on {(total > 184).sum()}; {checked} colour bits", flush=True)
+    assert (total > 56).sum() > 10_000 and (total > 184).sum() > 1000   # second and fourth words in use
+    N = kw["n_hypotheses"]
+    hy = room.buffer_np(rl.BUF_HYPS, rl.HYP_DTYPE)[:N]
+    v = ref["hyp_valid"].astype(bool)
+    np.testing.assert_array_equal(hy["valid"].astype(bool), v)
+    assert v.sum() >= 8
+    np.testing.assert_array_equal(hy["iter"][v], ref["hyp_iter"][v])
+    np.testing.assert_array_equal(hy["pix"][v], ref["hyp_pix"][v])
+    np.testing.assert_array_equal(hy["mode"][v], ref["hyp_mode"][v])
+    assert int(hy["mode"][v].max()) >= 56                 # triplet modes beyond the first record word
+    # with LM the survivors of the first round hold their refined poses
+    # (compared below); the others keep the Kabsch pose
+    kab = v.copy()
+    if kw["pose_update"]:
+        kab[ref["round_slots"][0]] = False
+    np.testing.assert_allclose(hy["R"][kab], ref["hyp_pose"][kab][:, :9], atol=1e-5)
+    np.testing.assert_allclose(hy["t"][kab], ref["hyp_pose"][kab][:, 9:], atol=1e-5)
+    assert res["rounds"] == ref["rounds"] >= 2
+    eta = kw["eta"]
+    np.testing.assert_array_equal(room.buffer_np(rl.BUF_ILIST, np.int32)[:ref["rounds"] * eta], ref["I"])
+    ts = room.buffer_np(rl.BUF_TRACE_SLOTS, np.int32).reshape(-1, N)
+    te = room.buffer_np(rl.BUF_TRACE_ENERGY, np.float64).reshape(-1, N)
+    for r in range(ref["rounds"]):
+        k = len(ref["round_slots"][r])
+        np.testing.assert_array_equal(ts[r, :k], ref["round_slots"][r])
+        np.testing.assert_allclose(te[r, :k], ref["round_energy"][r], rtol=1e-4)
+    if kw["pose_update"]:
+        P64 = room.buffer_np(rl.BUF_POSE64, np.float64).reshape(-1, 12)
+        outs = ref["round_slots"][-1]
+        assert float(np.abs(P64[outs] - ref["refined_pose64"][outs]).max()) < 1e-5
+    assert res["status"] == ref["status"] == "ok" and res["winner"] == ref["winner"]
+    assert pose_diff(res["pose"], ref["pose"]) < 1e-5
+    assert abs(res["energy"] - ref["energy"]) <= 1e-4 * abs(ref["energy"])
+    dt, dr = scene.pose_error(res["pose"].astype(np.float64), q.pose)
+    print(f"[forest row {stage}] valid {int(v.sum())}, rounds {res['rounds']}, error {dt * 100:.2f} cm "
+          f"{dr:.2f} deg", flush=True)
+    room.set_trace(False)
