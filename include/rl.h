@@ -305,6 +305,27 @@ rl_status rl_depth_scores(rl_room* room, const rl_frame* frame, const rl_surface
                           float max_depth, double* host_scores, double* host_mu, int64_t* host_counts);
 
 /*
+ * rl_depth_scores without caller work space, for callers that cannot allocate
+ * device memory (no room, no workspace argument).  Same computation, limits
+ * on n_surfaces / n_poses / depths, outputs and errors as rl_depth_scores,
+ * for a frame of at most 2^21 pixels (RL_EINVAL beyond; also for sizes that
+ * are not multiples of 4 or below 8x8, and NULL depth or rgb pointers; rgb is
+ * not read).  The work space is a fixed device array of this library (about
+ * 2.01 MiB per device, held until the process ends); it allocates nothing
+ * (no hipMalloc / hipFree, no allocating library call).  hip_stream: the
+ * stream the copies and kernels run on (NULL = default stream), ordered after
+ * the caller's earlier work on it.  Synchronous.  Every call on a device
+ * shares that device's array, which keeps the last call's contents: calls
+ * from threads of one process are serialised per device by a lock held for
+ * the whole call, so they never overlap.  RL_EDEVICE on devices numbered 64
+ * or above.
+ */
+rl_status rl_depth_scores_noalloc(const rl_frame* frame, const rl_surface* host_surfaces, int32_t n_surfaces,
+                                  const float* host_poses, int32_t n_poses, float min_depth, float max_depth,
+                                  void* hip_stream, double* host_scores, double* host_mu,
+                                  int64_t* host_counts);
+
+/*
  * Introspection for tests and tools: byte offset and size of an internal
  * array inside the caller's persistent (*region = 0) or scratch (*region = 1)
  * buffer.  which: see RL_BUF_* below.  Contents are valid after the stream

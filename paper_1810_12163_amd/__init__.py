@@ -112,6 +112,7 @@ EXPORTS = [
     "relocaliser_set_mode_schedule", "relocaliser_set_schedule", "rl_batch_set_schedule",
     "relocaliser_set_degeneracy_screen", "rl_batch_set_degeneracy_screen",
     "rl_depth_scores", "rl_forest_generate", "relocaliser_save", "relocaliser_load",
+    "rl_depth_scores_noalloc",
 ]
 
 # launch schedules the library accepts (iterations per thread, fast waves)
@@ -166,6 +167,8 @@ def lib():
         L.rl_batch_set_degeneracy_screen.argtypes = [P, I32]
         L.rl_depth_scores.argtypes = [P, ctypes.POINTER(Frame), P, I32, P, I32, ctypes.c_float, ctypes.c_float,
                                       P, P, P]
+        L.rl_depth_scores_noalloc.argtypes = [ctypes.POINTER(Frame), P, I32, P, I32, ctypes.c_float,
+                                              ctypes.c_float, P, P, P, P]
         L.rl_last_error.restype = ctypes.c_char_p
         L.rl_version.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -483,6 +486,25 @@ class Batch:
             r = Result.from_buffer_copy(raw[i * ctypes.sizeof(Result):(i + 1) * ctypes.sizeof(Result)].tobytes())
             out.append(_result(r))
         return out
+
+
+def depth_scores_noalloc(depth, rgb, K, surfaces: np.ndarray, poses12: np.ndarray, min_depth: float = 0.5,
+                         max_depth: float = 4.0):
+    """Depth-raycast scores of Eq. 6-7 per pose, (s, mu, counts (n, 2)), with the
+    library's fixed device work space (no room, nothing allocated); runs on
+    torch's current stream."""
+    torch = _torch()
+    f = _frame(depth, rgb, K)
+    S = np.ascontiguousarray(surfaces, dtype=np.float32).reshape(-1, 16)
+    P = np.ascontiguousarray(poses12, dtype=np.float32).reshape(-1, 12)
+    s = np.zeros(P.shape[0], dtype=np.float64)
+    mu = np.zeros(P.shape[0], dtype=np.float64)
+    cnt = np.zeros((P.shape[0], 2), dtype=np.int64)
+    st = torch.cuda.current_stream(depth.device).cuda_stream
+    _check(lib().rl_depth_scores_noalloc(ctypes.byref(f), S.ctypes.data, S.shape[0], P.ctypes.data, P.shape[0],
+                                         float(min_depth), float(max_depth), st, s.ctypes.data, mu.ctypes.data,
+                                         cnt.ctypes.data))
+    return s, mu, cnt
 
 
 def rounds_for(N: int, n_cull: int, n_out: int) -> int:

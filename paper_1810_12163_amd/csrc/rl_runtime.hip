@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -1294,6 +1295,108 @@ RL_API rl_status rl_depth_scores(rl_room* r, const rl_frame* f, const rl_surface
         if (counts) {
             counts[2 * k] = c[2 * k];
             counts[2 * k + 1] = c[2 * k + 1];
+        }
+    }
+    return RL_OK;
+}
+
+// ------------------------------------------------------------------------
+// Depth-raycast scores without caller work space (for callers that cannot
+// allocate): the surfaces, poses, per-tile partial sums and counts and the
+// outputs live in one fixed device array of this library, whose address on
+// each device is looked up once, with that device current.
+
+namespace {
+
+constexpr size_t align256c(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr int kStaticScoreMaxPixels = 1 << 21;     // 2048 tiles of 1024 pixels
+constexpr size_t kStaticScoreTiles = ((size_t)kStaticScoreMaxPixels + 1023) / 1024;
+constexpr size_t kSsSurfaces = 0;
+constexpr size_t kSsPoses = align256c(kSsSurfaces + (size_t)kMaxModelSurfaces * 64);
+constexpr size_t kSsPartial = align256c(kSsPoses + (size_t)kMaxModelPoses * 48);
+constexpr size_t kSsCnt = align256c(kSsPartial + kStaticScoreTiles * kMaxModelPoses * 8);
+constexpr size_t kSsOut = align256c(kSsCnt + kStaticScoreTiles * kMaxModelPoses * 2 * 4);
+constexpr size_t kSsCounts = align256c(kSsOut + (size_t)kMaxModelPoses * 2 * 8);
+constexpr size_t kStaticScoreBytes = align256c(kSsCounts + (size_t)kMaxModelPoses * 2 * 8);
+constexpr int kStaticScoreDevices = 64;
+
+// Host code never passes this name to a kernel or a copy: the address it
+// stands for on a device comes from hipGetSymbolAddress (g_score_scratch_ptr).
+static __device__ __align__(256) unsigned char score_scratch[kStaticScoreBytes];
+
+std::mutex g_score_scratch_mu[kStaticScoreDevices];
+std::mutex g_score_scratch_init_mu;
+void* g_score_scratch_ptr[kStaticScoreDevices] = {};
+
+// The current device's copy of score_scratch (looked up on its first use).
+rl_status score_scratch_address(int* dev_out, char** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kStaticScoreDevices)
+        return fail(RL_EDEVICE, "device %d is beyond the %d devices the fixed work space supports", dev,
+                    kStaticScoreDevices);
+    std::lock_guard<std::mutex> lk(g_score_scratch_init_mu);
+    if (!g_score_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(score_scratch));
+        if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "work space lookup");
+        g_score_scratch_ptr[dev] = p;
+    }
+    *dev_out = dev;
+    *out = static_cast<char*>(g_score_scratch_ptr[dev]);
+    return RL_OK;
+}
+
+}  // namespace
+
+RL_API rl_status rl_depth_scores_noalloc(const rl_frame* f, const rl_surface* surfaces, int32_t n_surf,
+                                         const float* poses, int32_t n_poses, float min_depth, float max_depth,
+                                         void* hip_stream, double* scores, double* mu, int64_t* counts)
+{
+    if (!f || !surfaces || !poses || !scores) return fail(RL_EINVAL, "NULL argument");
+    if ((long long)f->width * f->height > kStaticScoreMaxPixels)
+        return fail(RL_EINVAL, "frame %dx%d exceeds the %d pixels of the fixed work space", f->width, f->height,
+                    kStaticScoreMaxPixels);
+    rl_status s = validate_frame(f, 1 << 30, 1 << 30);
+    if (s != RL_OK) return s;
+    if (n_surf < 1 || n_surf > kMaxModelSurfaces) return fail(RL_EINVAL, "n_surfaces must be in 1..%d", kMaxModelSurfaces);
+    if (n_poses < 1 || n_poses > kMaxModelPoses) return fail(RL_EINVAL, "n_poses must be in 1..%d", kMaxModelPoses);
+    if (!finite_f(min_depth) || !finite_f(max_depth) || min_depth < 0.0f)
+        return fail(RL_EINVAL, "min_depth must be finite and >= 0, max_depth finite");
+    for (int i = 0; i < n_surf * 16; ++i)
+        if (!finite_f(reinterpret_cast<const float*>(surfaces)[i])) return fail(RL_EINVAL, "non-finite surface");
+    for (int i = 0; i < n_poses * 12; ++i)
+        if (!finite_f(poses[i])) return fail(RL_EINVAL, "non-finite pose");
+    int dev = 0;
+    char* ws = nullptr;
+    s = score_scratch_address(&dev, &ws);
+    if (s != RL_OK) return s;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    double hout[kMaxModelPoses * 2];
+    long long hcnt[kMaxModelPoses * 2];
+    // one call at a time per device: the work space is shared by every call
+    std::lock_guard<std::mutex> lk(g_score_scratch_mu[dev]);
+    hipError_t e = hipMemcpyAsync(ws + kSsSurfaces, surfaces, (size_t)n_surf * 64, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(ws + kSsPoses, poses, (size_t)n_poses * 48, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = launch_depth_scores(f->depth, f->width, f->height, f->K.fx, f->K.fy, f->K.cx, f->K.cy,
+                                reinterpret_cast<const float*>(ws + kSsSurfaces), n_surf,
+                                reinterpret_cast<const float*>(ws + kSsPoses), n_poses, min_depth, max_depth,
+                                reinterpret_cast<double*>(ws + kSsPartial), reinterpret_cast<int*>(ws + kSsCnt),
+                                reinterpret_cast<double*>(ws + kSsOut), reinterpret_cast<long long*>(ws + kSsCounts),
+                                st);
+    if (e == hipSuccess) e = hipMemcpyAsync(hout, ws + kSsOut, (size_t)n_poses * 16, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(hcnt, ws + kSsCounts, (size_t)n_poses * 16, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "depth scores (fixed work space)");
+    for (int k = 0; k < n_poses; ++k) {
+        scores[k] = hout[2 * k];
+        if (mu) mu[k] = hout[2 * k + 1];
+        if (counts) {
+            counts[2 * k] = hcnt[2 * k];
+            counts[2 * k + 1] = hcnt[2 * k + 1];
         }
     }
     return RL_OK;
