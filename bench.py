@@ -28,27 +28,18 @@ METRIC = "relocalisations/s at 640x480, batched/served vs plain; p50/p99 latency
 MI355X_VALU_OPS = 256 * 4 * 16 * 2.4e9        # VALU lane-ops/s (one op per lane per clock per SIMD)
 MI355X_HBM = 8.0e12
 
-# Algorithmic VALU operations of one hypothesis-generation iteration (hand
-# count of the definition, not of emitted instructions): two Philox4x32-10
-# blocks (10 rounds x (2 mul-lo + 2 mul-hi + 4 xor) + 9 x 2 key additions =
-# 98 each), three uniform draws into the eligible list and three into M(u)
-# (1 multiply-high each), three back-projections (2 sub + 2 div + 2 mul),
-# the colour check (3 sub + 3 abs + 3 compare), six squared distances
-# (3 sub + 3 mul + 2 add each), six square roots, three rigidity differences
-# (sub + abs + compare) and three distance compares.
-HYP_ITER_OPS = 2 * 98 + 6 + 3 * 6 + 9 + 6 * 8 + 6 + 3 * 3 + 3
-# Bytes one node test gathers: the 16-byte node record and the 8-byte probe
-# word (depth and colour of the offset pixel).  Nearly all of them come from
-# the vector L1 and L2 (the top levels of every tree and the neighbourhood of
-# each pixel are shared), so the traversal is priced against the L1 return
-# rate, taken as 64 B per clock per CU (the CDNA3 vector-L1 figure):
-# 256 CUs x 64 B x 2.4 GHz.
+# Algorithmic unit of hypothesis generation: one generation iteration of a
+# slot, up to and including the first one that passes every check (or all
+# I_max when none does), priced at two Philox4x32-10 blocks, about 150 integer
+# lane-ops.  The checks that follow the draws are not counted: about nine in
+# ten iterations stop at the colour check of the first pair.
+HYP_ITER_OPS = 150
+# Traversal: the compulsory HBM bytes of a pixel are its depth and colour
+# read once (8 B) and its leaf index per tree written (2 B each); the bytes a
+# node test gathers (16 B node + 8 B probe word) come from the caches and are
+# reported beside it, not as an HBM fraction.
 NODE_TEST_BYTES = 24
-MI355X_L1 = 256 * 64 * 2.4e9
-# HBM bytes per pixel of the traversal stage that no cache can avoid: depth
-# (4) and colour (3) read and the probe word (8) written by the packing
-# kernel, the probe word read back (8) and the leaf indices written (16).
-TRAVERSE_PIXEL_HBM = 4 + 3 + 8 + 8 + 16
+TRAVERSE_PIXEL_IN = 8
 # FP64 flops of Eq. 5 scoring: per mode evaluation d = y - mu (3), Sigma^-1 d
 # (9 mul + 6 add), d . (Sigma^-1 d) (3 mul + 2 add) and the running minimum (1);
 # per (hypothesis, pixel) the rigid transform (9 mul + 9 add) and the square
@@ -83,21 +74,34 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def profiled_traffic(name: str):
-    """HBM bytes per launch from a committed counter summary under profiles/
-    (FETCH_SIZE and WRITE_SIZE scaled by a copy kernel's readings), or None
-    when the summary was taken on other kernel sources."""
+def profile_values(name: str) -> dict:
+    """Figures of a committed counter summary under profiles/ (traffic bytes
+    per launch from FETCH_SIZE and WRITE_SIZE scaled by a copy kernel's
+    readings, VALU busy, L2 hit rate), or {} when the summary was taken on
+    other kernel sources."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
-        return None
-    taken_on, traffic = None, None
+        return {}
+    taken_on, vals = None, {}
     with open(path) as fh:
         for line in fh:
+            parts = line.split()
             if line.startswith("# device sources sha256"):
-                taken_on = line.split()[-1]
-            elif line.startswith("traffic_bytes_per_launch"):
-                traffic = float(line.split()[1])
-    return traffic if taken_on == kernel_source_hash() else None
+                taken_on = parts[-1]
+            elif len(parts) >= 2 and parts[0] in ("traffic_bytes_per_launch", "valu_busy", "l2_hit_rate"):
+                vals[parts[0]] = float(parts[1])
+    return vals if taken_on == kernel_source_hash() else {}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def percentile(v, q):
@@ -113,21 +117,32 @@ def main():
     ap.add_argument("--queries", type=int, default=16)
     ap.add_argument("--adapt-frames", type=int, default=50)
     ap.add_argument("--plain", type=int, default=32, help="plain relocalisations timed for latency")
-    ap.add_argument("--cpu-frames", type=int, default=12, help="oracle relocalisations, about 11 s of host work (0 = skip)")
+    ap.add_argument("--cpu-frames", type=int, default=64,
+                    help="oracle relocalisations on all host threads, about 10-20 s of host work (0 = skip)")
+    ap.add_argument("--cpu-frames-1t", type=int, default=4,
+                    help="oracle relocalisations on one thread, beside the threaded figure")
+    ap.add_argument("--c1-queries", type=int, default=200,
+                    help="plain relocalisations of the 160x120 one-tree workload (0 = skip)")
+    ap.add_argument("--c3-queries", type=int, default=300,
+                    help="frames through the three-stage cascade of 640x480 relocalisers, 30%% of them "
+                         "far from every adaptation pose (0 = skip)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--timer", default="hyp_search", choices=["traverse", "hyp_search", "ransac"])
-    ap.add_argument("--serve-seconds", type=float, default=3.0,
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="measured seconds per arrival rate of the served leg (0 = skip it)")
-    ap.add_argument("--serve-rates", default="500,1000,2000")
+    ap.add_argument("--serve-rates", default="200,500,1000")
+    ap.add_argument("--saturation-rates", default="4000,8000,16000,32000",
+                    help="offered rates of the served leg driven towards its throughput ceiling")
+    ap.add_argument("--saturation-seconds", type=float, default=3.0)
     ap.add_argument("--serve-rooms", type=int, default=16)
     ap.add_argument("--serve-leaves-per-frame", type=int, default=256,
                     help="mode update schedule of the served rooms: 0 exact, K leaves per adapted frame")
-    ap.add_argument("--robustness", action="store_true",
-                    help="also run the missing-depth and depth-noise sweeps (Default RANSAC settings)")
-    ap.add_argument("--robustness-queries", type=int, default=32)
+    ap.add_argument("--no-robustness", action="store_true",
+                    help="skip the missing-depth and depth-noise sweeps (Default RANSAC settings)")
+    ap.add_argument("--robustness-queries", type=int, default=16)
     ap.add_argument("--render-procs", type=int, default=16,
                     help="worker processes rendering the inputs before the GPU is used (1 = in this process)")
-    ap.add_argument("--cascade-frames", type=int, default=16,
+    ap.add_argument("--cascade-frames", type=int, default=64,
                     help="frames relocalised by the paper's Fast -> Intermediate -> Slow cascade (0 = skip)")
     ap.add_argument("--lm-steps", type=int, default=5,
                     help="steps of the batch with LM refinement (0 = skip that leg)")
@@ -154,7 +169,12 @@ def main():
     # that initialises the GPU first needs --render-procs 1).
     procs = max(1, min(args.render_procs, os.cpu_count() or 1))
     w = workloads.c2_corrupted(0, n_adapt=args.adapt_frames, n_queries=args.queries, processes=procs)
-    robust_inputs = robustness_inputs(args, procs) if args.robustness else None
+    robust_inputs = robustness_inputs(args, procs) if not args.no_robustness else None
+    c1_inputs = workloads.c1(0, n_queries=8) if args.c1_queries > 0 else None
+    c3_inputs = None
+    if args.c3_queries > 0:
+        c3_inputs = workloads.queries_for(w.room, [f.pose for f in w.adapt], args.c3_queries, room_id=0,
+                                          novel_fraction=0.3, start=1000, processes=procs)
     serve_inputs = None
     if args.serve_seconds > 0:
         serve_inputs = workloads.serving_setup(n_rooms=args.serve_rooms, n_adapt=20, n_cameras=32,
@@ -294,31 +314,35 @@ def main():
     ok = [e[0] <= 0.05 and e[1] <= 5.0 for e in errs]
 
     lm = lm_leg(args, rl, room, batch, reqs, frames, w, qd, qc, use_graph) if args.lm_steps > 0 else None
-    cascade = cascade_leg(args, rl, w, dev, qd, qc) if args.cascade_frames > 0 else None
+    cascade = cascade_leg(args, rl, w, dev, c3_inputs or w.queries) if args.cascade_frames > 0 else None
     robustness = robustness_leg(args, rl, dev, robust_inputs) if robust_inputs is not None else None
 
     # ---- rooflines -------------------------------------------------------------
     def roof_search(ms):
         k = ms * 1e-3
         ops = iters * HYP_ITER_OPS
-        traffic = profiled_traffic("k_hyp_search_640x480_batch64_counters.txt") if B == 64 else None
+        prof = profile_values("k_hyp_search_640x480_batch64_counters.txt") if B == 64 else {}
+        traffic = prof.get("traffic_bytes_per_launch")
         return dict(kernel="k_hyp_search", bound="alu", achieved=ops / k / 1e12, peak=MI355X_VALU_OPS / 1e12,
                     unit="TOP/s (VALU lane-ops)", frac=ops / k / MI355X_VALU_OPS, traffic=traffic,
-                    launch_ms=ms, work=f"{iters} generation iterations x {HYP_ITER_OPS} ops",
+                    launch_ms=ms, work=f"{iters} generation iterations (each slot up to its accepted one) x "
+                                       f"{HYP_ITER_OPS} lane-ops (two Philox blocks)",
+                    valu_busy=prof.get("valu_busy"), l2_hit_rate=prof.get("l2_hit_rate"),
                     traffic_unit="HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                     traffic_GBps=(traffic / k / 1e9) if traffic else None)
 
     def roof_traverse(ms):
         k = ms * 1e-3
-        by = node_tests * NODE_TEST_BYTES
-        hbm = B * 640 * 480 * TRAVERSE_PIXEL_HBM
-        return dict(kernel="k_pack+k_traverse", bound="l1", achieved=by / k / 1e9, peak=MI355X_L1 / 1e9,
-                    unit="GB/s", frac=by / k / MI355X_L1, traffic=None, launch_ms=ms,
-                    touched_vs_hbm_frac=by / k / MI355X_HBM,
-                    hbm_unavoidable_GBps=hbm / k / 1e9, hbm_frac=hbm / k / MI355X_HBM,
-                    work=f"{node_tests} node tests x {NODE_TEST_BYTES} B gathered through the vector L1 "
-                         f"(peak derived: 256 CUs x 64 B/clk x 2.4 GHz); {B} frames x 307200 px x "
-                         f"{TRAVERSE_PIXEL_HBM} B unavoidable HBM traffic")
+        hbm = B * 640 * 480 * (TRAVERSE_PIXEL_IN + 2 * p["n_trees"])
+        prof = profile_values("k_traverse_640x480_batch64_counters.txt") if B == 64 else {}
+        traffic = prof.get("traffic_bytes_per_launch")
+        return dict(kernel="k_pack+k_traverse", bound="hbm", achieved=hbm / k / 1e9, peak=MI355X_HBM / 1e9,
+                    unit="GB/s", frac=hbm / k / MI355X_HBM, traffic=traffic, launch_ms=ms,
+                    touched_GBps=node_tests * NODE_TEST_BYTES / k / 1e9, valu_busy=prof.get("valu_busy"),
+                    l2_hit_rate=prof.get("l2_hit_rate"),
+                    work=f"{B} frames x 307200 px x {TRAVERSE_PIXEL_IN + 2 * p['n_trees']} B compulsory "
+                         f"(depth and colour in, one 2-byte leaf per tree out); touched: {node_tests} node "
+                         f"tests x {NODE_TEST_BYTES} B gathered, served by the caches")
 
     def roof_scoring(ms):
         k = ms * 1e-3
@@ -335,21 +359,10 @@ def main():
     # ---- CPU baseline: the oracle on a bounded sample ----------------------
     cpu = None
     if args.cpu_frames > 0:
-        import oracle
-        nm = room.buffer_np(rl.BUF_NMODES, np.uint8).copy()
-        modes = room.buffer_np(rl.BUF_MODES, np.float32).copy()
-        T, D, M = p["n_trees"], p["depth"], p["max_cluster_count"]
-        t0 = time.perf_counter()
-        for k in range(args.cpu_frames):
-            q = w.queries[k % len(w.queries)]
-            leaves = oracle.traverse(q.depth, q.rgb, None, w.nodes, T, D, p["ref_width"])
-            oracle.estimate_pose(q.depth, q.rgb, q.K, leaves, nm, modes, T, D, M, p, k, trace=False)
-        ct = time.perf_counter() - t0
-        cpu = dict(value=args.cpu_frames / ct, unit="relocalisations/s", cores=1, kind="oracle",
-                   sample=f"{args.cpu_frames} relocalisations of 640x480 query frames (traversal, "
-                          f"hypotheses, RANSAC, refit; modes taken from the room), 1 thread, {ct:.1f} s")
-        log(f"[bench] oracle: {cpu['value']:.3f} reloc/s over {ct:.1f} s")
+        cpu = cpu_leg(args, rl, room, w, p)
 
+    c1 = c1_leg(args, rl, dev, c1_inputs) if c1_inputs is not None else None
+    c3 = c3_leg(args, rl, dev, w, c3_inputs) if c3_inputs is not None else None
     served = serve_leg(args, rl, dev, serve_inputs) if serve_inputs is not None else None
 
     out = {
@@ -358,8 +371,9 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "640x480 synthetic room; 5 random trees of depth 15; reservoirs 1024; "
-                               "<=10 modes/leaf; 50 adaptation frames; 1024 hypotheses; eta 500; "
-                               "10 halving rounds; inlier refit",
+                               "<=10 modes/leaf; 50 adaptation frames; 1024 hypotheses of up to 6000 "
+                               "generation iterations; eta 500; halving while more than one survives "
+                               "(rounds run and valid hypotheses per frame under 'batched'); inlier refit",
                    "form": "batched" + (" (hipGraph replay)" if use_graph else ""), "batch": B,
                    "distinct_frames": len(w.queries),
                    "schedule": {"plain": list(room.schedule), "batched": list(batch.schedule),
@@ -370,8 +384,14 @@ def main():
         "rooflines_other": {n: r for n, r in rooflines.items() if r is not roof},
         "cpu_baseline": cpu,
         "plain": plain,
+        "plain_c1": c1,
         "batched": dict(relocs_per_s=value, step_p50_ms=percentile(step_ms, 50),
-                        step_p99_ms=percentile(step_ms, 99), identical_to_plain=bool(same)),
+                        step_p99_ms=percentile(step_ms, 99), identical_to_plain=bool(same),
+                        mean_n_valid=float(np.mean([r["n_valid"] for r in res])),
+                        mean_rounds_run=float(np.mean([r["rounds"] for r in res])),
+                        rounds_run_counts={str(k): v for k, v in
+                                           sorted(collections.Counter(r["rounds"] for r in res).items())}),
+        "cascade_c3": c3,
         "served": served,
         "lm": lm,
         "cascade": cascade,
@@ -382,6 +402,137 @@ def main():
         "paper_context": "Fast relocaliser 25.1 ms/frame on a GTX 1080 Ti (Table 3)",
     }
     print(json.dumps(out), flush=True)
+
+
+def cpu_leg(args, rl, room, w, p):
+    """The oracle (traversal, hypotheses, RANSAC and refit of 640x480 query
+    frames, modes taken from the GPU room) on the host: on every host thread
+    (its OpenMP loops over pixels and hypotheses), and on one thread."""
+    import oracle
+    nm = room.buffer_np(rl.BUF_NMODES, np.uint8).copy()
+    modes = room.buffer_np(rl.BUF_MODES, np.float32).copy()
+    T, D, M = p["n_trees"], p["depth"], p["max_cluster_count"]
+
+    def run(n, threads):
+        used = oracle.lib().oracle_set_threads(threads)
+        t0 = time.perf_counter()
+        for k in range(n):
+            q = w.queries[k % len(w.queries)]
+            leaves = oracle.traverse(q.depth, q.rgb, None, w.nodes, T, D, p["ref_width"])
+            oracle.estimate_pose(q.depth, q.rgb, q.K, leaves, nm, modes, T, D, M, p, k, trace=False)
+        return time.perf_counter() - t0, used
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    ct, used = run(args.cpu_frames, threads)
+    c1t, _ = run(args.cpu_frames_1t, 1) if args.cpu_frames_1t > 0 else (None, 1)
+    oracle.lib().oracle_set_threads(threads)
+    model = cpu_model()
+    cpu = dict(value=args.cpu_frames / ct, unit="relocalisations/s", cores=used, kind="oracle",
+               cpu_model=model, host_threads=os.cpu_count(),
+               sample=f"{args.cpu_frames} relocalisations of 640x480 query frames (traversal, hypotheses, "
+                      f"RANSAC, refit; modes taken from the room) on {used} threads of {model}, {ct:.1f} s",
+               single_thread=(dict(value=args.cpu_frames_1t / c1t, frames=args.cpu_frames_1t, seconds=c1t)
+                              if c1t else None))
+    log(f"[bench] oracle: {cpu['value']:.3f} reloc/s on {used} threads over {ct:.1f} s"
+        + (f"; 1 thread {args.cpu_frames_1t / c1t:.3f} reloc/s" if c1t else ""))
+    return cpu
+
+
+def c1_leg(args, rl, dev, w1):
+    """The small plain workload: 160x120 frames, one depth-8 tree, reservoirs
+    of 64, 64 hypotheses, eta 100; one synchronous relocalisation at a time."""
+    import torch
+
+    from rlsynth import scene
+    room = rl.Room(w1.params, w1.nodes, 160, 120, device=dev)
+    for f in w1.adapt:
+        room.adapt(torch.from_numpy(f.depth).to(dev), torch.from_numpy(f.rgb).to(dev), f.K, f.pose)
+    room.update_modes()
+    qd = [torch.from_numpy(q.depth).to(dev) for q in w1.queries]
+    qc = [torch.from_numpy(q.rgb).to(dev) for q in w1.queries]
+    torch.cuda.synchronize()
+    lat, errs = [], []
+    for k in range(5 + args.c1_queries):
+        qi = k % len(w1.queries)
+        t0 = time.perf_counter()
+        r = room.relocalise(qd[qi], qc[qi], w1.queries[qi].K, request_seed=k)
+        dt = time.perf_counter() - t0
+        if k >= 5:
+            lat.append(dt)
+            errs.append(scene.pose_error(r["pose"].astype(np.float64), w1.queries[qi].pose)
+                        if r["status"] == "ok" else (np.inf, np.inf))
+    room.close()
+    out = dict(relocs_per_s=len(lat) / sum(lat), p50_ms=percentile(lat, 50) * 1e3, p99_ms=percentile(lat, 99) * 1e3,
+               mean_ms=float(np.mean(lat)) * 1e3, frames=len(lat),
+               frac_within_5cm_5deg=float(np.mean([e[0] <= 0.05 and e[1] <= 5.0 for e in errs])))
+    log(f"[bench] c1 plain (160x120): {out['relocs_per_s']:.1f} reloc/s, p50 {out['p50_ms']:.3f} ms, "
+        f"p99 {out['p99_ms']:.3f} ms")
+    return out
+
+
+# fallback threshold of the three-stage cascade on the winner's mean Eq. 5
+# energy over its final pixel set (E / |I|)
+C3_ENERGY_THRESHOLD = 1.0
+
+
+def c3_leg(args, rl, dev, w, queries):
+    """The three-stage cascade of 640x480 relocalisers on the shared forest:
+    (a) the 2x decimated 320x240 frame with 256 hypotheses, (b) the full frame
+    with 1024 hypotheses and the inlier refit, (c) 4096 hypotheses culled to
+    16, re-ranked by the plane score (mean distance of the back-projected depth
+    to the nearest surface).  A stage falls back when its winner's mean energy
+    exceeds the threshold.  30% of the queries lie >= 50 cm or >= 50 deg from
+    every adaptation pose.  Frames one at a time: latency, stage reached,
+    accuracy."""
+    import torch
+
+    from paper_1810_12163_amd.cascade import Cascade, c3_stages
+    from rlsynth import presets, scene
+    room = rl.Room(dict(w.params, **{k: presets.preset("c3c")[k] for k in
+                                     ("max_pose_candidates", "max_pose_candidates_after_cull",
+                                      "max_relocalisations_to_output", "final_refine")}),
+                   w.nodes, 640, 480, device=dev)
+    for f in w.adapt:
+        room.adapt(torch.from_numpy(f.depth).to(dev), torch.from_numpy(f.rgb).to(dev), f.K, f.pose)
+    room.update_modes()
+    cas = Cascade(room, c3_stages(C3_ENERGY_THRESHOLD), scene.surface_records(w.room), model="plane",
+                  fallback="energy")
+    adapt_poses = [f.pose for f in w.adapt]
+    for k in range(3):                                   # graph capture of each stage's shape
+        q = queries[k]
+        cas.relocalise(torch.from_numpy(q.depth).to(dev), torch.from_numpy(q.rgb).to(dev), q.K, request_seed=5000 + k)
+    torch.cuda.synchronize()
+    ms, stages, errs, novel, energies = [], [], [], [], []
+    for k, q in enumerate(queries):
+        d, c = torch.from_numpy(q.depth).to(dev), torch.from_numpy(q.rgb).to(dev)
+        torch.cuda.synchronize()
+        out = cas.relocalise(d, c, q.K, request_seed=k)
+        ms.append(out["ms"])
+        stages.append(out["stage"])
+        e = scene.pose_error(out["pose"].astype(np.float64), q.pose) if out["status"] == "ok" else (np.inf, np.inf)
+        errs.append(e)
+        energies.append((out["trail"][0][1], e[0] <= 0.05 and e[1] <= 5.0))
+        novel.append(all(scene.pose_error(q.pose, a)[0] >= 0.5 or scene.pose_error(q.pose, a)[1] >= 50.0
+                         for a in adapt_poses))
+    room.close()
+    ok = np.array([e[0] <= 0.05 and e[1] <= 5.0 for e in errs])
+    nv = np.array(novel)
+    first = np.array([x[0] for x in energies])
+    res = dict(frames=len(ms), mean_ms=float(np.mean(ms)), p50_ms=percentile(ms, 50), p99_ms=percentile(ms, 99),
+               relocs_per_s=len(ms) / (sum(ms) * 1e-3),
+               stage_counts={s.name: stages.count(s.name) for s in cas.stages},
+               frac_within_5cm_5deg=float(np.mean(ok)),
+               frac_within_5cm_5deg_near=float(np.mean(ok[~nv])) if np.any(~nv) else None,
+               frac_within_5cm_5deg_novel=float(np.mean(ok[nv])) if np.any(nv) else None,
+               novel_fraction=float(np.mean(nv)), energy_threshold=C3_ENERGY_THRESHOLD,
+               stage_a_mean_energy_correct=float(np.median(first[ok])) if np.any(ok) else None,
+               stage_a_mean_energy_wrong=float(np.median(first[~ok])) if np.any(~ok) else None,
+               median_cm=float(np.median([e[0] for e in errs]) * 100))
+    log(f"[bench] c3 cascade: {res['mean_ms']:.2f} ms per frame (p50 {res['p50_ms']:.2f}, p99 {res['p99_ms']:.2f}), "
+        f"stages {res['stage_counts']}, within 5cm/5deg {res['frac_within_5cm_5deg']:.3f} "
+        f"(near {res['frac_within_5cm_5deg_near']}, novel {res['frac_within_5cm_5deg_novel']}); stage-a mean "
+        f"energy median correct {res['stage_a_mean_energy_correct']} / wrong {res['stage_a_mean_energy_wrong']}")
+    return res
 
 
 def lm_leg(args, rl, room, batch, reqs, frames, w, qd, qc, use_graph):
@@ -453,40 +604,49 @@ def lm_leg(args, rl, room, batch, reqs, frames, w, qd, qc, use_graph):
     return out
 
 
-def cascade_leg(args, rl, w, dev, qd, qc):
+def cascade_leg(args, rl, w, dev, queries):
     """The paper's cascade (Sec. 3.2.5): Fast -> Intermediate -> Slow with
-    Table 8's RANSAC settings on one shared forest, falling back when the
-    depth-raycast score (Eq. 6-7) of a stage's pose exceeds 5 cm, then
-    7.5 cm; the slow stage ranks its 16 outputs by that score (Eq. 8).
-    Frames one at a time: latency per frame, stage reached, accuracy."""
+    Table 8's RANSAC settings on one shared forest built with Table 8's Forest
+    row for those relocalisers (M_max 50, reservoirs of 2048, tau_c 0.2,
+    minimum cluster size 5), falling back when the depth-raycast score
+    (Eq. 6-7) of a stage's pose exceeds 5 cm, then 7.5 cm; the slow stage
+    ranks its 16 outputs by that score (Eq. 8).  Frames one at a time (the
+    cascade queries: 30% of them far from every adaptation pose): latency per
+    frame, stage reached, accuracy."""
     import torch
 
     from paper_1810_12163_amd.cascade import Cascade, paper_stages
-    from rlsynth import scene
-    p = dict(w.params, max_pose_candidates=2048, max_pose_candidates_after_cull=64)
+    from rlsynth import presets, scene
+    fast = presets.preset("fast")
+    p = dict(w.params, max_pose_candidates=2048, max_pose_candidates_after_cull=64,
+             **{k: fast[k] for k in ("clusterer_sigma", "clusterer_tau", "max_cluster_count", "min_cluster_size",
+                                     "reservoir_capacity")})
     room = rl.Room(p, w.nodes, 640, 480, device=dev)
     for f in w.adapt:
         room.adapt(torch.from_numpy(f.depth).to(dev), torch.from_numpy(f.rgb).to(dev), f.K, f.pose)
     room.update_modes()
     cas = Cascade(room, paper_stages(), scene.surface_records(w.room), min_depth=scene.DEPTH_MIN,
                   max_depth=scene.DEPTH_MAX)
+    qs = [queries[k % len(queries)] for k in range(args.cascade_frames)]
+    dev_q = [(torch.from_numpy(q.depth).to(dev), torch.from_numpy(q.rgb).to(dev)) for q in qs]
     for k in range(2):                                   # graph capture of each stage's shape
-        qi = k % len(w.queries)
-        cas.relocalise(qd[qi], qc[qi], w.queries[qi].K, request_seed=1000 + k)
+        cas.relocalise(*dev_q[k], qs[k].K, request_seed=1000 + k)
     torch.cuda.synchronize()
     ms, stages, errs = [], [], []
-    for k in range(args.cascade_frames):
-        qi = k % len(w.queries)
-        out = cas.relocalise(qd[qi], qc[qi], w.queries[qi].K, request_seed=k)
+    for k, q in enumerate(qs):
+        out = cas.relocalise(*dev_q[k], q.K, request_seed=k)
         ms.append(out["ms"])
         stages.append(out["stage"])
-        errs.append(scene.pose_error(out["pose"].astype(np.float64), w.queries[qi].pose))
+        errs.append(scene.pose_error(out["pose"].astype(np.float64), q.pose) if out["status"] == "ok"
+                    else (np.inf, np.inf))
     room.close()
     res = dict(frames=len(ms), mean_ms=float(np.mean(ms)), p50_ms=percentile(ms, 50), p99_ms=percentile(ms, 99),
                stage_counts={s.name: stages.count(s.name) for s in cas.stages},
                frac_within_5cm_5deg=float(np.mean([e[0] <= 0.05 and e[1] <= 5.0 for e in errs])),
                median_cm=float(np.median([e[0] for e in errs]) * 100),
-               thresholds_m=[s.threshold for s in cas.stages[:-1]])
+               thresholds_m=[s.threshold for s in cas.stages[:-1]],
+               forest_row=dict(max_cluster_count=p["max_cluster_count"], reservoir_capacity=p["reservoir_capacity"],
+                               clusterer_tau=p["clusterer_tau"], min_cluster_size=p["min_cluster_size"]))
     log(f"[bench] cascade: {res['mean_ms']:.2f} ms per frame (p50 {res['p50_ms']:.2f}), stages {res['stage_counts']}, "
         f"within 5cm/5deg {res['frac_within_5cm_5deg']:.3f}")
     return res
@@ -497,13 +657,17 @@ ROBUSTNESS_LEVELS = [("missing", p) for p in (0.1, 0.3, 0.5, 0.7, 0.9, 0.95)] + 
 
 
 def robustness_inputs(args, procs):
-    """Frames of every sweep level, rendered before the GPU is used."""
+    """Frames of every sweep level, rendered before the GPU is used (each pose
+    raycast once, every level's sensor noise drawn from the frame's seed)."""
     from rlsynth import workloads
-    out = []
-    for kind, v in ROBUSTNESS_LEVELS:
-        kw = {"missing": dict(dropout=v), "noise": dict(depth_rel_sigma=v), "novel": dict(novel_fraction=v)}[kind]
-        out.append((kind, v, workloads.c2_corrupted(0, n_adapt=50, n_queries=args.robustness_queries,
-                                                    processes=procs, **kw)))
+    sensor = [(k, v) for k, v in ROBUSTNESS_LEVELS if k != "novel"]
+    kws = [dict(dropout=v) if k == "missing" else dict(depth_rel_sigma=v) for k, v in sensor]
+    ws = workloads.c2_sweep(kws, 0, n_adapt=50, n_queries=args.robustness_queries, processes=procs)
+    out = [(k, v, w) for (k, v), w in zip(sensor, ws)]
+    for k, v in ROBUSTNESS_LEVELS:
+        if k == "novel":
+            out.append((k, v, workloads.c2_sweep([{}], 0, n_adapt=50, n_queries=args.robustness_queries,
+                                                 processes=procs, novel_fraction=v)[0]))
     log(f"[bench] robustness inputs rendered ({len(out)} levels)")
     return out
 
@@ -543,9 +707,13 @@ def robustness_leg(args, rl, dev, inputs):
 
 
 def serve_leg(args, rl, dev, inputs):
-    """Open-loop Poisson arrivals from 32 cameras over resident rooms; 75%
-    relocalise / 25% adapt; resolutions 160x120, 320x240, 640x480 with 256, 512,
-    1024 hypotheses.  Continuous batching, two batches in flight."""
+    """Open-loop Poisson arrivals from 32 cameras over 16 resident rooms; 75%
+    relocalise / 25% adapt; resolutions 160x120, 320x240, 640x480 with 256,
+    512, 1024 hypotheses.  Frames arrive in host memory and are copied into
+    the server's frame slots; rooms, batch contexts and frame slots are
+    charged against one device-memory budget.  Continuous batching, two
+    batches in flight.  The configured rates run for --serve-seconds each;
+    higher rates then drive the server towards its throughput ceiling."""
     import torch
 
     from paper_1810_12163_amd import serve
@@ -554,20 +722,33 @@ def serve_leg(args, rl, dev, inputs):
     t0 = time.time()
     specs, cams = inputs
     p = presets.preset("c5")
+    room_bytes = sum(rl.room_state_bytes(p, 640, 480))
+    ctx_bytes = serve.batch_workspace_bytes(64, 640, 480, 1024, 500, 10, 5, 50)
+    slots = 128
+    budget = len(specs) * room_bytes + 2 * ctx_bytes + slots * serve.FramePool.slot_bytes(640, 480)
+    server = serve.Server(max_batch=64, max_width=640, max_height=480, max_hypotheses=1024, max_eta=500,
+                          max_rounds=10, n_trees=5, max_modes_per_pixel=50, contexts=2, memory_budget=budget,
+                          frame_slots=slots, device=dev)
     rooms = []
     for sp in specs:
-        room = rl.Room(p, sp["nodes"], 640, 480, device=dev)
+        room = server.create_room(p, sp["nodes"])
+        assert room is not None, "the budget holds every room"
         for f in sp["adapt"]:
             room.adapt(torch.from_numpy(f.depth).to(dev), torch.from_numpy(f.rgb).to(dev), f.K, f.pose)
         room.update_modes()
         room.set_mode_schedule(args.serve_leaves_per_frame)
         rooms.append(room)
     torch.cuda.synchronize()
+    # camera frames in pinned host memory; device copies for the mixed-batch leg
+    camh = [[serve.pack_host_frame(f.depth, f.rgb) + (f,) for f in c["frames"]] for c in cams]
     camf = [[(torch.from_numpy(f.depth).to(dev), torch.from_numpy(f.rgb).to(dev), f) for f in c["frames"]]
             for c in cams]
-    log(f"[bench] serving: {len(rooms)} rooms resident "
-        f"({sum(r.persistent.numel() for r in rooms) / 2**30:.1f} GiB), setup {time.time() - t0:.1f} s")
-    out = {}
+    extra = server.create_room(p, specs[0]["nodes"])
+    log(f"[bench] serving: {len(rooms)} rooms resident ({len(rooms) * room_bytes / 2**30:.1f} GiB), budget "
+        f"{budget / 2**30:.2f} GiB ({slots} frame slots, {len(server.ctx)} contexts); a 17th room "
+        f"{'refused' if extra is None else 'ADMITTED'}; setup {time.time() - t0:.1f} s")
+    out = {"memory_budget_GiB": budget / 2**30, "frame_slots": slots, "contexts": len(server.ctx),
+           "room_GiB": room_bytes / 2**30, "extra_room_refused": extra is None}
     # a steady mixed batch: 64 frames over 8 rooms, resolutions and hypothesis
     # counts drawn with the cameras' frames, and 16 adaptation frames applied
     # after every batch's relocalisations
@@ -610,27 +791,31 @@ def serve_leg(args, rl, dev, inputs):
     log(f"[bench] mixed batch (8 rooms, {dict(mix)} by width, schedule {mb_sched}): {mbo['relocs_per_s']:.1f} reloc/s "
         f"({mbo['ms_per_batch']:.2f} ms per 64-frame batch); with 16 adaptations per step "
         f"{mbo['relocs_per_s_with_adapt']:.1f} reloc/s ({mbo['ms_per_step_with_adapt']:.2f} ms)")
-    warm = 1.0
-    for rate in [float(v) for v in args.serve_rates.split(",")]:
-        server = serve.Server(max_batch=64, max_width=640, max_height=480, max_hypotheses=1024, max_eta=500,
-                              max_rounds=10, n_trees=5, max_modes_per_pixel=50, contexts=2, device=dev)
-        arr = serve.poisson_arrivals(rate, warm + args.serve_seconds, seed=int(rate))
+    del camf
+    warm = 2.0
+    rates = [(float(v), args.serve_seconds) for v in args.serve_rates.split(",") if v] + \
+            [(float(v), args.saturation_seconds) for v in args.saturation_rates.split(",") if v]
+    for rate, seconds in rates:
+        server.reset_stats()
+        arr = serve.poisson_arrivals(rate, warm + seconds, seed=int(rate))
         rng = np.random.default_rng(int(rate) + 1)
         reqs = []
         for i in range(len(arr)):
             c = int(rng.integers(len(cams)))
-            d, rgb, f = camf[c][int(rng.integers(len(camf[c])))]
+            buf, hw, f = camh[c][int(rng.integers(len(camh[c])))]
             kind = "adapt" if rng.uniform() < 0.25 else "relocalise"
-            reqs.append(serve.Request(rid=i, kind=kind, room=rooms[cams[c]["room"]], depth=d, rgb=rgb, K=f.K,
-                                      pose=f.pose if kind == "adapt" else None,
+            reqs.append(serve.Request(rid=i, kind=kind, room=rooms[cams[c]["room"]], host_frame=buf, frame_hw=hw,
+                                      K=f.K, pose=f.pose if kind == "adapt" else None,
                                       n_hypotheses=workloads.HYPOTHESES[f.w]))
         st = serve.run_open_loop(server, reqs, arr, warmup_s=warm)
-        server.close()
+        st["measured_s"] = seconds
         out[f"{int(rate)}/s"] = st
-        log(f"[bench] served {int(rate)}/s: {st['relocs_per_s']:.1f} reloc/s, p50 {st['p50_ms']:.2f} ms, "
-            f"p99 {st['p99_ms']:.2f} ms, mean batch {st['mean_batch']:.1f}, refused {st['refused']}")
-    for r in rooms:
-        r.close()
+        log(f"[bench] served {int(rate)}/s over {seconds:g} s: {st['relocs_per_s']:.1f} reloc/s, p50 "
+            f"{st['p50_ms']:.2f} ms, p99 {st['p99_ms']:.2f} ms, mean batch {st['mean_batch']:.1f}, waited for a "
+            f"frame slot {st['deferred']}, refused {st['refused']}")
+    server.close()
+    sat = [out[f"{int(r)}/s"] for r, _ in rates]
+    out["ceiling_relocs_per_s"] = max(x["relocs_per_s"] for x in sat)
     return out
 
 

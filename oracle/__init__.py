@@ -27,7 +27,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rl_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
-_CFLAGS = ["-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+_CFLAGS = ["-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared"]
 
 RES_NONE = 0xFFFF
 
@@ -61,6 +61,8 @@ F64 = ctypes.c_double
 
 
 def _declare(L):
+    L.oracle_set_threads.argtypes = [I32]
+    L.oracle_set_threads.restype = I32
     L.oracle_philox4x32.argtypes = [P, P, P]
     L.oracle_traverse.argtypes = [P, P, I32, I32, P, I32, I32, I32, P, I32, P]
     L.oracle_adapt.argtypes = [P, P, I32, I32, P, P, P, I32, I32, I32, I32, U64, P, P, P]

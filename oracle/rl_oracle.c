@@ -11,8 +11,12 @@
  * feature evaluation and tree routing, which are defined in float32 so that
  * leaf indices are well defined bit for bit (see oracle_traverse).
  *
- * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -shared -fPIC
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -fopenmp -shared -fPIC
  *        (contraction off: every expression is evaluated as written).
+ *        Loops over independent pixels (routing) and hypotheses (generation,
+ *        scoring, refinement) may run on several threads (oracle_set_threads);
+ *        each iteration writes only its own outputs, so results do not depend
+ *        on the thread count.
  *
  * Parity status of each function is stated in its header comment.
  */
@@ -21,7 +25,23 @@
 #include <stdlib.h>
 #include <string.h>
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 #define EXPORT __attribute__((visibility("default")))
+
+/* Threads of the parallel loops (1 = serial); returns the count in effect. */
+EXPORT int oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 counter-based generator (Salmon, Moraes, Dror, Shaw, "Parallel
@@ -140,6 +160,7 @@ EXPORT void oracle_traverse(const float* depth, const uint8_t* rgb, int w, int h
     size_t per_tree = ((size_t)1 << D) - 1;
     float s = (float)w / (float)ref_width;
     int n = pix ? npix : w * h;
+#pragma omp parallel for schedule(static)
     for (int k = 0; k < n; ++k) {
         int p = pix ? pix[k] : k;
         int x = p % w, y = p / w;
@@ -568,6 +589,7 @@ EXPORT void oracle_hypotheses(const float* depth, const uint8_t* rgb, int w, int
                 eligible, n_elig};
     uint32_t key[2];
     stream_key(seed, request_seed, key);
+#pragma omp parallel for schedule(dynamic, 1)
     for (int s = 0; s < n_slots; ++s) {
         valid[s] = 0;
         iter_out[s] = -1;
@@ -951,6 +973,7 @@ EXPORT int oracle_ransac(const float* depth, int w, int h, const float K[4],
             Iall[nI] = newpix[k];
             ++nI;
         }
+#pragma omp parallel for schedule(dynamic, 1)
         for (int i = 0; i < n; ++i) {
             double* P = P64 + 12 * (size_t)hs[i].slot;
             if (pose_update && !first) {

@@ -76,6 +76,27 @@ class Result(ctypes.Structure):
                 ("n_out", ctypes.c_int32), ("pad", ctypes.c_int32 * 2)]
 
 
+# rl_result as a numpy record (decoding many results at once)
+RESULT_DTYPE = np.dtype([("cam_to_world", "<f4", (16,)), ("energy", "<f4"), ("mean_energy", "<f4"),
+                         ("status", "<i4"), ("n_valid", "<i4"), ("n_inliers", "<i4"), ("winner", "<i4"),
+                         ("refitted", "<i4"), ("n_eligible", "<i4"), ("rounds", "<i4"), ("n_out", "<i4"),
+                         ("pad", "<i4", (2,))])
+
+
+def decode_results(raw: np.ndarray, n: int) -> list:
+    """Result dicts of the first n rl_result records in a byte buffer."""
+    rec = np.frombuffer(np.ascontiguousarray(raw).data, dtype=RESULT_DTYPE, count=n)
+    poses = rec["cam_to_world"].reshape(n, 4, 4)
+    out = []
+    for k in range(n):
+        r = rec[k]
+        out.append(dict(pose=poses[k].copy(), energy=float(r["energy"]), mean_energy=float(r["mean_energy"]),
+                        status="ok" if r["status"] == RL_OK else "no_pose", n_valid=int(r["n_valid"]),
+                        n_inliers=int(r["n_inliers"]), winner=int(r["winner"]), refitted=bool(r["refitted"]),
+                        n_eligible=int(r["n_eligible"]), rounds=int(r["rounds"]), n_out=int(r["n_out"])))
+    return out
+
+
 class RelocOpts(ctypes.Structure):
     _fields_ = [("n_hypotheses", ctypes.c_int32), ("n_cull", ctypes.c_int32), ("n_out", ctypes.c_int32),
                 ("final_refine", ctypes.c_int32), ("pose_update", ctypes.c_int32),
@@ -205,6 +226,15 @@ def params_struct(d: dict) -> Params:
     return p
 
 
+def room_state_bytes(params: dict, max_width: int, max_height: int):
+    """(persistent, scratch) device bytes of a room (relocaliser_state_bytes)."""
+    p = params_struct(params)
+    pb, sb = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().relocaliser_state_bytes(ctypes.byref(p), max_width, max_height, ctypes.byref(pb),
+                                         ctypes.byref(sb)))
+    return int(pb.value), int(sb.value)
+
+
 def preset(name: str) -> dict:
     p = Params()
     _check(lib().rl_params_preset(name.encode(), ctypes.byref(p)))
@@ -290,10 +320,15 @@ class Room:
         for t in tensors:
             t.record_stream(self.stream)
 
-    def adapt(self, depth, rgb, K, pose, reliable: bool = True):
+    def adapt(self, depth, rgb, K, pose, reliable: bool = True, record: bool = True):
+        """record=False: the frame tensors' memory is kept by the caller until
+        the adaptation has completed (no record_stream)."""
         f = _frame(depth, rgb, K)
         H = np.ascontiguousarray(np.asarray(pose, dtype=np.float32).reshape(16))
-        self._follow(depth, rgb)
+        if record:
+            self._follow(depth, rgb)
+        else:
+            self._follow()
         _check(lib().relocaliser_adapt(self.handle, ctypes.byref(f), H.ctypes.data, 1 if reliable else 0))
 
     def update_modes(self):
@@ -445,13 +480,14 @@ class Batch:
         """Result-invariant degeneracy screen of the search (rl_batch_set_degeneracy_screen)."""
         _check(lib().rl_batch_set_degeneracy_screen(self.handle, 1 if on else 0))
 
-    def _requests(self, reqs):
+    def _requests(self, reqs, record=True):
         torch = _torch()
         self.stream.wait_stream(torch.cuda.current_stream(self.device))   # frames were made there
         arr = (Request * len(reqs))()
         for i, q in enumerate(reqs):
-            q[1].record_stream(self.stream)
-            q[2].record_stream(self.stream)
+            if record:
+                q[1].record_stream(self.stream)
+                q[2].record_stream(self.stream)
             room, depth, rgb, K = q[0], q[1], q[2], q[3]
             seed = q[4] if len(q) > 4 else 0
             nh = q[5] if len(q) > 5 else 0
@@ -471,9 +507,11 @@ class Batch:
         _check(lib().rl_batch_relocalise(self.handle, arr, len(reqs), res, 1 if use_graph else 0))
         return [_result(r) for r in res]
 
-    def relocalise_async(self, reqs, dev_results, use_graph: bool = True):
-        """Queues the batch; dev_results: torch uint8 CUDA tensor of >= len(reqs) * sizeof(Result) bytes."""
-        arr = self._requests(reqs)
+    def relocalise_async(self, reqs, dev_results, use_graph: bool = True, record: bool = True):
+        """Queues the batch; dev_results: torch uint8 CUDA tensor of >= len(reqs) * sizeof(Result) bytes.
+        record=False: the frame tensors' memory is kept by the caller until the
+        batch has completed (no record_stream with torch's allocator)."""
+        arr = self._requests(reqs, record)
         dev_results.record_stream(self.stream)
         _check(lib().rl_batch_relocalise_async(self.handle, arr, len(reqs), dev_results.data_ptr(),
                                                1 if use_graph else 0))

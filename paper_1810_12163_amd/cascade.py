@@ -64,6 +64,16 @@ def paper_stages(thresholds=(0.05, 0.075)) -> list:
     ]
 
 
+def c3_stages(threshold: float) -> list:
+    """The cascade of the 640x480 workload on one forest: (a) the 2x decimated
+    frame with 256 hypotheses, (b) the full frame with 1024 hypotheses and the
+    inlier refit, (c) 4096 hypotheses kept down to 16, which the cascade ranks
+    by its model score.  Stages a and b fall back above ``threshold``."""
+    return [Stage("a", 256, decimate=True, threshold=threshold),
+            Stage("b", 1024, final_refine=1, threshold=threshold),
+            Stage("c", 4096, n_out=16)]
+
+
 def decimate(depth, rgb, K):
     """2x decimation on the device: pixel (x, y) <- (2x, 2y), intrinsics halved."""
     d = depth[::2, ::2].contiguous()

@@ -222,6 +222,13 @@ def render(room: Room, pose: np.ndarray, w: int, h: int, seed: int,
     r <= dropout, r ~ U[0,1].  Returns (depth float32 (h,w), rgb uint8 (h,w,3)).
     """
     z, rgb, _ = raycast(room, pose, w, h, K)
+    return corrupt(z, seed, noise_sigma, dropout, depth_rel_sigma), rgb
+
+
+def corrupt(z: np.ndarray, seed: int, noise_sigma: float = 0.002, dropout: float = 0.05,
+            depth_rel_sigma: float = 0.0) -> np.ndarray:
+    """The sensor model of render() applied to a noise-free depth map z
+    (inf where no surface): float32 depth, 0 = invalid."""
     rng = np.random.default_rng(seed)
     valid = np.isfinite(z) & (z >= DEPTH_MIN) & (z <= DEPTH_MAX)
     d = np.where(valid, z, 0.0)
@@ -233,7 +240,7 @@ def render(room: Room, pose: np.ndarray, w: int, h: int, seed: int,
         r = rng.uniform(0.0, 1.0, size=d.shape)
         d = np.where(r <= dropout, 0.0, d)
     d = np.where(d > 0, d, 0.0)
-    return d.astype(np.float32), rgb
+    return d.astype(np.float32)
 
 
 def _rot_axis(axis, ang):

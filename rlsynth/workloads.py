@@ -96,11 +96,16 @@ def room_setup(room_id: int, n_adapt: int, w: int = 640, h: int = 480, forest_cf
     return room, nodes, adapt
 
 
-def queries_for(room, adapt_poses, n, w=640, h=480, room_id=0, novel_fraction=0.0, start=0):
+def queries_for(room, adapt_poses, n, w=640, h=480, room_id=0, novel_fraction=0.0, start=0, processes=0):
     """Query frames near random adaptation poses; a ``novel_fraction`` of them
     are instead drawn >= 50 cm or >= 50 degrees away from every adaptation
-    pose (the paper's hardest novelty bin)."""
+    pose (the paper's hardest novelty bin).  ``room`` must be room ``room_id``
+    of make_room; with processes > 1 the frames are rendered in worker
+    processes (the same frames)."""
     poses = query_poses(room, adapt_poses, n, room_id, novel_fraction, start)
+    if processes and processes > 1:
+        return render_many([(room_id, p, w, h, frame_seed(room_id, 1, start + q)) for q, p in enumerate(poses)],
+                           processes)
     return [_frame(room, p, w, h, frame_seed(room_id, 1, start + q)) for q, p in enumerate(poses)]
 
 
@@ -168,6 +173,40 @@ def render_many(jobs, processes=None):
     ctx = mp.get_context("spawn")
     with ctx.Pool(processes) as pool:
         return pool.map(_render_job, jobs, chunksize=max(1, len(jobs) // (4 * processes)))
+
+
+def _sweep_job(job):
+    room_id, pose, w, h, seed, levels = job
+    room = _scene.make_room(room_id)
+    z, rgb, _ = _scene.raycast(room, pose, w, h)
+    K = _scene.intrinsics(w, h)
+    return [Frame(depth=_scene.corrupt(z, seed, **kw), rgb=rgb, pose=pose, K=K) for kw in levels]
+
+
+def c2_sweep(levels, room_id: int = 0, n_adapt: int = 50, n_queries: int = 16, processes: int = 0,
+             novel_fraction: float = 0.0):
+    """c2_corrupted for several sensor settings at once (a list of render
+    keywords: dropout, depth_rel_sigma): each pose is raycast once and every
+    setting's noise is drawn from the frame's own seed, so the frames equal
+    c2_corrupted's.  Returns one Workload per setting."""
+    room = _scene.make_room(room_id)
+    nodes = _forest.make_forest(1000 + room_id, **_presets.FOREST["c2"])
+    ap = adapt_poses_for(room, room_id, n_adapt)
+    qp = query_poses(room, ap, n_queries, room_id, novel_fraction=novel_fraction)
+    levels = [dict(dict(dropout=0.05, depth_rel_sigma=0.0), **kw) for kw in levels]
+    jobs = [(room_id, p, 640, 480, frame_seed(room_id, 0, i), levels) for i, p in enumerate(ap)]
+    jobs += [(room_id, p, 640, 480, frame_seed(room_id, 1, q), levels) for q, p in enumerate(qp)]
+    if processes and processes > 1 and len(jobs) >= 4:
+        import multiprocessing as mp
+        with mp.get_context("spawn").Pool(processes) as pool:
+            per_pose = pool.map(_sweep_job, jobs, chunksize=max(1, len(jobs) // (4 * processes)))
+    else:
+        per_pose = [_sweep_job(j) for j in jobs]
+    out = []
+    for li in range(len(levels)):
+        frames = [fr[li] for fr in per_pose]
+        out.append(Workload("c2", _presets.preset("c2"), room, nodes, frames[:n_adapt], frames[n_adapt:]))
+    return out
 
 
 RESOLUTIONS = [(160, 120), (320, 240), (640, 480)]

@@ -3,6 +3,7 @@
 it), batches respect their cap, admission refuses beyond the queue bound and
 every request is eventually issued."""
 import collections
+import os
 import random
 
 import pytest
@@ -93,9 +94,114 @@ def test_admission_refuses_beyond_the_queue_bound():
     from paper_1810_12163_amd import serve
     s = serve.Server.__new__(serve.Server)          # policy-only: no device state needed
     s.pending = collections.deque()
+    s.backlog = collections.deque()
     s.refused = []
+    s.host_s = collections.Counter()
     s.max_queue = 3
     rooms = [FakeRoom(0)]
     ok = [s.admit(Request(i, "relocalise", rooms[0]), float(i)) for i in range(5)]
     assert ok == [True, True, True, False, False]
     assert [q.rid for q in s.refused] == [3, 4] and all(q.refused for q in s.refused)
+
+
+def _policy_server(n_slots, max_queue=64, budget=None):
+    """A server reduced to its admission state, with a frame pool in host
+    memory (no device work)."""
+    from paper_1810_12163_amd import serve
+    s = serve.Server.__new__(serve.Server)
+    s.pending = collections.deque()
+    s.backlog = collections.deque()
+    s.refused = []
+    s.deferred = 0
+    s.max_backlog = 0
+    s.max_queue = max_queue
+    s.host_s = collections.Counter()
+    s.ledger = serve.Ledger(budget)
+    s.pool = serve.FramePool(n_slots, 16, 8, "cpu") if n_slots else None
+    return s
+
+
+def _host_req(i, room, h=8, w=16):
+    import torch
+    from paper_1810_12163_amd.serve import Request
+    d = torch.full((h, w), float(i), dtype=torch.float32)
+    c = torch.full((h, w, 3), i % 256, dtype=torch.uint8)
+    return Request(i, "relocalise", room, host_depth=d, host_rgb=c)
+
+
+def test_requests_wait_for_frame_slots_in_arrival_order():
+    """With two frame slots, later requests wait in the backlog (not refused)
+    and take slots in arrival order as earlier requests release theirs; the
+    frame copied into a slot is the request's own."""
+    pytest.importorskip("torch")
+    s = _policy_server(2)
+    room = FakeRoom(0)
+    reqs = [_host_req(i, room) for i in range(5)]
+    assert all(s.admit(q, float(i)) for i, q in enumerate(reqs))
+    assert [q.rid for q in s.pending] == [0, 1] and [q.rid for q in s.backlog] == [2, 3, 4]
+    assert s.deferred == 3 and s.max_backlog == 3 and not s.refused
+    for q in list(s.pending):
+        assert float(q.depth[0, 0]) == q.rid and int(q.rgb[0, 0, 0]) == q.rid
+    s._release(s.pending.popleft())          # request 0 completes
+    s._refill()
+    assert [q.rid for q in s.pending] == [1, 2] and [q.rid for q in s.backlog] == [3, 4]
+    assert float(s.pending[1].depth[0, 0]) == 2.0
+    # a smaller frame uses the head of a slot
+    small = _host_req(9, room, h=4, w=8)
+    s._release(s.pending.popleft())
+    s._release(s.pending.popleft())
+    s._refill()
+    assert [q.rid for q in s.pending] == [3, 4] and not s.backlog
+    assert s.admit(small, 9.0) is True and s.backlog[0] is small     # no free slot: waits
+    s._release(s.pending.popleft())
+    s._refill()
+    assert small.depth.shape == (4, 8) and float(small.depth[3, 7]) == 9.0
+
+
+def test_queue_bound_counts_waiting_requests():
+    pytest.importorskip("torch")
+    s = _policy_server(1, max_queue=3)
+    room = FakeRoom(0)
+    ok = [s.admit(_host_req(i, room), float(i)) for i in range(5)]
+    assert ok == [True, True, True, False, False]
+    assert len(s.pending) == 1 and len(s.backlog) == 2 and len(s.refused) == 2
+
+
+def test_ledger_refuses_what_does_not_fit():
+    from paper_1810_12163_amd.serve import Ledger
+    led = Ledger(100)
+    assert led.charge("a", 60) and led.used == 60
+    assert not led.charge("b", 41) and "b" not in led.items
+    assert led.charge("b", 40) and led.used == 100 and not led.fits(1)
+    led.release("a")
+    assert led.fits(60) and not led.fits(61)
+    assert Ledger(None).charge("x", 1 << 60)
+
+
+def test_room_admission_by_budget():
+    """A room whose persistent state and scratch exceed what is left of the
+    budget is refused before any device memory is taken."""
+    rl = pytest.importorskip("paper_1810_12163_amd")
+    if not os.path.exists(rl.LIB_PATH):
+        pytest.skip("librl.so not built")
+    pb, sb = rl.room_state_bytes(rl.preset("c2"), 640, 480)
+    s = _policy_server(0, budget=pb + sb - 1)
+    s.rooms = []
+    s.max_width, s.max_height = 640, 480
+    assert s.create_room(rl.preset("c2"), None) is None and s.ledger.used == 0
+
+
+def test_one_buffer_host_frame_lands_in_its_slot():
+    """A frame packed as one host buffer (depth bytes, then colour bytes) is
+    copied into a slot in one piece; the slot's views give back the frame."""
+    torch = pytest.importorskip("torch")
+    import numpy as np
+    from paper_1810_12163_amd.serve import Request
+    s = _policy_server(1)
+    rng = np.random.default_rng(0)
+    d = rng.uniform(0.5, 4.0, size=(4, 8)).astype(np.float32)
+    c = rng.integers(0, 256, size=(4, 8, 3), dtype=np.uint8)
+    buf = torch.from_numpy(np.concatenate([d.view(np.uint8).reshape(-1), c.reshape(-1)]))
+    q = Request(0, "relocalise", FakeRoom(0), host_frame=buf, frame_hw=(4, 8))
+    assert s.admit(q, 0.0) and q.slot == 0
+    assert np.array_equal(q.depth.numpy(), d) and np.array_equal(q.rgb.numpy(), c)
