@@ -470,9 +470,12 @@ def c1_leg(args, rl, dev, w1):
     return out
 
 
-# fallback threshold of the three-stage cascade on the winner's mean Eq. 5
-# energy over its final pixel set (E / |I|)
-C3_ENERGY_THRESHOLD = 1.0
+# fallback thresholds of the three-stage cascade on the plane score of a
+# stage's pose (metres): the paper's 5 cm after the first stage, 7.5 cm after
+# the second.  The winner's mean Eq. 5 energy does not separate right from
+# wrong poses on these rooms (its median is higher for correct poses), so the
+# fallback uses the model-based score as the paper's cascade does.
+C3_THRESHOLDS = (0.05, 0.075)
 
 
 def c3_leg(args, rl, dev, w, queries):
@@ -480,8 +483,8 @@ def c3_leg(args, rl, dev, w, queries):
     (a) the 2x decimated 320x240 frame with 256 hypotheses, (b) the full frame
     with 1024 hypotheses and the inlier refit, (c) 4096 hypotheses culled to
     16, re-ranked by the plane score (mean distance of the back-projected depth
-    to the nearest surface).  A stage falls back when its winner's mean energy
-    exceeds the threshold.  30% of the queries lie >= 50 cm or >= 50 deg from
+    to the nearest surface).  A stage falls back when the plane score of its
+    pose exceeds 5 cm (stage a) or 7.5 cm (stage b).  30% of the queries lie >= 50 cm or >= 50 deg from
     every adaptation pose.  Frames one at a time: latency, stage reached,
     accuracy."""
     import torch
@@ -495,8 +498,8 @@ def c3_leg(args, rl, dev, w, queries):
     for f in w.adapt:
         room.adapt(torch.from_numpy(f.depth).to(dev), torch.from_numpy(f.rgb).to(dev), f.K, f.pose)
     room.update_modes()
-    cas = Cascade(room, c3_stages(C3_ENERGY_THRESHOLD), scene.surface_records(w.room), model="plane",
-                  fallback="energy")
+    cas = Cascade(room, c3_stages(C3_THRESHOLDS), scene.surface_records(w.room), model="plane",
+                  fallback="model")
     adapt_poses = [f.pose for f in w.adapt]
     for k in range(3):                                   # graph capture of each stage's shape
         q = queries[k]
@@ -511,7 +514,7 @@ def c3_leg(args, rl, dev, w, queries):
         stages.append(out["stage"])
         e = scene.pose_error(out["pose"].astype(np.float64), q.pose) if out["status"] == "ok" else (np.inf, np.inf)
         errs.append(e)
-        energies.append((out["trail"][0][1], e[0] <= 0.05 and e[1] <= 5.0))
+        energies.append((out.get("mean_energy", np.inf), e[0] <= 0.05 and e[1] <= 5.0))
         novel.append(all(scene.pose_error(q.pose, a)[0] >= 0.5 or scene.pose_error(q.pose, a)[1] >= 50.0
                          for a in adapt_poses))
     room.close()
@@ -524,14 +527,14 @@ def c3_leg(args, rl, dev, w, queries):
                frac_within_5cm_5deg=float(np.mean(ok)),
                frac_within_5cm_5deg_near=float(np.mean(ok[~nv])) if np.any(~nv) else None,
                frac_within_5cm_5deg_novel=float(np.mean(ok[nv])) if np.any(nv) else None,
-               novel_fraction=float(np.mean(nv)), energy_threshold=C3_ENERGY_THRESHOLD,
-               stage_a_mean_energy_correct=float(np.median(first[ok])) if np.any(ok) else None,
-               stage_a_mean_energy_wrong=float(np.median(first[~ok])) if np.any(~ok) else None,
+               novel_fraction=float(np.mean(nv)), thresholds_m=list(C3_THRESHOLDS),
+               mean_energy_median_correct=float(np.median(first[ok])) if np.any(ok) else None,
+               mean_energy_median_wrong=float(np.median(first[~ok])) if np.any(~ok) else None,
                median_cm=float(np.median([e[0] for e in errs]) * 100))
     log(f"[bench] c3 cascade: {res['mean_ms']:.2f} ms per frame (p50 {res['p50_ms']:.2f}, p99 {res['p99_ms']:.2f}), "
         f"stages {res['stage_counts']}, within 5cm/5deg {res['frac_within_5cm_5deg']:.3f} "
-        f"(near {res['frac_within_5cm_5deg_near']}, novel {res['frac_within_5cm_5deg_novel']}); stage-a mean "
-        f"energy median correct {res['stage_a_mean_energy_correct']} / wrong {res['stage_a_mean_energy_wrong']}")
+        f"(near {res['frac_within_5cm_5deg_near']}, novel {res['frac_within_5cm_5deg_novel']}); returned pose's "
+        f"mean energy, median: correct {res['mean_energy_median_correct']} / wrong {res['mean_energy_median_wrong']}")
     return res
 
 

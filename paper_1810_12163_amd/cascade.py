@@ -64,13 +64,14 @@ def paper_stages(thresholds=(0.05, 0.075)) -> list:
     ]
 
 
-def c3_stages(threshold: float) -> list:
+def c3_stages(thresholds=(0.05, 0.075)) -> list:
     """The cascade of the 640x480 workload on one forest: (a) the 2x decimated
     frame with 256 hypotheses, (b) the full frame with 1024 hypotheses and the
     inlier refit, (c) 4096 hypotheses kept down to 16, which the cascade ranks
-    by its model score.  Stages a and b fall back above ``threshold``."""
-    return [Stage("a", 256, decimate=True, threshold=threshold),
-            Stage("b", 1024, final_refine=1, threshold=threshold),
+    by its model score.  Stage a falls back above thresholds[0], stage b above
+    thresholds[1] (the paper's 5 cm and 7.5 cm by default)."""
+    return [Stage("a", 256, decimate=True, threshold=thresholds[0]),
+            Stage("b", 1024, final_refine=1, threshold=thresholds[1]),
             Stage("c", 4096, n_out=16)]
 
 
