@@ -777,23 +777,39 @@ def serve_leg(args, rl, dev, inputs):
         mb.relocalise(breqs)
     torch.cuda.synchronize()
     el_r = time.perf_counter() - t1
+    # the 16 adaptations inside the batch, after its relocalisations
+    areqs = breqs + [rl.AdaptRequest(room, d, rgb, f.K, f.pose) for room, d, rgb, f in adapts]
+    mba = rl.Batch(80, 640, 480, 1024, 500, 10, 5, 50, device=dev)
+    mba.set_schedule(*mb_sched)
+    for _ in range(2):
+        mba.relocalise(areqs)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        mba.relocalise(areqs)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    # the same adaptations as separate calls on the rooms' streams
     t1 = time.perf_counter()
     for _ in range(steps):
         mb.relocalise(breqs)
         for room, d, rgb, f in adapts:
             room.adapt(d, rgb, f.K, f.pose)
     torch.cuda.synchronize()
-    el = time.perf_counter() - t1
+    el_sep = time.perf_counter() - t1
     mb.close()
+    mba.close()
     mix = collections.Counter(camf[c][k][2].w for c, k in picks)
     out["mixed_batch"] = dict(relocs_per_s=64 * steps / el_r, ms_per_batch=el_r / steps * 1e3,
                               relocs_per_s_with_adapt=64 * steps / el, ms_per_step_with_adapt=el / steps * 1e3,
+                              ms_per_step_with_separate_adapt_calls=el_sep / steps * 1e3,
                               rooms=8, widths={str(k): v for k, v in sorted(mix.items())}, adapts_per_step=16,
                               schedule=list(mb_sched))
     mbo = out["mixed_batch"]
     log(f"[bench] mixed batch (8 rooms, {dict(mix)} by width, schedule {mb_sched}): {mbo['relocs_per_s']:.1f} reloc/s "
-        f"({mbo['ms_per_batch']:.2f} ms per 64-frame batch); with 16 adaptations per step "
-        f"{mbo['relocs_per_s_with_adapt']:.1f} reloc/s ({mbo['ms_per_step_with_adapt']:.2f} ms)")
+        f"({mbo['ms_per_batch']:.2f} ms per 64-frame batch); with 16 adaptations in the batch "
+        f"{mbo['relocs_per_s_with_adapt']:.1f} reloc/s ({mbo['ms_per_step_with_adapt']:.2f} ms; as separate calls "
+        f"{mbo['ms_per_step_with_separate_adapt_calls']:.2f} ms)")
     del camf
     warm = 2.0
     rates = [(float(v), args.serve_seconds) for v in args.serve_rates.split(",") if v] + \

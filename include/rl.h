@@ -388,12 +388,24 @@ typedef struct {
     int32_t max_modes_per_pixel; /* largest n_trees * M_max                    */
 } rl_batch_params;
 
+/* Request kinds of a batch. */
+enum { RL_REQ_RELOCALISE = 0, RL_REQ_ADAPT = 1 };
+
+/*
+ * One request of a batch.  kind RL_REQ_RELOCALISE: relocalise frame in room
+ * (Sec. 3.2.3); cam_to_world is ignored.  kind RL_REQ_ADAPT: online
+ * adaptation of room by frame at the reliable pose cam_to_world (Sec. 3.2.2,
+ * as relocaliser_adapt with reliable != 0; camera->world, 4x4 row-major, must
+ * be rigid); request_seed, n_hypotheses and pose_update are ignored.
+ */
 typedef struct {
     rl_room* room;
     rl_frame frame;
     uint64_t request_seed;
     int32_t n_hypotheses;    /* 0 = the room's max_pose_candidates              */
     int32_t pose_update;     /* LM refinement: 0 = the room's value, 1 = on, -1 = off */
+    int32_t kind;            /* RL_REQ_RELOCALISE or RL_REQ_ADAPT               */
+    float cam_to_world[16];  /* RL_REQ_ADAPT: the frame's pose                  */
 } rl_request;
 
 /* Device workspace bytes of a batch context (256-byte aligned buffer); the
@@ -405,12 +417,24 @@ rl_status rl_batch_create(const rl_batch_params* bp, void* dev_workspace, void* 
 rl_status rl_batch_destroy(rl_batch* b);
 
 /*
- * Relocalises n <= max_frames requests with one launch sequence on the
- * batch's stream.  Every room's modes are brought up to date first.  The
- * result for request i is identical to relocaliser_relocalise_ex on the same
- * room, frame and request_seed.  results: host array of n records; the call
- * is synchronous.  use_graph != 0 captures the launch sequence for this batch
- * shape once and replays it on later calls with the same shape.
+ * Runs n <= max_frames requests on the batch's stream: the relocalisations
+ * as one launch sequence, then the adaptations in request order (a snapshot:
+ * every relocalisation of the batch sees the rooms as they were before the
+ * batch's adaptations).  Every room's modes are brought up to date first.
+ * The result for relocalisation request i is identical to
+ * relocaliser_relocalise_ex on the same room, frame and request_seed, and the
+ * rooms afterwards equal those of relocaliser_adapt calls of the adaptation
+ * requests in order (under either mode schedule); the record of an
+ * adaptation request has status RL_OK, winner -1 and the identity pose.
+ * An adaptation runs on its room's stream, after the batch's
+ * relocalisations and the work already queued there (a room's adaptations in
+ * request order, different rooms concurrently); the batch completes after
+ * all of them.  results: host array of n records; the call is
+ * synchronous.  use_graph != 0 captures the relocalisations' launch sequence
+ * for this batch shape once and replays it on later calls with the same
+ * shape (adaptations are launched directly).  RL_EINVAL for an unknown kind,
+ * a frame beyond the batch's limits (relocalisation) or the room's
+ * (adaptation), or a pose that is not rigid.
  */
 rl_status rl_batch_relocalise(rl_batch* b, const rl_request* reqs, int32_t n, rl_result* results,
                               int32_t use_graph);

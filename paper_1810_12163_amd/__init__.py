@@ -106,7 +106,20 @@ class RelocOpts(ctypes.Structure):
 
 class Request(ctypes.Structure):
     _fields_ = [("room", ctypes.c_void_p), ("frame", Frame), ("request_seed", ctypes.c_uint64),
-                ("n_hypotheses", ctypes.c_int32), ("pose_update", ctypes.c_int32)]
+                ("n_hypotheses", ctypes.c_int32), ("pose_update", ctypes.c_int32), ("kind", ctypes.c_int32),
+                ("cam_to_world", ctypes.c_float * 16)]
+
+
+REQ_RELOCALISE, REQ_ADAPT = 0, 1
+
+
+class AdaptRequest:
+    """An adaptation request of a batch: room, frame (CUDA tensors, intrinsics)
+    and the frame's camera->world pose."""
+    __slots__ = ("room", "depth", "rgb", "K", "pose")
+
+    def __init__(self, room, depth, rgb, K, pose):
+        self.room, self.depth, self.rgb, self.K, self.pose = room, depth, rgb, K, pose
 
 
 class ForestParams(ctypes.Structure):
@@ -485,6 +498,17 @@ class Batch:
         self.stream.wait_stream(torch.cuda.current_stream(self.device))   # frames were made there
         arr = (Request * len(reqs))()
         for i, q in enumerate(reqs):
+            if isinstance(q, AdaptRequest):
+                if record:
+                    q.depth.record_stream(self.stream)
+                    q.rgb.record_stream(self.stream)
+                arr[i].room = q.room.handle
+                arr[i].frame = _frame(q.depth, q.rgb, q.K)
+                arr[i].kind = REQ_ADAPT
+                H = np.asarray(q.pose, dtype=np.float32).reshape(16)
+                for k in range(16):
+                    arr[i].cam_to_world[k] = float(H[k])
+                continue
             if record:
                 q[1].record_stream(self.stream)
                 q[2].record_stream(self.stream)
@@ -500,8 +524,9 @@ class Batch:
         return arr
 
     def relocalise(self, reqs, use_graph: bool = True) -> list:
-        """reqs: sequence of (room, depth, rgb, K[, request_seed[, n_hypotheses[, pose_update]]]);
-        pose_update 0 = the room's value, 1 = LM on, -1 = off."""
+        """reqs: sequence of (room, depth, rgb, K[, request_seed[, n_hypotheses[, pose_update]]]) and
+        AdaptRequest; pose_update 0 = the room's value, 1 = LM on, -1 = off.  The adaptations run after
+        every relocalisation of the batch, in order."""
         arr = self._requests(reqs)
         res = (Result * len(reqs))()
         _check(lib().rl_batch_relocalise(self.handle, arr, len(reqs), res, 1 if use_graph else 0))

@@ -156,6 +156,7 @@ struct AdaptArgs {
     uint32_t* hval;           // [hmask + 1] largest arrival number drawing that slot, 0 when empty
     int Gp;                   // chunks * kAdaptChunk
     uint32_t hmask;           // hash-table size - 1 (size a power of two >= 2 T G)
+    rl_result* result;        // batched adaptation: its result record (status RL_OK), else NULL
 };
 
 constexpr int kAdaptChunk = 1024;

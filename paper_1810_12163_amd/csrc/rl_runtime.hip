@@ -343,6 +343,9 @@ struct rl_room {
     // that read it since then (a pool, reused).
     hipEvent_t wev;
     bool wrote;
+    // batched adaptations run on the room's stream; bev marks their end for
+    // the batch's stream to wait on
+    hipEvent_t bev;
     std::vector<hipEvent_t> readers, spare;
     Job* job_host;
     rl_result* res_host;
@@ -366,6 +369,7 @@ struct rl_batch {
     char* ws;
     hipStream_t stream;
     hipEvent_t ev;
+    hipEvent_t mark;          // end of the relocalisations, for the rooms' adaptations to wait on
     int TP, rows;
     size_t jobs_off, results_off;
     std::vector<FrameLayout> slots;
@@ -665,8 +669,10 @@ RL_API rl_status relocaliser_create(const rl_params* p, const rl_node* host_node
     r->rr_cursor = 0;
     hipError_t e = hipEventCreateWithFlags(&r->ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&r->wev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&r->bev, hipEventDisableTiming);
     if (e != hipSuccess) {
-        if (r->ev) (void)hipEventDestroy(r->ev);
+        for (hipEvent_t ev : {r->ev, r->wev, r->bev})
+            if (ev) (void)hipEventDestroy(ev);
         delete r;
         return hip_fail(e, "hipEventCreate");
     }
@@ -679,8 +685,7 @@ RL_API rl_status relocaliser_create(const rl_params* p, const rl_node* host_node
     if (e != hipSuccess) {
         for (void* hp : {(void*)r->job_host, (void*)r->res_host, (void*)r->model_host})
             if (hp) (void)hipHostFree(hp);
-        (void)hipEventDestroy(r->ev);
-        (void)hipEventDestroy(r->wev);
+        for (hipEvent_t ev : {r->ev, r->wev, r->bev}) (void)hipEventDestroy(ev);
         delete r;
         return fail(RL_ENOMEM, "pinned host allocation failed: %s", hipGetErrorString(e));
     }
@@ -720,8 +725,8 @@ RL_API rl_status relocaliser_destroy(rl_room* r)
     if (r->job_host) (void)hipHostFree(r->job_host);
     if (r->res_host) (void)hipHostFree(r->res_host);
     if (r->model_host) (void)hipHostFree(r->model_host);
-    if (r->ev) (void)hipEventDestroy(r->ev);
-    if (r->wev) (void)hipEventDestroy(r->wev);
+    for (hipEvent_t ev : {r->ev, r->wev, r->bev})
+        if (ev) (void)hipEventDestroy(ev);
     for (hipEvent_t ev : r->readers) {
         (void)hipEventSynchronize(ev);      // recorded on a batch stream that may still run
         (void)hipEventDestroy(ev);
@@ -882,13 +887,8 @@ RL_API rl_status relocaliser_set_trace(rl_room* r, int32_t on)
     return RL_OK;
 }
 
-static rl_status round_robin_step(rl_room* r);
-
-RL_API rl_status relocaliser_adapt(rl_room* r, const rl_frame* f, const float H[16], int32_t reliable)
+static rl_status check_pose(const float* H)
 {
-    if (!r) return fail(RL_EINVAL, "room is NULL");
-    rl_status s = validate_frame(f, r->max_w, r->max_h);
-    if (s != RL_OK) return s;
     if (!H) return fail(RL_EINVAL, "pose is NULL");
     for (int i = 0; i < 16; ++i)
         if (!finite_f(H[i])) return fail(RL_EINVAL, "pose has a non-finite entry");
@@ -900,7 +900,12 @@ RL_API rl_status relocaliser_adapt(rl_room* r, const rl_frame* f, const float H[
         }
     if (std::fabs(H[12]) > 1e-6f || std::fabs(H[13]) > 1e-6f || std::fabs(H[14]) > 1e-6f || std::fabs(H[15] - 1.0f) > 1e-6f)
         return fail(RL_EINVAL, "pose last row must be 0 0 0 1");
-    if (!reliable) return RL_OK;
+    return RL_OK;
+}
+
+// Arguments of one adaptation of room r by frame f at pose H (validated).
+static AdaptArgs adapt_args(const rl_room* r, const rl_frame* f, const float H[16])
+{
     AdaptArgs a;
     std::memset(&a, 0, sizeof(a));
     a.nodes = reinterpret_cast<const float4*>(r->pers + r->PL.nodes);
@@ -947,25 +952,36 @@ RL_API rl_status relocaliser_adapt(rl_room* r, const rl_frame* f, const float H[
     a.hval = reinterpret_cast<uint32_t*>(sc + A.hval);
     a.Gp = (a.G + kAdaptChunk - 1) / kAdaptChunk * kAdaptChunk;
     a.hmask = A.hsize - 1;
-    const hipError_t e = launch_adapt(a, r->stream);
-    if (e != hipSuccess) return hip_fail(e, "adapt launch");
-    r->modes_stale = true;
-    return r->rr_leaves ? round_robin_step(r) : RL_OK;
+    a.result = nullptr;
+    return a;
 }
 
-// Brings the modes up to date on the room's stream: after every batch that
-// read the old modes (write-after-read), and marked by wev for batches that
-// read the new ones.
-static rl_status write_modes(rl_room* r, const RqsArgs& a)
+static rl_status round_robin_step(rl_room* r, hipStream_t st);
+
+RL_API rl_status relocaliser_adapt(rl_room* r, const rl_frame* f, const float H[16], int32_t reliable)
+{
+    if (!r) return fail(RL_EINVAL, "room is NULL");
+    rl_status s = validate_frame(f, r->max_w, r->max_h);
+    if (s != RL_OK) return s;
+    s = check_pose(H);
+    if (s != RL_OK) return s;
+    if (!reliable) return RL_OK;
+    const hipError_t e = launch_adapt(adapt_args(r, f, H), r->stream);
+    if (e != hipSuccess) return hip_fail(e, "adapt launch");
+    r->modes_stale = true;
+    return r->rr_leaves ? round_robin_step(r, r->stream) : RL_OK;
+}
+
+static rl_status write_modes(rl_room* r, const RqsArgs& a, hipStream_t st)
 {
     hipError_t e = hipSuccess;
     for (hipEvent_t ev : r->readers) {
-        if (e == hipSuccess) e = hipStreamWaitEvent(r->stream, ev, 0);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, ev, 0);
         r->spare.push_back(ev);
     }
     r->readers.clear();
-    if (e == hipSuccess) e = launch_rqs(a, 1024, r->stream);
-    if (e == hipSuccess) e = hipEventRecord(r->wev, r->stream);
+    if (e == hipSuccess) e = launch_rqs(a, 1024, st);
+    if (e == hipSuccess) e = hipEventRecord(r->wev, st);
     if (e != hipSuccess) return hip_fail(e, "mode update launch");
     r->wrote = true;
     return RL_OK;
@@ -975,7 +991,7 @@ static rl_status write_modes(rl_room* r, const RqsArgs& a)
 static rl_status update_dirty_modes(rl_room* r)
 {
     if (!r->modes_stale) return RL_OK;
-    const rl_status s = write_modes(r, rqs_args(r));
+    const rl_status s = write_modes(r, rqs_args(r), r->stream);
     if (s == RL_OK) r->modes_stale = false;
     return s;
 }
@@ -989,12 +1005,12 @@ static rl_status ensure_modes(rl_room* r)
 
 // Round-robin schedule (Sec. 3.2.2): after each adapted frame, the next K
 // leaves of the forest in index order, wrapping around.
-static rl_status round_robin_step(rl_room* r)
+static rl_status round_robin_step(rl_room* r, hipStream_t st)
 {
     RqsArgs a = rqs_args(r);
     a.rr_first = r->rr_cursor;
     a.rr_count = (uint32_t)r->rr_leaves;
-    const rl_status s = write_modes(r, a);
+    const rl_status s = write_modes(r, a, st);
     if (s == RL_OK) r->rr_cursor = (uint32_t)((r->rr_cursor + (uint64_t)r->rr_leaves) % a.n_leaves);
     return s;
 }
@@ -1499,6 +1515,7 @@ RL_API rl_status rl_batch_create(const rl_batch_params* bp, void* ws, void* hip_
         b->up_ev[k] = nullptr;
     }
     hipError_t e = hipEventCreateWithFlags(&b->ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->mark, hipEventDisableTiming);
     for (int k = 0; k < kJobRing && e == hipSuccess; ++k) {
         e = hipEventCreateWithFlags(&b->up_ev[k], hipEventDisableTiming);
         if (e == hipSuccess)
@@ -1527,56 +1544,30 @@ RL_API rl_status rl_batch_destroy(rl_batch* b)
     }
     if (b->res_host) (void)hipHostFree(b->res_host);
     if (b->ev) (void)hipEventDestroy(b->ev);
+    if (b->mark) (void)hipEventDestroy(b->mark);
     delete b;
     return RL_OK;
 }
 
-RL_API rl_status rl_batch_relocalise_async(rl_batch* b, const rl_request* reqs, int32_t n, rl_result* dev_results,
-                                           int32_t use_graph)
+// The relocalisation requests of a batch (indices reloc into reqs) as one
+// launch sequence on the batch's stream.
+static rl_status batch_relocalise_queue(rl_batch* b, const rl_request* reqs, const std::vector<int>& reloc,
+                                        rl_result* dev_results, int maxN, int maxIters, int maxEta, bool any_lm,
+                                        int lm_iters, const std::vector<int>& entering, int32_t use_graph)
 {
-    if (!b || !reqs || !dev_results) return fail(RL_EINVAL, "NULL argument");
-    if (n < 1 || n > b->bp.max_frames) return fail(RL_EINVAL, "batch of %d requests (1..%d allowed)", n, b->bp.max_frames);
-    int maxP = 0, maxN = 0, maxIters = 0, maxEta = 0;
-    bool any_lm = false;
-    int lm_iters = 0;
-    std::vector<int> entering;
-    for (int i = 0; i < n; ++i) {
-        const rl_request& q = reqs[i];
-        rl_room* r = q.room;
-        if (!r) return fail(RL_EINVAL, "request %d: room is NULL", i);
-        rl_status s = validate_frame(&q.frame, b->bp.max_width, b->bp.max_height);
-        if (s != RL_OK) return fail(s, "request %d: %s", i, g_err.c_str());
-        if (r->T != b->bp.n_trees) return fail(RL_EINVAL, "request %d: room has %d trees, batch %d", i, r->T, b->bp.n_trees);
-        if (r->T * r->M > b->rows) return fail(RL_EINVAL, "request %d: room has up to %d modes per pixel, batch %d", i, r->T * r->M, b->rows);
-        const int N = q.n_hypotheses > 0 ? q.n_hypotheses : r->N;
-        if (N > b->bp.max_hypotheses || N > 4096) return fail(RL_EINVAL, "request %d: %d hypotheses exceed the batch maximum", i, N);
-        if (r->eta > b->bp.max_eta) return fail(RL_EINVAL, "request %d: eta exceeds the batch maximum", i);
-        std::vector<int> ent;
-        const int R = rounds_for(N, r->p.max_pose_candidates_after_cull, r->p.max_relocalisations_to_output, &ent);
-        if (R > b->bp.max_rounds) return fail(RL_EINVAL, "request %d: %d rounds exceed the batch maximum", i, R);
-        if (ent.size() > entering.size()) entering.resize(ent.size(), 0);
-        for (size_t k = 0; k < ent.size(); ++k) entering[k] = std::max(entering[k], ent[k]);
-        maxP = std::max(maxP, q.frame.width * q.frame.height);
-        maxN = std::max(maxN, N);
-        maxIters = std::max(maxIters, r->p.max_candidate_generation_iterations);
-        maxEta = std::max(maxEta, r->eta);
-        if (q.pose_update < -1 || q.pose_update > 1) return fail(RL_EINVAL, "request %d: pose_update must be -1, 0 or 1", i);
-        const bool lm = q.pose_update == 0 ? r->p.pose_update != 0 : q.pose_update > 0;
-        any_lm = any_lm || lm;
-        if (lm) lm_iters = std::max(lm_iters, r->p.lm_iterations);
-    }
     // Launch shapes come in few classes so that few graphs are captured:
     // grids cover the batch's largest frame, and the job count is padded to
     // a power of two with empty jobs (no pixels, no hypotheses), which every
     // kernel leaves at once.
-    maxP = b->bp.max_width * b->bp.max_height;
+    const int maxP = b->bp.max_width * b->bp.max_height;
+    const int n = (int)reloc.size();
     int nq = 1;
     while (nq < n) nq *= 2;
     nq = std::min(nq, b->bp.max_frames);
     // each room: mode update if stale (on the room's stream, after the batches
     // that read the old modes), and this batch after the last update
     std::vector<rl_room*> rooms;
-    for (int i = 0; i < n; ++i)
+    for (int i : reloc)
         if (std::find(rooms.begin(), rooms.end(), reqs[i].room) == rooms.end()) rooms.push_back(reqs[i].room);
     for (rl_room* r : rooms) {
         rl_status s = room_read_begin(r, b->stream);
@@ -1591,10 +1582,10 @@ RL_API rl_status rl_batch_relocalise_async(rl_batch* b, const rl_request* reqs, 
     for (int i = 0; i < nq; ++i) {
         Job J;
         if (i < n) {
-            const rl_request& q = reqs[i];
+            const rl_request& q = reqs[reloc[i]];
             const int N = q.n_hypotheses > 0 ? q.n_hypotheses : q.room->N;
             J = make_job(q.room, b->ws, b->slots[i], &q.frame, q.request_seed, N);
-            J.result = dev_results + i;
+            J.result = dev_results + reloc[i];
             if (q.pose_update != 0) J.lm = q.pose_update > 0 ? 1 : 0;
         } else {
             std::memset(&J, 0, sizeof(J));
@@ -1625,13 +1616,104 @@ RL_API rl_status rl_batch_relocalise_async(rl_batch* b, const rl_request* reqs, 
                                lm_iters, b->sched, b->timer, b->stream);
     });
     if (e != hipSuccess) return hip_fail(e, "batch launch");
-    e = hipEventRecord(b->ev, b->stream);
-    if (e != hipSuccess) return hip_fail(e, "batch event");
     // the next mode update of each room waits for this batch
     for (rl_room* r : rooms) {
         rl_status s = room_read_end(r, b->stream);
         if (s != RL_OK) return s;
     }
+    return RL_OK;
+}
+
+// The adaptation requests of a batch: each on its room's stream, after the
+// batch's relocalisations (event mark on the batch's stream) and after the
+// work queued so far on the room's stream; a room's adaptations in request
+// order, different rooms concurrently.  The batch's stream then waits for
+// every one of them.
+static rl_status batch_adapt(rl_batch* b, const rl_request* reqs, const std::vector<int>& adapt,
+                             rl_result* dev_results)
+{
+    hipError_t e = hipEventRecord(b->mark, b->stream);
+    if (e != hipSuccess) return hip_fail(e, "batched adaptation ordering");
+    std::vector<rl_room*> rooms;
+    for (int i : adapt) {
+        rl_room* r = reqs[i].room;
+        if (std::find(rooms.begin(), rooms.end(), r) == rooms.end()) {
+            rooms.push_back(r);
+            e = hipStreamWaitEvent(r->stream, b->mark, 0);
+            if (e != hipSuccess) return hip_fail(e, "batched adaptation ordering");
+        }
+        AdaptArgs a = adapt_args(r, &reqs[i].frame, reqs[i].cam_to_world);
+        a.result = dev_results + i;
+        e = launch_adapt(a, r->stream);
+        if (e != hipSuccess) return hip_fail(e, "batched adaptation");
+        r->modes_stale = true;
+        if (r->rr_leaves) {
+            const rl_status s = round_robin_step(r, r->stream);
+            if (s != RL_OK) return s;
+        }
+    }
+    for (rl_room* r : rooms) {
+        e = hipEventRecord(r->bev, r->stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, r->bev, 0);
+        if (e != hipSuccess) return hip_fail(e, "batched adaptation ordering");
+    }
+    return RL_OK;
+}
+
+RL_API rl_status rl_batch_relocalise_async(rl_batch* b, const rl_request* reqs, int32_t n, rl_result* dev_results,
+                                           int32_t use_graph)
+{
+    if (!b || !reqs || !dev_results) return fail(RL_EINVAL, "NULL argument");
+    if (n < 1 || n > b->bp.max_frames) return fail(RL_EINVAL, "batch of %d requests (1..%d allowed)", n, b->bp.max_frames);
+    int maxN = 0, maxIters = 0, maxEta = 0;
+    bool any_lm = false;
+    int lm_iters = 0;
+    std::vector<int> entering, reloc, adapt;
+    for (int i = 0; i < n; ++i) {
+        const rl_request& q = reqs[i];
+        rl_room* r = q.room;
+        if (!r) return fail(RL_EINVAL, "request %d: room is NULL", i);
+        if (q.kind == RL_REQ_ADAPT) {
+            rl_status s = validate_frame(&q.frame, r->max_w, r->max_h);
+            if (s == RL_OK) s = check_pose(q.cam_to_world);
+            if (s != RL_OK) return fail(s, "request %d: %s", i, g_err.c_str());
+            adapt.push_back(i);
+            continue;
+        }
+        if (q.kind != RL_REQ_RELOCALISE) return fail(RL_EINVAL, "request %d: kind must be 0 or 1", i);
+        reloc.push_back(i);
+        rl_status s = validate_frame(&q.frame, b->bp.max_width, b->bp.max_height);
+        if (s != RL_OK) return fail(s, "request %d: %s", i, g_err.c_str());
+        if (r->T != b->bp.n_trees) return fail(RL_EINVAL, "request %d: room has %d trees, batch %d", i, r->T, b->bp.n_trees);
+        if (r->T * r->M > b->rows) return fail(RL_EINVAL, "request %d: room has up to %d modes per pixel, batch %d", i, r->T * r->M, b->rows);
+        const int N = q.n_hypotheses > 0 ? q.n_hypotheses : r->N;
+        if (N > b->bp.max_hypotheses || N > 4096) return fail(RL_EINVAL, "request %d: %d hypotheses exceed the batch maximum", i, N);
+        if (r->eta > b->bp.max_eta) return fail(RL_EINVAL, "request %d: eta exceeds the batch maximum", i);
+        std::vector<int> ent;
+        const int R = rounds_for(N, r->p.max_pose_candidates_after_cull, r->p.max_relocalisations_to_output, &ent);
+        if (R > b->bp.max_rounds) return fail(RL_EINVAL, "request %d: %d rounds exceed the batch maximum", i, R);
+        if (ent.size() > entering.size()) entering.resize(ent.size(), 0);
+        for (size_t k = 0; k < ent.size(); ++k) entering[k] = std::max(entering[k], ent[k]);
+        maxN = std::max(maxN, N);
+        maxIters = std::max(maxIters, r->p.max_candidate_generation_iterations);
+        maxEta = std::max(maxEta, r->eta);
+        if (q.pose_update < -1 || q.pose_update > 1) return fail(RL_EINVAL, "request %d: pose_update must be -1, 0 or 1", i);
+        const bool lm = q.pose_update == 0 ? r->p.pose_update != 0 : q.pose_update > 0;
+        any_lm = any_lm || lm;
+        if (lm) lm_iters = std::max(lm_iters, r->p.lm_iterations);
+    }
+    if (!reloc.empty()) {
+        const rl_status s = batch_relocalise_queue(b, reqs, reloc, dev_results, maxN, maxIters, maxEta, any_lm,
+                                                   lm_iters, entering, use_graph);
+        if (s != RL_OK) return s;
+    }
+    // adaptations after every relocalisation of the batch
+    if (!adapt.empty()) {
+        const rl_status s = batch_adapt(b, reqs, adapt, dev_results);
+        if (s != RL_OK) return s;
+    }
+    const hipError_t e = hipEventRecord(b->ev, b->stream);
+    if (e != hipSuccess) return hip_fail(e, "batch event");
     return RL_OK;
 }
 

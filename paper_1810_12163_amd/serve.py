@@ -11,14 +11,15 @@ the server
   backlog while every slot is taken (refused only when the queue is full),
 * keeps up to ``contexts`` batches in flight at once, each on its own stream
   with its own workspace, their number capped by the device-memory budget,
-* whenever a context is free, forms a batch from the pending relocalise
-  requests (up to ``max_batch``) and submits it asynchronously, so requests
-  that arrive while other batches run overlap with them on the device,
+* whenever a context is free, forms a batch from the pending requests
+  (relocalisations and adaptations, up to ``max_batch``) and submits it
+  asynchronously, so requests that arrive while other batches run overlap
+  with them on the device,
 * serves each room's requests in arrival order: a relocalisation sees exactly
-  the adaptations of its room that arrived before it.  An adapt is queued on
-  its room's stream only once every earlier request of that room has been
-  submitted; the library orders a room's batches and adaptations on the
-  device with stream events,
+  the adaptations of its room that arrived before it.  A batch runs its
+  relocalisations before its adaptations, so a relocalisation never joins a
+  batch that already holds an adaptation of its room; the library orders a
+  room's batches and adaptations on the device with stream events,
 * records per-request latency (completion observed by the host minus arrival).
 
 Results depend only on (room state, frame, request seed), so a request gives
@@ -32,6 +33,8 @@ import dataclasses
 import time
 
 import numpy as np
+
+from . import AdaptRequest
 
 
 @dataclasses.dataclass
@@ -60,32 +63,25 @@ class Request:
 def form_batch(pending, max_batch):
     """Scheduling policy (pure).  Walks the pending requests in arrival order.
 
-    Returns (batch, adapts, keep):
-    * ``batch``: relocalisations to submit now (at most max_batch), none of
-      them behind a pending adapt of its room;
-    * ``adapts``: adaptations to issue now, in arrival order, none of them
-      behind a pending or batched relocalisation of its room;
-    * ``keep``: everything else, still in arrival order.
-    Adaptations are issued before the batch is submitted, which is the
-    arrival order for every room involved."""
-    blocked, in_batch = set(), set()
-    batch, adapts, keep = [], [], collections.deque()
+    Returns (batch, keep):
+    * ``batch``: requests to submit now as one batch (at most max_batch),
+      in arrival order.  The library runs a batch's relocalisations first and
+      its adaptations after them, so a relocalisation may join the batch only
+      if no adaptation of its room is already in it (it must see that
+      adaptation), and nothing may pass a request of its room left waiting;
+    * ``keep``: everything else, still in arrival order."""
+    blocked, adapted = set(), set()
+    batch, keep = [], collections.deque()
     for q in pending:
         r = id(q.room)
+        if len(batch) >= max_batch or r in blocked or (q.kind != "adapt" and r in adapted):
+            blocked.add(r)
+            keep.append(q)
+            continue
+        batch.append(q)
         if q.kind == "adapt":
-            if r in blocked or r in in_batch:
-                blocked.add(r)
-                keep.append(q)
-            else:
-                adapts.append(q)
-        else:
-            if r in blocked or len(batch) >= max_batch:
-                blocked.add(r)
-                keep.append(q)
-            else:
-                batch.append(q)
-                in_batch.add(r)
-    return batch, adapts, keep
+            adapted.add(r)
+    return batch, keep
 
 
 class Ledger:
@@ -192,7 +188,6 @@ class Server:
         self.use_graph = use_graph
         self.pending = collections.deque()
         self.backlog = collections.deque()   # admitted, waiting for a frame slot
-        self.adapts_in_flight = {}           # per room: (event, request) of adaptations holding a slot
         self.completed = []
         self.refused = []
         self.deferred = 0
@@ -298,42 +293,21 @@ class Server:
                     self.completed.append(q)
                 done += len(reqs)
                 self.busy[i] = None
-        # a room's adaptations complete in issue order (its stream): query each
-        # room's oldest only
-        for key in list(self.adapts_in_flight):
-            fifo = self.adapts_in_flight[key]
-            while fifo and fifo[0][0].query():
-                self._release(fifo.popleft()[1])
-            if not fifo:
-                del self.adapts_in_flight[key]
         self._refill()
         self.host_s["complete"] += time.perf_counter() - tp
         while True:
-            tf = time.perf_counter()
             free = [i for i, b in enumerate(self.busy) if b is None]
-            batch, adapts, keep = form_batch(self.pending, self.max_batch if free else 0)
+            if not free or not self.pending:
+                break
+            tf = time.perf_counter()
+            batch, keep = form_batch(self.pending, self.max_batch)
             self.pending = keep
-            t = now_fn()
-            t0 = time.perf_counter()
-            self.host_s["form"] += t0 - tf
-            for q in adapts:
-                q.submitted = t
-                q.room.adapt(q.depth, q.rgb, q.K, q.pose, record=q.slot < 0)
-                q.done = t                    # queued on the device, ordered before later requests
-                q.result = {"status": "adapted"}
-                self.completed.append(q)
-                if q.slot >= 0:
-                    ev = self.torch.cuda.Event()
-                    ev.record(q.room.stream)
-                    self.adapts_in_flight.setdefault(id(q.room), collections.deque()).append((ev, q))
             t1 = time.perf_counter()
-            self.host_s["adapt"] += t1 - t0
+            self.host_s["form"] += t1 - tf
             if not batch:
                 break
-            self._submit(free[0], batch, t)
+            self._submit(free[0], batch, now_fn())
             self.host_s["submit"] += time.perf_counter() - t1
-            if len(free) == 1:
-                break
         return done
 
     def _submit(self, i, reqs, t):
@@ -341,7 +315,8 @@ class Server:
         for q in reqs:
             q.submitted = t
         b = self.ctx[i]
-        items = [(q.room, q.depth, q.rgb, q.K, q.rid, q.n_hypotheses) for q in reqs]
+        items = [AdaptRequest(q.room, q.depth, q.rgb, q.K, q.pose) if q.kind == "adapt" else
+                 (q.room, q.depth, q.rgb, q.K, q.rid, q.n_hypotheses) for q in reqs]
         # frames in the server's slots stay put until the batch has completed
         b.relocalise_async(items, self._res[i], use_graph=self.use_graph, record=any(q.slot < 0 for q in reqs))
         nbytes = len(reqs) * ctypes.sizeof(self._Result)
@@ -362,7 +337,7 @@ class Server:
         return not self.pending and not self.backlog and all(b is None for b in self.busy)
 
     def drain(self, now_fn=time.perf_counter):
-        while not self.idle() or self.adapts_in_flight:
+        while not self.idle():
             self.poll(now_fn)
 
     def close(self):

@@ -55,12 +55,14 @@ int main(void) {
          offsetof(rl_request, request_seed));
   printf("%zu %zu %zu %zu %zu\\n", sizeof(rl_reloc_opts), offsetof(rl_reloc_opts, max_translation_error),
          offsetof(rl_params, lm_iterations), offsetof(rl_request, pose_update), sizeof(rl_surface));
+  printf("%zu %zu %d %d\\n", offsetof(rl_request, kind), offsetof(rl_request, cam_to_world), RL_REQ_RELOCALISE,
+         RL_REQ_ADAPT);
   return 0;
 }
 ''')
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(prog)], check=True)
-    a, b, c = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.strip().splitlines()
+    a, b, c, d = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.strip().splitlines()
     sizes = [int(v) for v in a.split()]
     offs = [int(v) for v in b.split()]
     assert sizes == [ctypes.sizeof(rl.Params), ctypes.sizeof(rl.Frame), ctypes.sizeof(rl.Result),
@@ -70,6 +72,11 @@ int main(void) {
                     rl.Request.request_seed.offset]
     assert [int(v) for v in c.split()] == [ctypes.sizeof(rl.RelocOpts), rl.RelocOpts.max_translation_error.offset,
                                            rl.Params.lm_iterations.offset, rl.Request.pose_update.offset, 64]
+    assert [int(v) for v in d.split()] == [rl.Request.kind.offset, rl.Request.cam_to_world.offset,
+                                           rl.REQ_RELOCALISE, rl.REQ_ADAPT]
+    assert rl.RESULT_DTYPE.itemsize == ctypes.sizeof(rl.Result)
+    assert [rl.RESULT_DTYPE.fields[name][1] for name, _ in rl.Result._fields_] == \
+        [getattr(rl.Result, name).offset for name, _ in rl.Result._fields_]
 
 
 def test_presets_match_the_shared_presets():

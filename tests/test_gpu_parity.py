@@ -406,6 +406,103 @@ def test_back_to_back_async_batches_equal_plain(c1):
     batch.close()
 
 
+def _same_room_state(A, B, tag):
+    """Arrival counters, dirty flags and mode counts equal; the filled part of
+    every reservoir and every mode row in use equal bit for bit."""
+    p = A.params
+    TL, kappa, M = p["n_trees"] << p["depth"], p["reservoir_capacity"], p["max_cluster_count"]
+    for buf, dt in ((rl.BUF_SEEN, np.uint32), (rl.BUF_DIRTY, np.uint32), (rl.BUF_NMODES, np.uint8)):
+        assert np.array_equal(A.buffer_np(buf, dt), B.buffer_np(buf, dt)), (tag, buf)
+    seen = A.buffer_np(rl.BUF_SEEN, np.uint32).copy()
+    ra = A.buffer_np(rl.BUF_RESERVOIR, np.uint32).reshape(TL, kappa, 4)
+    rb = B.buffer_np(rl.BUF_RESERVOIR, np.uint32).reshape(TL, kappa, 4)
+    used = np.arange(kappa)[None, :] < np.minimum(seen, kappa)[:, None]
+    assert np.array_equal(ra[used], rb[used]), (tag, "reservoir")
+    nm = A.buffer_np(rl.BUF_NMODES, np.uint8).astype(np.int64)
+    ma = A.buffer_np(rl.BUF_MODES, np.uint32).reshape(TL, M, 16)
+    mb = B.buffer_np(rl.BUF_MODES, np.uint32).reshape(TL, M, 16)
+    used = np.arange(M)[None, :] < nm[:, None]
+    assert np.array_equal(ma[used], mb[used]), (tag, "modes")
+
+
+@pytest.mark.parametrize("leaves_per_frame", [0, 64])
+def test_batched_adaptations_equal_plain_sequence(leaves_per_frame):
+    """Adaptation requests inside batches (two rooms, mixed with
+    relocalisations, one batch replayed from a graph and one launched
+    directly): each batch's relocalisations see the rooms as they were before
+    its adaptations, and afterwards reservoirs, arrival counters, dirty flags
+    and modes equal those of plain adapt calls in request order, bit for bit,
+    under the exact and the round-robin mode schedule."""
+    specs = [workloads.c1(room_id=r, n_queries=2) for r in (0, 1)]
+
+    def make():
+        out = []
+        for w in specs:
+            room = rl.Room(w.params, w.nodes, 160, 120)
+            room.set_mode_schedule(leaves_per_frame)
+            for f in w.adapt[:2]:
+                room.adapt(*dev(f), f.K, f.pose)
+            out.append(room)
+        return out
+
+    A, B = make(), make()
+    batch = rl.Batch(8, 160, 120, 64, 100, 6, 1, 5)
+    frames = {}
+
+    def F(f):
+        if id(f) not in frames:
+            frames[id(f)] = dev(f)
+        return frames[id(f)]
+
+    plans = [
+        [("r", 0, specs[0].queries[0], 11), ("a", 0, specs[0].adapt[2]), ("r", 1, specs[1].queries[0], 12),
+         ("a", 1, specs[1].adapt[2]), ("a", 0, specs[0].adapt[3]), ("r", 0, specs[0].queries[1], 13)],
+        [("a", 1, specs[1].adapt[3]), ("r", 0, specs[0].queries[0], 21), ("r", 1, specs[1].queries[1], 22)],
+    ]
+    for k, plan in enumerate(plans):
+        items = []
+        for step in plan:
+            if step[0] == "r":
+                _, r, q, seed = step
+                items.append((A[r], *F(q), q.K, seed))
+            else:
+                _, r, f = step
+                items.append(rl.AdaptRequest(A[r], *F(f), f.K, f.pose))
+        got = batch.relocalise(items, use_graph=(k == 0))
+        # plain: the relocalisations first, then the adaptations in order
+        for step, g in zip(plan, got):
+            if step[0] == "r":
+                _, r, q, seed = step
+                want = B[r].relocalise(*F(q), q.K, request_seed=seed)
+                assert g["status"] == want["status"] and g["winner"] == want["winner"], step
+                assert np.array_equal(g["pose"], want["pose"]) and g["energy"] == want["energy"], step
+            else:
+                assert g["status"] == "ok" and g["winner"] == -1 and g["rounds"] == 0
+        for step in plan:
+            if step[0] == "a":
+                _, r, f = step
+                B[r].adapt(*F(f), f.K, f.pose)
+        torch.cuda.synchronize()
+        for r in (0, 1):
+            if leaves_per_frame == 0:
+                A[r].update_modes()
+                B[r].update_modes()
+            torch.cuda.synchronize()
+            _same_room_state(A[r], B[r], (k, r))
+    # a room's own stream continues after a batch's adaptation of it
+    f = specs[0].adapt[0]
+    A[0].adapt(*F(f), f.K, f.pose)
+    B[0].adapt(*F(f), f.K, f.pose)
+    q = specs[0].queries[1]
+    a, b = A[0].relocalise(*F(q), q.K, request_seed=5), B[0].relocalise(*F(q), q.K, request_seed=5)
+    assert np.array_equal(a["pose"], b["pose"]) and a["energy"] == b["energy"]
+    with pytest.raises(rl.RlError):
+        batch.relocalise([rl.AdaptRequest(A[0], *F(f), f.K, np.diag([2.0, 1.0, 1.0, 1.0]))])
+    batch.close()
+    for room in A + B:
+        room.close()
+
+
 def test_adapt_every_grid_pixel_into_one_leaf_bit_exact():
     """Adaptation when every grid pixel of a 640x480 frame reaches the same
     leaf of each tree (constant depth and colour: every feature is 0): 18,921

@@ -22,72 +22,72 @@ def simulate(seed, n_rooms=4, n_req=300, max_batch=5):
     reqs = [Request(rid=i, kind="adapt" if rng.random() < 0.3 else "relocalise", room=rng.choice(rooms))
             for i in range(n_req)]
     pending = collections.deque()
-    issued = []                      # (pass, order within pass, request)
+    issued = []                      # (batch, position in batch, request)
     k = 0
-    p = 0
+    nb = 0
     while k < n_req or pending:
         for _ in range(rng.randint(0, 6)):          # arrivals of this pass
             if k < n_req:
                 pending.append(reqs[k])
                 k += 1
-        free = rng.random() < 0.6                   # is a context free?
-        batch, adapts, keep = form_batch(pending, max_batch if free else 0)
-        assert len(batch) <= max_batch
-        assert not batch or free
-        order = 0
-        for q in adapts:
-            issued.append((p, order, q))
-            order += 1
-        for q in batch:
-            issued.append((p, order, q))            # batch submitted after the adapts
-        assert [q.rid for q in keep] == sorted(q.rid for q in keep)
-        pending = keep
-        p += 1
-        assert p < 10_000
+        if rng.random() < 0.6:                      # is a context free?
+            batch, keep = form_batch(pending, max_batch)
+            assert len(batch) <= max_batch
+            assert [q.rid for q in batch] == sorted(q.rid for q in batch)
+            for i, q in enumerate(batch):
+                issued.append((nb, i, q))
+            assert [q.rid for q in keep] == sorted(q.rid for q in keep)
+            pending = keep
+            nb += 1
+        assert nb < 10_000
     return reqs, issued
 
 
 @pytest.mark.parametrize("seed", range(20))
 def test_per_room_arrival_order(seed):
+    """Per room, in arrival order: a relocalisation after an adaptation runs in
+    a later batch (a batch's relocalisations run before its adaptations and
+    see the rooms as they were); otherwise a later request is never in an
+    earlier batch, and adaptations of one batch keep their order."""
     reqs, issued = simulate(seed)
     assert sorted(q.rid for _, _, q in issued) == list(range(len(reqs)))
-    when = {q.rid: (p, o) for p, o, q in issued}
+    when = {q.rid: (b, i) for b, i, q in issued}
     by_room = collections.defaultdict(list)
     for q in reqs:
         by_room[q.room.name].append(q)
     for rq in by_room.values():
-        for a, b in zip(rq, rq[1:]):
-            if a.kind == "relocalise" and b.kind == "relocalise":
-                assert when[a.rid][0] <= when[b.rid][0]     # may share a batch
+        for x, y in zip(rq, rq[1:]):
+            if x.kind == "adapt" and y.kind != "adapt":
+                assert when[x.rid][0] < when[y.rid][0], (x, y)
             else:
-                assert when[a.rid] < when[b.rid], (a, b)     # adapts are barriers
+                assert when[x.rid] < when[y.rid], (x, y)
 
 
-def test_batch_fills_across_rooms_and_adapt_blocks_only_its_room():
+def test_batch_fills_across_rooms_and_adapt_blocks_later_relocalisations_of_its_room():
     rooms = [FakeRoom(i) for i in range(3)]
     pending = collections.deque([
         Request(0, "relocalise", rooms[0]), Request(1, "relocalise", rooms[1]),
         Request(2, "adapt", rooms[0]), Request(3, "relocalise", rooms[0]),
         Request(4, "relocalise", rooms[2]), Request(5, "adapt", rooms[1]),
         Request(6, "adapt", rooms[2]), Request(7, "relocalise", rooms[1]),
+        Request(8, "adapt", rooms[0]),
     ])
-    batch, adapts, keep = form_batch(pending, 8)
-    assert [q.rid for q in batch] == [0, 1, 4]
-    assert [q.rid for q in adapts] == []           # each follows a batched request of its room
-    assert [q.rid for q in keep] == [2, 3, 5, 6, 7]
-    batch, adapts, keep = form_batch(keep, 8)
-    assert [q.rid for q in adapts] == [2, 5, 6]
-    assert [q.rid for q in batch] == [3, 7]
-    assert not keep
+    batch, keep = form_batch(pending, 8)
+    # 3 waits for adapt 2 of its room; 8 may not pass 3; 7 waits for adapt 5
+    assert [q.rid for q in batch] == [0, 1, 2, 4, 5, 6]
+    assert [q.rid for q in keep] == [3, 7, 8]
+    batch, keep = form_batch(keep, 8)
+    assert [q.rid for q in batch] == [3, 7, 8] and not keep
 
 
-def test_no_free_context_still_issues_ready_adapts():
+def test_full_batch_keeps_the_rest_in_order():
     rooms = [FakeRoom(i) for i in range(2)]
-    pending = collections.deque([Request(0, "adapt", rooms[0]), Request(1, "relocalise", rooms[1]),
-                                 Request(2, "adapt", rooms[1]), Request(3, "relocalise", rooms[0])])
-    batch, adapts, keep = form_batch(pending, 0)
-    assert not batch and [q.rid for q in adapts] == [0]
-    assert [q.rid for q in keep] == [1, 2, 3]
+    pending = collections.deque([Request(i, "relocalise" if i % 3 else "adapt", rooms[i % 2]) for i in range(7)])
+    batch, keep = form_batch(pending, 3)
+    # 2 (room 0) waits for adapt 0 of its room; adapt 3 (room 1) fills the batch
+    assert [q.rid for q in batch] == [0, 1, 3] and [q.rid for q in keep] == [2, 4, 5, 6]
+    batch, keep = form_batch(pending, 0)
+    assert not batch and len(keep) == 7
 
 
 def test_admission_refuses_beyond_the_queue_bound():
