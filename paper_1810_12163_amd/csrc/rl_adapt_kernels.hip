@@ -252,9 +252,12 @@ __device__ __forceinline__ double dist2(float4 a, float4 b)
     return dx * dx + dy * dy + dz * dz;
 }
 
+// Sum over the first 256 threads of the block in a fixed tree order (the
+// other threads only take part in the barriers), so that a moment does not
+// depend on the block size.
 __device__ __forceinline__ double rqs_block_sum(double v, double* s_red)
 {
-    s_red[threadIdx.x] = v;
+    if (threadIdx.x < 256) s_red[threadIdx.x] = v;
     __syncthreads();
     for (int stride = 128; stride > 0; stride >>= 1) {
         if ((int)threadIdx.x < stride) s_red[threadIdx.x] += s_red[threadIdx.x + stride];
@@ -266,7 +269,11 @@ __device__ __forceinline__ double rqs_block_sum(double v, double* s_red)
 }
 
 // dynamic LDS: float4 pts[kappa], double rho[kappa], int parent[kappa], int root[kappa], int size[kappa]
-__global__ __launch_bounds__(256) void k_rqs(RqsArgs a)
+// BS threads per leaf: the per-point O(n^2) passes (density, links, ranks)
+// stride over all of them; the moments use the first 256 in a fixed order,
+// so every block size gives the same rows.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_rqs(RqsArgs a)
 {
     extern __shared__ unsigned char s_raw[];
     float4* pts = reinterpret_cast<float4*>(s_raw);
@@ -285,20 +292,20 @@ __global__ __launch_bounds__(256) void k_rqs(RqsArgs a)
         const uint32_t tl = a.rr_count ? (a.rr_first + li) % a.n_leaves : a.dirty_list[li];
         const int n = (int)min(a.seen[tl], (uint32_t)a.kappa);
         const float4* src = a.reservoir + (size_t)tl * a.kappa;
-        for (int k = tid; k < n; k += 256) {
+        for (int k = tid; k < n; k += BS) {
             pts[k] = src[k];
             size[k] = 0;
         }
         if (tid == 0) s_ncand = 0;
         __syncthreads();
-        for (int k = tid; k < n; k += 256) {
+        for (int k = tid; k < n; k += BS) {
             const float4 pk = pts[k];
             double acc = 0.0;
             for (int j = 0; j < n; ++j) acc += exp(-dist2(pk, pts[j]) / two_s2);
             rho[k] = acc;
         }
         __syncthreads();
-        for (int k = tid; k < n; k += 256) {
+        for (int k = tid; k < n; k += BS) {
             const float4 pk = pts[k];
             const double rk = rho[k];
             int best = -1;
@@ -319,16 +326,16 @@ __global__ __launch_bounds__(256) void k_rqs(RqsArgs a)
         __syncthreads();
         // pointer jumping: after ceil(log2 n) + 1 passes every point holds its root
         for (int pass = 0; (1 << pass) <= 2 * n; ++pass) {
-            for (int k = tid; k < n; k += 256) {
+            for (int k = tid; k < n; k += BS) {
                 const int r = root[k];
                 root[k] = root[r];
             }
             __syncthreads();
         }
-        for (int k = tid; k < n; k += 256) atomicAdd(&size[root[k]], 1);
+        for (int k = tid; k < n; k += BS) atomicAdd(&size[root[k]], 1);
         __syncthreads();
         // candidates ranked by (size desc, root asc); keep ranks < M
-        for (int k = tid; k < n; k += 256) {
+        for (int k = tid; k < n; k += BS) {
             if (parent[k] >= 0 || size[k] < a.min_size) continue;
             const int sk = size[k];
             int rank = 0;
@@ -345,7 +352,7 @@ __global__ __launch_bounds__(256) void k_rqs(RqsArgs a)
         for (int m = 0; m < nm; ++m) {
             const int r = s_chosen[m];
             double sx = 0, sy = 0, sz = 0, cnt = 0, cr = 0, cg = 0, cb = 0;
-            for (int k = tid; k < n; k += 256) {
+            for (int k = tid; k < n && tid < 256; k += 256) {
                 if (root[k] != r) continue;
                 const float4 pk = pts[k];
                 sx += pk.x; sy += pk.y; sz += pk.z; cnt += 1.0;
@@ -360,7 +367,7 @@ __global__ __launch_bounds__(256) void k_rqs(RqsArgs a)
             const double mr = rqs_block_sum(cr, s_red) / cnt, mg = rqs_block_sum(cg, s_red) / cnt,
                          mb = rqs_block_sum(cb, s_red) / cnt;
             double S[6] = {0, 0, 0, 0, 0, 0};
-            for (int k = tid; k < n; k += 256) {
+            for (int k = tid; k < n && tid < 256; k += 256) {
                 if (root[k] != r) continue;
                 const float4 pk = pts[k];
                 const double dx = (double)pk.x - mx, dy = (double)pk.y - my, dz = (double)pk.z - mz;
@@ -432,7 +439,13 @@ hipError_t launch_adapt(const AdaptArgs& a, hipStream_t st)
 hipError_t launch_rqs(const RqsArgs& a, int blocks, hipStream_t st)
 {
     const size_t lds = 36 * (size_t)a.kappa;
-    k_rqs<<<dim3(blocks), dim3(256), lds, st>>>(a);
+    if (a.rr_count) {
+        // a round-robin step: few leaves, most of them full; 1024 threads each
+        const int nb = (int)min((uint32_t)blocks, a.rr_count);
+        k_rqs<1024><<<dim3(nb), dim3(1024), lds, st>>>(a);
+    } else {
+        k_rqs<256><<<dim3(blocks), dim3(256), lds, st>>>(a);
+    }
     RL_CHECK_LAUNCH();
     if (a.rr_count) return hipSuccess;      // the dirty list is left for an exact update
     k_rqs_done<<<dim3(1), dim3(64), 0, st>>>(a);
