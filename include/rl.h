@@ -50,12 +50,30 @@ typedef enum {
 
 typedef struct { float fx, fy, cx, cy; } rl_intrinsics;
 
-/* One RGB-D frame in device memory. width and height must be multiples of 4. */
+/*
+ * One RGB-D frame in device memory, read in place (no copy is required of
+ * the caller).  width and height (multiples of 4) and K describe the frame as
+ * relocalised.  Pixel (x, y) is sample (step * x, step * y) of the buffers:
+ *   depth: float32 metres (0 = invalid) at byte offset
+ *          step * y * depth_pitch_bytes + step * x * 4;
+ *   rgb:   channel c (0 = R, 1 = G, 2 = B) at byte offset
+ *          step * y * rgb_pitch_bytes + step * x * rgb_channels + c.
+ * step 2 relocalises the 2x decimated frame of Sec. 3.2.5's cascade in place
+ * (K then is the decimated frame's: the full frame's fx, fy, cx, cy halved).
+ * Zero fields take defaults: rgb_channels 3, step 1, pitches of tightly
+ * packed rows of the buffers (width * step * 4 and width * step *
+ * rgb_channels bytes).  RL_EINVAL for rgb_channels other than 3 or 4, step
+ * other than 1 or 2, or pitches below those of packed rows.
+ */
 typedef struct {
     int32_t width, height;
-    const float* depth;      /* device, height*width float32, row-major, metres, 0 = invalid */
-    const uint8_t* rgb;      /* device, height*width*3 uint8, row-major R,G,B              */
+    const float* depth;      /* device, float32 metres, 0 = invalid              */
+    const uint8_t* rgb;      /* device, uint8 R, G, B[, unused]                  */
     rl_intrinsics K;
+    int32_t rgb_channels;    /* 3 (RGB) or 4 (RGBA, the fourth byte unused); 0 = 3 */
+    int32_t rgb_pitch_bytes; /* bytes from one buffer row to the next; 0 = packed  */
+    int32_t depth_pitch_bytes; /* bytes from one buffer row to the next; 0 = packed */
+    int32_t step;            /* 1: every pixel; 2: every second pixel and row; 0 = 1 */
 } rl_frame;
 
 /*
@@ -125,9 +143,13 @@ rl_status rl_forest_generate(const rl_forest_params* fp, rl_node* host_nodes, si
 
 /*
  * Fills *out with a named preset: "default", "fast", "intermediate", "slow"
- * (Table 8 of the paper) or "c1" (160x120, one depth-8 tree, kappa 64,
- * 64 hypotheses, eta 100) / "c2" (640x480, five depth-15 trees, kappa 1024,
- * 1024 hypotheses, eta 500, refit).  RL_EINVAL for an unknown name.
+ * (Table 8 of the paper) or one of the synthetic workloads: "c1" (160x120,
+ * one depth-8 tree, kappa 64, 64 hypotheses, eta 100), "c2" (640x480, five
+ * depth-15 trees, kappa 1024, at most 10 modes per leaf, 1024 hypotheses,
+ * eta 500, refit), "c3" (the c2 forest with room for the cascade's widest
+ * stage: 4096 hypotheses, 16 outputs; its stages are per-call settings),
+ * "c4" and "c5" (the c2 room of the batching and serving workloads).
+ * RL_EINVAL for an unknown name.
  */
 rl_status rl_params_preset(const char* name, rl_params* out);
 
@@ -246,7 +268,11 @@ typedef struct {
     int32_t n_eligible;      /* pixels with depth and at least one mode */
     int32_t rounds;          /* RANSAC rounds run */
     int32_t n_out;           /* hypotheses returned in the survivor list */
-    int32_t pad[2];
+    uint32_t mode_version;   /* mode updates the room had received when this request read its modes
+                                (relocalisation), or after this adaptation's own (adaptation): a
+                                relocalisation sees exactly the adaptations whose mode updates it
+                                counts; counted from 0 at relocaliser_create */
+    int32_t pad;
 } rl_result;
 
 /* Like relocaliser_relocalise but returns the full result record (host). */

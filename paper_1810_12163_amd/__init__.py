@@ -45,7 +45,9 @@ class Intrinsics(ctypes.Structure):
 
 class Frame(ctypes.Structure):
     _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
-                ("depth", ctypes.c_void_p), ("rgb", ctypes.c_void_p), ("K", Intrinsics)]
+                ("depth", ctypes.c_void_p), ("rgb", ctypes.c_void_p), ("K", Intrinsics),
+                ("rgb_channels", ctypes.c_int32), ("rgb_pitch_bytes", ctypes.c_int32),
+                ("depth_pitch_bytes", ctypes.c_int32), ("step", ctypes.c_int32)]
 
 
 class Params(ctypes.Structure):
@@ -73,14 +75,14 @@ class Result(ctypes.Structure):
                 ("n_valid", ctypes.c_int32), ("n_inliers", ctypes.c_int32),
                 ("winner", ctypes.c_int32), ("refitted", ctypes.c_int32),
                 ("n_eligible", ctypes.c_int32), ("rounds", ctypes.c_int32),
-                ("n_out", ctypes.c_int32), ("pad", ctypes.c_int32 * 2)]
+                ("n_out", ctypes.c_int32), ("mode_version", ctypes.c_uint32), ("pad", ctypes.c_int32)]
 
 
 # rl_result as a numpy record (decoding many results at once)
 RESULT_DTYPE = np.dtype([("cam_to_world", "<f4", (16,)), ("energy", "<f4"), ("mean_energy", "<f4"),
                          ("status", "<i4"), ("n_valid", "<i4"), ("n_inliers", "<i4"), ("winner", "<i4"),
                          ("refitted", "<i4"), ("n_eligible", "<i4"), ("rounds", "<i4"), ("n_out", "<i4"),
-                         ("pad", "<i4", (2,))])
+                         ("mode_version", "<u4"), ("pad", "<i4")])
 
 
 def decode_results(raw: np.ndarray, n: int) -> list:
@@ -93,7 +95,8 @@ def decode_results(raw: np.ndarray, n: int) -> list:
         out.append(dict(pose=poses[k].copy(), energy=float(r["energy"]), mean_energy=float(r["mean_energy"]),
                         status="ok" if r["status"] == RL_OK else "no_pose", n_valid=int(r["n_valid"]),
                         n_inliers=int(r["n_inliers"]), winner=int(r["winner"]), refitted=bool(r["refitted"]),
-                        n_eligible=int(r["n_eligible"]), rounds=int(r["rounds"]), n_out=int(r["n_out"])))
+                        n_eligible=int(r["n_eligible"]), rounds=int(r["rounds"]), n_out=int(r["n_out"]),
+                        mode_version=int(r["mode_version"])))
     return out
 
 
@@ -260,18 +263,35 @@ def _torch():
 
 
 def _frame(depth, rgb, K) -> Frame:
+    """The rl_frame of a (h, w) float32 depth tensor and an (h, w, 3) uint8
+    colour tensor on the GPU, read in place: rows may be padded (any row
+    stride), colour may be RGB or the first three channels of RGBA, and both
+    may be views taking every second pixel of every second row (the 2x
+    decimated frame, e.g. depth[::2, ::2]); K is the frame's own."""
     torch = _torch()
     if not (isinstance(depth, torch.Tensor) and isinstance(rgb, torch.Tensor)):
         raise TypeError("depth and rgb must be torch tensors on the GPU")
-    if depth.dtype != torch.float32 or depth.dim() != 2 or not depth.is_cuda or not depth.is_contiguous():
-        raise TypeError("depth must be a contiguous (h, w) float32 CUDA tensor")
+    if depth.dtype != torch.float32 or depth.dim() != 2 or not depth.is_cuda:
+        raise TypeError("depth must be an (h, w) float32 CUDA tensor")
     h, w = depth.shape
-    if rgb.dtype != torch.uint8 or tuple(rgb.shape) != (h, w, 3) or not rgb.is_cuda or not rgb.is_contiguous():
-        raise TypeError("rgb must be a contiguous (h, w, 3) uint8 CUDA tensor")
+    if rgb.dtype != torch.uint8 or rgb.dim() != 3 or tuple(rgb.shape[:2]) != (h, w) or rgb.shape[2] not in (3, 4) \
+            or not rgb.is_cuda:
+        raise TypeError("rgb must be an (h, w, 3) or (h, w, 4) uint8 CUDA tensor")
+    sd0, sd1 = depth.stride()
+    sr0, sr1, sr2 = rgb.stride()
+    step = sd1
+    ch = sr1 // step if step in (1, 2) else 0
+    if step not in (1, 2) or sd0 % step or sr0 % step or sr2 != 1 or ch not in (3, 4) or sr1 != ch * step:
+        raise TypeError("depth and rgb must take every pixel (or every second one, both alike) of rows with unit "
+                        "element stride, colour with 3 or 4 bytes per pixel")
     f = Frame()
     f.width, f.height = int(w), int(h)
     f.depth, f.rgb = depth.data_ptr(), rgb.data_ptr()
     f.K = Intrinsics(*[float(v) for v in K])
+    f.rgb_channels = ch
+    f.step = step
+    f.depth_pitch_bytes = sd0 * 4 // step
+    f.rgb_pitch_bytes = sr0 // step
     return f
 
 
@@ -280,7 +300,8 @@ def _result(r: Result) -> dict:
     return dict(pose=H, energy=float(r.energy), mean_energy=float(r.mean_energy),
                 status="ok" if r.status == RL_OK else "no_pose", n_valid=int(r.n_valid),
                 n_inliers=int(r.n_inliers), winner=int(r.winner), refitted=bool(r.refitted),
-                n_eligible=int(r.n_eligible), rounds=int(r.rounds), n_out=int(r.n_out))
+                n_eligible=int(r.n_eligible), rounds=int(r.rounds), n_out=int(r.n_out),
+                mode_version=int(r.mode_version))
 
 
 class Room:

@@ -76,11 +76,11 @@ def c3_stages(thresholds=(0.05, 0.075)) -> list:
 
 
 def decimate(depth, rgb, K):
-    """2x decimation on the device: pixel (x, y) <- (2x, 2y), intrinsics halved."""
-    d = depth[::2, ::2].contiguous()
-    c = rgb[::2, ::2].contiguous()
+    """The 2x decimated frame: pixel (x, y) <- (2x, 2y), intrinsics halved.
+    Views of the full frame (no copy): the library reads every second pixel
+    of every second row in place."""
     fx, fy, cx, cy = [float(v) for v in K]
-    return d, c, (fx / 2, fy / 2, cx / 2, cy / 2)
+    return depth[::2, ::2], rgb[::2, ::2], (fx / 2, fy / 2, cx / 2, cy / 2)
 
 
 class Cascade:

@@ -47,21 +47,21 @@ __global__ __launch_bounds__(256) void k_ad_items(AdaptArgs a)
             r->n_eligible = 0;
             r->rounds = 0;
             r->n_out = 0;
-            r->pad[0] = 0;
-            r->pad[1] = 0;
+            r->mode_version = a.mode_version;
+            r->pad = 0;
         }
     }
     const int g = blockIdx.x * 256 + threadIdx.x;
     if (g >= a.G) return;
     const int x = 4 * (g % a.gw + 1), y = 4 * (g / a.gw + 1);
-    const float d = a.depth[y * a.w + x];
+    const float d = a.src.d(x, y);
     if (!depth_ok(d)) {
 #pragma unroll
         for (int t = 0; t < T; ++t) a.item_leaf[(size_t)t * a.G + g] = (uint16_t)kLeafNone;
         return;
     }
     int leaf[T];
-    const PlanarProbe pr{a.depth, a.rgb, a.w};
+    const PlanarProbe pr{a.src};
     if (a.s == 1.0f) route<T, true>(a.nodes, a.L - 1, a.D, pr, a.w, a.h, x, y, d, a.s, leaf);
     else route<T, false>(a.nodes, a.L - 1, a.D, pr, a.w, a.h, x, y, d, a.s, leaf);
     double xc[3];
@@ -73,7 +73,7 @@ __global__ __launch_bounds__(256) void k_ad_items(AdaptArgs a)
         v = v + a.H[4 * r + 3];
         xw[r] = (float)v;
     }
-    const uint8_t* c = a.rgb + 3 * (y * a.w + x);
+    const uint8_t* c = a.src.c(x, y);
     const uint32_t col = (uint32_t)c[0] | ((uint32_t)c[1] << 8) | ((uint32_t)c[2] << 16);
     a.item_pt[g] = make_float4(xw[0], xw[1], xw[2], __uint_as_float(col));
 #pragma unroll

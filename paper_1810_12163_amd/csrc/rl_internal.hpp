@@ -65,6 +65,35 @@ struct Hyp {                 // == rl_hypothesis
 };
 static_assert(sizeof(Hyp) == sizeof(rl_hypothesis), "hypothesis layout");
 
+// Load through the global address space.  Pointers read from the job table
+// are generic to the compiler; generic (flat) loads wait on both the memory
+// and LDS counters and cannot be reordered around LDS stores, which
+// serialises independent gathers.
+template <class T>
+__device__ __forceinline__ T ldg(const T* p)
+{
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+
+// The caller's frame buffers, read in place: pixel (x, y) of the frame is
+// sample (step x, step y) of the buffers (step 2: the 2x decimated frame);
+// row pitches in bytes, ch bytes per colour sample (3 or 4).
+struct FrameView {
+    const float* depth;
+    const uint8_t* rgb;
+    uint32_t dpitch, rpitch, ch, step;
+    __device__ __forceinline__ float d(int x, int y) const
+    {
+        return ldg(reinterpret_cast<const float*>(reinterpret_cast<const char*>(depth) +
+                                                  (size_t)(step * (uint32_t)y) * dpitch +
+                                                  (size_t)(step * (uint32_t)x) * 4u));
+    }
+    __device__ __forceinline__ const uint8_t* c(int x, int y) const
+    {
+        return rgb + (size_t)(step * (uint32_t)y) * rpitch + (size_t)(step * (uint32_t)x) * ch;
+    }
+};
+
 struct Job {
     // room (persistent)
     const float4* nodes;      // [T][NT] (dx, dy, tau, kind bits)
@@ -74,8 +103,7 @@ struct Job {
     int T, D, M;
     int screen;               // 1: the search rejects clearly degenerate triplets itself
     // frame
-    const float* depth;
-    const uint8_t* rgb;
+    FrameView src;            // the caller's buffers (read by the ingest only)
     uint2* probe;             // [P] interleaved probe image (depth bits, RGB bytes), built per frame
     int w, h;
     float fx, fy, cx, cy;
@@ -97,7 +125,7 @@ struct Job {
     uint4* ecold;             // [P][2] per list entry: (pixel, depth bits, mode counts), leaves
     uint64_t* erec;           // [P][ew] eligible-pixel records (see erec_* below)
     int ew;                   // words per record: 1 for |M(u)| <= 56
-    int pad1;
+    uint32_t mode_version;    // the room's mode updates when this job was queued (result record)
     int* hyp_best;            // [N]
     Hyp* hyps;                // [N]
     int* surv;                // [N]
@@ -125,8 +153,7 @@ struct Job {
 struct AdaptArgs {
     const float4* nodes;
     int T, D, L, kappa;
-    const float* depth;
-    const uint8_t* rgb;
+    FrameView src;
     int w, h, gw, G;
     float fx, fy, cx, cy, s;
     double H[12];             // camera->world rows (from float32)
@@ -157,6 +184,7 @@ struct AdaptArgs {
     int Gp;                   // chunks * kAdaptChunk
     uint32_t hmask;           // hash-table size - 1 (size a power of two >= 2 T G)
     rl_result* result;        // batched adaptation: its result record (status RL_OK), else NULL
+    uint32_t mode_version;    // ... and the room's mode version after it
 };
 
 constexpr int kAdaptChunk = 1024;
@@ -209,15 +237,6 @@ __device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1)
     return c;
 }
 
-// Load through the global address space.  Pointers read from the job table
-// are generic to the compiler; generic (flat) loads wait on both the memory
-// and LDS counters and cannot be reordered around LDS stores, which
-// serialises independent gathers.
-template <class T>
-__device__ __forceinline__ T ldg(const T* p)
-{
-    return *(const __attribute__((address_space(1))) T*)p;
-}
 // HIP's vector structs would be copied through a generic reference: load
 // them as native vectors instead.
 typedef uint32_t rl_u32x2 __attribute__((ext_vector_type(2)));
@@ -273,20 +292,19 @@ __device__ __forceinline__ void backproject(float d, int x, int y, float fx, flo
 // then R, G, B bytes) that a relocalisation builds first, so that a probe is
 // one load with no branch on the feature kind.  Both give the same values.
 struct PlanarProbe {
-    const float* depth;
-    const uint8_t* rgb;
-    int w;
+    FrameView f;
     typedef float Centre[3];
-    __device__ __forceinline__ void centre(int pc, Centre cc) const
+    __device__ __forceinline__ void centre(int x, int y, Centre cc) const
     {
-        cc[0] = (float)ldg(rgb + 3 * pc);
-        cc[1] = (float)ldg(rgb + 3 * pc + 1);
-        cc[2] = (float)ldg(rgb + 3 * pc + 2);
+        const uint8_t* c = f.c(x, y);
+        cc[0] = (float)ldg(c);
+        cc[1] = (float)ldg(c + 1);
+        cc[2] = (float)ldg(c + 2);
     }
     typedef float2 Word;
-    __device__ __forceinline__ Word load(int q, uint32_t c) const
+    __device__ __forceinline__ Word load(int qx, int qy, uint32_t c) const
     {
-        return make_float2(ldg(depth + q), (float)ldg(rgb + 3 * q + c));
+        return make_float2(f.d(qx, qy), (float)ldg(f.c(qx, qy) + c));
     }
     // the split feature: depth kind D(p) - D(q); colour kind C(p,c) - C(q,c)
     __device__ __forceinline__ float feature(Word v, bool is_depth, uint32_t c, float d, const Centre cc) const
@@ -298,12 +316,17 @@ struct PlanarProbe {
 
 struct PackedProbe {
     const uint2* img;
+    uint32_t w;
     typedef uint32_t Centre[1];
-    __device__ __forceinline__ void centre(int pc, Centre cw) const { cw[0] = ldg(img + pc).y; }
-    typedef uint2 Word;
-    // 32-bit byte offset from the image base (below 2^27 bytes)
-    __device__ __forceinline__ Word load(int q, uint32_t) const
+    __device__ __forceinline__ void centre(int x, int y, Centre cw) const
     {
+        cw[0] = ldg(img + (uint32_t)y * w + (uint32_t)x).y;
+    }
+    typedef uint2 Word;
+    // 32-bit byte offset from the image base (below 2^27 bytes; w * h < 2^24)
+    __device__ __forceinline__ Word load(int qx, int qy, uint32_t) const
+    {
+        const int q = (int)__umul24((uint32_t)qy, w) + qx;
         return ldg(reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(img) + (uint32_t)q * 8u));
     }
     // colour bytes are subtracted as integers: the difference of two bytes
@@ -334,7 +357,7 @@ __device__ __forceinline__ void route(const float4* __restrict__ nodes, int NT, 
 {
     const float inv = 1.0f / d;
     typename Probe::Centre cen;
-    pr.centre(y * w + x, cen);
+    pr.centre(x, y, cen);
     const float lox = (float)(-x), hix = (float)(w - 1 - x), loy = (float)(-y), hiy = (float)(h - 1 - y);
     int idx[T];
 #pragma unroll
@@ -360,11 +383,10 @@ __device__ __forceinline__ void route(const float4* __restrict__ nodes, int NT, 
             float foy = rintf((UNIT ? nd[t].y : nd[t].y * s) * inv);
             fox = fminf(fmaxf(fox, lox), hix);
             foy = fminf(fmaxf(foy, loy), hiy);
-            const int q = (int)__umul24((uint32_t)(y + (int)foy), (uint32_t)w) + x + (int)fox;   // w * h < 2^24
             // kinds are validated at creation (<= 3); the clamp keeps the
             // colour read inside the pixel whatever the device memory holds
             ch[t] = min(__float_as_uint(nd[t].w) - 1u, 2u);
-            pv[t] = pr.load(q, ch[t]);
+            pv[t] = pr.load(x + (int)fox, y + (int)foy, ch[t]);
         }
 #pragma unroll
         for (int t = 0; t < T; ++t) {

@@ -48,7 +48,7 @@ __device__ __forceinline__ double raycast_depth(const float* __restrict__ S0, in
 
 // grid (tiles, poses), 256 threads; partial[tile * 64 + pose],
 // cnt[(tile * 64 + pose) * 2 + {0: valid raycast, 1: valid in both}]
-__global__ __launch_bounds__(256) void k_depth_partial(const float* __restrict__ depth, int w, int h, float fx,
+__global__ __launch_bounds__(256) void k_depth_partial(FrameView src, int w, int h, float fx,
                                                        float fy, float cx, float cy,
                                                        const float* __restrict__ surfaces, int n_surf,
                                                        const float* __restrict__ poses, float zmin, float zmax,
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void k_depth_partial(const float* __restrict__
         const double z = raycast_depth(s_surf, n_surf, ox, oy, oz, dx, dy, dz);
         if (!(z >= (double)zmin && (zmax <= 0.0f || z <= (double)zmax))) continue;
         ++nm;
-        const float d = depth[p];
+        const float d = src.d(x, y);
         if (!depth_ok(d)) continue;
         acc += fabs((double)d - z);
         ++nb;
@@ -126,7 +126,7 @@ __global__ void k_depth_final(const double* __restrict__ partial, const int* __r
     counts[2 * pose + 1] = nb;
 }
 
-hipError_t launch_depth_scores(const float* depth, int w, int h, float fx, float fy, float cx, float cy,
+hipError_t launch_depth_scores(const FrameView& src, int w, int h, float fx, float fy, float cx, float cy,
                                const float* surfaces, int n_surf, const float* poses, int n_poses, float zmin,
                                float zmax, double* partial, int* cnt, double* out, long long* counts,
                                hipStream_t st)
@@ -134,7 +134,7 @@ hipError_t launch_depth_scores(const float* depth, int w, int h, float fx, float
     if (n_surf < 1 || n_surf > kMaxModelSurfaces || n_poses < 1 || n_poses > kMaxModelPoses)
         return hipErrorInvalidValue;
     const int ntiles = (w * h + kRankTile - 1) / kRankTile;
-    k_depth_partial<<<dim3(ntiles, n_poses), dim3(256), 0, st>>>(depth, w, h, fx, fy, cx, cy, surfaces, n_surf,
+    k_depth_partial<<<dim3(ntiles, n_poses), dim3(256), 0, st>>>(src, w, h, fx, fy, cx, cy, surfaces, n_surf,
                                                                   poses, zmin, zmax, partial, cnt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

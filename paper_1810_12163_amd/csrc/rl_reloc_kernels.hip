@@ -60,15 +60,19 @@ __global__ __launch_bounds__(256) void k_prep(const Job* __restrict__ jobs)
 
 // ------------------------------------------------------------------------
 // Frame ingest: the interleaved probe image (depth bits, R, G, B bytes) that
-// routing reads, one coalesced pass over the caller's planar buffers.
+// routing reads, one pass over the caller's buffers (any row pitch, RGB or
+// RGBA, every pixel or every second one); every later read of the frame is a
+// read of this image.
 __global__ __launch_bounds__(256) void k_pack(const Job* __restrict__ jobs)
 {
     const Job& J = jobs[blockIdx.y];
     const int P = J.w * J.h;
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (p >= P) return;
-    const uint32_t r = ldg(J.rgb + 3 * p), g = ldg(J.rgb + 3 * p + 1), b = ldg(J.rgb + 3 * p + 2);
-    J.probe[p] = make_uint2(__float_as_uint(ldg(J.depth + p)), r | (g << 8) | (b << 16));
+    const int x = p % J.w, y = p / J.w;
+    const uint8_t* c = J.src.c(x, y);
+    const uint32_t r = ldg(c), g = ldg(c + 1), b = ldg(c + 2);
+    J.probe[p] = make_uint2(__float_as_uint(J.src.d(x, y)), r | (g << 8) | (b << 16));
 }
 
 // ------------------------------------------------------------------------
@@ -105,7 +109,7 @@ __global__ __launch_bounds__(256) void k_traverse(const Job* __restrict__ jobs)
         if (depth_ok(d)) {
             const int NT = (1 << J.D) - 1;
             int leaf[T];
-            const PackedProbe pr{J.probe};
+            const PackedProbe pr{J.probe, (uint32_t)w};
             if (J.s == 1.0f) route<T, true>(J.nodes, NT, J.D, pr, w, h, x, y, d, J.s, leaf, s_top, ktop);
             else route<T, false>(J.nodes, NT, J.D, pr, w, h, x, y, d, J.s, leaf, s_top, ktop);
 #pragma unroll
@@ -1338,7 +1342,7 @@ __global__ __launch_bounds__(256) void k_refit_assign(const Job* __restrict__ jo
     for (int i = 0; i < 3; ++i) t[i] = hy.t[i];
     const int p = J.I[k];
     double x[3];
-    backproject(J.depth[p], p % J.w, p / J.w, J.fx, J.fy, J.cx, J.cy, x);
+    backproject(__uint_as_float(J.probe[p].x), p % J.w, p / J.w, J.fx, J.fy, J.cx, J.cy, x);
     const double y0 = R[0] * x[0] + R[1] * x[1] + R[2] * x[2] + t[0];
     const double y1 = R[3] * x[0] + R[4] * x[1] + R[5] * x[2] + t[1];
     const double y2 = R[6] * x[0] + R[7] * x[1] + R[8] * x[2] + t[2];
@@ -1435,7 +1439,7 @@ __device__ __forceinline__ void inlier_chunk(const Job& J, int k, int nI, bool o
 #pragma unroll
     for (int u = 0; u < kFinChunk; ++u) {
         ok[u] = ri[u] >= 0;
-        d[u] = ok[u] ? J.depth[p[u]] : 0.0f;
+        d[u] = ok[u] ? __uint_as_float(J.probe[p[u]].x) : 0.0f;
         a[u] = ok[u] ? J.modes[(size_t)ri[u] * 4] : make_float4(0.f, 0.f, 0.f, 0.f);
     }
 #pragma unroll
@@ -1468,6 +1472,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Job* __restrict_
             res->n_eligible = J.st->n_elig;
             res->rounds = rounds;
             res->n_out = 0;
+            res->mode_version = J.mode_version;
         }
         return;
     }
@@ -1549,6 +1554,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Job* __restrict_
         res->n_eligible = J.st->n_elig;
         res->rounds = rounds;
         res->n_out = min(n, J.n_out);
+        res->mode_version = J.mode_version;
     }
 }
 
@@ -1557,7 +1563,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Job* __restrict_
 // e1, e2, half-extents; half_a <= 0 = infinite plane): per (tile of 1024
 // pixels, pose) the sum of nearest-surface distances of H x^C(u) over valid
 // pixels, reduced in a fixed order; then the per-pose means.
-__global__ __launch_bounds__(256) void k_plane_partial(const float* __restrict__ depth, int w, int h, float fx,
+__global__ __launch_bounds__(256) void k_plane_partial(FrameView src, int w, int h, float fx,
                                                        float fy, float cx, float cy,
                                                        const float* __restrict__ surfaces, int n_surf,
                                                        const float* __restrict__ poses,
@@ -1578,7 +1584,7 @@ __global__ __launch_bounds__(256) void k_plane_partial(const float* __restrict__
     for (int k = 0; k < 4; ++k) {
         const int p = tile * 1024 + k * 256 + threadIdx.x;
         if (p >= P) break;
-        const float d = depth[p];
+        const float d = src.d(p % w, p / w);
         if (!depth_ok(d)) continue;
         double x[3];
         backproject(d, p % w, p / w, fx, fy, cx, cy, x);
@@ -1750,12 +1756,12 @@ hipError_t launch_select(const Job* jobs, int njobs, int round, int nptiles, int
     return hipSuccess;
 }
 
-hipError_t launch_plane_scores(const float* depth, int w, int h, float fx, float fy, float cx, float cy,
+hipError_t launch_plane_scores(const FrameView& src, int w, int h, float fx, float fy, float cx, float cy,
                                const float* surfaces, int n_surf, const float* poses, int n_poses,
                                double* partial, int* cnt, double* scores, hipStream_t st)
 {
     const int ntiles = (w * h + 1023) / 1024;
-    k_plane_partial<<<dim3(ntiles, n_poses), dim3(256), 0, st>>>(depth, w, h, fx, fy, cx, cy, surfaces, n_surf,
+    k_plane_partial<<<dim3(ntiles, n_poses), dim3(256), 0, st>>>(src, w, h, fx, fy, cx, cy, surfaces, n_surf,
                                                                   poses, partial, cnt);
     RL_CHECK_LAUNCH();
     k_plane_final<<<dim3(1), dim3(64), 0, st>>>(partial, cnt, ntiles, n_poses, scores);

@@ -33,11 +33,11 @@ hipError_t launch_score_all(const Job* jobs, int njobs, int rounds, int nptiles,
 hipError_t launch_lm(const Job* jobs, int njobs, int round, int maxSurv, int maxEta, int maxIters, hipStream_t st);
 hipError_t launch_select(const Job* jobs, int njobs, int round, int nptiles, int maxN, hipStream_t st);
 hipError_t launch_finalize(const Job* jobs, int njobs, int maxIlen, hipStream_t st);
-hipError_t launch_depth_scores(const float* depth, int w, int h, float fx, float fy, float cx, float cy,
+hipError_t launch_depth_scores(const FrameView& src, int w, int h, float fx, float fy, float cx, float cy,
                                const float* surfaces, int n_surf, const float* poses, int n_poses, float zmin,
                                float zmax, double* partial, int* cnt, double* out, long long* counts,
                                hipStream_t st);
-hipError_t launch_plane_scores(const float* depth, int w, int h, float fx, float fy, float cx, float cy,
+hipError_t launch_plane_scores(const FrameView& src, int w, int h, float fx, float fy, float cx, float cy,
                                const float* surfaces, int n_surf, const float* poses, int n_poses,
                                double* partial, int* cnt, double* scores, hipStream_t st);
 hipError_t launch_adapt(const AdaptArgs& a, hipStream_t st);
@@ -284,10 +284,33 @@ rl_status validate_frame(const rl_frame* f, int max_w, int max_h)
         return fail(RL_EINVAL, "frame %dx%d exceeds the %dx%d the scratch was sized for", f->width,
                     f->height, max_w, max_h);
     if (!f->depth || !f->rgb) return fail(RL_EINVAL, "frame depth/rgb pointer is NULL");
+    if (f->rgb_channels != 0 && f->rgb_channels != 3 && f->rgb_channels != 4)
+        return fail(RL_EINVAL, "rgb_channels must be 3 or 4 (0 = 3), got %d", f->rgb_channels);
+    if (f->step != 0 && f->step != 1 && f->step != 2) return fail(RL_EINVAL, "step must be 1 or 2 (0 = 1)");
+    const long long st = f->step ? f->step : 1, ch = f->rgb_channels ? f->rgb_channels : 3;
+    if (f->depth_pitch_bytes != 0 && (f->depth_pitch_bytes < 4 * st * f->width || f->depth_pitch_bytes % 4))
+        return fail(RL_EINVAL, "depth_pitch_bytes %d: at least %lld and a multiple of 4", f->depth_pitch_bytes,
+                    4 * st * f->width);
+    if (f->rgb_pitch_bytes != 0 && f->rgb_pitch_bytes < ch * st * f->width)
+        return fail(RL_EINVAL, "rgb_pitch_bytes %d: at least %lld", f->rgb_pitch_bytes, ch * st * f->width);
+    if (((uintptr_t)f->depth & 3) != 0) return fail(RL_EINVAL, "depth must be 4-byte aligned");
     const rl_intrinsics& K = f->K;
     if (!(finite_f(K.fx) && finite_f(K.fy) && finite_f(K.cx) && finite_f(K.cy)) || !(K.fx > 0) || !(K.fy > 0))
         return fail(RL_EINVAL, "invalid intrinsics");
     return RL_OK;
+}
+
+// The device view of a validated frame (zero fields take their defaults).
+FrameView frame_view(const rl_frame* f)
+{
+    FrameView v;
+    v.depth = f->depth;
+    v.rgb = f->rgb;
+    v.step = f->step ? (uint32_t)f->step : 1u;
+    v.ch = f->rgb_channels ? (uint32_t)f->rgb_channels : 3u;
+    v.dpitch = f->depth_pitch_bytes ? (uint32_t)f->depth_pitch_bytes : 4u * v.step * (uint32_t)f->width;
+    v.rpitch = f->rgb_pitch_bytes ? (uint32_t)f->rgb_pitch_bytes : v.ch * v.step * (uint32_t)f->width;
+    return v;
 }
 
 uint64_t stream_key64(uint64_t seed, uint64_t request_seed)
@@ -346,6 +369,7 @@ struct rl_room {
     // batched adaptations run on the room's stream; bev marks their end for
     // the batch's stream to wait on
     hipEvent_t bev;
+    uint32_t mode_version;    // mode updates queued so far (each RQS launch)
     std::vector<hipEvent_t> readers, spare;
     Job* job_host;
     rl_result* res_host;
@@ -430,7 +454,7 @@ RL_API rl_status rl_params_preset(const char* name, rl_params* out)
         p.min_squared_distance_between_sampled_modes = 0.0225f; p.pose_update = 1;
         p.ransac_inliers_per_iteration = 256; p.use_prediction_covariance = 0;
         p.max_relocalisations_to_output = 16;
-    } else if (n == "c1" || n == "c2") {
+    } else if (n == "c1" || n == "c2" || n == "c3" || n == "c4" || n == "c5") {
         p.clusterer_tau = 0.05f; p.min_cluster_size = 20; p.max_cluster_count = 10;
         p.reservoir_capacity = 1024; p.max_candidate_generation_iterations = 6000;
         p.max_pose_candidates = 1024; p.max_pose_candidates_after_cull = 1024;
@@ -443,6 +467,9 @@ RL_API rl_status rl_params_preset(const char* name, rl_params* out)
             p.min_cluster_size = 5; p.max_cluster_count = 5; p.reservoir_capacity = 64;
             p.max_pose_candidates = 64; p.max_pose_candidates_after_cull = 64;
             p.ransac_inliers_per_iteration = 100; p.final_refine = 0;
+        } else if (n == "c3") {
+            p.max_pose_candidates = 4096; p.max_pose_candidates_after_cull = 4096;
+            p.max_relocalisations_to_output = 16; p.final_refine = 0;
         }
     } else {
         return fail(RL_EINVAL, "unknown preset '%s'", name);
@@ -515,8 +542,8 @@ static Job make_job(const rl_room* r, char* scr, const FrameLayout& FL, const rl
     J.T = r->T;
     J.D = r->D;
     J.M = r->M;
-    J.depth = f->depth;
-    J.rgb = f->rgb;
+    J.src = frame_view(f);
+    J.mode_version = r->mode_version;
     J.w = f->width;
     J.h = f->height;
     J.fx = f->K.fx;
@@ -667,6 +694,7 @@ RL_API rl_status relocaliser_create(const rl_params* p, const rl_node* host_node
     r->modes_stale = false;
     r->rr_leaves = 0;
     r->rr_cursor = 0;
+    r->mode_version = 0;
     hipError_t e = hipEventCreateWithFlags(&r->ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&r->wev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&r->bev, hipEventDisableTiming);
@@ -913,8 +941,7 @@ static AdaptArgs adapt_args(const rl_room* r, const rl_frame* f, const float H[1
     a.D = r->D;
     a.L = (int)r->L;
     a.kappa = r->kappa;
-    a.depth = f->depth;
-    a.rgb = f->rgb;
+    a.src = frame_view(f);
     a.w = f->width;
     a.h = f->height;
     a.gw = f->width / 4 - 1;
@@ -982,6 +1009,7 @@ static rl_status write_modes(rl_room* r, const RqsArgs& a, hipStream_t st)
     r->readers.clear();
     if (e == hipSuccess) e = launch_rqs(a, 1024, st);
     if (e == hipSuccess) e = hipEventRecord(r->wev, st);
+    ++r->mode_version;
     if (e != hipSuccess) return hip_fail(e, "mode update launch");
     r->wrote = true;
     return RL_OK;
@@ -1250,7 +1278,7 @@ RL_API rl_status rl_plane_scores(rl_room* r, const rl_frame* f, const rl_surface
         e = hipMemcpyAsync(r->scr + r->ML.poses, hs + kMaxModelSurfaces * 64, (size_t)n_poses * 48,
                            hipMemcpyHostToDevice, r->stream);
     if (e == hipSuccess)
-        e = launch_plane_scores(f->depth, f->width, f->height, f->K.fx, f->K.fy, f->K.cx, f->K.cy,
+        e = launch_plane_scores(frame_view(f), f->width, f->height, f->K.fx, f->K.fy, f->K.cx, f->K.cy,
                                 reinterpret_cast<const float*>(r->scr + r->ML.surfaces), n_surf,
                                 reinterpret_cast<const float*>(r->scr + r->ML.poses), n_poses,
                                 reinterpret_cast<double*>(r->scr + r->ML.partial),
@@ -1290,7 +1318,7 @@ RL_API rl_status rl_depth_scores(rl_room* r, const rl_frame* f, const rl_surface
     if (e == hipSuccess)
         e = hipMemcpyAsync(r->scr + r->ML.poses, hp, (size_t)n_poses * 48, hipMemcpyHostToDevice, r->stream);
     if (e == hipSuccess)
-        e = launch_depth_scores(f->depth, f->width, f->height, f->K.fx, f->K.fy, f->K.cx, f->K.cy,
+        e = launch_depth_scores(frame_view(f), f->width, f->height, f->K.fx, f->K.fy, f->K.cx, f->K.cy,
                                 reinterpret_cast<const float*>(r->scr + r->ML.surfaces), n_surf,
                                 reinterpret_cast<const float*>(r->scr + r->ML.poses), n_poses, min_depth, max_depth,
                                 reinterpret_cast<double*>(r->scr + r->ML.dpartial),
@@ -1397,7 +1425,7 @@ RL_API rl_status rl_depth_scores_noalloc(const rl_frame* f, const rl_surface* su
     hipError_t e = hipMemcpyAsync(ws + kSsSurfaces, surfaces, (size_t)n_surf * 64, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(ws + kSsPoses, poses, (size_t)n_poses * 48, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
-        e = launch_depth_scores(f->depth, f->width, f->height, f->K.fx, f->K.fy, f->K.cx, f->K.cy,
+        e = launch_depth_scores(frame_view(f), f->width, f->height, f->K.fx, f->K.fy, f->K.cx, f->K.cy,
                                 reinterpret_cast<const float*>(ws + kSsSurfaces), n_surf,
                                 reinterpret_cast<const float*>(ws + kSsPoses), n_poses, min_depth, max_depth,
                                 reinterpret_cast<double*>(ws + kSsPartial), reinterpret_cast<int*>(ws + kSsCnt),
@@ -1644,6 +1672,7 @@ static rl_status batch_adapt(rl_batch* b, const rl_request* reqs, const std::vec
         }
         AdaptArgs a = adapt_args(r, &reqs[i].frame, reqs[i].cam_to_world);
         a.result = dev_results + i;
+        a.mode_version = r->mode_version + (r->rr_leaves ? 1u : 0u);   // after its own round-robin step
         e = launch_adapt(a, r->stream);
         if (e != hipSuccess) return hip_fail(e, "batched adaptation");
         r->modes_stale = true;

@@ -98,6 +98,8 @@ CONFIGS = {
     "c4": dict(_C2),
     "c5": dict(_C2),
 }
+# the cascade workload's room: sized for its widest stage
+CONFIGS["c3"] = dict(CONFIGS["c3c"])
 
 
 def preset(name: str) -> dict:

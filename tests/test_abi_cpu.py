@@ -81,7 +81,7 @@ int main(void) {
 
 def test_presets_match_the_shared_presets():
     from rlsynth import presets
-    for name in ["default", "fast", "intermediate", "slow", "c1", "c2"]:
+    for name in ["default", "fast", "intermediate", "slow", "c1", "c2", "c3", "c4", "c5"]:
         got = rl.preset(name)
         want = presets.preset(name)
         for k, v in got.items():

@@ -533,3 +533,97 @@ def test_adapt_every_grid_pixel_into_one_leaf_bit_exact():
     dirty = room.buffer_np(rl.BUF_DIRTY, np.uint32)
     np.testing.assert_array_equal(dirty != 0, o.dirty != 0)
     room.close()
+
+
+def _same_result(a, b):
+    assert a["status"] == b["status"] and a["winner"] == b["winner"] and a["n_valid"] == b["n_valid"]
+    assert np.array_equal(a["pose"], b["pose"]) and a["energy"] == b["energy"]
+
+
+def test_frames_read_in_place_pitched_rgba_and_decimated(c1):
+    """Frames in any row pitch, RGB or RGBA, and the 2x decimated frame read
+    in place (every second pixel of every second row) give the results of the
+    same pixels in tightly packed RGB buffers: relocalisation, adaptation and
+    the depth-raycast score, bit for bit."""
+    w, o, room = c1
+    q = w.queries[0]
+    d, c = dev(q)
+    ref = room.relocalise(d, c, q.K, request_seed=9)
+    # rows padded to 176 pixels, colour as RGBA
+    dp = torch.zeros((120, 176), dtype=torch.float32, device="cuda")
+    dp[:, :160] = d
+    cp = torch.full((120, 184, 4), 255, dtype=torch.uint8, device="cuda")
+    cp[:, :160, :3] = c
+    _same_result(room.relocalise(dp[:, :160], cp[:, :160], q.K, request_seed=9), ref)
+    _same_result(room.relocalise(dp[:, :160], cp[:, :160, :3], q.K, request_seed=9), ref)
+    # the 2x decimated view of a 320x240 frame against its packed copy
+    geom = scene.make_room(0)
+    d2, c2 = scene.render(geom, q.pose, 320, 240, seed=31)
+    D2, C2 = torch.from_numpy(d2).cuda(), torch.from_numpy(c2).cuda()
+    fx, fy, cx, cy = scene.intrinsics(320, 240)
+    Kd = (fx / 2, fy / 2, cx / 2, cy / 2)
+    packed = room.relocalise(D2[::2, ::2].contiguous(), C2[::2, ::2].contiguous(), Kd, request_seed=4)
+    _same_result(room.relocalise(D2[::2, ::2], C2[::2, ::2], Kd, request_seed=4), packed)
+    assert packed["n_eligible"] > 0
+    # depth-raycast scores from views
+    S = scene.surface_records(geom)
+    P = np.concatenate([q.pose[:3, :3].reshape(-1), q.pose[:3, 3]])[None].astype(np.float32)
+    a = room.depth_scores(dp[:, :160], cp[:, :160], q.K, S, P, 0.5, 4.0)
+    b = room.depth_scores(d, c, q.K, S, P, 0.5, 4.0)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+    # adaptation from a pitched RGBA view and from packed buffers
+    rooms = [rl.Room(w.params, w.nodes, 160, 120) for _ in range(2)]
+    for f in w.adapt:
+        fd, fc = dev(f)
+        rooms[0].adapt(fd, fc, f.K, f.pose)
+        pd = torch.zeros((120, 168), dtype=torch.float32, device="cuda")
+        pd[:, :160] = fd
+        pc = torch.zeros((120, 160, 4), dtype=torch.uint8, device="cuda")
+        pc[..., :3] = fc
+        rooms[1].adapt(pd[:, :160], pc, f.K, f.pose)
+    rooms[0].update_modes()
+    rooms[1].update_modes()
+    _same_room_state(rooms[0], rooms[1], "adapt from views")
+    for r in rooms:
+        r.close()
+    # views the library cannot read in place are refused
+    with pytest.raises(TypeError):
+        room.relocalise(d[:, ::3], c[:, ::3], q.K)
+
+
+@pytest.mark.parametrize("leaves_per_frame", [0, 64])
+def test_mode_version_counts_mode_updates(leaves_per_frame):
+    """rl_result.mode_version: the mode updates a relocalisation's room had
+    received; equal for the plain and the batched path, unchanged between two
+    relocalisations with no adaptation in between, and advanced by an
+    adaptation (at the next relocalisation under the exact schedule, at the
+    adaptation itself under the round-robin one)."""
+    w = workloads.c1(n_queries=1)
+    room = rl.Room(w.params, w.nodes, 160, 120)
+    room.set_mode_schedule(leaves_per_frame)
+    q = w.queries[0]
+    d, c = dev(q)
+    v0 = room.relocalise(d, c, q.K)["mode_version"]
+    assert v0 == 0
+    versions = []
+    batch = rl.Batch(2, 160, 120, 64, 100, 6, 1, 5)
+    for f in w.adapt:
+        room.adapt(*dev(f), f.K, f.pose)
+        a = room.relocalise(d, c, q.K, request_seed=1)
+        b = room.relocalise(d, c, q.K, request_seed=2)
+        g = batch.relocalise([(room, d, c, q.K, 1)])[0]
+        assert a["mode_version"] == b["mode_version"] == g["mode_version"]
+        _same_result(a, g)
+        versions.append(a["mode_version"])
+    assert versions == list(range(1, len(w.adapt) + 1))
+    # an adaptation inside a batch reports the version after its own update
+    f = w.adapt[0]
+    got = batch.relocalise([(room, d, c, q.K, 3), rl.AdaptRequest(room, *dev(f), f.K, f.pose)])
+    assert got[0]["mode_version"] == versions[-1]
+    after = room.relocalise(d, c, q.K)["mode_version"]
+    assert after == versions[-1] + 1
+    if leaves_per_frame:
+        assert got[1]["mode_version"] == after
+    batch.close()
+    room.close()
