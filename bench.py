@@ -147,7 +147,7 @@ def main():
     ap.add_argument("--lm-steps", type=int, default=5,
                     help="steps of the batch with LM refinement (0 = skip that leg)")
     ap.add_argument("--schedule", default="auto",
-                    help="launch schedule 'ipt,fast_waves' (e.g. 4,1), or 'auto' to time every one first")
+                    help="launch schedule 'ipt,fast_waves[,lds_levels]' (e.g. 4,1,8), or 'auto' to time every one first")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device-to-device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -217,7 +217,7 @@ def main():
         room.set_schedule(*fixed)
     elif args.plain > 0:
         best, t = autotune.tune_room(room, qd[0], qc[0], w.queries[0].K, reps=5)
-        tuning["plain"] = {f"{k[0]},{k[1]}": float(np.median(v)) for k, v in t.items()}
+        tuning["plain"] = {",".join(str(x) for x in k): float(np.median(v)) for k, v in t.items()}
         log(f"[bench] plain schedule {best} (median ms {tuning['plain']})")
 
     # ---- plain path: one frame per synchronous call -----------------------
@@ -272,7 +272,7 @@ def main():
         batch.set_schedule(*fixed)
     else:
         best, t = autotune.tune_batch(batch, reqs, reps=5, use_graph=not args.no_graph)
-        tuning["batched"] = {f"{k[0]},{k[1]}": float(np.median(v)) for k, v in t.items()}
+        tuning["batched"] = {",".join(str(x) for x in k): float(np.median(v)) for k, v in t.items()}
         log(f"[bench] batched schedule {best} (median ms {tuning['batched']})")
     timer = {"traverse": rl.TIMER_TRAVERSE, "hyp_search": rl.TIMER_HYP_SEARCH, "ransac": rl.TIMER_RANSAC}[args.timer]
     use_graph = not args.no_graph

@@ -1,11 +1,12 @@
 """Chooses the launch schedule of a batch or a room by timing it on the
 caller's own requests.
 
-The schedule (search iterations per thread, width of the all-rounds scoring)
-changes no result: every hypothesis draws its samples from its own Philox
-counters whichever thread runs it, and every energy is summed in the same
-order.  So the choice is a pure timing decision, made on the device and
-workload that will use it.
+The schedule (search iterations per thread, width of the all-rounds scoring,
+tree levels the traversal reads from LDS) changes no result: every hypothesis
+draws its samples from its own Philox counters whichever thread runs it,
+every energy is summed in the same order, and a node is the same bits from
+LDS or from global memory.  So the choice is a pure timing decision, made on
+the device and workload that will use it.
 """
 
 from __future__ import annotations
@@ -15,15 +16,15 @@ import time
 
 import numpy as np
 
-from . import SCHEDULE_FAST_WAVES, SCHEDULE_IPT, Result
+from . import SCHEDULE_FAST_WAVES, SCHEDULE_IPT, SCHEDULE_LDS_LEVELS, Result
 
-DEFAULT = (4, 1)
+DEFAULT = (4, 1, 8)
 
 
-def candidates(ipts=SCHEDULE_IPT, fast_waves=SCHEDULE_FAST_WAVES) -> list:
-    """Every (iterations per thread, fast waves) pair, the default first."""
-    out = [DEFAULT] if DEFAULT[0] in ipts and DEFAULT[1] in fast_waves else []
-    out += [(i, f) for i in ipts for f in fast_waves if (i, f) != DEFAULT]
+def candidates(ipts=SCHEDULE_IPT, fast_waves=SCHEDULE_FAST_WAVES, lds_levels=SCHEDULE_LDS_LEVELS) -> list:
+    """Every (iterations per thread, fast waves, LDS levels) schedule, the default first."""
+    out = [DEFAULT] if DEFAULT[0] in ipts and DEFAULT[1] in fast_waves and DEFAULT[2] in lds_levels else []
+    out += [(i, f, l) for i in ipts for f in fast_waves for l in lds_levels if (i, f, l) != DEFAULT]
     return out
 
 

@@ -34,12 +34,9 @@ constexpr int kMaxBatchFrames = 4096;
 
 constexpr int kMaxFastWaves = 4;
 
-// levels of every tree the traversal reads from LDS (T x (2^levels - 1)
-// node records per block)
-#ifndef RL_TOP_LEVELS
-#define RL_TOP_LEVELS 6
-#endif
-constexpr int kTopLevels = RL_TOP_LEVELS;
+// levels of every tree the traversal may read from LDS (T x (2^levels - 1)
+// node records per block): a launch schedule, 6 or 8
+constexpr int kTopLevelsMin = 6, kTopLevelsMax = 8;
 
 // LM refinement: pixels per pass wave, doubles of per-slot state
 constexpr int kLmTile = 128;

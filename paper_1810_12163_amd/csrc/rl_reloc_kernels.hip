@@ -78,7 +78,7 @@ __global__ __launch_bounds__(256) void k_pack(const Job* __restrict__ jobs)
 // ------------------------------------------------------------------------
 // One thread per pixel, all trees in lockstep.  Writes leaves (16 B/pixel),
 // per-tree mode counts (8 B/pixel), |M(u)| and the tile's eligible count.
-template <int T>
+template <int T, int TOP>
 __global__ __launch_bounds__(256) void k_traverse(const Job* __restrict__ jobs)
 {
     const Job& J = jobs[blockIdx.y];
@@ -86,8 +86,8 @@ __global__ __launch_bounds__(256) void k_traverse(const Job* __restrict__ jobs)
     if ((int)blockIdx.x * 256 >= P) return;
     __shared__ int s_wave[4];
     // the top levels of every tree, shared by the block's pixels
-    __shared__ float4 s_top[T * ((1 << kTopLevels) - 1)];
-    const int ktop = min(J.D, kTopLevels), ntop = (1 << ktop) - 1;
+    __shared__ float4 s_top[T * ((1 << TOP) - 1)];
+    const int ktop = min(J.D, TOP), ntop = (1 << ktop) - 1;
     for (int i = threadIdx.x; i < T * ntop; i += 256) {
         const int t = i / ntop;
         s_top[i] = ldg(J.nodes + t * ((1 << J.D) - 1) + (i - t * ntop));
@@ -1651,24 +1651,32 @@ hipError_t launch_prep(const Job* jobs, int njobs, int maxN, hipStream_t st)
     return hipSuccess;
 }
 
-hipError_t launch_traverse(const Job* jobs, int njobs, int maxP, int T, hipStream_t st)
+template <int TOP>
+static hipError_t launch_traverse_top(const Job* jobs, dim3 gp, dim3 blk, int T, hipStream_t st)
+{
+    switch (T) {
+        case 1: k_traverse<1, TOP><<<gp, blk, 0, st>>>(jobs); break;
+        case 2: k_traverse<2, TOP><<<gp, blk, 0, st>>>(jobs); break;
+        case 3: k_traverse<3, TOP><<<gp, blk, 0, st>>>(jobs); break;
+        case 4: k_traverse<4, TOP><<<gp, blk, 0, st>>>(jobs); break;
+        case 5: k_traverse<5, TOP><<<gp, blk, 0, st>>>(jobs); break;
+        case 6: k_traverse<6, TOP><<<gp, blk, 0, st>>>(jobs); break;
+        case 7: k_traverse<7, TOP><<<gp, blk, 0, st>>>(jobs); break;
+        case 8: k_traverse<8, TOP><<<gp, blk, 0, st>>>(jobs); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// top: tree levels read from LDS (6 or 8; a launch schedule, same leaves)
+hipError_t launch_traverse(const Job* jobs, int njobs, int maxP, int T, int top, hipStream_t st)
 {
     const dim3 blk(256), gp((maxP + 255) / 256, njobs);
     k_pack<<<gp, blk, 0, st>>>(jobs);
     RL_CHECK_LAUNCH();
-    switch (T) {
-        case 1: k_traverse<1><<<gp, blk, 0, st>>>(jobs); break;
-        case 2: k_traverse<2><<<gp, blk, 0, st>>>(jobs); break;
-        case 3: k_traverse<3><<<gp, blk, 0, st>>>(jobs); break;
-        case 4: k_traverse<4><<<gp, blk, 0, st>>>(jobs); break;
-        case 5: k_traverse<5><<<gp, blk, 0, st>>>(jobs); break;
-        case 6: k_traverse<6><<<gp, blk, 0, st>>>(jobs); break;
-        case 7: k_traverse<7><<<gp, blk, 0, st>>>(jobs); break;
-        case 8: k_traverse<8><<<gp, blk, 0, st>>>(jobs); break;
-        default: return hipErrorInvalidValue;
-    }
-    RL_CHECK_LAUNCH();
-    return hipSuccess;
+    if (top == kTopLevelsMax) return launch_traverse_top<kTopLevelsMax>(jobs, gp, blk, T, st);
+    if (top == kTopLevelsMin) return launch_traverse_top<kTopLevelsMin>(jobs, gp, blk, T, st);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_eligible(const Job* jobs, int njobs, int maxP, hipStream_t st)

@@ -23,7 +23,7 @@
 
 namespace rl {
 hipError_t launch_prep(const Job* jobs, int njobs, int maxN, hipStream_t st);
-hipError_t launch_traverse(const Job* jobs, int njobs, int maxP, int T, hipStream_t st);
+hipError_t launch_traverse(const Job* jobs, int njobs, int maxP, int T, int top, hipStream_t st);
 hipError_t launch_eligible(const Job* jobs, int njobs, int maxP, hipStream_t st);
 hipError_t launch_hyp_search(const Job* jobs, int njobs, int maxN, int maxIters, int ipt, hipStream_t st);
 hipError_t launch_hyp_finalize(const Job* jobs, int njobs, int maxN, hipStream_t st);
@@ -340,6 +340,7 @@ struct Timer {
 struct Schedule {
     int ipt = 4;
     int fw = 1;
+    int top = kTopLevelsMax;   // tree levels the traversal reads from LDS
     int screen = 1;   // the search rejects clearly degenerate triplets (else only the exact test does)
 };
 
@@ -1093,30 +1094,34 @@ RL_API rl_status relocaliser_set_mode_schedule(rl_room* r, int32_t leaves_per_fr
     return RL_OK;
 }
 
-static rl_status check_schedule(int ipt, int fast_waves)
+static rl_status check_schedule(int ipt, int fast_waves, int lds_levels)
 {
     if (ipt != 2 && ipt != 4 && ipt != 8) return fail(RL_EINVAL, "iterations per thread must be 2, 4 or 8");
     if (fast_waves != 1 && fast_waves != 2 && fast_waves != 4) return fail(RL_EINVAL, "fast_waves must be 1, 2 or 4");
+    if (lds_levels != kTopLevelsMin && lds_levels != kTopLevelsMax)
+        return fail(RL_EINVAL, "lds_levels must be %d or %d", kTopLevelsMin, kTopLevelsMax);
     return RL_OK;
 }
 
-RL_API rl_status relocaliser_set_schedule(rl_room* r, int32_t ipt, int32_t fast_waves)
+RL_API rl_status relocaliser_set_schedule(rl_room* r, int32_t ipt, int32_t fast_waves, int32_t lds_levels)
 {
     if (!r) return fail(RL_EINVAL, "room is NULL");
-    rl_status s = check_schedule(ipt, fast_waves);
+    rl_status s = check_schedule(ipt, fast_waves, lds_levels);
     if (s != RL_OK) return s;
     r->sched.ipt = ipt;
     r->sched.fw = fast_waves;
+    r->sched.top = lds_levels;
     return RL_OK;
 }
 
-RL_API rl_status rl_batch_set_schedule(rl_batch* b, int32_t ipt, int32_t fast_waves)
+RL_API rl_status rl_batch_set_schedule(rl_batch* b, int32_t ipt, int32_t fast_waves, int32_t lds_levels)
 {
     if (!b) return fail(RL_EINVAL, "batch is NULL");
-    rl_status s = check_schedule(ipt, fast_waves);
+    rl_status s = check_schedule(ipt, fast_waves, lds_levels);
     if (s != RL_OK) return s;
     b->sched.ipt = ipt;
     b->sched.fw = fast_waves;
+    b->sched.top = lds_levels;
     return RL_OK;
 }
 
@@ -1143,7 +1148,7 @@ static hipError_t launch_sequence(const Job* jobs, int njobs, int maxP, int maxN
 #define RL_MARK(k, ev) do { if (tm.kernel == (k)) RL_TRY(hipEventRecord(tm.ev, st)); } while (0)
     RL_TRY(launch_prep(jobs, njobs, maxN, st));
     RL_MARK(RL_TIMER_TRAVERSE, start);
-    RL_TRY(launch_traverse(jobs, njobs, maxP, T, st));
+    RL_TRY(launch_traverse(jobs, njobs, maxP, T, sc.top, st));
     RL_MARK(RL_TIMER_TRAVERSE, stop);
     RL_TRY(launch_eligible(jobs, njobs, maxP, st));
     RL_MARK(RL_TIMER_HYP_SEARCH, start);
@@ -1239,7 +1244,7 @@ RL_API rl_status relocaliser_relocalise_opts(rl_room* r, const rl_frame* f, uint
     if (e != hipSuccess) return hip_fail(e, "job upload");
     const int nptiles = (eta + r->TP - 1) / r->TP;
     const int P = f->width * f->height;
-    std::vector<long long> key = {P, N, r->sched.ipt, r->sched.fw, lm, r->p.lm_iterations, iters, eta};
+    std::vector<long long> key = {P, N, r->sched.ipt, r->sched.fw, r->sched.top, lm, r->p.lm_iterations, iters, eta};
     for (int v : entering) key.push_back(v);
     e = run_sequence(r->graphs, key, r->timer.kernel == RL_TIMER_NONE, r->stream, [&]() {
         return launch_sequence(jd, 1, P, N, iters, r->T, entering, nptiles, eta, lm != 0, r->p.lm_iterations,
@@ -1636,7 +1641,7 @@ static rl_status batch_relocalise_queue(rl_batch* b, const rl_request* reqs, con
     const int nptiles = (maxEta + b->TP - 1) / b->TP;
     if (use_graph && b->stream == nullptr)
         return fail(RL_EINVAL, "graph replay needs a batch created on a non-default stream");
-    std::vector<long long> key = {nq, maxN, maxIters, nptiles, maxEta, b->bp.n_trees, b->sched.ipt, b->sched.fw,
+    std::vector<long long> key = {nq, maxN, maxIters, nptiles, maxEta, b->bp.n_trees, b->sched.ipt, b->sched.fw, b->sched.top,
                                   any_lm ? 1 : 0, lm_iters};
     for (int v : entering) key.push_back(v);
     e = run_sequence(b->graphs, key, use_graph && b->timer.kernel == RL_TIMER_NONE, b->stream, [&]() {
