@@ -291,7 +291,7 @@ __device__ __forceinline__ uint32_t mode_row_index(const Job& J, uint4 lw, uint2
 
 // One (pixel, mode) pair of a triplet, from list entry e and mode index m of
 // M(u): the entry's 32-byte record holds the pixel, its depth and its leaf
-// record, so the pair costs two gathers (record, mode row).
+// record, so the pair costs two dependent gathers (record, mode row).
 struct Pair {
     int p, m;
     float d;
@@ -299,9 +299,9 @@ struct Pair {
     double xw[3], xc[3];
 };
 
-__device__ __forceinline__ void pair_at(const Job& J, uint32_t e, int m, Pair& q)
+// the pair from list-entry record (c0, c1) and mode index m of M(u)
+__device__ __forceinline__ void pair_from(const Job& J, uint4 c0, uint4 c1, int m, Pair& q)
 {
-    const uint4 c0 = ldg(J.ecold + 2 * e), c1 = ldg(J.ecold + 2 * e + 1);
     q.p = (int)c0.x;
     q.d = __uint_as_float(c0.y);
     q.m = m;
@@ -312,13 +312,15 @@ __device__ __forceinline__ void pair_at(const Job& J, uint32_t e, int m, Pair& q
     q.xw[2] = w.z;
 }
 
-// the pair drawn by (rp, rm): entry from rp, mode from rm over |M(u)|
+// the pair drawn by (rp, rm): entry from rp, mode from rm over |M(u)|; both
+// halves of the entry's record are loaded together (one cache line), so the
+// pair costs two dependent gathers
 __device__ __forceinline__ void draw_pair(const Job& J, int n_elig, uint32_t rp, uint32_t rm, Pair& q)
 {
     const uint32_t e = below(rp, (uint32_t)n_elig);
-    const uint4 c0 = ldg(J.ecold + 2 * e);
+    const uint4 c0 = ldg(J.ecold + 2 * e), c1 = ldg(J.ecold + 2 * e + 1);
     const uint2 nw = make_uint2(c0.z, c0.w);
-    pair_at(J, e, (int)below(rm, (uint32_t)modes_total(nw, J.T)), q);
+    pair_from(J, c0, c1, (int)below(rm, (uint32_t)modes_total(nw, J.T)), q);
 }
 
 __device__ __forceinline__ void pair_backproject(const Job& J, Pair& q)
@@ -400,9 +402,11 @@ __device__ __forceinline__ bool hyp_stage_b(const Job& J, int n_elig, int slot, 
                                             Hyp* out)
 {
 #pragma clang fp contract(off)
+    // pair k*'s record is known before the second block is drawn
+    const uint4 k0 = ldg(J.ecold + 2 * (uint32_t)ec), k1 = ldg(J.ecold + 2 * (uint32_t)ec + 1);
     const uint4 b = philox(make_uint4((kTagHyp << 28) | 1u, (uint32_t)slot, (uint32_t)it, 0u), J.key0, J.key1);
     Pair pk, pa, pb;
-    pair_at(J, (uint32_t)ec, mc, pk);
+    pair_from(J, k0, k1, mc, pk);
     draw_pair(J, n_elig, b.x, b.z, pa);
     double dka, dkb, dab;
     if (!world_far(J, pk, pa, dka)) return false;
