@@ -497,13 +497,12 @@ __global__ RL_HYP_BOUNDS void k_hyp_search(const Job* __restrict__ jobs, int Nma
     if (n_elig <= 0) return;
     __shared__ uint32_t q_it[256 * IPT];   // iteration | k* << 30
     __shared__ uint32_t q_em[256 * IPT];   // list entry | mode << 24
-    __shared__ int s_n, s_best, s_skip;
+    __shared__ int s_n, s_skip;
     // The early-exit test reads a value other blocks lower concurrently, so
     // one thread takes it for the whole block: every wave leaves together,
     // and no wave runs on without the shared counters initialised.
     if (threadIdx.x == 0) {
         s_n = 0;
-        s_best = INT_MAX;
 #if RL_HYP_EARLY_EXIT
         s_skip = __hip_atomic_load(&J.hyp_best[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < it0;
 #else
@@ -536,14 +535,15 @@ __global__ RL_HYP_BOUNDS void k_hyp_search(const Job* __restrict__ jobs, int Nma
         }
     }
     __syncthreads();
+    // Stage B holds no barrier: a wave with no queued entry ends here and
+    // frees its slot for other blocks; a passing iteration lowers the slot's
+    // minimum directly (rare, so the atomics are few).
     const int n = min(s_n, 256 * IPT);
     for (int j = threadIdx.x; j < n; j += 256) {
         const int it = (int)(q_it[j] & 0x3FFFFFFFu), kc = (int)(q_it[j] >> 30);
         const int ec = (int)(q_em[j] & 0xFFFFFFu), mc = (int)(q_em[j] >> 24);
-        if (hyp_stage_b<false>(J, n_elig, slot, it, kc, ec, mc, nullptr)) atomicMin(&s_best, it);
+        if (hyp_stage_b<false>(J, n_elig, slot, it, kc, ec, mc, nullptr)) atomicMin(&J.hyp_best[slot], it);
     }
-    __syncthreads();
-    if (threadIdx.x == 0 && s_best != INT_MAX) atomicMin(&J.hyp_best[slot], s_best);
 }
 
 __global__ __launch_bounds__(256) void k_hyp_finalize(const Job* __restrict__ jobs)
