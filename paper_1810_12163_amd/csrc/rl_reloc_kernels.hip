@@ -480,9 +480,13 @@ __device__ __forceinline__ bool xcd_place(int w, int X, int njobs, int s, int& j
 }
 
 // Per job, x = chunk * Nmax + slot (chunk-major); a block covers 256 * IPT
-// consecutive iterations of one slot.  A block whose chunk starts after an
-// already-found passing iteration exits early; the minimum stays exact
-// because every lower iteration is always evaluated.
+// consecutive iterations of one slot, each of its waves 64 * IPT of them on
+// its own: stage A, a queue in the wave's part of LDS (positions from a
+// ballot), stage B, with no block barrier, so a wave never waits for
+// another.  A wave whose iterations start after an already-found passing
+// iteration leaves at once; the minimum stays exact because every lower
+// iteration is always evaluated, and a passing iteration lowers the slot's
+// minimum directly (rare, so the atomics are few).
 template <int IPT>
 __global__ RL_HYP_BOUNDS void k_hyp_search(const Job* __restrict__ jobs, int Nmax, int njobs, int X, int s)
 {
@@ -491,57 +495,53 @@ __global__ RL_HYP_BOUNDS void k_hyp_search(const Job* __restrict__ jobs, int Nma
     const Job& J = jobs[job];
     const int slot = x % Nmax, chunk = x / Nmax;
     if (slot >= J.N) return;
-    const int it0 = chunk * 256 * IPT;
+    const int wv = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+    const int it0 = chunk * 256 * IPT + wv * 64 * IPT;
     if (it0 >= J.I_max) return;
     const int n_elig = J.st->n_elig;
     if (n_elig <= 0) return;
-    __shared__ uint32_t q_it[256 * IPT];   // iteration | k* << 30
-    __shared__ uint32_t q_em[256 * IPT];   // list entry | mode << 24
-    __shared__ int s_n, s_skip;
-    // The early-exit test reads a value other blocks lower concurrently, so
-    // one thread takes it for the whole block: every wave leaves together,
-    // and no wave runs on without the shared counters initialised.
-    if (threadIdx.x == 0) {
-        s_n = 0;
+    __shared__ uint32_t q_it[4][64 * IPT];   // iteration | k* << 30
+    __shared__ uint32_t q_em[4][64 * IPT];   // list entry | mode << 24
 #if RL_HYP_EARLY_EXIT
-        s_skip = __hip_atomic_load(&J.hyp_best[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < it0;
-#else
-        s_skip = 0;
+    // the exit is decided on one value for the whole wave (other blocks
+    // lower it concurrently), so its lanes leave together
+    const int best = __builtin_amdgcn_readfirstlane(
+        __hip_atomic_load(&J.hyp_best[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (best < it0) return;
 #endif
-    }
-    __syncthreads();
-    if (s_skip) return;
     // stage A in two passes: all IPT draws and record loads are issued before
     // any of them is consumed, so the gathers overlap
     uint32_t ka[IPT], ea[IPT], za[IPT];
     uint64_t ha[IPT];
 #pragma unroll
     for (int k = 0; k < IPT; ++k) {
-        const uint32_t it = (uint32_t)(it0 + k * 256 + (int)threadIdx.x);
+        const uint32_t it = (uint32_t)(it0 + k * 64 + lane);
         const uint4 a = philox(make_uint4((kTagHyp << 28) | 0u, (uint32_t)slot, it, 0u), J.key0, J.key1);
         ka[k] = below(a.x, 3u);
         ea[k] = below(a.y, (uint32_t)n_elig);
         za[k] = a.z;
         ha[k] = ldg(J.erec + ea[k] * (uint32_t)J.ew);
     }
+    int n = 0;
 #pragma unroll
     for (int k = 0; k < IPT; ++k) {
-        const int it = it0 + k * 256 + (int)threadIdx.x;
+        const int it = it0 + k * 64 + lane;
         const uint32_t m = below(za[k], erec_total(ha[k]));
-        if (it < J.I_max && erec_bit(J.erec + ea[k] * (uint32_t)J.ew, ha[k], m)) {
-            const int q = atomicAdd(&s_n, 1);
-            q_it[q] = (uint32_t)it | (ka[k] << 30);
-            q_em[q] = ea[k] | (m << 24);
+        const bool pass = it < J.I_max && erec_bit(J.erec + ea[k] * (uint32_t)J.ew, ha[k], m);
+        const uint64_t mask = __ballot(pass);
+        if (pass) {
+            const int q = n + (int)__popcll(mask & ((1ull << lane) - 1ull));
+            q_it[wv][q] = (uint32_t)it | (ka[k] << 30);
+            q_em[wv][q] = ea[k] | (m << 24);
         }
+        n += (int)__popcll(mask);
     }
-    __syncthreads();
-    // Stage B holds no barrier: a wave with no queued entry ends here and
-    // frees its slot for other blocks; a passing iteration lowers the slot's
-    // minimum directly (rare, so the atomics are few).
-    const int n = min(s_n, 256 * IPT);
-    for (int j = threadIdx.x; j < n; j += 256) {
-        const int it = (int)(q_it[j] & 0x3FFFFFFFu), kc = (int)(q_it[j] >> 30);
-        const int ec = (int)(q_em[j] & 0xFFFFFFu), mc = (int)(q_em[j] >> 24);
+    // the wave reads back only its own queue: its LDS writes precede its reads
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int j = lane; j < n; j += 64) {
+        const int it = (int)(q_it[wv][j] & 0x3FFFFFFFu), kc = (int)(q_it[wv][j] >> 30);
+        const int ec = (int)(q_em[wv][j] & 0xFFFFFFu), mc = (int)(q_em[wv][j] >> 24);
         if (hyp_stage_b<false>(J, n_elig, slot, it, kc, ec, mc, nullptr)) atomicMin(&J.hyp_best[slot], it);
     }
 }
