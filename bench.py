@@ -117,7 +117,7 @@ def main():
     ap.add_argument("--queries", type=int, default=16)
     ap.add_argument("--adapt-frames", type=int, default=50)
     ap.add_argument("--plain", type=int, default=32, help="plain relocalisations timed for latency")
-    ap.add_argument("--cpu-frames", type=int, default=64,
+    ap.add_argument("--cpu-frames", type=int, default=160,
                     help="oracle relocalisations on all host threads, about 10-20 s of host work (0 = skip)")
     ap.add_argument("--cpu-frames-1t", type=int, default=4,
                     help="oracle relocalisations on one thread, beside the threaded figure")
