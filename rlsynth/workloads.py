@@ -213,11 +213,14 @@ RESOLUTIONS = [(160, 120), (320, 240), (640, 480)]
 HYPOTHESES = {160: 256, 320: 512, 640: 1024}
 
 
-def serving_setup(n_rooms=16, n_adapt=20, n_cameras=32, frames_per_camera=4, processes=16):
+def serving_setup(n_rooms=16, n_adapt=20, n_cameras=32, frames_per_camera=4, processes=16, query_rooms=0,
+                  queries_per_room=0):
     """Rooms for the serving workload: room r has the 640x480 forest of seed
     1000 + r, adapted from n_adapt frames.  Camera c watches room c % n_rooms at
     resolution RESOLUTIONS[c % 3]; its frames lie within 20 cm / 20 degrees of
-    that room's adaptation poses (ground-truth poses kept for adaptation)."""
+    that room's adaptation poses (ground-truth poses kept for adaptation).
+    Rooms below query_rooms also get queries_per_room distinct 640x480 query
+    frames (rooms[r]["queries"]), drawn the same way."""
     rooms, adapt_jobs, cam_jobs = [], [], []
     for r in range(n_rooms):
         room = _scene.make_room(r)
@@ -235,10 +238,20 @@ def serving_setup(n_rooms=16, n_adapt=20, n_cameras=32, frames_per_camera=4, pro
             base = rooms[r]["poses"][int(rng.integers(n_adapt))]
             p = _scene.near_pose(room, base, rng, 0.20, 20.0)
             cam_jobs.append((r, p, w, h, frame_seed(r, 5, c * 100 + k)))
-    frames = render_many(adapt_jobs + cam_jobs, processes)
+    q_jobs = []
+    for r in range(min(n_rooms, query_rooms)):
+        room = _scene.make_room(r)
+        rng = np.random.default_rng(frame_seed(r, 4, 0))
+        for k in range(queries_per_room):
+            base = rooms[r]["poses"][int(rng.integers(n_adapt))]
+            q_jobs.append((r, _scene.near_pose(room, base, rng, 0.20, 20.0), 640, 480, frame_seed(r, 4, k)))
+    frames = render_many(adapt_jobs + cam_jobs + q_jobs, processes)
     na = len(adapt_jobs)
     for r in range(n_rooms):
         rooms[r]["adapt"] = frames[r * n_adapt:(r + 1) * n_adapt]
+        rooms[r]["queries"] = []
+    for j, fr in zip(q_jobs, frames[na + len(cam_jobs):]):
+        rooms[j[0]]["queries"].append(fr)
     cams = []
     for c in range(n_cameras):
         cams.append(dict(room=c % n_rooms, frames=frames[na + c * frames_per_camera: na + (c + 1) * frames_per_camera]))
