@@ -147,7 +147,8 @@ def main():
     ap.add_argument("--lm-steps", type=int, default=5,
                     help="steps of the batch with LM refinement (0 = skip that leg)")
     ap.add_argument("--schedule", default="auto",
-                    help="launch schedule 'ipt,fast_waves[,lds_levels]' (e.g. 4,1,8), or 'auto' to time every one first")
+                    help="launch schedule 'ipt,fast_waves[,lds_levels[,score_window]]' (e.g. 4,1,8,0), or 'auto' to "
+                         "time every one first")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device-to-device copy of this size (counter calibration)")
     args = ap.parse_args()

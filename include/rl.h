@@ -497,15 +497,21 @@ rl_status rl_batch_set_timer(rl_batch* b, int32_t kernel, void* start_event, voi
  * width in 64-lane waves (1, 2 or 4) of the scoring that, once a request has
  * at most 64 * fast_waves surviving hypotheses, scores all its remaining
  * rounds at once; lds_levels = tree levels the traversal reads from a
- * per-workgroup LDS copy instead of global memory (6 or 8).  None changes
- * any result: each hypothesis draws from its own Philox counters whichever
- * thread runs it, every energy is summed in the same order, and a node
- * record is the same bits wherever it is read from.  Defaults: ipt 4,
- * fast_waves 1, lds_levels 8.  Applies to later calls; RL_EINVAL for other
- * values.  Not thread-safe against concurrent calls on the same room / batch.
+ * per-workgroup LDS copy instead of global memory (6 or 8); score_window =
+ * 0 to score all those remaining rounds in one pass, or 1..3 to score that
+ * many rounds first, select, and then score the rest for the survivors only
+ * (less scoring work, one more pass).  None changes any result: each
+ * hypothesis draws from its own Philox counters whichever thread runs it,
+ * every energy is summed in the same order, and a node record is the same
+ * bits wherever it is read from.  Defaults: ipt 4, fast_waves 1, lds_levels
+ * 8, score_window 0 for a room (one frame per call: fewer launches) and 2
+ * for a batch.  Applies to later calls; RL_EINVAL for other values.
+ * Not thread-safe against concurrent calls on the same room / batch.
  */
-rl_status relocaliser_set_schedule(rl_room* room, int32_t ipt, int32_t fast_waves, int32_t lds_levels);
-rl_status rl_batch_set_schedule(rl_batch* b, int32_t ipt, int32_t fast_waves, int32_t lds_levels);
+rl_status relocaliser_set_schedule(rl_room* room, int32_t ipt, int32_t fast_waves, int32_t lds_levels,
+                                   int32_t score_window);
+rl_status rl_batch_set_schedule(rl_batch* b, int32_t ipt, int32_t fast_waves, int32_t lds_levels,
+                                int32_t score_window);
 
 /*
  * Degeneracy screen of the hypothesis search (result-invariant, on by

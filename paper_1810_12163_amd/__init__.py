@@ -157,6 +157,7 @@ EXPORTS = [
 SCHEDULE_IPT = (2, 4, 8)
 SCHEDULE_FAST_WAVES = (1, 2, 4)
 SCHEDULE_LDS_LEVELS = (8, 6)
+SCHEDULE_SCORE_WINDOWS = (0, 2)
 
 TIMER_NONE, TIMER_TRAVERSE, TIMER_HYP_SEARCH, TIMER_RANSAC = 0, 1, 2, 3
 
@@ -197,11 +198,11 @@ def lib():
         L.rl_plane_scores.argtypes = [P, ctypes.POINTER(Frame), P, I32, P, I32, P]
         L.rl_batch_set_timer.argtypes = [P, I32, P, P]
         L.relocaliser_set_mode_schedule.argtypes = [P, I32]
-        L.relocaliser_set_schedule.argtypes = [P, I32, I32, I32]
+        L.relocaliser_set_schedule.argtypes = [P, I32, I32, I32, I32]
         L.rl_forest_generate.argtypes = [ctypes.POINTER(ForestParams), P, ctypes.POINTER(ctypes.c_size_t)]
         L.relocaliser_save.argtypes = [P, ctypes.c_char_p]
         L.relocaliser_load.argtypes = [P, ctypes.c_char_p]
-        L.rl_batch_set_schedule.argtypes = [P, I32, I32, I32]
+        L.rl_batch_set_schedule.argtypes = [P, I32, I32, I32, I32]
         L.relocaliser_set_degeneracy_screen.argtypes = [P, I32]
         L.rl_batch_set_degeneracy_screen.argtypes = [P, I32]
         L.rl_depth_scores.argtypes = [P, ctypes.POINTER(Frame), P, I32, P, I32, ctypes.c_float, ctypes.c_float,
@@ -333,7 +334,7 @@ class Room:
                                     self.persistent.data_ptr(), self.scratch.data_ptr(),
                                     self.stream.cuda_stream, ctypes.byref(h)))
         self.handle = h.value
-        self.schedule = (4, 1, 8)
+        self.schedule = (4, 1, 8, 0)
         self.max_width, self.max_height = max_width, max_height
 
     def close(self):
@@ -384,12 +385,13 @@ class Room:
         """Reads a saved room of the same forest shape (relocaliser_load)."""
         _check(lib().relocaliser_load(self.handle, str(path).encode()))
 
-    def set_schedule(self, ipt: int, fast_waves: int, lds_levels: int = 8):
+    def set_schedule(self, ipt: int, fast_waves: int, lds_levels: int = 8, score_window: int = 0):
         """Result-invariant launch schedule: search iterations per thread
-        (2, 4, 8), all-rounds scoring width in waves (1, 2, 4) and the tree
-        levels the traversal reads from LDS (6, 8)."""
-        _check(lib().relocaliser_set_schedule(self.handle, int(ipt), int(fast_waves), int(lds_levels)))
-        self.schedule = (int(ipt), int(fast_waves), int(lds_levels))
+        (2, 4, 8), all-rounds scoring width in waves (1, 2, 4), the tree
+        levels the traversal reads from LDS (6, 8) and the rounds of the
+        first all-rounds scoring pass (0 = all in one pass, 1..3)."""
+        _check(lib().relocaliser_set_schedule(self.handle, int(ipt), int(fast_waves), int(lds_levels), int(score_window)))
+        self.schedule = (int(ipt), int(fast_waves), int(lds_levels), int(score_window))
 
     def set_degeneracy_screen(self, on: bool):
         """Result-invariant: with the screen off every triplet passing checks
@@ -487,7 +489,7 @@ class Batch:
         _check(L.rl_batch_create(ctypes.byref(self._bp), self.workspace.data_ptr(),
                                  self.stream.cuda_stream, ctypes.byref(h)))
         self.handle = h.value
-        self.schedule = (4, 1, 8)
+        self.schedule = (4, 1, 8, 2)
         self.max_frames = max_frames
 
     def close(self):
@@ -507,12 +509,14 @@ class Batch:
         _check(lib().rl_batch_set_timer(self.handle, kernel, start.cuda_event if start else None,
                                         stop.cuda_event if stop else None))
 
-    def set_schedule(self, ipt: int, fast_waves: int, lds_levels: int = 8):
+    def set_schedule(self, ipt: int, fast_waves: int, lds_levels: int = 8, score_window: int = 2):
         """Result-invariant launch schedule: search iterations per thread
-        (2, 4, 8), all-rounds scoring width in waves (1, 2, 4) and the tree
-        levels the traversal reads from LDS (6, 8)."""
-        _check(lib().rl_batch_set_schedule(self.handle, int(ipt), int(fast_waves), int(lds_levels)))
-        self.schedule = (int(ipt), int(fast_waves), int(lds_levels))
+        (2, 4, 8), all-rounds scoring width in waves (1, 2, 4), the tree
+        levels the traversal reads from LDS (6, 8) and the rounds of the
+        first all-rounds scoring pass (0 = all in one pass, 1..3; a batch's
+        default is 2)."""
+        _check(lib().rl_batch_set_schedule(self.handle, int(ipt), int(fast_waves), int(lds_levels), int(score_window)))
+        self.schedule = (int(ipt), int(fast_waves), int(lds_levels), int(score_window))
 
     def set_degeneracy_screen(self, on: bool):
         """Result-invariant degeneracy screen of the search (rl_batch_set_degeneracy_screen)."""

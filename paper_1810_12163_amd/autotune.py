@@ -2,10 +2,10 @@
 caller's own requests.
 
 The schedule (search iterations per thread, width of the all-rounds scoring,
-tree levels the traversal reads from LDS) changes no result: every hypothesis
-draws its samples from its own Philox counters whichever thread runs it,
-every energy is summed in the same order, and a node is the same bits from
-LDS or from global memory.  So the choice is a pure timing decision, made on
+tree levels the traversal reads from LDS, rounds of the first all-rounds
+scoring pass) changes no result: every hypothesis draws its samples from its
+own Philox counters whichever thread runs it, every energy is summed in the
+same order, and a node is the same bits from LDS or from global memory.  So the choice is a pure timing decision, made on
 the device and workload that will use it.
 """
 
@@ -16,16 +16,18 @@ import time
 
 import numpy as np
 
-from . import SCHEDULE_FAST_WAVES, SCHEDULE_IPT, SCHEDULE_LDS_LEVELS, Result
+from . import SCHEDULE_FAST_WAVES, SCHEDULE_IPT, SCHEDULE_LDS_LEVELS, SCHEDULE_SCORE_WINDOWS, Result
 
-DEFAULT = (4, 1, 8)
+DEFAULT = (4, 1, 8, 0)          # a room's default schedule
+BATCH_DEFAULT = (4, 1, 8, 2)    # a batch's
 
 
-def candidates(ipts=SCHEDULE_IPT, fast_waves=SCHEDULE_FAST_WAVES, lds_levels=SCHEDULE_LDS_LEVELS) -> list:
-    """Every (iterations per thread, fast waves, LDS levels) schedule, the default first."""
-    out = [DEFAULT] if DEFAULT[0] in ipts and DEFAULT[1] in fast_waves and DEFAULT[2] in lds_levels else []
-    out += [(i, f, l) for i in ipts for f in fast_waves for l in lds_levels if (i, f, l) != DEFAULT]
-    return out
+def candidates(ipts=SCHEDULE_IPT, fast_waves=SCHEDULE_FAST_WAVES, lds_levels=SCHEDULE_LDS_LEVELS,
+               windows=SCHEDULE_SCORE_WINDOWS, first=DEFAULT) -> list:
+    """Every (iterations per thread, fast waves, LDS levels, score window)
+    schedule, `first` (the default) first."""
+    every = [(i, f, l, w) for i in ipts for f in fast_waves for l in lds_levels for w in windows]
+    return ([first] if first in every else []) + [sc for sc in every if sc != first]
 
 
 def pick(timings: dict, default=DEFAULT, margin: float = 0.02):
@@ -48,7 +50,7 @@ def tune_batch(batch, reqs, schedules=None, reps: int = 5, warmup: int = 2, use_
     one queued batch (graph replays after the warm-up capture)."""
     import torch
 
-    schedules = schedules or candidates()
+    schedules = schedules or candidates(first=BATCH_DEFAULT)
     out = torch.empty(len(reqs) * ctypes.sizeof(Result), dtype=torch.uint8, device=batch.device)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -65,7 +67,7 @@ def tune_batch(batch, reqs, schedules=None, reps: int = 5, warmup: int = 2, use_
             ev1.synchronize()
             ms.append(ev0.elapsed_time(ev1))
         timings[sc] = ms
-    best = pick(timings)
+    best = pick(timings, default=BATCH_DEFAULT)
     batch.set_schedule(*best)
     return best, timings
 

@@ -684,7 +684,7 @@ __device__ __forceinline__ double score_pixels(const Job& J, int round, int k0, 
         if (i >= tp) break;
         const int k = k0 + i;
         const int p = (int)c0[i].x;
-        if (write_I && threadIdx.x == 0) J.I[round * J.eta + k] = p;
+        if (write_I) J.I[round * J.eta + k] = p;
         double x[3];
         backproject(__uint_as_float(c0[i].y), p % J.w, p / J.w, J.fx, J.fy, J.cx, J.cy, x);
         const double y0 = R[0] * x[0] + R[1] * x[1] + R[2] * x[2] + t[0];
@@ -739,7 +739,7 @@ __global__ __launch_bounds__(64) void k_score(const Job* __restrict__ jobs, int 
     const bool active = pos < n;
     double R[9], t[3];
     hyp_pose(J.hyps[active ? J.surv[pos] : J.surv[0]], R, t);
-    const double acc = score_pixels(J, round, k0, tp, htile == 0, R, t);
+    const double acc = score_pixels(J, round, k0, tp, htile == 0 && threadIdx.x == 0, R, t);
     if (active) J.partial[(size_t)ptile * J.N + pos] = acc;
 }
 
@@ -762,22 +762,34 @@ __device__ __forceinline__ int rounds_of(int n, int n_cull, int n_out, int r = 0
 // adds does not depend on the survivors, so each (round, pixel tile, 64
 // hypotheses) wave scores every current survivor, whether or not it lives to
 // that round; the selection below uses only the survivors' values.
-// grid.x = rounds * ptiles * fw (absolute round index), fw = fast_max / 64.
+// The rounds can also be taken a window at a time (the first wr rounds, a
+// selection, then the rest): the later rounds then score only the survivors
+// of the window, with the same per-round sums.  A wave serves 64 lanes: with
+// at most 32 survivors it takes G = 64 / H pixel tiles, H lanes (the power of
+// two at or above the survivor count) per tile, so the waves a round needs
+// shrink with its survivors; every (survivor, tile) sum is the same.
+// grid.x = wr * ptiles * fw: rounds r0 .. r0 + wr - 1 of each job, r0 = the
+// rounds it has run; fw = fast_max / 64.
 __global__ __launch_bounds__(64) void k_score_all(const Job* __restrict__ jobs, int nptiles, int fw)
 {
     const Job& J = jobs[blockIdx.y];
     if (J.st->done || J.lm) return;
     const int n = J.st->n_surv, r0 = J.st->rounds_run;
     const int htile = blockIdx.x % fw, rt = blockIdx.x / fw;
-    const int round = rt / nptiles, ptile = rt % nptiles;
-    if (htile * 64 >= n || round < r0 || round >= rounds_of(n, J.n_cull, J.n_out, r0)) return;
+    const int round = r0 + rt / nptiles, pt = rt % nptiles;
+    if (htile * 64 >= n || round >= rounds_of(n, J.n_cull, J.n_out, r0)) return;
+    int H = 64;
+    while (H > 1 && (H >> 1) >= n) H >>= 1;
+    const int G = 64 / H, lane = (int)threadIdx.x;
+    if (pt * G * J.TP >= J.eta) return;
+    const int ptile = pt * G + lane / H;
     const int k0 = ptile * J.TP;
     if (k0 >= J.eta) return;
     const int tp = min(J.TP, J.eta - k0);
-    const int pos = htile * 64 + (int)threadIdx.x;
+    const int pos = htile * 64 + (lane & (H - 1));
     double R[9], t[3];
     hyp_pose(J.hyps[ldg(J.surv + (pos < n ? pos : 0))], R, t);
-    const double acc = score_pixels(J, round, k0, tp, htile == 0, R, t);
+    const double acc = score_pixels(J, round, k0, tp, htile == 0 && (lane & (H - 1)) == 0, R, t);
     if (pos < n) J.partial_all[((size_t)round * nptiles + ptile) * kFastStride + pos] = acc;
 }
 
@@ -790,7 +802,9 @@ __global__ __launch_bounds__(64) void k_score_all(const Job* __restrict__ jobs, 
 // the same value).
 constexpr int kSelSums = 4096;
 
-__global__ __launch_bounds__(kFastStride) void k_select_all(const Job* __restrict__ jobs, int nptiles)
+// At most wr rounds are run; the job is done once its survivors are down to
+// n_out.
+__global__ __launch_bounds__(kFastStride) void k_select_all(const Job* __restrict__ jobs, int nptiles, int wr)
 {
     const Job& J = jobs[blockIdx.x];
     if (J.st->done || J.lm) return;
@@ -800,7 +814,8 @@ __global__ __launch_bounds__(kFastStride) void k_select_all(const Job* __restric
     const int n0 = J.st->n_surv, r0 = J.st->rounds_run;
     const int lane = (int)threadIdx.x;
     const int ptiles = min(nptiles, (J.eta + J.TP - 1) / J.TP);
-    const int nsum = min((rounds_of(n0, J.n_cull, J.n_out, r0) - r0) * n0, kSelSums);
+    const int r_end = min(rounds_of(n0, J.n_cull, J.n_out, r0), r0 + wr);
+    const int nsum = min((r_end - r0) * n0, kSelSums);
     for (int i = lane; i < nsum; i += kFastStride) {
         const int rr = i / n0, pos = i - rr * n0;
         sSum[i] = sum_in_order<32>(J.partial_all + (size_t)(r0 + rr) * nptiles * kFastStride + pos, kFastStride,
@@ -813,7 +828,7 @@ __global__ __launch_bounds__(kFastStride) void k_select_all(const Job* __restric
     bool alive = valid;
     int n = n0, round = r0, rank = 0;
     bool first = round == 0;
-    while (first || n > J.n_out) {
+    while ((first || n > J.n_out) && round < r_end) {
         if (alive) {
             const int i = (round - r0) * n0 + lane;
             E = E + (i < nsum ? sSum[i]
@@ -850,7 +865,7 @@ __global__ __launch_bounds__(kFastStride) void k_select_all(const Job* __restric
     if (lane == 0) {
         J.st->n_surv = n;
         J.st->rounds_run = round;
-        J.st->done = 1;
+        J.st->done = (first || n > J.n_out) ? 0 : 1;
     }
 }
 
@@ -1750,13 +1765,22 @@ hipError_t launch_lm(const Job* jobs, int njobs, int round, int maxSurv, int max
     return hipSuccess;
 }
 
-hipError_t launch_score_all(const Job* jobs, int njobs, int rounds, int nptiles, int fw, hipStream_t st)
+// window = 0: every remaining round in one pass; else the first `window`
+// rounds, then the rest
+hipError_t launch_score_all(const Job* jobs, int njobs, int rounds, int nptiles, int fw, int window, hipStream_t st)
 {
-    if (fw < 1 || fw > kMaxFastWaves) return hipErrorInvalidValue;
-    k_score_all<<<dim3(rounds * nptiles * fw, njobs), dim3(64), 0, st>>>(jobs, nptiles, fw);
+    if (fw < 1 || fw > kMaxFastWaves || window < 0) return hipErrorInvalidValue;
+    const int w0 = (window > 0 && window < rounds) ? window : rounds;
+    k_score_all<<<dim3(w0 * nptiles * fw, njobs), dim3(64), 0, st>>>(jobs, nptiles, fw);
     RL_CHECK_LAUNCH();
-    k_select_all<<<dim3(njobs), dim3(kFastStride), 0, st>>>(jobs, nptiles);
+    k_select_all<<<dim3(njobs), dim3(kFastStride), 0, st>>>(jobs, nptiles, w0);
     RL_CHECK_LAUNCH();
+    if (w0 < rounds) {
+        k_score_all<<<dim3((rounds - w0) * nptiles * fw, njobs), dim3(64), 0, st>>>(jobs, nptiles, fw);
+        RL_CHECK_LAUNCH();
+        k_select_all<<<dim3(njobs), dim3(kFastStride), 0, st>>>(jobs, nptiles, rounds);
+        RL_CHECK_LAUNCH();
+    }
     return hipSuccess;
 }
 

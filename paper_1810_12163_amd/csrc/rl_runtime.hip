@@ -29,7 +29,7 @@ hipError_t launch_hyp_search(const Job* jobs, int njobs, int maxN, int maxIters,
 hipError_t launch_hyp_finalize(const Job* jobs, int njobs, int maxN, hipStream_t st);
 hipError_t launch_score(const Job* jobs, int njobs, int round, int nptiles, int maxSurv,
                         hipStream_t st);
-hipError_t launch_score_all(const Job* jobs, int njobs, int rounds, int nptiles, int fw, hipStream_t st);
+hipError_t launch_score_all(const Job* jobs, int njobs, int rounds, int nptiles, int fw, int window, hipStream_t st);
 hipError_t launch_lm(const Job* jobs, int njobs, int round, int maxSurv, int maxEta, int maxIters, hipStream_t st);
 hipError_t launch_select(const Job* jobs, int njobs, int round, int nptiles, int maxN, hipStream_t st);
 hipError_t launch_finalize(const Job* jobs, int njobs, int maxIlen, hipStream_t st);
@@ -341,6 +341,7 @@ struct Schedule {
     int ipt = 4;
     int fw = 1;
     int top = kTopLevelsMax;   // tree levels the traversal reads from LDS
+    int win = 0;   // rounds of the first all-rounds scoring pass (0: every remaining round in one pass)
     int screen = 1;   // the search rejects clearly degenerate triplets (else only the exact test does)
 };
 
@@ -1094,8 +1095,9 @@ RL_API rl_status relocaliser_set_mode_schedule(rl_room* r, int32_t leaves_per_fr
     return RL_OK;
 }
 
-static rl_status check_schedule(int ipt, int fast_waves, int lds_levels)
+static rl_status check_schedule(int ipt, int fast_waves, int lds_levels, int score_window)
 {
+    if (score_window < 0 || score_window > 3) return fail(RL_EINVAL, "score_window must be in 0..3");
     if (ipt != 2 && ipt != 4 && ipt != 8) return fail(RL_EINVAL, "iterations per thread must be 2, 4 or 8");
     if (fast_waves != 1 && fast_waves != 2 && fast_waves != 4) return fail(RL_EINVAL, "fast_waves must be 1, 2 or 4");
     if (lds_levels != kTopLevelsMin && lds_levels != kTopLevelsMax)
@@ -1103,25 +1105,29 @@ static rl_status check_schedule(int ipt, int fast_waves, int lds_levels)
     return RL_OK;
 }
 
-RL_API rl_status relocaliser_set_schedule(rl_room* r, int32_t ipt, int32_t fast_waves, int32_t lds_levels)
+RL_API rl_status relocaliser_set_schedule(rl_room* r, int32_t ipt, int32_t fast_waves, int32_t lds_levels,
+                                         int32_t score_window)
 {
     if (!r) return fail(RL_EINVAL, "room is NULL");
-    rl_status s = check_schedule(ipt, fast_waves, lds_levels);
+    rl_status s = check_schedule(ipt, fast_waves, lds_levels, score_window);
     if (s != RL_OK) return s;
     r->sched.ipt = ipt;
     r->sched.fw = fast_waves;
     r->sched.top = lds_levels;
+    r->sched.win = score_window;
     return RL_OK;
 }
 
-RL_API rl_status rl_batch_set_schedule(rl_batch* b, int32_t ipt, int32_t fast_waves, int32_t lds_levels)
+RL_API rl_status rl_batch_set_schedule(rl_batch* b, int32_t ipt, int32_t fast_waves, int32_t lds_levels,
+                                       int32_t score_window)
 {
     if (!b) return fail(RL_EINVAL, "batch is NULL");
-    rl_status s = check_schedule(ipt, fast_waves, lds_levels);
+    rl_status s = check_schedule(ipt, fast_waves, lds_levels, score_window);
     if (s != RL_OK) return s;
     b->sched.ipt = ipt;
     b->sched.fw = fast_waves;
     b->sched.top = lds_levels;
+    b->sched.win = score_window;
     return RL_OK;
 }
 
@@ -1164,7 +1170,7 @@ static hipError_t launch_sequence(const Job* jobs, int njobs, int maxP, int maxN
         if (any_lm && r > 0) RL_TRY(launch_lm(jobs, njobs, r, entering[r], maxEta, lm_iters, st));
         RL_TRY(launch_select(jobs, njobs, r, nptiles, maxN, st));
     }
-    RL_TRY(launch_score_all(jobs, njobs, (int)entering.size(), nptiles, sc.fw, st));
+    RL_TRY(launch_score_all(jobs, njobs, (int)entering.size(), nptiles, sc.fw, sc.win, st));
     RL_MARK(RL_TIMER_RANSAC, stop);
     RL_TRY(launch_finalize(jobs, njobs, (int)entering.size() * maxEta, st));
 #undef RL_MARK
@@ -1244,7 +1250,7 @@ RL_API rl_status relocaliser_relocalise_opts(rl_room* r, const rl_frame* f, uint
     if (e != hipSuccess) return hip_fail(e, "job upload");
     const int nptiles = (eta + r->TP - 1) / r->TP;
     const int P = f->width * f->height;
-    std::vector<long long> key = {P, N, r->sched.ipt, r->sched.fw, r->sched.top, lm, r->p.lm_iterations, iters, eta};
+    std::vector<long long> key = {P, N, r->sched.ipt, r->sched.fw, r->sched.top, r->sched.win, lm, r->p.lm_iterations, iters, eta};
     for (int v : entering) key.push_back(v);
     e = run_sequence(r->graphs, key, r->timer.kernel == RL_TIMER_NONE, r->stream, [&]() {
         return launch_sequence(jd, 1, P, N, iters, r->T, entering, nptiles, eta, lm != 0, r->p.lm_iterations,
@@ -1532,6 +1538,9 @@ RL_API rl_status rl_batch_create(const rl_batch_params* bp, void* ws, void* hip_
     b->stream = reinterpret_cast<hipStream_t>(hip_stream);
     b->TP = score_tile(bp->max_modes_per_pixel);
     b->rows = bp->max_modes_per_pixel;
+    // many frames per launch: scoring the first two all-rounds rounds apart
+    // from the rest saves more waves than its extra launches cost
+    b->sched.win = 2;
     Carver c;
     b->jobs_off = c.take((size_t)bp->max_frames * sizeof(Job));
     b->results_off = c.take((size_t)bp->max_frames * sizeof(rl_result));
@@ -1642,7 +1651,7 @@ static rl_status batch_relocalise_queue(rl_batch* b, const rl_request* reqs, con
     if (use_graph && b->stream == nullptr)
         return fail(RL_EINVAL, "graph replay needs a batch created on a non-default stream");
     std::vector<long long> key = {nq, maxN, maxIters, nptiles, maxEta, b->bp.n_trees, b->sched.ipt, b->sched.fw, b->sched.top,
-                                  any_lm ? 1 : 0, lm_iters};
+                                  b->sched.win, any_lm ? 1 : 0, lm_iters};
     for (int v : entering) key.push_back(v);
     e = run_sequence(b->graphs, key, use_graph && b->timer.kernel == RL_TIMER_NONE, b->stream, [&]() {
         return launch_sequence(jd, nq, maxP, maxN, maxIters, b->bp.n_trees, entering, nptiles, maxEta, any_lm,

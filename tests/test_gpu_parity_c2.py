@@ -376,10 +376,12 @@ def test_mixed_batch_equals_plain(c2, c3_room):
 def test_every_schedule_gives_identical_results(c2, c3_room):
     """Every launch schedule (search iterations per thread 2/4/8, all-rounds
     scoring width 1/2/4 waves, 6 or 8 tree levels of the traversal read from
-    LDS) gives bit-identical results, batched (graph
-    replay and direct launches) and plain; a request of 256 hypotheses enters
-    the all-rounds scoring at its first round under the 4-wave width.  The
-    tuner then leaves one of them set."""
+    LDS, the all-rounds scoring in one pass or in a first window of 1-3 rounds
+    and the rest) gives bit-identical results, batched (graph replay and
+    direct launches) and plain; a request of 256 hypotheses enters the
+    all-rounds scoring at its first round under the 4-wave width (its window
+    then includes the initial cull), the 1024-hypothesis requests after
+    per-round scoring.  The tuner then leaves one of them set."""
     from paper_1810_12163_amd import autotune
     w, o, room = c2
     p3, r3 = c3_room
@@ -400,12 +402,12 @@ def test_every_schedule_gives_identical_results(c2, c3_room):
 
     batch = rl.Batch(4, 640, 480, 1024, 500, 12, 5, 50)
     for sc in autotune.candidates():
-        print(f"[schedule] batch ipt={sc[0]} fast_waves={sc[1]} lds_levels={sc[2]}", flush=True)
+        print(f"[schedule] batch ipt={sc[0]} fast_waves={sc[1]} lds_levels={sc[2]} window={sc[3]}", flush=True)
         batch.set_schedule(*sc)
         same(batch.relocalise(reqs, use_graph=True), want, sc)
         same(batch.relocalise(reqs, use_graph=sc[:2] == (8, 4)), want, sc)
-    for sc in ((2, 4, 6), (8, 2, 8), (4, 4, 6)):
-        print(f"[schedule] plain ipt={sc[0]} fast_waves={sc[1]} lds_levels={sc[2]}", flush=True)
+    for sc in ((2, 4, 6, 2), (8, 2, 8, 0), (4, 4, 6, 1), (4, 1, 8, 3)):
+        print(f"[schedule] plain ipt={sc[0]} fast_waves={sc[1]} lds_levels={sc[2]} window={sc[3]}", flush=True)
         for rm in (room, r3):
             rm.set_schedule(*sc)
         same([rm.relocalise(d, c, K, request_seed=s, n_hypotheses=N) for (rm, d, c, K, s, N) in reqs], want, sc)
@@ -420,6 +422,8 @@ def test_every_schedule_gives_identical_results(c2, c3_room):
         room.set_schedule(4, 8)
     with pytest.raises(rl.RlError):
         room.set_schedule(4, 1, 7)
+    with pytest.raises(rl.RlError):
+        batch.set_schedule(4, 1, 8, 4)
     batch.close()
 
 
