@@ -28,11 +28,14 @@
 
 namespace rl {
 
+// Each kernel body takes its frame's arguments and block index, so that one
+// launch serves one frame (arguments by value) or one frame of each of
+// several rooms (a job table in device memory, blockIdx.y or .z = job).
 template <int T>
-__global__ __launch_bounds__(256) void k_ad_items(AdaptArgs a)
+__device__ __forceinline__ void ad_items(const AdaptArgs& a, int bx)
 {
 #pragma clang fp contract(off)
-    if (a.result && blockIdx.x == 0) {
+    if (a.result && bx == 0) {
         // the record of a batched adaptation: done, no pose
         if (threadIdx.x < 16) a.result->cam_to_world[threadIdx.x] = (threadIdx.x % 5 == 0) ? 1.0f : 0.0f;
         if (threadIdx.x == 0) {
@@ -51,7 +54,7 @@ __global__ __launch_bounds__(256) void k_ad_items(AdaptArgs a)
             r->pad = 0;
         }
     }
-    const int g = blockIdx.x * 256 + threadIdx.x;
+    const int g = bx * 256 + threadIdx.x;
     if (g >= a.G) return;
     const int x = 4 * (g % a.gw + 1), y = 4 * (g / a.gw + 1);
     const float d = a.src.d(x, y);
@@ -80,16 +83,25 @@ __global__ __launch_bounds__(256) void k_ad_items(AdaptArgs a)
     for (int t = 0; t < T; ++t) a.item_leaf[(size_t)t * a.G + g] = (uint16_t)leaf[t];
 }
 
+template <int T>
+__global__ __launch_bounds__(256) void k_ad_items(AdaptArgs a) { ad_items<T>(a, blockIdx.x); }
+
+template <int T>
+__global__ __launch_bounds__(256) void k_ad_items_jobs(const AdaptArgs* __restrict__ jobs)
+{
+    ad_items<T>(jobs[blockIdx.y], blockIdx.x);
+}
+
 // One block per (chunk, tree): the chunk's (leaf << 10 | position) keys are
 // sorted in LDS (bitonic; the position makes every key distinct, so equal
 // leaves stay in raster order), runs of equal leaves are delimited, and every
 // run heads a list entry of its leaf.  Positions of the sorted order index
 // the run arrays: run_cnt is the run's length at its head, 0 elsewhere.
-__global__ __launch_bounds__(kAdaptChunk) void k_ad_sort(AdaptArgs a)
+__device__ __forceinline__ void ad_sort(const AdaptArgs& a, int c, int t)
 {
     __shared__ uint32_t s_v[kAdaptChunk];
     __shared__ int s_start[kAdaptChunk];
-    const int c = blockIdx.x, t = blockIdx.y, i = threadIdx.x;
+    const int i = threadIdx.x;
     const int g = c * kAdaptChunk + i;
     const uint32_t leaf0 = g < a.G ? (uint32_t)a.item_leaf[(size_t)t * a.G + g] : (uint32_t)kLeafNone;
     s_v[i] = (leaf0 << 10) | (uint32_t)i;
@@ -136,11 +148,22 @@ __global__ __launch_bounds__(kAdaptChunk) void k_ad_sort(AdaptArgs a)
     }
 }
 
+__global__ __launch_bounds__(kAdaptChunk) void k_ad_sort(AdaptArgs a) { ad_sort(a, blockIdx.x, blockIdx.y); }
+
+// grid (chunks, trees, jobs) of the largest frame; blocks past a job's own
+// chunks or trees leave at once (before any barrier)
+__global__ __launch_bounds__(kAdaptChunk) void k_ad_sort_jobs(const AdaptArgs* __restrict__ jobs)
+{
+    const AdaptArgs& a = jobs[blockIdx.z];
+    if ((int)blockIdx.x * kAdaptChunk >= a.Gp || (int)blockIdx.y >= a.T) return;
+    ad_sort(a, blockIdx.x, blockIdx.y);
+}
+
 // One thread per sorted position; each run adds up the runs of its leaf in
 // earlier chunks.  A leaf's list holds at most one run per chunk.
-__global__ __launch_bounds__(256) void k_ad_runs(AdaptArgs a, int n_chunks)
+__device__ __forceinline__ void ad_runs(const AdaptArgs& a, int n_chunks, int bx)
 {
-    const uint32_t r = blockIdx.x * 256 + threadIdx.x;
+    const uint32_t r = bx * 256 + threadIdx.x;
     if (r >= (uint32_t)a.T * (uint32_t)a.Gp) return;
     const uint32_t cnt = a.run_cnt[r];
     if (cnt == 0u) return;
@@ -158,14 +181,22 @@ __global__ __launch_bounds__(256) void k_ad_runs(AdaptArgs a, int n_chunks)
     a.run_tot[r] = pre + cnt == total ? total : 0u;
 }
 
+__global__ __launch_bounds__(256) void k_ad_runs(AdaptArgs a, int n_chunks) { ad_runs(a, n_chunks, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void k_ad_runs_jobs(const AdaptArgs* __restrict__ jobs)
+{
+    const AdaptArgs& a = jobs[blockIdx.y];
+    ad_runs(a, a.Gp / kAdaptChunk, blockIdx.x);
+}
+
 __device__ __forceinline__ uint32_t slot_hash(uint32_t key, uint32_t mask)
 {
     return (key * 0x9E3779B1u) & mask;
 }
 
-__global__ __launch_bounds__(256) void k_ad_claim(AdaptArgs a)
+__device__ __forceinline__ void ad_claim(const AdaptArgs& a, int bx)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int i = bx * 256 + threadIdx.x;
     if (i >= a.T * a.G) return;
     const int t = i / a.G;
     const uint16_t lf = a.item_leaf[i];
@@ -199,9 +230,16 @@ __global__ __launch_bounds__(256) void k_ad_claim(AdaptArgs a)
     a.item_slot[i] = -1;                // unreachable: the table is never full
 }
 
-__global__ __launch_bounds__(256) void k_ad_write(AdaptArgs a)
+__global__ __launch_bounds__(256) void k_ad_claim(AdaptArgs a) { ad_claim(a, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void k_ad_claim_jobs(const AdaptArgs* __restrict__ jobs)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
+    ad_claim(jobs[blockIdx.y], blockIdx.x);
+}
+
+__device__ __forceinline__ void ad_write(const AdaptArgs& a, int bx)
+{
+    const int i = bx * 256 + threadIdx.x;
     if (i >= a.T * a.G) return;
     const uint16_t lf = a.item_leaf[i];
     if (lf == kLeafNone) return;
@@ -217,12 +255,19 @@ __global__ __launch_bounds__(256) void k_ad_write(AdaptArgs a)
     }
 }
 
+__global__ __launch_bounds__(256) void k_ad_write(AdaptArgs a) { ad_write(a, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void k_ad_write_jobs(const AdaptArgs* __restrict__ jobs)
+{
+    ad_write(jobs[blockIdx.y], blockIdx.x);
+}
+
 // One thread per sorted position (covering the items too): the leaf's
 // arrival counter from its last run, leaf lists and used table entries back
 // to their empty state.
-__global__ __launch_bounds__(256) void k_ad_cleanup(AdaptArgs a)
+__device__ __forceinline__ void ad_cleanup(const AdaptArgs& a, int bx)
 {
-    const uint32_t x = blockIdx.x * 256 + threadIdx.x;
+    const uint32_t x = bx * 256 + threadIdx.x;
     if (x < (uint32_t)a.T * (uint32_t)a.G && a.item_leaf[x] != kLeafNone && a.item_slot[x] >= 0) {
         const uint32_t h = a.item_h[x];
         a.hkey[h] = kNone32;
@@ -234,6 +279,13 @@ __global__ __launch_bounds__(256) void k_ad_cleanup(AdaptArgs a)
         const uint32_t tot = a.run_tot[x];
         if (tot) a.seen[tl] += tot;
     }
+}
+
+__global__ __launch_bounds__(256) void k_ad_cleanup(AdaptArgs a) { ad_cleanup(a, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void k_ad_cleanup_jobs(const AdaptArgs* __restrict__ jobs)
+{
+    ad_cleanup(jobs[blockIdx.y], blockIdx.x);
 }
 
 // ------------------------------------------------------------------------
@@ -273,7 +325,7 @@ __device__ __forceinline__ double rqs_block_sum(double v, double* s_red)
 // stride over all of them; the moments use the first 256 in a fixed order,
 // so every block size gives the same rows.
 template <int BS>
-__global__ __launch_bounds__(BS) void k_rqs(RqsArgs a)
+__device__ __forceinline__ void rqs(const RqsArgs& a, uint32_t bx, uint32_t gx)
 {
     extern __shared__ unsigned char s_raw[];
     float4* pts = reinterpret_cast<float4*>(s_raw);
@@ -288,7 +340,7 @@ __global__ __launch_bounds__(BS) void k_rqs(RqsArgs a)
     const uint32_t ndirty = a.rr_count ? a.rr_count : a.counters[0];
     const double two_s2 = 2.0 * a.sigma * a.sigma;
     const double tau2 = a.tau * a.tau;
-    for (uint32_t li = blockIdx.x; li < ndirty; li += gridDim.x) {
+    for (uint32_t li = bx; li < ndirty; li += gx) {
         const uint32_t tl = a.rr_count ? (a.rr_first + li) % a.n_leaves : a.dirty_list[li];
         const int n = (int)min(a.seen[tl], (uint32_t)a.kappa);
         const float4* src = a.reservoir + (size_t)tl * a.kappa;
@@ -397,6 +449,16 @@ __global__ __launch_bounds__(BS) void k_rqs(RqsArgs a)
     }
 }
 
+template <int BS>
+__global__ __launch_bounds__(BS) void k_rqs(RqsArgs a) { rqs<BS>(a, blockIdx.x, gridDim.x); }
+
+// round-robin steps of several rooms at once: blockIdx.y = room
+template <int BS>
+__global__ __launch_bounds__(BS) void k_rqs_jobs(const RqsArgs* __restrict__ jobs)
+{
+    rqs<BS>(jobs[blockIdx.y], blockIdx.x, gridDim.x);
+}
+
 __global__ void k_rqs_done(RqsArgs a)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) a.counters[0] = 0u;
@@ -432,6 +494,63 @@ hipError_t launch_adapt(const AdaptArgs& a, hipStream_t st)
     k_ad_write<<<gT, blk, 0, st>>>(a);
     RL_CHECK_LAUNCH();
     k_ad_cleanup<<<gR, blk, 0, st>>>(a);
+    RL_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+// One frame for each of njobs rooms (device job table, host copy hjobs for
+// the shapes); all jobs have T trees.
+hipError_t launch_adapt_jobs(const AdaptArgs* jobs, const AdaptArgs* hjobs, int njobs, hipStream_t st)
+{
+    if (njobs <= 0) return hipSuccess;
+    int T = hjobs[0].T, G = 0, Gp = 0;
+    for (int j = 0; j < njobs; ++j) {
+        if (hjobs[j].T != T) return hipErrorInvalidValue;
+        G = max(G, hjobs[j].G);
+        Gp = max(Gp, hjobs[j].Gp);
+    }
+    if (G <= 0) return hipSuccess;
+    const dim3 blk(256), g1((G + 255) / 256, njobs), gT((T * G + 255) / 256, njobs);
+    switch (T) {
+        case 1: k_ad_items_jobs<1><<<g1, blk, 0, st>>>(jobs); break;
+        case 2: k_ad_items_jobs<2><<<g1, blk, 0, st>>>(jobs); break;
+        case 3: k_ad_items_jobs<3><<<g1, blk, 0, st>>>(jobs); break;
+        case 4: k_ad_items_jobs<4><<<g1, blk, 0, st>>>(jobs); break;
+        case 5: k_ad_items_jobs<5><<<g1, blk, 0, st>>>(jobs); break;
+        case 6: k_ad_items_jobs<6><<<g1, blk, 0, st>>>(jobs); break;
+        case 7: k_ad_items_jobs<7><<<g1, blk, 0, st>>>(jobs); break;
+        case 8: k_ad_items_jobs<8><<<g1, blk, 0, st>>>(jobs); break;
+        default: return hipErrorInvalidValue;
+    }
+    RL_CHECK_LAUNCH();
+    const dim3 gR((T * Gp + 255) / 256, njobs);
+    k_ad_sort_jobs<<<dim3(Gp / kAdaptChunk, T, njobs), dim3(kAdaptChunk), 0, st>>>(jobs);
+    RL_CHECK_LAUNCH();
+    k_ad_runs_jobs<<<gR, blk, 0, st>>>(jobs);
+    RL_CHECK_LAUNCH();
+    k_ad_claim_jobs<<<gT, blk, 0, st>>>(jobs);
+    RL_CHECK_LAUNCH();
+    k_ad_write_jobs<<<gT, blk, 0, st>>>(jobs);
+    RL_CHECK_LAUNCH();
+    k_ad_cleanup_jobs<<<gR, blk, 0, st>>>(jobs);
+    RL_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+// Round-robin steps (rr_count > 0) of njobs rooms; LDS for the largest
+// reservoir capacity.
+hipError_t launch_rqs_jobs(const RqsArgs* jobs, const RqsArgs* hjobs, int njobs, int blocks, hipStream_t st)
+{
+    if (njobs <= 0) return hipSuccess;
+    int kappa = 0;
+    uint32_t cnt = 0;
+    for (int j = 0; j < njobs; ++j) {
+        if (hjobs[j].rr_count == 0) return hipErrorInvalidValue;
+        kappa = max(kappa, hjobs[j].kappa);
+        cnt = max(cnt, hjobs[j].rr_count);
+    }
+    const int nb = (int)min((uint32_t)blocks, cnt);
+    k_rqs_jobs<1024><<<dim3(nb, njobs), dim3(1024), 36 * (size_t)kappa, st>>>(jobs);
     RL_CHECK_LAUNCH();
     return hipSuccess;
 }

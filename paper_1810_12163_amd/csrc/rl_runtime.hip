@@ -42,6 +42,8 @@ hipError_t launch_plane_scores(const FrameView& src, int w, int h, float fx, flo
                                double* partial, int* cnt, double* scores, hipStream_t st);
 hipError_t launch_adapt(const AdaptArgs& a, hipStream_t st);
 hipError_t launch_rqs(const RqsArgs& a, int blocks, hipStream_t st);
+hipError_t launch_adapt_jobs(const AdaptArgs* jobs, const AdaptArgs* hjobs, int njobs, hipStream_t st);
+hipError_t launch_rqs_jobs(const RqsArgs* jobs, const RqsArgs* hjobs, int njobs, int blocks, hipStream_t st);
 
 __global__ void k_fill_u32(uint32_t* p, size_t n, uint32_t v)
 {
@@ -395,15 +397,20 @@ struct rl_batch {
     char* ws;
     hipStream_t stream;
     hipEvent_t ev;
-    hipEvent_t mark;          // end of the relocalisations, for the rooms' adaptations to wait on
+    hipEvent_t mark;          // end of the batch's adaptations, for the rooms' streams to wait on
     int TP, rows;
-    size_t jobs_off, results_off;
+    size_t jobs_off, results_off, ad_off, rq_off;
     std::vector<FrameLayout> slots;
     Schedule sched;
     Timer timer;
     Job* job_ring[kJobRing];
     hipEvent_t up_ev[kJobRing];
     int ring;
+    // adaptation job tables: pinned host copies ([max_frames] AdaptArgs, then
+    // [max_frames] RqsArgs) and their upload events, a ring like job_ring
+    char* ad_ring[kJobRing];
+    hipEvent_t ad_ev[kJobRing];
+    int ad_slot;
     rl_result* res_host;
     std::map<std::vector<long long>, hipGraphExec_t> graphs;
 };
@@ -1518,6 +1525,8 @@ RL_API rl_status rl_batch_workspace_bytes(const rl_batch_params* bp, size_t* byt
     Carver c;
     c.take((size_t)bp->max_frames * sizeof(Job));
     c.take((size_t)bp->max_frames * sizeof(rl_result));
+    c.take((size_t)bp->max_frames * sizeof(AdaptArgs));
+    c.take((size_t)bp->max_frames * sizeof(RqsArgs));
     const FrameLayout FL = frame_layout(bp->max_width * bp->max_height, bp->max_hypotheses, bp->max_eta,
                                         batch_rounds(*bp), TP, bp->max_modes_per_pixel, 0);
     *bytes = c.cur + (size_t)bp->max_frames * align256(FL.total);
@@ -1544,6 +1553,8 @@ RL_API rl_status rl_batch_create(const rl_batch_params* bp, void* ws, void* hip_
     Carver c;
     b->jobs_off = c.take((size_t)bp->max_frames * sizeof(Job));
     b->results_off = c.take((size_t)bp->max_frames * sizeof(rl_result));
+    b->ad_off = c.take((size_t)bp->max_frames * sizeof(AdaptArgs));
+    b->rq_off = c.take((size_t)bp->max_frames * sizeof(RqsArgs));
     const FrameLayout proto = frame_layout(bp->max_width * bp->max_height, bp->max_hypotheses, bp->max_eta,
                                            batch_rounds(*bp), b->TP, bp->max_modes_per_pixel, 0);
     for (int i = 0; i < bp->max_frames; ++i) {
@@ -1552,9 +1563,12 @@ RL_API rl_status rl_batch_create(const rl_batch_params* bp, void* ws, void* hip_
                                         batch_rounds(*bp), b->TP, bp->max_modes_per_pixel, base));
     }
     b->ring = 0;
+    b->ad_slot = 0;
     for (int k = 0; k < kJobRing; ++k) {
         b->job_ring[k] = nullptr;
         b->up_ev[k] = nullptr;
+        b->ad_ring[k] = nullptr;
+        b->ad_ev[k] = nullptr;
     }
     hipError_t e = hipEventCreateWithFlags(&b->ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->mark, hipEventDisableTiming);
@@ -1563,6 +1577,10 @@ RL_API rl_status rl_batch_create(const rl_batch_params* bp, void* ws, void* hip_
         if (e == hipSuccess)
             e = hipHostMalloc(reinterpret_cast<void**>(&b->job_ring[k]), (size_t)bp->max_frames * sizeof(Job),
                               hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ad_ev[k], hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipHostMalloc(reinterpret_cast<void**>(&b->ad_ring[k]),
+                              (size_t)bp->max_frames * (sizeof(AdaptArgs) + sizeof(RqsArgs)), hipHostMallocDefault);
     }
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->res_host), (size_t)bp->max_frames * sizeof(rl_result), hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -1583,6 +1601,11 @@ RL_API rl_status rl_batch_destroy(rl_batch* b)
             (void)hipEventDestroy(b->up_ev[k]);
         }
         if (b->job_ring[k]) (void)hipHostFree(b->job_ring[k]);
+        if (b->ad_ev[k]) {
+            (void)hipEventSynchronize(b->ad_ev[k]);
+            (void)hipEventDestroy(b->ad_ev[k]);
+        }
+        if (b->ad_ring[k]) (void)hipHostFree(b->ad_ring[k]);
     }
     if (b->res_host) (void)hipHostFree(b->res_host);
     if (b->ev) (void)hipEventDestroy(b->ev);
@@ -1666,40 +1689,103 @@ static rl_status batch_relocalise_queue(rl_batch* b, const rl_request* reqs, con
     return RL_OK;
 }
 
-// The adaptation requests of a batch: each on its room's stream, after the
-// batch's relocalisations (event mark on the batch's stream) and after the
-// work queued so far on the room's stream; a room's adaptations in request
-// order, different rooms concurrently.  The batch's stream then waits for
-// every one of them.
+// The adaptation requests of a batch, on the batch's stream after its
+// relocalisations and after the work queued so far on each room's stream.
+// Round k holds the k-th adaptation of every room (so a room's adaptations
+// keep their request order) and is one launch sequence over those rooms
+// (split by tree count), followed by one launch for the rooms' round-robin
+// mode steps, which first wait for the batches still reading the old modes.
+// Each room's stream, and every later reader of its modes, is then ordered
+// after the batch.
 static rl_status batch_adapt(rl_batch* b, const rl_request* reqs, const std::vector<int>& adapt,
                              rl_result* dev_results)
 {
-    hipError_t e = hipEventRecord(b->mark, b->stream);
-    if (e != hipSuccess) return hip_fail(e, "batched adaptation ordering");
     std::vector<rl_room*> rooms;
+    std::vector<int> seen_count;
+    std::vector<std::vector<int>> rounds;
     for (int i : adapt) {
         rl_room* r = reqs[i].room;
-        if (std::find(rooms.begin(), rooms.end(), r) == rooms.end()) {
+        const auto it = std::find(rooms.begin(), rooms.end(), r);
+        const size_t ri = (size_t)(it - rooms.begin());
+        if (it == rooms.end()) {
             rooms.push_back(r);
-            e = hipStreamWaitEvent(r->stream, b->mark, 0);
-            if (e != hipSuccess) return hip_fail(e, "batched adaptation ordering");
+            seen_count.push_back(0);
         }
-        AdaptArgs a = adapt_args(r, &reqs[i].frame, reqs[i].cam_to_world);
-        a.result = dev_results + i;
-        a.mode_version = r->mode_version + (r->rr_leaves ? 1u : 0u);   // after its own round-robin step
-        e = launch_adapt(a, r->stream);
-        if (e != hipSuccess) return hip_fail(e, "batched adaptation");
-        r->modes_stale = true;
-        if (r->rr_leaves) {
-            const rl_status s = round_robin_step(r, r->stream);
-            if (s != RL_OK) return s;
-        }
+        const size_t k = (size_t)seen_count[ri]++;
+        if (k >= rounds.size()) rounds.emplace_back();
+        rounds[k].push_back(i);
     }
+    hipError_t e = hipSuccess;
     for (rl_room* r : rooms) {
         e = hipEventRecord(r->bev, r->stream);
         if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, r->bev, 0);
+        if (e == hipSuccess && r->rr_leaves) {
+            for (hipEvent_t ev : r->readers) {
+                if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, ev, 0);
+                r->spare.push_back(ev);
+            }
+            r->readers.clear();
+        }
         if (e != hipSuccess) return hip_fail(e, "batched adaptation ordering");
     }
+    // the pinned tables to fill: their previous upload has to have been read
+    const int slot_k = b->ad_slot;
+    e = hipEventSynchronize(b->ad_ev[slot_k]);
+    if (e != hipSuccess) return hip_fail(e, "adaptation table reuse");
+    AdaptArgs* ha = reinterpret_cast<AdaptArgs*>(b->ad_ring[slot_k]);
+    RqsArgs* hr = reinterpret_cast<RqsArgs*>(b->ad_ring[slot_k] + (size_t)b->bp.max_frames * sizeof(AdaptArgs));
+    struct Step { int a0, na, r0, nr; };
+    std::vector<Step> steps;
+    int na = 0, nr = 0;
+    for (const std::vector<int>& rd : rounds) {
+        std::vector<int> trees;
+        for (int i : rd)
+            if (std::find(trees.begin(), trees.end(), reqs[i].room->T) == trees.end()) trees.push_back(reqs[i].room->T);
+        for (int T : trees) {
+            Step st{na, 0, nr, 0};
+            for (int i : rd) {
+                rl_room* r = reqs[i].room;
+                if (r->T != T) continue;
+                AdaptArgs a = adapt_args(r, &reqs[i].frame, reqs[i].cam_to_world);
+                a.result = dev_results + i;
+                a.mode_version = r->mode_version + (r->rr_leaves ? 1u : 0u);   // after its own round-robin step
+                ha[na++] = a;
+                ++st.na;
+                r->modes_stale = true;
+                if (r->rr_leaves) {
+                    RqsArgs q = rqs_args(r);
+                    q.rr_first = r->rr_cursor;
+                    q.rr_count = (uint32_t)r->rr_leaves;
+                    r->rr_cursor = (uint32_t)((r->rr_cursor + (uint64_t)r->rr_leaves) % q.n_leaves);
+                    ++r->mode_version;
+                    hr[nr++] = q;
+                    ++st.nr;
+                }
+            }
+            steps.push_back(st);
+        }
+    }
+    AdaptArgs* da = reinterpret_cast<AdaptArgs*>(b->ws + b->ad_off);
+    RqsArgs* dr = reinterpret_cast<RqsArgs*>(b->ws + b->rq_off);
+    e = hipMemcpyAsync(da, ha, (size_t)na * sizeof(AdaptArgs), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess && nr > 0) e = hipMemcpyAsync(dr, hr, (size_t)nr * sizeof(RqsArgs), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipEventRecord(b->ad_ev[slot_k], b->stream);
+    if (e != hipSuccess) return hip_fail(e, "adaptation table upload");
+    b->ad_slot = (slot_k + 1) % kJobRing;
+    for (const Step& st : steps) {
+        e = launch_adapt_jobs(da + st.a0, ha + st.a0, st.na, b->stream);
+        if (e == hipSuccess && st.nr > 0) e = launch_rqs_jobs(dr + st.r0, hr + st.r0, st.nr, 1024, b->stream);
+        if (e != hipSuccess) return hip_fail(e, "batched adaptation");
+    }
+    e = hipEventRecord(b->mark, b->stream);
+    for (rl_room* r : rooms) {
+        if (e == hipSuccess) e = hipStreamWaitEvent(r->stream, b->mark, 0);
+        if (e == hipSuccess && r->rr_leaves) {
+            e = hipEventRecord(r->wev, b->stream);
+            r->wrote = true;
+        }
+    }
+    if (e != hipSuccess) return hip_fail(e, "batched adaptation ordering");
     return RL_OK;
 }
 
