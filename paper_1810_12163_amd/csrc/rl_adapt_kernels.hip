@@ -304,6 +304,92 @@ __device__ __forceinline__ double dist2(float4 a, float4 b)
     return dx * dx + dy * dy + dz * dz;
 }
 
+// rho_k, j in order
+__device__ __forceinline__ double rqs_density(const float4* pts, int n, float4 pk, double two_s2)
+{
+    double acc = 0.0;
+    for (int j = 0; j < n; ++j) acc += exp(-dist2(pk, pts[j]) / two_s2);
+    return acc;
+}
+
+// parent(k): the nearest point of higher (rho, index) within tau, or -1
+__device__ __forceinline__ int rqs_link(const float4* pts, const double* rho, int n, int k, double tau2)
+{
+    const float4 pk = pts[k];
+    const double rk = rho[k];
+    int best = -1;
+    double bestd = INFINITY;
+    for (int j = 0; j < n; ++j) {
+        const double rj = rho[j];
+        const bool higher = rj > rk || (rj == rk && j > k);
+        if (!higher) continue;
+        const double d2 = dist2(pk, pts[j]);
+        if (d2 < tau2 && d2 < bestd) {
+            bestd = d2;
+            best = j;
+        }
+    }
+    return best;
+}
+
+// A round-robin step of at most kRqsSplitLeaves leaves computes its O(n^2)
+// passes (density, then links) as row chunks of kRqsRows points in
+// workgroups of their own, so that a full reservoir is spread over
+// kappa / kRqsRows workgroups instead of holding one for all its rows; each
+// row runs the same loop as in k_rqs, so the links are the same.
+__host__ __device__ inline bool rqs_split(const RqsArgs& a)
+{
+    return a.rr_count > 0 && a.rr_count <= (uint32_t)kRqsSplitLeaves;
+}
+
+// grid (row chunks, leaves of the step[, rooms]); dynamic LDS float4[kappa]
+__device__ __forceinline__ void rqs_density_rows(const RqsArgs& a, int c, uint32_t li)
+{
+    extern __shared__ unsigned char s_raw[];
+    float4* pts = reinterpret_cast<float4*>(s_raw);
+    if (!rqs_split(a) || li >= a.rr_count) return;
+    const uint32_t tl = (a.rr_first + li) % a.n_leaves;
+    const int n = (int)min(a.seen[tl], (uint32_t)a.kappa);
+    if (c * kRqsRows >= n) return;
+    const float4* src = a.reservoir + (size_t)tl * a.kappa;
+    for (int k = threadIdx.x; k < n; k += kRqsRows) pts[k] = src[k];
+    __syncthreads();
+    const int k = c * kRqsRows + (int)threadIdx.x;
+    if (k < n) a.rr_rho[(size_t)li * a.kappa + k] = rqs_density(pts, n, pts[k], 2.0 * a.sigma * a.sigma);
+}
+
+// dynamic LDS float4[kappa], then double[kappa]
+__device__ __forceinline__ void rqs_link_rows(const RqsArgs& a, int c, uint32_t li)
+{
+    extern __shared__ unsigned char s_raw[];
+    float4* pts = reinterpret_cast<float4*>(s_raw);
+    double* rho = reinterpret_cast<double*>(s_raw + 16 * (size_t)a.kappa);
+    if (!rqs_split(a) || li >= a.rr_count) return;
+    const uint32_t tl = (a.rr_first + li) % a.n_leaves;
+    const int n = (int)min(a.seen[tl], (uint32_t)a.kappa);
+    if (c * kRqsRows >= n) return;
+    const float4* src = a.reservoir + (size_t)tl * a.kappa;
+    const double* lr = a.rr_rho + (size_t)li * a.kappa;
+    for (int k = threadIdx.x; k < n; k += kRqsRows) {
+        pts[k] = src[k];
+        rho[k] = lr[k];
+    }
+    __syncthreads();
+    const int k = c * kRqsRows + (int)threadIdx.x;
+    if (k < n) a.rr_parent[(size_t)li * a.kappa + k] = rqs_link(pts, rho, n, k, a.tau * a.tau);
+}
+
+__global__ __launch_bounds__(kRqsRows) void k_rqs_density(RqsArgs a) { rqs_density_rows(a, blockIdx.x, blockIdx.y); }
+__global__ __launch_bounds__(kRqsRows) void k_rqs_links(RqsArgs a) { rqs_link_rows(a, blockIdx.x, blockIdx.y); }
+__global__ __launch_bounds__(kRqsRows) void k_rqs_density_jobs(const RqsArgs* __restrict__ jobs)
+{
+    rqs_density_rows(jobs[blockIdx.z], blockIdx.x, blockIdx.y);
+}
+__global__ __launch_bounds__(kRqsRows) void k_rqs_links_jobs(const RqsArgs* __restrict__ jobs)
+{
+    rqs_link_rows(jobs[blockIdx.z], blockIdx.x, blockIdx.y);
+}
+
 // Sum over the first 256 threads of the block in a fixed tree order (the
 // other threads only take part in the barriers), so that a moment does not
 // depend on the block size.
@@ -340,6 +426,7 @@ __device__ __forceinline__ void rqs(const RqsArgs& a, uint32_t bx, uint32_t gx)
     const uint32_t ndirty = a.rr_count ? a.rr_count : a.counters[0];
     const double two_s2 = 2.0 * a.sigma * a.sigma;
     const double tau2 = a.tau * a.tau;
+    const bool split = rqs_split(a);
     for (uint32_t li = bx; li < ndirty; li += gx) {
         const uint32_t tl = a.rr_count ? (a.rr_first + li) % a.n_leaves : a.dirty_list[li];
         const int n = (int)min(a.seen[tl], (uint32_t)a.kappa);
@@ -350,30 +437,22 @@ __device__ __forceinline__ void rqs(const RqsArgs& a, uint32_t bx, uint32_t gx)
         }
         if (tid == 0) s_ncand = 0;
         __syncthreads();
-        for (int k = tid; k < n; k += BS) {
-            const float4 pk = pts[k];
-            double acc = 0.0;
-            for (int j = 0; j < n; ++j) acc += exp(-dist2(pk, pts[j]) / two_s2);
-            rho[k] = acc;
-        }
-        __syncthreads();
-        for (int k = tid; k < n; k += BS) {
-            const float4 pk = pts[k];
-            const double rk = rho[k];
-            int best = -1;
-            double bestd = INFINITY;
-            for (int j = 0; j < n; ++j) {
-                const double rj = rho[j];
-                const bool higher = rj > rk || (rj == rk && j > k);
-                if (!higher) continue;
-                const double d2 = dist2(pk, pts[j]);
-                if (d2 < tau2 && d2 < bestd) {
-                    bestd = d2;
-                    best = j;
-                }
+        if (split) {
+            // links computed by k_rqs_density / k_rqs_links
+            const int* lp = a.rr_parent + (size_t)li * a.kappa;
+            for (int k = tid; k < n; k += BS) {
+                const int best = lp[k];
+                parent[k] = best;
+                root[k] = best < 0 ? k : best;
             }
-            parent[k] = best;
-            root[k] = best < 0 ? k : best;
+        } else {
+            for (int k = tid; k < n; k += BS) rho[k] = rqs_density(pts, n, pts[k], two_s2);
+            __syncthreads();
+            for (int k = tid; k < n; k += BS) {
+                const int best = rqs_link(pts, rho, n, k, tau2);
+                parent[k] = best;
+                root[k] = best < 0 ? k : best;
+            }
         }
         __syncthreads();
         // pointer jumping: after ceil(log2 n) + 1 passes every point holds its root
@@ -543,13 +622,22 @@ hipError_t launch_rqs_jobs(const RqsArgs* jobs, const RqsArgs* hjobs, int njobs,
 {
     if (njobs <= 0) return hipSuccess;
     int kappa = 0;
-    uint32_t cnt = 0;
+    uint32_t cnt = 0, split_cnt = 0;
     for (int j = 0; j < njobs; ++j) {
         if (hjobs[j].rr_count == 0) return hipErrorInvalidValue;
         kappa = max(kappa, hjobs[j].kappa);
         cnt = max(cnt, hjobs[j].rr_count);
+        if (rqs_split(hjobs[j])) split_cnt = max(split_cnt, hjobs[j].rr_count);
     }
     const int nb = (int)min((uint32_t)blocks, cnt);
+    if (split_cnt > 0) {
+        // the rooms whose steps are split (the others' blocks leave at once)
+        const dim3 g((kappa + kRqsRows - 1) / kRqsRows, split_cnt, njobs);
+        k_rqs_density_jobs<<<g, dim3(kRqsRows), 16 * (size_t)kappa, st>>>(jobs);
+        RL_CHECK_LAUNCH();
+        k_rqs_links_jobs<<<g, dim3(kRqsRows), 24 * (size_t)kappa, st>>>(jobs);
+        RL_CHECK_LAUNCH();
+    }
     k_rqs_jobs<1024><<<dim3(nb, njobs), dim3(1024), 36 * (size_t)kappa, st>>>(jobs);
     RL_CHECK_LAUNCH();
     return hipSuccess;
@@ -561,6 +649,13 @@ hipError_t launch_rqs(const RqsArgs& a, int blocks, hipStream_t st)
     if (a.rr_count) {
         // a round-robin step: few leaves, most of them full; 1024 threads each
         const int nb = (int)min((uint32_t)blocks, a.rr_count);
+        if (rqs_split(a)) {
+            const dim3 g((a.kappa + kRqsRows - 1) / kRqsRows, a.rr_count);
+            k_rqs_density<<<g, dim3(kRqsRows), 16 * (size_t)a.kappa, st>>>(a);
+            RL_CHECK_LAUNCH();
+            k_rqs_links<<<g, dim3(kRqsRows), 24 * (size_t)a.kappa, st>>>(a);
+            RL_CHECK_LAUNCH();
+        }
         k_rqs<1024><<<dim3(nb), dim3(1024), lds, st>>>(a);
     } else {
         k_rqs<256><<<dim3(blocks), dim3(256), lds, st>>>(a);

@@ -203,7 +203,14 @@ struct RqsArgs {
     // rr_first + rr_count - 1 (mod n_leaves) are clustered instead of the
     // dirty list, whose state is left as it is
     uint32_t rr_first, rr_count, n_leaves;
+    // a step of at most kRqsSplitLeaves leaves: densities and links per
+    // (leaf of the step, point), [kRqsSplitLeaves][kappa]
+    double* rr_rho;
+    int* rr_parent;
 };
+
+constexpr int kRqsSplitLeaves = 256;
+constexpr int kRqsRows = 256;
 
 // ---------------------------------------------------------------------------
 #ifndef RL_PHILOX_WIDE

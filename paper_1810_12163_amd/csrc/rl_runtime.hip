@@ -230,7 +230,7 @@ ModelLayout model_layout(int maxP, size_t base)
 
 struct AdaptLayout {
     size_t item_leaf, item_pt, item_run, item_lrank, item_n, item_slot, item_h, run_cnt, run_tl, run_next, run_pre,
-        run_tot, head, hkey, hval, total;
+        run_tot, head, hkey, hval, rr_rho, rr_parent, total;
     int Gp;
     uint32_t hsize;
 };
@@ -267,6 +267,8 @@ AdaptLayout adapt_layout(const rl_params& p, int G, size_t base)
     A.head = c.take(T * L * 4);
     A.hkey = c.take((size_t)A.hsize * 4);
     A.hval = c.take((size_t)A.hsize * 4);
+    A.rr_rho = c.take((size_t)kRqsSplitLeaves * (size_t)p.reservoir_capacity * 8);
+    A.rr_parent = c.take((size_t)kRqsSplitLeaves * (size_t)p.reservoir_capacity * 4);
     A.total = c.cur - base;
     return A;
 }
@@ -634,6 +636,8 @@ static RqsArgs rqs_args(rl_room* r)
     a.rr_first = 0;
     a.rr_count = 0;
     a.n_leaves = (uint32_t)(r->T * r->L);
+    a.rr_rho = reinterpret_cast<double*>(r->scr + r->AL.rr_rho);
+    a.rr_parent = reinterpret_cast<int*>(r->scr + r->AL.rr_parent);
     return a;
 }
 

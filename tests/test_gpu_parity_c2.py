@@ -635,3 +635,42 @@ def test_forest_row_multiword_records_and_rounds(c2, forest_row, stage):
     print(f"[forest row {stage}] valid {int(v.sum())}, rounds {res['rounds']}, error {dt * 100:.2f} cm "
           f"{dr:.2f} deg", flush=True)
     room.set_trace(False)
+
+
+def test_round_robin_split_rows_equal_one_workgroup_per_leaf(c2):
+    """A round-robin mode step of at most 256 leaves computes its densities
+    and links in row chunks of 256 points spread over workgroups; a longer
+    step keeps one workgroup per leaf for them.  On rooms whose first tree has
+    256 leaves (depth 8) and full reservoirs of 1024 points, a 256-leaf step
+    (split) and a 300-leaf step (not split) over the same reservoirs give the
+    same mode counts and rows, bit for bit, on the 256 leaves both cover."""
+    from rlsynth import forest, presets
+    w, _, _ = c2
+    p = dict(w.params, depth=8, n_trees=2)
+    nodes = forest.make_forest(77, **dict(presets.FOREST["c1"], n_trees=2))
+    rooms = []
+    for K in (256, 300):
+        print(f"[rr split] leaves per frame {K}", flush=True)
+        room = rl.Room(p, nodes, 640, 480)
+        for f in w.adapt[:12]:
+            d, c = dev(f)
+            room.adapt(d, c, f.K, f.pose)
+        room.set_mode_schedule(K)
+        f = w.adapt[12]
+        d, c = dev(f)
+        room.adapt(d, c, f.K, f.pose)
+        rooms.append(room)
+    torch.cuda.synchronize()
+    A, B = rooms
+    M = p["max_cluster_count"]
+    seen = A.buffer_np(rl.BUF_SEEN, np.uint32)[:256].copy()
+    assert seen.max() >= p["reservoir_capacity"] and (seen > 256).sum() >= 8, seen.max()
+    nA = A.buffer_np(rl.BUF_NMODES, np.uint8)[:256].astype(np.int64)
+    nB = B.buffer_np(rl.BUF_NMODES, np.uint8)[:256].astype(np.int64)
+    assert np.array_equal(nA, nB) and nA.sum() > 0
+    mA = A.buffer_np(rl.BUF_MODES, np.uint32).reshape(-1, M, 16)[:256]
+    mB = B.buffer_np(rl.BUF_MODES, np.uint32).reshape(-1, M, 16)[:256]
+    used = np.arange(M)[None, :] < nA[:, None]
+    assert np.array_equal(mA[used], mB[used])
+    for room in rooms:
+        room.close()
