@@ -204,8 +204,6 @@ __device__ __forceinline__ void write_erec(const Job& J, int e, uint4 lw, uint2 
     rec[0] = w0 | (uint64_t)total;
 }
 
-// Raster-order compaction of eligible pixels over the traversal's tiles, and
-// their records.
 // Exclusive scan of the traversal's per-tile eligible counts (in place) and
 // the list length; one block per job.
 __global__ __launch_bounds__(1024) void k_tile_scan(const Job* __restrict__ jobs)
@@ -235,8 +233,39 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const Job* __restrict__ jobs
     if (threadIdx.x == 1023) J.st->n_elig = s_sum[1023];
 }
 
+// The record when every pixel's bits fit word 0 (the room, or the batch,
+// has at most 56 modes per pixel): M(u) is walked tree by tree, a tree's rows
+// contiguous from its leaf's base row, eight loaded ahead of their tests.
+// A wave runs each tree's loop to its largest count, but no lane leaves a
+// loop for another tree mid-way, which in the single walk above made every
+// step pay for some lane's tree switch.  Same order, same bits.
+template <int T>
+__device__ __forceinline__ void write_erec_w0(const Job& J, int e, uint4 lw, uint2 nw, uint32_t rgb)
+{
+    const uint32_t x = box_colour(rgb);
+    uint64_t w0 = 0;
+    int m0 = 0;   // modes of M(u) in the trees before t
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int c = (int)count_of(nw, t);
+        const uint2* rows = J.cbox + (size_t)((((uint32_t)t << J.D) + leaf_of(lw, t)) * (uint32_t)J.M);
+        for (int j0 = 0; j0 < c; j0 += 8) {
+            uint2 bx[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (j0 + u < c) bx[u] = ldg(rows + j0 + u);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (j0 + u < c && box_pass(bx[u], x)) w0 |= 1ull << (8 + m0 + j0 + u);
+        }
+        m0 += c;
+    }
+    J.erec[(size_t)e * J.ew] = w0 | (uint64_t)m0;
+}
+
 // Raster-order compaction of eligible pixels over the traversal's tiles, and
 // their records.
+template <int T>
 __global__ __launch_bounds__(256) void k_eligible(const Job* __restrict__ jobs)
 {
     const Job& J = jobs[blockIdx.y];
@@ -257,7 +286,8 @@ __global__ __launch_bounds__(256) void k_eligible(const Job* __restrict__ jobs)
         const uint2 pv = ldg(J.probe + p);
         J.ecold[2 * k] = make_uint4((uint32_t)p, pv.x, nw.x, nw.y);
         J.ecold[2 * k + 1] = lw;
-        write_erec(J, k, lw, nw, pv.y);
+        if (J.ew == 1) write_erec_w0<T>(J, k, lw, nw, pv.y);
+        else write_erec(J, k, lw, nw, pv.y);
     }
 }
 
@@ -1698,11 +1728,22 @@ hipError_t launch_traverse(const Job* jobs, int njobs, int maxP, int T, int top,
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_eligible(const Job* jobs, int njobs, int maxP, hipStream_t st)
+hipError_t launch_eligible(const Job* jobs, int njobs, int maxP, int T, hipStream_t st)
 {
     k_tile_scan<<<dim3(njobs), dim3(1024), 0, st>>>(jobs);
     RL_CHECK_LAUNCH();
-    k_eligible<<<dim3((maxP + 255) / 256, njobs), dim3(256), 0, st>>>(jobs);
+    const dim3 g((maxP + 255) / 256, njobs), b(256);
+    switch (T) {
+        case 1: k_eligible<1><<<g, b, 0, st>>>(jobs); break;
+        case 2: k_eligible<2><<<g, b, 0, st>>>(jobs); break;
+        case 3: k_eligible<3><<<g, b, 0, st>>>(jobs); break;
+        case 4: k_eligible<4><<<g, b, 0, st>>>(jobs); break;
+        case 5: k_eligible<5><<<g, b, 0, st>>>(jobs); break;
+        case 6: k_eligible<6><<<g, b, 0, st>>>(jobs); break;
+        case 7: k_eligible<7><<<g, b, 0, st>>>(jobs); break;
+        case 8: k_eligible<8><<<g, b, 0, st>>>(jobs); break;
+        default: return hipErrorInvalidValue;
+    }
     RL_CHECK_LAUNCH();
     return hipSuccess;
 }

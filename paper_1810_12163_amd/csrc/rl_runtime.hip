@@ -24,7 +24,7 @@
 namespace rl {
 hipError_t launch_prep(const Job* jobs, int njobs, int maxN, hipStream_t st);
 hipError_t launch_traverse(const Job* jobs, int njobs, int maxP, int T, int top, hipStream_t st);
-hipError_t launch_eligible(const Job* jobs, int njobs, int maxP, hipStream_t st);
+hipError_t launch_eligible(const Job* jobs, int njobs, int maxP, int T, hipStream_t st);
 hipError_t launch_hyp_search(const Job* jobs, int njobs, int maxN, int maxIters, int ipt, hipStream_t st);
 hipError_t launch_hyp_finalize(const Job* jobs, int njobs, int maxN, hipStream_t st);
 hipError_t launch_score(const Job* jobs, int njobs, int round, int nptiles, int maxSurv,
@@ -1167,7 +1167,7 @@ static hipError_t launch_sequence(const Job* jobs, int njobs, int maxP, int maxN
     RL_MARK(RL_TIMER_TRAVERSE, start);
     RL_TRY(launch_traverse(jobs, njobs, maxP, T, sc.top, st));
     RL_MARK(RL_TIMER_TRAVERSE, stop);
-    RL_TRY(launch_eligible(jobs, njobs, maxP, st));
+    RL_TRY(launch_eligible(jobs, njobs, maxP, T, st));
     RL_MARK(RL_TIMER_HYP_SEARCH, start);
     RL_TRY(launch_hyp_search(jobs, njobs, maxN, maxIters, sc.ipt, st));
     RL_MARK(RL_TIMER_HYP_SEARCH, stop);
