@@ -1050,8 +1050,12 @@ __device__ __forceinline__ int plan_job(const int* plan, int njobs, int g)
 }
 
 // 1-D grid of waves striding over the plan's items of all jobs, so that a
-// job with many survivors gets as many waves as its items need.
-__global__ __launch_bounds__(64) void k_lm_pass(const Job* __restrict__ jobs, int njobs, int round)
+// job with many survivors gets as many waves as its items need.  The pass
+// waits on its row loads, so it is held to 128 VGPRs (four waves per SIMD;
+// a few values spill) with two rows in flight: faster than two waves per SIMD
+// with four rows in flight (190 VGPRs), or than three waves (142).
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_lm_pass(
+    const Job* __restrict__ jobs, int njobs, int round)
 {
 #pragma clang fp contract(off)
     const int* plan = jobs[0].lm_plan;
@@ -1092,15 +1096,15 @@ __device__ __forceinline__ void lm_pass_item(const Job& J, int pos, int tile, in
         const double y0 = P[0] * x[0] + P[1] * x[1] + P[2] * x[2] + P[9];
         const double y1 = P[3] * x[0] + P[4] * x[1] + P[5] * x[2] + P[10];
         const double y2 = P[6] * x[0] + P[7] * x[1] + P[8] * x[2] + P[11];
-        // nearest mode (ties to the lower index) over the staged rows, four at
+        // nearest mode (ties to the lower index) over the staged rows, two at
         // a time; the best row stays in registers
         double best = INFINITY;
         bool found = false;
         float4 ba = make_float4(0.f, 0.f, 0.f, 0.f), bb = ba, bc = ba;
-        for (int j0 = 0; j0 < nm; j0 += 4) {
-            float4 ra[4], rb[4], rc[4];
+        for (int j0 = 0; j0 < nm; j0 += 2) {
+            float4 ra[2], rb[2], rc[2];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < 2; ++u) {
                 const int j = min(j0 + u, nm - 1);
                 const float4* row = J.lm_rows + ((size_t)j * J.lm_icap + k) * 3;
                 ra[u] = ldg(row);
@@ -1112,7 +1116,7 @@ __device__ __forceinline__ void lm_pass_item(const Job& J, int pos, int tile, in
                 }
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < 2; ++u) {
                 if (j0 + u >= nm) break;
                 double qq = row_q<COV>(ra[u], rb[u], rc[u], y0, y1, y2);
                 qq = qq < 0.0 ? 0.0 : qq;
