@@ -425,28 +425,38 @@ def _same_room_state(A, B, tag):
     assert np.array_equal(ma[used], mb[used]), (tag, "modes")
 
 
-@pytest.mark.parametrize("leaves_per_frame", [0, 64])
+@pytest.mark.parametrize("leaves_per_frame", [0, 64, (64, 300)])
 def test_batched_adaptations_equal_plain_sequence(leaves_per_frame):
     """Adaptation requests inside batches (two rooms, mixed with
     relocalisations, one batch replayed from a graph and one launched
     directly): each batch's relocalisations see the rooms as they were before
     its adaptations, and afterwards reservoirs, arrival counters, dirty flags
     and modes equal those of plain adapt calls in request order, bit for bit,
-    under the exact and the round-robin mode schedule."""
+    under the exact and the round-robin mode schedule.  (64, 300): two-tree
+    rooms whose round-robin steps share one launch, the first split into row
+    chunks (at most 256 leaves), the second not."""
+    from rlsynth import forest, presets
     specs = [workloads.c1(room_id=r, n_queries=2) for r in (0, 1)]
+    mixed = isinstance(leaves_per_frame, tuple)
+    T = 2 if mixed else 1
+    nodes = [forest.make_forest(1000 + r, **dict(presets.FOREST["c1"], n_trees=2)) if mixed else w.nodes
+             for r, w in enumerate(specs)]
+    params = [dict(w.params, n_trees=T) for w in specs]
+    schedules = leaves_per_frame if mixed else (leaves_per_frame, leaves_per_frame)
 
     def make():
         out = []
-        for w in specs:
-            room = rl.Room(w.params, w.nodes, 160, 120)
-            room.set_mode_schedule(leaves_per_frame)
+        for r, w in enumerate(specs):
+            room = rl.Room(params[r], nodes[r], 160, 120)
+            room.set_mode_schedule(schedules[r])
             for f in w.adapt[:2]:
                 room.adapt(*dev(f), f.K, f.pose)
             out.append(room)
         return out
 
     A, B = make(), make()
-    batch = rl.Batch(8, 160, 120, 64, 100, 6, 1, 5)
+    M = params[0]["max_cluster_count"]
+    batch = rl.Batch(8, 160, 120, 64, 100, 6, T, T * M)
     frames = {}
 
     def F(f):
@@ -484,7 +494,7 @@ def test_batched_adaptations_equal_plain_sequence(leaves_per_frame):
                 B[r].adapt(*F(f), f.K, f.pose)
         torch.cuda.synchronize()
         for r in (0, 1):
-            if leaves_per_frame == 0:
+            if schedules[r] == 0:
                 A[r].update_modes()
                 B[r].update_modes()
             torch.cuda.synchronize()
