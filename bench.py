@@ -126,6 +126,8 @@ def main():
     ap.add_argument("--c3-queries", type=int, default=300,
                     help="frames through the three-stage cascade of 640x480 relocalisers, 30%% of them "
                          "far from every adaptation pose (0 = skip)")
+    ap.add_argument("--c3-calibration", type=int, default=60,
+                    help="queries of the disjoint set that calibrates the cascade's fallback thresholds")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--timer", default="hyp_search", choices=["traverse", "hyp_search", "ransac"])
     ap.add_argument("--serve-seconds", type=float, default=20.0,
@@ -176,6 +178,10 @@ def main():
     if args.c3_queries > 0:
         c3_inputs = workloads.queries_for(w.room, [f.pose for f in w.adapt], args.c3_queries, room_id=0,
                                           novel_fraction=0.3, start=1000, processes=procs)
+        # a disjoint calibration set for the cascade's fallback thresholds
+        c3_calib = workloads.queries_for(w.room, [f.pose for f in w.adapt], args.c3_calibration, room_id=0,
+                                         novel_fraction=0.3, start=3000, processes=procs)
+        c3_inputs = (c3_inputs, c3_calib)
     serve_inputs = None
     if args.serve_seconds > 0:
         serve_inputs = workloads.serving_setup(n_rooms=args.serve_rooms, n_adapt=20, n_cameras=32,
@@ -326,7 +332,7 @@ def main():
     ok = [e[0] <= 0.05 and e[1] <= 5.0 for e in errs]
 
     lm = lm_leg(args, rl, room, batch, reqs, frames, w, qd, qc, use_graph) if args.lm_steps > 0 else None
-    cascade = cascade_leg(args, rl, w, dev, c3_inputs or w.queries) if args.cascade_frames > 0 else None
+    cascade = cascade_leg(args, rl, w, dev, c3_inputs[0] if c3_inputs else w.queries) if args.cascade_frames > 0 else None
     robustness = robustness_leg(args, rl, dev, robust_inputs) if robust_inputs is not None else None
 
     # ---- rooflines -------------------------------------------------------------
@@ -490,19 +496,22 @@ def c1_leg(args, rl, dev, w1):
 C3_THRESHOLDS = (0.05, 0.075)
 
 
-def c3_leg(args, rl, dev, w, queries):
+def c3_leg(args, rl, dev, w, inputs):
     """The three-stage cascade of 640x480 relocalisers on the shared forest:
     (a) the 2x decimated 320x240 frame with 256 hypotheses, (b) the full frame
     with 1024 hypotheses and the inlier refit, (c) 4096 hypotheses culled to
     16, re-ranked by the plane score (mean distance of the back-projected depth
     to the nearest surface).  A stage falls back when the plane score of its
-    pose exceeds 5 cm (stage a) or 7.5 cm (stage b).  30% of the queries lie >= 50 cm or >= 50 deg from
-    every adaptation pose.  Frames one at a time: latency, stage reached,
-    accuracy."""
+    pose exceeds its threshold: the paper's 5 cm (stage a) and 7.5 cm (stage
+    b), and thresholds calibrated on a disjoint set of queries (the 95th
+    percentile of each stage's score over the frames it relocalises within
+    5 cm / 5 deg).  30% of the queries lie >= 50 cm or >= 50 deg from every
+    adaptation pose.  Frames one at a time: latency, stage reached, accuracy."""
     import torch
 
-    from paper_1810_12163_amd.cascade import Cascade, c3_stages
+    from paper_1810_12163_amd.cascade import Cascade, c3_stages, calibrate_thresholds
     from rlsynth import presets, scene
+    queries, calib = inputs
     room = rl.Room(dict(w.params, **{k: presets.preset("c3c")[k] for k in
                                      ("max_pose_candidates", "max_pose_candidates_after_cull",
                                       "max_relocalisations_to_output", "final_refine")}),
@@ -517,36 +526,55 @@ def c3_leg(args, rl, dev, w, queries):
         q = queries[k]
         cas.relocalise(torch.from_numpy(q.depth).to(dev), torch.from_numpy(q.rgb).to(dev), q.K, request_seed=5000 + k)
     torch.cuda.synchronize()
-    ms, stages, errs, novel, energies = [], [], [], [], []
-    for k, q in enumerate(queries):
-        d, c = torch.from_numpy(q.depth).to(dev), torch.from_numpy(q.rgb).to(dev)
-        torch.cuda.synchronize()
-        out = cas.relocalise(d, c, q.K, request_seed=k)
-        ms.append(out["ms"])
-        stages.append(out["stage"])
-        e = scene.pose_error(out["pose"].astype(np.float64), q.pose) if out["status"] == "ok" else (np.inf, np.inf)
-        errs.append(e)
-        energies.append((out.get("mean_energy", np.inf), e[0] <= 0.05 and e[1] <= 5.0))
-        novel.append(all(scene.pose_error(q.pose, a)[0] >= 0.5 or scene.pose_error(q.pose, a)[1] >= 50.0
-                         for a in adapt_poses))
-    room.close()
-    ok = np.array([e[0] <= 0.05 and e[1] <= 5.0 for e in errs])
-    nv = np.array(novel)
-    first = np.array([x[0] for x in energies])
-    res = dict(frames=len(ms), mean_ms=float(np.mean(ms)), p50_ms=percentile(ms, 50), p99_ms=percentile(ms, 99),
-               relocs_per_s=len(ms) / (sum(ms) * 1e-3),
-               stage_counts={s.name: stages.count(s.name) for s in cas.stages},
-               frac_within_5cm_5deg=float(np.mean(ok)),
-               frac_within_5cm_5deg_near=float(np.mean(ok[~nv])) if np.any(~nv) else None,
-               frac_within_5cm_5deg_novel=float(np.mean(ok[nv])) if np.any(nv) else None,
-               novel_fraction=float(np.mean(nv)), thresholds_m=list(C3_THRESHOLDS),
-               mean_energy_median_correct=float(np.median(first[ok])) if np.any(ok) else None,
-               mean_energy_median_wrong=float(np.median(first[~ok])) if np.any(~ok) else None,
-               median_cm=float(np.median([e[0] for e in errs]) * 100))
+    frames = [(torch.from_numpy(q.depth).to(dev), torch.from_numpy(q.rgb).to(dev), q) for q in queries]
+    novel = np.array([all(scene.pose_error(q.pose, a)[0] >= 0.5 or scene.pose_error(q.pose, a)[1] >= 50.0
+                          for a in adapt_poses) for q in queries])
+
+    def run(thresholds):
+        ms, stages, errs, energies = [], [], [], []
+        for k, (d, c, q) in enumerate(frames):
+            torch.cuda.synchronize()
+            out = cas.relocalise(d, c, q.K, request_seed=k)
+            ms.append(out["ms"])
+            stages.append(out["stage"])
+            e = scene.pose_error(out["pose"].astype(np.float64), q.pose) if out["status"] == "ok" else (np.inf, np.inf)
+            errs.append(e)
+            energies.append(out.get("mean_energy", np.inf))
+        ok = np.array([e[0] <= 0.05 and e[1] <= 5.0 for e in errs])
+        first = np.array(energies)
+        return dict(frames=len(ms), mean_ms=float(np.mean(ms)), p50_ms=percentile(ms, 50), p99_ms=percentile(ms, 99),
+                    relocs_per_s=len(ms) / (sum(ms) * 1e-3),
+                    stage_counts={s.name: stages.count(s.name) for s in cas.stages},
+                    frac_within_5cm_5deg=float(np.mean(ok)),
+                    frac_within_5cm_5deg_near=float(np.mean(ok[~novel])) if np.any(~novel) else None,
+                    frac_within_5cm_5deg_novel=float(np.mean(ok[novel])) if np.any(novel) else None,
+                    novel_fraction=float(np.mean(novel)), thresholds_m=[float(t) for t in thresholds],
+                    mean_energy_median_correct=float(np.median(first[ok])) if np.any(ok) else None,
+                    mean_energy_median_wrong=float(np.median(first[~ok])) if np.any(~ok) else None,
+                    median_cm=float(np.median([e[0] for e in errs]) * 100))
+
+    res = run(C3_THRESHOLDS)
     log(f"[bench] c3 cascade: {res['mean_ms']:.2f} ms per frame (p50 {res['p50_ms']:.2f}, p99 {res['p99_ms']:.2f}), "
         f"stages {res['stage_counts']}, within 5cm/5deg {res['frac_within_5cm_5deg']:.3f} "
         f"(near {res['frac_within_5cm_5deg_near']}, novel {res['frac_within_5cm_5deg_novel']}); returned pose's "
         f"mean energy, median: correct {res['mean_energy_median_correct']} / wrong {res['mean_energy_median_wrong']}")
+    if calib:
+        cal = [(torch.from_numpy(q.depth).to(dev), torch.from_numpy(q.rgb).to(dev), q.K, 20000 + k, q.pose)
+               for k, q in enumerate(calib)]
+
+        def correct(pose, truth):
+            e = scene.pose_error(pose.astype(np.float64), truth)
+            return e[0] <= 0.05 and e[1] <= 5.0
+
+        th = calibrate_thresholds(cas, cal, correct, q=95.0)
+        rc = run(th)
+        rc["calibration_frames"] = len(cal)
+        res["calibrated"] = rc
+        log(f"[bench] c3 cascade, thresholds calibrated on {len(cal)} disjoint queries "
+            f"({', '.join(f'{t * 100:.1f} cm' for t in th)}): {rc['mean_ms']:.2f} ms per frame, stages "
+            f"{rc['stage_counts']}, within 5cm/5deg {rc['frac_within_5cm_5deg']:.3f} "
+            f"(near {rc['frac_within_5cm_5deg_near']}, novel {rc['frac_within_5cm_5deg_novel']})")
+    room.close()
     return res
 
 

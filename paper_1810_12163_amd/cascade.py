@@ -101,39 +101,67 @@ class Cascade:
             return self.room.depth_scores(depth, rgb, K, self.surfaces, poses12, self.min_depth, self.max_depth)[0]
         return self.room.plane_scores(depth, rgb, K, self.surfaces, poses12)
 
+    def _stage(self, si, depth, rgb, K, request_seed):
+        """Stage si on the frame: (result, fallback score); the score is +inf
+        when the stage returns no pose."""
+        st = self.stages[si]
+        d, c, Kk = decimate(depth, rgb, K) if st.decimate else (depth, rgb, K)
+        res = self.room.relocalise(d, c, Kk, request_seed=request_seed * 8 + si, **st.call_settings())
+        if res["status"] != "ok":
+            return res, float("inf")
+        if st.n_out > 1:
+            k = res["n_out"]
+            slots, poses = self.room.survivors(k)
+            scores = self.scores(depth, rgb, K, poses)
+            best = int(np.argmin(scores))          # ties -> the better-energy hypothesis
+            H = np.eye(4, dtype=np.float32)
+            H[:3, :3] = poses[best, :9].reshape(3, 3)
+            H[:3, 3] = poses[best, 9:]
+            res = dict(res, pose=H, winner=int(slots[best]), model_score=float(scores[best]), ranked=scores)
+            return res, (float(scores[best]) if self.fallback == "model" else res["mean_energy"])
+        if self.fallback == "model":
+            p12 = np.concatenate([res["pose"][:3, :3].reshape(-1), res["pose"][:3, 3]])
+            score = float(self.scores(depth, rgb, K, p12[None])[0])
+            return dict(res, model_score=score), score
+        return res, res["mean_energy"]
+
     def relocalise(self, depth, rgb, K, request_seed: int = 0) -> dict:
         t0 = time.perf_counter()
         trail = []
         res = None
         for si, st in enumerate(self.stages):
-            d, c, Kk = decimate(depth, rgb, K) if st.decimate else (depth, rgb, K)
-            seed = request_seed * 8 + si
-            res = self.room.relocalise(d, c, Kk, request_seed=seed, **st.call_settings())
+            res, score = self._stage(si, depth, rgb, K, request_seed)
             last = si == len(self.stages) - 1
+            trail.append((st.name, score))
             if res["status"] != "ok":
-                trail.append((st.name, float("inf")))
                 if last:
                     break
                 continue
-            if st.n_out > 1:
-                k = res["n_out"]
-                slots, poses = self.room.survivors(k)
-                scores = self.scores(depth, rgb, K, poses)
-                best = int(np.argmin(scores))          # ties -> the better-energy hypothesis
-                H = np.eye(4, dtype=np.float32)
-                H[:3, :3] = poses[best, :9].reshape(3, 3)
-                H[:3, 3] = poses[best, 9:]
-                res = dict(res, pose=H, winner=int(slots[best]), model_score=float(scores[best]),
-                           ranked=scores)
-                score = float(scores[best]) if self.fallback == "model" else res["mean_energy"]
-            elif self.fallback == "model":
-                p12 = np.concatenate([res["pose"][:3, :3].reshape(-1), res["pose"][:3, 3]])
-                score = float(self.scores(depth, rgb, K, p12[None])[0])
-                res = dict(res, model_score=score)
-            else:
-                score = res["mean_energy"]
-            trail.append((st.name, score))
             if last or score <= st.threshold:
                 break
         out = dict(res, stage=trail[-1][0], trail=trail, ms=(time.perf_counter() - t0) * 1e3)
         return out
+
+    def stage_outputs(self, depth, rgb, K, request_seed: int = 0) -> list:
+        """Every stage but the last on the frame, whatever the thresholds (the
+        seeds relocalise uses): per stage (result, fallback score)."""
+        return [self._stage(si, depth, rgb, K, request_seed) for si in range(len(self.stages) - 1)]
+
+
+def calibrate_thresholds(cascade, frames, correct, q: float = 95.0) -> list:
+    """Fallback thresholds from a calibration set: for each stage but the
+    last, the q-th percentile of the stage's score over the frames whose
+    stage pose is correct.  frames: (depth, rgb, K, request_seed, truth);
+    correct(pose, truth) -> bool.  A stage with no correct frame keeps its
+    threshold.  Returns the thresholds and sets them on the stages."""
+    per_stage = [[] for _ in cascade.stages[:-1]]
+    for depth, rgb, K, seed, truth in frames:
+        for si, (res, score) in enumerate(cascade.stage_outputs(depth, rgb, K, request_seed=seed)):
+            if res["status"] == "ok" and np.isfinite(score) and correct(res["pose"], truth):
+                per_stage[si].append(score)
+    out = []
+    for st, v in zip(cascade.stages[:-1], per_stage):
+        if v:
+            st.threshold = float(np.percentile(v, q))
+        out.append(st.threshold)
+    return out
