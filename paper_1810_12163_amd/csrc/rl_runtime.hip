@@ -372,8 +372,8 @@ struct rl_room {
     // that read it since then (a pool, reused).
     hipEvent_t wev;
     bool wrote;
-    // batched adaptations run on the room's stream; bev marks their end for
-    // the batch's stream to wait on
+    // bev marks the work queued so far on the room's stream, for a batch that
+    // adapts the room to wait on (the room's stream then waits for that batch)
     hipEvent_t bev;
     uint32_t mode_version;    // mode updates queued so far (each RQS launch)
     std::vector<hipEvent_t> readers, spare;
