@@ -1648,13 +1648,30 @@ static rl_status batch_relocalise_queue(rl_batch* b, const rl_request* reqs, con
     Job* job_host = b->job_ring[slot_k];
     hipError_t e = hipEventSynchronize(b->up_ev[slot_k]);
     if (e != hipSuccess) return hip_fail(e, "job table reuse");
+    // job slot -> request (position in reloc), -1 for an empty job.  The
+    // search runs job j's blocks on XCD j % 8 (eight jobs or more), so the
+    // requests are grouped by room and each group is dealt to as few XCDs as
+    // the balance allows: an XCD's L2 then holds few rooms' tables.  A job's
+    // slot changes no result.
+    std::vector<int> at(nq, -1);
+    if (nq >= 8 && nq % 8 == 0) {
+        std::vector<int> order;
+        for (rl_room* r : rooms)
+            for (int k = 0; k < n; ++k)
+                if (reqs[reloc[k]].room == r) order.push_back(k);
+        int k = 0;
+        for (int x = 0; x < 8; ++x)
+            for (int i = 0; i < n / 8 + (x < n % 8 ? 1 : 0); ++i) at[i * 8 + x] = order[k++];
+    } else {
+        for (int k = 0; k < n; ++k) at[k] = k;
+    }
     for (int i = 0; i < nq; ++i) {
         Job J;
-        if (i < n) {
-            const rl_request& q = reqs[reloc[i]];
+        if (at[i] >= 0) {
+            const rl_request& q = reqs[reloc[at[i]]];
             const int N = q.n_hypotheses > 0 ? q.n_hypotheses : q.room->N;
             J = make_job(q.room, b->ws, b->slots[i], &q.frame, q.request_seed, N);
-            J.result = dev_results + reloc[i];
+            J.result = dev_results + reloc[at[i]];
             if (q.pose_update != 0) J.lm = q.pose_update > 0 ? 1 : 0;
         } else {
             std::memset(&J, 0, sizeof(J));
