@@ -76,6 +76,18 @@ __global__ __launch_bounds__(256) void k_pack(const Job* __restrict__ jobs)
 }
 
 // ------------------------------------------------------------------------
+// Workgroup (x, y) of a (tiles, jobs) grid runs on XCD (x + y gridDim.x) mod
+// 8.  With gridDim.x a multiple of 8, XCD e takes the e-th eighth of each
+// frame's tiles (a band of rows), so its L2 holds the part of the frame that
+// its probes read rather than the whole frame.  -1: no tile.
+__device__ __forceinline__ int band_tile(int bx, int gx, int ntiles)
+{
+    if (gx & 7) return bx < ntiles ? bx : -1;
+    const int per = (ntiles + 7) >> 3, k = bx >> 3;
+    const int t = (bx & 7) * per + k;
+    return (k < per && t < ntiles) ? t : -1;
+}
+
 // One thread per pixel, all trees in lockstep.  Writes leaves (16 B/pixel),
 // per-tree mode counts (8 B/pixel), |M(u)| and the tile's eligible count.
 template <int T, int TOP>
@@ -83,7 +95,8 @@ __global__ __launch_bounds__(256) void k_traverse(const Job* __restrict__ jobs)
 {
     const Job& J = jobs[blockIdx.y];
     const int w = J.w, h = J.h, P = w * h;
-    if ((int)blockIdx.x * 256 >= P) return;
+    const int tile = band_tile((int)blockIdx.x, (int)gridDim.x, (P + 255) / 256);
+    if (tile < 0) return;
     __shared__ int s_wave[4];
     // the top levels of every tree, shared by the block's pixels
     __shared__ float4 s_top[T * ((1 << TOP) - 1)];
@@ -93,7 +106,7 @@ __global__ __launch_bounds__(256) void k_traverse(const Job* __restrict__ jobs)
         s_top[i] = ldg(J.nodes + t * ((1 << J.D) - 1) + (i - t * ntop));
     }
     __syncthreads();
-    const int p = blockIdx.x * 256 + threadIdx.x;
+    const int p = tile * 256 + threadIdx.x;
     bool elig = false;
     if (p < P) {
         const int x = p % w, y = p / w;
@@ -135,7 +148,7 @@ __global__ __launch_bounds__(256) void k_traverse(const Job* __restrict__ jobs)
     }
     int tot;
     (void)block_prefix256(elig, s_wave, &tot);
-    if (threadIdx.x == 0) J.tile_count[blockIdx.x] = tot;
+    if (threadIdx.x == 0) J.tile_count[tile] = tot;
 }
 
 // A walk over M(u) in tree-major order (the order mode_row numbers it): the
