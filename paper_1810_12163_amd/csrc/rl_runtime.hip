@@ -1649,12 +1649,25 @@ static rl_status batch_relocalise_queue(rl_batch* b, const rl_request* reqs, con
     hipError_t e = hipEventSynchronize(b->up_ev[slot_k]);
     if (e != hipSuccess) return hip_fail(e, "job table reuse");
     // job slot -> request (position in reloc), -1 for an empty job.  The
-    // search runs job j's blocks on XCD j % 8 (eight jobs or more), so the
-    // requests are grouped by room and each group is dealt to as few XCDs as
-    // the balance allows: an XCD's L2 then holds few rooms' tables.  A job's
-    // slot changes no result.
+    // search runs job j's blocks on XCD j % 8 (eight jobs or more).  When the
+    // jobs carry equal search work (hypotheses x iterations), the requests
+    // are grouped by room and dealt to the XCDs in equal contiguous runs: an
+    // XCD's L2 then holds few rooms' tables, and each XCD gets a run of
+    // consecutive requests rather than every eighth.  Jobs of unequal work
+    // keep request order, which balances the XCDs better than runs by count.
+    // A job's slot changes no result.
     std::vector<int> at(nq, -1);
-    if (nq >= 8 && nq % 8 == 0) {
+    bool equal_work = true;
+    for (int k = 1; k < n && equal_work; ++k) {
+        const rl_request& a = reqs[reloc[0]];
+        const rl_request& q = reqs[reloc[k]];
+        const long long wa = (long long)(a.n_hypotheses > 0 ? a.n_hypotheses : a.room->N) *
+                             a.room->p.max_candidate_generation_iterations;
+        const long long wq = (long long)(q.n_hypotheses > 0 ? q.n_hypotheses : q.room->N) *
+                             q.room->p.max_candidate_generation_iterations;
+        equal_work = wa == wq;
+    }
+    if (equal_work && nq >= 8 && nq % 8 == 0) {
         std::vector<int> order;
         for (rl_room* r : rooms)
             for (int k = 0; k < n; ++k)
