@@ -1657,17 +1657,15 @@ static rl_status batch_relocalise_queue(rl_batch* b, const rl_request* reqs, con
     // keep request order, which balances the XCDs better than runs by count.
     // A job's slot changes no result.
     std::vector<int> at(nq, -1);
+    std::vector<long long> work(n);
     bool equal_work = true;
-    for (int k = 1; k < n && equal_work; ++k) {
-        const rl_request& a = reqs[reloc[0]];
+    for (int k = 0; k < n; ++k) {
         const rl_request& q = reqs[reloc[k]];
-        const long long wa = (long long)(a.n_hypotheses > 0 ? a.n_hypotheses : a.room->N) *
-                             a.room->p.max_candidate_generation_iterations;
-        const long long wq = (long long)(q.n_hypotheses > 0 ? q.n_hypotheses : q.room->N) *
-                             q.room->p.max_candidate_generation_iterations;
-        equal_work = wa == wq;
+        work[k] = (long long)(q.n_hypotheses > 0 ? q.n_hypotheses : q.room->N) *
+                  q.room->p.max_candidate_generation_iterations;
+        equal_work = equal_work && work[k] == work[0];
     }
-    if (equal_work && nq >= 8 && nq % 8 == 0) {
+    if (nq >= 8 && nq % 8 == 0 && equal_work) {
         std::vector<int> order;
         for (rl_room* r : rooms)
             for (int k = 0; k < n; ++k)
@@ -1675,6 +1673,31 @@ static rl_status batch_relocalise_queue(rl_batch* b, const rl_request* reqs, con
         int k = 0;
         for (int x = 0; x < 8; ++x)
             for (int i = 0; i < n / 8 + (x < n % 8 ? 1 : 0); ++i) at[i * 8 + x] = order[k++];
+    } else if (nq >= 8 && nq % 8 == 0) {
+        // unequal work: longest first, each to the least loaded XCD with a
+        // free slot (on a tie, one that already holds the job's room)
+        std::vector<int> order(n);
+        for (int k = 0; k < n; ++k) order[k] = k;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return work[a] > work[c]; });
+        long long load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int used[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        std::vector<rl_room*> held[8];
+        for (int k : order) {
+            rl_room* r = reqs[reloc[k]].room;
+            int best = -1;
+            bool best_room = false;
+            for (int x = 0; x < 8; ++x) {
+                if (used[x] * 8 + x >= nq) continue;
+                const bool has = std::find(held[x].begin(), held[x].end(), r) != held[x].end();
+                if (best < 0 || load[x] < load[best] || (load[x] == load[best] && has && !best_room)) {
+                    best = x;
+                    best_room = has;
+                }
+            }
+            at[used[best]++ * 8 + best] = k;
+            load[best] += work[k];
+            if (std::find(held[best].begin(), held[best].end(), r) == held[best].end()) held[best].push_back(r);
+        }
     } else {
         for (int k = 0; k < n; ++k) at[k] = k;
     }
