@@ -452,10 +452,12 @@ rl_status rl_batch_destroy(rl_batch* b);
  * rooms afterwards equal those of relocaliser_adapt calls of the adaptation
  * requests in order (under either mode schedule); the record of an
  * adaptation request has status RL_OK, winner -1 and the identity pose.
- * An adaptation runs on its room's stream, after the batch's
- * relocalisations and the work already queued there (a room's adaptations in
- * request order, different rooms concurrently); the batch completes after
- * all of them.  results: host array of n records; the call is
+ * The adaptations run on the batch's stream after its relocalisations and
+ * after the work already queued on each adapted room's stream, as rounds of
+ * multi-room launches (round k adapts the k-th frame of each room, so a
+ * room's adaptations keep request order); each room's stream, and every
+ * later reader of its modes, is ordered after them, and the batch completes
+ * after all of them.  results: host array of n records; the call is
  * synchronous.  use_graph != 0 captures the relocalisations' launch sequence
  * for this batch shape once and replays it on later calls with the same
  * shape (adaptations are launched directly).  RL_EINVAL for an unknown kind,
