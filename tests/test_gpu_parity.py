@@ -196,6 +196,20 @@ def test_batch_equals_plain(c1):
     for a, b in zip(got, plain[::-1][:4]):
         assert np.array_equal(a["pose"], b["pose"]) and a["energy"] == b["energy"]
     batch.close()
+    # 12 requests over both rooms: equal work (the job table grouped by room)
+    # and unequal hypothesis counts (longest first over the XCDs); a job's
+    # place in the table changes no result
+    big = rl.Batch(16, 160, 120, 64, 100, 6, 1, 5)
+    for counts in ((64,) * 12, (64, 32, 16, 64, 48, 32, 64, 16, 32, 64, 48, 16)):
+        reqs = [(room if k % 3 else room2, *dev((w if k % 3 else w2).queries[k % 2]),
+                 (w if k % 3 else w2).queries[k % 2].K, 300 + k, counts[k]) for k in range(12)]
+        want = [r.relocalise(d, c, K, request_seed=sd, n_hypotheses=nh) for (r, d, c, K, sd, nh) in reqs]
+        for use_graph in (False, True):
+            got = big.relocalise(reqs, use_graph=use_graph)
+            for a, b in zip(got, want):
+                assert a["status"] == b["status"] and a["winner"] == b["winner"] and a["n_valid"] == b["n_valid"]
+                assert np.array_equal(a["pose"], b["pose"]) and a["energy"] == b["energy"]
+    big.close()
     room2.close()
 
 
