@@ -38,8 +38,9 @@ constexpr int kMaxFastWaves = 4;
 // node records per block): a launch schedule, 6 or 8
 constexpr int kTopLevelsMin = 6, kTopLevelsMax = 8;
 
-// LM refinement: pixels per pass wave, doubles of per-slot state
-constexpr int kLmTile = 128;
+// LM refinement: pixels per partial-sum tile of a pass (a wave takes one or
+// two tiles), doubles of per-slot state
+constexpr int kLmTile = 64;
 constexpr int kLmStateDoubles = 56;
 constexpr int kFastStride = 64 * kMaxFastWaves;
 

@@ -927,8 +927,8 @@ __global__ __launch_bounds__(kFastStride) void k_select_all(const Job* __restric
 // the final pose.
 //
 // The work is spread over the grid: a pass evaluates (E, g, N) for every
-// survivor of every job at once, one wave per (survivor, kLmTile-pixel
-// tile) writing its partial sums; a step kernel (one wave per survivor)
+// survivor of every job at once, one wave per (survivor, one or two
+// kLmTile-pixel tiles) writing each tile's partial sums; a step kernel (one wave per survivor)
 // adds the tiles in order, takes the accept/reject decision and the next
 // damped step.  Both stride over the round's plan of the running jobs'
 // items and survivors, so their grids do not scale with the batch's
@@ -1003,13 +1003,13 @@ __global__ __launch_bounds__(256) void k_lm_init(const Job* __restrict__ jobs, i
     S[kLmGo] = 1.0;
 }
 
-template <bool COV>
-__device__ __forceinline__ void lm_pass_item(const Job& J, int pos, int tile, int nI);
+template <bool COV, int PAIR>
+__device__ __forceinline__ void lm_pass_item(const Job& J, int pos, int tile, int tiles, int nI);
 
 // Work plan of a round (one block), over the jobs with LM still running:
 // plan[j] = first (survivor, tile) item of job j and plan[njobs] = their
 // total; splan = plan + kMaxBatchFrames + 1 likewise numbers the survivors.
-__global__ __launch_bounds__(1024) void k_lm_plan(const Job* __restrict__ jobs, int njobs, int round)
+__global__ __launch_bounds__(1024) void k_lm_plan(const Job* __restrict__ jobs, int njobs, int round, int tpw)
 {
     __shared__ int s_x[1024], s_y[1024];
     int* plan = jobs[0].lm_plan;
@@ -1022,7 +1022,7 @@ __global__ __launch_bounds__(1024) void k_lm_plan(const Job* __restrict__ jobs, 
             const Job& J = jobs[j];
             if (J.lm && !J.st->done) {
                 surv = J.st->n_surv;
-                items = surv * (((round + 1) * J.eta + kLmTile - 1) / kLmTile);
+                items = surv * ((((round + 1) * J.eta + kLmTile - 1) / kLmTile + tpw - 1) / tpw);
             }
         }
         s_x[threadIdx.x] = items;
@@ -1063,14 +1063,18 @@ __device__ __forceinline__ int plan_job(const int* plan, int njobs, int g)
 }
 
 // 1-D grid of waves striding over the plan's items of all jobs, so that a
-// job with many survivors gets as many waves as its items need.  The pass
+// job with many survivors gets as many waves as its items need.  An item is
+// tpw (1 or 2) consecutive tiles of one survivor, whose partials do not
+// depend on tpw (lm_pass_item).  The pass
 // waits on its row loads, so it is held to 128 VGPRs (four waves per SIMD;
 // a few values spill) with two rows in flight: faster than two waves per SIMD
 // with four rows in flight (190 VGPRs), or than three waves (142).
+template <int PAIR>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_lm_pass(
     const Job* __restrict__ jobs, int njobs, int round)
 {
 #pragma clang fp contract(off)
+    constexpr int tpw = PAIR ? 2 : 1;
     const int* plan = jobs[0].lm_plan;
     const int total = plan[njobs];
     // workgroup w runs on XCD w % 8 (gridDim.x is a multiple of 8): XCD e
@@ -1082,15 +1086,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
         const int lo = plan_job(plan, njobs, gi);
         const Job& J = jobs[lo];
         const int nI = (round + 1) * J.eta;
-        const int tiles = (nI + kLmTile - 1) / kLmTile;
+        const int tiles = (nI + kLmTile - 1) / kLmTile, groups = (tiles + tpw - 1) / tpw;
         const int item = gi - plan[lo];
-        if (J.use_cov) lm_pass_item<true>(J, item / tiles, item % tiles, nI);
-        else lm_pass_item<false>(J, item / tiles, item % tiles, nI);
+        const int pos = item / groups, t0 = (item % groups) * tpw;
+        if (J.use_cov) lm_pass_item<true, PAIR>(J, pos, t0, tiles, nI);
+        else lm_pass_item<false, PAIR>(J, pos, t0, tiles, nI);
     }
 }
 
-template <bool COV>
-__device__ __forceinline__ void lm_pass_item(const Job& J, int pos, int tile, int nI)
+// The partial of a tile is the sum over its 64 pixels of the per-pixel
+// terms, pixel l and l + 32 added first, then halves, quarters, ... (the
+// lane xor tree).  With pair = 0 a wave takes one tile, a pixel per lane;
+// with pair = 1 it takes tiles tile and tile + 1, lanes 0-31 and 32-63, each
+// lane adding pixel l and then pixel l + 32 of its tile, which is the tree's
+// first level, so both forms give the same partials bit for bit.
+template <bool COV, int PAIR>
+__device__ __forceinline__ void lm_pass_item(const Job& J, int pos, int tile, int tiles, int nI)
 {
 #pragma clang fp contract(off)
     const int slot = J.surv[pos];
@@ -1100,9 +1111,12 @@ __device__ __forceinline__ void lm_pass_item(const Job& J, int pos, int tile, in
     for (int i = 0; i < 12; ++i) P[i] = S[kLmCand + i];
     double v[kLmVals];
     for (int i = 0; i < kLmVals; ++i) v[i] = 0.0;
-    for (int j = 0; j < kLmTile / 64; ++j) {
-        const int k = tile * kLmTile + j * 64 + (int)threadIdx.x;
-        if (k >= nI) break;
+    const int lane = (int)threadIdx.x;
+    const int my_tile = PAIR ? tile + (lane >> 5) : tile;
+#pragma unroll
+    for (int j = 0; j < (PAIR ? 2 : 1); ++j) {
+        const int k = PAIR ? my_tile * 64 + (lane & 31) + 32 * j : tile * 64 + lane;
+        if (my_tile >= tiles || k >= nI) break;
         const double4 px = ldg(J.lm_px + k);
         const double x[3] = {px.x, px.y, px.z};
         const int nm = (int)px.w;
@@ -1176,11 +1190,12 @@ __device__ __forceinline__ void lm_pass_item(const Job& J, int pos, int tile, in
 #pragma unroll
     for (int i = 0; i < kLmVals; ++i) {
         double x = v[i];
-        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+#pragma unroll
+        for (int o = PAIR ? 16 : 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
         v[i] = x;
     }
-    if (threadIdx.x == 0) {
-        double* out = J.lm_part + ((size_t)pos * J.lm_tiles + tile) * kLmVals;
+    if ((lane & (PAIR ? 31 : 63)) == 0 && my_tile < tiles) {
+        double* out = J.lm_part + ((size_t)pos * J.lm_tiles + my_tile) * kLmVals;
         for (int i = 0; i < kLmVals; ++i) out[i] = v[i];
     }
 }
@@ -1809,13 +1824,19 @@ hipError_t launch_lm(const Job* jobs, int njobs, int round, int maxSurv, int max
     RL_CHECK_LAUNCH();
     k_lm_init<<<thr, dim3(256), 0, st>>>(jobs, round);
     RL_CHECK_LAUNCH();
-    k_lm_plan<<<dim3(1), dim3(1024), 0, st>>>(jobs, njobs, round);
-    RL_CHECK_LAUNCH();
+    // tiles per pass item: one while the round has few (survivor, tile) pairs
+    // (one frame: waves are scarce, and shorter ones finish sooner), two for
+    // many frames (fewer per-item overheads); the results are the same
     const long long tiles = ((round + 1) * (long long)maxEta + kLmTile - 1) / kLmTile;
-    const int waves = (int)(std::min<long long>((long long)maxSurv * tiles * njobs, 8192) + 7) / 8 * 8;
+    const int tpw = (long long)maxSurv * tiles * njobs > 4096 ? 2 : 1;
+    k_lm_plan<<<dim3(1), dim3(1024), 0, st>>>(jobs, njobs, round, tpw);
+    RL_CHECK_LAUNCH();
+    const long long items = (long long)maxSurv * ((tiles + tpw - 1) / tpw) * njobs;
+    const int waves = (int)(std::min<long long>(items, 8192) + 7) / 8 * 8;
     const int step_waves = (int)std::min<long long>((long long)maxSurv * njobs, 1024);
     for (int it = -1; it < maxIters; ++it) {
-        k_lm_pass<<<dim3(waves), dim3(64), 0, st>>>(jobs, njobs, round);
+        if (tpw == 2) k_lm_pass<1><<<dim3(waves), dim3(64), 0, st>>>(jobs, njobs, round);
+        else k_lm_pass<0><<<dim3(waves), dim3(64), 0, st>>>(jobs, njobs, round);
         RL_CHECK_LAUNCH();
         k_lm_step<<<dim3(step_waves), dim3(64), 0, st>>>(jobs, njobs, round, it);
         RL_CHECK_LAUNCH();

@@ -142,6 +142,18 @@ def test_lm_batch_equals_plain(lm_rooms):
             assert a["status"] == b["status"] and a["winner"] == b["winner"] and a["rounds"] == b["rounds"]
             assert np.array_equal(a["pose"], b["pose"]) and a["energy"] == b["energy"]
     batch.close()
+    # 40 LM requests: the batch's passes take two pixel tiles per wave (lane
+    # halves), the plain calls one; the partial sums, and so the results,
+    # are the same
+    many = [(rooms["cov" if i % 2 else "l2"][1], *dev(w.queries[i % 3]), w.queries[i % 3].K, 700 + i)
+            for i in range(40)]
+    want40 = [rm.relocalise(d, c, K, request_seed=s) for (rm, d, c, K, s) in many]
+    big = rl.Batch(64, 160, 120, 64, 100, 8, 1, 5)
+    got = big.relocalise(many, use_graph=True)
+    for a, b in zip(got, want40):
+        assert a["status"] == b["status"] and a["winner"] == b["winner"] and a["rounds"] == b["rounds"]
+        assert np.array_equal(a["pose"], b["pose"]) and a["energy"] == b["energy"]
+    big.close()
     errs = [scene.pose_error(r["pose"].astype(np.float64), w.queries[i % 3].pose)
             for i, r in enumerate(want) if r["status"] == "ok"]
     print(f"[lm batch] pose errors (m, deg) {[(round(a, 3), round(b, 2)) for a, b in errs]}", flush=True)
