@@ -39,8 +39,10 @@ constexpr int kMaxFastWaves = 4;
 constexpr int kTopLevelsMin = 6, kTopLevelsMax = 8;
 
 // LM refinement: pixels per partial-sum tile of a pass (a wave takes one or
-// two tiles), doubles of per-slot state
+// two tiles), doubles per partial (E, g (6), upper triangle of N (21,
+// row-major)), doubles of per-slot state
 constexpr int kLmTile = 64;
+constexpr int kLmVals = 28;
 constexpr int kLmStateDoubles = 56;
 constexpr int kFastStride = 64 * kMaxFastWaves;
 
@@ -130,13 +132,12 @@ struct Job {
     double* E;                // [N] energy per slot
     double* pose64;           // [N][12] LM-refined poses (R row-major, t), FP64
     double* lm_state;         // [N][kLmStateDoubles] LM iteration state per slot
-    double* lm_part;          // [N][lm_tiles][28] LM pass partial sums per (survivor position, tile)
+    double* lm_part;          // [round's survivors][round's tiles][kLmVals] LM pass partial sums per (survivor position, tile)
     int* Ie;                  // [rounds_max * eta] eligible-list entries of I
     int* lm_plan;             // 2 x [kMaxBatchFrames + 1] LM item and survivor plans of the launch (shared by its jobs)
     double4* lm_px;           // [rounds_max * eta] camera point and |M(u)| of each pixel of I
     float4* lm_rows;          // [rows per pixel][rounds_max * eta][3] staged rows of M(u) (mean, Sigma^-1)
     int lm_icap, pad3;        // rounds_max * eta: stride of lm_rows
-    int lm_tiles, pad2;       // tiles of the largest cumulative I
     double* partial;          // [ptiles][N]
     double* partial_all;      // [rounds][ptiles][kFastStride] per-round partials once survivors fit fast_max
     int* I;                   // [rounds_max * eta]

@@ -934,7 +934,6 @@ __global__ __launch_bounds__(kFastStride) void k_select_all(const Job* __restric
 // items and survivors, so their grids do not scale with the batch's
 // survivor bound.  Per round: k_lm_draw, k_lm_init, k_lm_plan, then
 // (iterations + 1) x (k_lm_pass, k_lm_step).
-constexpr int kLmVals = 28;      // E, g (6), upper triangle of N (21, row-major)
 
 // per-slot state (doubles): current pose, candidate pose, N (upper), g, E,
 // lambda, go (the candidate awaits evaluation)
@@ -1195,7 +1194,7 @@ __device__ __forceinline__ void lm_pass_item(const Job& J, int pos, int tile, in
         v[i] = x;
     }
     if ((lane & (PAIR ? 31 : 63)) == 0 && my_tile < tiles) {
-        double* out = J.lm_part + ((size_t)pos * J.lm_tiles + my_tile) * kLmVals;
+        double* out = J.lm_part + ((size_t)pos * tiles + my_tile) * kLmVals;
         for (int i = 0; i < kLmVals; ++i) out[i] = v[i];
     }
 }
@@ -1331,7 +1330,7 @@ __device__ __forceinline__ void lm_step_one(const Job& J, int pos, int round, in
     const bool go = S[kLmGo] != 0.0;
     if (go && threadIdx.x < kLmVals) {
         const int tiles = ((round + 1) * J.eta + kLmTile - 1) / kLmTile;
-        s_v[threadIdx.x] = sum_in_order(J.lm_part + (size_t)pos * J.lm_tiles * kLmVals + threadIdx.x, kLmVals, tiles);
+        s_v[threadIdx.x] = sum_in_order(J.lm_part + (size_t)pos * tiles * kLmVals + threadIdx.x, kLmVals, tiles);
     }
     __syncthreads();
     if (threadIdx.x == 0) lm_decide(J, slot, S, go, it, s_v);

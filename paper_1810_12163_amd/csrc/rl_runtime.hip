@@ -127,7 +127,7 @@ struct FrameLayout {
         partial_all, pose64, lm_state, lm_part, Ie, lm_plan, lm_px, lm_rows,
         I, inl, trace_slots, trace_E, total;
     int ew;
-    int lm_tiles, lm_icap;
+    int lm_icap;
 };
 
 // 64-bit words per eligible-pixel record: |M(u)| and 56 colour-check bits in
@@ -158,9 +158,13 @@ FrameLayout frame_layout(int maxP, int N, int eta, int rounds, int TP, int rows_
     L.surv = c.take((size_t)N * 4);
     L.E = c.take((size_t)N * 8);
     L.pose64 = c.take((size_t)N * 96);
-    L.lm_tiles = (rounds * eta + kLmTile - 1) / kLmTile;
+    // LM partials of round r >= 1: (survivor, tile) pairs, at most N / 2^(r-1)
+    // (rounded up) survivors times the tiles of (r + 1) eta pixels
+    size_t lm_pairs = 0;
+    for (int r = 1, n = N; r < rounds; ++r, n = (n + 1) / 2)
+        lm_pairs = std::max(lm_pairs, (size_t)n * (size_t)(((r + 1) * eta + kLmTile - 1) / kLmTile));
     L.lm_state = c.take((size_t)N * kLmStateDoubles * 8);
-    L.lm_part = c.take((size_t)N * L.lm_tiles * 28 * 8);
+    L.lm_part = c.take(lm_pairs * kLmVals * 8);
     L.Ie = c.take((size_t)rounds * eta * 4);
     L.lm_plan = c.take((size_t)2 * (kMaxBatchFrames + 1) * 4);   // item plan, survivor plan
     L.lm_icap = rounds * eta;
@@ -603,7 +607,6 @@ static Job make_job(const rl_room* r, char* scr, const FrameLayout& FL, const rl
     J.lm_px = reinterpret_cast<double4*>(scr + FL.lm_px);
     J.lm_rows = reinterpret_cast<float4*>(scr + FL.lm_rows);
     J.lm_icap = FL.lm_icap;
-    J.lm_tiles = FL.lm_tiles;
     J.partial = reinterpret_cast<double*>(scr + FL.partial);
     J.partial_all = reinterpret_cast<double*>(scr + FL.partial_all);
     J.I = reinterpret_cast<int*>(scr + FL.I);
