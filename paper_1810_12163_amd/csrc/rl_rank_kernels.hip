@@ -113,11 +113,23 @@ __global__ void k_depth_final(const double* __restrict__ partial, const int* __r
     if (pose >= n_poses) return;
     double acc = 0.0;
     long long nm = 0, nb = 0;
-    for (int t = 0; t < ntiles; ++t) {
-        const size_t o = (size_t)t * kMaxModelPoses + pose;
-        acc += partial[o];
-        nm += cnt[2 * o];
-        nb += cnt[2 * o + 1];
+    for (int t0 = 0; t0 < ntiles; t0 += 16) {         // tiles in order, 16 loaded ahead
+        const int m = min(16, ntiles - t0);
+        double v[16];
+        int a[16], b[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const size_t o = (size_t)(t0 + k) * kMaxModelPoses + pose;
+            v[k] = k < m ? partial[o] : 0.0;
+            a[k] = k < m ? cnt[2 * o] : 0;
+            b[k] = k < m ? cnt[2 * o + 1] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            if (k < m) acc += v[k];
+            nm += a[k];
+            nb += b[k];
+        }
     }
     const double mu = nb > 0 ? acc / (double)nb : NAN;
     out[2 * pose] = (nb > 0 && 10 * nm >= np) ? mu : INFINITY;

@@ -167,6 +167,17 @@ struct ModeWalk {
         while (t < T - 1 && c == 0) c = (int)count_of(nw, ++t);
         base = (((uint32_t)t << D) + leaf_of(lw, t)) * (uint32_t)M;
     }
+    // positioned at mode m of M(u) (m below |M(u)|)
+    __device__ __forceinline__ ModeWalk(const Job& J, uint4 lw_, uint2 nw_, int m)
+        : lw(lw_), nw(nw_), T(J.T), D(J.D), M(J.M), t(0), j(m)
+    {
+        c = (int)count_of(nw, 0);
+        while (j >= c) {
+            j -= c;
+            c = (int)count_of(nw, ++t);
+        }
+        base = (((uint32_t)t << D) + leaf_of(lw, t)) * (uint32_t)M;
+    }
     __device__ __forceinline__ uint32_t row() const { return base + (uint32_t)j; }
     // called only while another mode of M(u) follows
     __device__ __forceinline__ void next()
@@ -955,34 +966,53 @@ __global__ __launch_bounds__(256) void k_lm_draw(const Job* __restrict__ jobs, i
     const int p = (int)c0.x;
     J.Ie[k] = (int)e;
     J.I[k] = p;
-    // the pixel's camera point and its rows of M(u) (mean, Sigma^-1: the
-    // first 48 bytes of each mode row), flattened tree-major, in a
-    // row-major-by-index array the passes read coalesced across pixels
+    // the pixel's camera point and |M(u)|; k_lm_rows stages its rows
     double x[3];
     backproject(__uint_as_float(c0.y), p % J.w, p / J.w, J.fx, J.fy, J.cx, J.cy, x);
+    (void)lw;
+    J.lm_px[k] = make_double4(x[0], x[1], x[2], (double)modes_total(make_uint2(c0.z, c0.w), J.T));
+}
+
+// The rows of M(u) (mean, Sigma^-1: the first 48 bytes of each mode row) of
+// the pixels k_lm_draw added, flattened tree-major into an array indexed
+// [row][pixel of I], which the passes read coalesced across pixels.  Thread
+// (k, g) copies rows 4g .. 4g + 3 of pixel k (grid: pixels / 64, row
+// groups, jobs), so a pixel's rows are copied in parallel and the stores of
+// one row index are contiguous across a wave.
+constexpr int kLmRowsPerThread = 4;
+__global__ __launch_bounds__(64) void k_lm_rows(const Job* __restrict__ jobs, int round)
+{
+    const Job& J = jobs[blockIdx.z];
+    if (!J.lm || J.st->done || J.st->n_elig <= 0) return;
+    const int k = (round == 1 ? 0 : round * J.eta) + (int)(blockIdx.x * 64 + threadIdx.x);
+    if (k >= (round + 1) * J.eta) return;
+    const int e = J.Ie[k];
+    const uint4 c0 = ldg(J.ecold + 2 * e), lw = ldg(J.ecold + 2 * e + 1);
     const uint2 nw = make_uint2(c0.z, c0.w);
-    const int total = modes_total(nw, J.T);
-    ModeWalk mw(J, lw, nw);
-    for (int m0 = 0; m0 < total; m0 += 4) {           // four rows loaded ahead of their stores
-        float4 r[4][3];
+    const int m0 = (int)blockIdx.y * kLmRowsPerThread, total = modes_total(nw, J.T);
+    if (m0 >= total) return;
+    const int n = min(kLmRowsPerThread, total - m0);
+    ModeWalk mw(J, lw, nw, m0);
+    float4 r[kLmRowsPerThread][3];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kLmRowsPerThread; ++u) {
+        if (u < n) {
             const float4* row = J.modes + (size_t)mw.row() * 4;
             r[u][0] = ldg(row);
             r[u][1] = ldg(row + 1);
             r[u][2] = ldg(row + 2);
-            if (m0 + u + 1 < total) mw.next();
+            if (u + 1 < n) mw.next();
         }
+    }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (m0 + u >= total) break;
+    for (int u = 0; u < kLmRowsPerThread; ++u) {
+        if (u < n) {
             float4* dst = J.lm_rows + ((size_t)(m0 + u) * J.lm_icap + k) * 3;
             dst[0] = r[u][0];
             dst[1] = r[u][1];
             dst[2] = r[u][2];
         }
     }
-    J.lm_px[k] = make_double4(x[0], x[1], x[2], (double)total);
 }
 
 __global__ __launch_bounds__(256) void k_lm_init(const Job* __restrict__ jobs, int round)
@@ -1713,9 +1743,20 @@ __global__ void k_plane_final(const double* __restrict__ partial, const int* __r
     if (pose >= n_poses) return;
     double acc = 0.0;
     long long c = 0;
-    for (int tI = 0; tI < ntiles; ++tI) {
-        acc += partial[(size_t)tI * 64 + pose];
-        c += cnt[tI];
+    for (int t0 = 0; t0 < ntiles; t0 += 16) {         // tiles in order, 16 loaded ahead
+        const int m = min(16, ntiles - t0);
+        double v[16];
+        int n[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            v[k] = k < m ? partial[(size_t)(t0 + k) * 64 + pose] : 0.0;
+            n[k] = k < m ? cnt[t0 + k] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            if (k < m) acc += v[k];
+            c += n[k];
+        }
     }
     scores[pose] = c > 0 ? acc / (double)c : INFINITY;
 }
@@ -1815,11 +1856,15 @@ hipError_t launch_score(const Job* jobs, int njobs, int round, int nptiles, int 
     return hipSuccess;
 }
 
-hipError_t launch_lm(const Job* jobs, int njobs, int round, int maxSurv, int maxEta, int maxIters, hipStream_t st)
+hipError_t launch_lm(const Job* jobs, int njobs, int round, int maxSurv, int maxEta, int maxRows, int maxIters,
+                     hipStream_t st)
 {
     if (maxSurv < 1) return hipSuccess;
     const dim3 thr((maxSurv + 255) / 256, njobs);
     k_lm_draw<<<dim3((2 * maxEta + 255) / 256, njobs), dim3(256), 0, st>>>(jobs, round);
+    RL_CHECK_LAUNCH();
+    k_lm_rows<<<dim3((2 * maxEta + 63) / 64, (maxRows + kLmRowsPerThread - 1) / kLmRowsPerThread, njobs), dim3(64),
+                0, st>>>(jobs, round);
     RL_CHECK_LAUNCH();
     k_lm_init<<<thr, dim3(256), 0, st>>>(jobs, round);
     RL_CHECK_LAUNCH();

@@ -30,7 +30,8 @@ hipError_t launch_hyp_finalize(const Job* jobs, int njobs, int maxN, hipStream_t
 hipError_t launch_score(const Job* jobs, int njobs, int round, int nptiles, int maxSurv,
                         hipStream_t st);
 hipError_t launch_score_all(const Job* jobs, int njobs, int rounds, int nptiles, int fw, int window, hipStream_t st);
-hipError_t launch_lm(const Job* jobs, int njobs, int round, int maxSurv, int maxEta, int maxIters, hipStream_t st);
+hipError_t launch_lm(const Job* jobs, int njobs, int round, int maxSurv, int maxEta, int maxRows, int maxIters,
+                     hipStream_t st);
 hipError_t launch_select(const Job* jobs, int njobs, int round, int nptiles, int maxN, hipStream_t st);
 hipError_t launch_finalize(const Job* jobs, int njobs, int maxIlen, hipStream_t st);
 hipError_t launch_depth_scores(const FrameView& src, int w, int h, float fx, float fy, float cx, float cy,
@@ -1160,7 +1161,7 @@ RL_API rl_status rl_batch_set_degeneracy_screen(rl_batch* b, int32_t on)
 }
 
 static hipError_t launch_sequence(const Job* jobs, int njobs, int maxP, int maxN, int maxIters, int T,
-                                  const std::vector<int>& entering, int nptiles, int maxEta, bool any_lm,
+                                  const std::vector<int>& entering, int nptiles, int maxEta, int maxRows, bool any_lm,
                                   int lm_iters, const Schedule& sc, const Timer& tm, hipStream_t st)
 {
     hipError_t e;
@@ -1181,7 +1182,7 @@ static hipError_t launch_sequence(const Job* jobs, int njobs, int maxP, int maxN
     // rounds one at a time
     for (int r = 0; r < (int)entering.size() && (any_lm || entering[r] > 64 * sc.fw); ++r) {
         RL_TRY(launch_score(jobs, njobs, r, nptiles, entering[r], st));
-        if (any_lm && r > 0) RL_TRY(launch_lm(jobs, njobs, r, entering[r], maxEta, lm_iters, st));
+        if (any_lm && r > 0) RL_TRY(launch_lm(jobs, njobs, r, entering[r], maxEta, maxRows, lm_iters, st));
         RL_TRY(launch_select(jobs, njobs, r, nptiles, maxN, st));
     }
     RL_TRY(launch_score_all(jobs, njobs, (int)entering.size(), nptiles, sc.fw, sc.win, st));
@@ -1267,8 +1268,8 @@ RL_API rl_status relocaliser_relocalise_opts(rl_room* r, const rl_frame* f, uint
     std::vector<long long> key = {P, N, r->sched.ipt, r->sched.fw, r->sched.top, r->sched.win, lm, r->p.lm_iterations, iters, eta};
     for (int v : entering) key.push_back(v);
     e = run_sequence(r->graphs, key, r->timer.kernel == RL_TIMER_NONE, r->stream, [&]() {
-        return launch_sequence(jd, 1, P, N, iters, r->T, entering, nptiles, eta, lm != 0, r->p.lm_iterations,
-                               r->sched, r->timer, r->stream);
+        return launch_sequence(jd, 1, P, N, iters, r->T, entering, nptiles, eta, r->T * r->M, lm != 0,
+                               r->p.lm_iterations, r->sched, r->timer, r->stream);
     });
     if (e != hipSuccess) return hip_fail(e, "relocalise launch");
     e = hipMemcpyAsync(r->res_host, r->scr + r->FL.result, sizeof(rl_result), hipMemcpyDeviceToHost, r->stream);
@@ -1737,8 +1738,8 @@ static rl_status batch_relocalise_queue(rl_batch* b, const rl_request* reqs, con
                                   b->sched.win, any_lm ? 1 : 0, lm_iters};
     for (int v : entering) key.push_back(v);
     e = run_sequence(b->graphs, key, use_graph && b->timer.kernel == RL_TIMER_NONE, b->stream, [&]() {
-        return launch_sequence(jd, nq, maxP, maxN, maxIters, b->bp.n_trees, entering, nptiles, maxEta, any_lm,
-                               lm_iters, b->sched, b->timer, b->stream);
+        return launch_sequence(jd, nq, maxP, maxN, maxIters, b->bp.n_trees, entering, nptiles, maxEta, b->rows,
+                               any_lm, lm_iters, b->sched, b->timer, b->stream);
     });
     if (e != hipSuccess) return hip_fail(e, "batch launch");
     // the next mode update of each room waits for this batch
