@@ -1125,10 +1125,45 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 
 // The partial of a tile is the sum over its 64 pixels of the per-pixel
 // terms, pixel l and l + 32 added first, then halves, quarters, ... (the
-// lane xor tree).  With pair = 0 a wave takes one tile, a pixel per lane;
+// lane xor tree, lane_tree_sums).  With pair = 0 a wave takes one tile, a pixel per lane;
 // with pair = 1 it takes tiles tile and tile + 1, lanes 0-31 and 32-63, each
 // lane adding pixel l and then pixel l + 32 of its tile, which is the tree's
 // first level, so both forms give the same partials bit for bit.
+// One level of a lane tree over H pairs of values: a lane whose bit O is
+// clear keeps values 0..H-1 and hands H..2H-1 to lane ^ O, which keeps
+// those; each kept value becomes its own copy plus the partner's.
+template <int H, int O>
+__device__ __forceinline__ void tree_level(double* w, int lane)
+{
+    const bool hi = (lane & O) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        const double send = hi ? w[i] : w[H + i];
+        const double keep = hi ? w[H + i] : w[i];
+        w[i] = keep + __shfl_xor(send, O);
+    }
+}
+
+// Sums of v[0..27] over the lane xor tree o = O0, O0 / 2, ..., 1 (O0 = 16:
+// each lane half on its own; 32: the whole wave).  Every sum adds the same
+// two operands at every level as a butterfly that adds all values at every
+// level, so the sums are the same bits; a level here halves the values a
+// lane carries.  Lane l ends with sum (l & 31) (O0 = 16) or ((l >> 1) & 31)
+// (O0 = 32; lanes l and l ^ 1 alike); sums 28..31 are padding.
+template <int O0>
+__device__ __forceinline__ double lane_tree_sums(const double* v, int lane)
+{
+    double w[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) w[i] = i < kLmVals ? v[i] : 0.0;
+    tree_level<16, O0>(w, lane);
+    tree_level<8, O0 / 2>(w, lane);
+    tree_level<4, O0 / 4>(w, lane);
+    tree_level<2, O0 / 8>(w, lane);
+    tree_level<1, O0 / 16>(w, lane);
+    return O0 == 32 ? w[0] + __shfl_xor(w[0], 1) : w[0];
+}
+
 template <bool COV, int PAIR>
 __device__ __forceinline__ void lm_pass_item(const Job& J, int pos, int tile, int tiles, int nI)
 {
@@ -1216,17 +1251,10 @@ __device__ __forceinline__ void lm_pass_item(const Job& J, int pos, int tile, in
                 v[o++] += wgt * (Jm[i] * AJ[jj] + Jm[6 + i] * AJ[6 + jj] + Jm[12 + i] * AJ[12 + jj]);
         }
     }
-#pragma unroll
-    for (int i = 0; i < kLmVals; ++i) {
-        double x = v[i];
-#pragma unroll
-        for (int o = PAIR ? 16 : 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-        v[i] = x;
-    }
-    if ((lane & (PAIR ? 31 : 63)) == 0 && my_tile < tiles) {
-        double* out = J.lm_part + ((size_t)pos * tiles + my_tile) * kLmVals;
-        for (int i = 0; i < kLmVals; ++i) out[i] = v[i];
-    }
+    const double sum = lane_tree_sums<PAIR ? 16 : 32>(v, lane);
+    const int idx = PAIR ? (lane & 31) : ((lane >> 1) & 31);
+    if (idx < kLmVals && (PAIR || (lane & 1) == 0) && my_tile < tiles)
+        J.lm_part[((size_t)pos * tiles + my_tile) * kLmVals + idx] = sum;
 }
 
 // M d = b for a symmetric positive definite 6x6 M; false on a pivot that is
