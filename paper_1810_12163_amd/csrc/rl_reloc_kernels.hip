@@ -1188,9 +1188,11 @@ __device__ __forceinline__ void lm_pass_item(const Job& J, int pos, int tile, in
         const double y1 = P[3] * x[0] + P[4] * x[1] + P[5] * x[2] + P[10];
         const double y2 = P[6] * x[0] + P[7] * x[1] + P[8] * x[2] + P[11];
         // nearest mode (ties to the lower index) over the staged rows, two at
-        // a time; the best row stays in registers
+        // a time.  With two tiles per wave (many waves in flight) the best
+        // row is kept in registers; with one (few waves, whose added load
+        // latency costs less than the copies) it is loaded again after the scan.
         double best = INFINITY;
-        bool found = false;
+        int bj = -1;
         float4 ba = make_float4(0.f, 0.f, 0.f, 0.f), bb = ba, bc = ba;
         for (int j0 = 0; j0 < nm; j0 += 2) {
             float4 ra[2], rb[2], rc[2];
@@ -1213,16 +1215,24 @@ __device__ __forceinline__ void lm_pass_item(const Job& J, int pos, int tile, in
                 qq = qq < 0.0 ? 0.0 : qq;
                 if (qq < best) {
                     best = qq;
-                    found = true;
-                    ba = ra[u];
-                    bb = rb[u];
-                    bc = rc[u];
+                    bj = j0 + u;
+                    if (PAIR) {
+                        ba = ra[u];
+                        bb = rb[u];
+                        bc = rc[u];
+                    }
                 }
             }
         }
         const double en = sqrt(best);
         v[0] += en;
-        if (!found) continue;
+        if (bj < 0) continue;
+        if (!PAIR) {
+            const float4* brow = J.lm_rows + ((size_t)bj * J.lm_icap + k) * 3;
+            ba = ldg(brow);
+            bb = COV ? ldg(brow + 1) : ba;
+            bc = COV ? ldg(brow + 2) : ba;
+        }
         const double r0 = y0 - (double)ba.x, r1 = y1 - (double)ba.y, r2 = y2 - (double)ba.z;
         double A[9] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0};
         if (COV) {
