@@ -36,9 +36,9 @@ MI355X_HBM = 8.0e12
 HYP_ITER_OPS = 150
 # Traversal: the compulsory HBM bytes of a pixel are its depth and colour
 # read once (8 B) and its leaf index per tree written (2 B each); the bytes a
-# node test gathers (16 B node + 8 B probe word) come from the caches and are
+# node test gathers (16 B node + 4 B probe word) come from the caches and are
 # reported beside it, not as an HBM fraction.
-NODE_TEST_BYTES = 24
+NODE_TEST_BYTES = 20
 TRAVERSE_PIXEL_IN = 8
 # FP64 flops of Eq. 5 scoring: per mode evaluation d = y - mu (3), Sigma^-1 d
 # (9 mul + 6 add), d . (Sigma^-1 d) (3 mul + 2 add) and the running minimum (1);

@@ -104,7 +104,7 @@ struct Job {
     int screen;               // 1: the search rejects clearly degenerate triplets itself
     // frame
     FrameView src;            // the caller's buffers (read by the ingest only)
-    uint2* probe;             // [P] interleaved probe image (depth bits, RGB bytes), built per frame
+    uint32_t* probe;          // [2][P] probe image planes (depth bits; R, G, B bytes), built per frame
     int w, h;
     float fx, fy, cx, cy;
     float s;                  // w / ref_width (float32 division)
@@ -294,9 +294,10 @@ __device__ __forceinline__ void backproject(float d, int x, int y, float fx, flo
 // Float32 definition: offset = rint(delta * s * (1/d)), probe clamped to the
 // image, f = D(p) - D(q) or C(p,c) - C(q,c), right child iff f >= tau.
 // Probe reads of the routing: from the caller's planar depth and RGB8, or
-// from the interleaved probe image (one 8-byte word per pixel: depth bits,
-// then R, G, B bytes) that a relocalisation builds first, so that a probe is
-// one load with no branch on the feature kind.  Both give the same values.
+// from the probe image that a relocalisation builds first (two planes of
+// 4-byte words: depth bits; R, G, B bytes), so that a probe is one 4-byte
+// load, its plane picked by the feature kind without a branch.  Both give
+// the same values.
 struct PlanarProbe {
     FrameView f;
     typedef float Centre[3];
@@ -308,7 +309,7 @@ struct PlanarProbe {
         cc[2] = (float)ldg(c + 2);
     }
     typedef float2 Word;
-    __device__ __forceinline__ Word load(int qx, int qy, uint32_t c) const
+    __device__ __forceinline__ Word load(int qx, int qy, uint32_t c, bool) const
     {
         return make_float2(f.d(qx, qy), (float)ldg(f.c(qx, qy) + c));
     }
@@ -321,28 +322,28 @@ struct PlanarProbe {
 };
 
 struct PackedProbe {
-    const uint2* img;
-    uint32_t w;
+    const uint32_t* img;      // [2][P]: depth bits, then R | G << 8 | B << 16
+    uint32_t w, P;
     typedef uint32_t Centre[1];
     __device__ __forceinline__ void centre(int x, int y, Centre cw) const
     {
-        cw[0] = ldg(img + (uint32_t)y * w + (uint32_t)x).y;
+        cw[0] = ldg(img + P + (uint32_t)y * w + (uint32_t)x);
     }
-    typedef uint2 Word;
+    typedef uint32_t Word;
     // 32-bit byte offset from the image base (below 2^27 bytes; w * h < 2^24)
-    __device__ __forceinline__ Word load(int qx, int qy, uint32_t) const
+    __device__ __forceinline__ Word load(int qx, int qy, uint32_t, bool is_depth) const
     {
-        const int q = (int)__umul24((uint32_t)qy, w) + qx;
-        return ldg(reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(img) + (uint32_t)q * 8u));
+        const uint32_t q = __umul24((uint32_t)qy, w) + (uint32_t)qx + (is_depth ? 0u : P);
+        return ldg(reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(img) + q * 4u));
     }
     // colour bytes are subtracted as integers: the difference of two bytes
     // converts to the same float as the difference of their conversions
     __device__ __forceinline__ float feature(Word v, bool is_depth, uint32_t c, float d, const Centre cw) const
     {
         const int ci = (int)__builtin_amdgcn_ubfe(cw[0], 8u * c, 8u);
-        const int qi = (int)__builtin_amdgcn_ubfe(v.y, 8u * c, 8u);
+        const int qi = (int)__builtin_amdgcn_ubfe(v, 8u * c, 8u);
         const float fc = (float)(ci - qi);
-        const float fd = d - __uint_as_float(v.x);
+        const float fd = d - __uint_as_float(v);
         // both features are computed; a bit select picks one without a branch
         const uint32_t m = is_depth ? 0xFFFFFFFFu : 0u;
         return __uint_as_float((__float_as_uint(fd) & m) | (__float_as_uint(fc) & ~m));
@@ -383,8 +384,10 @@ __device__ __forceinline__ void route(const float4* __restrict__ nodes, int NT, 
         // every tree's probe is issued before any is used
         typename Probe::Word pv[T];
         uint32_t ch[T];
+        bool dk[T];
 #pragma unroll
         for (int t = 0; t < T; ++t) {
+            dk[t] = __float_as_uint(nd[t].w) == 0u;
             float fox = rintf((UNIT ? nd[t].x : nd[t].x * s) * inv);
             float foy = rintf((UNIT ? nd[t].y : nd[t].y * s) * inv);
             fox = fminf(fmaxf(fox, lox), hix);
@@ -392,11 +395,11 @@ __device__ __forceinline__ void route(const float4* __restrict__ nodes, int NT, 
             // kinds are validated at creation (<= 3); the clamp keeps the
             // colour read inside the pixel whatever the device memory holds
             ch[t] = min(__float_as_uint(nd[t].w) - 1u, 2u);
-            pv[t] = pr.load(x + (int)fox, y + (int)foy, ch[t]);
+            pv[t] = pr.load(x + (int)fox, y + (int)foy, ch[t], dk[t]);
         }
 #pragma unroll
         for (int t = 0; t < T; ++t) {
-            const float f = pr.feature(pv[t], __float_as_uint(nd[t].w) == 0u, ch[t], d, cen);
+            const float f = pr.feature(pv[t], dk[t], ch[t], d, cen);
             idx[t] = 2 * idx[t] + 1 + (f >= nd[t].z ? 1 : 0);
         }
     }

@@ -59,8 +59,8 @@ __global__ __launch_bounds__(256) void k_prep(const Job* __restrict__ jobs)
 }
 
 // ------------------------------------------------------------------------
-// Frame ingest: the interleaved probe image (depth bits, R, G, B bytes) that
-// routing reads, one pass over the caller's buffers (any row pitch, RGB or
+// Frame ingest: the probe image (a plane of depth bits, a plane of R, G, B
+// bytes) that routing reads, one pass over the caller's buffers (any row pitch, RGB or
 // RGBA, every pixel or every second one); every later read of the frame is a
 // read of this image.
 __global__ __launch_bounds__(256) void k_pack(const Job* __restrict__ jobs)
@@ -72,7 +72,8 @@ __global__ __launch_bounds__(256) void k_pack(const Job* __restrict__ jobs)
     const int x = p % J.w, y = p / J.w;
     const uint8_t* c = J.src.c(x, y);
     const uint32_t r = ldg(c), g = ldg(c + 1), b = ldg(c + 2);
-    J.probe[p] = make_uint2(__float_as_uint(J.src.d(x, y)), r | (g << 8) | (b << 16));
+    J.probe[p] = __float_as_uint(J.src.d(x, y));
+    J.probe[P + p] = r | (g << 8) | (b << 16);
 }
 
 // ------------------------------------------------------------------------
@@ -110,7 +111,7 @@ __global__ __launch_bounds__(256) void k_traverse(const Job* __restrict__ jobs)
     bool elig = false;
     if (p < P) {
         const int x = p % w, y = p / w;
-        const float d = __uint_as_float(ldg(J.probe + p).x);
+        const float d = __uint_as_float(ldg(J.probe + p));
         uint16_t lf[8];
         uint8_t nmt[8];
 #pragma unroll
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(256) void k_traverse(const Job* __restrict__ jobs)
         if (depth_ok(d)) {
             const int NT = (1 << J.D) - 1;
             int leaf[T];
-            const PackedProbe pr{J.probe, (uint32_t)w};
+            const PackedProbe pr{J.probe, (uint32_t)w, (uint32_t)P};
             if (J.s == 1.0f) route<T, true>(J.nodes, NT, J.D, pr, w, h, x, y, d, J.s, leaf, s_top, ktop);
             else route<T, false>(J.nodes, NT, J.D, pr, w, h, x, y, d, J.s, leaf, s_top, ktop);
 #pragma unroll
@@ -307,11 +308,11 @@ __global__ __launch_bounds__(256) void k_eligible(const Job* __restrict__ jobs)
         J.eligible[k] = p;
         const uint4 lw = ldg(reinterpret_cast<const uint4*>(J.leaves) + p);
         const uint2 nw = ldg(reinterpret_cast<const uint2*>(J.nmt) + p);
-        const uint2 pv = ldg(J.probe + p);
-        J.ecold[2 * k] = make_uint4((uint32_t)p, pv.x, nw.x, nw.y);
+        const uint32_t pd = ldg(J.probe + p), pc = ldg(J.probe + P + p);
+        J.ecold[2 * k] = make_uint4((uint32_t)p, pd, nw.x, nw.y);
         J.ecold[2 * k + 1] = lw;
-        if (J.ew == 1) write_erec_w0<T>(J, k, lw, nw, pv.y);
-        else write_erec(J, k, lw, nw, pv.y);
+        if (J.ew == 1) write_erec_w0<T>(J, k, lw, nw, pc);
+        else write_erec(J, k, lw, nw, pc);
     }
 }
 
@@ -1490,7 +1491,7 @@ __global__ __launch_bounds__(256) void k_refit_assign(const Job* __restrict__ jo
     for (int i = 0; i < 3; ++i) t[i] = hy.t[i];
     const int p = J.I[k];
     double x[3];
-    backproject(__uint_as_float(J.probe[p].x), p % J.w, p / J.w, J.fx, J.fy, J.cx, J.cy, x);
+    backproject(__uint_as_float(J.probe[p]), p % J.w, p / J.w, J.fx, J.fy, J.cx, J.cy, x);
     const double y0 = R[0] * x[0] + R[1] * x[1] + R[2] * x[2] + t[0];
     const double y1 = R[3] * x[0] + R[4] * x[1] + R[5] * x[2] + t[1];
     const double y2 = R[6] * x[0] + R[7] * x[1] + R[8] * x[2] + t[2];
@@ -1587,7 +1588,7 @@ __device__ __forceinline__ void inlier_chunk(const Job& J, int k, int nI, bool o
 #pragma unroll
     for (int u = 0; u < kFinChunk; ++u) {
         ok[u] = ri[u] >= 0;
-        d[u] = ok[u] ? __uint_as_float(J.probe[p[u]].x) : 0.0f;
+        d[u] = ok[u] ? __uint_as_float(J.probe[p[u]]) : 0.0f;
         a[u] = ok[u] ? J.modes[(size_t)ri[u] * 4] : make_float4(0.f, 0.f, 0.f, 0.f);
     }
 #pragma unroll

@@ -145,7 +145,7 @@ FrameLayout frame_layout(int maxP, int N, int eta, int rounds, int TP, int rows_
     FrameLayout L;
     L.state = c.take(sizeof(JobState));
     L.result = c.take(sizeof(rl_result));
-    L.probe = c.take((size_t)maxP * 8);
+    L.probe = c.take((size_t)maxP * 8);                  // two planes of w h words
     L.leaves = c.take((size_t)maxP * 16);
     L.nmt = c.take((size_t)maxP * 8);
     L.nm = c.take((size_t)maxP);
@@ -587,7 +587,7 @@ static Job make_job(const rl_room* r, char* scr, const FrameLayout& FL, const rl
     const uint64_t k = stream_key64(r->p.seed, request_seed);
     J.key0 = (uint32_t)k;
     J.key1 = (uint32_t)(k >> 32);
-    J.probe = reinterpret_cast<uint2*>(scr + FL.probe);
+    J.probe = reinterpret_cast<uint32_t*>(scr + FL.probe);
     J.leaves = reinterpret_cast<uint16_t*>(scr + FL.leaves);
     J.nmt = reinterpret_cast<uint8_t*>(scr + FL.nmt);
     J.nm = reinterpret_cast<uint8_t*>(scr + FL.nm);
