@@ -136,8 +136,9 @@ struct Job {
     int* Ie;                  // [rounds_max * eta] eligible-list entries of I
     int* lm_plan;             // 2 x [kMaxBatchFrames + 1] LM item and survivor plans of the launch (shared by its jobs)
     double4* lm_px;           // [rounds_max * eta] camera point and |M(u)| of each pixel of I
-    float4* lm_rows;          // [rows per pixel][rounds_max * eta][3] staged rows of M(u) (mean, Sigma^-1)
-    int lm_icap, pad3;        // rounds_max * eta: stride of lm_rows
+    float4* lm_rows;          // [rows per pixel][3 x rounds_max * eta] staged rows of M(u) (mean, Sigma^-1), lm_split below
+    int lm_icap;              // rounds_max * eta
+    int lm_split;             // 1: lm_rows [row][16-byte part][pixel of I]; 0: [row][pixel of I][16-byte part]
     double* partial;          // [ptiles][N]
     double* partial_all;      // [rounds][ptiles][kFastStride] per-round partials once survivors fit fast_max
     int* I;                   // [rounds_max * eta]

@@ -976,7 +976,10 @@ __global__ __launch_bounds__(256) void k_lm_draw(const Job* __restrict__ jobs, i
 
 // The rows of M(u) (mean, Sigma^-1: the first 48 bytes of each mode row) of
 // the pixels k_lm_draw added, flattened tree-major into an array indexed
-// [row][pixel of I], which the passes read coalesced across pixels.  Thread
+// [row][16-byte part][pixel of I] (lm_split: each 16-byte load of a pass
+// reads consecutive addresses across a wave's pixels; faster for one frame)
+// or [row][pixel of I][16-byte part] (a row's three loads share cache lines;
+// faster for many frames).  The results do not depend on it.  Thread
 // (k, g) copies rows 4g .. 4g + 3 of pixel k (grid: pixels / 64, row
 // groups, jobs), so a pixel's rows are copied in parallel and the stores of
 // one row index are contiguous across a wave.
@@ -993,6 +996,7 @@ __global__ __launch_bounds__(64) void k_lm_rows(const Job* __restrict__ jobs, in
     const int m0 = (int)blockIdx.y * kLmRowsPerThread, total = modes_total(nw, J.T);
     if (m0 >= total) return;
     const int n = min(kLmRowsPerThread, total - m0);
+    const int ks = J.lm_split ? 1 : 3, ps = J.lm_split ? J.lm_icap : 1;
     ModeWalk mw(J, lw, nw, m0);
     float4 r[kLmRowsPerThread][3];
 #pragma unroll
@@ -1008,10 +1012,10 @@ __global__ __launch_bounds__(64) void k_lm_rows(const Job* __restrict__ jobs, in
 #pragma unroll
     for (int u = 0; u < kLmRowsPerThread; ++u) {
         if (u < n) {
-            float4* dst = J.lm_rows + ((size_t)(m0 + u) * J.lm_icap + k) * 3;
+            float4* dst = J.lm_rows + (size_t)(m0 + u) * 3 * J.lm_icap + (size_t)k * ks;
             dst[0] = r[u][0];
-            dst[1] = r[u][1];
-            dst[2] = r[u][2];
+            dst[ps] = r[u][1];
+            dst[2 * ps] = r[u][2];
         }
     }
 }
@@ -1033,7 +1037,7 @@ __global__ __launch_bounds__(256) void k_lm_init(const Job* __restrict__ jobs, i
     S[kLmGo] = 1.0;
 }
 
-template <bool COV, int PAIR>
+template <bool COV, int PAIR, bool SPLIT>
 __device__ __forceinline__ void lm_pass_item(const Job& J, int pos, int tile, int tiles, int nI);
 
 // Work plan of a round (one block), over the jobs with LM still running:
@@ -1099,7 +1103,7 @@ __device__ __forceinline__ int plan_job(const int* plan, int njobs, int g)
 // waits on its row loads, so it is held to 128 VGPRs (four waves per SIMD;
 // a few values spill) with two rows in flight: faster than two waves per SIMD
 // with four rows in flight (190 VGPRs), or than three waves (142).
-template <int PAIR>
+template <int PAIR, bool SPLIT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_lm_pass(
     const Job* __restrict__ jobs, int njobs, int round)
 {
@@ -1119,8 +1123,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
         const int tiles = (nI + kLmTile - 1) / kLmTile, groups = (tiles + tpw - 1) / tpw;
         const int item = gi - plan[lo];
         const int pos = item / groups, t0 = (item % groups) * tpw;
-        if (J.use_cov) lm_pass_item<true, PAIR>(J, pos, t0, tiles, nI);
-        else lm_pass_item<false, PAIR>(J, pos, t0, tiles, nI);
+        if (J.use_cov) lm_pass_item<true, PAIR, SPLIT>(J, pos, t0, tiles, nI);
+        else lm_pass_item<false, PAIR, SPLIT>(J, pos, t0, tiles, nI);
     }
 }
 
@@ -1165,7 +1169,7 @@ __device__ __forceinline__ double lane_tree_sums(const double* v, int lane)
     return O0 == 32 ? w[0] + __shfl_xor(w[0], 1) : w[0];
 }
 
-template <bool COV, int PAIR>
+template <bool COV, int PAIR, bool SPLIT>
 __device__ __forceinline__ void lm_pass_item(const Job& J, int pos, int tile, int tiles, int nI)
 {
 #pragma clang fp contract(off)
@@ -1178,6 +1182,7 @@ __device__ __forceinline__ void lm_pass_item(const Job& J, int pos, int tile, in
     for (int i = 0; i < kLmVals; ++i) v[i] = 0.0;
     const int lane = (int)threadIdx.x;
     const int my_tile = PAIR ? tile + (lane >> 5) : tile;
+    const int ks = SPLIT ? 1 : 3, ps = SPLIT ? J.lm_icap : 1;   // lm_rows strides (SPLIT = J.lm_split)
 #pragma unroll
     for (int j = 0; j < (PAIR ? 2 : 1); ++j) {
         const int k = PAIR ? my_tile * 64 + (lane & 31) + 32 * j : tile * 64 + lane;
@@ -1200,11 +1205,11 @@ __device__ __forceinline__ void lm_pass_item(const Job& J, int pos, int tile, in
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 const int j = min(j0 + u, nm - 1);
-                const float4* row = J.lm_rows + ((size_t)j * J.lm_icap + k) * 3;
+                const float4* row = J.lm_rows + (size_t)j * 3 * J.lm_icap + (size_t)k * ks;
                 ra[u] = ldg(row);
                 if (COV) {
-                    rb[u] = ldg(row + 1);
-                    rc[u] = ldg(row + 2);
+                    rb[u] = ldg(row + ps);
+                    rc[u] = ldg(row + 2 * ps);
                 } else {
                     rb[u] = rc[u] = ra[u];
                 }
@@ -1229,10 +1234,10 @@ __device__ __forceinline__ void lm_pass_item(const Job& J, int pos, int tile, in
         v[0] += en;
         if (bj < 0) continue;
         if (!PAIR) {
-            const float4* brow = J.lm_rows + ((size_t)bj * J.lm_icap + k) * 3;
+            const float4* brow = J.lm_rows + (size_t)bj * 3 * J.lm_icap + (size_t)k * ks;
             ba = ldg(brow);
-            bb = COV ? ldg(brow + 1) : ba;
-            bc = COV ? ldg(brow + 2) : ba;
+            bb = COV ? ldg(brow + ps) : ba;
+            bc = COV ? ldg(brow + 2 * ps) : ba;
         }
         const double r0 = y0 - (double)ba.x, r1 = y1 - (double)ba.y, r2 = y2 - (double)ba.z;
         double A[9] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0};
@@ -1896,7 +1901,7 @@ hipError_t launch_score(const Job* jobs, int njobs, int round, int nptiles, int 
 }
 
 hipError_t launch_lm(const Job* jobs, int njobs, int round, int maxSurv, int maxEta, int maxRows, int maxIters,
-                     hipStream_t st)
+                     bool split, hipStream_t st)
 {
     if (maxSurv < 1) return hipSuccess;
     const dim3 thr((maxSurv + 255) / 256, njobs);
@@ -1918,8 +1923,13 @@ hipError_t launch_lm(const Job* jobs, int njobs, int round, int maxSurv, int max
     const int waves = (int)(std::min<long long>(items, 8192) + 7) / 8 * 8;
     const int step_waves = (int)std::min<long long>((long long)maxSurv * njobs, 1024);
     for (int it = -1; it < maxIters; ++it) {
-        if (tpw == 2) k_lm_pass<1><<<dim3(waves), dim3(64), 0, st>>>(jobs, njobs, round);
-        else k_lm_pass<0><<<dim3(waves), dim3(64), 0, st>>>(jobs, njobs, round);
+        if (split) {
+            if (tpw == 2) k_lm_pass<1, true><<<dim3(waves), dim3(64), 0, st>>>(jobs, njobs, round);
+            else k_lm_pass<0, true><<<dim3(waves), dim3(64), 0, st>>>(jobs, njobs, round);
+        } else {
+            if (tpw == 2) k_lm_pass<1, false><<<dim3(waves), dim3(64), 0, st>>>(jobs, njobs, round);
+            else k_lm_pass<0, false><<<dim3(waves), dim3(64), 0, st>>>(jobs, njobs, round);
+        }
         RL_CHECK_LAUNCH();
         k_lm_step<<<dim3(step_waves), dim3(64), 0, st>>>(jobs, njobs, round, it);
         RL_CHECK_LAUNCH();

@@ -31,7 +31,7 @@ hipError_t launch_score(const Job* jobs, int njobs, int round, int nptiles, int 
                         hipStream_t st);
 hipError_t launch_score_all(const Job* jobs, int njobs, int rounds, int nptiles, int fw, int window, hipStream_t st);
 hipError_t launch_lm(const Job* jobs, int njobs, int round, int maxSurv, int maxEta, int maxRows, int maxIters,
-                     hipStream_t st);
+                     bool split, hipStream_t st);
 hipError_t launch_select(const Job* jobs, int njobs, int round, int nptiles, int maxN, hipStream_t st);
 hipError_t launch_finalize(const Job* jobs, int njobs, int maxIlen, hipStream_t st);
 hipError_t launch_depth_scores(const FrameView& src, int w, int h, float fx, float fy, float cx, float cy,
@@ -608,6 +608,7 @@ static Job make_job(const rl_room* r, char* scr, const FrameLayout& FL, const rl
     J.lm_px = reinterpret_cast<double4*>(scr + FL.lm_px);
     J.lm_rows = reinterpret_cast<float4*>(scr + FL.lm_rows);
     J.lm_icap = FL.lm_icap;
+    J.lm_split = 1;                         // one frame per launch: split rows (a batch resets it)
     J.partial = reinterpret_cast<double*>(scr + FL.partial);
     J.partial_all = reinterpret_cast<double*>(scr + FL.partial_all);
     J.I = reinterpret_cast<int*>(scr + FL.I);
@@ -1162,7 +1163,7 @@ RL_API rl_status rl_batch_set_degeneracy_screen(rl_batch* b, int32_t on)
 
 static hipError_t launch_sequence(const Job* jobs, int njobs, int maxP, int maxN, int maxIters, int T,
                                   const std::vector<int>& entering, int nptiles, int maxEta, int maxRows, bool any_lm,
-                                  int lm_iters, const Schedule& sc, const Timer& tm, hipStream_t st)
+                                  int lm_iters, bool lm_split, const Schedule& sc, const Timer& tm, hipStream_t st)
 {
     hipError_t e;
 #define RL_TRY(x) do { e = (x); if (e != hipSuccess) return e; } while (0)
@@ -1182,7 +1183,7 @@ static hipError_t launch_sequence(const Job* jobs, int njobs, int maxP, int maxN
     // rounds one at a time
     for (int r = 0; r < (int)entering.size() && (any_lm || entering[r] > 64 * sc.fw); ++r) {
         RL_TRY(launch_score(jobs, njobs, r, nptiles, entering[r], st));
-        if (any_lm && r > 0) RL_TRY(launch_lm(jobs, njobs, r, entering[r], maxEta, maxRows, lm_iters, st));
+        if (any_lm && r > 0) RL_TRY(launch_lm(jobs, njobs, r, entering[r], maxEta, maxRows, lm_iters, lm_split, st));
         RL_TRY(launch_select(jobs, njobs, r, nptiles, maxN, st));
     }
     RL_TRY(launch_score_all(jobs, njobs, (int)entering.size(), nptiles, sc.fw, sc.win, st));
@@ -1269,7 +1270,7 @@ RL_API rl_status relocaliser_relocalise_opts(rl_room* r, const rl_frame* f, uint
     for (int v : entering) key.push_back(v);
     e = run_sequence(r->graphs, key, r->timer.kernel == RL_TIMER_NONE, r->stream, [&]() {
         return launch_sequence(jd, 1, P, N, iters, r->T, entering, nptiles, eta, r->T * r->M, lm != 0,
-                               r->p.lm_iterations, r->sched, r->timer, r->stream);
+                               r->p.lm_iterations, J.lm_split != 0, r->sched, r->timer, r->stream);
     });
     if (e != hipSuccess) return hip_fail(e, "relocalise launch");
     e = hipMemcpyAsync(r->res_host, r->scr + r->FL.result, sizeof(rl_result), hipMemcpyDeviceToHost, r->stream);
@@ -1711,6 +1712,7 @@ static rl_status batch_relocalise_queue(rl_batch* b, const rl_request* reqs, con
             const rl_request& q = reqs[reloc[at[i]]];
             const int N = q.n_hypotheses > 0 ? q.n_hypotheses : q.room->N;
             J = make_job(q.room, b->ws, b->slots[i], &q.frame, q.request_seed, N);
+            J.lm_split = 0;                 // the batch's passes are launched for this layout
             J.result = dev_results + reloc[at[i]];
             if (q.pose_update != 0) J.lm = q.pose_update > 0 ? 1 : 0;
         } else {
@@ -1739,7 +1741,7 @@ static rl_status batch_relocalise_queue(rl_batch* b, const rl_request* reqs, con
     for (int v : entering) key.push_back(v);
     e = run_sequence(b->graphs, key, use_graph && b->timer.kernel == RL_TIMER_NONE, b->stream, [&]() {
         return launch_sequence(jd, nq, maxP, maxN, maxIters, b->bp.n_trees, entering, nptiles, maxEta, b->rows,
-                               any_lm, lm_iters, b->sched, b->timer, b->stream);
+                               any_lm, lm_iters, false, b->sched, b->timer, b->stream);
     });
     if (e != hipSuccess) return hip_fail(e, "batch launch");
     // the next mode update of each room waits for this batch
