@@ -963,14 +963,13 @@ __global__ __launch_bounds__(256) void k_lm_draw(const Job* __restrict__ jobs, i
     const uint4 rb = philox(make_uint4(kTagScore << 28, (uint32_t)rk, (uint32_t)(kk >> 2), 0u), J.key0, J.key1);
     const uint32_t rv = (kk & 3) == 0 ? rb.x : (kk & 3) == 1 ? rb.y : (kk & 3) == 2 ? rb.z : rb.w;
     const uint32_t e = below(rv, (uint32_t)J.st->n_elig);
-    const uint4 c0 = ldg(J.ecold + 2 * e), lw = ldg(J.ecold + 2 * e + 1);
+    const uint4 c0 = ldg(J.ecold + 2 * e);
     const int p = (int)c0.x;
     J.Ie[k] = (int)e;
     J.I[k] = p;
     // the pixel's camera point and |M(u)|; k_lm_rows stages its rows
     double x[3];
     backproject(__uint_as_float(c0.y), p % J.w, p / J.w, J.fx, J.fy, J.cx, J.cy, x);
-    (void)lw;
     J.lm_px[k] = make_double4(x[0], x[1], x[2], (double)modes_total(make_uint2(c0.z, c0.w), J.T));
 }
 
