@@ -4,7 +4,7 @@
 //   k_depth_partial  per (1024-pixel tile, pose): synthetic depth raycast of
 //                    the surfaces from the pose, compared with the live
 //                    depth; per-tile sum of |D_l - D~| and the two counts
-//   k_depth_final    per pose: tiles in order -> mu (Eq. 6), s (Eq. 7)
+//   k_depth_final    per pose (one block): tile sums -> mu (Eq. 6), s (Eq. 7)
 //
 // The raycast's hit tests decide the counts, so they are evaluated in FP64
 // with no contraction, in a fixed operation order.
@@ -104,38 +104,45 @@ __global__ __launch_bounds__(256) void k_depth_partial(FrameView src, int w, int
     }
 }
 
-// one thread per pose: out[2 * pose] = s, out[2 * pose + 1] = mu (NaN when
-// no pixel is valid in both); counts[2 * pose + {0, 1}]
-__global__ void k_depth_final(const double* __restrict__ partial, const int* __restrict__ cnt, int ntiles,
-                              int n_poses, long long np, double* __restrict__ out, long long* __restrict__ counts)
+// one block per pose: thread i adds tiles i, i + 256, ... in order, then a
+// fixed tree over the threads (every tile's partial is read by a single
+// load, not by a pose's chain of dependent batches).  out[2 * pose] = s,
+// out[2 * pose + 1] = mu (NaN when no pixel is valid in both);
+// counts[2 * pose + {0, 1}]
+__global__ __launch_bounds__(256) void k_depth_final(const double* __restrict__ partial,
+                                                     const int* __restrict__ cnt, int ntiles, long long np,
+                                                     double* __restrict__ out, long long* __restrict__ counts)
 {
-    const int pose = threadIdx.x;
-    if (pose >= n_poses) return;
+    __shared__ double s_acc[256];
+    __shared__ long long s_nm[256], s_nb[256];
+    const int pose = blockIdx.x, i = threadIdx.x;
     double acc = 0.0;
     long long nm = 0, nb = 0;
-    for (int t0 = 0; t0 < ntiles; t0 += 16) {         // tiles in order, 16 loaded ahead
-        const int m = min(16, ntiles - t0);
-        double v[16];
-        int a[16], b[16];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const size_t o = (size_t)(t0 + k) * kMaxModelPoses + pose;
-            v[k] = k < m ? partial[o] : 0.0;
-            a[k] = k < m ? cnt[2 * o] : 0;
-            b[k] = k < m ? cnt[2 * o + 1] : 0;
-        }
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            if (k < m) acc += v[k];
-            nm += a[k];
-            nb += b[k];
-        }
+    for (int t = i; t < ntiles; t += 256) {
+        const size_t o = (size_t)t * kMaxModelPoses + pose;
+        acc += partial[o];
+        nm += cnt[2 * o];
+        nb += cnt[2 * o + 1];
     }
-    const double mu = nb > 0 ? acc / (double)nb : NAN;
-    out[2 * pose] = (nb > 0 && 10 * nm >= np) ? mu : INFINITY;
-    out[2 * pose + 1] = mu;
-    counts[2 * pose] = nm;
-    counts[2 * pose + 1] = nb;
+    s_acc[i] = acc;
+    s_nm[i] = nm;
+    s_nb[i] = nb;
+    __syncthreads();
+    for (int stride = 128; stride > 0; stride >>= 1) {
+        if (i < stride) {
+            s_acc[i] += s_acc[i + stride];
+            s_nm[i] += s_nm[i + stride];
+            s_nb[i] += s_nb[i + stride];
+        }
+        __syncthreads();
+    }
+    if (i == 0) {
+        const double mu = s_nb[0] > 0 ? s_acc[0] / (double)s_nb[0] : NAN;
+        out[2 * pose] = (s_nb[0] > 0 && 10 * s_nm[0] >= np) ? mu : INFINITY;
+        out[2 * pose + 1] = mu;
+        counts[2 * pose] = s_nm[0];
+        counts[2 * pose + 1] = s_nb[0];
+    }
 }
 
 hipError_t launch_depth_scores(const FrameView& src, int w, int h, float fx, float fy, float cx, float cy,
@@ -150,8 +157,7 @@ hipError_t launch_depth_scores(const FrameView& src, int w, int h, float fx, flo
                                                                   poses, zmin, zmax, partial, cnt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_depth_final<<<dim3(1), dim3(kMaxModelPoses), 0, st>>>(partial, cnt, ntiles, n_poses, (long long)w * h, out,
-                                                            counts);
+    k_depth_final<<<dim3(n_poses), dim3(256), 0, st>>>(partial, cnt, ntiles, (long long)w * h, out, counts);
     return hipGetLastError();
 }
 

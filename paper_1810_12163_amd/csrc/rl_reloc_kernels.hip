@@ -1779,29 +1779,32 @@ __global__ __launch_bounds__(256) void k_plane_partial(FrameView src, int w, int
     }
 }
 
-__global__ void k_plane_final(const double* __restrict__ partial, const int* __restrict__ cnt, int ntiles,
-                              int n_poses, double* __restrict__ scores)
+// one block per pose: thread i adds tiles i, i + 256, ... in order, then a
+// fixed tree over the threads
+__global__ __launch_bounds__(256) void k_plane_final(const double* __restrict__ partial,
+                                                     const int* __restrict__ cnt, int ntiles,
+                                                     double* __restrict__ scores)
 {
-    const int pose = threadIdx.x;
-    if (pose >= n_poses) return;
+    __shared__ double s_acc[256];
+    __shared__ long long s_c[256];
+    const int pose = blockIdx.x, i = threadIdx.x;
     double acc = 0.0;
     long long c = 0;
-    for (int t0 = 0; t0 < ntiles; t0 += 16) {         // tiles in order, 16 loaded ahead
-        const int m = min(16, ntiles - t0);
-        double v[16];
-        int n[16];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            v[k] = k < m ? partial[(size_t)(t0 + k) * 64 + pose] : 0.0;
-            n[k] = k < m ? cnt[t0 + k] : 0;
-        }
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            if (k < m) acc += v[k];
-            c += n[k];
-        }
+    for (int t = i; t < ntiles; t += 256) {
+        acc += partial[(size_t)t * 64 + pose];
+        c += cnt[t];
     }
-    scores[pose] = c > 0 ? acc / (double)c : INFINITY;
+    s_acc[i] = acc;
+    s_c[i] = c;
+    __syncthreads();
+    for (int stride = 128; stride > 0; stride >>= 1) {
+        if (i < stride) {
+            s_acc[i] += s_acc[i + stride];
+            s_c[i] += s_c[i + stride];
+        }
+        __syncthreads();
+    }
+    if (i == 0) scores[pose] = s_c[0] > 0 ? s_acc[0] / (double)s_c[0] : INFINITY;
 }
 
 // ------------------------------------------------------------------------
@@ -1967,11 +1970,12 @@ hipError_t launch_plane_scores(const FrameView& src, int w, int h, float fx, flo
                                const float* surfaces, int n_surf, const float* poses, int n_poses,
                                double* partial, int* cnt, double* scores, hipStream_t st)
 {
+    if (n_poses < 1 || n_poses > 64) return hipErrorInvalidValue;
     const int ntiles = (w * h + 1023) / 1024;
     k_plane_partial<<<dim3(ntiles, n_poses), dim3(256), 0, st>>>(src, w, h, fx, fy, cx, cy, surfaces, n_surf,
                                                                   poses, partial, cnt);
     RL_CHECK_LAUNCH();
-    k_plane_final<<<dim3(1), dim3(64), 0, st>>>(partial, cnt, ntiles, n_poses, scores);
+    k_plane_final<<<dim3(n_poses), dim3(256), 0, st>>>(partial, cnt, ntiles, scores);
     RL_CHECK_LAUNCH();
     return hipSuccess;
 }
